@@ -1,0 +1,451 @@
+/*
+ * paircount_oracle.c -- TEST INFRASTRUCTURE, not part of the library.
+ *
+ * A plain, slow, obviously correct CPU implementation of binned pair counting
+ * as defined in Sinha & Garrison, "Corrfunc -- a suite of blazing fast
+ * correlation functions on the CPU" (arXiv:1911.03545).  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg load it.  It shares no
+ * code, header, table or constant with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * What is computed (the brute-force pair counter of Code 1 in section 2.1,
+ * "How to compute a correlation function"):
+ *
+ *   for every ordered pair (i, j) in D1 x D2:
+ *       s = separation(i, j)                      -- distance_metric
+ *       skip unless E_0 <= s < E_nb               -- min/max separation cut
+ *       k = bin of s                              -- dist_to_bin_index
+ *       counts[k] += 1; wsum[k] += w_i * w_j      -- weight_func (product)
+ *
+ * Precision rules (binary64, round to nearest even, no FMA contraction: the
+ * file is compiled with -ffp-contract=off and without -ffast-math):
+ *   * inputs are promoted exactly to binary64 by the caller;
+ *   * separations are compared in squared form (section "Finding and updating
+ *     the histogram bins": bins on r^2 avoid the square root), so the squared
+ *     edges are E_k = fl(e_k * e_k) and a pair lies in bin k iff
+ *     E_k <= s < E_{k+1} (half-open bins, Code 1's skip test);
+ *   * per axis dx = x_i - x_j, then the periodic wrap of Code 3
+ *     ("Accounting for periodic boundary conditions"):
+ *         if (dx >  L/2) dx -= L;   if (dx <= -L/2) dx += L;
+ *   * 3-D separation (Appendix A, eq. for r^2): s = (dx*dx + dy*dy) + dz*dz;
+ *   * rp^2 = dx*dx + dy*dy and pi = |dz| with z the line of sight
+ *     (Appendix A, Cartesian volumes);
+ *   * angular separations use unit vectors v = (cos d cos a, cos d sin a, sin d)
+ *     and the squared chord |v1 - v2|^2 with edges c_k = 2 sin(theta_k / 2);
+ *     this is the cos(theta) = v1.v2 relation of Appendix A rewritten as a
+ *     monotone function of theta that needs no arccos.
+ *
+ * Pair convention (section "Symmetry considerations for autocorrelations" and
+ * Appendix B): an autocorrelation of D must equal the cross-correlation of D
+ * with itself, i.e. all N^2 ordered pairs including i == j.  It is computed as
+ * the paper describes: unique pairs j > i only, counts doubled, and N
+ * self-pairs added to bin 0 when the first edge is exactly zero.  Weighted
+ * sums follow the same rule (unique-pair products doubled, w_i^2 added when
+ * the first edge is zero).  Weighted sums are the exact real sum of the
+ * binary64 products, rounded once, via Shewchuk's non-overlapping expansions
+ * (the algorithm behind Python's math.fsum).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-3)
+#define ORACLE_EINTERNAL (-7)
+
+/* ------------------------------------------------------------------------ */
+/* Exact summation: a sum is held as a list of non-overlapping partials in   */
+/* increasing magnitude (Shewchuk 1997, "Adaptive precision floating-point   */
+/* arithmetic"), and rounded to binary64 once at the end with the            */
+/* round-half-even correction used by Python's math.fsum.                    */
+/* ------------------------------------------------------------------------ */
+#define XSUM_MAX 64
+typedef struct {
+    int n;
+    int overflow;
+    double p[XSUM_MAX];
+} xacc;
+
+static void xacc_add(xacc *a, double x)
+{
+    int i = 0;
+    for (int k = 0; k < a->n; k++) {
+        double y = a->p[k];
+        if (fabs(x) < fabs(y)) {
+            double t = x;
+            x = y;
+            y = t;
+        }
+        double hi = x + y;
+        double lo = y - (hi - x);
+        if (lo != 0.0)
+            a->p[i++] = lo;
+        x = hi;
+    }
+    if (i >= XSUM_MAX) {
+        a->overflow = 1;
+        return;
+    }
+    a->p[i++] = x;
+    a->n = i;
+}
+
+static double xacc_value(const xacc *a)
+{
+    int n = a->n;
+    double hi = 0.0;
+    if (n > 0) {
+        double lo = 0.0;
+        n--;
+        hi = a->p[n];
+        while (n > 0) {
+            double x = hi;
+            n--;
+            double y = a->p[n];
+            hi = x + y;
+            double yr = hi - x;
+            lo = y - yr;
+            if (lo != 0.0)
+                break;
+        }
+        /* If the discarded tail pushes past a half-way case, round away. */
+        if (n > 0 && ((lo < 0.0 && a->p[n - 1] < 0.0) ||
+                      (lo > 0.0 && a->p[n - 1] > 0.0))) {
+            double y = lo * 2.0;
+            double x = hi + y;
+            double yr = x - hi;
+            if (y == yr)
+                hi = x;
+        }
+    }
+    return hi;
+}
+
+static void xacc_merge(xacc *dst, const xacc *src)
+{
+    for (int k = 0; k < src->n; k++)
+        xacc_add(dst, src->p[k]);
+    dst->overflow |= src->overflow;
+}
+
+/* Exact rounded sum of an array: exported so the tests can pin the
+   summation against an independent implementation. */
+double oracle_xsum(int64_t n, const double *v)
+{
+    xacc a;
+    a.n = 0;
+    a.overflow = 0;
+    for (int64_t i = 0; i < n; i++)
+        xacc_add(&a, v[i]);
+    return xacc_value(&a);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Separations                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Code 3: minimum-image wrap of one axis difference, for positions in the
+   closed interval [0, L]. */
+static double wrap_axis(double d, double L, double half)
+{
+    if (d > half)
+        d -= L;
+    if (d <= -half)
+        d += L;
+    return d;
+}
+
+static int check_edges(const double *edges, int32_t nbins)
+{
+    if (nbins < 1 || edges == NULL)
+        return ORACLE_EINVAL;
+    for (int k = 0; k <= nbins; k++)
+        if (!isfinite(edges[k]) || edges[k] < 0.0)
+            return ORACLE_EINVAL;
+    for (int k = 0; k < nbins; k++)
+        if (!(edges[k] < edges[k + 1]))
+            return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* pi bins of Appendix A: npi bins of equal width pimax/npi in [0, pimax).
+   q_p = p * fl(pimax / npi) for p < npi, and q_npi = pimax exactly, so the
+   line-of-sight cut is pi < pimax. */
+int oracle_pi_edges(double pimax, int32_t npi, double *q)
+{
+    if (!(pimax > 0.0) || !isfinite(pimax) || npi < 1)
+        return ORACLE_EINVAL;
+    double dpi = pimax / (double)npi;
+    for (int p = 0; p < npi; p++)
+        q[p] = (double)p * dpi;
+    q[npi] = pimax;
+    for (int p = 0; p < npi; p++)
+        if (!(q[p] < q[p + 1]))
+            return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* One engine for the 1-D (r or chord) and the 2-D (rp, pi) statistics.
+   mode 0: s = (dx*dx + dy*dy) + dz*dz, bins k over E
+   mode 1: s = dx*dx + dy*dy, pi = |dz|, bins k*npi + p over E x q           */
+static int count_engine(int mode,
+                        int64_t n1, const double *x1, const double *y1,
+                        const double *z1, const double *w1,
+                        int64_t n2, const double *x2, const double *y2,
+                        const double *z2, const double *w2,
+                        int autocorr, const double *edges, int32_t nbins,
+                        const double *q, int32_t npi, double boxsize,
+                        uint64_t *counts, double *wsum, int nthreads)
+{
+    int rc = check_edges(edges, nbins);
+    if (rc)
+        return rc;
+    if (n1 < 0 || counts == NULL)
+        return ORACLE_EINVAL;
+    if (autocorr) {
+        n2 = n1;
+        x2 = x1;
+        y2 = y1;
+        z2 = z1;
+        w2 = w1;
+    } else if (n2 < 0) {
+        return ORACLE_EINVAL;
+    }
+    const int weighted = (w1 != NULL);
+    if (weighted && w2 == NULL)
+        return ORACLE_EINVAL;
+    const int nout = (mode == 1) ? nbins * npi : nbins;
+    const int periodic = boxsize > 0.0;
+    const double L = boxsize;
+    const double half = 0.5 * boxsize;
+    const double pimax = (mode == 1) ? q[npi] : 0.0;
+
+    double *E = (double *)malloc(sizeof(double) * (size_t)(nbins + 1));
+    if (!E)
+        return ORACLE_ENOMEM;
+    for (int k = 0; k <= nbins; k++)
+        E[k] = edges[k] * edges[k];
+
+    memset(counts, 0, sizeof(uint64_t) * (size_t)nout);
+    xacc *total = NULL;
+    if (weighted) {
+        total = (xacc *)calloc((size_t)nout, sizeof(xacc));
+        if (!total) {
+            free(E);
+            return ORACLE_ENOMEM;
+        }
+    }
+    int failed = 0;
+
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        uint64_t *c = (uint64_t *)calloc((size_t)nout, sizeof(uint64_t));
+        xacc *acc = weighted ? (xacc *)calloc((size_t)nout, sizeof(xacc)) : NULL;
+        int ok = (c != NULL) && (!weighted || acc != NULL);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t i = 0; i < n1; i++) {
+            if (!ok)
+                continue;
+            const double xi = x1[i], yi = y1[i], zi = z1[i];
+            const int64_t j0 = autocorr ? i + 1 : 0;
+            for (int64_t j = j0; j < n2; j++) {
+                double dx = xi - x2[j];
+                double dy = yi - y2[j];
+                double dz = zi - z2[j];
+                if (periodic) {
+                    dx = wrap_axis(dx, L, half);
+                    dy = wrap_axis(dy, L, half);
+                    dz = wrap_axis(dz, L, half);
+                }
+                int bin;
+                if (mode == 0) {
+                    double s = (dx * dx + dy * dy) + dz * dz;
+                    if (s < E[0] || s >= E[nbins])
+                        continue;
+                    int k = nbins - 1; /* reverse scan over the bins */
+                    while (s < E[k])
+                        k--;
+                    bin = k;
+                } else {
+                    double s = dx * dx + dy * dy;
+                    double pi = fabs(dz);
+                    if (s < E[0] || s >= E[nbins] || pi >= pimax)
+                        continue;
+                    int k = nbins - 1;
+                    while (s < E[k])
+                        k--;
+                    int p = npi - 1;
+                    while (pi < q[p])
+                        p--;
+                    bin = k * npi + p;
+                }
+                c[bin]++;
+                if (weighted) {
+                    double prod = w1[i] * w2[j];
+                    /* autocorrelation: the unique pair stands for (i,j) and
+                       (j,i); doubling is exact in binary64 */
+                    xacc_add(&acc[bin], autocorr ? 2.0 * prod : prod);
+                }
+            }
+        }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+        {
+            if (!ok) {
+                failed = 1;
+            } else {
+                for (int b = 0; b < nout; b++) {
+                    counts[b] += c[b];
+                    if (weighted)
+                        xacc_merge(&total[b], &acc[b]);
+                }
+            }
+        }
+        free(c);
+        free(acc);
+    }
+    if (failed) {
+        free(E);
+        free(total);
+        return ORACLE_ENOMEM;
+    }
+
+    if (autocorr) {
+        for (int b = 0; b < nout; b++)
+            counts[b] *= 2u;
+        /* Appendix B: self-pairs belong to bin 0 when it starts at zero
+           separation (and, for (rp, pi), pi bin 0 always starts at zero). */
+        if (E[0] == 0.0) {
+            counts[0] += (uint64_t)n1;
+            if (weighted)
+                for (int64_t i = 0; i < n1; i++)
+                    xacc_add(&total[0], w1[i] * w1[i]);
+        }
+    }
+    if (wsum) {
+        for (int b = 0; b < nout; b++)
+            wsum[b] = weighted ? xacc_value(&total[b]) : 0.0;
+    }
+    if (weighted) {
+        for (int b = 0; b < nout; b++)
+            if (total[b].overflow)
+                rc = ORACLE_EINTERNAL;
+    }
+    free(E);
+    free(total);
+    return rc;
+}
+
+/* DD(r): counts[k] over r edges (edges[0..nbins]); boxsize <= 0 means
+   non-periodic; autocorr != 0 ignores the second catalogue. */
+int oracle_count_r(int64_t n1, const double *x1, const double *y1,
+                   const double *z1, const double *w1,
+                   int64_t n2, const double *x2, const double *y2,
+                   const double *z2, const double *w2,
+                   int autocorr, const double *edges, int32_t nbins,
+                   double boxsize, uint64_t *counts, double *wsum,
+                   int nthreads)
+{
+    return count_engine(0, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
+                        edges, nbins, NULL, 0, boxsize, counts, wsum,
+                        nthreads);
+}
+
+/* DD(rp, pi): counts[k * npi + p]; rp edges rp_edges[0..nrp]. */
+int oracle_count_rppi(int64_t n1, const double *x1, const double *y1,
+                      const double *z1, const double *w1,
+                      int64_t n2, const double *x2, const double *y2,
+                      const double *z2, const double *w2,
+                      int autocorr, const double *rp_edges, int32_t nrp,
+                      double pimax, int32_t npi, double boxsize,
+                      uint64_t *counts, double *wsum, int nthreads)
+{
+    if (npi < 1)
+        return ORACLE_EINVAL;
+    double *q = (double *)malloc(sizeof(double) * (size_t)(npi + 1));
+    if (!q)
+        return ORACLE_ENOMEM;
+    int rc = oracle_pi_edges(pimax, npi, q);
+    if (rc == ORACLE_OK)
+        rc = count_engine(1, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2,
+                          autocorr, rp_edges, nrp, q, npi, boxsize, counts,
+                          wsum, nthreads);
+    free(q);
+    return rc;
+}
+
+/* RA/DEC in degrees -> unit vectors (binary64, host libm). */
+int oracle_radec_to_unit(int64_t n, const double *ra, const double *dec,
+                         double *x, double *y, double *z)
+{
+    const double d2r = M_PI / 180.0;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(ra[i] >= 0.0 && ra[i] <= 360.0 && dec[i] >= -90.0 &&
+              dec[i] <= 90.0))
+            return ORACLE_EINVAL;
+        double a = ra[i] * d2r;
+        double d = dec[i] * d2r;
+        double cd = cos(d);
+        x[i] = cd * cos(a);
+        y[i] = cd * sin(a);
+        z[i] = sin(d);
+    }
+    return ORACLE_OK;
+}
+
+/* Angular edges (degrees) -> chord lengths c = 2 sin(theta / 2). */
+int oracle_theta_chord_edges(int32_t nedges, const double *theta_deg,
+                             double *chord)
+{
+    const double d2r = M_PI / 180.0;
+    for (int k = 0; k < nedges; k++) {
+        if (!(theta_deg[k] >= 0.0 && theta_deg[k] <= 180.0))
+            return ORACLE_EINVAL;
+        chord[k] = 2.0 * sin(0.5 * (theta_deg[k] * d2r));
+    }
+    return ORACLE_OK;
+}
+
+/* DD(theta) / DR(theta) from RA/DEC in degrees. */
+int oracle_count_theta(int64_t n1, const double *ra1, const double *dec1,
+                       const double *w1, int64_t n2, const double *ra2,
+                       const double *dec2, const double *w2, int autocorr,
+                       const double *theta_edges_deg, int32_t nbins,
+                       uint64_t *counts, double *wsum, int nthreads)
+{
+    if (n1 < 0 || nbins < 1)
+        return ORACLE_EINVAL;
+    if (autocorr)
+        n2 = 0;
+    double *v1 = (double *)malloc(sizeof(double) * 3 * (size_t)(n1 + 1));
+    double *v2 = (double *)malloc(sizeof(double) * 3 * (size_t)(n2 + 1));
+    double *c = (double *)malloc(sizeof(double) * (size_t)(nbins + 1));
+    int rc = ORACLE_ENOMEM;
+    if (v1 && v2 && c) {
+        rc = oracle_theta_chord_edges(nbins + 1, theta_edges_deg, c);
+        if (rc == ORACLE_OK)
+            rc = oracle_radec_to_unit(n1, ra1, dec1, v1, v1 + n1, v1 + 2 * n1);
+        if (rc == ORACLE_OK && !autocorr)
+            rc = oracle_radec_to_unit(n2, ra2, dec2, v2, v2 + n2, v2 + 2 * n2);
+        if (rc == ORACLE_OK)
+            rc = count_engine(0, n1, v1, v1 + n1, v1 + 2 * n1, w1, n2, v2,
+                              v2 + n2, v2 + 2 * n2, w2, autocorr, c, nbins,
+                              NULL, 0, 0.0, counts, wsum, nthreads);
+    }
+    free(v1);
+    free(v2);
+    free(c);
+    return rc;
+}

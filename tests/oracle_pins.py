@@ -1,0 +1,397 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Every ``pin_*`` function takes a loaded oracle library and raises
+``AssertionError`` when the oracle disagrees with the fact it checks.  The same
+functions run against the real oracle (``test_oracle.py``) and against copies of
+it with deliberately planted mistakes (``test_oracle_mutations.py``), which must
+each be caught by at least one pin.
+
+Sources of truth used here:
+  * hand-enumerated counts in ``tests/golden/*.json`` (each cites the passage);
+  * exact rational arithmetic (``fractions``) on lattice inputs, where binary64
+    is exact, with the periodic separation taken as the minimum over images;
+  * closed-form expectations for uniform random points (Appendix B);
+  * invariants the paper fixes (auto == cross(D, D), doubling, self-pairs);
+  * exact scaling by powers of two, bin-merge additivity, permutation
+    invariance, and reductions of one statistic to another;
+  * Python's ``math.fsum`` for exactly rounded sums.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# --------------------------------------------------------------------------
+# hand enumeration
+# --------------------------------------------------------------------------
+def pin_golden_r_edges(lib):
+    g = _golden("r_edge_inclusion.json")
+    pts = np.array(g["points"], dtype=np.float64)
+    w = np.array(g["weights"], dtype=np.float64)
+    for case in g["cases"]:
+        c, ws = oracle.count_r(pts, None, case["edges"], g["boxsize"], w1=w, lib=lib)
+        assert c.tolist() == case["counts"], (c, case)
+        assert ws.tolist() == case["wsum"], (ws, case)
+        c2, ws2 = oracle.count_r(pts, pts, case["edges"], g["boxsize"], w1=w, w2=w, lib=lib)
+        assert c2.tolist() == case["counts"], (c2, case)
+        assert ws2.tolist() == case["wsum"], (ws2, case)
+
+
+def pin_golden_r_periodic(lib):
+    for name in ("r_periodic_wrap.json", "r_corner_wrap.json"):
+        g = _golden(name)
+        pts = np.array(g["points"], dtype=np.float64)
+        for case in g["cases"]:
+            c, _ = oracle.count_r(pts, None, case["edges"], case["boxsize"], lib=lib)
+            assert c.tolist() == case["counts"], (name, c, case)
+            c2, _ = oracle.count_r(pts, pts, case["edges"], case["boxsize"], lib=lib)
+            assert c2.tolist() == case["counts"], (name, c2, case)
+
+
+def pin_golden_rppi(lib):
+    g = _golden("rppi_small.json")
+    pts = np.array(g["points"], dtype=np.float64)
+    for case in g["cases"]:
+        c, _ = oracle.count_rppi(pts, None, case["rp_edges"], g["pimax"], g["npi"],
+                                 g["boxsize"], lib=lib)
+        assert c.tolist() == case["counts"], (c, case)
+        c2, _ = oracle.count_rppi(pts, pts, case["rp_edges"], g["pimax"], g["npi"],
+                                  g["boxsize"], lib=lib)
+        assert c2.tolist() == case["counts"], (c2, case)
+
+
+def pin_golden_theta(lib):
+    g = _golden("theta_small.json")
+    rd = np.array(g["radec"], dtype=np.float64)
+    for case in g["cases"]:
+        c, _ = oracle.count_theta(rd[:, 0], rd[:, 1], None, None,
+                                  case["theta_edges"], lib=lib)
+        assert c.tolist() == case["counts"], (c, case)
+        c2, _ = oracle.count_theta(rd[:, 0], rd[:, 1], rd[:, 0], rd[:, 1],
+                                   case["theta_edges"], lib=lib)
+        assert c2.tolist() == case["counts"], (c2, case)
+
+
+# --------------------------------------------------------------------------
+# exact arithmetic on lattice inputs
+# --------------------------------------------------------------------------
+def _min_image_sq(d: Fraction, L: Fraction | None) -> Fraction:
+    """Squared axis separation, minimised over periodic images."""
+    if L is None:
+        return d * d
+    return min((d + m * L) ** 2 for m in (-1, 0, 1))
+
+
+def _exact_counts_r(pts, edges, L, auto=True, pts2=None):
+    Q = [[Fraction(float(v)) for v in p] for p in pts]
+    Q2 = Q if pts2 is None else [[Fraction(float(v)) for v in p] for p in pts2]
+    E = [Fraction(float(e) * float(e)) for e in edges]
+    Lf = None if L <= 0 else Fraction(float(L))
+    nb = len(edges) - 1
+    out = [0] * nb
+    for a in range(len(Q)):
+        for b in range(len(Q2)):
+            s = sum(_min_image_sq(Q[a][k] - Q2[b][k], Lf) for k in range(3))
+            for k in range(nb):
+                if E[k] <= s < E[k + 1]:
+                    out[k] += 1
+    return out
+
+
+def pin_lattice_exact_r(lib):
+    L = 64
+    pts = synth.lattice_box(50, L, seed=11, denom=1024)
+    # a few coincident points and points on the box faces
+    pts[1] = pts[0]
+    pts[2, 0] = L
+    pts[3, 1] = 0.0
+    edges = np.array([0.0, 1.5, 4.0, 9.25, 16.0, 21.0])
+    for box in (float(L), 0.0):
+        want = _exact_counts_r(pts, edges, box)
+        got, _ = oracle.count_r(pts, None, edges, box, lib=lib)
+        assert got.tolist() == want, (box, got, want)
+    # cross-correlation between two different lattice sets
+    pts2 = synth.lattice_box(30, L, seed=12, denom=1024)
+    want = _exact_counts_r(pts, edges, float(L), pts2=pts2)
+    got, _ = oracle.count_r(pts, pts2, edges, float(L), lib=lib)
+    assert got.tolist() == want, (got, want)
+
+
+def pin_lattice_exact_rppi(lib):
+    L = 64
+    pts = synth.lattice_box(45, L, seed=13, denom=1024)
+    pts[1] = pts[0]
+    pts[5, 2] = L
+    rp_edges = [0.0, 2.0, 5.5, 12.0, 20.0]
+    pimax, npi = 16.0, 8
+    q = [Fraction(2 * p) for p in range(npi + 1)]
+    E = [Fraction(e) ** 2 for e in rp_edges]
+    Q = [[Fraction(float(v)) for v in p] for p in pts]
+    for box in (float(L), 0.0):
+        Lf = None if box <= 0 else Fraction(box)
+        want = np.zeros((len(rp_edges) - 1, npi), dtype=np.int64)
+        for a in range(len(Q)):
+            for b in range(len(Q)):
+                rp2 = _min_image_sq(Q[a][0] - Q[b][0], Lf) + _min_image_sq(Q[a][1] - Q[b][1], Lf)
+                pi = _min_image_sq(Q[a][2] - Q[b][2], Lf)  # squared; compare squared
+                for k in range(len(rp_edges) - 1):
+                    if not (E[k] <= rp2 < E[k + 1]):
+                        continue
+                    for p in range(npi):
+                        if q[p] ** 2 <= pi < q[p + 1] ** 2:
+                            want[k, p] += 1
+        got, _ = oracle.count_rppi(pts, None, rp_edges, pimax, npi, box, lib=lib)
+        assert (got == want).all(), (box, got, want)
+
+
+def pin_weighted_exact(lib):
+    """Weighted sums equal the exactly rounded rational sum of products."""
+    pts = synth.lattice_box(40, 32, seed=21, denom=1024)
+    rng = synth.rng_for(22)
+    w = rng.uniform(0.5, 1.5, size=40)   # full 53-bit mantissas
+    w2 = rng.uniform(-1.0, 2.0, size=40)
+    edges = [0.0, 3.0, 7.0, 12.0]
+    E = [Fraction(e) ** 2 for e in edges]
+    Q = [[Fraction(float(v)) for v in p] for p in pts]
+    Lf = Fraction(32)
+    for auto in (True, False):
+        wb = w if auto else w2
+        sums = [Fraction(0)] * 3
+        cnt = [0] * 3
+        for a in range(40):
+            for b in range(40):
+                s = sum(_min_image_sq(Q[a][k] - Q[b][k], Lf) for k in range(3))
+                for k in range(3):
+                    if E[k] <= s < E[k + 1]:
+                        # each product is rounded to binary64, then summed exactly
+                        sums[k] += Fraction(float(w[a]) * float(wb[b]))
+                        cnt[k] += 1
+        if auto:
+            c, ws = oracle.count_r(pts, None, edges, 32.0, w1=w, lib=lib)
+        else:
+            c, ws = oracle.count_r(pts, pts, edges, 32.0, w1=w, w2=w2, lib=lib)
+        assert c.tolist() == cnt, (auto, c, cnt)
+        assert ws.tolist() == [float(x) for x in sums], (auto, ws, sums)
+
+
+def pin_xsum_vs_fsum(lib):
+    rng = synth.rng_for(31)
+    cases = [
+        rng.normal(size=1000),
+        np.concatenate([rng.normal(size=500) * 1e16, rng.normal(size=500)]),
+        np.array([1e100, 1.0, -1e100, 1e-100, 3.0, -2.0]),
+        np.array([0.1] * 10),
+        np.array([2.0 ** 53, 1.0, 1e-30]),   # half-way case broken by a tiny tail
+        np.array([1.0, 2.0 ** -53, 2.0 ** -106]),
+    ]
+    for v in cases:
+        assert oracle.xsum(v, lib=lib) == math.fsum(v.tolist())
+
+
+# --------------------------------------------------------------------------
+# invariants fixed by the paper and by the arithmetic
+# --------------------------------------------------------------------------
+def pin_auto_equals_cross(lib):
+    pts = synth.clustered_box(600, 50.0, seed=41, nblobs=20, sigma=1.0)
+    w = synth.uniform_weights(600, seed=42).astype(np.float64)
+    for edges in (synth.log_edges(0.05, 12.0, 10), np.r_[0.0, synth.log_edges(0.05, 12.0, 10)]):
+        for box in (50.0, 0.0):
+            ca, wa = oracle.count_r(pts, None, edges, box, w1=w, lib=lib)
+            cc, wc = oracle.count_r(pts, pts, edges, box, w1=w, w2=w, lib=lib)
+            assert (ca == cc).all(), (box, ca, cc)
+            assert (wa == wc).all(), (box, wa, wc)
+            ra, _ = oracle.count_rppi(pts, None, edges, 12.0, 6, box, lib=lib)
+            rc, _ = oracle.count_rppi(pts, pts, edges, 12.0, 6, box, lib=lib)
+            assert (ra == rc).all()
+    ra, dec = synth.cap_radec(400, seed=43, radius_deg=5.0, clustered=True,
+                              nblobs=20, sigma_deg=0.2)
+    te = synth.log_edges(0.01, 3.0, 8)
+    ta, _ = oracle.count_theta(ra, dec, None, None, te, lib=lib)
+    tc, _ = oracle.count_theta(ra, dec, ra, dec, te, lib=lib)
+    assert (ta == tc).all(), (ta, tc)
+
+
+def pin_pair_convention(lib):
+    """Auto counts are ordered pairs: even, plus N self-pairs in bin 0 iff the
+    first edge is zero (Appendix B)."""
+    pts = synth.uniform_box(300, 20.0, seed=51)
+    pts[7] = pts[3]            # a coincident pair
+    e_pos = synth.log_edges(0.1, 5.0, 6)
+    c, _ = oracle.count_r(pts, None, e_pos, 20.0, lib=lib)
+    assert all(int(x) % 2 == 0 for x in c)
+    e0 = np.r_[0.0, e_pos]
+    c0, _ = oracle.count_r(pts, None, e0, 20.0, lib=lib)
+    # the coincident pair (2 ordered) + 300 self-pairs land below e_pos[0]
+    assert int(c0[0]) == 300 + 2
+    assert (c0[1:] == c).all()
+    n = 300
+    assert int(c0.sum()) <= n * n
+
+
+def pin_bin_merge_and_total(lib):
+    pts = synth.clustered_box(700, 60.0, seed=61, nblobs=30, sigma=1.5)
+    edges = synth.log_edges(0.2, 14.0, 12)
+    c, _ = oracle.count_r(pts, None, edges, 60.0, lib=lib)
+    merged = np.delete(edges, [3, 7, 8])
+    cm, _ = oracle.count_r(pts, None, merged, 60.0, lib=lib)
+    # removing edges 3, 7 and 8 merges bins (2, 3) and (6, 7, 8)
+    want = [c[0], c[1], c[2] + c[3], c[4], c[5], c[6] + c[7] + c[8], c[9], c[10], c[11]]
+    assert cm.tolist() == [int(x) for x in want], (cm, want)
+    one, _ = oracle.count_r(pts, None, [edges[0], edges[-1]], 60.0, lib=lib)
+    assert int(one[0]) == int(c.sum())
+
+
+def pin_permutation_and_scaling(lib):
+    pts = synth.clustered_box(500, 40.0, seed=71, nblobs=25, sigma=1.0)
+    w = synth.uniform_weights(500, seed=72).astype(np.float64)
+    edges = synth.log_edges(0.1, 9.0, 9)
+    c, ws = oracle.count_r(pts, None, edges, 40.0, w1=w, lib=lib)
+    perm = synth.rng_for(73).permutation(500)
+    cp, wsp = oracle.count_r(pts[perm], None, edges, 40.0, w1=w[perm], lib=lib)
+    assert (c == cp).all() and (ws == wsp).all()
+    for m in (-3, 5):
+        f = 2.0 ** m
+        cs, wss = oracle.count_r(pts * f, None, edges * f, 40.0 * f, w1=w * f, lib=lib)
+        assert (cs == c).all(), (m, cs, c)
+        assert (wss == ws * f * f).all(), (m, wss, ws)
+    ones = np.ones(500)
+    c1, w1 = oracle.count_r(pts, None, edges, 40.0, w1=ones, lib=lib)
+    assert (w1 == c1.astype(np.float64)).all()
+
+
+def pin_periodic_interior(lib):
+    """With every point inside a sub-box narrower than L/2 no wrap can trigger,
+    so periodic and non-periodic counts agree exactly."""
+    rng = synth.rng_for(81)
+    pts = 30.0 + rng.uniform(0.0, 39.0, size=(500, 3))
+    edges = synth.log_edges(0.5, 15.0, 8)
+    a, _ = oracle.count_r(pts, None, edges, 100.0, lib=lib)
+    b, _ = oracle.count_r(pts, None, edges, 0.0, lib=lib)
+    assert (a == b).all()
+    a, _ = oracle.count_rppi(pts, None, edges, 20.0, 5, 100.0, lib=lib)
+    b, _ = oracle.count_rppi(pts, None, edges, 20.0, 5, 0.0, lib=lib)
+    assert (a == b).all()
+
+
+def pin_rppi_reductions(lib):
+    """(1) With all z equal, pi = 0 and rp^2 is exactly the 3-D s, so DD(rp,pi)
+    puts DD(r) into pi bin 0.  (2) With x = y = 0 on lattice inputs, rp = 0 and
+    the pi histogram equals the r histogram over the pi edges."""
+    pts = synth.clustered_box(500, 50.0, seed=91, nblobs=20, sigma=1.0)
+    pts[:, 2] = 7.0
+    edges = synth.log_edges(0.1, 12.0, 10)
+    cr, _ = oracle.count_r(pts, None, edges, 50.0, lib=lib)
+    cp, _ = oracle.count_rppi(pts, None, edges, 10.0, 5, 50.0, lib=lib)
+    assert (cp[:, 0] == cr).all() and (cp[:, 1:] == 0).all()
+    lat = synth.lattice_box(200, 64, seed=92)
+    lat[:, 0] = 0.0
+    lat[:, 1] = 0.0
+    q = oracle.pi_edges(16.0, 8, lib=lib)
+    assert q.tolist() == [2.0 * p for p in range(9)]
+    cp, _ = oracle.count_rppi(lat, None, [0.0, 1.0], 16.0, 8, 64.0, lib=lib)
+    cr, _ = oracle.count_r(lat, None, q, 64.0, lib=lib)
+    assert (cp[0] == cr).all(), (cp, cr)
+
+
+def pin_inclusion_r_in_rppi(lib):
+    """r < R implies rp < R and pi < R, so counts inside the sphere never exceed
+    counts inside the enclosing cylinder; the cylinder of half-height R has
+    3/2 the sphere's volume, which the uniform counts must reflect."""
+    pts = synth.uniform_box(2500, 50.0, seed=101)
+    R = 6.0
+    cr, _ = oracle.count_r(pts, None, [0.0, R], 50.0, lib=lib)
+    cp, _ = oracle.count_rppi(pts, None, [0.0, R], R, 1, 50.0, lib=lib)
+    assert int(cr[0]) <= int(cp[0, 0])
+    ratio = (int(cp[0, 0]) - 2500) / (int(cr[0]) - 2500)
+    assert abs(ratio - 1.5) < 0.1, ratio
+
+
+def _zscores(got, expect):
+    return (got.astype(np.float64) - expect) / np.sqrt(np.maximum(2.0 * expect, 1.0))
+
+
+def pin_uniform_analytic(lib):
+    """Appendix B: for N uniform points in a periodic box the expected ordered
+    pair count in a shell is N (N-1) dV / V (variance ~ 2x the mean)."""
+    N, L = 4000, 100.0
+    pts = synth.uniform_box(N, L, seed=111)
+    e = synth.log_edges(0.5, 20.0, 10)
+    c, _ = oracle.count_r(pts, None, e, L, lib=lib)
+    exp = N * (N - 1) * (4.0 / 3.0) * np.pi * (e[1:] ** 3 - e[:-1] ** 3) / L ** 3
+    assert np.all(np.abs(_zscores(c, exp)) < 5), _zscores(c, exp)
+    pimax, npi = 20.0, 5
+    cp, _ = oracle.count_rppi(pts, None, e, pimax, npi, L, lib=lib)
+    dpi = pimax / npi
+    expp = (N * (N - 1) * np.pi * (e[1:] ** 2 - e[:-1] ** 2) * 2 * dpi / L ** 3)[:, None] \
+        * np.ones(npi)[None, :]
+    assert np.all(np.abs(_zscores(cp, expp)) < 5), _zscores(cp, expp)
+    # full sphere: uniform directions, expected N(N-1)(cos t0 - cos t1)/2
+    rng = synth.rng_for(112)
+    v = rng.normal(size=(3000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    ra = np.mod(np.degrees(np.arctan2(v[:, 1], v[:, 0])), 360.0)
+    dec = np.degrees(np.arcsin(v[:, 2]))
+    te = np.array([1.0, 5.0, 20.0, 45.0, 90.0, 135.0, 179.0])
+    ct, _ = oracle.count_theta(ra, dec, None, None, te, lib=lib)
+    n = 3000
+    expt = n * (n - 1) * (np.cos(np.radians(te[:-1])) - np.cos(np.radians(te[1:]))) / 2
+    assert np.all(np.abs(_zscores(ct, expt)) < 5), _zscores(ct, expt)
+
+
+def pin_theta_conversion(lib):
+    """Unit vectors have unit norm, reproduce cos(theta) = v1.v2 of Appendix A,
+    and chord edges satisfy c^2 = 2 - 2 cos(theta)."""
+    rng = synth.rng_for(121)
+    ra = rng.uniform(0, 360, 200)
+    dec = rng.uniform(-90, 90, 200)
+    v = oracle.radec_to_unit(ra, dec, lib=lib)
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-15)
+    # independent spherical law of cosines for the angle between two points
+    a1, d1 = np.radians(ra[:100]), np.radians(dec[:100])
+    a2, d2 = np.radians(ra[100:]), np.radians(dec[100:])
+    cosang = np.sin(d1) * np.sin(d2) + np.cos(d1) * np.cos(d2) * np.cos(a1 - a2)
+    dots = np.sum(v[:100] * v[100:], axis=1)
+    assert np.allclose(dots, cosang, atol=1e-14)
+    assert np.allclose(v[:, 2], np.sin(np.radians(dec)), atol=1e-15)
+    assert np.allclose(np.arctan2(v[:, 1], v[:, 0]) % (2 * np.pi), np.radians(ra) % (2 * np.pi),
+                       atol=1e-12)
+    t = np.array([0.0, 0.01, 1.0, 10.0, 60.0, 90.0, 179.0])
+    c = oracle.theta_chord_edges(t, lib=lib)
+    # 2 - 2 cos(t) cancels for small t: allow its absolute rounding (~4e-16)
+    assert np.allclose(c * c, 2.0 - 2.0 * np.cos(np.radians(t)), rtol=1e-13, atol=1e-15)
+
+
+ALL_PINS = [
+    pin_golden_r_edges,
+    pin_golden_r_periodic,
+    pin_golden_rppi,
+    pin_golden_theta,
+    pin_lattice_exact_r,
+    pin_lattice_exact_rppi,
+    pin_weighted_exact,
+    pin_xsum_vs_fsum,
+    pin_auto_equals_cross,
+    pin_pair_convention,
+    pin_bin_merge_and_total,
+    pin_permutation_and_scaling,
+    pin_periodic_interior,
+    pin_rppi_reductions,
+    pin_inclusion_r_in_rppi,
+    pin_uniform_analytic,
+    pin_theta_conversion,
+]

@@ -1,0 +1,60 @@
+"""Each plausible mistake planted into a copy of the oracle must be caught by
+at least one pin.  Mistakes are planted in the oracle source on the CPU only."""
+import os
+
+import pytest
+
+import oracle
+from oracle_pins import ALL_PINS
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "paircount_oracle.c")
+
+# (name, exact text in the oracle, replacement)
+MUTATIONS = [
+    ("dropped_z_term", "double s = (dx * dx + dy * dy) + dz * dz;", "double s = (dx * dx + dy * dy);"),
+    ("wrong_sign_dy", "double dy = yi - y2[j];", "double dy = yi + y2[j];"),
+    ("wrong_array_z", "double dz = zi - z2[j];", "double dz = zi - y2[j];"),
+    ("bottom_edge_exclusive", "if (s < E[0] || s >= E[nbins])\n                        continue;\n                    int k",
+     "if (s <= E[0] || s >= E[nbins])\n                        continue;\n                    int k"),
+    ("wrap_positive_side_missing", "if (d > half)", "if (d > L)"),
+    ("wrap_wrong_direction", "d -= L;", "d += L;"),
+    ("edge_inclusive_upper", "while (s < E[k])\n                        k--;\n                    bin = k;",
+     "while (s <= E[k] && k > 0)\n                        k--;\n                    bin = k;"),
+    ("top_edge_inclusive", "if (s < E[0] || s >= E[nbins])\n                        continue;\n                    int k",
+     "if (s < E[0] || s > E[nbins])\n                        continue;\n                    int k"),
+    ("unsquared_edges", "E[k] = edges[k] * edges[k];", "E[k] = edges[k];"),
+    ("no_self_pairs", "counts[0] += (uint64_t)n1;", ""),
+    ("no_doubling", "counts[b] *= 2u;", ""),
+    ("auto_includes_diagonal", "autocorr ? i + 1 : 0", "autocorr ? i : 0"),
+    ("pi_cut_inclusive", "pi >= pimax", "pi > pimax"),
+    ("pi_bin_off_by_one", "while (pi < q[p])", "while (pi <= q[p] && p > 0)"),
+    ("rp_uses_dz", "double s = dx * dx + dy * dy;\n                    double pi", "double s = dx * dx + dz * dz;\n                    double pi"),
+    ("chord_not_halved", "2.0 * sin(0.5 * (theta_deg[k] * d2r))", "2.0 * sin(theta_deg[k] * d2r)"),
+    ("radec_swapped_trig", "x[i] = cd * cos(a);", "x[i] = cd * sin(a);"),
+    ("xsum_no_compensation", "double lo = y - (hi - x);", "double lo = 0.0 * (y - (hi - x));"),
+    ("weight_transposed", "double prod = w1[i] * w2[j];", "double prod = w1[i] * w1[j];"),
+    ("weights_not_doubled", "autocorr ? 2.0 * prod : prod", "prod"),
+    ("self_weight_missing", "xacc_add(&total[0], w1[i] * w1[i]);", "(void)0;"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_mutation_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation {name}: pattern not found"
+    mutated = src.replace(old, new, 1)
+    path = tmp_path / "mut.c"
+    path.write_text(mutated)
+    so = str(tmp_path / "libmut.so")
+    oracle.build(src=str(path), out=so)
+    lib = oracle.load(so)
+    failures = []
+    for pin in ALL_PINS:
+        try:
+            pin(lib)
+        except AssertionError:
+            failures.append(pin.__name__)
+        except oracle.OracleError:
+            failures.append(pin.__name__ + "(error)")
+    assert failures, f"planted mistake {name} was not caught by any pin"
