@@ -1,0 +1,219 @@
+/*
+ * paircount.h -- C ABI of the MI355X (gfx950) binned pair counter.
+ *
+ * Binned pair counting of Sinha & Garrison, "Corrfunc" (arXiv:1911.03545):
+ * the brute-force definition of Code 1 (section "How to compute a correlation
+ * function") evaluated with the paper's cell-list method (sections
+ * "Partitioning the particles on a grid", "Associating pairs of cells",
+ * "Symmetry considerations for autocorrelations").  Separations follow
+ * Appendix A, periodic wrapping follows Code 3, the pair convention follows
+ * Appendix B.
+ *
+ * Conventions shared by every counting call
+ * -----------------------------------------
+ *  * Positions are structure-of-arrays (x[], y[], z[]), float32 or float64,
+ *    promoted exactly to binary64.  Weights are optional, float32 or float64.
+ *  * Bin edges e_0 < e_1 < ... < e_nb (e_0 >= 0) are compared in squared
+ *    form: a pair lies in bin k iff fl(e_k*e_k) <= s < fl(e_{k+1}*e_{k+1}),
+ *    with s evaluated in binary64 in the order ((dx*dx + dy*dy) + dz*dz),
+ *    dx = x_i - x_j, and for periodic boxes the wrap of Code 3
+ *    (dx > L/2 -> dx - L; dx <= -L/2 -> dx + L).  Integer counts are
+ *    bit-exact with that definition in both precision modes.
+ *  * counts[] are ordered-pair counts (uint64).  An autocorrelation (d2 ==
+ *    NULL) equals the cross-correlation of d1 with itself, i.e. it includes
+ *    the N self-pairs in bin 0 when e_0 == 0 (Appendix B).
+ *  * wsum[] (optional) is sum over the same pairs of w_i * w_j accumulated in
+ *    binary64; its order of accumulation is not fixed, so it matches the
+ *    exact sum to a relative error of about 1e-13 rather than bit-exactly.
+ *  * boxsize > 0 selects a periodic cube [0, boxsize]^3 (every coordinate
+ *    must lie in the closed interval); boxsize <= 0 selects a non-periodic
+ *    domain bounded by the bounding box of both catalogues.
+ *  * Precision: CF_PREC_FP64 evaluates every pair in binary64 exactly as
+ *    above.  CF_PREC_FP32_RECHECK evaluates pairs in float32 and decides only
+ *    the pairs that a proven error bound places away from every squared edge;
+ *    the remaining pairs are re-evaluated in binary64.  Both give identical
+ *    counts.
+ *
+ * Memory and streams
+ * ------------------
+ *  Inputs are borrowed for the duration of the call and never retained.
+ *  They may be host or device memory (cf_catalog.mem).  Outputs are host
+ *  memory unless cf_options.output_on_device is set.  Work runs on the
+ *  context's HIP stream; every counting call returns only after its results
+ *  are in the output arrays.  A context is not thread safe.
+ *
+ * Errors
+ * ------
+ *  Every function returns a cf_status; on error the outputs are unspecified
+ *  and cf_last_error() describes the failure.  No call aborts the process.
+ */
+#ifndef PAIRCOUNT_H
+#define PAIRCOUNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CF_OK = 0,
+    CF_EINVAL = -1,       /* bad argument: NULL pointer, nbins < 1, edges not
+                             increasing or negative, NaN/Inf, npi < 1,
+                             pimax <= 0, weights on one catalogue only,
+                             unsupported dtype, too many points or bins     */
+    CF_ERANGE = -2,       /* periodic coordinate outside [0, boxsize];
+                             RA outside [0,360], DEC outside [-90,90];
+                             theta edge above 180 degrees                   */
+    CF_ENOMEM = -3,       /* device or pinned-host allocation failed        */
+    CF_EDEVICE = -4,      /* HIP runtime error                              */
+    CF_EUNSUPPORTED = -5, /* periodic reach above boxsize/3                 */
+    CF_EOVERFLOW = -6     /* a count would exceed 2^64 - 1                  */
+} cf_status;
+
+typedef enum { CF_F32 = 1, CF_F64 = 2 } cf_dtype;
+typedef enum { CF_MEM_HOST = 0, CF_MEM_DEVICE = 1 } cf_mem;
+typedef enum { CF_PREC_FP64 = 0, CF_PREC_FP32_RECHECK = 1 } cf_precision;
+
+/* A borrowed view of one catalogue.  For count_pairs_theta x holds RA and y
+   holds DEC in degrees and z is unused, unless cf_options.theta_unit_vectors
+   is set, in which case x, y, z are unit vectors. */
+typedef struct cf_catalog {
+    int64_t n;          /* number of points, >= 0                          */
+    int32_t dtype;      /* cf_dtype of x, y, z                             */
+    int32_t wdtype;     /* cf_dtype of w (ignored when w == NULL)          */
+    int32_t mem;        /* cf_mem: where x, y, z and w live                */
+    int32_t reserved;   /* must be 0                                       */
+    const void *x;
+    const void *y;
+    const void *z;
+    const void *w;      /* NULL: unweighted                                */
+} cf_catalog;
+
+/* Tuning and output options; zero-initialise and set struct_size, or call
+   cf_default_options.  Zero fields take the defaults. */
+typedef struct cf_options {
+    int32_t struct_size;        /* sizeof(cf_options)                          */
+    int32_t slices_per_reach;   /* z slices per line-of-sight reach (default 8) */
+    int32_t chunk;              /* max j points per work item (default 2048)   */
+    int32_t recheck_capacity;   /* initial FP32 recheck queue entries (<= 0:
+                                   default); a queue that overflows makes the
+                                   sweep run again with a larger queue         */
+    int32_t output_on_device;   /* counts / wsum are device pointers           */
+    int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC     */
+    int32_t collect_timing;     /* time phases with HIP events (cf_stats)      */
+    int32_t hist_copies;        /* LDS histogram replicas per wave (0: auto)   */
+    int32_t reserved[8];
+} cf_options;
+
+/* Statistics of the last counting call on a context. */
+typedef struct cf_stats {
+    int32_t grid[3];            /* x columns, y columns, z slices              */
+    int32_t zreach;             /* z slices searched on each side              */
+    double cell_width[3];       /* x, y column widths and z slice width        */
+    int64_t n_blocks;           /* i-blocks of up to 64 points                 */
+    int64_t n_items;            /* work items processed by the pair sweep      */
+    uint64_t candidate_pairs;   /* pair evaluations performed by the sweep     */
+    uint64_t rechecks;          /* FP32 pairs re-evaluated in binary64         */
+    uint64_t sweep_reruns;      /* sweeps repeated after a recheck-queue overflow */
+    int32_t sweep_workgroups;   /* persistent workgroups of the sweep launch   */
+    int32_t hist_copies;        /* LDS histogram replicas per wave             */
+    float t_prepare_ms;         /* validation, conversion, bounding box        */
+    float t_grid_ms;            /* cell index + scan + scatter                 */
+    float t_worklist_ms;        /* blocks + work items                         */
+    float t_sweep_ms;           /* pair sweep kernel                           */
+    float t_recheck_ms;         /* binary64 recheck kernel                     */
+    float t_finalize_ms;        /* doubling, self-pairs, copy-out              */
+    float t_total_ms;           /* whole call, first to last event             */
+    float reserved_f[3];
+} cf_stats;
+
+typedef struct cf_ctx cf_ctx;
+
+/* Create a context on HIP device `device` that enqueues all work on
+   `hip_stream` (a hipStream_t; NULL = the null stream).  The stream stays
+   owned by the caller and must outlive the context. */
+cf_status cf_create(int device, void *hip_stream, cf_ctx **out);
+cf_status cf_destroy(cf_ctx *ctx);
+/* Message of the last failing call on ctx, or with ctx == NULL of the last
+   failing cf_create on this thread (never NULL). */
+const char *cf_last_error(const cf_ctx *ctx);
+cf_status cf_get_stats(const cf_ctx *ctx, cf_stats *out);
+void cf_default_options(cf_options *opt);
+
+/* DD(r) -- Table 1 "xi(r)" / "DD": 3-D separations (Appendix A).
+   counts[nbins], wsum[nbins] (wsum may be NULL). */
+cf_status count_pairs_r(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                        const double *edges, int32_t nbins, double boxsize,
+                        cf_precision prec, uint64_t *counts, double *wsum);
+cf_status count_pairs_r_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                           const double *edges, int32_t nbins, double boxsize,
+                           cf_precision prec, uint64_t *counts, double *wsum,
+                           const cf_options *opt);
+
+/* DD(rp, pi) -- Table 1 "DDrppi" / "wp": rp^2 = dx^2 + dy^2 and pi = |dz|
+   with z the line of sight (Appendix A).  pi bins are q_p = p * fl(pimax/npi)
+   for p < npi and q_npi = pimax, half-open, so pi < pimax; wp(rp) counts are
+   the sums over p.  counts[k * npi + p], wsum likewise. */
+cf_status count_pairs_rppi(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                           const double *rp_edges, int32_t nrp, double pimax,
+                           int32_t npi, double boxsize, cf_precision prec,
+                           uint64_t *counts, double *wsum);
+cf_status count_pairs_rppi_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                              const double *rp_edges, int32_t nrp, double pimax,
+                              int32_t npi, double boxsize, cf_precision prec,
+                              uint64_t *counts, double *wsum, const cf_options *opt);
+
+/* DD(theta) / DR(theta) -- Table 1 "DDtheta_mocks": angular separations
+   (Appendix A, spherical volumes) binned through the squared chord of unit
+   vectors, |v1 - v2|^2 = 2 - 2 cos(theta), a monotone function of theta.
+   Unit vectors v = (cos d cos a, cos d sin a, sin d) with a, d = RA, DEC in
+   radians (degrees * fl(pi/180)) are formed on the device; chord edges
+   c_k = 2 sin(theta_k / 2) on the host.  theta edges in degrees, at most 180.
+   Never periodic.  counts[nbins], wsum[nbins]. */
+cf_status count_pairs_theta(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                            const double *theta_edges_deg, int32_t nbins,
+                            cf_precision prec, uint64_t *counts, double *wsum);
+cf_status count_pairs_theta_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                               const double *theta_edges_deg, int32_t nbins,
+                               cf_precision prec, uint64_t *counts, double *wsum,
+                               const cf_options *opt);
+
+/* Grid plan (host only, no device work) -- the cell grid of section
+   "Partitioning the particles on a grid": columns of width >= reach_xy in x
+   and y (a pair within the reach can only be one column apart), and z
+   slices of width extent_z / n_z with zreach slices searched on each side.
+   lo/hi: bounding box (ignored when boxsize > 0, which selects [0, boxsize]).
+   Returns CF_EUNSUPPORTED when a periodic axis would have fewer than three
+   columns, CF_EINVAL on non-finite or non-positive reaches. */
+typedef struct cf_grid_plan {
+    double lo[3];
+    double extent[3];
+    double inv_width[3];   /* cells per unit length used for cell assignment */
+    double width[3];
+    int32_t n[3];          /* x columns, y columns, z slices                 */
+    int32_t zreach;
+    int32_t periodic;
+    int32_t reserved;
+    double boxsize;
+    int64_t ncell;
+} cf_grid_plan;
+cf_status cf_plan_grid(const double lo[3], const double hi[3], double boxsize,
+                       double reach_xy, double reach_z, int32_t slices_per_reach,
+                       cf_grid_plan *out);
+
+/* Float32 decision bands (host only) -- for each squared edge E_k the float32
+   interval [lo_k, hi_k] outside which a float32-evaluated separation decides
+   the comparison with E_k the same way as the binary64 definition.  `ndim`
+   is the number of squared axis differences summed (3 for r and theta, 2 for
+   rp^2, 1 for the line-of-sight pi with E_k given unsquared); `coord_scale`
+   bounds the magnitude of every coordinate and periodic offset.  A zero edge
+   gets the empty band [-1, -1].  Returns CF_EINVAL on bad input. */
+cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32_t ndim,
+                        double coord_scale, float *lo, float *hi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAIRCOUNT_H */

@@ -1,0 +1,393 @@
+"""MI355X (gfx950) binned pair counting -- Python binding of ``libpaircount.so``.
+
+The library counts pairs of points in separation bins as defined by Sinha &
+Garrison (Corrfunc, arXiv:1911.03545): DD(r), DD(rp, pi) / wp(rp) and
+DD(theta) / DR(theta), autocorrelations and cross-correlations, periodic or
+not, optionally weighted by the product of point weights.  Every step of the
+computation runs in the library's HIP kernels; this module only marshals
+arguments (NumPy arrays stay in host memory, torch CUDA tensors are passed by
+device pointer) and converts status codes into exceptions.
+
+The shared library is built in-tree with ``python -m paper_1911_03545_amd.build``.
+There is no CPU fallback: without the library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpaircount.so")
+
+CF_OK, CF_EINVAL, CF_ERANGE, CF_ENOMEM, CF_EDEVICE, CF_EUNSUPPORTED, CF_EOVERFLOW = (
+    0, -1, -2, -3, -4, -5, -6)
+CF_F32, CF_F64 = 1, 2
+CF_MEM_HOST, CF_MEM_DEVICE = 0, 1
+CF_PREC_FP64, CF_PREC_FP32_RECHECK = 0, 1
+
+STATUS_NAMES = {
+    CF_OK: "CF_OK", CF_EINVAL: "CF_EINVAL", CF_ERANGE: "CF_ERANGE",
+    CF_ENOMEM: "CF_ENOMEM", CF_EDEVICE: "CF_EDEVICE",
+    CF_EUNSUPPORTED: "CF_EUNSUPPORTED", CF_EOVERFLOW: "CF_EOVERFLOW",
+}
+
+EXPORTED_SYMBOLS = (
+    "cf_create", "cf_destroy", "cf_last_error", "cf_get_stats", "cf_default_options",
+    "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
+    "count_pairs_theta", "count_pairs_theta_ex", "cf_plan_grid", "cf_fp32_bands",
+)
+
+
+class cf_catalog(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("wdtype", ctypes.c_int32), ("mem", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class cf_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("slices_per_reach", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("recheck_capacity", ctypes.c_int32),
+                ("output_on_device", ctypes.c_int32), ("theta_unit_vectors", ctypes.c_int32),
+                ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class cf_stats(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32 * 3), ("zreach", ctypes.c_int32),
+                ("cell_width", ctypes.c_double * 3), ("n_blocks", ctypes.c_int64),
+                ("n_items", ctypes.c_int64), ("candidate_pairs", ctypes.c_uint64),
+                ("rechecks", ctypes.c_uint64), ("sweep_reruns", ctypes.c_uint64),
+                ("sweep_workgroups", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
+                ("t_prepare_ms", ctypes.c_float), ("t_grid_ms", ctypes.c_float),
+                ("t_worklist_ms", ctypes.c_float), ("t_sweep_ms", ctypes.c_float),
+                ("t_recheck_ms", ctypes.c_float), ("t_finalize_ms", ctypes.c_float),
+                ("t_total_ms", ctypes.c_float), ("reserved_f", ctypes.c_float * 3)]
+
+
+class cf_grid_plan(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("extent", ctypes.c_double * 3),
+                ("inv_width", ctypes.c_double * 3), ("width", ctypes.c_double * 3),
+                ("n", ctypes.c_int32 * 3), ("zreach", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("boxsize", ctypes.c_double), ("ncell", ctypes.c_int64)]
+
+
+class PairCountError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpaircount.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library with "
+            "'python -m paper_1911_03545_amd.build' (there is no CPU fallback)")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # loading torch first makes the library bind to that single runtime, so
+    # both share one device context (loading the system runtime first leaves
+    # torch without a usable GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    cat = ctypes.POINTER(cf_catalog)
+    lib.cf_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.cf_create.restype = ctypes.c_int
+    lib.cf_destroy.argtypes = [vp]
+    lib.cf_destroy.restype = ctypes.c_int
+    lib.cf_last_error.argtypes = [vp]
+    lib.cf_last_error.restype = ctypes.c_char_p
+    lib.cf_get_stats.argtypes = [vp, ctypes.POINTER(cf_stats)]
+    lib.cf_get_stats.restype = ctypes.c_int
+    lib.cf_default_options.argtypes = [ctypes.POINTER(cf_options)]
+    lib.cf_default_options.restype = None
+    for name in ("count_pairs_r", "count_pairs_r_ex"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, cat, cat, vp, i32, dbl, ctypes.c_int, vp, vp] + (
+            [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
+        f.restype = ctypes.c_int
+    for name in ("count_pairs_rppi", "count_pairs_rppi_ex"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, cat, cat, vp, i32, dbl, i32, dbl, ctypes.c_int, vp, vp] + (
+            [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
+        f.restype = ctypes.c_int
+    for name in ("count_pairs_theta", "count_pairs_theta_ex"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, cat, cat, vp, i32, ctypes.c_int, vp, vp] + (
+            [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
+        f.restype = ctypes.c_int
+    lib.cf_plan_grid.argtypes = [vp, vp, dbl, dbl, dbl, i32, ctypes.POINTER(cf_grid_plan)]
+    lib.cf_plan_grid.restype = ctypes.c_int
+    lib.cf_fp32_bands.argtypes = [vp, i32, i32, dbl, vp, vp]
+    lib.cf_fp32_bands.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def default_options(**overrides) -> cf_options:
+    lib = load_library()
+    o = cf_options()
+    lib.cf_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, int(v))
+    return o
+
+
+def plan_grid(lo, hi, boxsize: float, reach_xy: float, reach_z: float,
+              slices_per_reach: int = 8) -> dict:
+    """Host-only grid plan (no device needed)."""
+    lib = load_library()
+    lo_a = np.ascontiguousarray(lo if lo is not None else [0, 0, 0], dtype=np.float64)
+    hi_a = np.ascontiguousarray(hi if hi is not None else [0, 0, 0], dtype=np.float64)
+    p = cf_grid_plan()
+    st = lib.cf_plan_grid(lo_a.ctypes.data, hi_a.ctypes.data, float(boxsize), float(reach_xy),
+                          float(reach_z), int(slices_per_reach), ctypes.byref(p))
+    if st != CF_OK:
+        raise PairCountError(st, "cf_plan_grid failed")
+    return {"n": list(p.n), "width": list(p.width), "extent": list(p.extent),
+            "inv_width": list(p.inv_width), "lo": list(p.lo), "zreach": p.zreach,
+            "periodic": p.periodic, "ncell": p.ncell}
+
+
+def fp32_bands(edges_sq, ndim: int, coord_scale: float):
+    """Host-only float32 decision bands of squared (or line-of-sight) edges."""
+    lib = load_library()
+    e = np.ascontiguousarray(edges_sq, dtype=np.float64)
+    lo = np.zeros(e.size, dtype=np.float32)
+    hi = np.zeros(e.size, dtype=np.float32)
+    st = lib.cf_fp32_bands(e.ctypes.data, e.size, int(ndim), float(coord_scale),
+                           lo.ctypes.data, hi.ctypes.data)
+    if st != CF_OK:
+        raise PairCountError(st, "cf_fp32_bands failed")
+    return lo, hi
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class _Cat:
+    """Marshal one catalogue; keeps referenced buffers alive."""
+
+    def __init__(self, pts, w=None, two_columns: bool = False):
+        self.keep = []
+        if isinstance(pts, (tuple, list)):
+            cols = list(pts)
+        else:
+            if _is_torch(pts):
+                ncol = pts.shape[1]
+                cols = [pts[:, k].contiguous() for k in range(ncol)]
+            else:
+                arr = np.asarray(pts)
+                if arr.ndim != 2:
+                    raise ValueError("positions must be (n, 3) or a tuple of columns")
+                cols = [np.ascontiguousarray(arr[:, k]) for k in range(arr.shape[1])]
+        need = 2 if two_columns else 3
+        if len(cols) < need:
+            raise ValueError(f"need {need} coordinate columns")
+        c = cf_catalog()
+        dev = _is_torch(cols[0]) and cols[0].is_cuda
+        c.mem = CF_MEM_DEVICE if dev else CF_MEM_HOST
+        ptrs = []
+        dts = set()
+        for col in cols[:3]:
+            p, dt, n = self._ptr(col, dev)
+            ptrs.append(p)
+            dts.add(dt)
+            c.n = n
+        if len(dts) != 1:
+            raise ValueError("coordinate columns must share one dtype")
+        c.dtype = dts.pop()
+        c.x, c.y = ptrs[0], ptrs[1]
+        c.z = ptrs[2] if len(ptrs) > 2 else None
+        if w is not None:
+            if _is_torch(w) != dev:
+                raise ValueError("weights must live where the coordinates live")
+            p, dt, n = self._ptr(w, dev)
+            if n != c.n:
+                raise ValueError("weights and positions differ in length")
+            c.w, c.wdtype = p, dt
+        self.c = c
+
+    def _ptr(self, col, dev):
+        if dev:
+            import torch
+            if not col.is_contiguous():
+                col = col.contiguous()
+            if col.dtype == torch.float32:
+                dt = CF_F32
+            elif col.dtype == torch.float64:
+                dt = CF_F64
+            else:
+                raise TypeError("coordinates must be float32 or float64")
+            self.keep.append(col)
+            return col.data_ptr(), dt, col.numel()
+        a = np.asarray(col)
+        if a.dtype == np.float32:
+            dt = CF_F32
+        elif a.dtype == np.float64:
+            dt = CF_F64
+        else:
+            a = a.astype(np.float64)
+            dt = CF_F64
+        a = np.ascontiguousarray(a)
+        self.keep.append(a)
+        return a.ctypes.data, dt, a.size
+
+
+class PairCounter:
+    """A library context bound to one device and one HIP stream.
+
+    ``stream``: a HIP stream handle (int) or a torch.cuda.Stream; by default
+    torch's current stream on ``device`` when torch is importable, else the
+    null stream.
+    """
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = load_library()
+        handle = None
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    handle = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                handle = None
+        elif hasattr(stream, "cuda_stream"):
+            handle = stream.cuda_stream
+        else:
+            handle = int(stream)
+        ctx = ctypes.c_void_p()
+        st = self._lib.cf_create(int(device), handle, ctypes.byref(ctx))
+        if st != CF_OK:
+            msg = self._lib.cf_last_error(None)
+            raise PairCountError(st, f"cf_create(device={device}): "
+                                     f"{msg.decode() if msg else ''}")
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.cf_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st != CF_OK:
+            msg = self._lib.cf_last_error(self._ctx)
+            raise PairCountError(st, msg.decode() if msg else "")
+
+    @staticmethod
+    def _prec(precision):
+        if precision in ("fp64", CF_PREC_FP64):
+            return CF_PREC_FP64
+        if precision in ("fp32", "fp32_recheck", CF_PREC_FP32_RECHECK):
+            return CF_PREC_FP32_RECHECK
+        raise ValueError(f"unknown precision {precision!r}")
+
+    def _opts(self, options):
+        if options is None:
+            return None
+        if isinstance(options, cf_options):
+            return ctypes.byref(options)
+        return ctypes.byref(default_options(**options))
+
+    def count_r(self, d1, d2=None, edges=None, boxsize: float = 0.0, precision="fp64",
+                w1=None, w2=None, options=None):
+        """DD(r): returns (counts uint64[nb], wsum float64[nb] or None)."""
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        nb = e.size - 1
+        c1 = _Cat(d1, w1)
+        c2 = None if d2 is None else _Cat(d2, w2 if w2 is not None else None)
+        counts = np.zeros(nb, dtype=np.uint64)
+        wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
+        st = self._lib.count_pairs_r_ex(
+            self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
+            e.ctypes.data, nb, float(boxsize), self._prec(precision), counts.ctypes.data,
+            None if wsum is None else wsum.ctypes.data, self._opts(options))
+        self._check(st)
+        return counts, wsum
+
+    def count_rppi(self, d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
+                   boxsize: float = 0.0, precision="fp64", w1=None, w2=None, options=None):
+        """DD(rp, pi): returns (counts uint64[nrp, npi], wsum or None)."""
+        e = np.ascontiguousarray(rp_edges, dtype=np.float64)
+        nb = e.size - 1
+        c1 = _Cat(d1, w1)
+        c2 = None if d2 is None else _Cat(d2, w2)
+        counts = np.zeros(nb * int(npi), dtype=np.uint64)
+        wsum = np.zeros(nb * int(npi), dtype=np.float64) if w1 is not None else None
+        st = self._lib.count_pairs_rppi_ex(
+            self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
+            e.ctypes.data, nb, float(pimax), int(npi), float(boxsize), self._prec(precision),
+            counts.ctypes.data, None if wsum is None else wsum.ctypes.data, self._opts(options))
+        self._check(st)
+        counts = counts.reshape(nb, int(npi))
+        if wsum is not None:
+            wsum = wsum.reshape(nb, int(npi))
+        return counts, wsum
+
+    def count_theta(self, ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
+                    precision="fp64", w1=None, w2=None, options=None, unit_vectors=None):
+        """DD(theta)/DR(theta) from RA/DEC in degrees (or unit vectors when
+        ``unit_vectors=(v1, v2)`` is given)."""
+        e = np.ascontiguousarray(theta_edges_deg, dtype=np.float64)
+        nb = e.size - 1
+        if unit_vectors is not None:
+            v1, v2 = unit_vectors
+            c1 = _Cat(v1, w1)
+            c2 = None if v2 is None else _Cat(v2, w2)
+            opt = default_options(theta_unit_vectors=1)
+            if options:
+                for k, v in (options.items() if isinstance(options, dict) else []):
+                    setattr(opt, k, int(v))
+            optp = ctypes.byref(opt)
+        else:
+            c1 = _Cat((ra1, dec1), w1, two_columns=True)
+            c2 = None if ra2 is None else _Cat((ra2, dec2), w2, two_columns=True)
+            optp = self._opts(options)
+        counts = np.zeros(nb, dtype=np.uint64)
+        wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
+        st = self._lib.count_pairs_theta_ex(
+            self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
+            e.ctypes.data, nb, self._prec(precision), counts.ctypes.data,
+            None if wsum is None else wsum.ctypes.data, optp)
+        self._check(st)
+        return counts, wsum
+
+    def stats(self) -> dict:
+        s = cf_stats()
+        self._check(self._lib.cf_get_stats(self._ctx, ctypes.byref(s)))
+        out = {}
+        for name, _ in cf_stats._fields_:
+            v = getattr(s, name)
+            if hasattr(v, "__len__"):
+                v = list(v)
+            out[name] = v
+        return out

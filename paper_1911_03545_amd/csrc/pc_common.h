@@ -1,0 +1,81 @@
+// pc_common.h -- layouts shared by the host planner and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#define PC_WAVE 64
+#define PC_BLOCK_I 64          // i points per work item: one per lane
+#define PC_TBL_MAX 8192        // bin lookup table entries (uint16)
+#define PC_MAX_EDGES 1025      // r / rp / theta edges
+#define PC_MAX_NPI 1024
+#define PC_MAX_BINS_TOTAL 4096 // r bins, or nrp * npi
+#define PC_MAX_HIST_WAVE 4096  // uint32 LDS counters per wave (bins * copies)
+
+// lookup-table entry flags (uint16): low 14 bits = number of edges whose
+// band lies entirely below the table cell.
+#define PC_TBL_BAND 0x8000u    // exactly one band (of edge `low bits`) meets the cell
+#define PC_TBL_MULTI 0x4000u   // several bands meet the cell: search them all
+#define PC_TBL_MASK 0x3FFFu
+
+// Periodic offset codes, two bits per axis: 0 -> 0, 1 -> +L, 2 -> -L.
+#define PC_D_ZERO 0u
+#define PC_D_PLUS 1u
+#define PC_D_MINUS 2u
+
+enum { PC_METRIC_R = 0, PC_METRIC_RPPI = 1 };
+
+// Cell grid: x/y columns of width >= the transverse reach, z slices.
+// Cell id = (ix * ny + iy) * nz + iz, so columns are contiguous runs of cells
+// ordered by z.
+struct pc_grid {
+    double lo[3];
+    double extent[3];
+    double inv_w[3];
+    double width[3];
+    int32_t n[3];
+    int32_t zreach;
+    int32_t periodic;
+    int32_t pad;
+    double boxsize;
+    int64_t ncell;
+};
+
+// A block: up to 64 consecutive sorted points of one column (one per lane).
+struct pc_block {
+    int32_t col;
+    int32_t i0;
+    int32_t ni;
+    int32_t pad;
+};
+
+// A work item: the block's points i0 .. i0+ni-1 against sorted points
+// j0 .. j1-1 of the second catalogue, with one periodic offset.
+struct pc_item {
+    int32_t i0;
+    int32_t j0;
+    int32_t j1;
+    uint32_t meta;   // [0,6) ni-1, [6,12) offset codes x|y<<2|z<<4, [12] triangle
+};
+#define PC_META_NI(m) (((m) & 63u) + 1)
+#define PC_META_DCODE(m) (((m) >> 6) & 63u)
+#define PC_META_TRI(m) (((m) >> 12) & 1u)
+
+// Bin description uploaded once per call; float bands are [lo_k, hi_k].
+struct pc_bins {
+    int32_t nb;          // r / rp bins
+    int32_t npi;         // pi bins (1 for r and theta)
+    int32_t tbl_shift;   // key = float_bits(s) >> tbl_shift
+    int32_t tbl_n;       // used table entries
+    int32_t e0_zero;     // first r / rp edge is exactly zero
+    int32_t pad;
+    float s_top;         // float32 prefilter: candidate only if s32 <= s_top
+    float pi_top;        // rppi: candidate only if pi32 <= pi_top
+    float inv_dpi;       // rppi: npi / pimax in float32
+    float pi_tau;        // rppi: margin of the fractional part of |dz| * inv_dpi
+    double E_top;        // binary64 cut: s64 < E_top
+    double pimax;        // binary64 cut: pi64 < pimax
+};
+
+// Offsets (bytes) of the arrays packed after pc_bins in one device buffer.
+struct pc_bins_layout {
+    size_t lo, hi, E, plo, phi, q, tbl, total;
+};

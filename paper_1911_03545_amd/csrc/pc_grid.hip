@@ -1,0 +1,516 @@
+// pc_grid.hip -- input staging, gridding (cell index + counting sort) and the
+// work-list kernels for gfx950.
+//
+// Gridding follows section "Partitioning the particles on a grid" (cell index
+// of each point from the bounding box and the cell count per axis) and
+// section "Improving cache locality" (points copied into contiguous per-cell
+// arrays), done as a parallel counting sort: an atomic histogram of cell ids,
+// an exclusive scan, and a scatter into structure-of-arrays buffers.
+//
+// The work list follows sections "Associating pairs of cells" and "Symmetry
+// considerations for autocorrelations": for each block of up to 64 points of
+// one x/y column, the neighbouring columns (periodic indices wrapped with a
+// stored offset of +-L) and, inside each, the contiguous run of z slices that
+// can hold a partner within the line-of-sight reach.
+#include <hip/hip_runtime.h>
+
+#include "pc_common.h"
+#include "pc_launch.h"
+
+namespace pc {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double ld(const void *p, int f32, int64_t i)
+{
+    return f32 ? (double)static_cast<const float *>(p)[i] : static_cast<const double *>(p)[i];
+}
+
+int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return (int)g;
+}
+
+// RA/DEC (degrees) -> unit vectors; d2r = fl(pi) / 180 as a binary64 value.
+__global__ void k_radec(int64_t n, const void *ra, const void *dec, int f32, double d2r,
+                        double *x, double *y, double *z, unsigned *flags)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = ld(ra, f32, i), d = ld(dec, f32, i);
+        if (!(a >= 0.0 && a <= 360.0 && d >= -90.0 && d <= 90.0))
+            atomicOr(flags, PC_FLAG_RADEC);
+        const double ar = a * d2r, dr = d * d2r;
+        const double cd = cos(dr);
+        x[i] = cd * cos(ar);
+        y[i] = cd * sin(ar);
+        z[i] = sin(dr);
+    }
+}
+
+__global__ void k_minmax(int64_t n, const void *x, const void *y, const void *z, int f32,
+                         double *part, unsigned *flags)
+{
+    double mn[3] = {INFINITY, INFINITY, INFINITY};
+    double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double c[3] = {ld(x, f32, i), ld(y, f32, i), ld(z, f32, i)};
+        for (int a = 0; a < 3; a++) {
+            if (!isfinite(c[a]))
+                bad = true;
+            else {
+                mn[a] = fmin(mn[a], c[a]);
+                mx[a] = fmax(mx[a], c[a]);
+            }
+        }
+    }
+    if (bad)
+        atomicOr(flags, PC_FLAG_NONFINITE);
+    __shared__ double sm[6][kThreads];
+    for (int a = 0; a < 3; a++) {
+        sm[a][threadIdx.x] = mn[a];
+        sm[3 + a][threadIdx.x] = mx[a];
+    }
+    __syncthreads();
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int a = 0; a < 3; a++) {
+                sm[a][threadIdx.x] = fmin(sm[a][threadIdx.x], sm[a][threadIdx.x + st]);
+                sm[3 + a][threadIdx.x] =
+                    fmax(sm[3 + a][threadIdx.x], sm[3 + a][threadIdx.x + st]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; a++)
+            part[blockIdx.x * 6 + a] = sm[a][0];
+}
+
+__global__ void k_minmax_final(const double *part, int nparts, double *out6)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int p = 0; p < nparts; p++)
+        for (int a = 0; a < 3; a++) {
+            r[a] = fmin(r[a], part[p * 6 + a]);
+            r[3 + a] = fmax(r[3 + a], part[p * 6 + 3 + a]);
+        }
+    for (int a = 0; a < 6; a++)
+        out6[a] = r[a];
+}
+
+__global__ void k_check_weights(int64_t n, const void *w, int f32, unsigned *flags)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(ld(w, f32, i)))
+            atomicOr(flags, PC_FLAG_WEIGHT);
+}
+
+// Cell coordinate: t = fl(fl(x - lo) * inv_w) is monotone in x; NaN and
+// negative values go to cell 0 and values at or past the far face to n - 1.
+__device__ __forceinline__ int cell_coord(double d, double inv, int n)
+{
+    const double t = d * inv;
+    if (!(t > 0.0))
+        return 0;
+    if (t >= (double)(n - 1))
+        return n - 1;
+    return (int)t;
+}
+
+__global__ void k_cell_index(int64_t n, const void *x, const void *y, const void *z, int f32,
+                             pc_grid g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
+                             unsigned *flags)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double c[3] = {ld(x, f32, i), ld(y, f32, i), ld(z, f32, i)};
+        int ia[3];
+        unsigned fl = 0;
+        for (int a = 0; a < 3; a++) {
+            if (!isfinite(c[a]))
+                fl |= PC_FLAG_NONFINITE;
+            else if (g.periodic && (c[a] < 0.0 || c[a] > g.boxsize))
+                fl |= PC_FLAG_RANGE;
+            ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
+        }
+        if (fl)
+            atomicOr(flags, fl);
+        const int cell = (ia[0] * g.n[1] + ia[1]) * g.n[2] + ia[2];
+        cell_of[i] = cell;
+        rank_of[i] = (int32_t)atomicAdd(&cnt[cell], 1u);
+    }
+}
+
+// ---- exclusive scan (int32), 1024 values per workgroup -------------------
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kThreads * kScanPer;
+
+__device__ int block_exclusive(int v, int *total)
+{
+    __shared__ int sm[kThreads];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        int t = (int)threadIdx.x >= off ? sm[threadIdx.x - off] : 0;
+        __syncthreads();
+        sm[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int incl = sm[threadIdx.x];
+    *total = sm[kThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_reduce(const int32_t *in, int64_t n, int32_t *part)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int s = 0;
+    for (int k = 0; k < kScanPer; k++)
+        if (base + k < n)
+            s += in[base + k];
+    int total;
+    block_exclusive(s, &total);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = total;
+}
+
+// out[i] = exclusive prefix + offset[block]; the workgroup holding the end
+// also writes out[n].
+__global__ void k_scan_apply(const int32_t *in, int64_t n, const int32_t *offs, int32_t *out)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int s = 0;
+    for (int k = 0; k < kScanPer; k++) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_exclusive(s, &total) + (offs ? offs[blockIdx.x] : 0);
+    for (int k = 0; k < kScanPer; k++) {
+        if (base + k < n)
+            out[base + k] = run;
+        run += v[k];
+    }
+    const int64_t end = (int64_t)(blockIdx.x + 1) * kScanBlock;
+    if (threadIdx.x == kThreads - 1 && end >= n)
+        out[n] = run;
+}
+
+// ---- scatter into per-cell contiguous structure-of-arrays ----------------
+__global__ void k_scatter(int64_t n, const void *x, const void *y, const void *z, int f32,
+                          const void *w, int wf32, pc_grid g, const int32_t *cell_of,
+                          const int32_t *rank_of, const int32_t *start, float *X, float *Y,
+                          float *Z, double *xd, double *yd, double *zd, double *wd,
+                          int32_t *cell_sorted)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int cell = cell_of[i];
+        const int64_t d = (int64_t)start[cell] + rank_of[i];
+        const double cx = ld(x, f32, i), cy = ld(y, f32, i), cz = ld(z, f32, i);
+        X[d] = (float)(cx - g.lo[0]);
+        Y[d] = (float)(cy - g.lo[1]);
+        Z[d] = (float)(cz - g.lo[2]);
+        xd[d] = cx;
+        yd[d] = cy;
+        zd[d] = cz;
+        if (w)
+            wd[d] = ld(w, wf32, i);
+        cell_sorted[d] = cell;
+    }
+}
+
+// ---- blocks of up to 64 points per column --------------------------------
+__global__ void k_block_count(int32_t ncol, int32_t nz, const int32_t *start, int32_t *bcnt)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += gridDim.x * blockDim.x) {
+        const int a = start[(int64_t)c * nz], b = start[(int64_t)(c + 1) * nz];
+        bcnt[c] = (b - a + PC_BLOCK_I - 1) / PC_BLOCK_I;
+    }
+}
+
+__global__ void k_block_emit(int32_t ncol, int32_t nz, const int32_t *start,
+                             const int32_t *boff, pc_block *blocks)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += gridDim.x * blockDim.x) {
+        const int a = start[(int64_t)c * nz], b = start[(int64_t)(c + 1) * nz];
+        int o = boff[c];
+        for (int i0 = a; i0 < b; i0 += PC_BLOCK_I, o++) {
+            pc_block blk;
+            blk.col = c;
+            blk.i0 = i0;
+            blk.ni = min(PC_BLOCK_I, b - i0);
+            blk.pad = 0;
+            blocks[o] = blk;
+        }
+    }
+}
+
+// ---- segments of one block ------------------------------------------------
+struct SegCtx {
+    pc_grid g;
+    const int32_t *start2;
+    const int32_t *cell1_sorted;
+    int autocorr;
+};
+
+// Calls f(j0, j1, dcode, tri) for every run of second-catalogue points the
+// block must be paired with.  dcode packs the periodic offset codes
+// (x | y << 2 | z << 4).
+//
+// Autocorrelation visits each unordered pair once: the block's own column
+// forward along the sorted order (the triangle j > i inside the block, then
+// later points up to zreach slices beyond the block's last slice, then the
+// periodic wrap past the top face), and the four columns (0,+1), (+1,-1),
+// (+1,0), (+1,+1) over the full z window.  Cross-correlation visits all nine
+// columns over the full window.
+template <class F>
+__device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
+{
+    const int nx = c.g.n[0], ny = c.g.n[1], nz = c.g.n[2];
+    const int ix = b.col / ny, iy = b.col % ny;
+    const int sa = c.cell1_sorted[b.i0] % nz;
+    const int sb = c.cell1_sorted[b.i0 + b.ni - 1] % nz;
+    const int zr = c.g.zreach;
+    const bool per = c.g.periodic != 0;
+
+    auto zwin = [&](int ccol, unsigned dxy) {
+        const int64_t base = (int64_t)ccol * nz;
+        const int lo_s = sa - zr, hi_s = sb + zr;
+        const int a0 = max(lo_s, 0), a1 = min(hi_s, nz - 1);
+        if (a0 <= a1)
+            f(c.start2[base + a0], c.start2[base + a1 + 1], dxy, 0);
+        if (per) {
+            if (lo_s < 0) {
+                const int w0 = max(lo_s + nz, 0);
+                f(c.start2[base + w0], c.start2[base + nz], dxy | (PC_D_PLUS << 4), 0);
+            }
+            if (hi_s >= nz) {
+                const int w1 = min(hi_s - nz, nz - 1);
+                f(c.start2[base], c.start2[base + w1 + 1], dxy | (PC_D_MINUS << 4), 0);
+            }
+        }
+    };
+    auto column = [&](int ox, int oy) {
+        int jx = ix + ox, jy = iy + oy;
+        unsigned code = 0;
+        if (jx < 0 || jx >= nx) {
+            if (!per)
+                return;
+            code |= (jx < 0) ? PC_D_PLUS : PC_D_MINUS;
+            jx = (jx < 0) ? jx + nx : jx - nx;
+        }
+        if (jy < 0 || jy >= ny) {
+            if (!per)
+                return;
+            code |= ((jy < 0) ? PC_D_PLUS : PC_D_MINUS) << 2;
+            jy = (jy < 0) ? jy + ny : jy - ny;
+        }
+        zwin(jx * ny + jy, code);
+    };
+
+    if (c.autocorr) {
+        if (b.ni > 1)
+            f(b.i0 + 1, b.i0 + b.ni, 0u, 1);
+        const int64_t base = (int64_t)b.col * nz;
+        const int hi_s = sb + zr;
+        const int jend = c.start2[base + min(hi_s, nz - 1) + 1];
+        if (jend > b.i0 + b.ni)
+            f(b.i0 + b.ni, jend, 0u, 0);
+        if (per && hi_s >= nz) {
+            const int w1 = min(hi_s - nz, nz - 1);
+            f(c.start2[base], c.start2[base + w1 + 1], PC_D_MINUS << 4, 0);
+        }
+        column(0, 1);
+        column(1, -1);
+        column(1, 0);
+        column(1, 1);
+    } else {
+        for (int ox = -1; ox <= 1; ox++)
+            for (int oy = -1; oy <= 1; oy++)
+                column(ox, oy);
+    }
+}
+
+__global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
+                             const pc_block *blocks, SegCtx c, int chunk, int32_t *icnt,
+                             unsigned long long *cand)
+{
+    const int nb = nblocks_dev ? *nblocks_dev : nblocks;
+    unsigned long long my = 0;
+    for (int bi = blockIdx.x * blockDim.x + threadIdx.x; bi < nb;
+         bi += gridDim.x * blockDim.x) {
+        const pc_block b = blocks[bi];
+        int total = 0;
+        for_each_segment(c, b, [&](int j0, int j1, unsigned, int tri) {
+            if (j1 <= j0)
+                return;
+            total += (j1 - j0 + chunk - 1) / chunk;
+            my += tri ? (unsigned long long)b.ni * (b.ni - 1) / 2
+                      : (unsigned long long)b.ni * (unsigned long long)(j1 - j0);
+        });
+        icnt[bi] = total;
+    }
+    if (my)
+        atomicAdd(cand, my);
+}
+
+__global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const pc_block *blocks,
+                            SegCtx c, int chunk, const int32_t *ioff, pc_item *items)
+{
+    const int nb = nblocks_dev ? *nblocks_dev : nblocks;
+    for (int bi = blockIdx.x * blockDim.x + threadIdx.x; bi < nb;
+         bi += gridDim.x * blockDim.x) {
+        const pc_block b = blocks[bi];
+        int o = ioff[bi];
+        for_each_segment(c, b, [&](int j0, int j1, unsigned dcode, int tri) {
+            for (int j = j0; j < j1; j += chunk) {
+                pc_item it;
+                it.i0 = b.i0;
+                it.j0 = j;
+                it.j1 = min(j + chunk, j1);
+                it.meta = (unsigned)(b.ni - 1) | (dcode << 6) | ((unsigned)tri << 12);
+                items[o++] = it;
+            }
+        });
+    }
+}
+
+}  // namespace
+
+hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
+                        double d2r, double *x, double *y, double *z, unsigned *flags)
+{
+    hipLaunchKernelGGL(k_radec, dim3(grid_for(n)), dim3(kThreads), 0, s, n, ra, dec, f32, d2r,
+                       x, y, z, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(hipStream_t s, int64_t n, const void *x, const void *y, const void *z,
+                         int f32, double *part, int nparts, unsigned *flags)
+{
+    hipLaunchKernelGGL(k_minmax, dim3(nparts), dim3(kThreads), 0, s, n, x, y, z, f32, part,
+                       flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, double *out6)
+{
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, s, part, nparts, out6);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_weights(hipStream_t s, int64_t n, const void *w, int f32,
+                                unsigned *flags)
+{
+    hipLaunchKernelGGL(k_check_weights, dim3(grid_for(n)), dim3(kThreads), 0, s, n, w, f32,
+                       flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_index(hipStream_t s, int64_t n, const void *x, const void *y,
+                             const void *z, int f32, const pc_grid &g, unsigned *cnt,
+                             int32_t *cell_of, int32_t *rank_of, unsigned *flags)
+{
+    hipLaunchKernelGGL(k_cell_index, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, f32,
+                       g, cnt, cell_of, rank_of, flags);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_elems(int64_t n)
+{
+    size_t total = 0;
+    while (n > kScanBlock) {
+        const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+        total += (size_t)nb + (size_t)nb + 1;
+        n = nb;
+    }
+    return total + 1;
+}
+
+hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *out,
+                          int32_t *tmp)
+{
+    if (n <= kScanBlock) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kThreads), 0, s, in, n,
+                           (const int32_t *)nullptr, out);
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    int32_t *part = tmp;
+    int32_t *part_scan = tmp + nb;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    e = scan_exclusive(s, part, nb, part_scan, tmp + 2 * nb + 1);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, in, n,
+                       (const int32_t *)part_scan, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t s, int64_t n, const void *x, const void *y, const void *z,
+                          int f32, const void *w, int wf32, const pc_grid &g,
+                          const int32_t *cell_of, const int32_t *rank_of, const int32_t *start,
+                          float *X, float *Y, float *Z, double *xd, double *yd, double *zd,
+                          double *wd, int32_t *cell_sorted)
+{
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, f32, w,
+                       wf32, g, cell_of, rank_of, start, X, Y, Z, xd, yd, zd, wd, cell_sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
+                              int32_t *bcnt)
+{
+    hipLaunchKernelGGL(k_block_count, dim3(grid_for(ncol)), dim3(kThreads), 0, s, ncol, nz,
+                       start, bcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_emit(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
+                             const int32_t *boff, pc_block *blocks)
+{
+    hipLaunchKernelGGL(k_block_emit, dim3(grid_for(ncol, 64)), dim3(64), 0, s, ncol, nz, start,
+                       boff, blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
+                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
+                             const int32_t *cell1_sorted, int autocorr, int chunk,
+                             int32_t *icnt, unsigned long long *cand)
+{
+    SegCtx c{g, start2, cell1_sorted, autocorr};
+    hipLaunchKernelGGL(k_item_count, dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
+                       nblocks_dev, blocks, c, chunk, icnt, cand);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
+                            const pc_block *blocks, const pc_grid &g, const int32_t *start2,
+                            const int32_t *cell1_sorted, int autocorr, int chunk,
+                            const int32_t *ioff, pc_item *items)
+{
+    SegCtx c{g, start2, cell1_sorted, autocorr};
+    hipLaunchKernelGGL(k_item_emit, dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
+                       nblocks_dev, blocks, c, chunk, ioff, items);
+    return hipGetLastError();
+}
+
+}  // namespace pc

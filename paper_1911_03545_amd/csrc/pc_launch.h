@@ -1,0 +1,86 @@
+// pc_launch.h -- host-callable launchers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pc_common.h"
+
+namespace pc {
+
+// flags raised by the input kernels
+#define PC_FLAG_NONFINITE 1u
+#define PC_FLAG_RANGE 2u
+#define PC_FLAG_WEIGHT 4u
+#define PC_FLAG_RADEC 8u
+
+struct SweepArgs {
+    const pc_item *items;
+    int32_t n_items;
+    int32_t *counter;
+    const float *X1, *Y1, *Z1, *X2, *Y2, *Z2;    // float32, box frame
+    const double *x1, *y1, *z1, *x2, *y2, *z2;   // binary64, input values
+    const double *w1, *w2;
+    double L;
+    pc_bins B;
+    const float *lo, *hi, *plo, *phi;
+    const double *E, *q;
+    const uint16_t *tbl;
+    unsigned long long *g_hist;
+    double *g_whist;
+    uint4 *rq;
+    unsigned *rq_count;
+    unsigned rq_cap;
+    int32_t copies;     // LDS histogram replicas per wave (power of two)
+    int32_t nbt;        // bins in total (nb * npi)
+    int32_t slots;      // slots per replica: (nb + 2) * npi
+    // dynamic LDS layout (bytes)
+    int32_t o_tbl, o_lo, o_hi, o_E, o_q, o_hist, o_whist;
+    int32_t hist_stride;   // uint32 per wave
+    int32_t whist_stride;  // double per wave
+    int32_t lds_bytes;
+};
+
+hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
+                        double d2r, double *x, double *y, double *z, unsigned *flags);
+hipError_t launch_minmax(hipStream_t s, int64_t n, const void *x, const void *y,
+                         const void *z, int f32, double *part, int nparts, unsigned *flags);
+hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, double *out6);
+hipError_t launch_check_weights(hipStream_t s, int64_t n, const void *w, int f32,
+                                unsigned *flags);
+hipError_t launch_cell_index(hipStream_t s, int64_t n, const void *x, const void *y,
+                             const void *z, int f32, const pc_grid &g, unsigned *cnt,
+                             int32_t *cell_of, int32_t *rank_of, unsigned *flags);
+// exclusive scan of n int32 values into out[0..n] (out[n] = total); `tmp`
+// needs scan_tmp_elems(n) int32.
+size_t scan_tmp_elems(int64_t n);
+hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *out,
+                          int32_t *tmp);
+hipError_t launch_scatter(hipStream_t s, int64_t n, const void *x, const void *y,
+                          const void *z, int f32, const void *w, int wf32, const pc_grid &g,
+                          const int32_t *cell_of, const int32_t *rank_of,
+                          const int32_t *start, float *X, float *Y, float *Z, double *xd,
+                          double *yd, double *zd, double *wd, int32_t *cell_sorted);
+hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
+                              int32_t *bcnt);
+hipError_t launch_block_emit(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
+                             const int32_t *boff, pc_block *blocks);
+hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
+                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
+                             const int32_t *cell1_sorted, int autocorr, int chunk,
+                             int32_t *icnt, unsigned long long *cand);
+hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
+                            const pc_block *blocks, const pc_grid &g, const int32_t *start2,
+                            const int32_t *cell1_sorted, int autocorr, int chunk,
+                            const int32_t *ioff, pc_item *items);
+hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted,
+                        const SweepArgs &a, int nwg);
+hipError_t launch_recheck(hipStream_t s, int metric, bool weighted, const SweepArgs &a);
+hipError_t launch_wsq(hipStream_t s, int64_t n, const double *w, double *out);
+hipError_t launch_finalize(hipStream_t s, int32_t nbt, int autocorr, int e0_zero, int64_t n1,
+                           const unsigned long long *g_hist, const double *g_whist,
+                           const double *wsq, unsigned long long *out_counts,
+                           double *out_wsum);
+// resident sweep workgroups per CU for a dynamic LDS size
+hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, int lds_bytes, int *per_cu);
+
+}  // namespace pc

@@ -1,0 +1,383 @@
+// pc_plan.cpp -- host-side planning: cell grid, float32 decision bands and the
+// bin lookup table.  No device work happens here.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/paircount.h"
+#include "pc_common.h"
+#include "pc_plan.h"
+
+namespace pc {
+
+namespace {
+
+const double kU32 = 0x1p-24;   // float32 unit roundoff
+const double kU64 = 0x1p-53;   // binary64 unit roundoff
+const double kSafety = 1.25;   // multiplies every derived bound
+
+float float_down(double v)
+{
+    float f = (float)v;
+    if ((double)f > v)
+        f = nextafterf(f, -INFINITY);
+    return f;
+}
+
+float float_up(double v)
+{
+    float f = (float)v;
+    if ((double)f < v)
+        f = nextafterf(f, INFINITY);
+    return f;
+}
+
+uint32_t fbits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+float bits_f(uint32_t u)
+{
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+}  // namespace
+
+// Cell grid of section "Partitioning the particles on a grid".
+//
+// Transverse columns (x, y) are at least `reach_xy` wide, so two points within
+// the reach are at most one column apart (the 27/9-neighbour argument).  The
+// width carries a relative margin of 2^-28 plus 2^-40 of the extent: cell
+// assignment t = fl(fl(x - lo) * fl(n / extent)) is monotone in x and its
+// rounding moves a cell boundary by far less than that margin, so two points
+// two columns apart are always separated by more than the reach.  The plain
+// rule n = floor(extent / reach) of the paper gives a width exactly equal to
+// the reach when the ratio is an integer, where rounding could hide a pair.
+//
+// Along z (the line of sight) the grid is finer: slices of about
+// reach_z / slices_per_reach, of which `zreach` are searched on each side of a
+// block.  zreach = floor(reach_z / width_z (1 + 2^-28) + 2^-28) + 1 covers
+// every point within reach_z of any point of the block.
+int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
+              double reach_xy, double reach_z, int slices_per_reach,
+              pc_grid *g)
+{
+    memset(g, 0, sizeof(*g));
+    if (!(reach_xy > 0.0) || !(reach_z > 0.0) || !isfinite(reach_xy) ||
+        !isfinite(reach_z))
+        return CF_EINVAL;
+    if (slices_per_reach <= 0)
+        slices_per_reach = 8;
+    const bool periodic = boxsize > 0.0;
+    if (periodic && !isfinite(boxsize))
+        return CF_EINVAL;
+    g->periodic = periodic ? 1 : 0;
+    g->boxsize = periodic ? boxsize : 0.0;
+    for (int a = 0; a < 3; a++) {
+        if (periodic) {
+            g->lo[a] = 0.0;
+            g->extent[a] = boxsize;
+        } else {
+            if (!isfinite(lo_in[a]) || !isfinite(hi_in[a]) || hi_in[a] < lo_in[a])
+                return CF_EINVAL;
+            g->lo[a] = lo_in[a];
+            g->extent[a] = hi_in[a] - lo_in[a];
+        }
+    }
+    const int max_cols = 1024;
+    for (int a = 0; a < 2; a++) {
+        const double ext = g->extent[a];
+        const double need = reach_xy * (1.0 + 0x1p-28) + ext * 0x1p-40;
+        double nd = ext > 0.0 ? floor(ext / need) : 1.0;
+        int n = (int)std::min(std::max(nd, 1.0), (double)max_cols);
+        while (n > 1 && ext / n < need)
+            n--;
+        if (periodic && n < 3)
+            return CF_EUNSUPPORTED;
+        g->n[a] = n;
+        g->inv_w[a] = ext > 0.0 ? (double)n / ext : 0.0;
+        g->width[a] = ext / n;
+    }
+    {
+        const double ext = g->extent[2];
+        if (periodic && !(3.0 * reach_z * (1.0 + 0x1p-28) <= ext))
+            return CF_EUNSUPPORTED;
+        const double target = reach_z / slices_per_reach;
+        double nd = ext > 0.0 ? floor(ext / target) : 1.0;
+        const double max_slices = 4096.0;
+        int n = (int)std::min(std::max(nd, 1.0), max_slices);
+        // keep the total cell count modest
+        const int64_t ncol = (int64_t)g->n[0] * g->n[1];
+        while (n > 1 && ncol * n > (int64_t(1) << 26))
+            n = (n + 1) / 2;
+        g->n[2] = n;
+        g->inv_w[2] = ext > 0.0 ? (double)n / ext : 0.0;
+        g->width[2] = ext / n;
+        const double r = reach_z * g->inv_w[2];
+        int zr = (int)floor(r * (1.0 + 0x1p-28) + 0x1p-28) + 1;
+        g->zreach = std::min(zr, n);
+    }
+    g->ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    return CF_OK;
+}
+
+// Float32 decision bands.  The float32 sweep evaluates, per axis,
+//   X = fl32(fl64(x - lo)),  A_i = fl32(X_i + fl32(D)),  d32 = fl32(A_i - X_j)
+// and then s32 with one multiply and fused multiply-adds.  With S bounding
+// every coordinate and periodic offset, u = 2^-24 and U = 2^-53:
+//   |d32 - d| <= eps_a + u (|d| + eps_a),   eps_a = 6 u S
+// for the exact wrapped difference d.  Summing ndim squares,
+//   |s32 - s| <= 2 sqrt(ndim) sqrt(s) dl + ndim dl^2 + (ndim + 1) u s'
+// with dl the per-axis bound; the binary64 definition itself differs from the
+// exact s by at most 2 sqrt(ndim) sqrt(s) (2 U S) + ... + (ndim + 1) U s.  The
+// band of edge E is [E - B(E), E + B(E)] rounded outward to float32, with B
+// the sum of both bounds times kSafety.  Because B grows slower than s, a
+// float32 value below the band proves s64 < E and one above proves s64 > E.
+int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale,
+               float *lo, float *hi)
+{
+    if (nedges < 1 || ndim < 1 || ndim > 3 || !(scale >= 0.0) || !isfinite(scale))
+        return CF_EINVAL;
+    const double eps_a = 6.0 * kU32 * scale;
+    const double d64 = 2.0 * kU64 * scale;
+    const double sq = sqrt((double)ndim);
+    for (int k = 0; k < nedges; k++) {
+        const double E = edges_sq[k];
+        if (!isfinite(E) || E < 0.0 || E > 1e30)
+            return CF_EINVAL;
+        if (E == 0.0) {
+            lo[k] = -1.0f;
+            hi[k] = -1.0f;
+            continue;
+        }
+        double B;
+        if (ndim == 1) {
+            // an unsquared line-of-sight edge compared with |dz|
+            B = eps_a * (1.0 + kU32) + kU32 * (E + eps_a) + d64;
+        } else {
+            const double r = sqrt(E);
+            const double dl = eps_a * (1.0 + kU32) + kU32 * (r + eps_a) + d64;
+            const double s_hi = E + 2.0 * sq * r * dl + ndim * dl * dl;
+            B = 2.0 * sq * r * dl + ndim * dl * dl + (ndim + 1) * kU32 * s_hi +
+                (ndim + 1) * kU64 * s_hi;
+        }
+        B = B * kSafety + 1e-300;
+        lo[k] = float_down(E - B);
+        hi[k] = float_up(E + B);
+    }
+    return CF_OK;
+}
+
+// Binary64 path: the float32 value fl32(s64) is compared against the edge
+// rounded down and up; only values inside [down, up] need the exact compare.
+static void fp64_bands(const double *edges_sq, int nedges, float *lo, float *hi)
+{
+    for (int k = 0; k < nedges; k++) {
+        const double E = edges_sq[k];
+        if (E == 0.0) {
+            lo[k] = -1.0f;
+            hi[k] = -1.0f;
+        } else {
+            lo[k] = float_down(E);
+            hi[k] = float_up(E);
+        }
+    }
+}
+
+// Lookup table over the float32 bit pattern of s (monotone for s >= 0):
+// entry = number of edges whose band lies wholly below the cell, flagged when
+// exactly one band meets the cell (that band's edge is the entry value) or
+// when several do.
+static int build_table(const float *lo, const float *hi, int nedges, float s_top,
+                       std::vector<uint16_t> &tbl, int *shift)
+{
+    const uint32_t top = fbits(std::max(s_top, 0.0f));
+    int sh = 0;
+    while ((top >> sh) >= (uint32_t)PC_TBL_MAX)
+        sh++;
+    const uint32_t n = (top >> sh) + 1;
+    tbl.assign(n, 0);
+    for (uint32_t key = 0; key < n; key++) {
+        const float c_lo = bits_f(key << sh);
+        const uint32_t hb = (sh == 0) ? (key << sh) : ((key << sh) | ((1u << sh) - 1u));
+        const float c_hi = bits_f(hb);
+        int below = 0, inter = 0, which = -1;
+        for (int k = 0; k < nedges; k++) {
+            if (hi[k] < c_lo)
+                below++;
+            else if (lo[k] <= c_hi) {
+                inter++;
+                which = k;
+            }
+        }
+        uint32_t e;
+        if (inter == 0)
+            e = (uint32_t)below;
+        else if (inter == 1 && which == below)
+            e = (uint32_t)below | PC_TBL_BAND;
+        else
+            e = PC_TBL_MULTI;
+        tbl[key] = (uint16_t)e;
+    }
+    *shift = sh;
+    return CF_OK;
+}
+
+static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
+
+// Pack pc_bins and its arrays for one call.  `edges` are linear (r, rp or
+// chord) edges, squared here as fl(e * e).  For rppi the pi edges are
+// q_p = p * fl(pimax / npi) (p < npi) and q_npi = pimax.
+int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
+               int npi, double coord_scale, HostBins *out)
+{
+    if (nb < 1 || nb + 1 > PC_MAX_EDGES)
+        return CF_EINVAL;
+    if (metric == PC_METRIC_RPPI) {
+        if (npi < 1 || npi > PC_MAX_NPI || !(pimax > 0.0) || !isfinite(pimax))
+            return CF_EINVAL;
+    } else {
+        npi = 1;
+    }
+    if ((int64_t)nb * npi > PC_MAX_BINS_TOTAL)
+        return CF_EINVAL;
+    const int ne = nb + 1;
+    std::vector<double> E(ne);
+    for (int k = 0; k < ne; k++)
+        E[k] = edges[k] * edges[k];
+    std::vector<float> lo(ne), hi(ne);
+    int rc;
+    const int ndim = (metric == PC_METRIC_RPPI) ? 2 : 3;
+    if (fp32) {
+        rc = fp32_bands(E.data(), ne, ndim, coord_scale, lo.data(), hi.data());
+        if (rc)
+            return rc;
+    } else {
+        fp64_bands(E.data(), ne, lo.data(), hi.data());
+    }
+    const int nq = (metric == PC_METRIC_RPPI) ? npi + 1 : 1;
+    std::vector<double> q(nq, 0.0);
+    std::vector<float> plo(nq, -1.0f), phi(nq, -1.0f);
+    if (metric == PC_METRIC_RPPI) {
+        const double dpi = pimax / (double)npi;
+        for (int p = 0; p < npi; p++)
+            q[p] = (double)p * dpi;
+        q[npi] = pimax;
+        for (int p = 0; p < npi; p++)
+            if (!(q[p] < q[p + 1]))
+                return CF_EINVAL;
+        if (fp32) {
+            rc = fp32_bands(q.data(), nq, 1, coord_scale, plo.data(), phi.data());
+            if (rc)
+                return rc;
+        } else {
+            fp64_bands(q.data(), nq, plo.data(), phi.data());
+        }
+    }
+    std::vector<uint16_t> tbl;
+    int shift = 0;
+    build_table(lo.data(), hi.data(), ne, hi[nb], tbl, &shift);
+
+    pc_bins h;
+    memset(&h, 0, sizeof(h));
+    h.nb = nb;
+    h.npi = npi;
+    h.tbl_shift = shift;
+    h.tbl_n = (int32_t)tbl.size();
+    h.e0_zero = (E[0] == 0.0) ? 1 : 0;
+    h.s_top = hi[nb];
+    h.pi_top = (metric == PC_METRIC_RPPI) ? phi[npi] : 0.0f;
+    h.inv_dpi = (metric == PC_METRIC_RPPI) ? (float)((double)npi / pimax) : 0.0f;
+    if (metric == PC_METRIC_RPPI) {
+        // error of the float32 |dz| (float32 pass) or of rounding the binary64
+        // |dz| to float32 (binary64 pass), in units of the pi bin width, plus
+        // the float32 product and the binary64 edges' offset from p * dpi
+        const double dpi = pimax / (double)npi;
+        double dz_err;
+        if (fp32) {
+            const double eps_a = 6.0 * kU32 * coord_scale;
+            dz_err = eps_a * (1.0 + kU32) + kU32 * (pimax + eps_a) + 2.0 * kU64 * coord_scale;
+        } else {
+            dz_err = kU32 * pimax;
+        }
+        const double tau = kSafety * (dz_err / dpi + 3.0 * kU32 * npi + 4.0 * kU64 * npi) + 0x1p-22;
+        if (!(tau < 0.25))
+            return CF_EINVAL;
+        h.pi_tau = (float)tau;
+    }
+    h.E_top = E[nb];
+    h.pimax = (metric == PC_METRIC_RPPI) ? pimax : 0.0;
+
+    pc_bins_layout L;
+    size_t off = align8(sizeof(pc_bins));
+    L.lo = off;  off = align8(off + sizeof(float) * ne);
+    L.hi = off;  off = align8(off + sizeof(float) * ne);
+    L.E = off;   off = align8(off + sizeof(double) * ne);
+    L.plo = off; off = align8(off + sizeof(float) * nq);
+    L.phi = off; off = align8(off + sizeof(float) * nq);
+    L.q = off;   off = align8(off + sizeof(double) * nq);
+    L.tbl = off; off = align8(off + sizeof(uint16_t) * tbl.size());
+    L.total = off;
+
+    out->hdr = h;
+    out->lay = L;
+    out->buf.assign(L.total, 0);
+    char *b = out->buf.data();
+    memcpy(b, &h, sizeof(h));
+    memcpy(b + L.lo, lo.data(), sizeof(float) * ne);
+    memcpy(b + L.hi, hi.data(), sizeof(float) * ne);
+    memcpy(b + L.E, E.data(), sizeof(double) * ne);
+    memcpy(b + L.plo, plo.data(), sizeof(float) * nq);
+    memcpy(b + L.phi, phi.data(), sizeof(float) * nq);
+    memcpy(b + L.q, q.data(), sizeof(double) * nq);
+    memcpy(b + L.tbl, tbl.data(), sizeof(uint16_t) * tbl.size());
+    out->nq = nq;
+    out->ne = ne;
+    return CF_OK;
+}
+
+}  // namespace pc
+
+extern "C" cf_status cf_plan_grid(const double lo[3], const double hi[3],
+                                  double boxsize, double reach_xy, double reach_z,
+                                  int32_t slices_per_reach, cf_grid_plan *out)
+{
+    if (!out)
+        return CF_EINVAL;
+    double zl[3] = {0, 0, 0}, zh[3] = {0, 0, 0};
+    if (boxsize <= 0.0 && (!lo || !hi))
+        return CF_EINVAL;
+    pc_grid g;
+    int rc = pc::plan_grid(lo ? lo : zl, hi ? hi : zh, boxsize, reach_xy, reach_z,
+                           slices_per_reach, &g);
+    if (rc)
+        return (cf_status)rc;
+    memset(out, 0, sizeof(*out));
+    for (int a = 0; a < 3; a++) {
+        out->lo[a] = g.lo[a];
+        out->extent[a] = g.extent[a];
+        out->inv_width[a] = g.inv_w[a];
+        out->width[a] = g.width[a];
+        out->n[a] = g.n[a];
+    }
+    out->zreach = g.zreach;
+    out->periodic = g.periodic;
+    out->boxsize = g.boxsize;
+    out->ncell = g.ncell;
+    return CF_OK;
+}
+
+extern "C" cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32_t ndim,
+                                   double coord_scale, float *lo, float *hi)
+{
+    if (!edges_sq || !lo || !hi)
+        return CF_EINVAL;
+    return (cf_status)pc::fp32_bands(edges_sq, nedges, ndim, coord_scale, lo, hi);
+}

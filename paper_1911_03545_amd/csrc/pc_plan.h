@@ -1,0 +1,26 @@
+// pc_plan.h -- host planner interface (grid, bands, bin description).
+#pragma once
+#include <stddef.h>
+
+#include <vector>
+
+#include "pc_common.h"
+
+namespace pc {
+
+struct HostBins {
+    pc_bins hdr;
+    pc_bins_layout lay;
+    std::vector<char> buf;   // pc_bins followed by its arrays, ready to upload
+    int ne = 0;              // r / rp edges
+    int nq = 0;              // pi edges (1 when unused)
+};
+
+int plan_grid(const double lo[3], const double hi[3], double boxsize, double reach_xy,
+              double reach_z, int slices_per_reach, pc_grid *g);
+int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
+               float *hi);
+int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax, int npi,
+               double coord_scale, HostBins *out);
+
+}  // namespace pc
