@@ -31,8 +31,8 @@
  *  * Precision: CF_PREC_FP64 evaluates every pair in binary64 exactly as
  *    above.  CF_PREC_FP32_RECHECK evaluates pairs in float32 and decides only
  *    the pairs that a proven error bound places away from every squared edge;
- *    the remaining pairs are re-evaluated in binary64.  Both give identical
- *    counts.
+ *    the remaining pairs are re-evaluated in binary64 inside the same sweep.
+ *    Both give identical counts.
  *
  * Memory and streams
  * ------------------
@@ -97,14 +97,11 @@ typedef struct cf_options {
     int32_t struct_size;        /* sizeof(cf_options)                          */
     int32_t slices_per_reach;   /* z slices per line-of-sight reach (default 8) */
     int32_t chunk;              /* max j points per work item (default 2048)   */
-    int32_t recheck_capacity;   /* initial FP32 recheck queue entries (<= 0:
-                                   default); a queue that overflows makes the
-                                   sweep run again with a larger queue         */
     int32_t output_on_device;   /* counts / wsum are device pointers           */
     int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC     */
     int32_t collect_timing;     /* time phases with HIP events (cf_stats)      */
     int32_t hist_copies;        /* LDS histogram replicas per wave (0: auto)   */
-    int32_t reserved[8];
+    int32_t reserved[9];
 } cf_options;
 
 /* Statistics of the last counting call on a context. */
@@ -116,17 +113,15 @@ typedef struct cf_stats {
     int64_t n_items;            /* work items processed by the pair sweep      */
     uint64_t candidate_pairs;   /* pair evaluations performed by the sweep     */
     uint64_t rechecks;          /* FP32 pairs re-evaluated in binary64         */
-    uint64_t sweep_reruns;      /* sweeps repeated after a recheck-queue overflow */
     int32_t sweep_workgroups;   /* persistent workgroups of the sweep launch   */
     int32_t hist_copies;        /* LDS histogram replicas per wave             */
     float t_prepare_ms;         /* validation, conversion, bounding box        */
     float t_grid_ms;            /* cell index + scan + scatter                 */
     float t_worklist_ms;        /* blocks + work items                         */
-    float t_sweep_ms;           /* pair sweep kernel                           */
-    float t_recheck_ms;         /* binary64 recheck kernel                     */
+    float t_sweep_ms;           /* pair sweep kernel (with binary64 rechecks)  */
     float t_finalize_ms;        /* doubling, self-pairs, copy-out              */
     float t_total_ms;           /* whole call, first to last event             */
-    float reserved_f[3];
+    float reserved_f[4];
 } cf_stats;
 
 typedef struct cf_ctx cf_ctx;

@@ -50,22 +50,22 @@ class cf_catalog(ctypes.Structure):
 
 class cf_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("slices_per_reach", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("recheck_capacity", ctypes.c_int32),
+                ("chunk", ctypes.c_int32),
                 ("output_on_device", ctypes.c_int32), ("theta_unit_vectors", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("reserved", ctypes.c_int32 * 9)]
 
 
 class cf_stats(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32 * 3), ("zreach", ctypes.c_int32),
                 ("cell_width", ctypes.c_double * 3), ("n_blocks", ctypes.c_int64),
                 ("n_items", ctypes.c_int64), ("candidate_pairs", ctypes.c_uint64),
-                ("rechecks", ctypes.c_uint64), ("sweep_reruns", ctypes.c_uint64),
+                ("rechecks", ctypes.c_uint64),
                 ("sweep_workgroups", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("t_prepare_ms", ctypes.c_float), ("t_grid_ms", ctypes.c_float),
                 ("t_worklist_ms", ctypes.c_float), ("t_sweep_ms", ctypes.c_float),
-                ("t_recheck_ms", ctypes.c_float), ("t_finalize_ms", ctypes.c_float),
-                ("t_total_ms", ctypes.c_float), ("reserved_f", ctypes.c_float * 3)]
+                ("t_finalize_ms", ctypes.c_float),
+                ("t_total_ms", ctypes.c_float), ("reserved_f", ctypes.c_float * 4)]
 
 
 class cf_grid_plan(ctypes.Structure):

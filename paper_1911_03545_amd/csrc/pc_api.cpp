@@ -1,6 +1,6 @@
 // pc_api.cpp -- the C ABI: contexts, argument validation and the per-call
-// pipeline (stage -> bounding box -> plan -> grid -> work list -> sweep ->
-// recheck -> finalize -> copy-out), all enqueued on the context's stream.
+// pipeline (stage -> bounding box -> plan -> grid -> work list -> sweep with
+// inline binary64 recheck -> finalize -> copy-out), all enqueued on the context's stream.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -29,7 +29,7 @@ enum BufId {
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
-    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_RQ, B_PART,
+    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_PART,
     B_COUNT
 };
 
@@ -519,15 +519,6 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         return st2;
     HIPCHK(hipMemsetAsync(c->buf[B_HIST].p, 0, sizeof(unsigned long long) * nbt, c->stream));
     HIPCHK(hipMemsetAsync(c->buf[B_WHIST].p, 0, sizeof(double) * nbt, c->stream));
-    unsigned rq_cap = 0;
-    if (fp32) {
-        int64_t cap = opt.recheck_capacity;
-        if (cap <= 0)
-            cap = std::max<int64_t>(1 << 16, std::min<int64_t>(1 << 24, (n1 + n2) / 4));
-        rq_cap = (unsigned)cap;
-        if ((st2 = ensure(c, B_RQ, sizeof(uint4) * (size_t)std::max<unsigned>(rq_cap, 1))))
-            return st2;
-    }
     const char *bb = (const char *)c->buf[B_BINS].p;
     pc::SweepArgs a;
     memset(&a, 0, sizeof(a));
@@ -565,14 +556,22 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     a.tbl = (const uint16_t *)(bb + hb.lay.tbl);
     a.g_hist = dptr<unsigned long long>(c, B_HIST);
     a.g_whist = weighted ? dptr<double>(c, B_WHIST) : nullptr;
-    a.rq = fp32 ? dptr<uint4>(c, B_RQ) : nullptr;
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
-    a.rq_cap = rq_cap;
     a.nbt = (int32_t)nbt;
     a.slots = (int32_t)((nb + 2) * npi);
-    int copies = opt.hist_copies > 0 ? pow2_floor(opt.hist_copies)
-                                     : pow2_floor((int)std::max<int64_t>(1, std::min<int64_t>(16, 512 / nbt)));
-    while (copies > 1 && copies * a.slots > PC_MAX_HIST_WAVE)
+    // Histogram replicas: one per lane (unconditional updates, no candidate
+    // branch) for unweighted 1-D counts with few bins, else a few shared ones.
+    const bool unc_ok = metric == PC_METRIC_R && !weighted && !hb.hdr.tbl_wide &&
+                        PC_WAVE * (a.slots | 1) <= PC_MAX_HIST_WAVE;
+    int copies;
+    if (opt.hist_copies > 0)
+        copies = pow2_floor(std::min(opt.hist_copies, PC_WAVE));
+    else
+        copies = unc_ok ? PC_WAVE
+                        : pow2_floor((int)std::max<int64_t>(1, std::min<int64_t>(16, 512 / nbt)));
+    if (copies == PC_WAVE && !unc_ok)
+        copies = PC_WAVE / 2;
+    while (copies > 1 && copies * (a.slots | 1) > PC_MAX_HIST_WAVE)
         copies /= 2;
     a.copies = copies;
     // dynamic LDS layout
@@ -583,21 +582,25 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         return o;
     };
     const int ne = nb + 1, nq = hb.nq;
-    a.o_tbl = take(2 * hb.hdr.tbl_n);
+    a.o_tbl = 0;   // the kernel keeps the table in a static LDS array
     a.o_lo = take(4 * (ne + nq));
     a.o_hi = take(4 * (ne + nq));
     a.o_E = take(8 * ne);
     a.o_q = take(8 * nq);
-    a.hist_stride = (int32_t)(copies * a.slots);
+    // replica stride: odd, so the 64 lanes' copies of one slot spread over banks
+    a.rep_stride = a.slots | 1;
+    a.hist_stride = (int32_t)(copies * a.rep_stride);
     a.o_hist = take(4 * 4 * a.hist_stride);
-    a.whist_stride = weighted ? (int32_t)(copies * a.slots) : 0;
+    a.whist_stride = weighted ? (int32_t)(copies * a.rep_stride) : 0;
     a.o_whist = take(weighted ? 8 * 4 * a.whist_stride : 0);
     a.lds_bytes = off;
-    if (off > 160 * 1024)
+    // static LDS of the sweep: the lookup table
+    if (off + (PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX) > 160 * 1024)
         return fail(c, CF_EINVAL, "bin configuration needs too much LDS (%d bytes)", off);
 
     int per_cu = 0;
-    HIPCHK(pc::sweep_occupancy(metric, fp32, weighted, off, &per_cu));
+    HIPCHK(pc::sweep_occupancy(metric, fp32, weighted, hb.hdr.tbl_wide != 0,
+                               copies == PC_WAVE, off, &per_cu));
     per_cu = std::max(per_cu, 1);
     int nwg = (int)std::min<int64_t>((n_items + 3) / 4, (int64_t)c->num_cu * per_cu);
     nwg = std::max(nwg, 1);
@@ -613,51 +616,29 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     if ((st2 = ensure_pinned(c, need)))
         return st2;
     char *hp = (char *)c->pinned;
-    unsigned rqn = 0;
-    int attempts = 0;
-    for (;;) {
-        record(c, timing, 4);
-        if (n_items > 0)
-            HIPCHK(pc::launch_sweep(c->stream, metric, fp32, weighted, a, nwg));
-        record(c, timing, 5);
-        if (fp32 && rq_cap > 0 && n_items > 0)
-            HIPCHK(pc::launch_recheck(c->stream, metric, weighted, a));
-        record(c, timing, 6);
-        // ---- finalize --------------------------------------------------------
-        if (wsq) {
-            HIPCHK(hipMemsetAsync(wsq, 0, sizeof(double), c->stream));
-            HIPCHK(pc::launch_wsq(c->stream, n1, dptr<double>(c, B_WD1), wsq));
-        }
-        HIPCHK(pc::launch_finalize(c->stream, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero, n1,
-                                   a.g_hist, a.g_whist, wsq, outc, outw));
-        HIPCHK(hipMemcpyAsync(hp, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
-        if (!opt.output_on_device) {
-            HIPCHK(hipMemcpyAsync(hp + M_SIZE, outc, sizeof(uint64_t) * nbt,
-                                  hipMemcpyDeviceToHost, c->stream));
-            if (outw)
-                HIPCHK(hipMemcpyAsync(hp + M_SIZE + sizeof(uint64_t) * nbt, outw,
-                                      sizeof(double) * nbt, hipMemcpyDeviceToHost, c->stream));
-        }
-        record(c, timing, 7);
-        HIPCHK(hipStreamSynchronize(c->stream));
-        memcpy(&rqn, hp + M_RQCOUNT, 4);
-        if (!fp32 || rqn <= rq_cap)
-            break;
-        // The recheck queue overflowed: the histogram lacks the dropped
-        // pairs.  Enlarge the queue and run the sweep again from scratch.
-        if (++attempts > 2)
-            return fail(c, CF_EOVERFLOW, "recheck queue overflow (%u entries)", rqn);
-        c->stats.sweep_reruns += 1;
-        rq_cap = (unsigned)std::min<uint64_t>(0xffffffffull, (uint64_t)rqn + rqn / 4 + 1024);
-        if ((st2 = ensure(c, B_RQ, sizeof(uint4) * (size_t)rq_cap)))
-            return st2;
-        a.rq = dptr<uint4>(c, B_RQ);
-        a.rq_cap = rq_cap;
-        HIPCHK(hipMemsetAsync(c->buf[B_HIST].p, 0, sizeof(unsigned long long) * nbt, c->stream));
-        HIPCHK(hipMemsetAsync(c->buf[B_WHIST].p, 0, sizeof(double) * nbt, c->stream));
-        HIPCHK(hipMemsetAsync(misc(c) + M_COUNTER, 0, 4, c->stream));
-        HIPCHK(hipMemsetAsync(misc(c) + M_RQCOUNT, 0, 4, c->stream));
+    record(c, timing, 4);
+    if (n_items > 0)
+        HIPCHK(pc::launch_sweep(c->stream, metric, fp32, weighted, a, nwg));
+    record(c, timing, 5);
+    // ---- finalize ------------------------------------------------------------
+    if (wsq) {
+        HIPCHK(hipMemsetAsync(wsq, 0, sizeof(double), c->stream));
+        HIPCHK(pc::launch_wsq(c->stream, n1, dptr<double>(c, B_WD1), wsq));
     }
+    HIPCHK(pc::launch_finalize(c->stream, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero, n1,
+                               a.g_hist, a.g_whist, wsq, outc, outw));
+    HIPCHK(hipMemcpyAsync(hp, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
+    if (!opt.output_on_device) {
+        HIPCHK(hipMemcpyAsync(hp + M_SIZE, outc, sizeof(uint64_t) * nbt, hipMemcpyDeviceToHost,
+                              c->stream));
+        if (outw)
+            HIPCHK(hipMemcpyAsync(hp + M_SIZE + sizeof(uint64_t) * nbt, outw,
+                                  sizeof(double) * nbt, hipMemcpyDeviceToHost, c->stream));
+    }
+    record(c, timing, 6);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    unsigned rqn = 0;
+    memcpy(&rqn, hp + M_RQCOUNT, 4);
 
     unsigned hflags;
     memcpy(&hflags, hp + M_FLAGS, 4);
@@ -691,9 +672,8 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         S.t_grid_ms = elapsed(c, 1, 2);
         S.t_worklist_ms = elapsed(c, 2, 3);
         S.t_sweep_ms = elapsed(c, 4, 5);
-        S.t_recheck_ms = elapsed(c, 5, 6);
-        S.t_finalize_ms = elapsed(c, 6, 7);
-        S.t_total_ms = elapsed(c, 0, 7);
+        S.t_finalize_ms = elapsed(c, 5, 6);
+        S.t_total_ms = elapsed(c, 0, 6);
     }
     return CF_OK;
 }

@@ -4,17 +4,25 @@
 
 #define PC_WAVE 64
 #define PC_BLOCK_I 64          // i points per work item: one per lane
-#define PC_TBL_MAX 8192        // bin lookup table entries (uint16)
+#define PC_TBL8_MAX 16384      // byte lookup-table entries (up to 125 bins)
+#define PC_TBL16_MAX 8192      // 16-bit lookup-table entries (more bins)
+#define PC_TBL8_MAX_BINS 125
 #define PC_MAX_EDGES 1025      // r / rp / theta edges
 #define PC_MAX_NPI 1024
 #define PC_MAX_BINS_TOTAL 4096 // r bins, or nrp * npi
 #define PC_MAX_HIST_WAVE 4096  // uint32 LDS counters per wave (bins * copies)
 
-// lookup-table entry flags (uint16): low 14 bits = number of edges whose
-// band lies entirely below the table cell.
-#define PC_TBL_BAND 0x8000u    // exactly one band (of edge `low bits`) meets the cell
-#define PC_TBL_MULTI 0x4000u   // several bands meet the cell: search them all
+// Lookup-table entries.  A plain entry is the histogram slot of every value
+// in the table cell: the number of edges whose band lies wholly below the
+// cell (bin + 1; 0 and nb + 1 mean out of range).  16-bit entries flag a cell
+// met by exactly one band with PC_TBL_BAND | edge, by several bands with
+// PC_TBL_MULTI; byte entries use 0x80 | edge and 0xFF.
+#define PC_TBL_BAND 0x8000u
+#define PC_TBL_MULTI 0x4000u
 #define PC_TBL_MASK 0x3FFFu
+#define PC_TBL8_BAND 0x80u
+#define PC_TBL8_MULTI 0xFFu
+#define PC_TBL8_MASK 0x7Fu
 
 // Periodic offset codes, two bits per axis: 0 -> 0, 1 -> +L, 2 -> -L.
 #define PC_D_ZERO 0u
@@ -63,9 +71,11 @@ struct pc_item {
 struct pc_bins {
     int32_t nb;          // r / rp bins
     int32_t npi;         // pi bins (1 for r and theta)
-    int32_t tbl_shift;   // key = float_bits(s) >> tbl_shift
+    int32_t tbl_shift;   // key = sat(float_bits(s) - tbl_base) >> tbl_shift
     int32_t tbl_n;       // used table entries
     int32_t e0_zero;     // first r / rp edge is exactly zero
+    int32_t tbl_wide;    // 0: byte entries, 1: 16-bit entries
+    uint32_t tbl_base;   // float bit pattern subtracted before the shift
     int32_t pad;
     float s_top;         // float32 prefilter: candidate only if s32 <= s_top
     float pi_top;        // rppi: candidate only if pi32 <= pi_top

@@ -27,12 +27,12 @@ struct SweepArgs {
     const uint16_t *tbl;
     unsigned long long *g_hist;
     double *g_whist;
-    uint4 *rq;
-    unsigned *rq_count;
-    unsigned rq_cap;
-    int32_t copies;     // LDS histogram replicas per wave (power of two)
+    unsigned *rq_count;   // float32 pass: pairs re-evaluated in binary64
+    int32_t copies;     // LDS histogram replicas per wave (power of two; 64 = one per
+                        // lane with unconditional updates, 1-D unweighted only)
     int32_t nbt;        // bins in total (nb * npi)
     int32_t slots;      // slots per replica: (nb + 2) * npi
+    int32_t rep_stride; // distance between replicas (slots rounded up to odd)
     // dynamic LDS layout (bytes)
     int32_t o_tbl, o_lo, o_hi, o_E, o_q, o_hist, o_whist;
     int32_t hist_stride;   // uint32 per wave
@@ -74,13 +74,13 @@ hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nbloc
                             const int32_t *ioff, pc_item *items);
 hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted,
                         const SweepArgs &a, int nwg);
-hipError_t launch_recheck(hipStream_t s, int metric, bool weighted, const SweepArgs &a);
 hipError_t launch_wsq(hipStream_t s, int64_t n, const double *w, double *out);
 hipError_t launch_finalize(hipStream_t s, int32_t nbt, int autocorr, int e0_zero, int64_t n1,
                            const unsigned long long *g_hist, const double *g_whist,
                            const double *wsq, unsigned long long *out_counts,
                            double *out_wsum);
 // resident sweep workgroups per CU for a dynamic LDS size
-hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, int lds_bytes, int *per_cu);
+hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc,
+                           int lds_bytes, int *per_cu);
 
 }  // namespace pc

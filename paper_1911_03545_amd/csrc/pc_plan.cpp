@@ -191,23 +191,42 @@ static void fp64_bands(const double *edges_sq, int nedges, float *lo, float *hi)
     }
 }
 
-// Lookup table over the float32 bit pattern of s (monotone for s >= 0):
-// entry = number of edges whose band lies wholly below the cell, flagged when
-// exactly one band meets the cell (that band's edge is the entry value) or
-// when several do.
-static int build_table(const float *lo, const float *hi, int nedges, float s_top,
-                       std::vector<uint16_t> &tbl, int *shift)
+// Lookup table over the float32 bit pattern of s (monotone for s >= 0),
+// key = sat(bits(s) - base) >> sh.  The table starts one cell below the first
+// band that matters, so every value below it shares cell 0; `sh` is the
+// smallest shift that fits [base, s_top] into `cap` entries.  Entry = number
+// of bands wholly below the cell (the histogram slot), flagged when one band
+// (entry = flag | edge) or several bands meet the cell.
+static int build_table(const float *lo, const float *hi, int nedges, float s_top, bool wide,
+                       std::vector<uint16_t> &tbl, int *shift, uint32_t *base_out)
 {
+    const uint32_t cap = wide ? PC_TBL16_MAX : PC_TBL8_MAX;
     const uint32_t top = fbits(std::max(s_top, 0.0f));
+    // first band that is not the empty band of a zero edge
+    uint32_t first = top;
+    for (int k = 0; k < nedges; k++)
+        if (hi[k] >= 0.0f) {
+            first = fbits(std::max(lo[k], 0.0f));
+            break;
+        }
     int sh = 0;
-    while ((top >> sh) >= (uint32_t)PC_TBL_MAX)
-        sh++;
-    const uint32_t n = (top >> sh) + 1;
+    uint32_t base = 0;
+    for (;; sh++) {
+        const uint32_t step = 1u << sh;
+        base = first > step ? first - step : 0u;
+        if (((top - base) >> sh) + 2 <= cap)
+            break;
+    }
+    // one extra entry past the last cell: "above every edge", the target of
+    // keys clamped in the sweep
+    const uint32_t n = ((top - base) >> sh) + 2;
     tbl.assign(n, 0);
-    for (uint32_t key = 0; key < n; key++) {
-        const float c_lo = bits_f(key << sh);
-        const uint32_t hb = (sh == 0) ? (key << sh) : ((key << sh) | ((1u << sh) - 1u));
-        const float c_hi = bits_f(hb);
+    tbl[n - 1] = (uint16_t)nedges;
+    for (uint32_t key = 0; key + 1 < n; key++) {
+        const uint32_t lo_b = key == 0 ? 0u : base + (key << sh);
+        const uint32_t hi_b = base + (key << sh) + ((1u << sh) - 1u);
+        const float c_lo = bits_f(lo_b);
+        const float c_hi = bits_f(std::min(hi_b, 0x7f7fffffu));
         int below = 0, inter = 0, which = -1;
         for (int k = 0; k < nedges; k++) {
             if (hi[k] < c_lo)
@@ -221,12 +240,13 @@ static int build_table(const float *lo, const float *hi, int nedges, float s_top
         if (inter == 0)
             e = (uint32_t)below;
         else if (inter == 1 && which == below)
-            e = (uint32_t)below | PC_TBL_BAND;
+            e = wide ? ((uint32_t)below | PC_TBL_BAND) : ((uint32_t)below | PC_TBL8_BAND);
         else
-            e = PC_TBL_MULTI;
+            e = wide ? PC_TBL_MULTI : PC_TBL8_MULTI;
         tbl[key] = (uint16_t)e;
     }
     *shift = sh;
+    *base_out = base;
     return CF_OK;
 }
 
@@ -283,7 +303,9 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     }
     std::vector<uint16_t> tbl;
     int shift = 0;
-    build_table(lo.data(), hi.data(), ne, hi[nb], tbl, &shift);
+    uint32_t base = 0;
+    const bool wide = nb > PC_TBL8_MAX_BINS;
+    build_table(lo.data(), hi.data(), ne, hi[nb], wide, tbl, &shift, &base);
 
     pc_bins h;
     memset(&h, 0, sizeof(h));
@@ -291,6 +313,8 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     h.npi = npi;
     h.tbl_shift = shift;
     h.tbl_n = (int32_t)tbl.size();
+    h.tbl_wide = wide ? 1 : 0;
+    h.tbl_base = base;
     h.e0_zero = (E[0] == 0.0) ? 1 : 0;
     h.s_top = hi[nb];
     h.pi_top = (metric == PC_METRIC_RPPI) ? phi[npi] : 0.0f;
@@ -323,7 +347,8 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     L.plo = off; off = align8(off + sizeof(float) * nq);
     L.phi = off; off = align8(off + sizeof(float) * nq);
     L.q = off;   off = align8(off + sizeof(double) * nq);
-    L.tbl = off; off = align8(off + sizeof(uint16_t) * tbl.size());
+    const size_t esz = wide ? sizeof(uint16_t) : sizeof(uint8_t);
+    L.tbl = off; off = align8(off + esz * tbl.size());
     L.total = off;
 
     out->hdr = h;
@@ -337,7 +362,12 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     memcpy(b + L.plo, plo.data(), sizeof(float) * nq);
     memcpy(b + L.phi, phi.data(), sizeof(float) * nq);
     memcpy(b + L.q, q.data(), sizeof(double) * nq);
-    memcpy(b + L.tbl, tbl.data(), sizeof(uint16_t) * tbl.size());
+    if (wide) {
+        memcpy(b + L.tbl, tbl.data(), sizeof(uint16_t) * tbl.size());
+    } else {
+        for (size_t k = 0; k < tbl.size(); k++)
+            b[L.tbl + k] = (char)(uint8_t)tbl[k];
+    }
     out->nq = nq;
     out->ne = ne;
     return CF_OK;

@@ -39,7 +39,6 @@ namespace {
 // the scalar cache (address space 4).
 #define LDS __attribute__((address_space(3)))
 #define KCONST __attribute__((address_space(4)))
-typedef const LDS uint16_t *lds_u16p;
 typedef const LDS float *lds_f32p;
 typedef const LDS double *lds_f64p;
 typedef LDS unsigned *lds_u32p;
@@ -58,6 +57,7 @@ __device__ __forceinline__ void lds_add(LDS double *p, double v)
 }
 
 constexpr int kSweepThreads = 256;
+constexpr int kTblBytes = PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX;
 constexpr int kWaves = kSweepThreads / PC_WAVE;
 constexpr unsigned kSlow = PC_TBL_BAND | PC_TBL_MULTI;
 
@@ -118,27 +118,53 @@ __device__ __forceinline__ int exact_bin(double s, double pz, P E, int nb, P q, 
 }
 
 struct Lds {
-    lds_u16p tbl;
+    const LDS unsigned char *tbl;   // byte or 16-bit entries
     lds_f32p lo, hi;  // r / rp bands, followed (rppi) by the pi bands
     lds_f64p E, q;
     lds_u32p hist;    // this wave's histogram replicas
     lds_f64wp whist;
 };
 
-// Float32 slot of a value in a flagged table cell (or of any value when e
-// carries PC_TBL_MULTI): number of bands wholly below it, i.e. bin + 1, or
-// -1 when the value lies inside a band.
-__device__ __forceinline__ int slow_slot(float s, unsigned e, lds_f32p lo, lds_f32p hi,
-                                         int nedges)
+// Table entry of a value (float bits already reduced to the key).
+// Table entries as signed values: flagged cells read negative (byte entries
+// sign-extend 0x80 | edge, 16-bit entries have 0x8000 or 0x4000 set and are
+// tested separately).
+template <bool T16>
+__device__ __forceinline__ int tbl_entry(const Lds &L, unsigned key)
 {
-    if (e & PC_TBL_BAND) {
-        const int c = (int)(e & PC_TBL_MASK);
-        if (s > hi[c])
-            return c + 1;
-        if (s < lo[c])
-            return c;
-        return -1;
-    }
+    if (T16)
+        return (int)((const LDS uint16_t *)L.tbl)[key];
+    return (int)((const LDS signed char *)L.tbl)[key];
+}
+
+template <bool T16>
+__device__ __forceinline__ bool is_slow(int e)
+{
+    return T16 ? (e & (int)(PC_TBL_BAND | PC_TBL_MULTI)) != 0 : e < 0;
+}
+
+template <bool T16>
+__device__ __forceinline__ bool is_multi(int e)
+{
+    return T16 ? (e & (int)PC_TBL_MULTI) != 0 : (e & 0xFF) == (int)PC_TBL8_MULTI;
+}
+
+template <bool T16>
+__device__ __forceinline__ int band_edge(int e)
+{
+    return T16 ? (e & (int)PC_TBL_MASK) : (e & (int)PC_TBL8_MASK);
+}
+
+// Table key of a value, clamped to the extra last entry, which places every
+// value beyond the table above all edges.
+__device__ __forceinline__ unsigned tbl_key(float s, unsigned base, int sh, unsigned last)
+{
+    return min(__builtin_elementwise_sub_sat(__float_as_uint(s), base) >> sh, last);
+}
+
+// Number of bands wholly below s (bin + 1), or -1 when s lies inside a band.
+__device__ __forceinline__ int band_scan(float s, lds_f32p lo, lds_f32p hi, int nedges)
+{
     int below = 0;
     for (int k = 0; k < nedges; k++) {
         if (s > hi[k])
@@ -149,21 +175,48 @@ __device__ __forceinline__ int slow_slot(float s, unsigned e, lds_f32p lo, lds_f
     return below;
 }
 
-// Binary64 slot of a value in a flagged cell: exact comparison with the edges.
-__device__ __forceinline__ int slow_slot_exact(double s, unsigned e, lds_f64p E, int nedges)
+// Float32 slot of a value in a flagged table cell: the number of bands
+// wholly below it (bin + 1), or -1 when the value lies inside a band.
+template <bool T16>
+__device__ __forceinline__ int slow_slot(float s, int e, lds_f32p lo, lds_f32p hi,
+                                         int nedges)
 {
-    if (e & PC_TBL_BAND) {
-        const int c = (int)(e & PC_TBL_MASK);
+    if (!is_multi<T16>(e)) {
+        const int c = band_edge<T16>(e);
+        if (s > hi[c])
+            return c + 1;
+        if (s < lo[c])
+            return c;
+        return -1;
+    }
+    return band_scan(s, lo, hi, nedges);
+}
+
+// Binary64 slot of a value in a flagged cell: exact comparison with the edges.
+template <bool T16>
+__device__ __forceinline__ int slow_slot_exact(double s, int e, lds_f64p E, int nedges)
+{
+    if (!is_multi<T16>(e)) {
+        const int c = band_edge<T16>(e);
         return (s >= E[c]) ? c + 1 : c;
     }
     return count_le(E, nedges, s);
 }
 
-__device__ __forceinline__ void push_recheck(const SweepArgs &a, int i, int j, unsigned dcode)
+// Exact histogram slot of a pair the float32 pass could not decide: the
+// binary64 separation of the definition from the binary64 copies of both
+// points (the second point is wave-uniform and comes through the scalar
+// cache), binned against the exact edges.  Returns the slot of bin + 1 (rppi:
+// (rp bin + 1) * npi + pi bin), or 0 when out of range.
+template <int M>
+__device__ __noinline__ int exact_slot(const SweepArgs &a, const Lds &L, int i, int j,
+                                       unsigned dcode)
 {
-    const unsigned slot = atomicAdd(a.rq_count, 1u);
-    if (slot < a.rq_cap)
-        a.rq[slot] = make_uint4((unsigned)i, (unsigned)j, dcode, 0u);
+    const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2;
+    double s, pz;
+    exact_sep<M>(a.x1[i], a.y1[i], a.z1[i], x2[j], y2[j], z2[j], dcode, a.L, &s, &pz);
+    const int b = exact_bin<M>(s, pz, L.E, a.B.nb, L.q, a.B.npi, a.B.pimax);
+    return b < 0 ? 0 : b + a.B.npi;
 }
 
 // Float32 pi bin of |dz|: t = |dz| * npi / pimax; the bin floor(t) is taken
@@ -179,122 +232,176 @@ __device__ __forceinline__ int pi_fast(float pz, float inv_dpi, float tau, int n
     return (fr > tau && fr < 1.0f - tau && k < npi) ? k : -1;
 }
 
-// ---- float32 pair -------------------------------------------------------
-template <int M, bool W, bool TRI>
-__device__ __forceinline__ void pair_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                         lds_f64wp whb, float ax, float ay, float az, double wi,
-                                         int i, float xj, float yj, float zj, double wj, int j,
-                                         unsigned dcode)
+// ---- float32 chunk: CH pairs sharing lane i ------------------------------
+// Three phases so that the CH table reads are in flight together: (1)
+// separations, candidate masks and table keys, (2) table reads, (3) slot
+// resolution and histogram updates.
+// UNC: every lane adds to its own histogram replica (out-of-range values land
+// in the catch-all slots), which needs no candidate branch; used for the
+// unweighted 1-D statistics.
+template <int M, bool W, bool TRI, bool T16, bool UNC, int CH>
+__device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
+                                          lds_f64wp whb, float ax, float ay, float az,
+                                          double wi, int i, const float *xs, const float *ys,
+                                          const float *zs, const double *ws, int j,
+                                          unsigned dcode, unsigned &rechecks)
 {
-    const float dx = ax - xj, dy = ay - yj, dz = az - zj;
-    if (M == PC_METRIC_R) {
-        const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        bool cand = s <= a.B.s_top;
+    float s[CH], pz[CH];
+    bool c[CH];
+    unsigned key[CH];
+    int e[CH];
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+        const float dx = ax - xs[k], dy = ay - ys[k], dz = az - zs[k];
+        if (M == PC_METRIC_R) {
+            s[k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            c[k] = s[k] <= a.B.s_top;
+        } else {
+            s[k] = fmaf(dy, dy, dx * dx);
+            pz[k] = fabsf(dz);
+            c[k] = (s[k] <= a.B.s_top) && (pz[k] <= a.B.pi_top);
+        }
         if (TRI)
-            cand = cand && (j > i);
-        if (cand) {
-            int slot = (int)L.tbl[__float_as_uint(s) >> a.B.tbl_shift];
-            if ((unsigned)slot & kSlow) {
-                slot = slow_slot(s, (unsigned)slot, L.lo, L.hi, a.B.nb + 1);
+            c[k] = c[k] && (j + k > i);
+        key[k] = tbl_key(s[k], a.B.tbl_base, a.B.tbl_shift, (unsigned)a.B.tbl_n - 1u);
+    }
+    // every lane reads (no exec-mask changes), so the CH reads stay in flight
+#pragma unroll
+    for (int k = 0; k < CH; k++)
+        e[k] = tbl_entry<T16>(L, key[k]);
+    if (UNC) {
+        // M == PC_METRIC_R, unweighted
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            int slot = e[k];
+            if (is_slow<T16>(slot)) {
+                slot = slow_slot<T16>(s[k], slot, L.lo, L.hi, a.B.nb + 1);
                 if (slot < 0) {
-                    push_recheck(a, i, j, dcode);
-                    slot = 0;
+                    slot = exact_slot<M>(a, L, i, j + k, dcode);
+                    rechecks++;
                 }
             }
+            if (TRI && !(j + k > i))
+                slot = 0;
             lds_add(&hb[slot], 1u);
-            if (W)
-                lds_add(&whb[slot], wi * wj);
         }
-    } else {
-        const float rp = fmaf(dy, dy, dx * dx);
-        const float pz = fabsf(dz);
-        bool cand = (rp <= a.B.s_top) && (pz <= a.B.pi_top);
-        if (TRI)
-            cand = cand && (j > i);
-        if (cand) {
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+        if (!c[k])
+            continue;
+        int slot = e[k];
+        if (M == PC_METRIC_R) {
+            if (is_slow<T16>(e[k])) {
+                slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
+                if (slot < 0) {
+                    slot = exact_slot<M>(a, L, i, j + k, dcode);
+                    rechecks++;
+                }
+            }
+        } else {
             const int npi = a.B.npi;
-            int row = (int)L.tbl[__float_as_uint(rp) >> a.B.tbl_shift];
-            int k = pi_fast(pz, a.B.inv_dpi, a.B.pi_tau, npi);
-            int slot;
-            if (((unsigned)row & kSlow) || k < 0) {
-                if ((unsigned)row & kSlow)
-                    row = slow_slot(rp, (unsigned)row, L.lo, L.hi, a.B.nb + 1);
-                int ps = k + 1;
-                if (k < 0)
-                    ps = slow_slot(pz, PC_TBL_MULTI, L.lo + a.B.nb + 1, L.hi + a.B.nb + 1,
-                                   npi + 1);
+            int kp = pi_fast(pz[k], a.B.inv_dpi, a.B.pi_tau, npi);
+            if (is_slow<T16>(e[k]) || kp < 0) {
+                int row = slot;
+                if (is_slow<T16>(e[k]))
+                    row = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
+                int ps = kp + 1;
+                if (kp < 0)
+                    ps = band_scan(pz[k], L.lo + a.B.nb + 1, L.hi + a.B.nb + 1, npi + 1);
                 // row / ps: bands below (bin + 1), or -1 when inside a band
                 if (row == 0 || row == a.B.nb + 1 || ps == 0 || ps == npi + 1) {
                     slot = 0;   // definitely out of range
                 } else if (row < 0 || ps < 0) {
-                    push_recheck(a, i, j, dcode);
-                    slot = 0;
+                    slot = exact_slot<M>(a, L, i, j + k, dcode);
+                    rechecks++;
                 } else {
                     slot = row * npi + (ps - 1);
                 }
             } else {
-                slot = row * npi + k;
+                slot = slot * npi + kp;
             }
-            lds_add(&hb[slot], 1u);
-            if (W)
-                lds_add(&whb[slot], wi * wj);
         }
+        lds_add(&hb[slot], 1u);
+        if (W)
+            lds_add(&whb[slot], wi * ws[k]);
     }
 }
 
-// ---- binary64 pair ------------------------------------------------------
-template <int M, bool W, bool TRI, bool OFS>
-__device__ __forceinline__ void pair_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                         lds_f64wp whb, double xi, double yi, double zi,
-                                         double Dx, double Dy, double Dz, double wi, int i,
-                                         double xj, double yj, double zj, double wj, int j)
+// ---- binary64 chunk ------------------------------------------------------
+template <int M, bool W, bool TRI, bool OFS, bool T16, bool UNC, int CH>
+__device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
+                                          lds_f64wp whb, double xi, double yi, double zi,
+                                          double Dx, double Dy, double Dz, double wi, int i,
+                                          const double *xs, const double *ys, const double *zs,
+                                          const double *ws, int j)
 {
-    double dx = __dsub_rn(xi, xj), dy = __dsub_rn(yi, yj), dz = __dsub_rn(zi, zj);
-    if (OFS) {
-        dx = __dadd_rn(dx, Dx);
-        dy = __dadd_rn(dy, Dy);
-        dz = __dadd_rn(dz, Dz);
+    double s[CH], pz[CH];
+    bool c[CH];
+    unsigned key[CH];
+    int e[CH];
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+        double dx = __dsub_rn(xi, xs[k]), dy = __dsub_rn(yi, ys[k]), dz = __dsub_rn(zi, zs[k]);
+        if (OFS) {
+            dx = __dadd_rn(dx, Dx);
+            dy = __dadd_rn(dy, Dy);
+            dz = __dadd_rn(dz, Dz);
+        }
+        if (M == PC_METRIC_R) {
+            s[k] = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            c[k] = s[k] < a.B.E_top;
+        } else {
+            s[k] = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+            pz[k] = fabs(dz);
+            c[k] = (s[k] < a.B.E_top) && (pz[k] < a.B.pimax);
+        }
+        if (TRI)
+            c[k] = c[k] && (j + k > i);
+        key[k] = tbl_key(__double2float_rn(s[k]), a.B.tbl_base, a.B.tbl_shift,
+                         (unsigned)a.B.tbl_n - 1u);
     }
-    if (M == PC_METRIC_R) {
-        const double s =
-            __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-        bool cand = s < a.B.E_top;
-        if (TRI)
-            cand = cand && (j > i);
-        if (cand) {
-            int slot = (int)L.tbl[__float_as_uint(__double2float_rn(s)) >> a.B.tbl_shift];
-            if ((unsigned)slot & kSlow)
-                slot = slow_slot_exact(s, (unsigned)slot, L.E, a.B.nb + 1);
+#pragma unroll
+    for (int k = 0; k < CH; k++)
+        e[k] = tbl_entry<T16>(L, key[k]);
+    if (UNC) {
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            int slot = e[k];
+            if (is_slow<T16>(slot))
+                slot = slow_slot_exact<T16>(s[k], slot, L.E, a.B.nb + 1);
+            if (TRI && !(j + k > i))
+                slot = 0;
             lds_add(&hb[slot], 1u);
-            if (W)
-                lds_add(&whb[slot], wi * wj);
         }
-    } else {
-        const double rp = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
-        const double pz = fabs(dz);
-        bool cand = (rp < a.B.E_top) && (pz < a.B.pimax);
-        if (TRI)
-            cand = cand && (j > i);
-        if (cand) {
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+        if (!c[k])
+            continue;
+        int slot = e[k];
+        if (is_slow<T16>(e[k]))
+            slot = slow_slot_exact<T16>(s[k], e[k], L.E, a.B.nb + 1);
+        if (M == PC_METRIC_RPPI) {
             const int npi = a.B.npi;
-            int row = (int)L.tbl[__float_as_uint(__double2float_rn(rp)) >> a.B.tbl_shift];
-            int k = pi_fast(__double2float_rn(pz), a.B.inv_dpi, a.B.pi_tau, npi);
-            if ((unsigned)row & kSlow)
-                row = slow_slot_exact(rp, (unsigned)row, L.E, a.B.nb + 1);
-            if (k < 0)
-                k = count_le(L.q, npi, pz) - 1;
-            lds_add(&hb[row * npi + k], 1u);
-            if (W)
-                lds_add(&whb[row * npi + k], wi * wj);
+            int kp = pi_fast(__double2float_rn(pz[k]), a.B.inv_dpi, a.B.pi_tau, npi);
+            if (kp < 0)
+                kp = count_le(L.q, npi, pz[k]) - 1;
+            slot = slot * npi + kp;
         }
+        lds_add(&hb[slot], 1u);
+        if (W)
+            lds_add(&whb[slot], wi * ws[k]);
     }
 }
 
 // ---- item loops ----------------------------------------------------------
-template <int M, bool W, bool TRI>
+template <int M, bool W, bool TRI, bool T16, bool UNC>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
-                                         unsigned dcode)
+                                         unsigned dcode, unsigned &rechecks)
 {
     const float Lf = (float)a.L;
     const unsigned cx = dcode & 3u, cy = (dcode >> 2) & 3u, cz = (dcode >> 4) & 3u;
@@ -322,17 +429,18 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
             zs[k] = Z2[j + k];
             ws[k] = W ? w2[j + k] : 0.0;
         }
-#pragma unroll
-        for (int k = 0; k < CH; k++)
-            pair_f32<M, W, TRI>(a, L, hb, whb, ax, ay, az, wi, i, xs[k], ys[k], zs[k], ws[k],
-                                j + k, dcode);
+        chunk_f32<M, W, TRI, T16, UNC, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs, ws, j,
+                                           dcode, rechecks);
     }
-    for (; j < j1; j++)
-        pair_f32<M, W, TRI>(a, L, hb, whb, ax, ay, az, wi, i, X2[j], Y2[j], Z2[j],
-                            W ? w2[j] : 0.0, j, dcode);
+    for (; j < j1; j++) {
+        const float x1 = X2[j], y1 = Y2[j], z1 = Z2[j];
+        const double w1 = W ? w2[j] : 0.0;
+        chunk_f32<M, W, TRI, T16, UNC, 1>(a, L, hb, whb, ax, ay, az, wi, i, &x1, &y1, &z1, &w1,
+                                          j, dcode, rechecks);
+    }
 }
 
-template <int M, bool W, bool TRI, bool OFS>
+template <int M, bool W, bool TRI, bool OFS, bool T16, bool UNC>
 __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
                                          unsigned dcode)
@@ -355,14 +463,15 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
             zs[k] = z2[j + k];
             ws[k] = W ? w2[j + k] : 0.0;
         }
-#pragma unroll
-        for (int k = 0; k < CH; k++)
-            pair_f64<M, W, TRI, OFS>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi, i, xs[k], ys[k],
-                                     zs[k], ws[k], j + k);
+        chunk_f64<M, W, TRI, OFS, T16, UNC, CH>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi, i, xs,
+                                                ys, zs, ws, j);
     }
-    for (; j < j1; j++)
-        pair_f64<M, W, TRI, OFS>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi, i, x2[j], y2[j],
-                                 z2[j], W ? w2[j] : 0.0, j);
+    for (; j < j1; j++) {
+        const double x1 = x2[j], y1 = y2[j], z1 = z2[j];
+        const double w1 = W ? w2[j] : 0.0;
+        chunk_f64<M, W, TRI, OFS, T16, UNC, 1>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi, i, &x1,
+                                               &y1, &z1, &w1, j);
+    }
 }
 
 __device__ __forceinline__ int wave_fetch(int *counter, int lane)
@@ -385,11 +494,11 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         unsigned long long c = 0;
         double w = 0.0;
         for (int r = 0; r < a.copies; r++) {
-            c += L.hist[r * a.slots + slot];
-            L.hist[r * a.slots + slot] = 0u;
+            c += L.hist[r * a.rep_stride + slot];
+            L.hist[r * a.rep_stride + slot] = 0u;
             if (W) {
-                w += L.whist[r * a.slots + slot];
-                L.whist[r * a.slots + slot] = 0.0;
+                w += L.whist[r * a.rep_stride + slot];
+                L.whist[r * a.rep_stride + slot] = 0.0;
             }
         }
         if (c)
@@ -399,26 +508,37 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
     }
     for (int t = lane; t < a.copies * npi; t += PC_WAVE) {
         const int r = t / npi, p = t % npi;
-        L.hist[r * a.slots + p] = 0u;
-        L.hist[r * a.slots + (a.B.nb + 1) * npi + p] = 0u;
+        L.hist[r * a.rep_stride + p] = 0u;
+        L.hist[r * a.rep_stride + (a.B.nb + 1) * npi + p] = 0u;
         if (W) {
-            L.whist[r * a.slots + p] = 0.0;
-            L.whist[r * a.slots + (a.B.nb + 1) * npi + p] = 0.0;
+            L.whist[r * a.rep_stride + p] = 0.0;
+            L.whist[r * a.rep_stride + (a.B.nb + 1) * npi + p] = 0.0;
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int M, bool P32, bool W>
+template <int M, bool P32, bool W, bool T16, bool UNC>
 __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
 {
+    // the lookup table has a fixed place so its address folds into the
+    // LDS instructions; the rest of the layout is dynamic
+    __shared__ __align__(16) unsigned char s_tbl[kTblBytes];
     extern __shared__ __align__(16) unsigned char smem[];
     LDS unsigned char *sm = (LDS unsigned char *)smem;
     {
         const int tid = threadIdx.x;
-        LDS uint16_t *tbl = (LDS uint16_t *)(sm + a.o_tbl);
-        for (int k = tid; k < a.B.tbl_n; k += kSweepThreads)
-            tbl[k] = a.tbl[k];
+        if (T16) {
+            LDS uint16_t *tbl = (LDS uint16_t *)(LDS unsigned char *)s_tbl;
+            const uint16_t *src = (const uint16_t *)a.tbl;
+            for (int k = tid; k < a.B.tbl_n; k += kSweepThreads)
+                tbl[k] = src[k];
+        } else {
+            LDS unsigned char *tbl = (LDS unsigned char *)s_tbl;
+            const unsigned char *src = (const unsigned char *)a.tbl;
+            for (int k = tid; k < a.B.tbl_n; k += kSweepThreads)
+                tbl[k] = src[k];
+        }
         // float bands: the r / rp edges, then (rppi) the pi edges
         const int ne = a.B.nb + 1, nq = (M == PC_METRIC_RPPI) ? a.B.npi + 1 : 0;
         LDS float *lo = (LDS float *)(sm + a.o_lo);
@@ -451,7 +571,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     const int lane = threadIdx.x & (PC_WAVE - 1);
     const int wave = threadIdx.x / PC_WAVE;
     Lds L;
-    L.tbl = (lds_u16p)(sm + a.o_tbl);
+    L.tbl = (const LDS unsigned char *)s_tbl;
     L.lo = (lds_f32p)(sm + a.o_lo);
     L.hi = (lds_f32p)(sm + a.o_hi);
     L.E = (lds_f64p)(sm + a.o_E);
@@ -460,13 +580,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     L.whist = W ? (lds_f64wp)(sm + a.o_whist) + wave * a.whist_stride : (lds_f64wp) nullptr;
     // this lane's replica
     const int rep = lane & (a.copies - 1);
-    lds_u32p hb = L.hist + rep * a.slots;
-    lds_f64wp whb = W ? L.whist + rep * a.slots : (lds_f64wp) nullptr;
+    lds_u32p hb = L.hist + rep * a.rep_stride;
+    lds_f64wp whb = W ? L.whist + rep * a.rep_stride : (lds_f64wp) nullptr;
 
     // pairs added to this wave's uint32 replicas since the last flush
     unsigned long long pending = 0;
     const unsigned long long flush_at = 0x7fffffffull;
 
+    unsigned rechecks = 0;   // pairs this lane settled in binary64
     int next = wave_fetch(a.counter, lane);
     while (next < a.n_items) {
         const int cur = next;
@@ -485,37 +606,30 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         const int i = it.i0 + (act ? lane : 0);
         if (P32) {
             if (tri)
-                item_f32<M, W, true>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
+                item_f32<M, W, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                                               rechecks);
             else
-                item_f32<M, W, false>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
+                item_f32<M, W, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                                                rechecks);
         } else {
             if (tri)
-                item_f64<M, W, true, false>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
+                item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
             else if (dcode == 0u)
-                item_f64<M, W, false, false>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
+                item_f64<M, W, false, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1,
+                                                       dcode);
             else
-                item_f64<M, W, false, true>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
+                item_f64<M, W, false, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1,
+                                                      dcode);
         }
     }
     flush_hist(a, L, lane, W);
-}
-
-// ---- binary64 recheck of queued pairs ------------------------------------
-template <int M, bool W>
-__global__ __launch_bounds__(256) void k_recheck(SweepArgs a)
-{
-    const unsigned n = min(*a.rq_count, a.rq_cap);
-    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const uint4 e = a.rq[t];
-        const int i = (int)e.x, j = (int)e.y;
-        double s, pz;
-        exact_sep<M>(a.x1[i], a.y1[i], a.z1[i], a.x2[j], a.y2[j], a.z2[j], e.z, a.L, &s, &pz);
-        const int b = exact_bin<M>(s, pz, a.E, a.B.nb, a.q, a.B.npi, a.B.pimax);
-        if (b >= 0) {
-            atomicAdd(&a.g_hist[b], 1ull);
-            if (W)
-                atomicAdd(&a.g_whist[b], a.w1[i] * a.w2[j]);
-        }
+    if (P32) {
+        // one atomic per wave for the recheck statistic
+        unsigned tot = rechecks;
+        for (int off = PC_WAVE / 2; off > 0; off >>= 1)
+            tot += __shfl_xor(tot, off);
+        if (lane == 0 && tot)
+            atomicAdd(a.rq_count, tot);
     }
 }
 
@@ -562,25 +676,29 @@ __global__ void k_finalize(int32_t nbt, int autocorr, int e0_zero, int64_t n1,
 }
 
 template <int M, bool P32, bool W>
-const void *sweep_fn()
+const void *sweep_fn(bool t16, bool unc)
 {
-    return (const void *)&k_sweep<M, P32, W>;
+    if (t16)
+        return (const void *)&k_sweep<M, P32, W, true, false>;
+    if (unc && M == PC_METRIC_R && !W)
+        return (const void *)&k_sweep<M, P32, W, false, (M == PC_METRIC_R && !W)>;
+    return (const void *)&k_sweep<M, P32, W, false, false>;
 }
 
-const void *sweep_ptr(int metric, bool fp32, bool weighted)
+const void *sweep_ptr(int metric, bool fp32, bool weighted, bool t16, bool unc)
 {
     if (metric == PC_METRIC_R) {
         if (fp32)
-            return weighted ? sweep_fn<PC_METRIC_R, true, true>()
-                            : sweep_fn<PC_METRIC_R, true, false>();
-        return weighted ? sweep_fn<PC_METRIC_R, false, true>()
-                        : sweep_fn<PC_METRIC_R, false, false>();
+            return weighted ? sweep_fn<PC_METRIC_R, true, true>(t16, unc)
+                            : sweep_fn<PC_METRIC_R, true, false>(t16, unc);
+        return weighted ? sweep_fn<PC_METRIC_R, false, true>(t16, unc)
+                        : sweep_fn<PC_METRIC_R, false, false>(t16, unc);
     }
     if (fp32)
-        return weighted ? sweep_fn<PC_METRIC_RPPI, true, true>()
-                        : sweep_fn<PC_METRIC_RPPI, true, false>();
-    return weighted ? sweep_fn<PC_METRIC_RPPI, false, true>()
-                    : sweep_fn<PC_METRIC_RPPI, false, false>();
+        return weighted ? sweep_fn<PC_METRIC_RPPI, true, true>(t16, unc)
+                        : sweep_fn<PC_METRIC_RPPI, true, false>(t16, unc);
+    return weighted ? sweep_fn<PC_METRIC_RPPI, false, true>(t16, unc)
+                    : sweep_fn<PC_METRIC_RPPI, false, false>(t16, unc);
 }
 
 }  // namespace
@@ -590,7 +708,7 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, con
 {
     SweepArgs copy = a;
     void *args[] = {&copy};
-    const void *fn = sweep_ptr(metric, fp32, weighted);
+    const void *fn = sweep_ptr(metric, fp32, weighted, a.B.tbl_wide != 0, a.copies == PC_WAVE);
     if (a.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            a.lds_bytes);
@@ -600,33 +718,18 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, con
     return hipLaunchKernel(fn, dim3(nwg), dim3(kSweepThreads), args, (size_t)a.lds_bytes, s);
 }
 
-hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, int lds_bytes, int *per_cu)
+hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc,
+                           int lds_bytes, int *per_cu)
 {
+    const void *fn = sweep_ptr(metric, fp32, weighted, t16, unc);
     if (lds_bytes > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(sweep_ptr(metric, fp32, weighted),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        hipError_t e =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess)
             return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, sweep_ptr(metric, fp32, weighted),
-                                                        kSweepThreads, (size_t)lds_bytes);
-}
-
-hipError_t launch_recheck(hipStream_t s, int metric, bool weighted, const SweepArgs &a)
-{
-    const int grid = 1024;
-    if (metric == PC_METRIC_R) {
-        if (weighted)
-            hipLaunchKernelGGL((k_recheck<PC_METRIC_R, true>), dim3(grid), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_recheck<PC_METRIC_R, false>), dim3(grid), dim3(256), 0, s, a);
-    } else {
-        if (weighted)
-            hipLaunchKernelGGL((k_recheck<PC_METRIC_RPPI, true>), dim3(grid), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_recheck<PC_METRIC_RPPI, false>), dim3(grid), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, kSweepThreads,
+                                                        (size_t)lds_bytes);
 }
 
 hipError_t launch_wsq(hipStream_t s, int64_t n, const double *w, double *out)

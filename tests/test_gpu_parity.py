@@ -157,16 +157,19 @@ def test_r_small_and_empty(pc, olib):
         assert (got == want).all()
 
 
-def test_r_recheck_queue_overflow(pc, olib):
-    say("r recheck overflow")
+def test_r_recheck_weighted_ties(pc, olib):
+    """Pairs on edges with weights: the float32 pass hands them to the inline
+    binary64 evaluation, which must add their weight products too."""
+    say("r weighted ties")
     rng = synth.rng_for(15)
     pts = rng.integers(0, 31, size=(4000, 3)).astype(np.float64)
+    w = synth.uniform_weights(4000, seed=151)
     e = np.arange(1.0, 10.0)
-    got, _ = pc.count_r(pts, None, e, 31.0, "fp32", options={"recheck_capacity": 1})
-    st = pc.stats()
-    want, _ = oracle.count_r(pts, None, e, 31.0, lib=olib)
+    got, gw = pc.count_r(pts, None, e, 31.0, "fp32", w1=w)
+    assert pc.stats()["rechecks"] > 1000
+    want, ww = oracle.count_r(pts, None, e, 31.0, w1=w, lib=olib)
     assert (got == want).all()
-    assert st["sweep_reruns"] >= 1 and st["rechecks"] > 1
+    check_w(gw, ww)
 
 
 @pytest.mark.parametrize("chunk,spr", [(64, 1), (300, 3), (2048, 8), (100000, 20)])
@@ -187,7 +190,7 @@ def test_r_hist_replicas(pc, olib):
     pts = synth.clustered_box(6000, 40.0, seed=17, nblobs=30)
     e = synth.log_edges(0.1, 12.0, 10)
     want, _ = oracle.count_r(pts, None, e, 40.0, lib=olib)
-    for copies in (1, 2, 8, 32):
+    for copies in (1, 2, 8, 32, 64):
         got, _ = pc.count_r(pts, None, e, 40.0, "fp32", options={"hist_copies": copies})
         assert (got == want).all(), copies
 
