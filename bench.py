@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison run")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-sized device buffer three times (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; every box in this "
@@ -136,6 +139,13 @@ def main():
     import paper_1911_03545_amd as pcm
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pts = workload()
     w_ref = ref_pairs(pts, L_BOX, EDGES[-1])
     cols = tuple(torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev) for k in range(3))

@@ -29,14 +29,13 @@ enum BufId {
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
-    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_PART,
+    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_PART, B_CTRS,
     B_COUNT
 };
 
 // byte offsets inside the B_MISC buffer
 enum {
     M_FLAGS = 0,        // unsigned
-    M_COUNTER = 8,      // int
     M_RQCOUNT = 16,     // unsigned
     M_CAND = 32,        // u64
     M_WSQ = 40,         // double
@@ -466,7 +465,7 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     // ---- work list ---------------------------------------------------------
     const int32_t ncol = g.n[0] * g.n[1];
     const int64_t maxblocks = n1 / PC_BLOCK_I + ncol + 1;
-    const int chunk = opt.chunk > 0 ? opt.chunk : 2048;
+    const int chunk = opt.chunk > 0 ? std::min(opt.chunk, 1 << 20) : 2048;
     if ((st2 = ensure(c, B_BCNT, sizeof(int32_t) * (size_t)ncol)) ||
         (st2 = ensure(c, B_BOFF, sizeof(int32_t) * (size_t)(ncol + 1))) ||
         (st2 = ensure(c, B_BLOCKS, sizeof(pc_block) * (size_t)maxblocks)) ||
@@ -515,8 +514,11 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     if ((st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nbt)) ||
         (st2 = ensure(c, B_WHIST, sizeof(double) * nbt)) ||
         (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nbt)) ||
-        (st2 = ensure(c, B_OUTW, sizeof(double) * nbt)))
+        (st2 = ensure(c, B_OUTW, sizeof(double) * nbt)) ||
+        (st2 = ensure(c, B_CTRS, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE)))
         return st2;
+    HIPCHK(hipMemsetAsync(c->buf[B_CTRS].p, 0, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE,
+                          c->stream));
     HIPCHK(hipMemsetAsync(c->buf[B_HIST].p, 0, sizeof(unsigned long long) * nbt, c->stream));
     HIPCHK(hipMemsetAsync(c->buf[B_WHIST].p, 0, sizeof(double) * nbt, c->stream));
     const char *bb = (const char *)c->buf[B_BINS].p;
@@ -524,7 +526,7 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     memset(&a, 0, sizeof(a));
     a.items = dptr<pc_item>(c, B_ITEMS);
     a.n_items = n_items;
-    a.counter = (int32_t *)(misc(c) + M_COUNTER);
+    a.counter = dptr<int32_t>(c, B_CTRS);
     a.X1 = dptr<float>(c, B_X1);
     a.Y1 = dptr<float>(c, B_Y1);
     a.Z1 = dptr<float>(c, B_Z1);
@@ -590,9 +592,9 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     // replica stride: odd, so the 64 lanes' copies of one slot spread over banks
     a.rep_stride = a.slots | 1;
     a.hist_stride = (int32_t)(copies * a.rep_stride);
-    a.o_hist = take(4 * 4 * a.hist_stride);
+    a.o_hist = take(4 * a.hist_stride);   // shared by the workgroup's waves
     a.whist_stride = weighted ? (int32_t)(copies * a.rep_stride) : 0;
-    a.o_whist = take(weighted ? 8 * 4 * a.whist_stride : 0);
+    a.o_whist = take(weighted ? 8 * a.whist_stride : 0);
     a.lds_bytes = off;
     // static LDS of the sweep: the lookup table
     if (off + (PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX) > 160 * 1024)
@@ -602,7 +604,8 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     HIPCHK(pc::sweep_occupancy(metric, fp32, weighted, hb.hdr.tbl_wide != 0,
                                copies == PC_WAVE, off, &per_cu));
     per_cu = std::max(per_cu, 1);
-    int nwg = (int)std::min<int64_t>((n_items + 3) / 4, (int64_t)c->num_cu * per_cu);
+    const int waves = pc::sweep_waves();
+    int nwg = (int)std::min<int64_t>((n_items + waves - 1) / waves, (int64_t)c->num_cu * per_cu);
     nwg = std::max(nwg, 1);
     c->stats.sweep_workgroups = nwg;
     c->stats.hist_copies = copies;
@@ -688,7 +691,7 @@ void cf_default_options(cf_options *opt)
         return;
     memset(opt, 0, sizeof(*opt));
     opt->struct_size = (int32_t)sizeof(cf_options);
-    opt->slices_per_reach = 8;
+    opt->slices_per_reach = 16;
     opt->chunk = 2048;
 }
 

@@ -4,9 +4,19 @@
 
 #define PC_WAVE 64
 #define PC_BLOCK_I 64          // i points per work item: one per lane
-#define PC_TBL8_MAX 16384      // byte lookup-table entries (up to 125 bins)
-#define PC_TBL16_MAX 8192      // 16-bit lookup-table entries (more bins)
+#ifndef PC_TBL8_MAX
+#define PC_TBL8_MAX 32768      // byte lookup-table entries (up to 125 bins)
+#endif
+#ifndef PC_TBL16_MAX
+#define PC_TBL16_MAX 16384     // 16-bit lookup-table entries (more bins)
+#endif
 #define PC_TBL8_MAX_BINS 125
+// The sweep's work items are dealt to PC_STREAMS interleaved streams (item
+// s + PC_STREAMS * t belongs to stream s), each with its own counter
+// PC_STREAM_STRIDE ints apart, so that item fetches spread over many
+// addresses instead of serialising on one.
+#define PC_STREAMS 64
+#define PC_STREAM_STRIDE 64
 #define PC_MAX_EDGES 1025      // r / rp / theta edges
 #define PC_MAX_NPI 1024
 #define PC_MAX_BINS_TOTAL 4096 // r bins, or nrp * npi

@@ -16,7 +16,7 @@ namespace pc {
 struct SweepArgs {
     const pc_item *items;
     int32_t n_items;
-    int32_t *counter;
+    int32_t *counter;      // PC_STREAMS item counters, PC_STREAM_STRIDE apart, zeroed
     const float *X1, *Y1, *Z1, *X2, *Y2, *Z2;    // float32, box frame
     const double *x1, *y1, *z1, *x2, *y2, *z2;   // binary64, input values
     const double *w1, *w2;
@@ -35,8 +35,8 @@ struct SweepArgs {
     int32_t rep_stride; // distance between replicas (slots rounded up to odd)
     // dynamic LDS layout (bytes)
     int32_t o_tbl, o_lo, o_hi, o_E, o_q, o_hist, o_whist;
-    int32_t hist_stride;   // uint32 per wave
-    int32_t whist_stride;  // double per wave
+    int32_t hist_stride;   // uint32 slots of all replicas (one set per workgroup)
+    int32_t whist_stride;  // double slots of all replicas
     int32_t lds_bytes;
 };
 
@@ -80,6 +80,8 @@ hipError_t launch_finalize(hipStream_t s, int32_t nbt, int autocorr, int e0_zero
                            const double *wsq, unsigned long long *out_counts,
                            double *out_wsum);
 // resident sweep workgroups per CU for a dynamic LDS size
+// waves per sweep workgroup
+int sweep_waves();
 hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc,
                            int lds_bytes, int *per_cu);
 

@@ -74,7 +74,7 @@ int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
         !isfinite(reach_z))
         return CF_EINVAL;
     if (slices_per_reach <= 0)
-        slices_per_reach = 8;
+        slices_per_reach = 16;
     const bool periodic = boxsize > 0.0;
     if (periodic && !isfinite(boxsize))
         return CF_EINVAL;

@@ -46,17 +46,28 @@ typedef LDS double *lds_f64wp;
 typedef const KCONST float *kf32p;
 typedef const KCONST double *kf64p;
 
-// LDS atomics on wave-private replicas
+// LDS atomics on the workgroup's histogram replicas
 __device__ __forceinline__ void lds_add(LDS unsigned *p, unsigned v)
 {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void lds_add(LDS double *p, double v)
 {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned lds_take(LDS unsigned *p)
+{
+    return __hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ double lds_take(LDS double *p)
+{
+    return __hip_atomic_exchange(p, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-constexpr int kSweepThreads = 256;
+#ifndef PC_SWEEP_THREADS
+#define PC_SWEEP_THREADS 512
+#endif
+constexpr int kSweepThreads = PC_SWEEP_THREADS;
 constexpr int kTblBytes = PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX;
 constexpr int kWaves = kSweepThreads / PC_WAVE;
 constexpr unsigned kSlow = PC_TBL_BAND | PC_TBL_MULTI;
@@ -209,7 +220,7 @@ __device__ __forceinline__ int slow_slot_exact(double s, int e, lds_f64p E, int 
 // cache), binned against the exact edges.  Returns the slot of bin + 1 (rppi:
 // (rp bin + 1) * npi + pi bin), or 0 when out of range.
 template <int M>
-__device__ __noinline__ int exact_slot(const SweepArgs &a, const Lds &L, int i, int j,
+__device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int i, int j,
                                        unsigned dcode)
 {
     const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2;
@@ -270,17 +281,29 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
     for (int k = 0; k < CH; k++)
         e[k] = tbl_entry<T16>(L, key[k]);
     if (UNC) {
-        // M == PC_METRIC_R, unweighted
+        // M == PC_METRIC_R, unweighted.  One test for the whole chunk: the
+        // slow flags of all CH entries are or-ed together, so the per-pair
+        // band resolution only runs for chunks that need it.
+        unsigned any = 0;
+#pragma unroll
+        for (int k = 0; k < CH; k++)
+            any |= (unsigned)e[k];
+        if (is_slow<T16>((int)any)) {
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                if (is_slow<T16>(e[k])) {
+                    int slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
+                    if (slot < 0) {
+                        slot = exact_slot<M>(a, L, i, j + k, dcode);
+                        rechecks++;
+                    }
+                    e[k] = slot;
+                }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < CH; k++) {
             int slot = e[k];
-            if (is_slow<T16>(slot)) {
-                slot = slow_slot<T16>(s[k], slot, L.lo, L.hi, a.B.nb + 1);
-                if (slot < 0) {
-                    slot = exact_slot<M>(a, L, i, j + k, dcode);
-                    rechecks++;
-                }
-            }
             if (TRI && !(j + k > i))
                 slot = 0;
             lds_add(&hb[slot], 1u);
@@ -474,48 +497,60 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
     }
 }
 
-__device__ __forceinline__ int wave_fetch(int *counter, int lane)
+// Take the next work item for this wave from stream s, moving on to the
+// following streams once it is exhausted.  Returns n_items when every stream
+// is exhausted.  Lane 0 reads the counter first and only increments it while
+// items remain, so exhausted streams cost one load each.
+__device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int &s)
 {
-    int v = 0;
-    if (lane == 0)
-        v = atomicAdd(counter, 1);
-    return __builtin_amdgcn_readfirstlane(v);
+    for (int tries = 0; tries < PC_STREAMS; tries++) {
+        const int len = (n_items - s + PC_STREAMS - 1) / PC_STREAMS;
+        int v = len;
+        if (lane == 0) {
+            int *c = ctrs + s * PC_STREAM_STRIDE;
+            if (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < len)
+                v = atomicAdd(c, 1);
+        }
+        v = __builtin_amdgcn_readfirstlane(v);
+        if (v < len)
+            return s + v * PC_STREAMS;
+        s = (s + 1) & (PC_STREAMS - 1);
+    }
+    return n_items;
 }
 
-// Merge this wave's replicas into the global bins and clear them.  Output bin
-// b = k * npi + p lives in slot (k + 1) * npi + p; rows 0 and nb + 1 are the
-// out-of-range catch-alls and are only cleared.
-__device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int lane, bool W)
+// Merge the workgroup's histogram replicas into the global bins and clear
+// them.  Output bin b = k * npi + p lives in slot (k + 1) * npi + p; rows 0
+// and nb + 1 are the out-of-range catch-alls and are only cleared.  Called
+// by threads t = first, first + step, ...; slots are taken with atomic
+// exchanges, so other waves may keep adding while one wave flushes.
+__device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int first, int step,
+                                           bool W)
 {
-    __builtin_amdgcn_wave_barrier();
     const int npi = a.B.npi;
-    for (int b = lane; b < a.nbt; b += PC_WAVE) {
+    for (int b = first; b < a.nbt; b += step) {
         const int slot = b + npi;
         unsigned long long c = 0;
         double w = 0.0;
         for (int r = 0; r < a.copies; r++) {
-            c += L.hist[r * a.rep_stride + slot];
-            L.hist[r * a.rep_stride + slot] = 0u;
-            if (W) {
-                w += L.whist[r * a.rep_stride + slot];
-                L.whist[r * a.rep_stride + slot] = 0.0;
-            }
+            c += lds_take(&L.hist[r * a.rep_stride + slot]);
+            if (W)
+                w += lds_take(&L.whist[r * a.rep_stride + slot]);
         }
         if (c)
             atomicAdd(&a.g_hist[b], c);
         if (W && w != 0.0)
             atomicAdd(&a.g_whist[b], w);
     }
-    for (int t = lane; t < a.copies * npi; t += PC_WAVE) {
+    for (int t = first; t < a.copies * npi; t += step) {
         const int r = t / npi, p = t % npi;
-        L.hist[r * a.rep_stride + p] = 0u;
-        L.hist[r * a.rep_stride + (a.B.nb + 1) * npi + p] = 0u;
+        lds_take(&L.hist[r * a.rep_stride + p]);
+        lds_take(&L.hist[r * a.rep_stride + (a.B.nb + 1) * npi + p]);
         if (W) {
-            L.whist[r * a.rep_stride + p] = 0.0;
-            L.whist[r * a.rep_stride + (a.B.nb + 1) * npi + p] = 0.0;
+            lds_take(&L.whist[r * a.rep_stride + p]);
+            lds_take(&L.whist[r * a.rep_stride + (a.B.nb + 1) * npi + p]);
         }
     }
-    __builtin_amdgcn_wave_barrier();
 }
 
 template <int M, bool P32, bool W, bool T16, bool UNC>
@@ -558,47 +593,51 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         for (int k = tid; k < nq; k += kSweepThreads)
             q[k] = a.q[k];
         LDS unsigned *hist = (LDS unsigned *)(sm + a.o_hist);
-        for (int k = tid; k < kWaves * a.hist_stride; k += kSweepThreads)
+        for (int k = tid; k < a.hist_stride; k += kSweepThreads)
             hist[k] = 0u;
         if (W) {
             LDS double *wh = (LDS double *)(sm + a.o_whist);
-            for (int k = tid; k < kWaves * a.whist_stride; k += kSweepThreads)
+            for (int k = tid; k < a.whist_stride; k += kSweepThreads)
                 wh[k] = 0.0;
         }
     }
     __syncthreads();
 
     const int lane = threadIdx.x & (PC_WAVE - 1);
-    const int wave = threadIdx.x / PC_WAVE;
     Lds L;
     L.tbl = (const LDS unsigned char *)s_tbl;
     L.lo = (lds_f32p)(sm + a.o_lo);
     L.hi = (lds_f32p)(sm + a.o_hi);
     L.E = (lds_f64p)(sm + a.o_E);
     L.q = (lds_f64p)(sm + a.o_q);
-    L.hist = (lds_u32p)(sm + a.o_hist) + wave * a.hist_stride;
-    L.whist = W ? (lds_f64wp)(sm + a.o_whist) + wave * a.whist_stride : (lds_f64wp) nullptr;
+    // one set of replicas shared by the workgroup's waves
+    L.hist = (lds_u32p)(sm + a.o_hist);
+    L.whist = W ? (lds_f64wp)(sm + a.o_whist) : (lds_f64wp) nullptr;
     // this lane's replica
     const int rep = lane & (a.copies - 1);
     lds_u32p hb = L.hist + rep * a.rep_stride;
     lds_f64wp whb = W ? L.whist + rep * a.rep_stride : (lds_f64wp) nullptr;
 
-    // pairs added to this wave's uint32 replicas since the last flush
+    // Pairs this wave added since its last flush.  A slot holds at most the
+    // adds since the most recent flush by any wave, i.e. at most the sum of
+    // every wave's pending count, so a per-wave bound of 2^31 / waves keeps
+    // the uint32 slots from wrapping.
     unsigned long long pending = 0;
-    const unsigned long long flush_at = 0x7fffffffull;
+    const unsigned long long flush_at = 0x7fffffffull / kWaves;
 
     unsigned rechecks = 0;   // pairs this lane settled in binary64
-    int next = wave_fetch(a.counter, lane);
+    int stream = (int)((blockIdx.x * kWaves + threadIdx.x / PC_WAVE) & (PC_STREAMS - 1));
+    int next = wave_fetch(a.counter, a.n_items, lane, stream);
     while (next < a.n_items) {
         const int cur = next;
-        next = wave_fetch(a.counter, lane);
+        next = wave_fetch(a.counter, a.n_items, lane, stream);
         const pc_item it = a.items[cur];
         const int ni = (int)PC_META_NI(it.meta);
         const unsigned dcode = PC_META_DCODE(it.meta);
         const bool tri = PC_META_TRI(it.meta) != 0;
         const unsigned long long work = (unsigned long long)ni * (unsigned)(it.j1 - it.j0);
         if (pending + work > flush_at) {
-            flush_hist(a, L, lane, W);
+            flush_hist(a, L, lane, PC_WAVE, W);
             pending = 0;
         }
         pending += work;
@@ -622,7 +661,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                                                       dcode);
         }
     }
-    flush_hist(a, L, lane, W);
+    __syncthreads();
+    flush_hist(a, L, (int)threadIdx.x, kSweepThreads, W);
     if (P32) {
         // one atomic per wave for the recheck statistic
         unsigned tot = rechecks;
@@ -717,6 +757,8 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, con
     }
     return hipLaunchKernel(fn, dim3(nwg), dim3(kSweepThreads), args, (size_t)a.lds_bytes, s);
 }
+
+int sweep_waves() { return kWaves; }
 
 hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc,
                            int lds_bytes, int *per_cu)
