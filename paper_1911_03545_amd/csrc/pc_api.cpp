@@ -434,6 +434,15 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
                     "periodic box needs every reach (r, rp, pi) at most boxsize/3");
     if (rc)
         return fail(c, (cf_status)rc, "grid planning failed");
+    record(c, timing, 1);
+
+    // ---- grid ------------------------------------------------------------
+    if ((st2 = grid_side(c, s1, g, B_START1, B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1)))
+        return st2;
+    if (!autocorr &&
+        (st2 = grid_side(c, s2, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2)))
+        return st2;
+    // the bin description is built on the host while the gridding kernels run
     double scale = periodic ? boxsize : 0.0;
     for (int a = 0; a < 3; a++)
         scale = std::max(scale, g.extent[a]);
@@ -446,20 +455,12 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         return st2;
     if ((st2 = ensure_pinned(c, std::max<size_t>(hb.buf.size(), 256))))
         return st2;
-    // pinned staging keeps the upload asynchronous; the previous contents of
-    // the pinned buffer were consumed by the synchronisation above
-    HIPCHK(hipStreamSynchronize(c->stream));
+    // pinned staging keeps the upload asynchronous; no copy that reads or
+    // writes the pinned buffer is pending here (the last one was followed by
+    // a synchronisation)
     memcpy(c->pinned, hb.buf.data(), hb.buf.size());
     HIPCHK(hipMemcpyAsync(c->buf[B_BINS].p, c->pinned, hb.buf.size(), hipMemcpyHostToDevice,
                           c->stream));
-    record(c, timing, 1);
-
-    // ---- grid ------------------------------------------------------------
-    if ((st2 = grid_side(c, s1, g, B_START1, B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1)))
-        return st2;
-    if (!autocorr &&
-        (st2 = grid_side(c, s2, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2)))
-        return st2;
     record(c, timing, 2);
 
     // ---- work list ---------------------------------------------------------

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "../../include/paircount.h"
@@ -222,18 +223,41 @@ static int build_table(const float *lo, const float *hi, int nedges, float s_top
     const uint32_t n = ((top - base) >> sh) + 2;
     tbl.assign(n, 0);
     tbl[n - 1] = (uint16_t)nedges;
+    // The band tops hi[] never decrease with k, so the bands wholly below a
+    // cell are a prefix that only grows with the key; the cell meets band k
+    // >= that prefix iff lo[k] <= c_hi, and the scan stops once every later
+    // band starts above the cell (suffix minimum of lo[]).  The general
+    // quadratic count is kept for band sets that break the ordering.
+    bool ordered = true;
+    for (int k = 1; k < nedges; k++)
+        ordered = ordered && hi[k] >= hi[k - 1];
+    std::vector<float> lo_min(nedges + 1, INFINITY);
+    for (int k = nedges - 1; k >= 0; k--)
+        lo_min[k] = std::min(lo[k], lo_min[k + 1]);
+    int prefix = 0;
     for (uint32_t key = 0; key + 1 < n; key++) {
         const uint32_t lo_b = key == 0 ? 0u : base + (key << sh);
         const uint32_t hi_b = base + (key << sh) + ((1u << sh) - 1u);
         const float c_lo = bits_f(lo_b);
         const float c_hi = bits_f(std::min(hi_b, 0x7f7fffffu));
         int below = 0, inter = 0, which = -1;
-        for (int k = 0; k < nedges; k++) {
-            if (hi[k] < c_lo)
-                below++;
-            else if (lo[k] <= c_hi) {
-                inter++;
-                which = k;
+        if (ordered) {
+            while (prefix < nedges && hi[prefix] < c_lo)
+                prefix++;
+            below = prefix;
+            for (int k = prefix; k < nedges && lo_min[k] <= c_hi; k++)
+                if (lo[k] <= c_hi) {
+                    inter++;
+                    which = k;
+                }
+        } else {
+            for (int k = 0; k < nedges; k++) {
+                if (hi[k] < c_lo)
+                    below++;
+                else if (lo[k] <= c_hi) {
+                    inter++;
+                    which = k;
+                }
             }
         }
         uint32_t e;
