@@ -626,7 +626,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     const unsigned long long flush_at = 0x7fffffffull / kWaves;
 
     unsigned rechecks = 0;   // pairs this lane settled in binary64
-    int stream = (int)((blockIdx.x * kWaves + threadIdx.x / PC_WAVE) & (PC_STREAMS - 1));
+    // wave-uniform (kept in a scalar register, so every item field and j
+    // index derived from it stays scalar)
+    int stream = __builtin_amdgcn_readfirstlane(
+        (int)((blockIdx.x * kWaves + threadIdx.x / PC_WAVE) & (PC_STREAMS - 1)));
     int next = wave_fetch(a.counter, a.n_items, lane, stream);
     while (next < a.n_items) {
         const int cur = next;
