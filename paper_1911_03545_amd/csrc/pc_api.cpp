@@ -434,6 +434,14 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
                     "periodic box needs every reach (r, rp, pi) at most boxsize/3");
     if (rc)
         return fail(c, (cf_status)rc, "grid planning failed");
+    double scale = periodic ? boxsize : 0.0;
+    for (int a = 0; a < 3; a++)
+        scale = std::max(scale, g.extent[a]);
+    const bool fp32 = prec == CF_PREC_FP32_RECHECK;
+    int fscale_log2 = 0;
+    if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, &fscale_log2)))
+        return fail(c, (cf_status)rc, "float32 scaling failed");
+    g.fscale = std::ldexp(1.0, fscale_log2);
     record(c, timing, 1);
 
     // ---- grid ------------------------------------------------------------
@@ -443,12 +451,8 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         (st2 = grid_side(c, s2, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2)))
         return st2;
     // the bin description is built on the host while the gridding kernels run
-    double scale = periodic ? boxsize : 0.0;
-    for (int a = 0; a < 3; a++)
-        scale = std::max(scale, g.extent[a]);
     pc::HostBins hb;
-    rc = pc::build_bins(metric, prec == CF_PREC_FP32_RECHECK, lin.data(), nb, pimax, npi, scale,
-                        &hb);
+    rc = pc::build_bins(metric, fp32, lin.data(), nb, pimax, npi, scale, fscale_log2, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
     if ((st2 = ensure(c, B_BINS, hb.buf.size())))
@@ -511,7 +515,6 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     record(c, timing, 3);
 
     // ---- sweep -------------------------------------------------------------
-    const bool fp32 = prec == CF_PREC_FP32_RECHECK;
     if ((st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nbt)) ||
         (st2 = ensure(c, B_WHIST, sizeof(double) * nbt)) ||
         (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nbt)) ||
@@ -549,6 +552,7 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         a.w2 = weighted ? dptr<double>(c, B_WD2) : nullptr;
     }
     a.L = periodic ? boxsize : 0.0;
+    a.Lf32 = (float)(a.L * g.fscale);
     a.B = hb.hdr;
     a.lo = (const float *)(bb + hb.lay.lo);
     a.hi = (const float *)(bb + hb.lay.hi);

@@ -5,10 +5,10 @@
 #define PC_WAVE 64
 #define PC_BLOCK_I 64          // i points per work item: one per lane
 #ifndef PC_TBL8_MAX
-#define PC_TBL8_MAX 32768      // byte lookup-table entries (up to 125 bins)
+#define PC_TBL8_MAX 40960      // byte lookup-table entries (up to 125 bins)
 #endif
 #ifndef PC_TBL16_MAX
-#define PC_TBL16_MAX 16384     // 16-bit lookup-table entries (more bins)
+#define PC_TBL16_MAX 20480     // 16-bit lookup-table entries (more bins)
 #endif
 #define PC_TBL8_MAX_BINS 125
 // The sweep's work items are dealt to PC_STREAMS interleaved streams (item
@@ -55,6 +55,7 @@ struct pc_grid {
     int32_t pad;
     double boxsize;
     int64_t ncell;
+    double fscale;       // power of two applied to the float32 coordinates
 };
 
 // A block: up to 64 consecutive sorted points of one column (one per lane).
@@ -86,7 +87,7 @@ struct pc_bins {
     int32_t e0_zero;     // first r / rp edge is exactly zero
     int32_t tbl_wide;    // 0: byte entries, 1: 16-bit entries
     uint32_t tbl_base;   // float bit pattern subtracted before the shift
-    int32_t pad;
+    int32_t fscale_log2; // float32 path: coordinates scaled by 2^fscale_log2
     float s_top;         // float32 prefilter: candidate only if s32 <= s_top
     float pi_top;        // rppi: candidate only if pi32 <= pi_top
     float inv_dpi;       // rppi: npi / pimax in float32

@@ -221,9 +221,9 @@ __global__ void k_scatter(int64_t n, const void *x, const void *y, const void *z
         const int cell = cell_of[i];
         const int64_t d = (int64_t)start[cell] + rank_of[i];
         const double cx = ld(x, f32, i), cy = ld(y, f32, i), cz = ld(z, f32, i);
-        X[d] = (float)(cx - g.lo[0]);
-        Y[d] = (float)(cy - g.lo[1]);
-        Z[d] = (float)(cz - g.lo[2]);
+        X[d] = (float)((cx - g.lo[0]) * g.fscale);
+        Y[d] = (float)((cy - g.lo[1]) * g.fscale);
+        Z[d] = (float)((cz - g.lo[2]) * g.fscale);
         xd[d] = cx;
         yd[d] = cy;
         zd[d] = cz;

@@ -21,6 +21,7 @@ struct SweepArgs {
     const double *x1, *y1, *z1, *x2, *y2, *z2;   // binary64, input values
     const double *w1, *w2;
     double L;
+    float Lf32;            // periodic length in the scaled float32 coordinates
     pc_bins B;
     const float *lo, *hi, *plo, *phi;
     const double *E, *q;

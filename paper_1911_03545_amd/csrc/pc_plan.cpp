@@ -71,6 +71,7 @@ int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
               pc_grid *g)
 {
     memset(g, 0, sizeof(*g));
+    g->fscale = 1.0;
     if (!(reach_xy > 0.0) || !(reach_z > 0.0) || !isfinite(reach_xy) ||
         !isfinite(reach_z))
         return CF_EINVAL;
@@ -192,6 +193,69 @@ static void fp64_bands(const double *edges_sq, int nedges, float *lo, float *hi)
     }
 }
 
+// Cells of the linear float32-path table: byte entries up to 125 bins, else
+// 16-bit entries, each filling the same LDS space.
+static int table_cells(int nb)
+{
+    return nb > PC_TBL8_MAX_BINS ? PC_TBL16_MAX : PC_TBL8_MAX;
+}
+
+// Entry of a table cell [c_lo, c_hi]: the number of bands wholly below the
+// cell (the histogram slot), flagged when one band (flag | edge) or several
+// bands meet the cell.
+static uint16_t cell_entry(int below, int inter, int which, bool wide)
+{
+    if (inter == 0)
+        return (uint16_t)below;
+    if (inter == 1 && which == below)
+        return (uint16_t)(wide ? ((uint32_t)below | PC_TBL_BAND) : ((uint32_t)below | PC_TBL8_BAND));
+    return (uint16_t)(wide ? PC_TBL_MULTI : PC_TBL8_MULTI);
+}
+
+// Linear table of the float32 path: cell k holds the values s with
+// floor(s) == k, i.e. [k, k + 1); the last cell also takes every clamped
+// value above it and must lie above the top band.
+static int build_linear_table(const float *lo, const float *hi, int nedges, int cells, bool wide,
+                              std::vector<uint16_t> &tbl)
+{
+    if (!(hi[nedges - 1] < (float)(cells - 1)))
+        return CF_EINVAL;
+    tbl.assign(cells, 0);
+    bool ordered = true;
+    for (int k = 1; k < nedges; k++)
+        ordered = ordered && hi[k] >= hi[k - 1];
+    std::vector<float> lo_min(nedges + 1, INFINITY);
+    for (int k = nedges - 1; k >= 0; k--)
+        lo_min[k] = std::min(lo[k], lo_min[k + 1]);
+    int prefix = 0;
+    for (int key = 0; key < cells; key++) {
+        const float c_lo = (float)key;
+        const float c_hi = key + 1 < cells ? std::nextafter((float)(key + 1), 0.0f) : INFINITY;
+        int below = 0, inter = 0, which = -1;
+        if (ordered) {
+            while (prefix < nedges && hi[prefix] < c_lo)
+                prefix++;
+            below = prefix;
+            for (int k = prefix; k < nedges && lo_min[k] <= c_hi; k++)
+                if (lo[k] <= c_hi) {
+                    inter++;
+                    which = k;
+                }
+        } else {
+            for (int k = 0; k < nedges; k++) {
+                if (hi[k] < c_lo)
+                    below++;
+                else if (lo[k] <= c_hi) {
+                    inter++;
+                    which = k;
+                }
+            }
+        }
+        tbl[key] = cell_entry(below, inter, which, wide);
+    }
+    return CF_OK;
+}
+
 // Lookup table over the float32 bit pattern of s (monotone for s >= 0),
 // key = sat(bits(s) - base) >> sh.  The table starts one cell below the first
 // band that matters, so every value below it shares cell 0; `sh` is the
@@ -260,14 +324,7 @@ static int build_table(const float *lo, const float *hi, int nedges, float s_top
                 }
             }
         }
-        uint32_t e;
-        if (inter == 0)
-            e = (uint32_t)below;
-        else if (inter == 1 && which == below)
-            e = wide ? ((uint32_t)below | PC_TBL_BAND) : ((uint32_t)below | PC_TBL8_BAND);
-        else
-            e = wide ? PC_TBL_MULTI : PC_TBL8_MULTI;
-        tbl[key] = (uint16_t)e;
+        tbl[key] = cell_entry(below, inter, which, wide);
     }
     *shift = sh;
     *base_out = base;
@@ -279,9 +336,41 @@ static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 // Pack pc_bins and its arrays for one call.  `edges` are linear (r, rp or
 // chord) edges, squared here as fl(e * e).  For rppi the pi edges are
 // q_p = p * fl(pimax / npi) (p < npi) and q_npi = pimax.
-int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
-               int npi, double coord_scale, HostBins *out)
+// Power of two m for the float32 path.  The sweep works on coordinates
+// scaled by 2^m, which scales every float32 difference, square and sum by an
+// exact power of two and so changes no rounding.  m is the largest power
+// that keeps the top band below cells - 1, where cells is the length of the
+// linear lookup table: the table cell of a value s is floor(min(s, cells -
+// 1)), so every value above the top band lands in the last cell, and the top
+// band lies in [(cells - 1) / 4, cells - 1).
+int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, int *m_out)
 {
+    const double E = edges[nb] * edges[nb];
+    float lo, hi;
+    const int ndim = (metric == PC_METRIC_RPPI) ? 2 : 3;
+    int rc = fp32_bands(&E, 1, ndim, coord_scale, &lo, &hi);
+    if (rc)
+        return rc;
+    if (!(hi > 0.0f) || !std::isfinite(hi))
+        return CF_EINVAL;
+    const double top = (double)(table_cells(nb) - 1);
+    int m = 0;
+    while (m > -60 && std::ldexp((double)hi, 2 * m) >= top)
+        m--;
+    while (m < 60 && std::ldexp((double)hi, 2 * (m + 1)) < top)
+        m++;
+    // keep every scaled coordinate and offset a normal float32 of moderate size
+    while (m > -60 && std::ldexp(2.0 * coord_scale + 1.0, m) > 0x1p100)
+        m--;
+    *m_out = m;
+    return CF_OK;
+}
+
+int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
+               int npi, double coord_scale, int fscale_log2, HostBins *out)
+{
+    if (!fp32)
+        fscale_log2 = 0;
     if (nb < 1 || nb + 1 > PC_MAX_EDGES)
         return CF_EINVAL;
     if (metric == PC_METRIC_RPPI) {
@@ -325,11 +414,33 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
             fp64_bands(q.data(), nq, plo.data(), phi.data());
         }
     }
+    // float32 path: move the float bands into the scaled coordinates (exact
+    // power-of-two scaling)
+    const int m = fscale_log2;
+    if (fp32) {
+        for (int k = 0; k < ne; k++) {
+            lo[k] = std::ldexp(lo[k], 2 * m);
+            hi[k] = std::ldexp(hi[k], 2 * m);
+            if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) ||
+                std::fpclassify(lo[k]) == FP_SUBNORMAL || std::fpclassify(hi[k]) == FP_SUBNORMAL)
+                return CF_EINVAL;
+        }
+        for (int p = 0; p < nq; p++) {
+            plo[p] = std::ldexp(plo[p], m);
+            phi[p] = std::ldexp(phi[p], m);
+        }
+    }
     std::vector<uint16_t> tbl;
     int shift = 0;
     uint32_t base = 0;
     const bool wide = nb > PC_TBL8_MAX_BINS;
-    build_table(lo.data(), hi.data(), ne, hi[nb], wide, tbl, &shift, &base);
+    if (fp32) {
+        rc = build_linear_table(lo.data(), hi.data(), ne, table_cells(nb), wide, tbl);
+        if (rc)
+            return rc;
+    } else {
+        build_table(lo.data(), hi.data(), ne, hi[nb], wide, tbl, &shift, &base);
+    }
 
     pc_bins h;
     memset(&h, 0, sizeof(h));
@@ -342,7 +453,8 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     h.e0_zero = (E[0] == 0.0) ? 1 : 0;
     h.s_top = hi[nb];
     h.pi_top = (metric == PC_METRIC_RPPI) ? phi[npi] : 0.0f;
-    h.inv_dpi = (metric == PC_METRIC_RPPI) ? (float)((double)npi / pimax) : 0.0f;
+    h.inv_dpi = (metric == PC_METRIC_RPPI) ? std::ldexp((float)((double)npi / pimax), -m) : 0.0f;
+    h.fscale_log2 = m;
     if (metric == PC_METRIC_RPPI) {
         // error of the float32 |dz| (float32 pass) or of rounding the binary64
         // |dz| to float32 (binary64 pass), in units of the pi bin width, plus

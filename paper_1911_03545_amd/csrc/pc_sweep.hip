@@ -173,6 +173,14 @@ __device__ __forceinline__ unsigned tbl_key(float s, unsigned base, int sh, unsi
     return min(__builtin_elementwise_sub_sat(__float_as_uint(s), base) >> sh, last);
 }
 
+// Key of the float32 path's linear table: floor(s) for s below the last
+// cell, the last cell for everything above (s >= 0; coordinates are scaled
+// so that the top band lies below the last cell).
+__device__ __forceinline__ unsigned tbl_key_linear(float s, float kmax)
+{
+    return (unsigned)fminf(s, kmax);
+}
+
 // Number of bands wholly below s (bin + 1), or -1 when s lies inside a band.
 __device__ __forceinline__ int band_scan(float s, lds_f32p lo, lds_f32p hi, int nedges)
 {
@@ -261,6 +269,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
     bool c[CH];
     unsigned key[CH];
     int e[CH];
+    const float kmax = (float)(a.B.tbl_n - 1);
 #pragma unroll
     for (int k = 0; k < CH; k++) {
         const float dx = ax - xs[k], dy = ay - ys[k], dz = az - zs[k];
@@ -274,7 +283,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         }
         if (TRI)
             c[k] = c[k] && (j + k > i);
-        key[k] = tbl_key(s[k], a.B.tbl_base, a.B.tbl_shift, (unsigned)a.B.tbl_n - 1u);
+        key[k] = tbl_key_linear(s[k], kmax);
     }
     // every lane reads (no exec-mask changes), so the CH reads stay in flight
 #pragma unroll
@@ -426,7 +435,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
                                          unsigned dcode, unsigned &rechecks)
 {
-    const float Lf = (float)a.L;
+    const float Lf = a.Lf32;
     const unsigned cx = dcode & 3u, cy = (dcode >> 2) & 3u, cz = (dcode >> 4) & 3u;
     const float Dx = cx == PC_D_PLUS ? Lf : (cx == PC_D_MINUS ? -Lf : 0.0f);
     const float Dy = cy == PC_D_PLUS ? Lf : (cy == PC_D_MINUS ? -Lf : 0.0f);
