@@ -101,7 +101,12 @@ typedef struct cf_options {
     int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC     */
     int32_t collect_timing;     /* time phases with HIP events (cf_stats)      */
     int32_t hist_copies;        /* LDS histogram replicas per wave (0: auto)   */
-    int32_t reserved[9];
+    int32_t use_graph;          /* replay repeated identical calls from a HIP
+                                   graph (periodic, device-resident inputs)    */
+    int32_t autotune;           /* time slices_per_reach and chunk candidates on
+                                   the first call of a workload class and reuse
+                                   the fastest (cached per context)            */
+    int32_t reserved[7];
 } cf_options;
 
 /* Statistics of the last counting call on a context. */
@@ -121,7 +126,10 @@ typedef struct cf_stats {
     float t_sweep_ms;           /* pair sweep kernel (with binary64 rechecks)  */
     float t_finalize_ms;        /* doubling, self-pairs, copy-out              */
     float t_total_ms;           /* whole call, first to last event             */
-    float reserved_f[4];
+    int32_t slices_per_reach;   /* z slices per reach used (after autotuning)  */
+    int32_t chunk;              /* max j points per work item used             */
+    int32_t replayed;           /* 1 when the call replayed a recorded graph   */
+    float reserved_f[1];
 } cf_stats;
 
 typedef struct cf_ctx cf_ctx;
@@ -159,6 +167,26 @@ cf_status count_pairs_rppi_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catalo
                               const double *rp_edges, int32_t nrp, double pimax,
                               int32_t npi, double boxsize, cf_precision prec,
                               uint64_t *counts, double *wsum, const cf_options *opt);
+
+/* Batched DD(rp, pi) autocorrelations -- many catalogues (for example the
+   mock catalogues of an MCMC fit, the use case of section "Introduction") with
+   the same bins, box and precision, counted in one pass: one gridding over
+   all catalogues (catalogue k owns its own cells), one work list and one
+   persistent sweep launch whose per-wave histograms are flushed per
+   catalogue.  cats[ncat] are borrowed like single catalogues (host or device
+   memory, any mix); all have weights or none.  Each catalogue's result
+   equals count_pairs_rppi on it alone.  counts[(c * nrp + k) * npi + p] and
+   wsum likewise; ncat in [1, 2^19]; the total number of points is limited
+   like a single call.  Returns CF_EINVAL when the cells of all catalogues
+   together exceed 2^31 (use fewer slices_per_reach). */
+cf_status count_pairs_rppi_batch(cf_ctx *ctx, const cf_catalog *cats, int32_t ncat,
+                                 const double *rp_edges, int32_t nrp, double pimax,
+                                 int32_t npi, double boxsize, cf_precision prec,
+                                 uint64_t *counts, double *wsum);
+cf_status count_pairs_rppi_batch_ex(cf_ctx *ctx, const cf_catalog *cats, int32_t ncat,
+                                    const double *rp_edges, int32_t nrp, double pimax,
+                                    int32_t npi, double boxsize, cf_precision prec,
+                                    uint64_t *counts, double *wsum, const cf_options *opt);
 
 /* DD(theta) / DR(theta) -- Table 1 "DDtheta_mocks": angular separations
    (Appendix A, spherical volumes) binned through the squared chord of unit

@@ -37,7 +37,8 @@ STATUS_NAMES = {
 EXPORTED_SYMBOLS = (
     "cf_create", "cf_destroy", "cf_last_error", "cf_get_stats", "cf_default_options",
     "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
-    "count_pairs_theta", "count_pairs_theta_ex", "cf_plan_grid", "cf_fp32_bands",
+    "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
+    "count_pairs_rppi_batch_ex", "cf_plan_grid", "cf_fp32_bands",
 )
 
 
@@ -53,7 +54,8 @@ class cf_options(ctypes.Structure):
                 ("chunk", ctypes.c_int32),
                 ("output_on_device", ctypes.c_int32), ("theta_unit_vectors", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 9)]
+                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class cf_stats(ctypes.Structure):
@@ -65,7 +67,9 @@ class cf_stats(ctypes.Structure):
                 ("t_prepare_ms", ctypes.c_float), ("t_grid_ms", ctypes.c_float),
                 ("t_worklist_ms", ctypes.c_float), ("t_sweep_ms", ctypes.c_float),
                 ("t_finalize_ms", ctypes.c_float),
-                ("t_total_ms", ctypes.c_float), ("reserved_f", ctypes.c_float * 4)]
+                ("t_total_ms", ctypes.c_float),
+                ("slices_per_reach", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("replayed", ctypes.c_int32), ("reserved_f", ctypes.c_float * 1)]
 
 
 class cf_grid_plan(ctypes.Structure):
@@ -129,6 +133,11 @@ def load_library(path: str = LIB_PATH):
         f = getattr(lib, name)
         f.argtypes = [vp, cat, cat, vp, i32, ctypes.c_int, vp, vp] + (
             [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
+        f.restype = ctypes.c_int
+    for name, ex in (("count_pairs_rppi_batch", False), ("count_pairs_rppi_batch_ex", True)):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, i32, vp, i32, dbl, i32, dbl, ctypes.c_int, vp, vp] + (
+            [ctypes.POINTER(cf_options)] if ex else [])
         f.restype = ctypes.c_int
     lib.cf_plan_grid.argtypes = [vp, vp, dbl, dbl, dbl, i32, ctypes.POINTER(cf_grid_plan)]
     lib.cf_plan_grid.restype = ctypes.c_int
@@ -351,6 +360,31 @@ class PairCounter:
         counts = counts.reshape(nb, int(npi))
         if wsum is not None:
             wsum = wsum.reshape(nb, int(npi))
+        return counts, wsum
+
+    def count_rppi_batch(self, catalogues, rp_edges=None, pimax: float = 40.0, npi: int = 40,
+                         boxsize: float = 0.0, precision="fp64", weights=None, options=None):
+        """Batched DD(rp, pi) autocorrelations of several catalogues in one
+        pass: returns (counts uint64[ncat, nrp, npi], wsum or None)."""
+        e = np.ascontiguousarray(rp_edges, dtype=np.float64)
+        nb = e.size - 1
+        ncat = len(catalogues)
+        if weights is not None and len(weights) != ncat:
+            raise ValueError("one weight array per catalogue")
+        cats = [_Cat(p, None if weights is None else weights[k]) for k, p in enumerate(catalogues)]
+        arr = (cf_catalog * max(ncat, 1))()
+        for k, cc in enumerate(cats):
+            arr[k] = cc.c
+        counts = np.zeros(ncat * nb * int(npi), dtype=np.uint64)
+        wsum = np.zeros(ncat * nb * int(npi), dtype=np.float64) if weights is not None else None
+        st = self._lib.count_pairs_rppi_batch_ex(
+            self._ctx, ctypes.cast(arr, ctypes.c_void_p), ncat, e.ctypes.data, nb, float(pimax),
+            int(npi), float(boxsize), self._prec(precision), counts.ctypes.data,
+            None if wsum is None else wsum.ctypes.data, self._opts(options))
+        self._check(st)
+        counts = counts.reshape(ncat, nb, int(npi))
+        if wsum is not None:
+            wsum = wsum.reshape(ncat, nb, int(npi))
         return counts, wsum
 
     def count_theta(self, ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,

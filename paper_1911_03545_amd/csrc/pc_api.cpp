@@ -8,6 +8,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -29,7 +31,7 @@ enum BufId {
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
-    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_PART, B_CTRS,
+    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
     B_COUNT
 };
 
@@ -38,7 +40,6 @@ enum {
     M_FLAGS = 0,        // unsigned
     M_RQCOUNT = 16,     // unsigned
     M_CAND = 32,        // u64
-    M_WSQ = 40,         // double
     M_OUT6 = 64,        // 6 doubles
     M_SIZE = 256
 };
@@ -58,6 +59,19 @@ struct cf_ctx {
     size_t pinned_cap = 0;
     hipEvent_t ev[8] = {};
     int num_cu = 256;
+    // graph replay of repeated identical calls (cf_options.use_graph)
+    int32_t last_items = 0;          // work items of the last eager call
+    std::vector<char> gkey;          // signature of the cached graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    void *gpin = nullptr;            // pinned staging owned by the graph
+    size_t gpin_cap = 0;
+    size_t g_misc = 0, g_out = 0, g_nout = 0;
+    bool g_wsum = false;
+    cf_stats gstats;
+    // autotuned (slices_per_reach, chunk) per workload class
+    std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned;
 };
 
 namespace {
@@ -82,12 +96,16 @@ cf_status fail(cf_ctx *c, cf_status st, const char *fmt, ...)
                         "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
     } while (0)
 
+void drop_graph(cf_ctx *c);
+
 cf_status ensure(cf_ctx *c, BufId id, size_t bytes)
 {
     bytes = std::max<size_t>(bytes, 256);
     DevBuf &b = c->buf[id];
     if (b.cap >= bytes)
         return CF_OK;
+    // a recorded graph holds the addresses of these buffers
+    drop_graph(c);
     if (b.p) {
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipFree(b.p));
@@ -190,12 +208,6 @@ cf_status stage(cf_ctx *c, const void *src, int dtype, int64_t n, int mem, BufId
     return CF_OK;
 }
 
-struct Side {
-    int64_t n = 0;
-    const void *x = nullptr, *y = nullptr, *z = nullptr, *w = nullptr;
-    int f32 = 0, wf32 = 0;
-};
-
 void record(cf_ctx *c, bool on, int k)
 {
     if (on)
@@ -212,42 +224,6 @@ float elapsed(cf_ctx *c, int a, int b)
     return ms;
 }
 
-// Grid one catalogue: cell index -> scan -> scatter.
-cf_status grid_side(cf_ctx *c, const Side &s, const pc_grid &g, BufId start, BufId X, BufId Y,
-                    BufId Z, BufId XD, BufId YD, BufId ZD, BufId WD, BufId CS)
-{
-    const int64_t n = s.n;
-    cf_status st;
-    if ((st = ensure(c, B_CNT, sizeof(int32_t) * (size_t)g.ncell)) ||
-        (st = ensure(c, start, sizeof(int32_t) * (size_t)(g.ncell + 1))) ||
-        (st = ensure(c, B_CELLOF, sizeof(int32_t) * (size_t)n)) ||
-        (st = ensure(c, B_RANKOF, sizeof(int32_t) * (size_t)n)) ||
-        (st = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(g.ncell))) ||
-        (st = ensure(c, X, sizeof(float) * (size_t)n)) ||
-        (st = ensure(c, Y, sizeof(float) * (size_t)n)) ||
-        (st = ensure(c, Z, sizeof(float) * (size_t)n)) ||
-        (st = ensure(c, XD, sizeof(double) * (size_t)n)) ||
-        (st = ensure(c, YD, sizeof(double) * (size_t)n)) ||
-        (st = ensure(c, ZD, sizeof(double) * (size_t)n)) ||
-        (st = ensure(c, CS, sizeof(int32_t) * (size_t)n)))
-        return st;
-    if (s.w && (st = ensure(c, WD, sizeof(double) * (size_t)n)))
-        return st;
-    unsigned *flags = (unsigned *)(misc(c) + M_FLAGS);
-    HIPCHK(hipMemsetAsync(c->buf[B_CNT].p, 0, sizeof(int32_t) * (size_t)g.ncell, c->stream));
-    HIPCHK(pc::launch_cell_index(c->stream, n, s.x, s.y, s.z, s.f32, g, dptr<unsigned>(c, B_CNT),
-                                 dptr<int32_t>(c, B_CELLOF), dptr<int32_t>(c, B_RANKOF), flags));
-    HIPCHK(pc::scan_exclusive(c->stream, dptr<int32_t>(c, B_CNT), g.ncell, dptr<int32_t>(c, start),
-                              dptr<int32_t>(c, B_SCANTMP)));
-    HIPCHK(pc::launch_scatter(c->stream, n, s.x, s.y, s.z, s.f32, s.w, s.wf32, g,
-                              dptr<int32_t>(c, B_CELLOF), dptr<int32_t>(c, B_RANKOF),
-                              dptr<int32_t>(c, start), dptr<float>(c, X), dptr<float>(c, Y),
-                              dptr<float>(c, Z), dptr<double>(c, XD), dptr<double>(c, YD),
-                              dptr<double>(c, ZD), s.w ? dptr<double>(c, WD) : nullptr,
-                              dptr<int32_t>(c, CS)));
-    return CF_OK;
-}
-
 int pow2_floor(int v)
 {
     int p = 1;
@@ -256,14 +232,158 @@ int pow2_floor(int v)
     return p;
 }
 
-cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_catalog *d2,
-              const double *edges, int32_t nb, double pimax, int32_t npi, double boxsize,
-              cf_precision prec, uint64_t *counts, double *wsum, const cf_options *opt_in)
+// One side of a call (the first or second catalogue argument): its
+// catalogues as device views, in the order of the call.
+struct SideData {
+    int ncat = 0;
+    int64_t ntot = 0;
+    std::vector<pc_cat> cats;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Stage the catalogues of one side on the device: host columns are copied
+// into one concatenated buffer per column, device columns are used in place,
+// RA/DEC become unit vectors.
+cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, int side,
+                     SideData &s, unsigned *flags)
+{
+    static const BufId inb[2][4] = {{B_IN1X, B_IN1Y, B_IN1Z, B_IN1W},
+                                    {B_IN2X, B_IN2Y, B_IN2Z, B_IN2W}};
+    s.ncat = ncat;
+    s.cats.assign(ncat, pc_cat{});
+    s.ntot = 0;
+    for (int i = 0; i < ncat; i++) {
+        s.cats[i].n = d[i].n;
+        s.cats[i].off = s.ntot;
+        s.ntot += d[i].n;
+    }
+    // host bytes of each column
+    size_t need[4] = {0, 0, 0, 0};
+    for (int i = 0; i < ncat; i++) {
+        if (d[i].mem != CF_MEM_HOST || d[i].n == 0)
+            continue;
+        const size_t b = align256(dsize(d[i].dtype) * (size_t)d[i].n);
+        need[0] += b;
+        need[1] += b;
+        if (!radec)
+            need[2] += b;
+        if (d[i].w)
+            need[3] += align256(dsize(d[i].wdtype) * (size_t)d[i].n);
+    }
+    cf_status st;
+    for (int k = 0; k < 4; k++)
+        if (need[k] && (st = ensure(c, inb[side][k], need[k])))
+            return st;
+    // unit vectors of RA/DEC input go to a separate buffer (3 ntot doubles)
+    const BufId uvb = side == 0 ? B_UV1 : B_UV2;
+    if (radec && (st = ensure(c, uvb, sizeof(double) * 3 * (size_t)std::max<int64_t>(s.ntot, 1))))
+        return st;
+    size_t hoff[4] = {0, 0, 0, 0};
+    auto place = [&](int k, const void *src, int dtype, const cf_catalog &cat) -> const void * {
+        if (cat.mem == CF_MEM_DEVICE || cat.n == 0)
+            return src;
+        char *dst = static_cast<char *>(c->buf[inb[side][k]].p) + hoff[k];
+        const size_t bytes = dsize(dtype) * (size_t)cat.n;
+        hoff[k] += align256(bytes);
+        if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return nullptr;
+        return dst;
+    };
+    for (int i = 0; i < ncat; i++) {
+        const cf_catalog &cat = d[i];
+        pc_cat &o = s.cats[i];
+        const void *x = place(0, cat.x, cat.dtype, cat);
+        const void *y = place(1, cat.y, cat.dtype, cat);
+        const void *z = radec ? nullptr : place(2, cat.z, cat.dtype, cat);
+        const void *w = cat.w ? place(3, cat.w, cat.wdtype, cat) : nullptr;
+        if (cat.n > 0 && (!x || !y || (!radec && !z) || (cat.w && !w)))
+            return fail(c, CF_EDEVICE, "host-to-device copy of catalogue %d failed", i);
+        if (radec) {
+            double *v = dptr<double>(c, uvb);
+            double *vx = v + o.off, *vy = v + s.ntot + o.off, *vz = v + 2 * s.ntot + o.off;
+            if (cat.n > 0)
+                HIPCHK(pc::launch_radec(c->stream, cat.n, x, y, cat.dtype == CF_F32,
+                                        M_PI / 180.0, vx, vy, vz, flags));
+            o.x = vx;
+            o.y = vy;
+            o.z = vz;
+            o.f32 = 0;
+        } else {
+            o.x = x;
+            o.y = y;
+            o.z = z;
+            o.f32 = cat.dtype == CF_F32;
+        }
+        o.w = w;
+        o.wf32 = cat.w ? (cat.wdtype == CF_F32) : 0;
+    }
+    return CF_OK;
+}
+
+// Grid the catalogues of one side: cell index -> scan -> scatter.  Cells of
+// catalogue k are k * ncell .. (k + 1) * ncell - 1, so the sorted arrays hold
+// the catalogues one after the other, each in cell order.
+cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool weighted,
+                    const pc_grid &g, BufId start, BufId X, BufId Y, BufId Z, BufId XD, BufId YD,
+                    BufId ZD, BufId WD, BufId CS, unsigned *flags)
+{
+    const int64_t n = s.ntot;
+    const int64_t ncells = (int64_t)s.ncat * g.ncell;
+    cf_status st;
+    if ((st = ensure(c, B_CNT, sizeof(int32_t) * (size_t)ncells)) ||
+        (st = ensure(c, start, sizeof(int32_t) * (size_t)(ncells + 1))) ||
+        (st = ensure(c, B_CELLOF, sizeof(int32_t) * (size_t)n)) ||
+        (st = ensure(c, B_RANKOF, sizeof(int32_t) * (size_t)n)) ||
+        (st = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(ncells))) ||
+        (st = ensure(c, X, sizeof(float) * (size_t)n)) ||
+        (st = ensure(c, Y, sizeof(float) * (size_t)n)) ||
+        (st = ensure(c, Z, sizeof(float) * (size_t)n)) ||
+        (st = ensure(c, XD, sizeof(double) * (size_t)n)) ||
+        (st = ensure(c, YD, sizeof(double) * (size_t)n)) ||
+        (st = ensure(c, ZD, sizeof(double) * (size_t)n)) ||
+        (st = ensure(c, CS, sizeof(int32_t) * (size_t)n)))
+        return st;
+    if (weighted && (st = ensure(c, WD, sizeof(double) * (size_t)n)))
+        return st;
+    HIPCHK(pc::launch_zero(c->stream, c->buf[B_CNT].p, sizeof(int32_t) * (size_t)ncells));
+    HIPCHK(pc::launch_cell_index(c->stream, s.ncat, cats_dev, n, g, dptr<unsigned>(c, B_CNT),
+                                 dptr<int32_t>(c, B_CELLOF), dptr<int32_t>(c, B_RANKOF), flags));
+    HIPCHK(pc::scan_exclusive(c->stream, dptr<int32_t>(c, B_CNT), ncells, dptr<int32_t>(c, start),
+                              dptr<int32_t>(c, B_SCANTMP)));
+    HIPCHK(pc::launch_scatter(c->stream, s.ncat, cats_dev, n, g, dptr<int32_t>(c, B_CELLOF),
+                              dptr<int32_t>(c, B_RANKOF), dptr<int32_t>(c, start),
+                              dptr<float>(c, X), dptr<float>(c, Y), dptr<float>(c, Z),
+                              dptr<double>(c, XD), dptr<double>(c, YD), dptr<double>(c, ZD),
+                              weighted ? dptr<double>(c, WD) : nullptr, dptr<int32_t>(c, CS)));
+    return CF_OK;
+}
+
+// The counting call behind every entry point.  d1 holds ncat catalogues
+// (ncat > 1 only for batched autocorrelations); d2 is NULL for an
+// autocorrelation.  counts / wsum hold ncat * nbins * npi values.
+// How run() executes: eagerly (with host synchronisations), or as the
+// synchronisation-free sequence recorded into a graph, with a fixed
+// work-item capacity and its own pinned staging.
+struct RunCtl {
+    bool capture = false;
+    int32_t item_cap = 0;
+    char *pin = nullptr;
+    size_t pin_cap = 0;
+    size_t pin_need = 0;   // out: pinned bytes the call needs
+    size_t p_misc = 0, p_out = 0;   // out: regions of the pinned staging
+};
+
+cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *d1,
+              int32_t ncat, const cf_catalog *d2, const double *edges, int32_t nb, double pimax,
+              int32_t npi, double boxsize, cf_precision prec, uint64_t *counts, double *wsum,
+              const cf_options *opt_in)
 {
     if (!c)
         return CF_EINVAL;
     c->err.clear();
-    memset(&c->stats, 0, sizeof(c->stats));
+    if (!ctl.capture)
+        memset(&c->stats, 0, sizeof(c->stats));
     cf_options opt;
     cf_default_options(&opt);
     if (opt_in) {
@@ -273,9 +393,21 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     }
     const bool unit_vec = theta && opt.theta_unit_vectors;
     cf_status st;
-    if ((st = check_catalog(c, d1, "d1", theta, unit_vec)))
-        return st;
+    if (ncat < 1 || ncat > PC_MAX_CATS)
+        return fail(c, CF_EINVAL, "number of catalogues must be in [1, %d]", PC_MAX_CATS);
+    if (!d1)
+        return fail(c, CF_EINVAL, "d1 is NULL");
+    for (int i = 0; i < ncat; i++) {
+        char name[32];
+        snprintf(name, sizeof(name), ncat > 1 ? "catalogue %d" : "d1", i);
+        if ((st = check_catalog(c, &d1[i], name, theta, unit_vec)))
+            return st;
+        if ((d1[i].w == nullptr) != (d1[0].w == nullptr))
+            return fail(c, CF_EINVAL, "weights must be given for every catalogue or none");
+    }
     const bool autocorr = (d2 == nullptr);
+    if (!autocorr && ncat != 1)
+        return fail(c, CF_EINVAL, "cross-correlations take one catalogue per side");
     if (!autocorr && (st = check_catalog(c, d2, "d2", theta, unit_vec)))
         return st;
     if (!autocorr && ((d1->w == nullptr) != (d2->w == nullptr)))
@@ -318,108 +450,114 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     }
     const double reach_xy = lin[nb];
     const double reach_z = (metric == PC_METRIC_RPPI) ? pimax : lin[nb];
-    const int64_t n1 = d1->n, n2 = autocorr ? d1->n : d2->n;
+    int64_t n1 = 0;
+    for (int i = 0; i < ncat; i++)
+        n1 += d1[i].n;
+    const int64_t n2 = autocorr ? n1 : d2->n;
     if (n1 + (autocorr ? 0 : n2) > (int64_t)0x7fffff00)
         return fail(c, CF_EINVAL, "too many points for one call (limit 2^31 - 256)");
+    const size_t nout = (size_t)ncat * (size_t)nbt;
 
     HIPCHK(hipSetDevice(c->device));
-    const bool timing = opt.collect_timing != 0;
+    const bool timing = opt.collect_timing != 0 && !ctl.capture;
     record(c, timing, 0);
 
     cf_status st2;
     if ((st2 = ensure(c, B_MISC, M_SIZE)))
         return st2;
-    HIPCHK(hipMemsetAsync(c->buf[B_MISC].p, 0, M_SIZE, c->stream));
+    HIPCHK(pc::launch_zero(c->stream, c->buf[B_MISC].p, M_SIZE));
 
     const bool empty = (n1 == 0) || (!autocorr && n2 == 0);
     if (empty) {
         if (opt.output_on_device) {
-            HIPCHK(hipMemsetAsync(counts, 0, sizeof(uint64_t) * nbt, c->stream));
+            HIPCHK(hipMemsetAsync(counts, 0, sizeof(uint64_t) * nout, c->stream));
             if (wsum)
-                HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double) * nbt, c->stream));
+                HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double) * nout, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
         } else {
-            memset(counts, 0, sizeof(uint64_t) * nbt);
+            memset(counts, 0, sizeof(uint64_t) * nout);
             if (wsum)
-                memset(wsum, 0, sizeof(double) * nbt);
+                memset(wsum, 0, sizeof(double) * nout);
         }
         return CF_OK;
     }
 
-    // ---- stage inputs ----------------------------------------------------
-    Side s1, s2;
-    const cf_catalog *cats[2] = {d1, autocorr ? d1 : d2};
-    Side *sides[2] = {&s1, &s2};
-    const BufId inb[2][4] = {{B_IN1X, B_IN1Y, B_IN1Z, B_IN1W}, {B_IN2X, B_IN2Y, B_IN2Z, B_IN2W}};
-    unsigned *flags = (unsigned *)(misc(c) + M_FLAGS);
-    for (int k = 0; k < (autocorr ? 1 : 2); k++) {
-        const cf_catalog *d = cats[k];
-        Side &s = *sides[k];
-        s.n = d->n;
-        if (theta && !unit_vec) {
-            const void *ra, *dec;
-            if ((st2 = stage(c, d->x, d->dtype, d->n, d->mem, inb[k][0], &ra)) ||
-                (st2 = stage(c, d->y, d->dtype, d->n, d->mem, inb[k][1], &dec)))
-                return st2;
-            // unit vectors go to the z slot and two fresh slots
-            if ((st2 = ensure(c, inb[k][2], sizeof(double) * 3 * (size_t)d->n)))
-                return st2;
-            double *v = dptr<double>(c, inb[k][2]);
-            HIPCHK(pc::launch_radec(c->stream, d->n, ra, dec, d->dtype == CF_F32, M_PI / 180.0,
-                                    v, v + d->n, v + 2 * d->n, flags));
-            s.x = v;
-            s.y = v + d->n;
-            s.z = v + 2 * d->n;
-            s.f32 = 0;
-        } else {
-            if ((st2 = stage(c, d->x, d->dtype, d->n, d->mem, inb[k][0], &s.x)) ||
-                (st2 = stage(c, d->y, d->dtype, d->n, d->mem, inb[k][1], &s.y)) ||
-                (st2 = stage(c, d->z, d->dtype, d->n, d->mem, inb[k][2], &s.z)))
-                return st2;
-            s.f32 = d->dtype == CF_F32;
-        }
-        if (d->w) {
-            if ((st2 = stage(c, d->w, d->wdtype, d->n, d->mem, inb[k][3], &s.w)))
-                return st2;
-            s.wf32 = d->wdtype == CF_F32;
-            HIPCHK(pc::launch_check_weights(c->stream, d->n, s.w, s.wf32, flags));
-        }
+    // pinned staging: [misc | side-1 catalogues | side-2 catalogue | bins |
+    // outputs]; every region has its own place, so no host write waits for a
+    // pending copy of another
+    const size_t p_misc = 0;
+    const size_t p_cats1 = align256(M_SIZE);
+    const size_t p_cats2 = p_cats1 + align256(sizeof(pc_cat) * (size_t)ncat);
+    const size_t p_bins = p_cats2 + align256(sizeof(pc_cat));
+    const size_t bins_cap = 256 * 1024 + 64 * (size_t)(nb + npi + 2);
+    const size_t p_out = p_bins + bins_cap;
+    ctl.pin_need = p_out + (sizeof(uint64_t) + sizeof(double)) * nout;
+    ctl.p_misc = p_misc;
+    ctl.p_out = p_out;
+    char *pin;
+    if (ctl.capture) {
+        if (ctl.pin_cap < ctl.pin_need)
+            return fail(c, CF_EINVAL, "graph staging too small");
+        pin = ctl.pin;
+    } else {
+        if ((st2 = ensure_pinned(c, ctl.pin_need)))
+            return st2;
+        pin = static_cast<char *>(c->pinned);
     }
-    if (autocorr)
-        s2 = s1;
+
+    // ---- stage inputs ----------------------------------------------------
+    unsigned *flags = (unsigned *)(misc(c) + M_FLAGS);
+    const bool radec = theta && !unit_vec;
+    SideData s1, s2;
+    if ((st2 = stage_side(c, d1, ncat, radec, 0, s1, flags)))
+        return st2;
+    if (!autocorr && (st2 = stage_side(c, d2, 1, radec, 1, s2, flags)))
+        return st2;
+    if ((st2 = ensure(c, B_CATS1, sizeof(pc_cat) * (size_t)ncat)) ||
+        (st2 = ensure(c, B_CATS2, sizeof(pc_cat))))
+        return st2;
+    memcpy(pin + p_cats1, s1.cats.data(), sizeof(pc_cat) * (size_t)ncat);
+    HIPCHK(hipMemcpyAsync(c->buf[B_CATS1].p, pin + p_cats1, sizeof(pc_cat) * (size_t)ncat,
+                          hipMemcpyHostToDevice, c->stream));
+    if (!autocorr) {
+        memcpy(pin + p_cats2, s2.cats.data(), sizeof(pc_cat));
+        HIPCHK(hipMemcpyAsync(c->buf[B_CATS2].p, pin + p_cats2, sizeof(pc_cat),
+                              hipMemcpyHostToDevice, c->stream));
+    }
+    const pc_cat *cats1_dev = dptr<pc_cat>(c, B_CATS1);
+    const pc_cat *cats2_dev = autocorr ? cats1_dev : dptr<pc_cat>(c, B_CATS2);
 
     // ---- bounding box ------------------------------------------------------
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     const bool periodic = boxsize > 0.0;
+    if (!periodic && ctl.capture)
+        return fail(c, CF_EINVAL, "graph replay needs a periodic box");
     if (!periodic) {
-        const int nparts = 256;
-        if ((st2 = ensure(c, B_PART, sizeof(double) * 6 * 2 * nparts)))
+        std::vector<const pc_cat *> all;
+        for (auto &k : s1.cats)
+            if (k.n > 0)
+                all.push_back(&k);
+        if (!autocorr && s2.cats[0].n > 0)
+            all.push_back(&s2.cats[0]);
+        const int nparts = all.size() > 4 ? 32 : 256;
+        if ((st2 = ensure(c, B_PART, sizeof(double) * 6 * nparts * all.size())))
             return st2;
         double *part = dptr<double>(c, B_PART);
-        HIPCHK(pc::launch_minmax(c->stream, s1.n, s1.x, s1.y, s1.z, s1.f32, part, nparts, flags));
-        int np = nparts;
-        if (!autocorr) {
-            HIPCHK(pc::launch_minmax(c->stream, s2.n, s2.x, s2.y, s2.z, s2.f32, part + 6 * nparts,
-                                     nparts, flags));
-            np = 2 * nparts;
-        }
+        for (size_t k = 0; k < all.size(); k++)
+            HIPCHK(pc::launch_minmax(c->stream, all[k]->n, all[k]->x, all[k]->y, all[k]->z,
+                                     all[k]->f32, part + 6 * nparts * k, nparts, flags));
         double *out6 = (double *)(misc(c) + M_OUT6);
-        HIPCHK(pc::launch_minmax_final(c->stream, part, np, out6));
-        if ((st2 = ensure_pinned(c, 256)))
-            return st2;
-        HIPCHK(hipMemcpyAsync(c->pinned, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(pc::launch_minmax_final(c->stream, part, nparts * (int)all.size(), out6));
+        HIPCHK(hipMemcpyAsync(pin + p_misc, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        const char *hm = (const char *)c->pinned;
+        const char *hm = pin + p_misc;
         unsigned hflags;
         memcpy(&hflags, hm + M_FLAGS, 4);
         if (hflags & PC_FLAG_RADEC)
             return fail(c, CF_ERANGE, "RA must lie in [0, 360] and DEC in [-90, 90]");
         if (hflags & PC_FLAG_NONFINITE)
             return fail(c, CF_EINVAL, "non-finite coordinate");
-        if (hflags & PC_FLAG_WEIGHT)
-            return fail(c, CF_EINVAL, "non-finite weight");
-        double o6[6];
-        memcpy(o6, hm + M_OUT6, sizeof(o6));
+        const double *o6 = (const double *)(hm + M_OUT6);
         for (int a = 0; a < 3; a++) {
             lo[a] = o6[a];
             hi[a] = o6[3 + a];
@@ -434,41 +572,44 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
                     "periodic box needs every reach (r, rp, pi) at most boxsize/3");
     if (rc)
         return fail(c, (cf_status)rc, "grid planning failed");
+    if ((int64_t)ncat * g.ncell + 1 > (int64_t)0x7fffffff)
+        return fail(c, CF_EINVAL, "too many cells for this batch; use fewer z slices");
     double scale = periodic ? boxsize : 0.0;
     for (int a = 0; a < 3; a++)
         scale = std::max(scale, g.extent[a]);
     const bool fp32 = prec == CF_PREC_FP32_RECHECK;
+    // batches: private per-wave histograms, flushed per catalogue
+    const bool priv = ncat > 1;
     int fscale_log2 = 0;
-    if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, &fscale_log2)))
+    if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, priv, &fscale_log2)))
         return fail(c, (cf_status)rc, "float32 scaling failed");
     g.fscale = std::ldexp(1.0, fscale_log2);
     record(c, timing, 1);
 
     // ---- grid ------------------------------------------------------------
-    if ((st2 = grid_side(c, s1, g, B_START1, B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1)))
+    if ((st2 = grid_side(c, s1, cats1_dev, weighted, g, B_START1, B_X1, B_Y1, B_Z1, B_XD1, B_YD1,
+                         B_ZD1, B_WD1, B_CS1, flags)))
         return st2;
     if (!autocorr &&
-        (st2 = grid_side(c, s2, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2)))
+        (st2 = grid_side(c, s2, cats2_dev, weighted, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2,
+                         B_YD2, B_ZD2, B_WD2, B_CS2, flags)))
         return st2;
     // the bin description is built on the host while the gridding kernels run
     pc::HostBins hb;
-    rc = pc::build_bins(metric, fp32, lin.data(), nb, pimax, npi, scale, fscale_log2, &hb);
+    rc = pc::build_bins(metric, fp32, lin.data(), nb, pimax, npi, scale, fscale_log2, priv, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
+    if (hb.buf.size() > bins_cap)
+        return fail(c, CF_EINVAL, "bin description too large");
     if ((st2 = ensure(c, B_BINS, hb.buf.size())))
         return st2;
-    if ((st2 = ensure_pinned(c, std::max<size_t>(hb.buf.size(), 256))))
-        return st2;
-    // pinned staging keeps the upload asynchronous; no copy that reads or
-    // writes the pinned buffer is pending here (the last one was followed by
-    // a synchronisation)
-    memcpy(c->pinned, hb.buf.data(), hb.buf.size());
-    HIPCHK(hipMemcpyAsync(c->buf[B_BINS].p, c->pinned, hb.buf.size(), hipMemcpyHostToDevice,
+    memcpy(pin + p_bins, hb.buf.data(), hb.buf.size());
+    HIPCHK(hipMemcpyAsync(c->buf[B_BINS].p, pin + p_bins, hb.buf.size(), hipMemcpyHostToDevice,
                           c->stream));
     record(c, timing, 2);
 
     // ---- work list ---------------------------------------------------------
-    const int32_t ncol = g.n[0] * g.n[1];
+    const int32_t ncol = g.n[0] * g.n[1] * ncat;   // columns of every catalogue
     const int64_t maxblocks = n1 / PC_BLOCK_I + ncol + 1;
     const int chunk = opt.chunk > 0 ? std::min(opt.chunk, 1 << 20) : 2048;
     if ((st2 = ensure(c, B_BCNT, sizeof(int32_t) * (size_t)ncol)) ||
@@ -477,7 +618,8 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         (st2 = ensure(c, B_ICNT, sizeof(int32_t) * (size_t)maxblocks)) ||
         (st2 = ensure(c, B_IOFF, sizeof(int32_t) * (size_t)(maxblocks + 1))) ||
         (st2 = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(std::max<int64_t>(
-                                        std::max<int64_t>(maxblocks, ncol), g.ncell)))))
+                                        std::max<int64_t>(maxblocks, ncol),
+                                        (int64_t)ncat * g.ncell)))))
         return st2;
     const int32_t *start1 = dptr<int32_t>(c, B_START1);
     const int32_t *start2 = autocorr ? start1 : dptr<int32_t>(c, B_START2);
@@ -487,49 +629,60 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     HIPCHK(pc::launch_block_emit(c->stream, ncol, g.n[2], start1, dptr<int32_t>(c, B_BOFF),
                                  dptr<pc_block>(c, B_BLOCKS)));
     const int32_t *nblocks_dev = dptr<int32_t>(c, B_BOFF) + ncol;
-    HIPCHK(hipMemsetAsync(c->buf[B_ICNT].p, 0, sizeof(int32_t) * (size_t)maxblocks, c->stream));
+    HIPCHK(pc::launch_zero(c->stream, c->buf[B_ICNT].p, sizeof(int32_t) * (size_t)maxblocks));
     unsigned long long *cand = (unsigned long long *)(misc(c) + M_CAND);
     HIPCHK(pc::launch_item_count(c->stream, (int32_t)maxblocks, nblocks_dev,
                                  dptr<pc_block>(c, B_BLOCKS), g, start2, dptr<int32_t>(c, B_CS1),
                                  autocorr ? 1 : 0, chunk, dptr<int32_t>(c, B_ICNT), cand));
     HIPCHK(pc::scan_exclusive(c->stream, dptr<int32_t>(c, B_ICNT), maxblocks,
                               dptr<int32_t>(c, B_IOFF), dptr<int32_t>(c, B_SCANTMP)));
-    // item count to the host (sizes the item array and the sweep launch)
-    int32_t hcounts[2];
-    HIPCHK(hipMemcpyAsync(c->pinned, dptr<int32_t>(c, B_IOFF) + maxblocks, sizeof(int32_t),
-                          hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync((char *)c->pinned + 8, nblocks_dev, sizeof(int32_t),
-                          hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    memcpy(&hcounts[0], c->pinned, 4);
-    memcpy(&hcounts[1], (char *)c->pinned + 8, 4);
-    const int32_t n_items = hcounts[0];
-    if (n_items < 0)
-        return fail(c, CF_EOVERFLOW, "work-item count overflow");
+    // Item count to the host (sizes the item array and the sweep launch);
+    // a recorded call instead takes a fixed capacity and leaves the count
+    // on the device, where the emit kernel and the sweep read it.
+    int32_t hcounts[2] = {0, 0};
+    int32_t n_items;
+    if (ctl.capture) {
+        n_items = ctl.item_cap;
+    } else {
+        HIPCHK(hipMemcpyAsync(pin + p_misc, dptr<int32_t>(c, B_IOFF) + maxblocks,
+                              sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(pin + p_misc + 8, nblocks_dev, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        memcpy(&hcounts[0], pin + p_misc, 4);
+        memcpy(&hcounts[1], pin + p_misc + 8, 4);
+        n_items = hcounts[0];
+        if (n_items < 0)
+            return fail(c, CF_EOVERFLOW, "work-item count overflow");
+        c->last_items = n_items;
+    }
     if ((st2 = ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)std::max(n_items, 1))))
         return st2;
     HIPCHK(pc::launch_item_emit(c->stream, (int32_t)maxblocks, nblocks_dev,
                                 dptr<pc_block>(c, B_BLOCKS), g, start2, dptr<int32_t>(c, B_CS1),
                                 autocorr ? 1 : 0, chunk, dptr<int32_t>(c, B_IOFF),
-                                dptr<pc_item>(c, B_ITEMS)));
+                                dptr<pc_item>(c, B_ITEMS), n_items, flags));
     record(c, timing, 3);
 
     // ---- sweep -------------------------------------------------------------
-    if ((st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nbt)) ||
-        (st2 = ensure(c, B_WHIST, sizeof(double) * nbt)) ||
-        (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nbt)) ||
-        (st2 = ensure(c, B_OUTW, sizeof(double) * nbt)) ||
+    if ((st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nout)) ||
+        (st2 = ensure(c, B_WHIST, sizeof(double) * nout)) ||
+        (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nout)) ||
+        (st2 = ensure(c, B_OUTW, sizeof(double) * nout)) ||
+        (st2 = ensure(c, B_WSQ, sizeof(double) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CTRS, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE)))
         return st2;
-    HIPCHK(hipMemsetAsync(c->buf[B_CTRS].p, 0, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE,
-                          c->stream));
-    HIPCHK(hipMemsetAsync(c->buf[B_HIST].p, 0, sizeof(unsigned long long) * nbt, c->stream));
-    HIPCHK(hipMemsetAsync(c->buf[B_WHIST].p, 0, sizeof(double) * nbt, c->stream));
+    HIPCHK(pc::launch_zero(c->stream, c->buf[B_CTRS].p,
+                           sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE));
+    HIPCHK(pc::launch_zero(c->stream, c->buf[B_HIST].p, sizeof(unsigned long long) * nout));
+    if (weighted)
+        HIPCHK(pc::launch_zero(c->stream, c->buf[B_WHIST].p, sizeof(double) * nout));
     const char *bb = (const char *)c->buf[B_BINS].p;
     pc::SweepArgs a;
     memset(&a, 0, sizeof(a));
     a.items = dptr<pc_item>(c, B_ITEMS);
     a.n_items = n_items;
+    a.n_items_dev = ctl.capture ? dptr<int32_t>(c, B_IOFF) + maxblocks : nullptr;
     a.counter = dptr<int32_t>(c, B_CTRS);
     a.X1 = dptr<float>(c, B_X1);
     a.Y1 = dptr<float>(c, B_Y1);
@@ -566,10 +719,14 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
     a.nbt = (int32_t)nbt;
     a.slots = (int32_t)((nb + 2) * npi);
+    a.priv = priv ? 1 : 0;
+    // replica stride: odd, so the lanes' copies of one slot spread over banks
+    a.rep_stride = a.slots | 1;
     // Histogram replicas: one per lane (unconditional updates, no candidate
-    // branch) for unweighted 1-D counts with few bins, else a few shared ones.
-    const bool unc_ok = metric == PC_METRIC_R && !weighted && !hb.hdr.tbl_wide &&
-                        PC_WAVE * (a.slots | 1) <= PC_MAX_HIST_WAVE;
+    // branch) for unweighted 1-D counts with few bins, else a few shared ones;
+    // private per-wave sets must fit eight waves into a modest LDS budget.
+    const bool unc_ok = !priv && metric == PC_METRIC_R && !weighted && !hb.hdr.tbl_wide &&
+                        PC_WAVE * a.rep_stride <= PC_MAX_HIST_WAVE;
     int copies;
     if (opt.hist_copies > 0)
         copies = pow2_floor(std::min(opt.hist_copies, PC_WAVE));
@@ -578,7 +735,11 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
                         : pow2_floor((int)std::max<int64_t>(1, std::min<int64_t>(16, 512 / nbt)));
     if (copies == PC_WAVE && !unc_ok)
         copies = PC_WAVE / 2;
-    while (copies > 1 && copies * (a.slots | 1) > PC_MAX_HIST_WAVE)
+    while (copies > 1 && copies * a.rep_stride > PC_MAX_HIST_WAVE)
+        copies /= 2;
+    const int waves = pc::sweep_waves();
+    const int slot_bytes = 4 + (weighted ? 8 : 0);
+    while (priv && copies > 1 && waves * copies * a.rep_stride * slot_bytes > 28 * 1024)
         copies /= 2;
     a.copies = copies;
     // dynamic LDS layout
@@ -594,62 +755,63 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     a.o_hi = take(4 * (ne + nq));
     a.o_E = take(8 * ne);
     a.o_q = take(8 * nq);
-    // replica stride: odd, so the 64 lanes' copies of one slot spread over banks
-    a.rep_stride = a.slots | 1;
+    const int sets = priv ? waves : 1;
     a.hist_stride = (int32_t)(copies * a.rep_stride);
-    a.o_hist = take(4 * a.hist_stride);   // shared by the workgroup's waves
+    a.o_hist = take(4 * sets * a.hist_stride);
     a.whist_stride = weighted ? (int32_t)(copies * a.rep_stride) : 0;
-    a.o_whist = take(weighted ? 8 * a.whist_stride : 0);
+    a.o_whist = take(weighted ? 8 * sets * a.whist_stride : 0);
     a.lds_bytes = off;
     // static LDS of the sweep: the lookup table
-    if (off + (PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX) > 160 * 1024)
+    const int tbl_bytes = priv ? PC_TBL_PRIV_BYTES
+                               : (PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX);
+    if (off + tbl_bytes > 160 * 1024)
         return fail(c, CF_EINVAL, "bin configuration needs too much LDS (%d bytes)", off);
 
     int per_cu = 0;
-    HIPCHK(pc::sweep_occupancy(metric, fp32, weighted, hb.hdr.tbl_wide != 0,
-                               copies == PC_WAVE, off, &per_cu));
+    HIPCHK(pc::sweep_occupancy(metric, fp32, weighted, hb.hdr.tbl_wide != 0, copies == PC_WAVE,
+                               priv, off, &per_cu));
     per_cu = std::max(per_cu, 1);
-    const int waves = pc::sweep_waves();
-    int nwg = (int)std::min<int64_t>((n_items + waves - 1) / waves, (int64_t)c->num_cu * per_cu);
+    int nwg = ctl.capture ? c->num_cu * per_cu
+                          : (int)std::min<int64_t>((n_items + waves - 1) / waves,
+                                                   (int64_t)c->num_cu * per_cu);
     nwg = std::max(nwg, 1);
     c->stats.sweep_workgroups = nwg;
     c->stats.hist_copies = copies;
     double *wsq = nullptr;
     if (weighted && autocorr && hb.hdr.e0_zero)
-        wsq = (double *)(misc(c) + M_WSQ);
+        wsq = dptr<double>(c, B_WSQ);
     unsigned long long *outc = opt.output_on_device ? (unsigned long long *)counts
                                                     : dptr<unsigned long long>(c, B_OUTC);
     double *outw = wsum ? (opt.output_on_device ? wsum : dptr<double>(c, B_OUTW)) : nullptr;
-    const size_t need = M_SIZE + (sizeof(uint64_t) + sizeof(double)) * (size_t)nbt;
-    if ((st2 = ensure_pinned(c, need)))
-        return st2;
-    char *hp = (char *)c->pinned;
     record(c, timing, 4);
     if (n_items > 0)
         HIPCHK(pc::launch_sweep(c->stream, metric, fp32, weighted, a, nwg));
     record(c, timing, 5);
     // ---- finalize ------------------------------------------------------------
     if (wsq) {
-        HIPCHK(hipMemsetAsync(wsq, 0, sizeof(double), c->stream));
-        HIPCHK(pc::launch_wsq(c->stream, n1, dptr<double>(c, B_WD1), wsq));
+        HIPCHK(pc::launch_zero(c->stream, wsq, sizeof(double) * (size_t)ncat));
+        HIPCHK(pc::launch_wsq(c->stream, ncat, g.ncell, start1, dptr<double>(c, B_WD1), wsq));
     }
-    HIPCHK(pc::launch_finalize(c->stream, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero, n1,
-                               a.g_hist, a.g_whist, wsq, outc, outw));
-    HIPCHK(hipMemcpyAsync(hp, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(pc::launch_finalize(c->stream, ncat, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero,
+                               cats1_dev, a.g_hist, a.g_whist, wsq, outc, outw));
+    char *hp = pin + p_out;
+    HIPCHK(hipMemcpyAsync(pin + p_misc, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
     if (!opt.output_on_device) {
-        HIPCHK(hipMemcpyAsync(hp + M_SIZE, outc, sizeof(uint64_t) * nbt, hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(hp, outc, sizeof(uint64_t) * nout, hipMemcpyDeviceToHost,
                               c->stream));
         if (outw)
-            HIPCHK(hipMemcpyAsync(hp + M_SIZE + sizeof(uint64_t) * nbt, outw,
-                                  sizeof(double) * nbt, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(hp + sizeof(uint64_t) * nout, outw, sizeof(double) * nout,
+                                  hipMemcpyDeviceToHost, c->stream));
     }
     record(c, timing, 6);
+    if (ctl.capture)
+        return CF_OK;
     HIPCHK(hipStreamSynchronize(c->stream));
+    const char *hm = pin + p_misc;
     unsigned rqn = 0;
-    memcpy(&rqn, hp + M_RQCOUNT, 4);
-
+    memcpy(&rqn, hm + M_RQCOUNT, 4);
     unsigned hflags;
-    memcpy(&hflags, hp + M_FLAGS, 4);
+    memcpy(&hflags, hm + M_FLAGS, 4);
     if (hflags & PC_FLAG_RADEC)
         return fail(c, CF_ERANGE, "RA must lie in [0, 360] and DEC in [-90, 90]");
     if (hflags & PC_FLAG_NONFINITE)
@@ -659,18 +821,20 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
     if (hflags & PC_FLAG_WEIGHT)
         return fail(c, CF_EINVAL, "non-finite weight");
     if (!opt.output_on_device) {
-        memcpy(counts, hp + M_SIZE, sizeof(uint64_t) * nbt);
+        memcpy(counts, hp, sizeof(uint64_t) * nout);
         if (wsum)
-            memcpy(wsum, hp + M_SIZE + sizeof(uint64_t) * nbt, sizeof(double) * nbt);
+            memcpy(wsum, hp + sizeof(uint64_t) * nout, sizeof(double) * nout);
     }
     unsigned long long cnd;
-    memcpy(&cnd, hp + M_CAND, 8);
+    memcpy(&cnd, hm + M_CAND, 8);
     cf_stats &S = c->stats;
     for (int k = 0; k < 3; k++) {
         S.grid[k] = g.n[k];
         S.cell_width[k] = g.width[k];
     }
     S.zreach = g.zreach;
+    S.slices_per_reach = opt.slices_per_reach > 0 ? opt.slices_per_reach : 16;
+    S.chunk = chunk;
     S.n_blocks = hcounts[1];
     S.n_items = n_items;
     S.candidate_pairs = cnd;
@@ -683,6 +847,271 @@ cf_status run(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, const cf_
         S.t_finalize_ms = elapsed(c, 5, 6);
         S.t_total_ms = elapsed(c, 0, 6);
     }
+    return CF_OK;
+}
+
+// ---- graph replay of repeated identical calls --------------------------
+
+void key_add(std::vector<char> &k, const void *p, size_t n)
+{
+    k.insert(k.end(), static_cast<const char *>(p), static_cast<const char *>(p) + n);
+}
+
+// Everything a recorded call depends on: the catalogue views (pointers and
+// sizes, not the data), bins, box, precision, options and device outputs.
+std::vector<char> call_key(int metric, bool theta, const cf_catalog *d1, int32_t ncat,
+                           const cf_catalog *d2, const double *edges, int32_t nb, double pimax,
+                           int32_t npi, double boxsize, cf_precision prec, uint64_t *counts,
+                           double *wsum, const cf_options &opt)
+{
+    std::vector<char> k;
+    const int32_t head[5] = {metric, theta ? 1 : 0, ncat, d2 ? 1 : 0, (int32_t)prec};
+    key_add(k, head, sizeof(head));
+    key_add(k, d1, sizeof(cf_catalog) * (size_t)ncat);
+    if (d2)
+        key_add(k, d2, sizeof(cf_catalog));
+    key_add(k, &nb, sizeof(nb));
+    key_add(k, edges, sizeof(double) * (size_t)(nb + 1));
+    key_add(k, &pimax, sizeof(pimax));
+    key_add(k, &npi, sizeof(npi));
+    key_add(k, &boxsize, sizeof(boxsize));
+    key_add(k, &opt, sizeof(opt));
+    const bool has_w = wsum != nullptr;
+    key_add(k, &has_w, sizeof(has_w));
+    if (opt.output_on_device) {
+        key_add(k, &counts, sizeof(counts));
+        key_add(k, &wsum, sizeof(wsum));
+    }
+    return k;
+}
+
+void drop_graph(cf_ctx *c)
+{
+    if (c->gexec)
+        (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gkey.clear();
+}
+
+// Replay the cached graph.  Returns CF_OK with the outputs filled, a
+// failure status, or CF_EOVERFLOW when the inputs now need more work items
+// than the graph holds (the caller then runs eagerly and records anew).
+cf_status replay(cf_ctx *c, uint64_t *counts, double *wsum, const cf_options &opt)
+{
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const char *pin = static_cast<const char *>(c->gpin);
+    const char *hm = pin + c->g_misc;
+    unsigned hflags;
+    memcpy(&hflags, hm + M_FLAGS, 4);
+    if (hflags & PC_FLAG_ITEMS)
+        return CF_EOVERFLOW;
+    if (hflags & PC_FLAG_NONFINITE)
+        return fail(c, CF_EINVAL, "non-finite coordinate");
+    if (hflags & PC_FLAG_RANGE)
+        return fail(c, CF_ERANGE, "periodic coordinate outside [0, boxsize]");
+    if (hflags & PC_FLAG_WEIGHT)
+        return fail(c, CF_EINVAL, "non-finite weight");
+    if (!opt.output_on_device) {
+        memcpy(counts, pin + c->g_out, sizeof(uint64_t) * c->g_nout);
+        if (wsum && c->g_wsum)
+            memcpy(wsum, pin + c->g_out + sizeof(uint64_t) * c->g_nout,
+                   sizeof(double) * c->g_nout);
+    }
+    c->stats = c->gstats;
+    c->stats.replayed = 1;
+    unsigned rqn = 0;
+    unsigned long long cnd = 0;
+    memcpy(&rqn, hm + M_RQCOUNT, 4);
+    memcpy(&cnd, hm + M_CAND, 8);
+    c->stats.rechecks = rqn;
+    c->stats.candidate_pairs = cnd;
+    return CF_OK;
+}
+
+// Record the call's device work into a graph (after an eager run of the same
+// call has sized every buffer).  Failure only means no graph is kept.
+void record_graph(cf_ctx *c, std::vector<char> &&key, const RunCtl &eager, int metric,
+                  bool theta, const cf_catalog *d1, int32_t ncat, const cf_catalog *d2,
+                  const double *edges, int32_t nb, double pimax, int32_t npi, double boxsize,
+                  cf_precision prec, uint64_t *counts, double *wsum, const cf_options *opt)
+{
+    drop_graph(c);
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) !=
+                              hipSuccess) {
+        (void)hipGetLastError();
+        c->cap_stream = nullptr;
+        return;
+    }
+    if (c->gpin_cap < eager.pin_need) {
+        if (c->gpin)
+            (void)hipHostFree(c->gpin);
+        c->gpin = nullptr;
+        c->gpin_cap = 0;
+        if (hipHostMalloc(&c->gpin, eager.pin_need, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->gpin = nullptr;
+            return;
+        }
+        c->gpin_cap = eager.pin_need;
+    }
+    RunCtl ctl;
+    ctl.capture = true;
+    ctl.item_cap = c->last_items + c->last_items / 4 + 1024;
+    ctl.pin = static_cast<char *>(c->gpin);
+    ctl.pin_cap = c->gpin_cap;
+    if (ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)ctl.item_cap) != CF_OK)
+        return;
+    const cf_stats keep = c->stats;
+    const std::string keep_err = c->err;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    cf_status st = CF_EDEVICE;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+        st = run(c, ctl, metric, theta, d1, ncat, d2, edges, nb, pimax, npi, boxsize, prec,
+                 counts, wsum, opt);
+        if (hipStreamEndCapture(c->cap_stream, &graph) != hipSuccess)
+            st = CF_EDEVICE;
+    }
+    c->stream = user;
+    c->stats = keep;
+    c->err = keep_err;
+    hipGraphExec_t exec = nullptr;
+    if (st == CF_OK && graph &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        c->graph = graph;
+        c->gexec = exec;
+        c->gkey = std::move(key);
+        c->g_misc = ctl.p_misc;
+        c->g_out = ctl.p_out;
+        c->g_nout = (size_t)ncat * (size_t)nb * (size_t)(metric == PC_METRIC_RPPI ? npi : 1);
+        c->g_wsum = wsum != nullptr;
+        c->gstats = keep;
+        return;
+    }
+    (void)hipGetLastError();
+    if (graph)
+        (void)hipGraphDestroy(graph);
+}
+
+// Entry of every counting call: eager, or (cf_options.use_graph) a replay of
+// the graph recorded for the same call.
+// Workload class of a call for the tuning cache: metric, precision,
+// weights, auto/cross, bins, and the orders of magnitude of the points per
+// catalogue, of the catalogue count and of the mean number of neighbours
+// within the reach (points per catalogue x reach volume / domain volume).
+std::vector<int64_t> tune_key(int metric, bool theta, const cf_catalog *d1, int32_t ncat,
+                              const cf_catalog *d2, const double *edges, int32_t nb,
+                              double pimax, int32_t npi, double boxsize, cf_precision prec)
+{
+    double n = 0.0;
+    for (int i = 0; i < ncat; i++)
+        n += (double)d1[i].n;
+    n /= ncat;
+    const double r = edges[nb];
+    const double rz = metric == PC_METRIC_RPPI ? pimax : r;
+    const double vol = boxsize > 0.0 ? boxsize * boxsize * boxsize : 0.0;
+    const double neigh = vol > 0.0 ? n * r * r * rz / vol : 0.0;
+    auto mag = [](double v) { return (int64_t)std::floor(std::log2(std::max(v, 1.0))); };
+    return {metric, theta ? 1 : 0, (int64_t)prec, d1->w ? 1 : 0, d2 ? 1 : 0, nb, npi,
+            mag(n), mag((double)ncat), mag(neigh * 1e3)};
+}
+
+cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t ncat,
+                const cf_catalog *d2, const double *edges, int32_t nb, double pimax, int32_t npi,
+                double boxsize, cf_precision prec, uint64_t *counts, double *wsum,
+                const cf_options *opt_in)
+{
+    // autotuning: pick slices_per_reach and chunk by timing whole calls on
+    // the live input (coordinate descent over both), once per workload class
+    cf_options tuned_opt;
+    const cf_options *opt = opt_in;
+    if (c && opt_in && opt_in->struct_size == (int32_t)sizeof(cf_options) && opt_in->autotune &&
+        d1 && edges && nb >= 1 && ncat >= 1 && !opt_in->output_on_device) {
+        tuned_opt = *opt_in;
+        tuned_opt.autotune = 0;
+        tuned_opt.collect_timing = 0;
+        const std::vector<int64_t> tk =
+            tune_key(metric, theta, d1, ncat, d2, edges, nb, pimax, npi, boxsize, prec);
+        auto it = c->tuned.find(tk);
+        if (it == c->tuned.end()) {
+            RunCtl probe;
+            auto time_call = [&](int32_t spr, int32_t chunk, double *ms) -> cf_status {
+                cf_options o = tuned_opt;
+                o.use_graph = 0;
+                o.slices_per_reach = spr;
+                o.chunk = chunk;
+                const auto t0 = std::chrono::steady_clock::now();
+                cf_status st = run(c, probe, metric, theta, d1, ncat, d2, edges, nb, pimax, npi,
+                                   boxsize, prec, counts, wsum, &o);
+                *ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t0).count();
+                return st;
+            };
+            int32_t best_spr = 16, best_chunk = 2048;
+            double best = 0.0;
+            cf_status st = time_call(best_spr, best_chunk, &best);   // also warms buffers
+            if (st != CF_OK)
+                return st;
+            if ((st = time_call(best_spr, best_chunk, &best)))
+                return st;
+            for (int32_t spr : {2, 4, 8, 32}) {
+                double ms;
+                if ((st = time_call(spr, best_chunk, &ms)))
+                    return st;
+                if (ms < best) {
+                    best = ms;
+                    best_spr = spr;
+                }
+            }
+            for (int32_t chunk : {512, 1024, 4096, 8192}) {
+                double ms;
+                if ((st = time_call(best_spr, chunk, &ms)))
+                    return st;
+                if (ms < best) {
+                    best = ms;
+                    best_chunk = chunk;
+                }
+            }
+            it = c->tuned.emplace(tk, std::make_pair(best_spr, best_chunk)).first;
+        }
+        tuned_opt.slices_per_reach = it->second.first;
+        tuned_opt.chunk = it->second.second;
+        tuned_opt.collect_timing = opt_in->collect_timing;
+        opt = &tuned_opt;
+    }
+    RunCtl eager;
+    const bool want_graph = c && opt && opt->struct_size == (int32_t)sizeof(cf_options) &&
+                            opt->use_graph && d1 && edges && nb >= 1 && ncat >= 1;
+    if (!want_graph)
+        return run(c, eager, metric, theta, d1, ncat, d2, edges, nb, pimax, npi, boxsize, prec,
+                   counts, wsum, opt);
+    std::vector<char> key = call_key(metric, theta, d1, ncat, d2, edges, nb, pimax, npi,
+                                     boxsize, prec, counts, wsum, *opt);
+    if (c->gexec && key == c->gkey) {
+        c->err.clear();
+        cf_status st = replay(c, counts, wsum, *opt);
+        if (st != CF_EOVERFLOW)
+            return st;
+        drop_graph(c);
+    }
+    cf_status st = run(c, eager, metric, theta, d1, ncat, d2, edges, nb, pimax, npi, boxsize,
+                       prec, counts, wsum, opt);
+    if (st != CF_OK)
+        return st;
+    bool ok = boxsize > 0.0 && !theta && c->last_items > 0;
+    for (int i = 0; i < ncat && ok; i++)
+        ok = d1[i].mem == CF_MEM_DEVICE;
+    if (d2)
+        ok = ok && d2->mem == CF_MEM_DEVICE;
+    if (ok)
+        record_graph(c, std::move(key), eager, metric, theta, d1, ncat, d2, edges, nb, pimax,
+                     npi, boxsize, prec, counts, wsum, opt);
     return CF_OK;
 }
 
@@ -753,6 +1182,11 @@ cf_status cf_destroy(cf_ctx *c)
             (void)hipFree(b.p);
     if (c->pinned)
         (void)hipHostFree(c->pinned);
+    drop_graph(c);
+    if (c->gpin)
+        (void)hipHostFree(c->gpin);
+    if (c->cap_stream)
+        (void)hipStreamDestroy(c->cap_stream);
     for (auto &ev : c->ev)
         if (ev)
             (void)hipEventDestroy(ev);
@@ -779,8 +1213,8 @@ cf_status count_pairs_r_ex(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2
                            const double *edges, int32_t nbins, double boxsize, cf_precision prec,
                            uint64_t *counts, double *wsum, const cf_options *opt)
 {
-    return run(c, PC_METRIC_R, false, d1, d2, edges, nbins, 0.0, 1, boxsize, prec, counts, wsum,
-               opt);
+    return count(c, PC_METRIC_R, false, d1, 1, d2, edges, nbins, 0.0, 1, boxsize, prec, counts,
+               wsum, opt);
 }
 
 cf_status count_pairs_r(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2,
@@ -795,8 +1229,8 @@ cf_status count_pairs_rppi_ex(cf_ctx *c, const cf_catalog *d1, const cf_catalog 
                               double boxsize, cf_precision prec, uint64_t *counts, double *wsum,
                               const cf_options *opt)
 {
-    return run(c, PC_METRIC_RPPI, false, d1, d2, rp_edges, nrp, pimax, npi, boxsize, prec, counts,
-               wsum, opt);
+    return count(c, PC_METRIC_RPPI, false, d1, 1, d2, rp_edges, nrp, pimax, npi, boxsize, prec,
+               counts, wsum, opt);
 }
 
 cf_status count_pairs_rppi(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2,
@@ -807,11 +1241,29 @@ cf_status count_pairs_rppi(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2
                                nullptr);
 }
 
+cf_status count_pairs_rppi_batch_ex(cf_ctx *c, const cf_catalog *cats, int32_t ncat,
+                                    const double *rp_edges, int32_t nrp, double pimax,
+                                    int32_t npi, double boxsize, cf_precision prec,
+                                    uint64_t *counts, double *wsum, const cf_options *opt)
+{
+    return count(c, PC_METRIC_RPPI, false, cats, ncat, nullptr, rp_edges, nrp, pimax, npi, boxsize,
+               prec, counts, wsum, opt);
+}
+
+cf_status count_pairs_rppi_batch(cf_ctx *c, const cf_catalog *cats, int32_t ncat,
+                                 const double *rp_edges, int32_t nrp, double pimax, int32_t npi,
+                                 double boxsize, cf_precision prec, uint64_t *counts,
+                                 double *wsum)
+{
+    return count_pairs_rppi_batch_ex(c, cats, ncat, rp_edges, nrp, pimax, npi, boxsize, prec,
+                                     counts, wsum, nullptr);
+}
+
 cf_status count_pairs_theta_ex(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2,
                                const double *theta_edges_deg, int32_t nbins, cf_precision prec,
                                uint64_t *counts, double *wsum, const cf_options *opt)
 {
-    return run(c, PC_METRIC_R, true, d1, d2, theta_edges_deg, nbins, 0.0, 1, 0.0, prec, counts,
+    return count(c, PC_METRIC_R, true, d1, 1, d2, theta_edges_deg, nbins, 0.0, 1, 0.0, prec, counts,
                wsum, opt);
 }
 

@@ -11,6 +11,8 @@
 #define PC_TBL16_MAX 20480     // 16-bit lookup-table entries (more bins)
 #endif
 #define PC_TBL8_MAX_BINS 125
+// lookup-table bytes of the private-histogram (batched) sweep
+#define PC_TBL_PRIV_BYTES 16384
 // The sweep's work items are dealt to PC_STREAMS interleaved streams (item
 // s + PC_STREAMS * t belongs to stream s), each with its own counter
 // PC_STREAM_STRIDE ints apart, so that item fetches spread over many
@@ -77,6 +79,18 @@ struct pc_item {
 #define PC_META_NI(m) (((m) & 63u) + 1)
 #define PC_META_DCODE(m) (((m) >> 6) & 63u)
 #define PC_META_TRI(m) (((m) >> 12) & 1u)
+#define PC_META_CAT(m) ((m) >> 13)
+#define PC_MAX_CATS (1 << 19)
+
+// One catalogue of a (possibly batched) side, as seen by the device kernels:
+// device pointers of its columns, its size and its first index in the
+// concatenation of the side's catalogues.
+struct pc_cat {
+    const void *x, *y, *z, *w;
+    int64_t n;
+    int64_t off;
+    int32_t f32, wf32;
+};
 
 // Bin description uploaded once per call; float bands are [lo_k, hi_k].
 struct pc_bins {

@@ -37,6 +37,15 @@ int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
     return (int)g;
 }
 
+// Zero n 32-bit words (a kernel rather than a memset node, so that the
+// call's device work can be captured into a graph and replayed).
+__global__ void k_zero(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 // RA/DEC (degrees) -> unit vectors; d2r = fl(pi) / 180 as a binary64 value.
 __global__ void k_radec(int64_t n, const void *ra, const void *dec, int f32, double d2r,
                         double *x, double *y, double *z, unsigned *flags)
@@ -108,14 +117,6 @@ __global__ void k_minmax_final(const double *part, int nparts, double *out6)
         out6[a] = r[a];
 }
 
-__global__ void k_check_weights(int64_t n, const void *w, int f32, unsigned *flags)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        if (!isfinite(ld(w, f32, i)))
-            atomicOr(flags, PC_FLAG_WEIGHT);
-}
-
 // Cell coordinate: t = fl(fl(x - lo) * inv_w) is monotone in x; NaN and
 // negative values go to cell 0 and values at or past the far face to n - 1.
 __device__ __forceinline__ int cell_coord(double d, double inv, int n)
@@ -128,15 +129,36 @@ __device__ __forceinline__ int cell_coord(double d, double inv, int n)
     return (int)t;
 }
 
-__global__ void k_cell_index(int64_t n, const void *x, const void *y, const void *z, int f32,
-                             pc_grid g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
+// Catalogue of flattened index i: the last catalogue starting at or before
+// i (empty catalogues share their start with the next one, which wins).
+__device__ __forceinline__ int find_cat(const pc_cat *cats, int ncat, int64_t i)
+{
+    int lo = 0, hi = ncat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cats[mid].off <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Cell of every point of every catalogue of a side (catalogue c owns cells
+// c * ncell .. (c + 1) * ncell - 1) and its rank inside the cell; input
+// checks (finite, inside the periodic box, finite weights) raise flags.
+__global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
+                             unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
                              unsigned *flags)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    unsigned fl = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntot;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double c[3] = {ld(x, f32, i), ld(y, f32, i), ld(z, f32, i)};
+        const int ci = ncat == 1 ? 0 : find_cat(cats, ncat, i);
+        const pc_cat &k = cats[ci];
+        const int64_t j = i - k.off;
+        const double c[3] = {ld(k.x, k.f32, j), ld(k.y, k.f32, j), ld(k.z, k.f32, j)};
         int ia[3];
-        unsigned fl = 0;
         for (int a = 0; a < 3; a++) {
             if (!isfinite(c[a]))
                 fl |= PC_FLAG_NONFINITE;
@@ -144,12 +166,14 @@ __global__ void k_cell_index(int64_t n, const void *x, const void *y, const void
                 fl |= PC_FLAG_RANGE;
             ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
         }
-        if (fl)
-            atomicOr(flags, fl);
-        const int cell = (ia[0] * g.n[1] + ia[1]) * g.n[2] + ia[2];
+        if (k.w && !isfinite(ld(k.w, k.wf32, j)))
+            fl |= PC_FLAG_WEIGHT;
+        const int cell = (int)(ci * g.ncell) + (ia[0] * g.n[1] + ia[1]) * g.n[2] + ia[2];
         cell_of[i] = cell;
         rank_of[i] = (int32_t)atomicAdd(&cnt[cell], 1u);
     }
+    if (fl)
+        atomicOr(flags, fl);
 }
 
 // ---- exclusive scan (int32), 1024 values per workgroup -------------------
@@ -210,25 +234,27 @@ __global__ void k_scan_apply(const int32_t *in, int64_t n, const int32_t *offs, 
 }
 
 // ---- scatter into per-cell contiguous structure-of-arrays ----------------
-__global__ void k_scatter(int64_t n, const void *x, const void *y, const void *z, int f32,
-                          const void *w, int wf32, pc_grid g, const int32_t *cell_of,
-                          const int32_t *rank_of, const int32_t *start, float *X, float *Y,
-                          float *Z, double *xd, double *yd, double *zd, double *wd,
-                          int32_t *cell_sorted)
+__global__ void k_scatter(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
+                          const int32_t *cell_of, const int32_t *rank_of, const int32_t *start,
+                          float *X, float *Y, float *Z, double *xd, double *yd, double *zd,
+                          double *wd, int32_t *cell_sorted)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntot;
          i += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = ncat == 1 ? 0 : find_cat(cats, ncat, i);
+        const pc_cat &k = cats[ci];
+        const int64_t j = i - k.off;
         const int cell = cell_of[i];
         const int64_t d = (int64_t)start[cell] + rank_of[i];
-        const double cx = ld(x, f32, i), cy = ld(y, f32, i), cz = ld(z, f32, i);
+        const double cx = ld(k.x, k.f32, j), cy = ld(k.y, k.f32, j), cz = ld(k.z, k.f32, j);
         X[d] = (float)((cx - g.lo[0]) * g.fscale);
         Y[d] = (float)((cy - g.lo[1]) * g.fscale);
         Z[d] = (float)((cz - g.lo[2]) * g.fscale);
         xd[d] = cx;
         yd[d] = cy;
         zd[d] = cz;
-        if (w)
-            wd[d] = ld(w, wf32, i);
+        if (wd)
+            wd[d] = ld(k.w, k.wf32, j);
         cell_sorted[d] = cell;
     }
 }
@@ -281,7 +307,11 @@ template <class F>
 __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
 {
     const int nx = c.g.n[0], ny = c.g.n[1], nz = c.g.n[2];
-    const int ix = b.col / ny, iy = b.col % ny;
+    // columns are numbered across catalogues: catalogue k owns columns
+    // k * nx * ny ..; neighbours stay inside the block's own catalogue
+    const int lcol = b.col % (nx * ny);
+    const int cbase = b.col - lcol;
+    const int ix = lcol / ny, iy = lcol % ny;
     const int sa = c.cell1_sorted[b.i0] % nz;
     const int sb = c.cell1_sorted[b.i0 + b.ni - 1] % nz;
     const int zr = c.g.zreach;
@@ -319,7 +349,7 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
             code |= ((jy < 0) ? PC_D_PLUS : PC_D_MINUS) << 2;
             jy = (jy < 0) ? jy + ny : jy - ny;
         }
-        zwin(jx * ny + jy, code);
+        zwin(cbase + jx * ny + jy, code);
     };
 
     if (c.autocorr) {
@@ -368,13 +398,17 @@ __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
         atomicAdd(cand, my);
 }
 
+// Items beyond `cap` are not written; the flag PC_FLAG_ITEMS reports them
+// (a replayed call whose inputs now need more items than it was built for).
 __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const pc_block *blocks,
-                            SegCtx c, int chunk, const int32_t *ioff, pc_item *items)
+                            SegCtx c, int chunk, const int32_t *ioff, pc_item *items, int32_t cap,
+                            unsigned *flags)
 {
     const int nb = nblocks_dev ? *nblocks_dev : nblocks;
     for (int bi = blockIdx.x * blockDim.x + threadIdx.x; bi < nb;
          bi += gridDim.x * blockDim.x) {
         const pc_block b = blocks[bi];
+        const int cat = b.col / (c.g.n[0] * c.g.n[1]);
         int o = ioff[bi];
         for_each_segment(c, b, [&](int j0, int j1, unsigned dcode, int tri) {
             for (int j = j0; j < j1; j += chunk) {
@@ -382,14 +416,29 @@ __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const p
                 it.i0 = b.i0;
                 it.j0 = j;
                 it.j1 = min(j + chunk, j1);
-                it.meta = (unsigned)(b.ni - 1) | (dcode << 6) | ((unsigned)tri << 12);
-                items[o++] = it;
+                it.meta = (unsigned)(b.ni - 1) | (dcode << 6) | ((unsigned)tri << 12) |
+                          ((unsigned)cat << 13);
+                if (o < cap)
+                    items[o] = it;
+                o++;
             }
         });
+        if (o > cap)
+            atomicOr(flags, PC_FLAG_ITEMS);
     }
 }
 
 }  // namespace
+
+hipError_t launch_zero(hipStream_t s, void *p, size_t bytes)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(n, kThreads, 2048)), dim3(kThreads), 0, s,
+                       static_cast<uint32_t *>(p), n);
+    return hipGetLastError();
+}
 
 hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
                         double d2r, double *x, double *y, double *z, unsigned *flags)
@@ -413,19 +462,11 @@ hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, do
     return hipGetLastError();
 }
 
-hipError_t launch_check_weights(hipStream_t s, int64_t n, const void *w, int f32,
-                                unsigned *flags)
+hipError_t launch_cell_index(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
+                             const pc_grid &g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
+                             unsigned *flags)
 {
-    hipLaunchKernelGGL(k_check_weights, dim3(grid_for(n)), dim3(kThreads), 0, s, n, w, f32,
-                       flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_cell_index(hipStream_t s, int64_t n, const void *x, const void *y,
-                             const void *z, int f32, const pc_grid &g, unsigned *cnt,
-                             int32_t *cell_of, int32_t *rank_of, unsigned *flags)
-{
-    hipLaunchKernelGGL(k_cell_index, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, f32,
+    hipLaunchKernelGGL(k_cell_index, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot,
                        g, cnt, cell_of, rank_of, flags);
     return hipGetLastError();
 }
@@ -464,14 +505,13 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(hipStream_t s, int64_t n, const void *x, const void *y, const void *z,
-                          int f32, const void *w, int wf32, const pc_grid &g,
-                          const int32_t *cell_of, const int32_t *rank_of, const int32_t *start,
-                          float *X, float *Y, float *Z, double *xd, double *yd, double *zd,
-                          double *wd, int32_t *cell_sorted)
+hipError_t launch_scatter(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
+                          const pc_grid &g, const int32_t *cell_of, const int32_t *rank_of,
+                          const int32_t *start, float *X, float *Y, float *Z, double *xd,
+                          double *yd, double *zd, double *wd, int32_t *cell_sorted)
 {
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, f32, w,
-                       wf32, g, cell_of, rank_of, start, X, Y, Z, xd, yd, zd, wd, cell_sorted);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot, g,
+                       cell_of, rank_of, start, X, Y, Z, xd, yd, zd, wd, cell_sorted);
     return hipGetLastError();
 }
 
@@ -505,11 +545,11 @@ hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblo
 hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
                             const int32_t *cell1_sorted, int autocorr, int chunk,
-                            const int32_t *ioff, pc_item *items)
+                            const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags)
 {
     SegCtx c{g, start2, cell1_sorted, autocorr};
     hipLaunchKernelGGL(k_item_emit, dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
-                       nblocks_dev, blocks, c, chunk, ioff, items);
+                       nblocks_dev, blocks, c, chunk, ioff, items, cap, flags);
     return hipGetLastError();
 }
 

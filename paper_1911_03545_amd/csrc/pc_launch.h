@@ -12,10 +12,12 @@ namespace pc {
 #define PC_FLAG_RANGE 2u
 #define PC_FLAG_WEIGHT 4u
 #define PC_FLAG_RADEC 8u
+#define PC_FLAG_ITEMS 16u
 
 struct SweepArgs {
     const pc_item *items;
-    int32_t n_items;
+    int32_t n_items;              // items, or the item capacity when n_items_dev is set
+    const int32_t *n_items_dev;   // device item count (replayed calls), or NULL
     int32_t *counter;      // PC_STREAMS item counters, PC_STREAM_STRIDE apart, zeroed
     const float *X1, *Y1, *Z1, *X2, *Y2, *Z2;    // float32, box frame
     const double *x1, *y1, *z1, *x2, *y2, *z2;   // binary64, input values
@@ -29,6 +31,7 @@ struct SweepArgs {
     unsigned long long *g_hist;
     double *g_whist;
     unsigned *rq_count;   // float32 pass: pairs re-evaluated in binary64
+    int32_t priv;       // per-wave private replicas, flushed per catalogue (batches)
     int32_t copies;     // LDS histogram replicas per wave (power of two; 64 = one per
                         // lane with unconditional updates, 1-D unweighted only)
     int32_t nbt;        // bins in total (nb * npi)
@@ -41,24 +44,23 @@ struct SweepArgs {
     int32_t lds_bytes;
 };
 
+// zero `bytes` (a multiple of 4) of device memory with a kernel
+hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
 hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
                         double d2r, double *x, double *y, double *z, unsigned *flags);
 hipError_t launch_minmax(hipStream_t s, int64_t n, const void *x, const void *y,
                          const void *z, int f32, double *part, int nparts, unsigned *flags);
 hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, double *out6);
-hipError_t launch_check_weights(hipStream_t s, int64_t n, const void *w, int f32,
-                                unsigned *flags);
-hipError_t launch_cell_index(hipStream_t s, int64_t n, const void *x, const void *y,
-                             const void *z, int f32, const pc_grid &g, unsigned *cnt,
-                             int32_t *cell_of, int32_t *rank_of, unsigned *flags);
+hipError_t launch_cell_index(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
+                             const pc_grid &g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
+                             unsigned *flags);
 // exclusive scan of n int32 values into out[0..n] (out[n] = total); `tmp`
 // needs scan_tmp_elems(n) int32.
 size_t scan_tmp_elems(int64_t n);
 hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *out,
                           int32_t *tmp);
-hipError_t launch_scatter(hipStream_t s, int64_t n, const void *x, const void *y,
-                          const void *z, int f32, const void *w, int wf32, const pc_grid &g,
-                          const int32_t *cell_of, const int32_t *rank_of,
+hipError_t launch_scatter(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
+                          const pc_grid &g, const int32_t *cell_of, const int32_t *rank_of,
                           const int32_t *start, float *X, float *Y, float *Z, double *xd,
                           double *yd, double *zd, double *wd, int32_t *cell_sorted);
 hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
@@ -72,18 +74,20 @@ hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblo
 hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
                             const int32_t *cell1_sorted, int autocorr, int chunk,
-                            const int32_t *ioff, pc_item *items);
+                            const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags);
 hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted,
                         const SweepArgs &a, int nwg);
-hipError_t launch_wsq(hipStream_t s, int64_t n, const double *w, double *out);
-hipError_t launch_finalize(hipStream_t s, int32_t nbt, int autocorr, int e0_zero, int64_t n1,
-                           const unsigned long long *g_hist, const double *g_whist,
-                           const double *wsq, unsigned long long *out_counts,
-                           double *out_wsum);
+// per-catalogue sum of w^2 over the cell-ordered weights of a side
+hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
+                      const double *w, double *out);
+hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
+                           const pc_cat *cats, const unsigned long long *g_hist,
+                           const double *g_whist, const double *wsq,
+                           unsigned long long *out_counts, double *out_wsum);
 // resident sweep workgroups per CU for a dynamic LDS size
 // waves per sweep workgroup
 int sweep_waves();
-hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc,
+hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc, bool priv,
                            int lds_bytes, int *per_cu);
 
 }  // namespace pc

@@ -193,10 +193,13 @@ static void fp64_bands(const double *edges_sq, int nedges, float *lo, float *hi)
     }
 }
 
-// Cells of the linear float32-path table: byte entries up to 125 bins, else
-// 16-bit entries, each filling the same LDS space.
-static int table_cells(int nb)
+// Cells of a lookup table: byte entries up to 125 bins, else 16-bit entries,
+// each filling the same LDS space (a smaller one for the private-histogram
+// sweep of batched calls).
+static int table_cells(int nb, bool priv)
 {
+    if (priv)
+        return nb > PC_TBL8_MAX_BINS ? PC_TBL_PRIV_BYTES / 2 : PC_TBL_PRIV_BYTES;
     return nb > PC_TBL8_MAX_BINS ? PC_TBL16_MAX : PC_TBL8_MAX;
 }
 
@@ -263,9 +266,8 @@ static int build_linear_table(const float *lo, const float *hi, int nedges, int 
 // of bands wholly below the cell (the histogram slot), flagged when one band
 // (entry = flag | edge) or several bands meet the cell.
 static int build_table(const float *lo, const float *hi, int nedges, float s_top, bool wide,
-                       std::vector<uint16_t> &tbl, int *shift, uint32_t *base_out)
+                       uint32_t cap, std::vector<uint16_t> &tbl, int *shift, uint32_t *base_out)
 {
-    const uint32_t cap = wide ? PC_TBL16_MAX : PC_TBL8_MAX;
     const uint32_t top = fbits(std::max(s_top, 0.0f));
     // first band that is not the empty band of a zero edge
     uint32_t first = top;
@@ -343,7 +345,8 @@ static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 // linear lookup table: the table cell of a value s is floor(min(s, cells -
 // 1)), so every value above the top band lands in the last cell, and the top
 // band lies in [(cells - 1) / 4, cells - 1).
-int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, int *m_out)
+int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, bool priv,
+                    int *m_out)
 {
     const double E = edges[nb] * edges[nb];
     float lo, hi;
@@ -353,7 +356,7 @@ int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale,
         return rc;
     if (!(hi > 0.0f) || !std::isfinite(hi))
         return CF_EINVAL;
-    const double top = (double)(table_cells(nb) - 1);
+    const double top = (double)(table_cells(nb, priv) - 1);
     int m = 0;
     while (m > -60 && std::ldexp((double)hi, 2 * m) >= top)
         m--;
@@ -367,7 +370,7 @@ int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale,
 }
 
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
-               int npi, double coord_scale, int fscale_log2, HostBins *out)
+               int npi, double coord_scale, int fscale_log2, bool priv, HostBins *out)
 {
     if (!fp32)
         fscale_log2 = 0;
@@ -435,11 +438,12 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     uint32_t base = 0;
     const bool wide = nb > PC_TBL8_MAX_BINS;
     if (fp32) {
-        rc = build_linear_table(lo.data(), hi.data(), ne, table_cells(nb), wide, tbl);
+        rc = build_linear_table(lo.data(), hi.data(), ne, table_cells(nb, priv), wide, tbl);
         if (rc)
             return rc;
     } else {
-        build_table(lo.data(), hi.data(), ne, hi[nb], wide, tbl, &shift, &base);
+        build_table(lo.data(), hi.data(), ne, hi[nb], wide, (uint32_t)table_cells(nb, priv), tbl,
+                    &shift, &base);
     }
 
     pc_bins h;

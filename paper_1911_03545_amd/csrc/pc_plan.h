@@ -20,8 +20,10 @@ int plan_grid(const double lo[3], const double hi[3], double boxsize, double rea
               double reach_z, int slices_per_reach, pc_grid *g);
 int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
                float *hi);
-int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, int *m);
+// `priv`: size the lookup table for the private-histogram (batched) sweep
+int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, bool priv,
+                    int *m);
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax, int npi,
-               double coord_scale, int fscale_log2, HostBins *out);
+               double coord_scale, int fscale_log2, bool priv, HostBins *out);
 
 }  // namespace pc

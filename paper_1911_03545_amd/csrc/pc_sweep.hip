@@ -69,6 +69,8 @@ __device__ __forceinline__ double lds_take(LDS double *p)
 #endif
 constexpr int kSweepThreads = PC_SWEEP_THREADS;
 constexpr int kTblBytes = PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX;
+// table of the private-histogram sweep, which leaves LDS to per-wave histograms
+constexpr int kTblBytesPriv = PC_TBL_PRIV_BYTES;
 constexpr int kWaves = kSweepThreads / PC_WAVE;
 constexpr unsigned kSlow = PC_TBL_BAND | PC_TBL_MULTI;
 
@@ -528,15 +530,17 @@ __device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int 
     return n_items;
 }
 
-// Merge the workgroup's histogram replicas into the global bins and clear
+// Merge histogram replicas into the global bins of catalogue `cat` and clear
 // them.  Output bin b = k * npi + p lives in slot (k + 1) * npi + p; rows 0
 // and nb + 1 are the out-of-range catch-alls and are only cleared.  Called
 // by threads t = first, first + step, ...; slots are taken with atomic
-// exchanges, so other waves may keep adding while one wave flushes.
+// exchanges, so other waves may keep adding to shared replicas meanwhile.
 __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int first, int step,
-                                           bool W)
+                                           bool W, unsigned cat)
 {
     const int npi = a.B.npi;
+    unsigned long long *gh = a.g_hist + (size_t)cat * a.nbt;
+    double *gw = W ? a.g_whist + (size_t)cat * a.nbt : nullptr;
     for (int b = first; b < a.nbt; b += step) {
         const int slot = b + npi;
         unsigned long long c = 0;
@@ -547,9 +551,9 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
                 w += lds_take(&L.whist[r * a.rep_stride + slot]);
         }
         if (c)
-            atomicAdd(&a.g_hist[b], c);
+            atomicAdd(&gh[b], c);
         if (W && w != 0.0)
-            atomicAdd(&a.g_whist[b], w);
+            atomicAdd(&gw[b], w);
     }
     for (int t = first; t < a.copies * npi; t += step) {
         const int r = t / npi, p = t % npi;
@@ -562,12 +566,15 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
     }
 }
 
-template <int M, bool P32, bool W, bool T16, bool UNC>
+// PRIV: every wave owns its histogram replicas and flushes them whenever the
+// catalogue of its work items changes (batched calls); otherwise the
+// workgroup's waves share one set of replicas for a single catalogue.
+template <int M, bool P32, bool W, bool T16, bool UNC, bool PRIV>
 __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
 {
     // the lookup table has a fixed place so its address folds into the
     // LDS instructions; the rest of the layout is dynamic
-    __shared__ __align__(16) unsigned char s_tbl[kTblBytes];
+    __shared__ __align__(16) unsigned char s_tbl[PRIV ? kTblBytesPriv : kTblBytes];
     extern __shared__ __align__(16) unsigned char smem[];
     LDS unsigned char *sm = (LDS unsigned char *)smem;
     {
@@ -601,12 +608,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         LDS double *q = (LDS double *)(sm + a.o_q);
         for (int k = tid; k < nq; k += kSweepThreads)
             q[k] = a.q[k];
+        constexpr int sets = PRIV ? kWaves : 1;
         LDS unsigned *hist = (LDS unsigned *)(sm + a.o_hist);
-        for (int k = tid; k < a.hist_stride; k += kSweepThreads)
+        for (int k = tid; k < sets * a.hist_stride; k += kSweepThreads)
             hist[k] = 0u;
         if (W) {
             LDS double *wh = (LDS double *)(sm + a.o_whist);
-            for (int k = tid; k < a.whist_stride; k += kSweepThreads)
+            for (int k = tid; k < sets * a.whist_stride; k += kSweepThreads)
                 wh[k] = 0.0;
         }
     }
@@ -619,37 +627,52 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     L.hi = (lds_f32p)(sm + a.o_hi);
     L.E = (lds_f64p)(sm + a.o_E);
     L.q = (lds_f64p)(sm + a.o_q);
-    // one set of replicas shared by the workgroup's waves
-    L.hist = (lds_u32p)(sm + a.o_hist);
-    L.whist = W ? (lds_f64wp)(sm + a.o_whist) : (lds_f64wp) nullptr;
+    // one set of replicas shared by the workgroup's waves, or one per wave
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / PC_WAVE));
+    L.hist = (lds_u32p)(sm + a.o_hist) + (PRIV ? wave * a.hist_stride : 0);
+    L.whist = W ? (lds_f64wp)(sm + a.o_whist) + (PRIV ? wave * a.whist_stride : 0)
+                : (lds_f64wp) nullptr;
     // this lane's replica
     const int rep = lane & (a.copies - 1);
     lds_u32p hb = L.hist + rep * a.rep_stride;
     lds_f64wp whb = W ? L.whist + rep * a.rep_stride : (lds_f64wp) nullptr;
 
-    // Pairs this wave added since its last flush.  A slot holds at most the
-    // adds since the most recent flush by any wave, i.e. at most the sum of
-    // every wave's pending count, so a per-wave bound of 2^31 / waves keeps
-    // the uint32 slots from wrapping.
+    // Pairs this wave added since its last flush.  A shared slot holds at
+    // most the adds since the most recent flush by any wave, i.e. at most the
+    // sum of every wave's pending count, so a per-wave bound of 2^31 / waves
+    // keeps the uint32 slots from wrapping; private slots take 2^31.
     unsigned long long pending = 0;
-    const unsigned long long flush_at = 0x7fffffffull / kWaves;
+    const unsigned long long flush_at = PRIV ? 0x7fffffffull : 0x7fffffffull / kWaves;
+    unsigned cur_cat = 0;
 
     unsigned rechecks = 0;   // pairs this lane settled in binary64
     // wave-uniform (kept in a scalar register, so every item field and j
     // index derived from it stays scalar)
     int stream = __builtin_amdgcn_readfirstlane(
-        (int)((blockIdx.x * kWaves + threadIdx.x / PC_WAVE) & (PC_STREAMS - 1)));
-    int next = wave_fetch(a.counter, a.n_items, lane, stream);
-    while (next < a.n_items) {
+        (int)((blockIdx.x * kWaves + wave) & (PC_STREAMS - 1)));
+    int n_items = a.n_items;
+    if (a.n_items_dev)
+        n_items = min(n_items, __builtin_amdgcn_readfirstlane(*(const volatile int32_t *)a.n_items_dev));
+    int next = wave_fetch(a.counter, n_items, lane, stream);
+    while (next < n_items) {
         const int cur = next;
-        next = wave_fetch(a.counter, a.n_items, lane, stream);
+        next = wave_fetch(a.counter, n_items, lane, stream);
         const pc_item it = a.items[cur];
         const int ni = (int)PC_META_NI(it.meta);
         const unsigned dcode = PC_META_DCODE(it.meta);
         const bool tri = PC_META_TRI(it.meta) != 0;
         const unsigned long long work = (unsigned long long)ni * (unsigned)(it.j1 - it.j0);
+        if (PRIV) {
+            const unsigned cat = PC_META_CAT(it.meta);
+            if (cat != cur_cat) {
+                if (pending)
+                    flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
+                pending = 0;
+                cur_cat = cat;
+            }
+        }
         if (pending + work > flush_at) {
-            flush_hist(a, L, lane, PC_WAVE, W);
+            flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
             pending = 0;
         }
         pending += work;
@@ -673,8 +696,12 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                                                       dcode);
         }
     }
-    __syncthreads();
-    flush_hist(a, L, (int)threadIdx.x, kSweepThreads, W);
+    if (PRIV) {
+        flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
+    } else {
+        __syncthreads();
+        flush_hist(a, L, (int)threadIdx.x, kSweepThreads, W, 0u);
+    }
     if (P32) {
         // one atomic per wave for the recheck statistic
         unsigned tot = rechecks;
@@ -685,10 +712,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     }
 }
 
-__global__ void k_wsq(int64_t n, const double *w, double *out)
+// Sum of w^2 of every catalogue of a side (for its self-pairs): the weights
+// are in cell order, so catalogue c owns [start[c * ncell], start[(c + 1) *
+// ncell]).  blockIdx.y is the catalogue.
+__global__ void k_wsq(int64_t ncell, const int32_t *start, const double *w, double *out)
 {
+    const int c = blockIdx.y;
+    const int64_t a = start[c * ncell], b = start[(c + 1) * ncell];
     double s = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
          i += (int64_t)gridDim.x * blockDim.x)
         s += w[i] * w[i];
     __shared__ double sm[256];
@@ -699,58 +731,65 @@ __global__ void k_wsq(int64_t n, const double *w, double *out)
             sm[threadIdx.x] += sm[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        atomicAdd(out, sm[0]);
+    if (threadIdx.x == 0 && sm[0] != 0.0)
+        atomicAdd(&out[c], sm[0]);
 }
 
-// Appendix B: autocorrelation counts are doubled (ordered pairs) and the N
-// self-pairs join bin 0 when the first edge is zero.
-__global__ void k_finalize(int32_t nbt, int autocorr, int e0_zero, int64_t n1,
-                           const unsigned long long *g_hist, const double *g_whist,
-                           const double *wsq, unsigned long long *out_counts, double *out_wsum)
+// Appendix B: autocorrelation counts are doubled (ordered pairs) and the
+// N self-pairs of each catalogue join its bin 0 when the first edge is zero.
+__global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
+                           const pc_cat *cats, const unsigned long long *g_hist,
+                           const double *g_whist, const double *wsq,
+                           unsigned long long *out_counts, double *out_wsum)
 {
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbt; b += gridDim.x * blockDim.x) {
-        unsigned long long c = g_hist[b];
-        double w = g_whist ? g_whist[b] : 0.0;
+    const int64_t total = (int64_t)ncat * nbt;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t / nbt), b = (int)(t % nbt);
+        unsigned long long v = g_hist[t];
+        double w = g_whist ? g_whist[t] : 0.0;
         if (autocorr) {
-            c *= 2ull;
+            v *= 2ull;
             w *= 2.0;
             if (e0_zero && b == 0) {
-                c += (unsigned long long)n1;
+                v += (unsigned long long)cats[c].n;
                 if (wsq)
-                    w += *wsq;
+                    w += wsq[c];
             }
         }
-        out_counts[b] = c;
+        out_counts[t] = v;
         if (out_wsum)
-            out_wsum[b] = w;
+            out_wsum[t] = w;
     }
 }
 
 template <int M, bool P32, bool W>
-const void *sweep_fn(bool t16, bool unc)
+const void *sweep_fn(bool t16, bool unc, bool priv)
 {
+    if (priv)
+        return t16 ? (const void *)&k_sweep<M, P32, W, true, false, true>
+                   : (const void *)&k_sweep<M, P32, W, false, false, true>;
     if (t16)
-        return (const void *)&k_sweep<M, P32, W, true, false>;
+        return (const void *)&k_sweep<M, P32, W, true, false, false>;
     if (unc && M == PC_METRIC_R && !W)
-        return (const void *)&k_sweep<M, P32, W, false, (M == PC_METRIC_R && !W)>;
-    return (const void *)&k_sweep<M, P32, W, false, false>;
+        return (const void *)&k_sweep<M, P32, W, false, (M == PC_METRIC_R && !W), false>;
+    return (const void *)&k_sweep<M, P32, W, false, false, false>;
 }
 
-const void *sweep_ptr(int metric, bool fp32, bool weighted, bool t16, bool unc)
+const void *sweep_ptr(int metric, bool fp32, bool weighted, bool t16, bool unc, bool priv)
 {
     if (metric == PC_METRIC_R) {
         if (fp32)
-            return weighted ? sweep_fn<PC_METRIC_R, true, true>(t16, unc)
-                            : sweep_fn<PC_METRIC_R, true, false>(t16, unc);
-        return weighted ? sweep_fn<PC_METRIC_R, false, true>(t16, unc)
-                        : sweep_fn<PC_METRIC_R, false, false>(t16, unc);
+            return weighted ? sweep_fn<PC_METRIC_R, true, true>(t16, unc, priv)
+                            : sweep_fn<PC_METRIC_R, true, false>(t16, unc, priv);
+        return weighted ? sweep_fn<PC_METRIC_R, false, true>(t16, unc, priv)
+                        : sweep_fn<PC_METRIC_R, false, false>(t16, unc, priv);
     }
     if (fp32)
-        return weighted ? sweep_fn<PC_METRIC_RPPI, true, true>(t16, unc)
-                        : sweep_fn<PC_METRIC_RPPI, true, false>(t16, unc);
-    return weighted ? sweep_fn<PC_METRIC_RPPI, false, true>(t16, unc)
-                    : sweep_fn<PC_METRIC_RPPI, false, false>(t16, unc);
+        return weighted ? sweep_fn<PC_METRIC_RPPI, true, true>(t16, unc, priv)
+                        : sweep_fn<PC_METRIC_RPPI, true, false>(t16, unc, priv);
+    return weighted ? sweep_fn<PC_METRIC_RPPI, false, true>(t16, unc, priv)
+                    : sweep_fn<PC_METRIC_RPPI, false, false>(t16, unc, priv);
 }
 
 }  // namespace
@@ -760,7 +799,8 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, con
 {
     SweepArgs copy = a;
     void *args[] = {&copy};
-    const void *fn = sweep_ptr(metric, fp32, weighted, a.B.tbl_wide != 0, a.copies == PC_WAVE);
+    const void *fn = sweep_ptr(metric, fp32, weighted, a.B.tbl_wide != 0, a.copies == PC_WAVE,
+                               a.priv != 0);
     if (a.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            a.lds_bytes);
@@ -772,10 +812,10 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, con
 
 int sweep_waves() { return kWaves; }
 
-hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc,
+hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc, bool priv,
                            int lds_bytes, int *per_cu)
 {
-    const void *fn = sweep_ptr(metric, fp32, weighted, t16, unc);
+    const void *fn = sweep_ptr(metric, fp32, weighted, t16, unc, priv);
     if (lds_bytes > 64 * 1024) {
         hipError_t e =
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -786,21 +826,23 @@ hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool 
                                                         (size_t)lds_bytes);
 }
 
-hipError_t launch_wsq(hipStream_t s, int64_t n, const double *w, double *out)
+hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
+                      const double *w, double *out)
 {
-    int64_t g = (n + 255) / 256;
-    g = g < 1 ? 1 : (g > 1024 ? 1024 : g);
-    hipLaunchKernelGGL(k_wsq, dim3((unsigned)g), dim3(256), 0, s, n, w, out);
+    hipLaunchKernelGGL(k_wsq, dim3(64, (unsigned)ncat), dim3(256), 0, s, ncell, start, w, out);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t s, int32_t nbt, int autocorr, int e0_zero, int64_t n1,
-                           const unsigned long long *g_hist, const double *g_whist,
-                           const double *wsq, unsigned long long *out_counts, double *out_wsum)
+hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
+                           const pc_cat *cats, const unsigned long long *g_hist,
+                           const double *g_whist, const double *wsq,
+                           unsigned long long *out_counts, double *out_wsum)
 {
-    const int g = (nbt + 255) / 256;
-    hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, nbt, autocorr, e0_zero, n1, g_hist,
-                       g_whist, wsq, out_counts, out_wsum);
+    const int64_t total = (int64_t)ncat * nbt;
+    int64_t g = (total + 255) / 256;
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(256), 0, s, ncat, nbt, autocorr,
+                       e0_zero, cats, g_hist, g_whist, wsq, out_counts, out_wsum);
     return hipGetLastError();
 }
 
