@@ -138,6 +138,8 @@ def batch_bench(args):
         w_ref += ref_pairs_rppi(pts, L, 25.0, 40.0)
         cats.append(tuple(torch.from_numpy(np.ascontiguousarray(pts[:, k])).to(dev)
                           for k in range(3)))
+        if (c + 1) % 32 == 0:
+            print(f"generated {c + 1}/{len(sizes)} catalogues", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t
     ctx = pcm.PairCounter(0, stream=torch.cuda.current_stream(dev))
@@ -158,12 +160,14 @@ def batch_bench(args):
         tb, (cb, _) = timed(lambda: ctx.count_rppi_batch(cats, edges, 40.0, 40, L, prec,
                                                          options=opts), args.steps)
         st = ctx.stats()
+        print(f"{prec}: batched {tb * 1e3:.2f} ms", file=sys.stderr, flush=True)
         sopts = pcm.default_options(autotune=1)
 
         def seq():
             return np.stack([ctx.count_rppi(cc, None, edges, 40.0, 40, L, prec,
                                             options=sopts)[0] for cc in cats])
         ts, cs = timed(seq, max(1, args.steps // 5))
+        print(f"{prec}: sequential {ts * 1e3:.2f} ms", file=sys.stderr, flush=True)
         if ref is None:
             ref = cb
         if not (np.array_equal(cb, ref) and np.array_equal(cs, ref)):

@@ -234,18 +234,30 @@ __global__ void k_scan_apply(const int32_t *in, int64_t n, const int32_t *offs, 
 }
 
 // ---- scatter into per-cell contiguous structure-of-arrays ----------------
-__global__ void k_scatter(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
-                          const int32_t *cell_of, const int32_t *rank_of, const int32_t *start,
-                          float *X, float *Y, float *Z, double *xd, double *yd, double *zd,
-                          double *wd, int32_t *cell_sorted)
+// Counting-sort placement in two steps.  Writing every column of a point to
+// its sorted place would scatter eight small writes per point over the whole
+// output; instead only the 4-byte source index goes to the sorted place
+// (k_perm), and k_gather walks the sorted order, reads the point's columns
+// (random reads, no partial-line writes) and writes every output column
+// contiguously.
+__global__ void k_perm(int64_t ntot, const int32_t *cell_of, const int32_t *rank_of,
+                       const int32_t *start, int32_t *perm)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntot;
-         i += (int64_t)gridDim.x * blockDim.x) {
+         i += (int64_t)gridDim.x * blockDim.x)
+        perm[(int64_t)start[cell_of[i]] + rank_of[i]] = (int32_t)i;
+}
+
+__global__ void k_gather(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
+                         const int32_t *perm, const int32_t *cell_of, float *X, float *Y, float *Z,
+                         double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
+{
+    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < ntot;
+         d += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[d];
         const int ci = ncat == 1 ? 0 : find_cat(cats, ncat, i);
         const pc_cat &k = cats[ci];
         const int64_t j = i - k.off;
-        const int cell = cell_of[i];
-        const int64_t d = (int64_t)start[cell] + rank_of[i];
         const double cx = ld(k.x, k.f32, j), cy = ld(k.y, k.f32, j), cz = ld(k.z, k.f32, j);
         X[d] = (float)((cx - g.lo[0]) * g.fscale);
         Y[d] = (float)((cy - g.lo[1]) * g.fscale);
@@ -255,7 +267,7 @@ __global__ void k_scatter(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
         zd[d] = cz;
         if (wd)
             wd[d] = ld(k.w, k.wf32, j);
-        cell_sorted[d] = cell;
+        cell_sorted[d] = cell_of[i];
     }
 }
 
@@ -507,11 +519,13 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
 
 hipError_t launch_scatter(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
                           const pc_grid &g, const int32_t *cell_of, const int32_t *rank_of,
-                          const int32_t *start, float *X, float *Y, float *Z, double *xd,
-                          double *yd, double *zd, double *wd, int32_t *cell_sorted)
+                          const int32_t *start, int32_t *perm, float *X, float *Y, float *Z,
+                          double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
 {
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot, g,
-                       cell_of, rank_of, start, X, Y, Z, xd, yd, zd, wd, cell_sorted);
+    hipLaunchKernelGGL(k_perm, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, cell_of, rank_of,
+                       start, perm);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot, g,
+                       perm, cell_of, X, Y, Z, xd, yd, zd, wd, cell_sorted);
     return hipGetLastError();
 }
 

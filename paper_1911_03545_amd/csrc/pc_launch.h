@@ -59,10 +59,12 @@ hipError_t launch_cell_index(hipStream_t s, int ncat, const pc_cat *cats, int64_
 size_t scan_tmp_elems(int64_t n);
 hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *out,
                           int32_t *tmp);
+// place every point at start[cell] + rank: a permutation scatter of source
+// indices into `perm` (ntot int32), then a gather in sorted order
 hipError_t launch_scatter(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
                           const pc_grid &g, const int32_t *cell_of, const int32_t *rank_of,
-                          const int32_t *start, float *X, float *Y, float *Z, double *xd,
-                          double *yd, double *zd, double *wd, int32_t *cell_sorted);
+                          const int32_t *start, int32_t *perm, float *X, float *Y, float *Z,
+                          double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted);
 hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
                               int32_t *bcnt);
 hipError_t launch_block_emit(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
