@@ -719,7 +719,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.g_whist = weighted ? dptr<double>(c, B_WHIST) : nullptr;
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
     a.nbt = (int32_t)nbt;
-    a.slots = (int32_t)((nb + 2) * npi);
+    a.slots = (int32_t)((nb + 2) * hb.hdr.row_w);
     a.priv = priv ? 1 : 0;
     // replica stride: odd, so the lanes' copies of one slot spread over banks
     a.rep_stride = a.slots | 1;

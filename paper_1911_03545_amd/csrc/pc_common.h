@@ -108,6 +108,11 @@ struct pc_bins {
     float pi_tau;        // rppi: margin of the fractional part of |dz| * inv_dpi
     double E_top;        // binary64 cut: s64 < E_top
     double pimax;        // binary64 cut: pi64 < pimax
+    // histogram slot of (row, col) = row * row_w + col: row = rp bin + 1
+    // (0 and nb + 1 out of range), col = pi bin + col0; r: row_w 1, col0 0;
+    // rppi: row_w npi + 2, col0 1 (columns 0 and npi + 1 out of range)
+    int32_t row_w;
+    int32_t col0;
 };
 
 // Offsets (bytes) of the arrays packed after pc_bins in one device buffer.

@@ -218,8 +218,11 @@ static uint16_t cell_entry(int below, int inter, int which, bool wide)
 // Linear table of the float32 path: cell k holds the values s with
 // floor(s) == k, i.e. [k, k + 1); the last cell also takes every clamped
 // value above it and must lie above the top band.
+// out_zero: entries of cells wholly out of range (below the first band or
+// above the last) are 0 instead of 0 / nedges, so that in-range entries are
+// exactly the nonzero unflagged ones (rp/pi tables).
 static int build_linear_table(const float *lo, const float *hi, int nedges, int cells, bool wide,
-                              std::vector<uint16_t> &tbl)
+                              bool out_zero, std::vector<uint16_t> &tbl)
 {
     if (!(hi[nedges - 1] < (float)(cells - 1)))
         return CF_EINVAL;
@@ -254,6 +257,8 @@ static int build_linear_table(const float *lo, const float *hi, int nedges, int 
                 }
             }
         }
+        if (out_zero && inter == 0 && below == nedges)
+            below = 0;
         tbl[key] = cell_entry(below, inter, which, wide);
     }
     return CF_OK;
@@ -266,7 +271,8 @@ static int build_linear_table(const float *lo, const float *hi, int nedges, int 
 // of bands wholly below the cell (the histogram slot), flagged when one band
 // (entry = flag | edge) or several bands meet the cell.
 static int build_table(const float *lo, const float *hi, int nedges, float s_top, bool wide,
-                       uint32_t cap, std::vector<uint16_t> &tbl, int *shift, uint32_t *base_out)
+                       uint32_t cap, bool out_zero, std::vector<uint16_t> &tbl, int *shift,
+                       uint32_t *base_out)
 {
     const uint32_t top = fbits(std::max(s_top, 0.0f));
     // first band that is not the empty band of a zero edge
@@ -288,7 +294,7 @@ static int build_table(const float *lo, const float *hi, int nedges, float s_top
     // keys clamped in the sweep
     const uint32_t n = ((top - base) >> sh) + 2;
     tbl.assign(n, 0);
-    tbl[n - 1] = (uint16_t)nedges;
+    tbl[n - 1] = out_zero ? 0 : (uint16_t)nedges;
     // The band tops hi[] never decrease with k, so the bands wholly below a
     // cell are a prefix that only grows with the key; the cell meets band k
     // >= that prefix iff lo[k] <= c_hi, and the scan stops once every later
@@ -326,6 +332,8 @@ static int build_table(const float *lo, const float *hi, int nedges, float s_top
                 }
             }
         }
+        if (out_zero && inter == 0 && below == nedges)
+            below = 0;
         tbl[key] = cell_entry(below, inter, which, wide);
     }
     *shift = sh;
@@ -437,15 +445,15 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     int shift = 0;
     uint32_t base = 0;
     const bool wide = nb > PC_TBL8_MAX_BINS;
+    const bool rppi = metric == PC_METRIC_RPPI;
     if (fp32) {
-        rc = build_linear_table(lo.data(), hi.data(), ne, table_cells(nb, priv), wide, tbl);
+        rc = build_linear_table(lo.data(), hi.data(), ne, table_cells(nb, priv), wide, rppi, tbl);
         if (rc)
             return rc;
     } else {
-        build_table(lo.data(), hi.data(), ne, hi[nb], wide, (uint32_t)table_cells(nb, priv), tbl,
-                    &shift, &base);
+        build_table(lo.data(), hi.data(), ne, hi[nb], wide, (uint32_t)table_cells(nb, priv), rppi,
+                    tbl, &shift, &base);
     }
-
     pc_bins h;
     memset(&h, 0, sizeof(h));
     h.nb = nb;
@@ -478,6 +486,8 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     }
     h.E_top = E[nb];
     h.pimax = (metric == PC_METRIC_RPPI) ? pimax : 0.0;
+    h.row_w = rppi ? npi + 2 : 1;
+    h.col0 = rppi ? 1 : 0;
 
     pc_bins_layout L;
     size_t off = align8(sizeof(pc_bins));

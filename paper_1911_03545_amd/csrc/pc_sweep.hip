@@ -224,20 +224,39 @@ __device__ __forceinline__ int slow_slot_exact(double s, int e, lds_f64p E, int 
     return count_le(E, nedges, s);
 }
 
-// Exact histogram slot of a pair the float32 pass could not decide: the
-// binary64 separation of the definition from the binary64 copies of both
-// points (the second point is wave-uniform and comes through the scalar
-// cache), binned against the exact edges.  Returns the slot of bin + 1 (rppi:
-// (rp bin + 1) * npi + pi bin), or 0 when out of range.
+// Exact histogram row and column of a pair the float32 pass could not
+// decide: the binary64 separation of the definition from the binary64 copies
+// of both points (the second point is wave-uniform and comes through the
+// scalar cache), binned against the exact edges.  row = rp bin + 1 and col =
+// pi bin + col0, or both 0 when out of range.
 template <int M>
-__device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int i, int j,
-                                       unsigned dcode)
+__device__ __forceinline__ void exact_rowcol(const SweepArgs &a, const Lds &L, int i, int j,
+                                             unsigned dcode, int &row, int &col)
 {
     const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2;
     double s, pz;
     exact_sep<M>(a.x1[i], a.y1[i], a.z1[i], x2[j], y2[j], z2[j], dcode, a.L, &s, &pz);
     const int b = exact_bin<M>(s, pz, L.E, a.B.nb, L.q, a.B.npi, a.B.pimax);
-    return b < 0 ? 0 : b + a.B.npi;
+    if (b < 0) {
+        row = 0;
+        col = 0;
+    } else if (M == PC_METRIC_R) {
+        row = b + 1;
+        col = 0;
+    } else {
+        row = b / a.B.npi + 1;
+        col = b % a.B.npi + a.B.col0;
+    }
+}
+
+// Histogram slot of exact_rowcol (0, a catch-all, when out of range).
+template <int M>
+__device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int i, int j,
+                                       unsigned dcode)
+{
+    int row, col;
+    exact_rowcol<M>(a, L, i, j, dcode, row, col);
+    return row * a.B.row_w + col;
 }
 
 // Float32 pi bin of |dz|: t = |dz| * npi / pimax; the bin floor(t) is taken
@@ -351,10 +370,10 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
                     slot = exact_slot<M>(a, L, i, j + k, dcode);
                     rechecks++;
                 } else {
-                    slot = row * npi + (ps - 1);
+                    slot = row * a.B.row_w + ps;
                 }
             } else {
-                slot = slot * npi + kp;
+                slot = slot * a.B.row_w + kp + 1;
             }
         }
         lds_add(&hb[slot], 1u);
@@ -423,7 +442,7 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
             int kp = pi_fast(__double2float_rn(pz[k]), a.B.inv_dpi, a.B.pi_tau, npi);
             if (kp < 0)
                 kp = count_le(L.q, npi, pz[k]) - 1;
-            slot = slot * npi + kp;
+            slot = slot * a.B.row_w + kp + a.B.col0;
         }
         lds_add(&hb[slot], 1u);
         if (W)
@@ -531,18 +550,18 @@ __device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int 
 }
 
 // Merge histogram replicas into the global bins of catalogue `cat` and clear
-// them.  Output bin b = k * npi + p lives in slot (k + 1) * npi + p; rows 0
-// and nb + 1 are the out-of-range catch-alls and are only cleared.  Called
+// them.  Output bin b = k * npi + p lives in slot (k + 1) * row_w + p + col0;
+// every other slot is an out-of-range catch-all and is only cleared.  Called
 // by threads t = first, first + step, ...; slots are taken with atomic
 // exchanges, so other waves may keep adding to shared replicas meanwhile.
 __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int first, int step,
                                            bool W, unsigned cat)
 {
-    const int npi = a.B.npi;
+    const int npi = a.B.npi, rw = a.B.row_w, c0 = a.B.col0;
     unsigned long long *gh = a.g_hist + (size_t)cat * a.nbt;
     double *gw = W ? a.g_whist + (size_t)cat * a.nbt : nullptr;
     for (int b = first; b < a.nbt; b += step) {
-        const int slot = b + npi;
+        const int slot = (b / npi + 1) * rw + b % npi + c0;
         unsigned long long c = 0;
         double w = 0.0;
         for (int r = 0; r < a.copies; r++) {
@@ -555,14 +574,14 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         if (W && w != 0.0)
             atomicAdd(&gw[b], w);
     }
-    for (int t = first; t < a.copies * npi; t += step) {
-        const int r = t / npi, p = t % npi;
-        lds_take(&L.hist[r * a.rep_stride + p]);
-        lds_take(&L.hist[r * a.rep_stride + (a.B.nb + 1) * npi + p]);
-        if (W) {
-            lds_take(&L.whist[r * a.rep_stride + p]);
-            lds_take(&L.whist[r * a.rep_stride + (a.B.nb + 1) * npi + p]);
-        }
+    for (int t = first; t < a.copies * a.slots; t += step) {
+        const int r = t / a.slots, sl = t % a.slots;
+        const int row = sl / rw, col = sl % rw - c0;
+        if (row >= 1 && row <= a.B.nb && col >= 0 && col < npi)
+            continue;
+        lds_take(&L.hist[r * a.rep_stride + sl]);
+        if (W)
+            lds_take(&L.whist[r * a.rep_stride + sl]);
     }
 }
 
