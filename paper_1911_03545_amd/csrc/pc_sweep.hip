@@ -302,8 +302,14 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
             pz[k] = fabsf(dz);
             c[k] = (s[k] <= a.B.s_top) && (pz[k] <= a.B.pi_top);
         }
-        if (TRI)
+        if (TRI) {
             c[k] = c[k] && (j + k > i);
+            // pairs j <= i of the block's own triangle (the lane's own point
+            // among them, s = 0) go to the catch-all above every edge rather
+            // than to the crowded low cells, which would take the slow path
+            if (!(j + k > i))
+                s[k] = kmax;
+        }
         key[k] = tbl_key_linear(s[k], kmax);
     }
     // every lane reads (no exec-mask changes), so the CH reads stay in flight
@@ -332,12 +338,8 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
             }
         }
 #pragma unroll
-        for (int k = 0; k < CH; k++) {
-            int slot = e[k];
-            if (TRI && !(j + k > i))
-                slot = 0;
-            lds_add(&hb[slot], 1u);
-        }
+        for (int k = 0; k < CH; k++)
+            lds_add(&hb[e[k]], 1u);
         return;
     }
 #pragma unroll
