@@ -297,6 +297,23 @@ def main():
         fp64 = {"value": w_ref / (ms64 / 1e3) / 1e9, "ms_per_step": ms64,
                 "sweep_ms": ctx.stats()["t_sweep_ms"]}
 
+    # the same call replayed from a recorded HIP graph (repeated identical
+    # calls on the same device buffers; every kernel still runs)
+    gopts = pcm.default_options(use_graph=1)
+    cg, _ = ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
+    for _ in range(3):
+        ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        cg, _ = ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
+    torch.cuda.synchronize()
+    msg = (time.perf_counter() - t) * 1e3 / args.steps
+    if not np.array_equal(cg, counts):
+        raise SystemExit("graph replay and eager counts differ")
+    graph = {"ms_per_step": msg, "value": w_ref / (msg / 1e3) / 1e9,
+             "replayed": ctx.stats()["replayed"]}
+
     t_sweep = float(np.mean(sweep_ms)) / 1e3
     achieved = FLOPS_PER_PAIR * st["candidate_pairs"] / t_sweep / 1e12
     line = {
@@ -343,6 +360,7 @@ def main():
                                             "t_sweep_ms", "t_finalize_ms", "t_total_ms")},
         },
         "fp64_path": fp64,
+        "graph_replay": graph,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pts, w_ref)

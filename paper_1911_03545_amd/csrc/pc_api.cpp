@@ -27,7 +27,7 @@ struct DevBuf {
 
 enum BufId {
     B_IN1X, B_IN1Y, B_IN1Z, B_IN1W, B_IN2X, B_IN2Y, B_IN2Z, B_IN2W,
-    B_CNT, B_START1, B_START2, B_CELLOF, B_RANKOF, B_PERM,
+    B_CNT, B_START1, B_START2, B_CELLOF, B_RANKOF, B_PERM, B_REC,
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
@@ -336,6 +336,7 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
         (st = ensure(c, B_CELLOF, sizeof(int32_t) * (size_t)n)) ||
         (st = ensure(c, B_RANKOF, sizeof(int32_t) * (size_t)n)) ||
         (st = ensure(c, B_PERM, sizeof(int32_t) * (size_t)n)) ||
+        (st = ensure(c, B_REC, 32 * (size_t)n)) ||
         (st = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(ncells))) ||
         (st = ensure(c, X, sizeof(float) * (size_t)n)) ||
         (st = ensure(c, Y, sizeof(float) * (size_t)n)) ||
@@ -349,12 +350,14 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
         return st;
     HIPCHK(pc::launch_zero(c->stream, c->buf[B_CNT].p, sizeof(int32_t) * (size_t)ncells));
     HIPCHK(pc::launch_cell_index(c->stream, s.ncat, cats_dev, n, g, dptr<unsigned>(c, B_CNT),
-                                 dptr<int32_t>(c, B_CELLOF), dptr<int32_t>(c, B_RANKOF), flags));
+                                 dptr<int32_t>(c, B_CELLOF), dptr<int32_t>(c, B_RANKOF),
+                                 c->buf[B_REC].p, flags));
     HIPCHK(pc::scan_exclusive(c->stream, dptr<int32_t>(c, B_CNT), ncells, dptr<int32_t>(c, start),
                               dptr<int32_t>(c, B_SCANTMP)));
-    HIPCHK(pc::launch_scatter(c->stream, s.ncat, cats_dev, n, g, dptr<int32_t>(c, B_CELLOF),
-                              dptr<int32_t>(c, B_RANKOF), dptr<int32_t>(c, start),
-                              dptr<int32_t>(c, B_PERM), dptr<float>(c, X), dptr<float>(c, Y), dptr<float>(c, Z),
+    HIPCHK(pc::launch_scatter(c->stream, n, g, dptr<int32_t>(c, B_CELLOF),
+                              dptr<int32_t>(c, B_RANKOF), c->buf[B_REC].p,
+                              dptr<int32_t>(c, start), dptr<int32_t>(c, B_PERM),
+                              dptr<float>(c, X), dptr<float>(c, Y), dptr<float>(c, Z),
                               dptr<double>(c, XD), dptr<double>(c, YD), dptr<double>(c, ZD),
                               weighted ? dptr<double>(c, WD) : nullptr, dptr<int32_t>(c, CS)));
     return CF_OK;
@@ -602,11 +605,18 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, (cf_status)rc, "bin description failed");
     if (hb.buf.size() > bins_cap)
         return fail(c, CF_EINVAL, "bin description too large");
-    if ((st2 = ensure(c, B_BINS, hb.buf.size())))
+    if ((st2 = ensure(c, B_BINS, hb.lay.total)))
         return st2;
     memcpy(pin + p_bins, hb.buf.data(), hb.buf.size());
     HIPCHK(hipMemcpyAsync(c->buf[B_BINS].p, pin + p_bins, hb.buf.size(), hipMemcpyHostToDevice,
                           c->stream));
+    {
+        char *bd = static_cast<char *>(c->buf[B_BINS].p);
+        HIPCHK(pc::launch_build_table(c->stream, hb.hdr, nb + 1,
+                                      (const float *)(bd + hb.lay.lo),
+                                      (const float *)(bd + hb.lay.hi),
+                                      (const float *)(bd + hb.lay.lo_min), bd + hb.lay.tbl));
+    }
     record(c, timing, 2);
 
     // ---- work list ---------------------------------------------------------

@@ -113,9 +113,16 @@ struct pc_bins {
     // rppi: row_w npi + 2, col0 1 (columns 0 and npi + 1 out of range)
     int32_t row_w;
     int32_t col0;
+    // lookup-table construction (done on the device): linear cells [k, k+1)
+    // (float32 path) or float-bit cells (binary64 path); out_zero: cells
+    // wholly out of range hold 0; ordered: band tops never decrease
+    int32_t tbl_linear;
+    int32_t tbl_out_zero;
+    int32_t tbl_ordered;
+    int32_t pad2;
 };
 
 // Offsets (bytes) of the arrays packed after pc_bins in one device buffer.
 struct pc_bins_layout {
-    size_t lo, hi, E, plo, phi, q, tbl, total;
+    size_t lo, hi, lo_min, E, plo, phi, q, tbl, total;
 };

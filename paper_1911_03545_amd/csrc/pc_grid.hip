@@ -147,8 +147,10 @@ __device__ __forceinline__ int find_cat(const pc_cat *cats, int ncat, int64_t i)
 // Cell of every point of every catalogue of a side (catalogue c owns cells
 // c * ncell .. (c + 1) * ncell - 1) and its rank inside the cell; input
 // checks (finite, inside the periodic box, finite weights) raise flags.
+// It also writes each point as one 32-byte record (x, y, z, w) in input
+// order, so that the gather after the sort reads one line per point.
 __global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
-                             unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
+                             unsigned *cnt, int32_t *cell_of, int32_t *rank_of, double4 *rec,
                              unsigned *flags)
 {
     unsigned fl = 0;
@@ -166,10 +168,12 @@ __global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid
                 fl |= PC_FLAG_RANGE;
             ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
         }
-        if (k.w && !isfinite(ld(k.w, k.wf32, j)))
+        const double w = k.w ? ld(k.w, k.wf32, j) : 0.0;
+        if (!isfinite(w))
             fl |= PC_FLAG_WEIGHT;
         const int cell = (int)(ci * g.ncell) + (ia[0] * g.n[1] + ia[1]) * g.n[2] + ia[2];
         cell_of[i] = cell;
+        rec[i] = make_double4(c[0], c[1], c[2], w);
         rank_of[i] = (int32_t)atomicAdd(&cnt[cell], 1u);
     }
     if (fl)
@@ -248,25 +252,22 @@ __global__ void k_perm(int64_t ntot, const int32_t *cell_of, const int32_t *rank
         perm[(int64_t)start[cell_of[i]] + rank_of[i]] = (int32_t)i;
 }
 
-__global__ void k_gather(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
-                         const int32_t *perm, const int32_t *cell_of, float *X, float *Y, float *Z,
-                         double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
+__global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int32_t *cell_of,
+                         const double4 *rec, float *X, float *Y, float *Z, double *xd, double *yd,
+                         double *zd, double *wd, int32_t *cell_sorted)
 {
     for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < ntot;
          d += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = perm[d];
-        const int ci = ncat == 1 ? 0 : find_cat(cats, ncat, i);
-        const pc_cat &k = cats[ci];
-        const int64_t j = i - k.off;
-        const double cx = ld(k.x, k.f32, j), cy = ld(k.y, k.f32, j), cz = ld(k.z, k.f32, j);
-        X[d] = (float)((cx - g.lo[0]) * g.fscale);
-        Y[d] = (float)((cy - g.lo[1]) * g.fscale);
-        Z[d] = (float)((cz - g.lo[2]) * g.fscale);
-        xd[d] = cx;
-        yd[d] = cy;
-        zd[d] = cz;
+        const double4 r = rec[i];
+        X[d] = (float)((r.x - g.lo[0]) * g.fscale);
+        Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
+        Z[d] = (float)((r.z - g.lo[2]) * g.fscale);
+        xd[d] = r.x;
+        yd[d] = r.y;
+        zd[d] = r.z;
         if (wd)
-            wd[d] = ld(k.w, k.wf32, j);
+            wd[d] = r.w;
         cell_sorted[d] = cell_of[i];
     }
 }
@@ -440,6 +441,78 @@ __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const p
     }
 }
 
+// ---- lookup table of the decision bands -------------------------------------
+// One thread per table cell [c_lo, c_hi]: linear cells [k, k + 1) (the last
+// cell takes everything above) or float-bit cells of the binary64 path (the
+// extra last cell is "above every edge").  Entry = number of bands wholly
+// below the cell (the histogram row), flagged when one band (flag | edge) or
+// several bands meet the cell; with out_zero, cells wholly above every edge
+// hold 0 like those below.  Band tops hi[] never decrease when `ordered`; the
+// scan over meeting bands stops once every later band starts above the cell
+// (lo_min is the suffix minimum of lo).
+__global__ void k_build_table(pc_bins B, int nedges, const float *lo, const float *hi,
+                              const float *lo_min, void *tbl)
+{
+    const bool wide = B.tbl_wide != 0;
+    for (int key = blockIdx.x * blockDim.x + threadIdx.x; key < B.tbl_n;
+         key += gridDim.x * blockDim.x) {
+        unsigned e;
+        if (!B.tbl_linear && key == B.tbl_n - 1) {
+            e = B.tbl_out_zero ? 0u : (unsigned)nedges;
+        } else {
+            float c_lo, c_hi;
+            if (B.tbl_linear) {
+                c_lo = (float)key;
+                c_hi = key + 1 < B.tbl_n ? nextafterf((float)(key + 1), 0.0f) : INFINITY;
+            } else {
+                const unsigned cell0 = B.tbl_base + ((unsigned)key << B.tbl_shift);
+                const unsigned lo_b = key == 0 ? 0u : cell0;
+                const unsigned hi_b = cell0 + ((1u << B.tbl_shift) - 1u);
+                c_lo = __uint_as_float(lo_b);
+                c_hi = __uint_as_float(min(hi_b, 0x7f7fffffu));
+            }
+            int below = 0, inter = 0, which = -1;
+            if (B.tbl_ordered) {
+                int a = 0, b = nedges;   // first band with hi >= c_lo
+                while (a < b) {
+                    const int m = (a + b) >> 1;
+                    if (hi[m] < c_lo)
+                        a = m + 1;
+                    else
+                        b = m;
+                }
+                below = a;
+                for (int k = a; k < nedges && lo_min[k] <= c_hi; k++)
+                    if (lo[k] <= c_hi) {
+                        inter++;
+                        which = k;
+                    }
+            } else {
+                for (int k = 0; k < nedges; k++) {
+                    if (hi[k] < c_lo)
+                        below++;
+                    else if (lo[k] <= c_hi) {
+                        inter++;
+                        which = k;
+                    }
+                }
+            }
+            if (B.tbl_out_zero && inter == 0 && below == nedges)
+                below = 0;
+            if (inter == 0)
+                e = (unsigned)below;
+            else if (inter == 1 && which == below)
+                e = (unsigned)below | (wide ? PC_TBL_BAND : PC_TBL8_BAND);
+            else
+                e = wide ? PC_TBL_MULTI : PC_TBL8_MULTI;
+        }
+        if (wide)
+            static_cast<uint16_t *>(tbl)[key] = (uint16_t)e;
+        else
+            static_cast<uint8_t *>(tbl)[key] = (uint8_t)e;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes)
@@ -476,10 +549,10 @@ hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, do
 
 hipError_t launch_cell_index(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
                              const pc_grid &g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
-                             unsigned *flags)
+                             void *rec, unsigned *flags)
 {
     hipLaunchKernelGGL(k_cell_index, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot,
-                       g, cnt, cell_of, rank_of, flags);
+                       g, cnt, cell_of, rank_of, static_cast<double4 *>(rec), flags);
     return hipGetLastError();
 }
 
@@ -517,15 +590,16 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
-                          const pc_grid &g, const int32_t *cell_of, const int32_t *rank_of,
-                          const int32_t *start, int32_t *perm, float *X, float *Y, float *Z,
-                          double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
+hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *cell_of,
+                          const int32_t *rank_of, const void *rec, const int32_t *start,
+                          int32_t *perm, float *X, float *Y, float *Z, double *xd, double *yd,
+                          double *zd, double *wd, int32_t *cell_sorted)
 {
     hipLaunchKernelGGL(k_perm, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, cell_of, rank_of,
                        start, perm);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot, g,
-                       perm, cell_of, X, Y, Z, xd, yd, zd, wd, cell_sorted);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, g, perm,
+                       cell_of, static_cast<const double4 *>(rec), X, Y, Z, xd, yd, zd, wd,
+                       cell_sorted);
     return hipGetLastError();
 }
 
@@ -564,6 +638,14 @@ hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nbloc
     SegCtx c{g, start2, cell1_sorted, autocorr};
     hipLaunchKernelGGL(k_item_emit, dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
                        nblocks_dev, blocks, c, chunk, ioff, items, cap, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_table(hipStream_t s, const pc_bins &B, int nedges, const float *lo,
+                              const float *hi, const float *lo_min, void *tbl)
+{
+    hipLaunchKernelGGL(k_build_table, dim3(grid_for(B.tbl_n)), dim3(kThreads), 0, s, B, nedges,
+                       lo, hi, lo_min, tbl);
     return hipGetLastError();
 }
 

@@ -44,6 +44,9 @@ struct SweepArgs {
     int32_t lds_bytes;
 };
 
+// fill the lookup table of a bin description (B.tbl_n cells) on the device
+hipError_t launch_build_table(hipStream_t s, const pc_bins &B, int nedges, const float *lo,
+                              const float *hi, const float *lo_min, void *tbl);
 // zero `bytes` (a multiple of 4) of device memory with a kernel
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
 hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
@@ -51,9 +54,11 @@ hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *de
 hipError_t launch_minmax(hipStream_t s, int64_t n, const void *x, const void *y,
                          const void *z, int f32, double *part, int nparts, unsigned *flags);
 hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, double *out6);
+// cell and in-cell rank of every point of a side's catalogues, plus a
+// 32-byte (x, y, z, w) record per point in input order (rec: ntot records)
 hipError_t launch_cell_index(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
                              const pc_grid &g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
-                             unsigned *flags);
+                             void *rec, unsigned *flags);
 // exclusive scan of n int32 values into out[0..n] (out[n] = total); `tmp`
 // needs scan_tmp_elems(n) int32.
 size_t scan_tmp_elems(int64_t n);
@@ -61,10 +66,10 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
                           int32_t *tmp);
 // place every point at start[cell] + rank: a permutation scatter of source
 // indices into `perm` (ntot int32), then a gather in sorted order
-hipError_t launch_scatter(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
-                          const pc_grid &g, const int32_t *cell_of, const int32_t *rank_of,
-                          const int32_t *start, int32_t *perm, float *X, float *Y, float *Z,
-                          double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted);
+hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *cell_of,
+                          const int32_t *rank_of, const void *rec, const int32_t *start,
+                          int32_t *perm, float *X, float *Y, float *Z, double *xd, double *yd,
+                          double *zd, double *wd, int32_t *cell_sorted);
 hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
                               int32_t *bcnt);
 hipError_t launch_block_emit(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,

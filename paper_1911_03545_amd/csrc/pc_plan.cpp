@@ -203,76 +203,13 @@ static int table_cells(int nb, bool priv)
     return nb > PC_TBL8_MAX_BINS ? PC_TBL16_MAX : PC_TBL8_MAX;
 }
 
-// Entry of a table cell [c_lo, c_hi]: the number of bands wholly below the
-// cell (the histogram slot), flagged when one band (flag | edge) or several
-// bands meet the cell.
-static uint16_t cell_entry(int below, int inter, int which, bool wide)
-{
-    if (inter == 0)
-        return (uint16_t)below;
-    if (inter == 1 && which == below)
-        return (uint16_t)(wide ? ((uint32_t)below | PC_TBL_BAND) : ((uint32_t)below | PC_TBL8_BAND));
-    return (uint16_t)(wide ? PC_TBL_MULTI : PC_TBL8_MULTI);
-}
-
-// Linear table of the float32 path: cell k holds the values s with
-// floor(s) == k, i.e. [k, k + 1); the last cell also takes every clamped
-// value above it and must lie above the top band.
-// out_zero: entries of cells wholly out of range (below the first band or
-// above the last) are 0 instead of 0 / nedges, so that in-range entries are
-// exactly the nonzero unflagged ones (rp/pi tables).
-static int build_linear_table(const float *lo, const float *hi, int nedges, int cells, bool wide,
-                              bool out_zero, std::vector<uint16_t> &tbl)
-{
-    if (!(hi[nedges - 1] < (float)(cells - 1)))
-        return CF_EINVAL;
-    tbl.assign(cells, 0);
-    bool ordered = true;
-    for (int k = 1; k < nedges; k++)
-        ordered = ordered && hi[k] >= hi[k - 1];
-    std::vector<float> lo_min(nedges + 1, INFINITY);
-    for (int k = nedges - 1; k >= 0; k--)
-        lo_min[k] = std::min(lo[k], lo_min[k + 1]);
-    int prefix = 0;
-    for (int key = 0; key < cells; key++) {
-        const float c_lo = (float)key;
-        const float c_hi = key + 1 < cells ? std::nextafter((float)(key + 1), 0.0f) : INFINITY;
-        int below = 0, inter = 0, which = -1;
-        if (ordered) {
-            while (prefix < nedges && hi[prefix] < c_lo)
-                prefix++;
-            below = prefix;
-            for (int k = prefix; k < nedges && lo_min[k] <= c_hi; k++)
-                if (lo[k] <= c_hi) {
-                    inter++;
-                    which = k;
-                }
-        } else {
-            for (int k = 0; k < nedges; k++) {
-                if (hi[k] < c_lo)
-                    below++;
-                else if (lo[k] <= c_hi) {
-                    inter++;
-                    which = k;
-                }
-            }
-        }
-        if (out_zero && inter == 0 && below == nedges)
-            below = 0;
-        tbl[key] = cell_entry(below, inter, which, wide);
-    }
-    return CF_OK;
-}
-
-// Lookup table over the float32 bit pattern of s (monotone for s >= 0),
-// key = sat(bits(s) - base) >> sh.  The table starts one cell below the first
-// band that matters, so every value below it shares cell 0; `sh` is the
-// smallest shift that fits [base, s_top] into `cap` entries.  Entry = number
-// of bands wholly below the cell (the histogram slot), flagged when one band
-// (entry = flag | edge) or several bands meet the cell.
-static int build_table(const float *lo, const float *hi, int nedges, float s_top, bool wide,
-                       uint32_t cap, bool out_zero, std::vector<uint16_t> &tbl, int *shift,
-                       uint32_t *base_out)
+// Table geometry of the binary64 path: key = sat(bits(s) - base) >> sh over
+// float bit patterns (monotone for s >= 0).  The table starts one cell below
+// the first band that matters, so every value below it shares cell 0; `sh`
+// is the smallest shift that fits [base, s_top] into `cap` cells, plus one
+// extra last cell "above every edge" for clamped keys.
+static void log_table_geometry(const float *lo, const float *hi, int nedges, float s_top,
+                               uint32_t cap, uint32_t *n_out, int *shift, uint32_t *base_out)
 {
     const uint32_t top = fbits(std::max(s_top, 0.0f));
     // first band that is not the empty band of a zero edge
@@ -290,55 +227,9 @@ static int build_table(const float *lo, const float *hi, int nedges, float s_top
         if (((top - base) >> sh) + 2 <= cap)
             break;
     }
-    // one extra entry past the last cell: "above every edge", the target of
-    // keys clamped in the sweep
-    const uint32_t n = ((top - base) >> sh) + 2;
-    tbl.assign(n, 0);
-    tbl[n - 1] = out_zero ? 0 : (uint16_t)nedges;
-    // The band tops hi[] never decrease with k, so the bands wholly below a
-    // cell are a prefix that only grows with the key; the cell meets band k
-    // >= that prefix iff lo[k] <= c_hi, and the scan stops once every later
-    // band starts above the cell (suffix minimum of lo[]).  The general
-    // quadratic count is kept for band sets that break the ordering.
-    bool ordered = true;
-    for (int k = 1; k < nedges; k++)
-        ordered = ordered && hi[k] >= hi[k - 1];
-    std::vector<float> lo_min(nedges + 1, INFINITY);
-    for (int k = nedges - 1; k >= 0; k--)
-        lo_min[k] = std::min(lo[k], lo_min[k + 1]);
-    int prefix = 0;
-    for (uint32_t key = 0; key + 1 < n; key++) {
-        const uint32_t lo_b = key == 0 ? 0u : base + (key << sh);
-        const uint32_t hi_b = base + (key << sh) + ((1u << sh) - 1u);
-        const float c_lo = bits_f(lo_b);
-        const float c_hi = bits_f(std::min(hi_b, 0x7f7fffffu));
-        int below = 0, inter = 0, which = -1;
-        if (ordered) {
-            while (prefix < nedges && hi[prefix] < c_lo)
-                prefix++;
-            below = prefix;
-            for (int k = prefix; k < nedges && lo_min[k] <= c_hi; k++)
-                if (lo[k] <= c_hi) {
-                    inter++;
-                    which = k;
-                }
-        } else {
-            for (int k = 0; k < nedges; k++) {
-                if (hi[k] < c_lo)
-                    below++;
-                else if (lo[k] <= c_hi) {
-                    inter++;
-                    which = k;
-                }
-            }
-        }
-        if (out_zero && inter == 0 && below == nedges)
-            below = 0;
-        tbl[key] = cell_entry(below, inter, which, wide);
-    }
+    *n_out = ((top - base) >> sh) + 2;
     *shift = sh;
     *base_out = base;
-    return CF_OK;
 }
 
 static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
@@ -441,25 +332,35 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
             phi[p] = std::ldexp(phi[p], m);
         }
     }
-    std::vector<uint16_t> tbl;
     int shift = 0;
-    uint32_t base = 0;
+    uint32_t base = 0, tbl_n = 0;
     const bool wide = nb > PC_TBL8_MAX_BINS;
     const bool rppi = metric == PC_METRIC_RPPI;
     if (fp32) {
-        rc = build_linear_table(lo.data(), hi.data(), ne, table_cells(nb, priv), wide, rppi, tbl);
-        if (rc)
-            return rc;
+        tbl_n = (uint32_t)table_cells(nb, priv);
+        if (!(hi[nb] < (float)(tbl_n - 1)))
+            return CF_EINVAL;
     } else {
-        build_table(lo.data(), hi.data(), ne, hi[nb], wide, (uint32_t)table_cells(nb, priv), rppi,
-                    tbl, &shift, &base);
+        log_table_geometry(lo.data(), hi.data(), ne, hi[nb], (uint32_t)table_cells(nb, priv),
+                           &tbl_n, &shift, &base);
+    }
+    bool ordered = true;
+    for (int k = 1; k < ne; k++)
+        ordered = ordered && hi[k] >= hi[k - 1];
+    // suffix minimum of the band bottoms (the table kernel stops its scan
+    // once every later band starts above the cell)
+    std::vector<float> lo_min(ne);
+    float m_run = INFINITY;
+    for (int k = ne - 1; k >= 0; k--) {
+        m_run = std::min(m_run, lo[k]);
+        lo_min[k] = m_run;
     }
     pc_bins h;
     memset(&h, 0, sizeof(h));
     h.nb = nb;
     h.npi = npi;
     h.tbl_shift = shift;
-    h.tbl_n = (int32_t)tbl.size();
+    h.tbl_n = (int32_t)tbl_n;
     h.tbl_wide = wide ? 1 : 0;
     h.tbl_base = base;
     h.e0_zero = (E[0] == 0.0) ? 1 : 0;
@@ -488,36 +389,38 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     h.pimax = (metric == PC_METRIC_RPPI) ? pimax : 0.0;
     h.row_w = rppi ? npi + 2 : 1;
     h.col0 = rppi ? 1 : 0;
+    h.tbl_linear = fp32 ? 1 : 0;
+    h.tbl_out_zero = rppi ? 1 : 0;
+    h.tbl_ordered = ordered ? 1 : 0;
 
     pc_bins_layout L;
     size_t off = align8(sizeof(pc_bins));
     L.lo = off;  off = align8(off + sizeof(float) * ne);
     L.hi = off;  off = align8(off + sizeof(float) * ne);
+    L.lo_min = off; off = align8(off + sizeof(float) * ne);
     L.E = off;   off = align8(off + sizeof(double) * ne);
     L.plo = off; off = align8(off + sizeof(float) * nq);
     L.phi = off; off = align8(off + sizeof(float) * nq);
     L.q = off;   off = align8(off + sizeof(double) * nq);
     const size_t esz = wide ? sizeof(uint16_t) : sizeof(uint8_t);
-    L.tbl = off; off = align8(off + esz * tbl.size());
+    L.tbl = off; off = align8(off + esz * tbl_n);
     L.total = off;
 
     out->hdr = h;
     out->lay = L;
-    out->buf.assign(L.total, 0);
+    // the table region is filled on the device (launch_build_table); only
+    // the header and band arrays travel
+    out->upload = L.tbl;
+    out->buf.assign(L.tbl, 0);
     char *b = out->buf.data();
     memcpy(b, &h, sizeof(h));
     memcpy(b + L.lo, lo.data(), sizeof(float) * ne);
     memcpy(b + L.hi, hi.data(), sizeof(float) * ne);
+    memcpy(b + L.lo_min, lo_min.data(), sizeof(float) * ne);
     memcpy(b + L.E, E.data(), sizeof(double) * ne);
     memcpy(b + L.plo, plo.data(), sizeof(float) * nq);
     memcpy(b + L.phi, phi.data(), sizeof(float) * nq);
     memcpy(b + L.q, q.data(), sizeof(double) * nq);
-    if (wide) {
-        memcpy(b + L.tbl, tbl.data(), sizeof(uint16_t) * tbl.size());
-    } else {
-        for (size_t k = 0; k < tbl.size(); k++)
-            b[L.tbl + k] = (char)(uint8_t)tbl[k];
-    }
     out->nq = nq;
     out->ne = ne;
     return CF_OK;

@@ -11,7 +11,8 @@ namespace pc {
 struct HostBins {
     pc_bins hdr;
     pc_bins_layout lay;
-    std::vector<char> buf;   // pc_bins followed by its arrays, ready to upload
+    std::vector<char> buf;   // pc_bins and its band arrays, ready to upload
+    size_t upload = 0;       // bytes of buf; the table (lay.tbl ..) is built on the device
     int ne = 0;              // r / rp edges
     int nq = 0;              // pi edges (1 when unused)
 };
