@@ -588,6 +588,20 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, priv, &fscale_log2)))
         return fail(c, (cf_status)rc, "float32 scaling failed");
     g.fscale = std::ldexp(1.0, fscale_log2);
+    // float32 rp/pi path: z as fixed point with one pi bin = 2^k quanta, k
+    // as large as keeps every biased value (and the periodic offset) below
+    // 2^31; skipped when a bin would get fewer than 2^4 quanta
+    if (fp32 && metric == PC_METRIC_RPPI) {
+        const double dpi = pimax / (double)npi;
+        const double span = periodic ? boxsize : g.extent[2];
+        int k = 24;
+        while (k >= 4 && std::ldexp(span / dpi, k) > 0x1p29)
+            k--;
+        if (k >= 4 && span > 0.0) {
+            g.zq_shift = k;
+            g.zq_inv = std::ldexp(1.0, k) / dpi;
+        }
+    }
     record(c, timing, 1);
 
     // ---- grid ------------------------------------------------------------
@@ -603,6 +617,11 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     rc = pc::build_bins(metric, fp32, lin.data(), nb, pimax, npi, scale, fscale_log2, priv, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
+    if (g.zq_shift > 0) {
+        hb.hdr.zq_shift = g.zq_shift;
+        hb.hdr.zq_L = periodic ? (uint32_t)llrint(boxsize * g.zq_inv) : 0u;
+        memcpy(hb.buf.data(), &hb.hdr, sizeof(hb.hdr));
+    }
     if (hb.buf.size() > bins_cap)
         return fail(c, CF_EINVAL, "bin description too large");
     if ((st2 = ensure(c, B_BINS, hb.lay.total)))

@@ -54,10 +54,13 @@ struct pc_grid {
     int32_t n[3];
     int32_t zreach;
     int32_t periodic;
-    int32_t pad;
+    int32_t zq_shift;    // > 0: float32 rp/pi path stores z as fixed point (below)
     double boxsize;
     int64_t ncell;
     double fscale;       // power of two applied to the float32 coordinates
+    // fixed-point z of the float32 rp/pi path: Zq = round((z - lo_z) * zq_inv)
+    // + 2^30 as uint32 bits, one pi bin = 2^zq_shift quanta
+    double zq_inv;
 };
 
 // A block: up to 64 consecutive sorted points of one column (one per lane).
@@ -119,8 +122,15 @@ struct pc_bins {
     int32_t tbl_linear;
     int32_t tbl_out_zero;
     int32_t tbl_ordered;
-    int32_t pad2;
+    // rp/pi float32 path with fixed-point z (zq_shift > 0): pi bin =
+    // |dq| >> zq_shift, undecided within PC_ZQ_MARGIN quanta of a bin edge;
+    // zq_L is the periodic length in quanta (the per-item z offset)
+    int32_t zq_shift;
+    uint32_t zq_L;
+    int32_t pad3;
 };
+#define PC_ZQ_MARGIN 2
+#define PC_ZQ_BIAS 0x40000000u
 
 // Offsets (bytes) of the arrays packed after pc_bins in one device buffer.
 struct pc_bins_layout {

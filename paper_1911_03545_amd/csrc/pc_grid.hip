@@ -262,7 +262,10 @@ __global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int
         const double4 r = rec[i];
         X[d] = (float)((r.x - g.lo[0]) * g.fscale);
         Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
-        Z[d] = (float)((r.z - g.lo[2]) * g.fscale);
+        if (g.zq_shift > 0)
+            Z[d] = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
+        else
+            Z[d] = (float)((r.z - g.lo[2]) * g.fscale);
         xd[d] = r.x;
         yd[d] = r.y;
         zd[d] = r.z;

@@ -72,6 +72,7 @@ int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
 {
     memset(g, 0, sizeof(*g));
     g->fscale = 1.0;
+    g->zq_inv = 0.0;
     if (!(reach_xy > 0.0) || !(reach_z > 0.0) || !isfinite(reach_xy) ||
         !isfinite(reach_z))
         return CF_EINVAL;

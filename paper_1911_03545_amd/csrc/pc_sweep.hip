@@ -279,12 +279,14 @@ __device__ __forceinline__ int pi_fast(float pz, float inv_dpi, float tau, int n
 // UNC: every lane adds to its own histogram replica (out-of-range values land
 // in the catch-all slots), which needs no candidate branch; used for the
 // unweighted 1-D statistics.
-template <int M, bool W, bool TRI, bool T16, bool UNC, int CH>
+// MASK: the item's last, partial chunk; pairs k >= rem are padding (their
+// loads repeat the item's last point) and are sent out of range.
+template <int M, bool W, bool TRI, bool T16, bool UNC, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                           lds_f64wp whb, float ax, float ay, float az,
                                           double wi, int i, const float *xs, const float *ys,
                                           const float *zs, const double *ws, int j,
-                                          unsigned dcode, unsigned &rechecks)
+                                          unsigned dcode, unsigned &rechecks, int rem = CH)
 {
     float s[CH], pz[CH];
     bool c[CH];
@@ -309,6 +311,10 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
             // than to the crowded low cells, which would take the slow path
             if (!(j + k > i))
                 s[k] = kmax;
+        }
+        if (MASK && k >= rem) {
+            c[k] = false;
+            s[k] = kmax;
         }
         key[k] = tbl_key_linear(s[k], kmax);
     }
@@ -385,12 +391,12 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
 }
 
 // ---- binary64 chunk ------------------------------------------------------
-template <int M, bool W, bool TRI, bool OFS, bool T16, bool UNC, int CH>
+template <int M, bool W, bool TRI, bool OFS, bool T16, bool UNC, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                           lds_f64wp whb, double xi, double yi, double zi,
                                           double Dx, double Dy, double Dz, double wi, int i,
                                           const double *xs, const double *ys, const double *zs,
-                                          const double *ws, int j)
+                                          const double *ws, int j, int rem = CH)
 {
     double s[CH], pz[CH];
     bool c[CH];
@@ -414,6 +420,10 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
         }
         if (TRI)
             c[k] = c[k] && (j + k > i);
+        if (MASK && k >= rem) {
+            c[k] = false;
+            s[k] = 1.0e300;
+        }
         key[k] = tbl_key(__double2float_rn(s[k]), a.B.tbl_base, a.B.tbl_shift,
                          (unsigned)a.B.tbl_n - 1u);
     }
@@ -452,6 +462,89 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
     }
 }
 
+// ---- float32 rp/pi chunk with fixed-point z ---------------------------------
+// z is stored as fixed point with one pi bin = 2^sh quanta, so the pi bin of a
+// pair is the integer |dq| >> sh, exact except within PC_ZQ_MARGIN quanta of a
+// bin edge (quantisation and the rounding of the periodic length stay below
+// 1.5 quanta).  rp comes from the float32 table (0 for cells wholly out of
+// range).  Pairs on a flagged rp cell or near a pi edge are settled against
+// the float32 rp bands and, when still undecided, in binary64.
+template <bool W, bool TRI, bool T16, int CH, bool MASK = false>
+__device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &L, lds_u32p hb,
+                                                 lds_f64wp whb, float ax, float ay,
+                                                 unsigned azq, double wi, int i,
+                                                 const float *xs, const float *ys,
+                                                 const float *zs, const double *ws, int j,
+                                                 unsigned dcode, unsigned &rechecks,
+                                                 int rem = CH)
+{
+    const float kmax = (float)(a.B.tbl_n - 1);
+    const unsigned kmaxb = __float_as_uint(kmax);
+    const int sh = a.B.zq_shift;
+    const unsigned mask = (1u << sh) - 1u;
+    const unsigned npi = (unsigned)a.B.npi;
+    float s[CH];
+    unsigned kp[CH], dq[CH], key[CH];
+    int er[CH], fl[CH];
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+        const float dx = ax - xs[k], dy = ay - ys[k];
+        s[k] = fmaf(dy, dy, dx * dx);
+        const int d = (int)(azq - __float_as_uint(zs[k]));
+        unsigned q = (unsigned)max(d, -d);
+        // the block's own triangle (j <= i) and the padding of a partial
+        // chunk: out of range in rp, mid-bin in pi (never undecided)
+        if ((TRI && !(j + k > i)) || (MASK && k >= rem)) {
+            s[k] = kmax;
+            q = 1u << (sh - 1);
+        }
+        dq[k] = q;
+        kp[k] = q >> sh;
+        // s >= 0, so the bit patterns order like the values (no NaN here)
+        key[k] = (unsigned)__uint_as_float(min(__float_as_uint(s[k]), kmaxb));
+        fl[k] = (int)((q + PC_ZQ_MARGIN) & mask) - 2 * PC_ZQ_MARGIN;   // < 0: near an edge
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++)
+        er[k] = tbl_entry<T16>(L, key[k]);
+    int flag = 0;
+#pragma unroll
+    for (int k = 0; k < CH; k++)
+        flag |= (T16 ? ((er[k] << 16) | (er[k] << 17)) : er[k]) | fl[k];
+    const int nb = a.B.nb;
+    if (flag < 0) {
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const bool sr = is_slow<T16>(er[k]);
+            const bool sp = fl[k] < 0;
+            if (sr || sp) {
+                int row = er[k];
+                if (sr) {
+                    row = slow_slot<T16>(s[k], er[k], L.lo, L.hi, nb + 1);
+                    if (row == nb + 1)
+                        row = 0;
+                }
+                if (row != 0 && (row < 0 || (sp && dq[k] >= 2u * PC_ZQ_MARGIN))) {
+                    int col;
+                    exact_rowcol<PC_METRIC_RPPI>(a, L, i, j + k, dcode, row, col);
+                    rechecks++;
+                    kp[k] = col > 0 ? (unsigned)(col - 1) : npi;
+                }
+                er[k] = row;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; k++) {
+        if ((er[k] > 0) & (kp[k] < npi)) {
+            const int slot = er[k] * a.B.row_w + (int)kp[k] + 1;
+            lds_add(&hb[slot], 1u);
+            if (W)
+                lds_add(&whb[slot], wi * ws[k]);
+        }
+    }
+}
+
 // ---- item loops ----------------------------------------------------------
 template <int M, bool W, bool TRI, bool T16, bool UNC>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
@@ -474,6 +567,40 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     const kf64p w2 = (kf64p)a.w2;
     constexpr int CH = W ? 4 : 8;
     int j = j0;
+    if (M == PC_METRIC_RPPI && a.B.zq_shift > 0) {
+        // z in fixed point: the periodic z offset is a whole number of quanta
+        const unsigned Dq = cz == PC_D_PLUS ? a.B.zq_L : (cz == PC_D_MINUS ? 0u - a.B.zq_L : 0u);
+        const unsigned azq = __float_as_uint(a.Z1[i]) + Dq;
+        for (; j + CH <= j1; j += CH) {
+            float xs[CH], ys[CH], zs[CH];
+            double ws[CH];
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                xs[k] = X2[j + k];
+                ys[k] = Y2[j + k];
+                zs[k] = Z2[j + k];
+                ws[k] = W ? w2[j + k] : 0.0;
+            }
+            chunk_f32_rppi_q<W, TRI, T16, CH>(a, L, hb, whb, ax, ay, azq, wi, i, xs, ys, zs, ws,
+                                              j, dcode, rechecks);
+        }
+        if (j < j1) {
+            const int rem = j1 - j;
+            float xs[CH], ys[CH], zs[CH];
+            double ws[CH];
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                const int jk = j + min(k, rem - 1);
+                xs[k] = X2[jk];
+                ys[k] = Y2[jk];
+                zs[k] = Z2[jk];
+                ws[k] = W ? w2[jk] : 0.0;
+            }
+            chunk_f32_rppi_q<W, TRI, T16, CH, true>(a, L, hb, whb, ax, ay, azq, wi, i, xs, ys,
+                                                    zs, ws, j, dcode, rechecks, rem);
+        }
+        return;
+    }
     for (; j + CH <= j1; j += CH) {
         float xs[CH], ys[CH], zs[CH];
         double ws[CH];
@@ -487,11 +614,21 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
         chunk_f32<M, W, TRI, T16, UNC, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs, ws, j,
                                            dcode, rechecks);
     }
-    for (; j < j1; j++) {
-        const float x1 = X2[j], y1 = Y2[j], z1 = Z2[j];
-        const double w1 = W ? w2[j] : 0.0;
-        chunk_f32<M, W, TRI, T16, UNC, 1>(a, L, hb, whb, ax, ay, az, wi, i, &x1, &y1, &z1, &w1,
-                                          j, dcode, rechecks);
+    if (j < j1) {
+        // the partial last chunk, padded with the item's last point
+        const int rem = j1 - j;
+        float xs[CH], ys[CH], zs[CH];
+        double ws[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const int jk = j + min(k, rem - 1);
+            xs[k] = X2[jk];
+            ys[k] = Y2[jk];
+            zs[k] = Z2[jk];
+            ws[k] = W ? w2[jk] : 0.0;
+        }
+        chunk_f32<M, W, TRI, T16, UNC, CH, true>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs,
+                                                 ws, j, dcode, rechecks, rem);
     }
 }
 
@@ -521,11 +658,20 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
         chunk_f64<M, W, TRI, OFS, T16, UNC, CH>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi, i, xs,
                                                 ys, zs, ws, j);
     }
-    for (; j < j1; j++) {
-        const double x1 = x2[j], y1 = y2[j], z1 = z2[j];
-        const double w1 = W ? w2[j] : 0.0;
-        chunk_f64<M, W, TRI, OFS, T16, UNC, 1>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi, i, &x1,
-                                               &y1, &z1, &w1, j);
+    if (j < j1) {
+        // the partial last chunk, padded with the item's last point
+        const int rem = j1 - j;
+        double xs[CH], ys[CH], zs[CH], ws[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const int jk = j + min(k, rem - 1);
+            xs[k] = x2[jk];
+            ys[k] = y2[jk];
+            zs[k] = z2[jk];
+            ws[k] = W ? w2[jk] : 0.0;
+        }
+        chunk_f64<M, W, TRI, OFS, T16, UNC, CH, true>(a, L, hb, whb, xi, yi, zi, Dx, Dy, Dz, wi,
+                                                      i, xs, ys, zs, ws, j, rem);
     }
 }
 
