@@ -13,10 +13,9 @@
 #define PC_TBL8_MAX_BINS 125
 // lookup-table bytes of the private-histogram (batched) sweep
 #define PC_TBL_PRIV_BYTES 16384
-// The sweep's work items are dealt to PC_STREAMS interleaved streams (item
-// s + PC_STREAMS * t belongs to stream s), each with its own counter
-// PC_STREAM_STRIDE ints apart, so that item fetches spread over many
-// addresses instead of serialising on one.
+// The sweep's work items are dealt to PC_STREAMS streams (contiguous item
+// ranges), each with its own counter PC_STREAM_STRIDE ints apart, so that
+// item fetches spread over many addresses instead of serialising on one.
 #define PC_STREAMS 64
 #define PC_STREAM_STRIDE 64
 #define PC_MAX_EDGES 1025      // r / rp / theta edges

@@ -676,13 +676,16 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
 }
 
 // Take the next work item for this wave from stream s, moving on to the
-// following streams once it is exhausted.  Returns n_items when every stream
-// is exhausted.  Lane 0 reads the counter first and only increments it while
-// items remain, so exhausted streams cost one load each.
+// following streams once it is exhausted.  Stream s owns the contiguous
+// items [s n / S, (s + 1) n / S), so a wave's consecutive items are
+// neighbours (same catalogue, nearby cells).  Returns n_items when every
+// stream is exhausted.  Lane 0 reads the counter first and only increments
+// it while items remain, so exhausted streams cost one load each.
 __device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int &s)
 {
     for (int tries = 0; tries < PC_STREAMS; tries++) {
-        const int len = (n_items - s + PC_STREAMS - 1) / PC_STREAMS;
+        const int first = (int)(((long long)n_items * s) / PC_STREAMS);
+        const int len = (int)(((long long)n_items * (s + 1)) / PC_STREAMS) - first;
         int v = len;
         if (lane == 0) {
             int *c = ctrs + s * PC_STREAM_STRIDE;
@@ -691,7 +694,7 @@ __device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int 
         }
         v = __builtin_amdgcn_readfirstlane(v);
         if (v < len)
-            return s + v * PC_STREAMS;
+            return first + v;
         s = (s + 1) & (PC_STREAMS - 1);
     }
     return n_items;
