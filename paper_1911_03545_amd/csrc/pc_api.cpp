@@ -581,27 +581,30 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     double scale = periodic ? boxsize : 0.0;
     for (int a = 0; a < 3; a++)
         scale = std::max(scale, g.extent[a]);
-    const bool fp32 = prec == CF_PREC_FP32_RECHECK;
-    // batches: private per-wave histograms, flushed per catalogue
-    const bool priv = ncat > 1;
-    int fscale_log2 = 0;
-    if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, priv, &fscale_log2)))
-        return fail(c, (cf_status)rc, "float32 scaling failed");
-    g.fscale = std::ldexp(1.0, fscale_log2);
+    bool fp32 = prec == CF_PREC_FP32_RECHECK;
     // float32 rp/pi path: z as fixed point with one pi bin = 2^k quanta, k
     // as large as keeps every biased value (and the periodic offset) below
-    // 2^31; skipped when a bin would get fewer than 2^4 quanta
+    // 2^31.  When a bin would get fewer than 2^4 quanta the call sweeps in
+    // binary64 instead, which gives the same counts.
     if (fp32 && metric == PC_METRIC_RPPI) {
         const double dpi = pimax / (double)npi;
         const double span = periodic ? boxsize : g.extent[2];
         int k = 24;
         while (k >= 4 && std::ldexp(span / dpi, k) > 0x1p29)
             k--;
-        if (k >= 4 && span > 0.0) {
+        if (k >= 4) {
             g.zq_shift = k;
             g.zq_inv = std::ldexp(1.0, k) / dpi;
+        } else {
+            fp32 = false;
         }
     }
+    // batches: private per-wave histograms, flushed per catalogue
+    const bool priv = ncat > 1;
+    int fscale_log2 = 0;
+    if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, priv, &fscale_log2)))
+        return fail(c, (cf_status)rc, "float32 scaling failed");
+    g.fscale = std::ldexp(1.0, fscale_log2);
     record(c, timing, 1);
 
     // ---- grid ------------------------------------------------------------

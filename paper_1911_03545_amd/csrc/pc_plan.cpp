@@ -369,18 +369,13 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     h.pi_top = (metric == PC_METRIC_RPPI) ? phi[npi] : 0.0f;
     h.inv_dpi = (metric == PC_METRIC_RPPI) ? std::ldexp((float)((double)npi / pimax), -m) : 0.0f;
     h.fscale_log2 = m;
-    if (metric == PC_METRIC_RPPI) {
-        // error of the float32 |dz| (float32 pass) or of rounding the binary64
-        // |dz| to float32 (binary64 pass), in units of the pi bin width, plus
-        // the float32 product and the binary64 edges' offset from p * dpi
+    if (metric == PC_METRIC_RPPI && !fp32) {
+        // (the float32 pass bins pi in fixed point and needs no margin)
+        // error of rounding the binary64 |dz| to float32, in units of the pi
+        // bin width, plus the float32 product and the binary64 edges' offset
+        // from p * dpi
         const double dpi = pimax / (double)npi;
-        double dz_err;
-        if (fp32) {
-            const double eps_a = 6.0 * kU32 * coord_scale;
-            dz_err = eps_a * (1.0 + kU32) + kU32 * (pimax + eps_a) + 2.0 * kU64 * coord_scale;
-        } else {
-            dz_err = kU32 * pimax;
-        }
+        const double dz_err = kU32 * pimax;
         const double tau = kSafety * (dz_err / dpi + 3.0 * kU32 * npi + 4.0 * kU64 * npi) + 0x1p-22;
         if (!(tau < 0.25))
             return CF_EINVAL;

@@ -259,19 +259,6 @@ __device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int 
     return row * a.B.row_w + col;
 }
 
-// Float32 pi bin of |dz|: t = |dz| * npi / pimax; the bin floor(t) is taken
-// only when the fractional part of t keeps clear of both integers by the
-// margin tau (covering the error of |dz|, of the product and the offset of
-// the binary64 edges q_p from p * pimax / npi).  Returns -1 otherwise.
-__device__ __forceinline__ int pi_fast(float pz, float inv_dpi, float tau, int npi)
-{
-    const float t = pz * inv_dpi;
-    const float fl = floorf(t);
-    const float fr = t - fl;
-    const int k = (int)fl;
-    return (fr > tau && fr < 1.0f - tau && k < npi) ? k : -1;
-}
-
 // ---- float32 chunk: CH pairs sharing lane i ------------------------------
 // Three phases so that the CH table reads are in flight together: (1)
 // separations, candidate masks and table keys, (2) table reads, (3) slot
@@ -288,7 +275,8 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
                                           const float *zs, const double *ws, int j,
                                           unsigned dcode, unsigned &rechecks, int rem = CH)
 {
-    float s[CH], pz[CH];
+    static_assert(M == PC_METRIC_R, "float32 rp/pi pairs take the fixed-point chunk");
+    float s[CH];
     bool c[CH];
     unsigned key[CH];
     int e[CH];
@@ -296,14 +284,8 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
 #pragma unroll
     for (int k = 0; k < CH; k++) {
         const float dx = ax - xs[k], dy = ay - ys[k], dz = az - zs[k];
-        if (M == PC_METRIC_R) {
-            s[k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            c[k] = s[k] <= a.B.s_top;
-        } else {
-            s[k] = fmaf(dy, dy, dx * dx);
-            pz[k] = fabsf(dz);
-            c[k] = (s[k] <= a.B.s_top) && (pz[k] <= a.B.pi_top);
-        }
+        s[k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        c[k] = s[k] <= a.B.s_top;
         if (TRI) {
             c[k] = c[k] && (j + k > i);
             // pairs j <= i of the block's own triangle (the lane's own point
@@ -353,41 +335,31 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         if (!c[k])
             continue;
         int slot = e[k];
-        if (M == PC_METRIC_R) {
-            if (is_slow<T16>(e[k])) {
-                slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
-                if (slot < 0) {
-                    slot = exact_slot<M>(a, L, i, j + k, dcode);
-                    rechecks++;
-                }
-            }
-        } else {
-            const int npi = a.B.npi;
-            int kp = pi_fast(pz[k], a.B.inv_dpi, a.B.pi_tau, npi);
-            if (is_slow<T16>(e[k]) || kp < 0) {
-                int row = slot;
-                if (is_slow<T16>(e[k]))
-                    row = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
-                int ps = kp + 1;
-                if (kp < 0)
-                    ps = band_scan(pz[k], L.lo + a.B.nb + 1, L.hi + a.B.nb + 1, npi + 1);
-                // row / ps: bands below (bin + 1), or -1 when inside a band
-                if (row == 0 || row == a.B.nb + 1 || ps == 0 || ps == npi + 1) {
-                    slot = 0;   // definitely out of range
-                } else if (row < 0 || ps < 0) {
-                    slot = exact_slot<M>(a, L, i, j + k, dcode);
-                    rechecks++;
-                } else {
-                    slot = row * a.B.row_w + ps;
-                }
-            } else {
-                slot = slot * a.B.row_w + kp + 1;
+        if (is_slow<T16>(e[k])) {
+            slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
+            if (slot < 0) {
+                slot = exact_slot<M>(a, L, i, j + k, dcode);
+                rechecks++;
             }
         }
         lds_add(&hb[slot], 1u);
         if (W)
             lds_add(&whb[slot], wi * ws[k]);
     }
+}
+
+// Fast pi bin of |dz| for the binary64 chunk: t = |dz| * npi / pimax in
+// float32; the bin floor(t) is taken only when the fractional part of t keeps
+// clear of both integers by the margin tau (covering the rounding of |dz| to
+// float32, of the product and the offset of the binary64 edges q_p from
+// p * pimax / npi).  Returns -1 otherwise.
+__device__ __forceinline__ int pi_fast(float pz, float inv_dpi, float tau, int npi)
+{
+    const float t = pz * inv_dpi;
+    const float fl = floorf(t);
+    const float fr = t - fl;
+    const int k = (int)fl;
+    return (fr > tau && fr < 1.0f - tau && k < npi) ? k : -1;
 }
 
 // ---- binary64 chunk ------------------------------------------------------
@@ -469,6 +441,15 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
 // 1.5 quanta).  rp comes from the float32 table (0 for cells wholly out of
 // range).  Pairs on a flagged rp cell or near a pi edge are settled against
 // the float32 rp bands and, when still undecided, in binary64.
+//
+// The chunk works with u = |dq| + PC_ZQ_MARGIN (one v_sad_u32): a pair is
+// near a pi edge iff (u mod 2^sh) < 2 * PC_ZQ_MARGIN, and otherwise u >> sh
+// equals |dq| >> sh, since subtracting the margin then stays inside the bin.
+__device__ __forceinline__ unsigned absdiff_plus(unsigned a, unsigned b, unsigned c)
+{
+    return (max(a, b) - min(a, b)) + c;
+}
+
 template <bool W, bool TRI, bool T16, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                                  lds_f64wp whb, float ax, float ay,
@@ -484,25 +465,24 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
     const unsigned mask = (1u << sh) - 1u;
     const unsigned npi = (unsigned)a.B.npi;
     float s[CH];
-    unsigned kp[CH], dq[CH], key[CH];
-    int er[CH], fl[CH];
+    unsigned u[CH], key[CH], near[CH];
+    int er[CH];
+    unsigned nmin = mask;
 #pragma unroll
     for (int k = 0; k < CH; k++) {
         const float dx = ax - xs[k], dy = ay - ys[k];
         s[k] = fmaf(dy, dy, dx * dx);
-        const int d = (int)(azq - __float_as_uint(zs[k]));
-        unsigned q = (unsigned)max(d, -d);
+        u[k] = absdiff_plus(azq, __float_as_uint(zs[k]), PC_ZQ_MARGIN);
         // the block's own triangle (j <= i) and the padding of a partial
         // chunk: out of range in rp, mid-bin in pi (never undecided)
         if ((TRI && !(j + k > i)) || (MASK && k >= rem)) {
             s[k] = kmax;
-            q = 1u << (sh - 1);
+            u[k] = 1u << (sh - 1);
         }
-        dq[k] = q;
-        kp[k] = q >> sh;
         // s >= 0, so the bit patterns order like the values (no NaN here)
         key[k] = (unsigned)__uint_as_float(min(__float_as_uint(s[k]), kmaxb));
-        fl[k] = (int)((q + PC_ZQ_MARGIN) & mask) - 2 * PC_ZQ_MARGIN;   // < 0: near an edge
+        near[k] = u[k] & mask;
+        nmin = min(nmin, near[k]);
     }
 #pragma unroll
     for (int k = 0; k < CH; k++)
@@ -510,13 +490,13 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
     int flag = 0;
 #pragma unroll
     for (int k = 0; k < CH; k++)
-        flag |= (T16 ? ((er[k] << 16) | (er[k] << 17)) : er[k]) | fl[k];
+        flag |= T16 ? ((er[k] << 16) | (er[k] << 17)) : er[k];
     const int nb = a.B.nb;
-    if (flag < 0) {
+    if ((flag < 0) | (nmin < 2u * PC_ZQ_MARGIN)) {
 #pragma unroll
         for (int k = 0; k < CH; k++) {
             const bool sr = is_slow<T16>(er[k]);
-            const bool sp = fl[k] < 0;
+            const bool sp = near[k] < 2u * PC_ZQ_MARGIN;
             if (sr || sp) {
                 int row = er[k];
                 if (sr) {
@@ -524,23 +504,30 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
                     if (row == nb + 1)
                         row = 0;
                 }
-                if (row != 0 && (row < 0 || (sp && dq[k] >= 2u * PC_ZQ_MARGIN))) {
+                // |dq| < 2 * margin lies well inside pi bin 0 (u >> sh is 0)
+                if (row != 0 && (row < 0 || (sp && u[k] >= 3u * PC_ZQ_MARGIN))) {
                     int col;
                     exact_rowcol<PC_METRIC_RPPI>(a, L, i, j + k, dcode, row, col);
                     rechecks++;
-                    kp[k] = col > 0 ? (unsigned)(col - 1) : npi;
+                    // a pi bin below |dz| / dpi <= 2^(29 - sh) shifts without
+                    // overflow; out of range gives row 0, which is not counted
+                    u[k] = col > 0 ? (unsigned)(col - 1) << sh : 0u;
                 }
                 er[k] = row;
             }
         }
     }
+    // kp < npi iff u < npi << sh (every u fits when that shift overflows);
+    // the slot's byte offset is one 24-bit multiply-add
+    const unsigned ulim = npi > (0xFFFFFFFFu >> sh) ? 0xFFFFFFFFu : npi << sh;
+    const unsigned rw4 = 4u * (unsigned)a.B.row_w;
 #pragma unroll
     for (int k = 0; k < CH; k++) {
-        if ((er[k] > 0) & (kp[k] < npi)) {
-            const int slot = er[k] * a.B.row_w + (int)kp[k] + 1;
-            lds_add(&hb[slot], 1u);
+        if ((er[k] > 0) & (u[k] < ulim)) {
+            const unsigned off = __umul24((unsigned)er[k], rw4) + ((u[k] >> sh) << 2) + 4u;
+            lds_add((lds_u32p)((LDS char *)hb + off), 1u);
             if (W)
-                lds_add(&whb[slot], wi * ws[k]);
+                lds_add(&whb[off >> 2], wi * ws[k]);
         }
     }
 }
@@ -559,7 +546,6 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     // inactive lanes sit far away: their separations overflow to +inf
     const float ax = act ? a.X1[i] + Dx : 3.0e30f;
     const float ay = act ? a.Y1[i] + Dy : 3.0e30f;
-    const float az = act ? a.Z1[i] + Dz : 3.0e30f;
     const double wi = (W && act) ? a.w1[i] : 0.0;
     // second-catalogue points are wave-uniform: read them through the scalar
     // cache (the arrays are not written during the sweep)
@@ -567,7 +553,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     const kf64p w2 = (kf64p)a.w2;
     constexpr int CH = W ? 4 : 8;
     int j = j0;
-    if (M == PC_METRIC_RPPI && a.B.zq_shift > 0) {
+    if constexpr (M == PC_METRIC_RPPI) {
         // z in fixed point: the periodic z offset is a whole number of quanta
         const unsigned Dq = cz == PC_D_PLUS ? a.B.zq_L : (cz == PC_D_MINUS ? 0u - a.B.zq_L : 0u);
         const unsigned azq = __float_as_uint(a.Z1[i]) + Dq;
@@ -600,35 +586,37 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
                                                     zs, ws, j, dcode, rechecks, rem);
         }
         return;
-    }
-    for (; j + CH <= j1; j += CH) {
-        float xs[CH], ys[CH], zs[CH];
-        double ws[CH];
+    } else {
+        const float az = act ? a.Z1[i] + Dz : 3.0e30f;
+        for (; j + CH <= j1; j += CH) {
+            float xs[CH], ys[CH], zs[CH];
+            double ws[CH];
 #pragma unroll
-        for (int k = 0; k < CH; k++) {
-            xs[k] = X2[j + k];
-            ys[k] = Y2[j + k];
-            zs[k] = Z2[j + k];
-            ws[k] = W ? w2[j + k] : 0.0;
+            for (int k = 0; k < CH; k++) {
+                xs[k] = X2[j + k];
+                ys[k] = Y2[j + k];
+                zs[k] = Z2[j + k];
+                ws[k] = W ? w2[j + k] : 0.0;
+            }
+            chunk_f32<M, W, TRI, T16, UNC, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs, ws, j,
+                                               dcode, rechecks);
         }
-        chunk_f32<M, W, TRI, T16, UNC, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs, ws, j,
-                                           dcode, rechecks);
-    }
-    if (j < j1) {
-        // the partial last chunk, padded with the item's last point
-        const int rem = j1 - j;
-        float xs[CH], ys[CH], zs[CH];
-        double ws[CH];
+        if (j < j1) {
+            // the partial last chunk, padded with the item's last point
+            const int rem = j1 - j;
+            float xs[CH], ys[CH], zs[CH];
+            double ws[CH];
 #pragma unroll
-        for (int k = 0; k < CH; k++) {
-            const int jk = j + min(k, rem - 1);
-            xs[k] = X2[jk];
-            ys[k] = Y2[jk];
-            zs[k] = Z2[jk];
-            ws[k] = W ? w2[jk] : 0.0;
+            for (int k = 0; k < CH; k++) {
+                const int jk = j + min(k, rem - 1);
+                xs[k] = X2[jk];
+                ys[k] = Y2[jk];
+                zs[k] = Z2[jk];
+                ws[k] = W ? w2[jk] : 0.0;
+            }
+            chunk_f32<M, W, TRI, T16, UNC, CH, true>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs,
+                                                     ws, j, dcode, rechecks, rem);
         }
-        chunk_f32<M, W, TRI, T16, UNC, CH, true>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs,
-                                                 ws, j, dcode, rechecks, rem);
     }
 }
 

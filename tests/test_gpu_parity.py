@@ -257,6 +257,19 @@ def test_rppi_noninteger_pi_bins(pc, olib, prec):
     assert (got == want).all()
 
 
+@pytest.mark.parametrize("box", [1000.0, 0.0])
+def test_rppi_fine_pi_bins(pc, olib, box):
+    """pi bins too fine for 2^4 fixed-point quanta each (box / dpi > 2^25):
+    the float32 call sweeps in binary64 and must still match."""
+    say("rppi fine pi bins", box)
+    pts = synth.clustered_box(6000, 1000.0, seed=28, nblobs=30, sigma=0.002)
+    e = synth.log_edges(0.001, 0.05, 6)
+    got, _ = pc.count_rppi(pts, None, e, 0.002, 100, box, "fp32")
+    want, _ = oracle.count_rppi(pts, None, e, 0.002, 100, box, lib=olib)
+    assert want.sum() > 0
+    assert (got == want).all()
+
+
 # ---------------------------------------------------------------- DD(theta)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_theta_auto_cross(pc, olib, prec):
