@@ -56,6 +56,19 @@ def _bind(lib):
                                        ctypes.c_int, dp, i32, up, dp,
                                        ctypes.c_int]
     lib.oracle_count_theta.restype = ctypes.c_int
+    lib.oracle_count_r_ex.argtypes = [i64, dp, dp, dp, dp, i64, dp, dp, dp, dp,
+                                      ctypes.c_int, dp, i32, dbl, up, dp,
+                                      ctypes.c_int, dp, ctypes.c_int]
+    lib.oracle_count_r_ex.restype = ctypes.c_int
+    lib.oracle_count_rppi_ex.argtypes = [i64, dp, dp, dp, dp, i64, dp, dp, dp,
+                                         dp, ctypes.c_int, dp, i32, dbl, i32,
+                                         dbl, up, dp, ctypes.c_int, dp,
+                                         ctypes.c_int]
+    lib.oracle_count_rppi_ex.restype = ctypes.c_int
+    lib.oracle_count_theta_ex.argtypes = [i64, dp, dp, dp, i64, dp, dp, dp,
+                                          ctypes.c_int, dp, i32, up, dp,
+                                          ctypes.c_int, dp, ctypes.c_int]
+    lib.oracle_count_theta_ex.restype = ctypes.c_int
     lib.oracle_radec_to_unit.argtypes = [i64, dp, dp, dp, dp, dp]
     lib.oracle_radec_to_unit.restype = ctypes.c_int
     lib.oracle_theta_chord_edges.argtypes = [i32, dp, dp]
@@ -107,9 +120,20 @@ def _check(rc, what):
         raise OracleError(f"{what} failed with status {rc}")
 
 
+WEIGHT_TYPES = {"product": 0, "sum": 1}
+
+
+def _wtype(weight_type):
+    if weight_type not in WEIGHT_TYPES:
+        raise ValueError(f"unknown weight_type {weight_type!r}")
+    return WEIGHT_TYPES[weight_type]
+
+
 def count_r(d1, d2=None, edges=None, boxsize: float = 0.0, w1=None, w2=None,
-            nthreads: int = 0, lib=None):
-    """DD(r) counts (uint64[nbins]) and weighted sums (float64[nbins] or None).
+            nthreads: int = 0, lib=None, weight_type: str = "product",
+            ravg: bool = False):
+    """DD(r) counts (uint64[nbins]) and weighted sums (float64[nbins] or None),
+    plus the mean separation per bin (float64[nbins]) when ``ravg``.
 
     ``d2 is None`` selects the autocorrelation of d1 (== cross(d1, d1))."""
     lib = lib or load()
@@ -122,18 +146,21 @@ def count_r(d1, d2=None, edges=None, boxsize: float = 0.0, w1=None, w2=None,
     ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
     counts = np.zeros(nb, dtype=np.uint64)
     wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
-    rc = lib.oracle_count_r(x1.size, _ptr(x1), _ptr(y1), _ptr(z1), _ptr(ww1),
-                            x2.size, _ptr(x2), _ptr(y2), _ptr(z2), _ptr(ww2),
-                            int(auto), _ptr(edges), nb, float(boxsize),
-                            counts.ctypes.data, _ptr(wsum), int(nthreads))
+    rv = np.zeros(nb, dtype=np.float64) if ravg else None
+    rc = lib.oracle_count_r_ex(x1.size, _ptr(x1), _ptr(y1), _ptr(z1), _ptr(ww1),
+                               x2.size, _ptr(x2), _ptr(y2), _ptr(z2), _ptr(ww2),
+                               int(auto), _ptr(edges), nb, float(boxsize),
+                               counts.ctypes.data, _ptr(wsum), _wtype(weight_type),
+                               _ptr(rv), int(nthreads))
     _check(rc, "oracle_count_r")
-    return counts, wsum
+    return (counts, wsum, rv) if ravg else (counts, wsum)
 
 
 def count_rppi(d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
                boxsize: float = 0.0, w1=None, w2=None, nthreads: int = 0,
-               lib=None):
-    """DD(rp, pi) counts as uint64[nrp, npi] (and weighted sums)."""
+               lib=None, weight_type: str = "product", ravg: bool = False):
+    """DD(rp, pi) counts as uint64[nrp, npi] (and weighted sums, and the mean
+    rp per bin when ``ravg``)."""
     lib = lib or load()
     rp_edges = _f64(rp_edges)
     nb = rp_edges.size - 1
@@ -144,21 +171,27 @@ def count_rppi(d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
     ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
     counts = np.zeros(nb * npi, dtype=np.uint64)
     wsum = np.zeros(nb * npi, dtype=np.float64) if w1 is not None else None
-    rc = lib.oracle_count_rppi(x1.size, _ptr(x1), _ptr(y1), _ptr(z1),
-                               _ptr(ww1), x2.size, _ptr(x2), _ptr(y2),
-                               _ptr(z2), _ptr(ww2), int(auto), _ptr(rp_edges),
-                               nb, float(pimax), int(npi), float(boxsize),
-                               counts.ctypes.data, _ptr(wsum), int(nthreads))
+    rv = np.zeros(nb * npi, dtype=np.float64) if ravg else None
+    rc = lib.oracle_count_rppi_ex(x1.size, _ptr(x1), _ptr(y1), _ptr(z1),
+                                  _ptr(ww1), x2.size, _ptr(x2), _ptr(y2),
+                                  _ptr(z2), _ptr(ww2), int(auto), _ptr(rp_edges),
+                                  nb, float(pimax), int(npi), float(boxsize),
+                                  counts.ctypes.data, _ptr(wsum), _wtype(weight_type),
+                                  _ptr(rv), int(nthreads))
     _check(rc, "oracle_count_rppi")
     counts = counts.reshape(nb, npi)
     if wsum is not None:
         wsum = wsum.reshape(nb, npi)
+    if ravg:
+        return counts, wsum, rv.reshape(nb, npi)
     return counts, wsum
 
 
 def count_theta(ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
-                w1=None, w2=None, nthreads: int = 0, lib=None):
-    """DD(theta) / DR(theta) counts from RA/DEC in degrees."""
+                w1=None, w2=None, nthreads: int = 0, lib=None,
+                weight_type: str = "product", ravg: bool = False):
+    """DD(theta) / DR(theta) counts from RA/DEC in degrees (and the mean
+    angle per bin in degrees when ``ravg``)."""
     lib = lib or load()
     te = _f64(theta_edges_deg)
     nb = te.size - 1
@@ -169,12 +202,14 @@ def count_theta(ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
     ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
     counts = np.zeros(nb, dtype=np.uint64)
     wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
-    rc = lib.oracle_count_theta(a1.size, _ptr(a1), _ptr(d1), _ptr(ww1),
-                                a2.size, _ptr(a2), _ptr(d2), _ptr(ww2),
-                                int(auto), _ptr(te), nb, counts.ctypes.data,
-                                _ptr(wsum), int(nthreads))
+    rv = np.zeros(nb, dtype=np.float64) if ravg else None
+    rc = lib.oracle_count_theta_ex(a1.size, _ptr(a1), _ptr(d1), _ptr(ww1),
+                                   a2.size, _ptr(a2), _ptr(d2), _ptr(ww2),
+                                   int(auto), _ptr(te), nb, counts.ctypes.data,
+                                   _ptr(wsum), _wtype(weight_type), _ptr(rv),
+                                   int(nthreads))
     _check(rc, "oracle_count_theta")
-    return counts, wsum
+    return (counts, wsum, rv) if ravg else (counts, wsum)
 
 
 def radec_to_unit(ra, dec, lib=None):

@@ -35,6 +35,21 @@
  *     this is the cos(theta) = v1.v2 relation of Appendix A rewritten as a
  *     monotone function of theta that needs no arccos.
  *
+ * Pair weights (section 2.1's weight_func): the product w_i * w_j, or, as a
+ * second example of a user weighting scheme, the sum w_i + w_j; each is one
+ * rounded binary64 operation per pair.
+ *
+ * Mean separation per bin (the average separation that the paper computes
+ * only on request, since it costs a square root, or an arc function for
+ * angles, per pair): the pair-weighted mean sum(sep_ij * w_ij) / sum(w_ij)
+ * over the pairs of the bin, with w_ij = 1 without weights (then the
+ * denominator is the count).  sep_ij = fl(sqrt(s)) for r and rp; for angles
+ * theta_ij = fl(fl(2 * asin(0.5 * fl(sqrt(chord^2)))) * fl(180 / pi)) in
+ * degrees, the arc form that stays accurate for small angles.  Self-pairs
+ * add their weight (w_i * w_i, or w_i + w_i) to the denominator and zero to
+ * the numerator.  Both sums are exactly rounded (below); the mean is their
+ * rounded quotient, and 0 for a bin without weight.
+ *
  * Pair convention (section "Symmetry considerations for autocorrelations" and
  * Appendix B): an autocorrelation of D must equal the cross-correlation of D
  * with itself, i.e. all N^2 ordered pairs including i == j.  It is computed as
@@ -190,9 +205,27 @@ int oracle_pi_edges(double pimax, int32_t npi, double *q)
     return ORACLE_OK;
 }
 
+/* Separation reported in the mean-separation output: the distance sqrt(s)
+   (r, rp), or (angle != 0) the angle in degrees of a squared chord s.       */
+static double separation_value(int angle, double s)
+{
+    const double c = sqrt(s);
+    if (!angle)
+        return c;
+    return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);
+}
+
+/* Weight of pair (a, b): 0 product, 1 sum.                                 */
+static double pair_weight(int wtype, double a, double b)
+{
+    return wtype == 1 ? a + b : a * b;
+}
+
 /* One engine for the 1-D (r or chord) and the 2-D (rp, pi) statistics.
    mode 0: s = (dx*dx + dy*dy) + dz*dz, bins k over E
-   mode 1: s = dx*dx + dy*dy, pi = |dz|, bins k*npi + p over E x q           */
+   mode 1: s = dx*dx + dy*dy, pi = |dz|, bins k*npi + p over E x q
+   wtype: pair weight (0 product, 1 sum); ravg (optional): mean separation
+   per bin, angle != 0 reporting angles from squared chords.                */
 static int count_engine(int mode,
                         int64_t n1, const double *x1, const double *y1,
                         const double *z1, const double *w1,
@@ -200,7 +233,8 @@ static int count_engine(int mode,
                         const double *z2, const double *w2,
                         int autocorr, const double *edges, int32_t nbins,
                         const double *q, int32_t npi, double boxsize,
-                        uint64_t *counts, double *wsum, int nthreads)
+                        uint64_t *counts, double *wsum, int wtype, int angle,
+                        double *ravg, int nthreads)
 {
     int rc = check_edges(edges, nbins);
     if (rc)
@@ -219,6 +253,9 @@ static int count_engine(int mode,
     const int weighted = (w1 != NULL);
     if (weighted && w2 == NULL)
         return ORACLE_EINVAL;
+    if (wtype != 0 && (wtype != 1 || !weighted))
+        return ORACLE_EINVAL;
+    const int want_r = (ravg != NULL);
     const int nout = (mode == 1) ? nbins * npi : nbins;
     const int periodic = boxsize > 0.0;
     const double L = boxsize;
@@ -232,13 +269,16 @@ static int count_engine(int mode,
         E[k] = edges[k] * edges[k];
 
     memset(counts, 0, sizeof(uint64_t) * (size_t)nout);
-    xacc *total = NULL;
-    if (weighted) {
+    xacc *total = NULL, *rtotal = NULL;
+    if (weighted)
         total = (xacc *)calloc((size_t)nout, sizeof(xacc));
-        if (!total) {
-            free(E);
-            return ORACLE_ENOMEM;
-        }
+    if (want_r)
+        rtotal = (xacc *)calloc((size_t)nout, sizeof(xacc));
+    if ((weighted && !total) || (want_r && !rtotal)) {
+        free(E);
+        free(total);
+        free(rtotal);
+        return ORACLE_ENOMEM;
     }
     int failed = 0;
 
@@ -250,7 +290,8 @@ static int count_engine(int mode,
     {
         uint64_t *c = (uint64_t *)calloc((size_t)nout, sizeof(uint64_t));
         xacc *acc = weighted ? (xacc *)calloc((size_t)nout, sizeof(xacc)) : NULL;
-        int ok = (c != NULL) && (!weighted || acc != NULL);
+        xacc *racc = want_r ? (xacc *)calloc((size_t)nout, sizeof(xacc)) : NULL;
+        int ok = (c != NULL) && (!weighted || acc != NULL) && (!want_r || racc != NULL);
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 16)
 #endif
@@ -269,8 +310,9 @@ static int count_engine(int mode,
                     dz = wrap_axis(dz, L, half);
                 }
                 int bin;
+                double s;
                 if (mode == 0) {
-                    double s = (dx * dx + dy * dy) + dz * dz;
+                    s = (dx * dx + dy * dy) + dz * dz;
                     if (s < E[0] || s >= E[nbins])
                         continue;
                     int k = nbins - 1; /* reverse scan over the bins */
@@ -278,7 +320,7 @@ static int count_engine(int mode,
                         k--;
                     bin = k;
                 } else {
-                    double s = dx * dx + dy * dy;
+                    s = dx * dx + dy * dy;
                     double pi = fabs(dz);
                     if (s < E[0] || s >= E[nbins] || pi >= pimax)
                         continue;
@@ -291,11 +333,16 @@ static int count_engine(int mode,
                     bin = k * npi + p;
                 }
                 c[bin]++;
+                double prod = 1.0;
                 if (weighted) {
-                    double prod = w1[i] * w2[j];
+                    prod = pair_weight(wtype, w1[i], w2[j]);
                     /* autocorrelation: the unique pair stands for (i,j) and
                        (j,i); doubling is exact in binary64 */
                     xacc_add(&acc[bin], autocorr ? 2.0 * prod : prod);
+                }
+                if (want_r) {
+                    const double rw = separation_value(angle, s) * prod;
+                    xacc_add(&racc[bin], autocorr ? 2.0 * rw : rw);
                 }
             }
         }
@@ -310,15 +357,19 @@ static int count_engine(int mode,
                     counts[b] += c[b];
                     if (weighted)
                         xacc_merge(&total[b], &acc[b]);
+                    if (want_r)
+                        xacc_merge(&rtotal[b], &racc[b]);
                 }
             }
         }
         free(c);
         free(acc);
+        free(racc);
     }
     if (failed) {
         free(E);
         free(total);
+        free(rtotal);
         return ORACLE_ENOMEM;
     }
 
@@ -331,7 +382,7 @@ static int count_engine(int mode,
             counts[0] += (uint64_t)n1;
             if (weighted)
                 for (int64_t i = 0; i < n1; i++)
-                    xacc_add(&total[0], w1[i] * w1[i]);
+                    xacc_add(&total[0], pair_weight(wtype, w1[i], w1[i]));
         }
     }
     if (wsum) {
@@ -343,13 +394,36 @@ static int count_engine(int mode,
             if (total[b].overflow)
                 rc = ORACLE_EINTERNAL;
     }
+    if (want_r) {
+        for (int b = 0; b < nout; b++) {
+            const double den = weighted ? xacc_value(&total[b]) : (double)counts[b];
+            ravg[b] = den != 0.0 ? xacc_value(&rtotal[b]) / den : 0.0;
+            if (rtotal[b].overflow)
+                rc = ORACLE_EINTERNAL;
+        }
+    }
     free(E);
     free(total);
+    free(rtotal);
     return rc;
 }
 
 /* DD(r): counts[k] over r edges (edges[0..nbins]); boxsize <= 0 means
-   non-periodic; autocorr != 0 ignores the second catalogue. */
+   non-periodic; autocorr != 0 ignores the second catalogue.  The _ex form
+   adds the pair weight type and the optional mean separation per bin. */
+int oracle_count_r_ex(int64_t n1, const double *x1, const double *y1,
+                      const double *z1, const double *w1,
+                      int64_t n2, const double *x2, const double *y2,
+                      const double *z2, const double *w2,
+                      int autocorr, const double *edges, int32_t nbins,
+                      double boxsize, uint64_t *counts, double *wsum,
+                      int wtype, double *ravg, int nthreads)
+{
+    return count_engine(0, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
+                        edges, nbins, NULL, 0, boxsize, counts, wsum, wtype,
+                        0, ravg, nthreads);
+}
+
 int oracle_count_r(int64_t n1, const double *x1, const double *y1,
                    const double *z1, const double *w1,
                    int64_t n2, const double *x2, const double *y2,
@@ -358,19 +432,21 @@ int oracle_count_r(int64_t n1, const double *x1, const double *y1,
                    double boxsize, uint64_t *counts, double *wsum,
                    int nthreads)
 {
-    return count_engine(0, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
-                        edges, nbins, NULL, 0, boxsize, counts, wsum,
-                        nthreads);
+    return oracle_count_r_ex(n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
+                             edges, nbins, boxsize, counts, wsum, 0, NULL,
+                             nthreads);
 }
 
-/* DD(rp, pi): counts[k * npi + p]; rp edges rp_edges[0..nrp]. */
-int oracle_count_rppi(int64_t n1, const double *x1, const double *y1,
-                      const double *z1, const double *w1,
-                      int64_t n2, const double *x2, const double *y2,
-                      const double *z2, const double *w2,
-                      int autocorr, const double *rp_edges, int32_t nrp,
-                      double pimax, int32_t npi, double boxsize,
-                      uint64_t *counts, double *wsum, int nthreads)
+/* DD(rp, pi): counts[k * npi + p]; rp edges rp_edges[0..nrp]; the mean
+   separation of the _ex form is the mean rp of each (rp, pi) bin. */
+int oracle_count_rppi_ex(int64_t n1, const double *x1, const double *y1,
+                         const double *z1, const double *w1,
+                         int64_t n2, const double *x2, const double *y2,
+                         const double *z2, const double *w2,
+                         int autocorr, const double *rp_edges, int32_t nrp,
+                         double pimax, int32_t npi, double boxsize,
+                         uint64_t *counts, double *wsum, int wtype,
+                         double *ravg, int nthreads)
 {
     if (npi < 1)
         return ORACLE_EINVAL;
@@ -381,9 +457,22 @@ int oracle_count_rppi(int64_t n1, const double *x1, const double *y1,
     if (rc == ORACLE_OK)
         rc = count_engine(1, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2,
                           autocorr, rp_edges, nrp, q, npi, boxsize, counts,
-                          wsum, nthreads);
+                          wsum, wtype, 0, ravg, nthreads);
     free(q);
     return rc;
+}
+
+int oracle_count_rppi(int64_t n1, const double *x1, const double *y1,
+                      const double *z1, const double *w1,
+                      int64_t n2, const double *x2, const double *y2,
+                      const double *z2, const double *w2,
+                      int autocorr, const double *rp_edges, int32_t nrp,
+                      double pimax, int32_t npi, double boxsize,
+                      uint64_t *counts, double *wsum, int nthreads)
+{
+    return oracle_count_rppi_ex(n1, x1, y1, z1, w1, n2, x2, y2, z2, w2,
+                                autocorr, rp_edges, nrp, pimax, npi, boxsize,
+                                counts, wsum, 0, NULL, nthreads);
 }
 
 /* RA/DEC in degrees -> unit vectors (binary64, host libm). */
@@ -418,12 +507,14 @@ int oracle_theta_chord_edges(int32_t nedges, const double *theta_deg,
     return ORACLE_OK;
 }
 
-/* DD(theta) / DR(theta) from RA/DEC in degrees. */
-int oracle_count_theta(int64_t n1, const double *ra1, const double *dec1,
-                       const double *w1, int64_t n2, const double *ra2,
-                       const double *dec2, const double *w2, int autocorr,
-                       const double *theta_edges_deg, int32_t nbins,
-                       uint64_t *counts, double *wsum, int nthreads)
+/* DD(theta) / DR(theta) from RA/DEC in degrees; the mean separation of
+   the _ex form is the mean angle in degrees. */
+int oracle_count_theta_ex(int64_t n1, const double *ra1, const double *dec1,
+                          const double *w1, int64_t n2, const double *ra2,
+                          const double *dec2, const double *w2, int autocorr,
+                          const double *theta_edges_deg, int32_t nbins,
+                          uint64_t *counts, double *wsum, int wtype,
+                          double *ravg, int nthreads)
 {
     if (n1 < 0 || nbins < 1)
         return ORACLE_EINVAL;
@@ -442,10 +533,22 @@ int oracle_count_theta(int64_t n1, const double *ra1, const double *dec1,
         if (rc == ORACLE_OK)
             rc = count_engine(0, n1, v1, v1 + n1, v1 + 2 * n1, w1, n2, v2,
                               v2 + n2, v2 + 2 * n2, w2, autocorr, c, nbins,
-                              NULL, 0, 0.0, counts, wsum, nthreads);
+                              NULL, 0, 0.0, counts, wsum, wtype, 1, ravg,
+                              nthreads);
     }
     free(v1);
     free(v2);
     free(c);
     return rc;
+}
+
+int oracle_count_theta(int64_t n1, const double *ra1, const double *dec1,
+                       const double *w1, int64_t n2, const double *ra2,
+                       const double *dec2, const double *w2, int autocorr,
+                       const double *theta_edges_deg, int32_t nbins,
+                       uint64_t *counts, double *wsum, int nthreads)
+{
+    return oracle_count_theta_ex(n1, ra1, dec1, w1, n2, ra2, dec2, w2,
+                                 autocorr, theta_edges_deg, nbins, counts,
+                                 wsum, 0, NULL, nthreads);
 }

@@ -376,6 +376,142 @@ def pin_theta_conversion(lib):
     assert np.allclose(c * c, 2.0 - 2.0 * np.cos(np.radians(t)), rtol=1e-13, atol=1e-15)
 
 
+# --------------------------------------------------------------------------
+# pair weight types and the mean separation per bin
+# --------------------------------------------------------------------------
+def _exact_chain_stats(x, z, w, edges, L, wtype, rp_edges_pi=None):
+    """Exact per-bin count, weight sum and separation-weight sum over all
+    ordered pairs (self-pairs included) of points (x_a, 2, z_a) whose pair
+    separations are integers: r = |dx| with z constant, or rp = |dx| and
+    pi = |dz| for the (rp, pi) case (rp_edges_pi = (pimax, npi))."""
+    Lf = None if L <= 0 else Fraction(L)
+    n = len(x)
+    E = [Fraction(float(e) * float(e)) for e in edges]
+    nb = len(edges) - 1
+    npi = 1 if rp_edges_pi is None else rp_edges_pi[1]
+    cnt = [[0] * npi for _ in range(nb)]
+    ws = [[Fraction(0)] * npi for _ in range(nb)]
+    rs = [[Fraction(0)] * npi for _ in range(nb)]
+    for a in range(n):
+        for b in range(n):
+            dx2 = _min_image_sq(Fraction(x[a]) - Fraction(x[b]), Lf)
+            d = Fraction(math.isqrt(int(dx2)))
+            assert d * d == dx2
+            p = 0
+            if rp_edges_pi is not None:
+                pimax, _ = rp_edges_pi
+                dz = Fraction(math.isqrt(int(_min_image_sq(Fraction(z[a]) - Fraction(z[b]), Lf))))
+                if dz >= pimax:
+                    continue
+                p = int(dz // (Fraction(pimax) / npi))
+            for k in range(nb):
+                if E[k] <= dx2 < E[k + 1]:
+                    wab = Fraction(w[a]) * Fraction(w[b]) if wtype == "product" else \
+                        Fraction(w[a]) + Fraction(w[b])
+                    cnt[k][p] += 1
+                    ws[k][p] += wab
+                    rs[k][p] += d * wab
+    return cnt, ws, rs
+
+
+def pin_ravg_chain_r(lib):
+    """Mean separation on a chain with integer separations: every sum is an
+    integer, so the oracle's rounded quotient equals the exact rational mean
+    rounded once; unit weights give the plain mean."""
+    x = [0.5, 1.5, 2.5, 3.5, 5.5, 8.5, 13.5, 14.5]
+    pts = np.array([[v, 2.0, 2.0] for v in x])
+    w = np.array([1.0, 2.0, 3.0, 1.0, 4.0, 2.0, 5.0, 3.0])
+    for edges in ([0.0, 1.5, 2.5, 6.5, 12.5], [0.5, 1.5, 4.5, 9.5]):
+        for box in (32.0, 0.0):
+            for wtype in ("product", "sum"):
+                cnt, ws, rs = _exact_chain_stats(x, None, w, edges, box, wtype)
+                c, gw, rv = oracle.count_r(pts, None, edges, box, w1=w, lib=lib,
+                                           weight_type=wtype, ravg=True)
+                assert c.tolist() == [v[0] for v in cnt], (edges, box, c, cnt)
+                assert gw.tolist() == [float(v[0]) for v in ws], (edges, box, wtype, gw)
+                want = [float(r[0] / q[0]) if q[0] else 0.0 for r, q in zip(rs, ws)]
+                assert rv.tolist() == want, (edges, box, wtype, rv, want)
+            one = np.ones(len(x))
+            cnt, ws, rs = _exact_chain_stats(x, None, one, edges, box, "product")
+            c, _, rv = oracle.count_r(pts, None, edges, box, lib=lib, ravg=True)
+            want = [float(r[0] / k[0]) if k[0] else 0.0 for r, k in zip(rs, cnt)]
+            assert rv.tolist() == want, (edges, box, rv, want)
+            # cross-correlation of the chain with itself gives the same means
+            _, _, rx = oracle.count_r(pts, pts.copy(), edges, box, lib=lib, ravg=True)
+            assert rx.tolist() == want
+
+
+def pin_ravg_chain_rppi(lib):
+    """Mean rp per (rp, pi) bin on a chain with integer rp and pi."""
+    x = [0.0, 1.0, 3.0, 4.0, 7.0, 11.0]
+    z = [0.0, 2.0, 1.0, 5.0, 3.0, 9.0]
+    pts = np.array([[a, 2.0, b] for a, b in zip(x, z)])
+    w = np.array([2.0, 1.0, 3.0, 1.0, 2.0, 4.0])
+    edges = [0.0, 1.5, 3.5, 8.5]
+    pimax, npi = 8.0, 4
+    for box in (24.0, 0.0):
+        for wtype in ("product", "sum"):
+            cnt, ws, rs = _exact_chain_stats(x, z, w, edges, box, wtype, (pimax, npi))
+            c, gw, rv = oracle.count_rppi(pts, None, edges, pimax, npi, box, w1=w, lib=lib,
+                                          weight_type=wtype, ravg=True)
+            assert c.tolist() == cnt, (box, c, cnt)
+            want = [[float(r / q) if q else 0.0 for r, q in zip(rr, qq)] for rr, qq in zip(rs, ws)]
+            assert rv.tolist() == want, (box, wtype, rv, want)
+
+
+def pin_ravg_theta_equator(lib):
+    """Points on the equator: the angle of a pair is the difference of RA,
+    so each bin's mean angle is a known rational (to the rounding of the
+    trigonometric round trip, about 1e-15 relative)."""
+    ra = np.array([0.0, 1.0, 2.5, 4.0, 7.0, 12.0])
+    dec = np.zeros_like(ra)
+    w = np.array([1.0, 3.0, 2.0, 2.0, 1.0, 4.0])
+    edges = [0.5, 1.75, 3.25, 6.0, 13.0]
+    for wtype in ("product", "sum"):
+        c, gw, rv = oracle.count_theta(ra, dec, theta_edges_deg=edges, w1=w, lib=lib,
+                                       weight_type=wtype, ravg=True)
+        for k in range(len(edges) - 1):
+            num = den = Fraction(0)
+            n = 0
+            for a in range(ra.size):
+                for b in range(ra.size):
+                    t = Fraction(abs(ra[a] - ra[b]))
+                    if Fraction(edges[k]) <= t < Fraction(edges[k + 1]):
+                        wab = Fraction(w[a]) * Fraction(w[b]) if wtype == "product" else \
+                            Fraction(w[a]) + Fraction(w[b])
+                        num += t * wab
+                        den += wab
+                        n += 1
+            assert int(c[k]) == n, (k, c, n)
+            want = float(num / den) if den else 0.0
+            assert abs(rv[k] - want) <= 1e-13 * max(want, 1.0), (wtype, k, rv[k], want)
+
+
+def pin_ravg_inside_bins(lib):
+    """Each non-empty bin's mean separation lies inside the bin (positive
+    weights), on clustered points, for r, rp and theta."""
+    pts = synth.clustered_box(700, 30.0, seed=91, nblobs=6, sigma=1.5)
+    w = synth.uniform_weights(700, seed=92)
+    e = synth.log_edges(0.2, 6.0, 8)
+    for box in (30.0, 0.0):
+        c, _, rv = oracle.count_r(pts, None, e, box, w1=w, lib=lib, ravg=True)
+        for k in range(e.size - 1):
+            if c[k]:
+                assert e[k] <= rv[k] <= e[k + 1], (box, k, rv[k])
+        c, _, rv = oracle.count_rppi(pts, None, e, 5.0, 5, box, lib=lib, ravg=True)
+        for k in range(e.size - 1):
+            for p in range(5):
+                if c[k, p]:
+                    assert e[k] <= rv[k, p] <= e[k + 1], (box, k, p, rv[k, p])
+    ra, dec = synth.cap_radec(600, seed=93, clustered=True)
+    te = synth.log_edges(0.05, 8.0, 8)
+    c, _, rv = oracle.count_theta(ra, dec, theta_edges_deg=te, lib=lib, ravg=True,
+                                  w1=w[:600], weight_type="sum")
+    for k in range(te.size - 1):
+        if c[k]:
+            assert te[k] * (1 - 1e-12) <= rv[k] <= te[k + 1] * (1 + 1e-12), (k, rv[k])
+
+
 ALL_PINS = [
     pin_golden_r_edges,
     pin_golden_r_periodic,
@@ -394,4 +530,8 @@ ALL_PINS = [
     pin_inclusion_r_in_rppi,
     pin_uniform_analytic,
     pin_theta_conversion,
+    pin_ravg_chain_r,
+    pin_ravg_chain_rppi,
+    pin_ravg_theta_equator,
+    pin_ravg_inside_bins,
 ]

@@ -11,7 +11,7 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "paircount_oracle.c")
 
 # (name, exact text in the oracle, replacement)
 MUTATIONS = [
-    ("dropped_z_term", "double s = (dx * dx + dy * dy) + dz * dz;", "double s = (dx * dx + dy * dy);"),
+    ("dropped_z_term", "s = (dx * dx + dy * dy) + dz * dz;", "s = (dx * dx + dy * dy);"),
     ("wrong_sign_dy", "double dy = yi - y2[j];", "double dy = yi + y2[j];"),
     ("wrong_array_z", "double dz = zi - z2[j];", "double dz = zi - y2[j];"),
     ("bottom_edge_exclusive", "if (s < E[0] || s >= E[nbins])\n                        continue;\n                    int k",
@@ -28,13 +28,27 @@ MUTATIONS = [
     ("auto_includes_diagonal", "autocorr ? i + 1 : 0", "autocorr ? i : 0"),
     ("pi_cut_inclusive", "pi >= pimax", "pi > pimax"),
     ("pi_bin_off_by_one", "while (pi < q[p])", "while (pi <= q[p] && p > 0)"),
-    ("rp_uses_dz", "double s = dx * dx + dy * dy;\n                    double pi", "double s = dx * dx + dz * dz;\n                    double pi"),
+    ("rp_uses_dz", "s = dx * dx + dy * dy;\n                    double pi", "s = dx * dx + dz * dz;\n                    double pi"),
     ("chord_not_halved", "2.0 * sin(0.5 * (theta_deg[k] * d2r))", "2.0 * sin(theta_deg[k] * d2r)"),
     ("radec_swapped_trig", "x[i] = cd * cos(a);", "x[i] = cd * sin(a);"),
     ("xsum_no_compensation", "double lo = y - (hi - x);", "double lo = 0.0 * (y - (hi - x));"),
-    ("weight_transposed", "double prod = w1[i] * w2[j];", "double prod = w1[i] * w1[j];"),
+    ("weight_transposed", "prod = pair_weight(wtype, w1[i], w2[j]);", "prod = pair_weight(wtype, w1[i], w1[j]);"),
     ("weights_not_doubled", "autocorr ? 2.0 * prod : prod", "prod"),
-    ("self_weight_missing", "xacc_add(&total[0], w1[i] * w1[i]);", "(void)0;"),
+    ("self_weight_missing", "xacc_add(&total[0], pair_weight(wtype, w1[i], w1[i]));", "(void)0;"),
+    ("self_weight_always_product", "xacc_add(&total[0], pair_weight(wtype, w1[i], w1[i]));",
+     "xacc_add(&total[0], w1[i] * w1[i]);"),
+    ("sum_weight_is_product", "return wtype == 1 ? a + b : a * b;", "return a * b;"),
+    ("ravg_of_squared_separation", "const double c = sqrt(s);", "const double c = s;"),
+    ("ravg_not_doubled", "xacc_add(&racc[bin], autocorr ? 2.0 * rw : rw);",
+     "xacc_add(&racc[bin], rw);"),
+    ("ravg_unweighted_numerator", "const double rw = separation_value(angle, s) * prod;",
+     "const double rw = separation_value(angle, s);"),
+    ("ravg_divides_by_count", "weighted ? xacc_value(&total[b]) : (double)counts[b]",
+     "(double)counts[b]"),
+    ("theta_mean_in_radians", "return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);",
+     "return 2.0 * asin(0.5 * c);"),
+    ("theta_mean_half_angle", "return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);",
+     "return asin(0.5 * c) * (180.0 / M_PI);"),
 ]
 
 
