@@ -22,9 +22,15 @@
  *  * counts[] are ordered-pair counts (uint64).  An autocorrelation (d2 ==
  *    NULL) equals the cross-correlation of d1 with itself, i.e. it includes
  *    the N self-pairs in bin 0 when e_0 == 0 (Appendix B).
- *  * wsum[] (optional) is sum over the same pairs of w_i * w_j accumulated in
+ *  * wsum[] (optional) is sum over the same pairs of the pair weight
+ *    (w_i * w_j, or w_i + w_j with cf_options.weight_type) accumulated in
  *    binary64; its order of accumulation is not fixed, so it matches the
  *    exact sum to a relative error of about 1e-13 rather than bit-exactly.
+ *  * cf_options.ravg (optional) receives the mean separation per bin.  The
+ *    binary64 mode sums sqrt(s) (theta: 2 asin(sqrt(s) / 2) in degrees) in
+ *    binary64 like wsum.  The float32 mode sums the separation of the
+ *    float32 evaluation, whose error is bounded by a few float32 roundings
+ *    of the coordinates (relative to the domain origin) and of the result.
  *  * boxsize > 0 selects a periodic cube [0, boxsize]^3 (every coordinate
  *    must lie in the closed interval); boxsize <= 0 selects a non-periodic
  *    domain bounded by the bounding box of both catalogues.
@@ -106,8 +112,23 @@ typedef struct cf_options {
     int32_t autotune;           /* time slices_per_reach and chunk candidates on
                                    the first call of a workload class and reuse
                                    the fastest (cached per context)            */
-    int32_t reserved[7];
+    int32_t weight_type;        /* cf_weight: weight of a pair from the weights
+                                   of its two points (needs weights unless
+                                   CF_WEIGHT_PRODUCT)                          */
+    int32_t reserved[6];
+    double *ravg;               /* optional output, same layout and memory kind
+                                   as counts: the mean separation of the pairs
+                                   in each bin (r, rp, or theta in degrees),
+                                   weighted by the pair weights when weights
+                                   are given; 0 for a bin with no weight.  The
+                                   paper's average separation output, which
+                                   costs a square root (theta: also an arc
+                                   sine) per pair in range; NULL skips it.     */
 } cf_options;
+
+/* Pair weight (section 2.1, weight_func): the product w_i * w_j (the usual
+   choice) or the sum w_i + w_j, each one rounded binary64 operation. */
+typedef enum { CF_WEIGHT_PRODUCT = 0, CF_WEIGHT_SUM = 1 } cf_weight;
 
 /* Statistics of the last counting call on a context. */
 typedef struct cf_stats {

@@ -49,13 +49,18 @@ class cf_catalog(ctypes.Structure):
                 ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("w", ctypes.c_void_p)]
 
 
+CF_WEIGHT_PRODUCT, CF_WEIGHT_SUM = 0, 1
+WEIGHT_TYPES = {"product": CF_WEIGHT_PRODUCT, "sum": CF_WEIGHT_SUM}
+
+
 class cf_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("slices_per_reach", ctypes.c_int32),
                 ("chunk", ctypes.c_int32),
                 ("output_on_device", ctypes.c_int32), ("theta_unit_vectors", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("weight_type", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+                ("ravg", ctypes.c_void_p)]
 
 
 class cf_stats(ctypes.Structure):
@@ -320,52 +325,78 @@ class PairCounter:
             return CF_PREC_FP32_RECHECK
         raise ValueError(f"unknown precision {precision!r}")
 
-    def _opts(self, options):
-        if options is None:
+    def _opts(self, options, weight_type=None, ravg=None, **fixed):
+        """cf_options for a call (None: library defaults).  ``ravg`` is the
+        float64 host array that receives the mean separations."""
+        if options is None and weight_type is None and ravg is None and not fixed:
             return None
         if isinstance(options, cf_options):
-            return ctypes.byref(options)
-        return ctypes.byref(default_options(**options))
+            o = cf_options.from_buffer_copy(options)
+        else:
+            o = default_options(**(options or {}))
+        for k, v in fixed.items():
+            setattr(o, k, int(v))
+        if weight_type is not None:
+            if weight_type not in WEIGHT_TYPES:
+                raise ValueError(f"unknown weight_type {weight_type!r}")
+            o.weight_type = WEIGHT_TYPES[weight_type]
+        o.ravg = None if ravg is None else ravg.ctypes.data
+        self._last_opts = o   # keep alive for the call
+        return ctypes.byref(o)
+
+    @staticmethod
+    def _result(counts, wsum, rv, shape):
+        counts = counts.reshape(shape)
+        if wsum is not None:
+            wsum = wsum.reshape(shape)
+        if rv is not None:
+            return counts, wsum, rv.reshape(shape)
+        return counts, wsum
 
     def count_r(self, d1, d2=None, edges=None, boxsize: float = 0.0, precision="fp64",
-                w1=None, w2=None, options=None):
-        """DD(r): returns (counts uint64[nb], wsum float64[nb] or None)."""
+                w1=None, w2=None, options=None, weight_type=None, ravg=False):
+        """DD(r): returns (counts uint64[nb], wsum float64[nb] or None), plus
+        the mean separation per bin (float64[nb]) when ``ravg``."""
         e = np.ascontiguousarray(edges, dtype=np.float64)
         nb = e.size - 1
         c1 = _Cat(d1, w1)
         c2 = None if d2 is None else _Cat(d2, w2 if w2 is not None else None)
         counts = np.zeros(nb, dtype=np.uint64)
         wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
+        rv = np.zeros(nb, dtype=np.float64) if ravg else None
         st = self._lib.count_pairs_r_ex(
             self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
             e.ctypes.data, nb, float(boxsize), self._prec(precision), counts.ctypes.data,
-            None if wsum is None else wsum.ctypes.data, self._opts(options))
+            None if wsum is None else wsum.ctypes.data, self._opts(options, weight_type, rv))
         self._check(st)
-        return counts, wsum
+        return self._result(counts, wsum, rv, (nb,))
 
     def count_rppi(self, d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
-                   boxsize: float = 0.0, precision="fp64", w1=None, w2=None, options=None):
-        """DD(rp, pi): returns (counts uint64[nrp, npi], wsum or None)."""
+                   boxsize: float = 0.0, precision="fp64", w1=None, w2=None, options=None,
+                   weight_type=None, ravg=False):
+        """DD(rp, pi): returns (counts uint64[nrp, npi], wsum or None), plus
+        the mean rp per bin when ``ravg``."""
         e = np.ascontiguousarray(rp_edges, dtype=np.float64)
         nb = e.size - 1
         c1 = _Cat(d1, w1)
         c2 = None if d2 is None else _Cat(d2, w2)
         counts = np.zeros(nb * int(npi), dtype=np.uint64)
         wsum = np.zeros(nb * int(npi), dtype=np.float64) if w1 is not None else None
+        rv = np.zeros(nb * int(npi), dtype=np.float64) if ravg else None
         st = self._lib.count_pairs_rppi_ex(
             self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
             e.ctypes.data, nb, float(pimax), int(npi), float(boxsize), self._prec(precision),
-            counts.ctypes.data, None if wsum is None else wsum.ctypes.data, self._opts(options))
+            counts.ctypes.data, None if wsum is None else wsum.ctypes.data,
+            self._opts(options, weight_type, rv))
         self._check(st)
-        counts = counts.reshape(nb, int(npi))
-        if wsum is not None:
-            wsum = wsum.reshape(nb, int(npi))
-        return counts, wsum
+        return self._result(counts, wsum, rv, (nb, int(npi)))
 
     def count_rppi_batch(self, catalogues, rp_edges=None, pimax: float = 40.0, npi: int = 40,
-                         boxsize: float = 0.0, precision="fp64", weights=None, options=None):
+                         boxsize: float = 0.0, precision="fp64", weights=None, options=None,
+                         weight_type=None, ravg=False):
         """Batched DD(rp, pi) autocorrelations of several catalogues in one
-        pass: returns (counts uint64[ncat, nrp, npi], wsum or None)."""
+        pass: returns (counts uint64[ncat, nrp, npi], wsum or None), plus the
+        mean rp per bin when ``ravg``."""
         e = np.ascontiguousarray(rp_edges, dtype=np.float64)
         nb = e.size - 1
         ncat = len(catalogues)
@@ -377,35 +408,32 @@ class PairCounter:
             arr[k] = cc.c
         counts = np.zeros(ncat * nb * int(npi), dtype=np.uint64)
         wsum = np.zeros(ncat * nb * int(npi), dtype=np.float64) if weights is not None else None
+        rv = np.zeros(ncat * nb * int(npi), dtype=np.float64) if ravg else None
         st = self._lib.count_pairs_rppi_batch_ex(
             self._ctx, ctypes.cast(arr, ctypes.c_void_p), ncat, e.ctypes.data, nb, float(pimax),
             int(npi), float(boxsize), self._prec(precision), counts.ctypes.data,
-            None if wsum is None else wsum.ctypes.data, self._opts(options))
+            None if wsum is None else wsum.ctypes.data, self._opts(options, weight_type, rv))
         self._check(st)
-        counts = counts.reshape(ncat, nb, int(npi))
-        if wsum is not None:
-            wsum = wsum.reshape(ncat, nb, int(npi))
-        return counts, wsum
+        return self._result(counts, wsum, rv, (ncat, nb, int(npi)))
 
     def count_theta(self, ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
-                    precision="fp64", w1=None, w2=None, options=None, unit_vectors=None):
+                    precision="fp64", w1=None, w2=None, options=None, unit_vectors=None,
+                    weight_type=None, ravg=False):
         """DD(theta)/DR(theta) from RA/DEC in degrees (or unit vectors when
-        ``unit_vectors=(v1, v2)`` is given)."""
+        ``unit_vectors=(v1, v2)`` is given), plus the mean angle per bin in
+        degrees when ``ravg``."""
         e = np.ascontiguousarray(theta_edges_deg, dtype=np.float64)
         nb = e.size - 1
+        rv = np.zeros(nb, dtype=np.float64) if ravg else None
         if unit_vectors is not None:
             v1, v2 = unit_vectors
             c1 = _Cat(v1, w1)
             c2 = None if v2 is None else _Cat(v2, w2)
-            opt = default_options(theta_unit_vectors=1)
-            if options:
-                for k, v in (options.items() if isinstance(options, dict) else []):
-                    setattr(opt, k, int(v))
-            optp = ctypes.byref(opt)
+            optp = self._opts(options, weight_type, rv, theta_unit_vectors=1)
         else:
             c1 = _Cat((ra1, dec1), w1, two_columns=True)
             c2 = None if ra2 is None else _Cat((ra2, dec2), w2, two_columns=True)
-            optp = self._opts(options)
+            optp = self._opts(options, weight_type, rv)
         counts = np.zeros(nb, dtype=np.uint64)
         wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
         st = self._lib.count_pairs_theta_ex(
@@ -413,7 +441,7 @@ class PairCounter:
             e.ctypes.data, nb, self._prec(precision), counts.ctypes.data,
             None if wsum is None else wsum.ctypes.data, optp)
         self._check(st)
-        return counts, wsum
+        return self._result(counts, wsum, rv, (nb,))
 
     def stats(self) -> dict:
         s = cf_stats()

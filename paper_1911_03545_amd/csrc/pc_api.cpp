@@ -31,7 +31,7 @@ enum BufId {
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
-    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
+    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_RHIST, B_OUTR, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
     B_COUNT
 };
 
@@ -69,6 +69,7 @@ struct cf_ctx {
     size_t gpin_cap = 0;
     size_t g_misc = 0, g_out = 0, g_nout = 0;
     bool g_wsum = false;
+    bool g_ravg = false;
     cf_stats gstats;
     // autotuned (slices_per_reach, chunk) per workload class
     std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned;
@@ -430,9 +431,17 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     } else {
         npi = 1;
     }
-    const bool weighted = d1->w != nullptr;
+    const bool user_w = d1->w != nullptr;
+    if (opt.weight_type != CF_WEIGHT_PRODUCT && opt.weight_type != CF_WEIGHT_SUM)
+        return fail(c, CF_EINVAL, "unknown weight_type %d", opt.weight_type);
+    if (opt.weight_type != CF_WEIGHT_PRODUCT && !user_w)
+        return fail(c, CF_EINVAL, "summed pair weights need weights");
+    const bool want_ravg = opt.ravg != nullptr;
+    // the sweep carries weights when the caller gives them or asks for the
+    // mean separation (unit weights then, whose sums are the counts)
+    const bool weighted = user_w || want_ravg;
     const int64_t nbt = (int64_t)nb * npi;
-    if (nbt > (weighted ? PC_MAX_BINS_TOTAL / 2 : PC_MAX_BINS_TOTAL))
+    if (nbt > PC_MAX_BINS_TOTAL / (want_ravg ? 3 : (weighted ? 2 : 1)))
         return fail(c, CF_EINVAL, "too many output bins (%lld)", (long long)nbt);
     if (!isfinite(boxsize) && boxsize > 0.0)
         return fail(c, CF_EINVAL, "boxsize must be finite");
@@ -477,11 +486,15 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
             HIPCHK(hipMemsetAsync(counts, 0, sizeof(uint64_t) * nout, c->stream));
             if (wsum)
                 HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double) * nout, c->stream));
+            if (want_ravg)
+                HIPCHK(hipMemsetAsync(opt.ravg, 0, sizeof(double) * nout, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
         } else {
             memset(counts, 0, sizeof(uint64_t) * nout);
             if (wsum)
                 memset(wsum, 0, sizeof(double) * nout);
+            if (want_ravg)
+                memset(opt.ravg, 0, sizeof(double) * nout);
         }
         return CF_OK;
     }
@@ -495,7 +508,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     const size_t p_bins = p_cats2 + align256(sizeof(pc_cat));
     const size_t bins_cap = 256 * 1024 + 64 * (size_t)(nb + npi + 2);
     const size_t p_out = p_bins + bins_cap;
-    ctl.pin_need = p_out + (sizeof(uint64_t) + sizeof(double)) * nout;
+    ctl.pin_need = p_out + (sizeof(uint64_t) + 2 * sizeof(double)) * nout;
     ctl.p_misc = p_misc;
     ctl.p_out = p_out;
     char *pin;
@@ -702,6 +715,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         (st2 = ensure(c, B_WHIST, sizeof(double) * nout)) ||
         (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nout)) ||
         (st2 = ensure(c, B_OUTW, sizeof(double) * nout)) ||
+        (want_ravg && (st2 = ensure(c, B_RHIST, sizeof(double) * nout))) ||
+        (want_ravg && (st2 = ensure(c, B_OUTR, sizeof(double) * nout))) ||
         (st2 = ensure(c, B_WSQ, sizeof(double) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CTRS, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE)))
         return st2;
@@ -710,6 +725,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     HIPCHK(pc::launch_zero(c->stream, c->buf[B_HIST].p, sizeof(unsigned long long) * nout));
     if (weighted)
         HIPCHK(pc::launch_zero(c->stream, c->buf[B_WHIST].p, sizeof(double) * nout));
+    if (want_ravg)
+        HIPCHK(pc::launch_zero(c->stream, c->buf[B_RHIST].p, sizeof(double) * nout));
     const char *bb = (const char *)c->buf[B_BINS].p;
     pc::SweepArgs a;
     memset(&a, 0, sizeof(a));
@@ -749,6 +766,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.tbl = (const uint16_t *)(bb + hb.lay.tbl);
     a.g_hist = dptr<unsigned long long>(c, B_HIST);
     a.g_whist = weighted ? dptr<double>(c, B_WHIST) : nullptr;
+    a.g_rhist = want_ravg ? dptr<double>(c, B_RHIST) : nullptr;
+    a.ravg = want_ravg ? (theta ? 2 : 1) : 0;
+    a.wtype = opt.weight_type;
+    a.sep_scale = 1.0 / g.fscale;
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
     a.nbt = (int32_t)nbt;
     a.slots = (int32_t)((nb + 2) * hb.hdr.row_w);
@@ -771,7 +792,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     while (copies > 1 && copies * a.rep_stride > PC_MAX_HIST_WAVE)
         copies /= 2;
     const int waves = pc::sweep_waves();
-    const int slot_bytes = 4 + (weighted ? 8 : 0);
+    const int slot_bytes = 4 + (weighted ? 8 : 0) + (want_ravg ? 8 : 0);
     while (priv && copies > 1 && waves * copies * a.rep_stride * slot_bytes > 28 * 1024)
         copies /= 2;
     a.copies = copies;
@@ -793,6 +814,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.o_hist = take(4 * sets * a.hist_stride);
     a.whist_stride = weighted ? (int32_t)(copies * a.rep_stride) : 0;
     a.o_whist = take(weighted ? 8 * sets * a.whist_stride : 0);
+    a.o_rhist = take(want_ravg ? 8 * sets * a.whist_stride : 0);
     a.lds_bytes = off;
     // static LDS of the sweep: the lookup table
     const int tbl_bytes = priv ? PC_TBL_PRIV_BYTES
@@ -801,7 +823,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "bin configuration needs too much LDS (%d bytes)", off);
 
     int per_cu = 0;
-    HIPCHK(pc::sweep_occupancy(metric, fp32, weighted, hb.hdr.tbl_wide != 0, copies == PC_WAVE,
+    const int wmode = weighted ? (want_ravg ? 2 : 1) : 0;
+    HIPCHK(pc::sweep_occupancy(metric, fp32, wmode, hb.hdr.tbl_wide != 0, copies == PC_WAVE,
                                priv, off, &per_cu));
     per_cu = std::max(per_cu, 1);
     int nwg = ctl.capture ? c->num_cu * per_cu
@@ -815,18 +838,26 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         wsq = dptr<double>(c, B_WSQ);
     unsigned long long *outc = opt.output_on_device ? (unsigned long long *)counts
                                                     : dptr<unsigned long long>(c, B_OUTC);
-    double *outw = wsum ? (opt.output_on_device ? wsum : dptr<double>(c, B_OUTW)) : nullptr;
+    double *outw = (wsum && user_w) ? (opt.output_on_device ? wsum : dptr<double>(c, B_OUTW))
+                                    : nullptr;
     record(c, timing, 4);
     if (n_items > 0)
-        HIPCHK(pc::launch_sweep(c->stream, metric, fp32, weighted, a, nwg));
+        HIPCHK(pc::launch_sweep(c->stream, metric, fp32, wmode, a, nwg));
     record(c, timing, 5);
     // ---- finalize ------------------------------------------------------------
     if (wsq) {
         HIPCHK(pc::launch_zero(c->stream, wsq, sizeof(double) * (size_t)ncat));
-        HIPCHK(pc::launch_wsq(c->stream, ncat, g.ncell, start1, dptr<double>(c, B_WD1), wsq));
+        HIPCHK(pc::launch_wsq(c->stream, ncat, g.ncell, start1, dptr<double>(c, B_WD1),
+                              opt.weight_type, wsq));
     }
+    double *outr = want_ravg ? (opt.output_on_device ? opt.ravg : dptr<double>(c, B_OUTR))
+                             : nullptr;
+    // without weights the weight sums are zero
+    if (wsum && !user_w && opt.output_on_device)
+        HIPCHK(pc::launch_zero(c->stream, wsum, sizeof(double) * nout));
     HIPCHK(pc::launch_finalize(c->stream, ncat, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero,
-                               cats1_dev, a.g_hist, a.g_whist, wsq, outc, outw));
+                               cats1_dev, a.g_hist, a.g_whist, a.g_rhist, wsq, outc, outw,
+                               outr));
     char *hp = pin + p_out;
     HIPCHK(hipMemcpyAsync(pin + p_misc, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
     if (!opt.output_on_device) {
@@ -835,6 +866,9 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         if (outw)
             HIPCHK(hipMemcpyAsync(hp + sizeof(uint64_t) * nout, outw, sizeof(double) * nout,
                                   hipMemcpyDeviceToHost, c->stream));
+        if (outr)
+            HIPCHK(hipMemcpyAsync(hp + (sizeof(uint64_t) + sizeof(double)) * nout, outr,
+                                  sizeof(double) * nout, hipMemcpyDeviceToHost, c->stream));
     }
     record(c, timing, 6);
     if (ctl.capture)
@@ -855,8 +889,13 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "non-finite weight");
     if (!opt.output_on_device) {
         memcpy(counts, hp, sizeof(uint64_t) * nout);
-        if (wsum)
+        if (wsum && user_w)
             memcpy(wsum, hp + sizeof(uint64_t) * nout, sizeof(double) * nout);
+        else if (wsum)
+            memset(wsum, 0, sizeof(double) * nout);
+        if (want_ravg)
+            memcpy(opt.ravg, hp + (sizeof(uint64_t) + sizeof(double)) * nout,
+                   sizeof(double) * nout);
     }
     unsigned long long cnd;
     memcpy(&cnd, hm + M_CAND, 8);
@@ -908,9 +947,15 @@ std::vector<char> call_key(int metric, bool theta, const cf_catalog *d1, int32_t
     key_add(k, &pimax, sizeof(pimax));
     key_add(k, &npi, sizeof(npi));
     key_add(k, &boxsize, sizeof(boxsize));
-    key_add(k, &opt, sizeof(opt));
-    const bool has_w = wsum != nullptr;
+    // host output arrays may change between replays (the results are copied
+    // out after each); device outputs are part of the graph
+    cf_options o = opt;
+    if (!opt.output_on_device)
+        o.ravg = nullptr;
+    key_add(k, &o, sizeof(o));
+    const bool has_w = wsum != nullptr, has_r = opt.ravg != nullptr;
     key_add(k, &has_w, sizeof(has_w));
+    key_add(k, &has_r, sizeof(has_r));
     if (opt.output_on_device) {
         key_add(k, &counts, sizeof(counts));
         key_add(k, &wsum, sizeof(wsum));
@@ -953,6 +998,11 @@ cf_status replay(cf_ctx *c, uint64_t *counts, double *wsum, const cf_options &op
         memcpy(counts, pin + c->g_out, sizeof(uint64_t) * c->g_nout);
         if (wsum && c->g_wsum)
             memcpy(wsum, pin + c->g_out + sizeof(uint64_t) * c->g_nout,
+                   sizeof(double) * c->g_nout);
+        else if (wsum)
+            memset(wsum, 0, sizeof(double) * c->g_nout);
+        if (opt.ravg && c->g_ravg)
+            memcpy(opt.ravg, pin + c->g_out + (sizeof(uint64_t) + sizeof(double)) * c->g_nout,
                    sizeof(double) * c->g_nout);
     }
     c->stats = c->gstats;
@@ -1023,7 +1073,8 @@ void record_graph(cf_ctx *c, std::vector<char> &&key, const RunCtl &eager, int m
         c->g_misc = ctl.p_misc;
         c->g_out = ctl.p_out;
         c->g_nout = (size_t)ncat * (size_t)nb * (size_t)(metric == PC_METRIC_RPPI ? npi : 1);
-        c->g_wsum = wsum != nullptr;
+        c->g_wsum = wsum != nullptr && d1->w != nullptr;
+        c->g_ravg = opt && opt->ravg != nullptr;
         c->gstats = keep;
         return;
     }

@@ -168,7 +168,8 @@ __global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid
                 fl |= PC_FLAG_RANGE;
             ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
         }
-        const double w = k.w ? ld(k.w, k.wf32, j) : 0.0;
+        // unit weights without weights (the mean-separation sums use them)
+        const double w = k.w ? ld(k.w, k.wf32, j) : 1.0;
         if (!isfinite(w))
             fl |= PC_FLAG_WEIGHT;
         const int cell = (int)(ci * g.ncell) + (ia[0] * g.n[1] + ia[1]) * g.n[2] + ia[2];

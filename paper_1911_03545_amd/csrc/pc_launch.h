@@ -30,6 +30,11 @@ struct SweepArgs {
     const uint16_t *tbl;
     unsigned long long *g_hist;
     double *g_whist;
+    double *g_rhist;       // sums of separation x pair weight (mean separation), or NULL
+    int32_t ravg;          // 0: no mean separation; 1: distance sqrt(s);
+                           // 2: angle in degrees of a squared chord s
+    int32_t wtype;         // pair weight: 0 product, 1 sum
+    double sep_scale;      // float32 pass: length per float32 coordinate unit (2^-m)
     unsigned *rq_count;   // float32 pass: pairs re-evaluated in binary64
     int32_t priv;       // per-wave private replicas, flushed per catalogue (batches)
     int32_t copies;     // LDS histogram replicas per wave (power of two; 64 = one per
@@ -38,7 +43,7 @@ struct SweepArgs {
     int32_t slots;      // slots per replica: (nb + 2) * npi
     int32_t rep_stride; // distance between replicas (slots rounded up to odd)
     // dynamic LDS layout (bytes)
-    int32_t o_tbl, o_lo, o_hi, o_E, o_q, o_hist, o_whist;
+    int32_t o_tbl, o_lo, o_hi, o_E, o_q, o_hist, o_whist, o_rhist;
     int32_t hist_stride;   // uint32 slots of all replicas (one set per workgroup)
     int32_t whist_stride;  // double slots of all replicas
     int32_t lds_bytes;
@@ -82,19 +87,25 @@ hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nbloc
                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
                             const int32_t *cell1_sorted, int autocorr, int chunk,
                             const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags);
-hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted,
-                        const SweepArgs &a, int nwg);
-// per-catalogue sum of w^2 over the cell-ordered weights of a side
+// wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums
+hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, int wmode, const SweepArgs &a,
+                        int nwg);
+// per-catalogue sum of the self-pair weights (w^2, or 2w for summed pair
+// weights) over the cell-ordered weights of a side
 hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
-                      const double *w, double *out);
+                      const double *w, int wtype, double *out);
+// counts (and weight sums, mean separations) of every catalogue: doubling
+// and self-pairs of autocorrelations; the mean separation is the separation
+// sum over the weight sum
 hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
-                           const double *g_whist, const double *wsq,
-                           unsigned long long *out_counts, double *out_wsum);
+                           const double *g_whist, const double *g_rhist, const double *wsq,
+                           unsigned long long *out_counts, double *out_wsum,
+                           double *out_ravg);
 // resident sweep workgroups per CU for a dynamic LDS size
 // waves per sweep workgroup
 int sweep_waves();
-hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc, bool priv,
+hipError_t sweep_occupancy(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv,
                            int lds_bytes, int *per_cu);
 
 }  // namespace pc

@@ -138,6 +138,67 @@ struct Lds {
     lds_f64wp whist;
 };
 
+// Weight of a pair (section 2.1's weight_func): 0 product, 1 sum.
+__device__ __forceinline__ double pair_weight(int wtype, double a, double b)
+{
+    return wtype == 1 ? a + b : a * b;
+}
+
+// A lane's side of the pair weight as one fused multiply-add,
+// w_ij = fma(a, w_j, b): (w_i, 0) for products, (1, w_i) for sums.  Either
+// form rounds once, so it equals w_i * w_j or w_i + w_j.
+struct LaneW {
+    double a, b;
+};
+
+__device__ __forceinline__ LaneW lane_weight(int wtype, double wi)
+{
+    return wtype == 1 ? LaneW{1.0, wi} : LaneW{wi, 0.0};
+}
+
+// Separation reported by the mean-separation output, from the squared
+// separation s: the distance (kind 1) or the angle in degrees of a squared
+// chord (kind 2).  Binary64 pass: from the binary64 s.
+__device__ __forceinline__ double sep_value(int kind, double s)
+{
+    const double c = sqrt(s);
+    return kind == 1 ? c : (2.0 * asin(0.5 * c)) * (180.0 / M_PI);
+}
+
+// Float32 pass: from the float32 s of the scaled coordinates (one float32
+// unit is `scale` in length).
+__device__ __forceinline__ double sep_value_f32(int kind, float s, double scale)
+{
+    const float c = sqrtf(s) * (float)scale;   // scale is a power of two
+    if (kind == 1)
+        return (double)c;
+    return (double)(2.0f * asinf(0.5f * c)) * (180.0 / M_PI);
+}
+
+// Pair weight and (W == 2) mean-separation sums of one pair in range.  The
+// separation sums live in a second set of replicas with the layout of the
+// weight sums, (o_rhist - o_whist) / 8 doubles further on.
+template <int W>
+__device__ __forceinline__ void add_weight_f32(const SweepArgs &a, lds_f64wp whb, int slot,
+                                               LaneW wi, double wj, float s, int kind)
+{
+    const double wp = fma(wi.a, wj, wi.b);
+    lds_add(&whb[slot], wp);
+    if (W == 2)
+        lds_add(&whb[slot + ((a.o_rhist - a.o_whist) >> 3)],
+                wp * sep_value_f32(kind, s, a.sep_scale));
+}
+
+template <int W>
+__device__ __forceinline__ void add_weight_f64(const SweepArgs &a, lds_f64wp whb, int slot,
+                                               LaneW wi, double wj, double s, int kind)
+{
+    const double wp = fma(wi.a, wj, wi.b);
+    lds_add(&whb[slot], wp);
+    if (W == 2)
+        lds_add(&whb[slot + ((a.o_rhist - a.o_whist) >> 3)], wp * sep_value(kind, s));
+}
+
 // Table entry of a value (float bits already reduced to the key).
 // Table entries as signed values: flagged cells read negative (byte entries
 // sign-extend 0x80 | edge, 16-bit entries have 0x8000 or 0x4000 set and are
@@ -268,10 +329,10 @@ __device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int 
 // unweighted 1-D statistics.
 // MASK: the item's last, partial chunk; pairs k >= rem are padding (their
 // loads repeat the item's last point) and are sent out of range.
-template <int M, bool W, bool TRI, bool T16, bool UNC, int CH, bool MASK = false>
+template <int M, int W, bool TRI, bool T16, bool UNC, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                           lds_f64wp whb, float ax, float ay, float az,
-                                          double wi, int i, const float *xs, const float *ys,
+                                          LaneW wi, int i, const float *xs, const float *ys,
                                           const float *zs, const double *ws, int j,
                                           unsigned dcode, unsigned &rechecks, int rem = CH)
 {
@@ -344,7 +405,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         }
         lds_add(&hb[slot], 1u);
         if (W)
-            lds_add(&whb[slot], wi * ws[k]);
+            add_weight_f32<W>(a, whb, slot, wi, ws[k], s[k], a.ravg);
     }
 }
 
@@ -363,10 +424,10 @@ __device__ __forceinline__ int pi_fast(float pz, float inv_dpi, float tau, int n
 }
 
 // ---- binary64 chunk ------------------------------------------------------
-template <int M, bool W, bool TRI, bool OFS, bool T16, bool UNC, int CH, bool MASK = false>
+template <int M, int W, bool TRI, bool OFS, bool T16, bool UNC, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                           lds_f64wp whb, double xi, double yi, double zi,
-                                          double Dx, double Dy, double Dz, double wi, int i,
+                                          double Dx, double Dy, double Dz, LaneW wi, int i,
                                           const double *xs, const double *ys, const double *zs,
                                           const double *ws, int j, int rem = CH)
 {
@@ -430,7 +491,8 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
         }
         lds_add(&hb[slot], 1u);
         if (W)
-            lds_add(&whb[slot], wi * ws[k]);
+            add_weight_f64<W>(a, whb, slot, wi, ws[k], s[k],
+                              M == PC_METRIC_RPPI ? 1 : a.ravg);
     }
 }
 
@@ -450,10 +512,10 @@ __device__ __forceinline__ unsigned absdiff_plus(unsigned a, unsigned b, unsigne
     return (max(a, b) - min(a, b)) + c;
 }
 
-template <bool W, bool TRI, bool T16, int CH, bool MASK = false>
+template <int W, bool TRI, bool T16, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                                  lds_f64wp whb, float ax, float ay,
-                                                 unsigned azq, double wi, int i,
+                                                 unsigned azq, LaneW wi, int i,
                                                  const float *xs, const float *ys,
                                                  const float *zs, const double *ws, int j,
                                                  unsigned dcode, unsigned &rechecks,
@@ -527,13 +589,13 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
             const unsigned off = __umul24((unsigned)er[k], rw4) + ((u[k] >> sh) << 2) + 4u;
             lds_add((lds_u32p)((LDS char *)hb + off), 1u);
             if (W)
-                lds_add(&whb[off >> 2], wi * ws[k]);
+                add_weight_f32<W>(a, whb, (int)(off >> 2), wi, ws[k], s[k], 1);
         }
     }
 }
 
 // ---- item loops ----------------------------------------------------------
-template <int M, bool W, bool TRI, bool T16, bool UNC>
+template <int M, int W, bool TRI, bool T16, bool UNC>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
                                          unsigned dcode, unsigned &rechecks)
@@ -546,7 +608,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     // inactive lanes sit far away: their separations overflow to +inf
     const float ax = act ? a.X1[i] + Dx : 3.0e30f;
     const float ay = act ? a.Y1[i] + Dy : 3.0e30f;
-    const double wi = (W && act) ? a.w1[i] : 0.0;
+    const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
     // second-catalogue points are wave-uniform: read them through the scalar
     // cache (the arrays are not written during the sweep)
     const kf32p X2 = (kf32p)a.X2, Y2 = (kf32p)a.Y2, Z2 = (kf32p)a.Z2;
@@ -620,7 +682,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     }
 }
 
-template <int M, bool W, bool TRI, bool OFS, bool T16, bool UNC>
+template <int M, int W, bool TRI, bool OFS, bool T16, bool UNC>
 __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
                                          unsigned dcode)
@@ -630,7 +692,7 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
     const double xi = act ? a.x1[i] : 1.0e300;
     const double yi = act ? a.y1[i] : 1.0e300;
     const double zi = act ? a.z1[i] : 1.0e300;
-    const double wi = (W && act) ? a.w1[i] : 0.0;
+    const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
     const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2, w2 = (kf64p)a.w2;
     constexpr int CH = W ? 4 : 8;
     int j = j0;
@@ -699,19 +761,27 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
     const int npi = a.B.npi, rw = a.B.row_w, c0 = a.B.col0;
     unsigned long long *gh = a.g_hist + (size_t)cat * a.nbt;
     double *gw = W ? a.g_whist + (size_t)cat * a.nbt : nullptr;
+    // mean-separation sums: a second set of replicas after the weight sums
+    const bool R = W && a.ravg;
+    const int roff = (a.o_rhist - a.o_whist) >> 3;
+    double *gr = R ? a.g_rhist + (size_t)cat * a.nbt : nullptr;
     for (int b = first; b < a.nbt; b += step) {
         const int slot = (b / npi + 1) * rw + b % npi + c0;
         unsigned long long c = 0;
-        double w = 0.0;
+        double w = 0.0, rs = 0.0;
         for (int r = 0; r < a.copies; r++) {
             c += lds_take(&L.hist[r * a.rep_stride + slot]);
             if (W)
                 w += lds_take(&L.whist[r * a.rep_stride + slot]);
+            if (R)
+                rs += lds_take(&L.whist[r * a.rep_stride + slot + roff]);
         }
         if (c)
             atomicAdd(&gh[b], c);
         if (W && w != 0.0)
             atomicAdd(&gw[b], w);
+        if (R && rs != 0.0)
+            atomicAdd(&gr[b], rs);
     }
     for (int t = first; t < a.copies * a.slots; t += step) {
         const int r = t / a.slots, sl = t % a.slots;
@@ -721,13 +791,15 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         lds_take(&L.hist[r * a.rep_stride + sl]);
         if (W)
             lds_take(&L.whist[r * a.rep_stride + sl]);
+        if (R)
+            lds_take(&L.whist[r * a.rep_stride + sl + roff]);
     }
 }
 
 // PRIV: every wave owns its histogram replicas and flushes them whenever the
 // catalogue of its work items changes (batched calls); otherwise the
 // workgroup's waves share one set of replicas for a single catalogue.
-template <int M, bool P32, bool W, bool T16, bool UNC, bool PRIV>
+template <int M, bool P32, int W, bool T16, bool UNC, bool PRIV>
 __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
 {
     // the lookup table has a fixed place so its address folds into the
@@ -771,8 +843,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         for (int k = tid; k < sets * a.hist_stride; k += kSweepThreads)
             hist[k] = 0u;
         if (W) {
+            // weight sums, then (mean separation) the separation sums
             LDS double *wh = (LDS double *)(sm + a.o_whist);
-            for (int k = tid; k < sets * a.whist_stride; k += kSweepThreads)
+            const int nw = (a.ravg ? (a.o_rhist - a.o_whist) >> 3 : 0) + sets * a.whist_stride;
+            for (int k = tid; k < nw; k += kSweepThreads)
                 wh[k] = 0.0;
         }
     }
@@ -870,17 +944,19 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     }
 }
 
-// Sum of w^2 of every catalogue of a side (for its self-pairs): the weights
-// are in cell order, so catalogue c owns [start[c * ncell], start[(c + 1) *
-// ncell]).  blockIdx.y is the catalogue.
-__global__ void k_wsq(int64_t ncell, const int32_t *start, const double *w, double *out)
+// Sum of the self-pair weights of every catalogue of a side (w^2 for
+// product pair weights, w + w for summed ones): the weights are in cell
+// order, so catalogue c owns [start[c * ncell], start[(c + 1) * ncell]).
+// blockIdx.y is the catalogue.
+__global__ void k_wsq(int64_t ncell, const int32_t *start, const double *w, int wtype,
+                      double *out)
 {
     const int c = blockIdx.y;
     const int64_t a = start[c * ncell], b = start[(c + 1) * ncell];
     double s = 0.0;
     for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
          i += (int64_t)gridDim.x * blockDim.x)
-        s += w[i] * w[i];
+        s += pair_weight(wtype, w[i], w[i]);
     __shared__ double sm[256];
     sm[threadIdx.x] = s;
     __syncthreads();
@@ -894,11 +970,13 @@ __global__ void k_wsq(int64_t ncell, const int32_t *start, const double *w, doub
 }
 
 // Appendix B: autocorrelation counts are doubled (ordered pairs) and the
-// N self-pairs of each catalogue join its bin 0 when the first edge is zero.
+// N self-pairs of each catalogue join its bin 0 when the first edge is zero
+// (with their weights, and separation 0).  The mean separation is the
+// separation sum over the weight sum (doubling cancels).
 __global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
-                           const double *g_whist, const double *wsq,
-                           unsigned long long *out_counts, double *out_wsum)
+                           const double *g_whist, const double *g_rhist, const double *wsq,
+                           unsigned long long *out_counts, double *out_wsum, double *out_ravg)
 {
     const int64_t total = (int64_t)ncat * nbt;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -918,10 +996,14 @@ __global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
         out_counts[t] = v;
         if (out_wsum)
             out_wsum[t] = w;
+        if (out_ravg) {
+            const double r = autocorr ? 2.0 * g_rhist[t] : g_rhist[t];
+            out_ravg[t] = w != 0.0 ? r / w : 0.0;
+        }
     }
 }
 
-template <int M, bool P32, bool W>
+template <int M, bool P32, int W>
 const void *sweep_fn(bool t16, bool unc, bool priv)
 {
     if (priv)
@@ -929,35 +1011,39 @@ const void *sweep_fn(bool t16, bool unc, bool priv)
                    : (const void *)&k_sweep<M, P32, W, false, false, true>;
     if (t16)
         return (const void *)&k_sweep<M, P32, W, true, false, false>;
-    if (unc && M == PC_METRIC_R && !W)
-        return (const void *)&k_sweep<M, P32, W, false, (M == PC_METRIC_R && !W), false>;
+    if (unc && M == PC_METRIC_R && W == 0)
+        return (const void *)&k_sweep<M, P32, W, false, (M == PC_METRIC_R && W == 0), false>;
     return (const void *)&k_sweep<M, P32, W, false, false, false>;
 }
 
-const void *sweep_ptr(int metric, bool fp32, bool weighted, bool t16, bool unc, bool priv)
+template <int M, bool P32>
+const void *sweep_fn_w(int wmode, bool t16, bool unc, bool priv)
 {
-    if (metric == PC_METRIC_R) {
-        if (fp32)
-            return weighted ? sweep_fn<PC_METRIC_R, true, true>(t16, unc, priv)
-                            : sweep_fn<PC_METRIC_R, true, false>(t16, unc, priv);
-        return weighted ? sweep_fn<PC_METRIC_R, false, true>(t16, unc, priv)
-                        : sweep_fn<PC_METRIC_R, false, false>(t16, unc, priv);
-    }
-    if (fp32)
-        return weighted ? sweep_fn<PC_METRIC_RPPI, true, true>(t16, unc, priv)
-                        : sweep_fn<PC_METRIC_RPPI, true, false>(t16, unc, priv);
-    return weighted ? sweep_fn<PC_METRIC_RPPI, false, true>(t16, unc, priv)
-                    : sweep_fn<PC_METRIC_RPPI, false, false>(t16, unc, priv);
+    if (wmode == 2)
+        return sweep_fn<M, P32, 2>(t16, unc, priv);
+    if (wmode == 1)
+        return sweep_fn<M, P32, 1>(t16, unc, priv);
+    return sweep_fn<M, P32, 0>(t16, unc, priv);
+}
+
+// wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums
+const void *sweep_ptr(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv)
+{
+    if (metric == PC_METRIC_R)
+        return fp32 ? sweep_fn_w<PC_METRIC_R, true>(wmode, t16, unc, priv)
+                    : sweep_fn_w<PC_METRIC_R, false>(wmode, t16, unc, priv);
+    return fp32 ? sweep_fn_w<PC_METRIC_RPPI, true>(wmode, t16, unc, priv)
+                : sweep_fn_w<PC_METRIC_RPPI, false>(wmode, t16, unc, priv);
 }
 
 }  // namespace
 
-hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, const SweepArgs &a,
+hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, int wmode, const SweepArgs &a,
                         int nwg)
 {
     SweepArgs copy = a;
     void *args[] = {&copy};
-    const void *fn = sweep_ptr(metric, fp32, weighted, a.B.tbl_wide != 0, a.copies == PC_WAVE,
+    const void *fn = sweep_ptr(metric, fp32, wmode, a.B.tbl_wide != 0, a.copies == PC_WAVE,
                                a.priv != 0);
     if (a.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -970,10 +1056,10 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, bool weighted, con
 
 int sweep_waves() { return kWaves; }
 
-hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool unc, bool priv,
+hipError_t sweep_occupancy(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv,
                            int lds_bytes, int *per_cu)
 {
-    const void *fn = sweep_ptr(metric, fp32, weighted, t16, unc, priv);
+    const void *fn = sweep_ptr(metric, fp32, wmode, t16, unc, priv);
     if (lds_bytes > 64 * 1024) {
         hipError_t e =
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -985,22 +1071,25 @@ hipError_t sweep_occupancy(int metric, bool fp32, bool weighted, bool t16, bool 
 }
 
 hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
-                      const double *w, double *out)
+                      const double *w, int wtype, double *out)
 {
-    hipLaunchKernelGGL(k_wsq, dim3(64, (unsigned)ncat), dim3(256), 0, s, ncell, start, w, out);
+    hipLaunchKernelGGL(k_wsq, dim3(64, (unsigned)ncat), dim3(256), 0, s, ncell, start, w, wtype,
+                       out);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
-                           const double *g_whist, const double *wsq,
-                           unsigned long long *out_counts, double *out_wsum)
+                           const double *g_whist, const double *g_rhist, const double *wsq,
+                           unsigned long long *out_counts, double *out_wsum,
+                           double *out_ravg)
 {
     const int64_t total = (int64_t)ncat * nbt;
     int64_t g = (total + 255) / 256;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(256), 0, s, ncat, nbt, autocorr,
-                       e0_zero, cats, g_hist, g_whist, wsq, out_counts, out_wsum);
+                       e0_zero, cats, g_hist, g_whist, g_rhist, wsq, out_counts, out_wsum,
+                       out_ravg);
     return hipGetLastError();
 }
 

@@ -132,3 +132,14 @@ def test_fp32_bands_cover_emulated_error(lib):
         above = s32 > hi[k]
         assert np.all(s64[below] < E[k])
         assert np.all(s64[above] > E[k])
+
+
+def test_options_layout_matches_library(lib):
+    """The library's cf_default_options fills struct_size with its own
+    sizeof(cf_options); the Python mirror must agree, with the output
+    pointer last and 8-byte aligned."""
+    o = pc.cf_options()
+    lib.cf_default_options(ctypes.byref(o))
+    assert o.struct_size == ctypes.sizeof(pc.cf_options)
+    assert pc.cf_options.ravg.offset == 64 and ctypes.sizeof(pc.cf_options) == 72
+    assert o.weight_type == pc.CF_WEIGHT_PRODUCT and not o.ravg

@@ -95,6 +95,29 @@ def test_rppi_n1e6(pc, olib, box420, dtype):
     assert (got == want).all()
 
 
+def test_r_ravg_n1e6(pc, olib, box420):
+    """Mean separation per bin at full size: sampled cross means against the
+    oracle (binary64: 1e-12 relative; float32: the float32 rounding bound,
+    10 u C + 8 u r with C = 420), and the full autocorrelation's float32
+    means within that bound of the binary64 ones."""
+    say("ravg r N=1e6 L=420")
+    u = 2.0 ** -24
+    pts = box420
+    e = synth.log_edges(0.1, 25.0, 20)
+    a32, _, r32 = pc.count_r(pts, None, e, 420.0, "fp32", ravg=True)
+    a64, _, r64 = pc.count_r(pts, None, e, 420.0, "fp64", ravg=True)
+    assert (a32 == a64).all()
+    assert np.all(np.abs(r32 - r64) <= 2 * (10 * u * 420.0 + 8 * u * r64))
+    s = pts[sample(pts.shape[0], NSAMPLE, 17)]
+    want, _, wr = oracle.count_r(s, pts, e, 420.0, lib=olib, ravg=True)
+    got, _, gr = pc.count_r(s, pts, e, 420.0, "fp64", ravg=True)
+    assert (got == want).all()
+    check_w(gr, wr)
+    got, _, gr = pc.count_r(s, pts, e, 420.0, "fp32", ravg=True)
+    assert (got == want).all()
+    assert np.all(np.abs(gr - wr) <= 10 * u * 420.0 + 8 * u * wr)
+
+
 # ------------------------------------------- 4 x 10^6 weighted, L = 1100
 @pytest.fixture(scope="module")
 def box1100():
