@@ -69,6 +69,12 @@ def _bind(lib):
                                           ctypes.c_int, dp, i32, up, dp,
                                           ctypes.c_int, dp, ctypes.c_int]
     lib.oracle_count_theta_ex.restype = ctypes.c_int
+    lib.oracle_count_rppi_mocks.argtypes = [i64, dp, dp, dp, dp, i64, dp, dp, dp,
+                                            dp, ctypes.c_int, dp, i32, dbl, i32,
+                                            up, dp, ctypes.c_int, dp, ctypes.c_int]
+    lib.oracle_count_rppi_mocks.restype = ctypes.c_int
+    lib.oracle_sky_to_cartesian.argtypes = [i64, dp, dp, dp, dp, dp, dp]
+    lib.oracle_sky_to_cartesian.restype = ctypes.c_int
     lib.oracle_radec_to_unit.argtypes = [i64, dp, dp, dp, dp, dp]
     lib.oracle_radec_to_unit.restype = ctypes.c_int
     lib.oracle_theta_chord_edges.argtypes = [i32, dp, dp]
@@ -210,6 +216,48 @@ def count_theta(ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
                                    int(nthreads))
     _check(rc, "oracle_count_theta")
     return (counts, wsum, rv) if ravg else (counts, wsum)
+
+
+def count_rppi_mocks(d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
+                     w1=None, w2=None, nthreads: int = 0, lib=None,
+                     weight_type: str = "product", ravg: bool = False):
+    """On-sky DD(rp, pi) (line of sight through each pair's midpoint) of
+    Cartesian positions (n, 3) from :func:`sky_to_cartesian`."""
+    lib = lib or load()
+    rp_edges = _f64(rp_edges)
+    nb = rp_edges.size - 1
+    x1, y1, z1 = _xyz(d1)
+    auto = d2 is None
+    x2, y2, z2 = (x1, y1, z1) if auto else _xyz(d2)
+    ww1 = None if w1 is None else _f64(w1)
+    ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
+    counts = np.zeros(nb * npi, dtype=np.uint64)
+    wsum = np.zeros(nb * npi, dtype=np.float64) if w1 is not None else None
+    rv = np.zeros(nb * npi, dtype=np.float64) if ravg else None
+    rc = lib.oracle_count_rppi_mocks(x1.size, _ptr(x1), _ptr(y1), _ptr(z1),
+                                     _ptr(ww1), x2.size, _ptr(x2), _ptr(y2),
+                                     _ptr(z2), _ptr(ww2), int(auto), _ptr(rp_edges),
+                                     nb, float(pimax), int(npi), counts.ctypes.data,
+                                     _ptr(wsum), _wtype(weight_type), _ptr(rv),
+                                     int(nthreads))
+    _check(rc, "oracle_count_rppi_mocks")
+    counts = counts.reshape(nb, npi)
+    if wsum is not None:
+        wsum = wsum.reshape(nb, npi)
+    if ravg:
+        return counts, wsum, rv.reshape(nb, npi)
+    return counts, wsum
+
+
+def sky_to_cartesian(ra, dec, dist, lib=None):
+    """(n, 3) positions D u from RA/DEC in degrees and distances D."""
+    lib = lib or load()
+    a, d, r = _f64(ra), _f64(dec), _f64(dist)
+    out = np.zeros((3, a.size), dtype=np.float64)
+    rc = lib.oracle_sky_to_cartesian(a.size, _ptr(a), _ptr(d), _ptr(r), out[0].ctypes.data,
+                                     out[1].ctypes.data, out[2].ctypes.data)
+    _check(rc, "oracle_sky_to_cartesian")
+    return np.ascontiguousarray(out.T)
 
 
 def radec_to_unit(ra, dec, lib=None):

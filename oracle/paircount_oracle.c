@@ -30,6 +30,16 @@
  *   * 3-D separation (Appendix A, eq. for r^2): s = (dx*dx + dy*dy) + dz*dz;
  *   * rp^2 = dx*dx + dy*dy and pi = |dz| with z the line of sight
  *     (Appendix A, Cartesian volumes);
+ *   * on-sky (rp, pi) ("mocks", Appendix A, spherical volumes, after Fisher et
+ *     al. 1994): positions v = D u with u the unit vector of (RA, DEC) below
+ *     and D the line-of-sight distance; s = v1 - v2 and the line of sight
+ *     l = (v1 + v2) / 2, evaluated as L = v1 + v2 (the factor 1/2 cancels
+ *     exactly in pi):
+ *         sl = (sx*Lx + sy*Ly) + sz*Lz,  LL = (Lx*Lx + Ly*Ly) + Lz*Lz,
+ *         ss = (sx*sx + sy*sy) + sz*sz,
+ *         pi = |sl| / sqrt(LL)   (0 when LL == 0: both points at the observer),
+ *         rp^2 = max(ss - pi*pi, 0)   (rounding cannot make it negative);
+ *     bins as for the Cartesian (rp, pi) statistic; never periodic;
  *   * angular separations use unit vectors v = (cos d cos a, cos d sin a, sin d)
  *     and the squared chord |v1 - v2|^2 with edges c_k = 2 sin(theta_k / 2);
  *     this is the cos(theta) = v1.v2 relation of Appendix A rewritten as a
@@ -224,6 +234,7 @@ static double pair_weight(int wtype, double a, double b)
 /* One engine for the 1-D (r or chord) and the 2-D (rp, pi) statistics.
    mode 0: s = (dx*dx + dy*dy) + dz*dz, bins k over E
    mode 1: s = dx*dx + dy*dy, pi = |dz|, bins k*npi + p over E x q
+   mode 2: s = rp^2 and pi of the on-sky convention, bins as mode 1
    wtype: pair weight (0 product, 1 sum); ravg (optional): mean separation
    per bin, angle != 0 reporting angles from squared chords.                */
 static int count_engine(int mode,
@@ -256,11 +267,13 @@ static int count_engine(int mode,
     if (wtype != 0 && (wtype != 1 || !weighted))
         return ORACLE_EINVAL;
     const int want_r = (ravg != NULL);
-    const int nout = (mode == 1) ? nbins * npi : nbins;
+    const int nout = (mode >= 1) ? nbins * npi : nbins;
     const int periodic = boxsize > 0.0;
+    if (mode == 2 && periodic)
+        return ORACLE_EINVAL;
     const double L = boxsize;
     const double half = 0.5 * boxsize;
-    const double pimax = (mode == 1) ? q[npi] : 0.0;
+    const double pimax = (mode >= 1) ? q[npi] : 0.0;
 
     double *E = (double *)malloc(sizeof(double) * (size_t)(nbins + 1));
     if (!E)
@@ -320,8 +333,18 @@ static int count_engine(int mode,
                         k--;
                     bin = k;
                 } else {
-                    s = dx * dx + dy * dy;
-                    double pi = fabs(dz);
+                    double pi;
+                    if (mode == 1) {
+                        s = dx * dx + dy * dy;
+                        pi = fabs(dz);
+                    } else {
+                        const double lx = xi + x2[j], ly = yi + y2[j], lz = zi + z2[j];
+                        const double sl = (dx * lx + dy * ly) + dz * lz;
+                        const double ll = (lx * lx + ly * ly) + lz * lz;
+                        const double ss = (dx * dx + dy * dy) + dz * dz;
+                        pi = ll > 0.0 ? fabs(sl) / sqrt(ll) : 0.0;
+                        s = fmax(ss - pi * pi, 0.0);
+                    }
                     if (s < E[0] || s >= E[nbins] || pi >= pimax)
                         continue;
                     int k = nbins - 1;
@@ -475,6 +498,32 @@ int oracle_count_rppi(int64_t n1, const double *x1, const double *y1,
                                 counts, wsum, 0, NULL, nthreads);
 }
 
+/* DD(rp, pi) of on-sky positions (mocks): Cartesian positions v = D u from
+   oracle_sky_to_cartesian; counts[k * npi + p]; the mean separation is the
+   mean rp per bin. */
+int oracle_count_rppi_mocks(int64_t n1, const double *x1, const double *y1,
+                            const double *z1, const double *w1,
+                            int64_t n2, const double *x2, const double *y2,
+                            const double *z2, const double *w2,
+                            int autocorr, const double *rp_edges, int32_t nrp,
+                            double pimax, int32_t npi, uint64_t *counts,
+                            double *wsum, int wtype, double *ravg,
+                            int nthreads)
+{
+    if (npi < 1)
+        return ORACLE_EINVAL;
+    double *q = (double *)malloc(sizeof(double) * (size_t)(npi + 1));
+    if (!q)
+        return ORACLE_ENOMEM;
+    int rc = oracle_pi_edges(pimax, npi, q);
+    if (rc == ORACLE_OK)
+        rc = count_engine(2, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2,
+                          autocorr, rp_edges, nrp, q, npi, 0.0, counts,
+                          wsum, wtype, 0, ravg, nthreads);
+    free(q);
+    return rc;
+}
+
 /* RA/DEC in degrees -> unit vectors (binary64, host libm). */
 int oracle_radec_to_unit(int64_t n, const double *ra, const double *dec,
                          double *x, double *y, double *z)
@@ -490,6 +539,24 @@ int oracle_radec_to_unit(int64_t n, const double *ra, const double *dec,
         x[i] = cd * cos(a);
         y[i] = cd * sin(a);
         z[i] = sin(d);
+    }
+    return ORACLE_OK;
+}
+
+/* RA/DEC in degrees and line-of-sight distance D -> positions D u. */
+int oracle_sky_to_cartesian(int64_t n, const double *ra, const double *dec,
+                            const double *dist, double *x, double *y,
+                            double *z)
+{
+    int rc = oracle_radec_to_unit(n, ra, dec, x, y, z);
+    if (rc)
+        return rc;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(dist[i] >= 0.0) || !isfinite(dist[i]))
+            return ORACLE_EINVAL;
+        x[i] = dist[i] * x[i];
+        y[i] = dist[i] * y[i];
+        z[i] = dist[i] * z[i];
     }
     return ORACLE_OK;
 }

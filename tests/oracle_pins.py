@@ -512,6 +512,118 @@ def pin_ravg_inside_bins(lib):
             assert te[k] * (1 - 1e-12) <= rv[k] <= te[k + 1] * (1 + 1e-12), (k, rv[k])
 
 
+# --------------------------------------------------------------------------
+# on-sky (rp, pi): line of sight through the pair's midpoint
+# --------------------------------------------------------------------------
+def _mocks_exact(P, rp_edges, pimax, npi):
+    """Exact counts of all ordered pairs of integer positions P: with
+    s = v1 - v2 and L = v1 + v2, pi^2 = (s.L)^2 / (L.L) and
+    rp^2 = s.s - pi^2 as rationals, compared with squared edges."""
+    E = [Fraction(float(e)) ** 2 for e in rp_edges]
+    q = [(Fraction(pimax) * p / npi) ** 2 for p in range(npi + 1)]
+    nb = len(rp_edges) - 1
+    want = np.zeros((nb, npi), dtype=np.int64)
+    for a in P:
+        for b in P:
+            s = [Fraction(int(a[k]) - int(b[k])) for k in range(3)]
+            L = [Fraction(int(a[k]) + int(b[k])) for k in range(3)]
+            sl = sum(s[k] * L[k] for k in range(3))
+            ll = sum(L[k] * L[k] for k in range(3))
+            ss = sum(s[k] * s[k] for k in range(3))
+            pi2 = sl * sl / ll if ll else Fraction(0)
+            rp2 = ss - pi2
+            if pi2 >= q[npi]:
+                continue
+            for k in range(nb):
+                if E[k] <= rp2 < E[k + 1]:
+                    p = max(i for i in range(npi) if q[i] <= pi2)
+                    want[k, p] += 1
+    return want
+
+
+def pin_mocks_lattice_exact(lib):
+    """Integer positions: every intermediate of the definition is exact or
+    decided far from its rounding, so the oracle must equal exact rational
+    arithmetic (including pairs exactly on a pi edge, which are radial)."""
+    rng = synth.rng_for(95)
+    P = rng.integers(-6, 7, size=(60, 3)) + np.array([40, -25, 30])
+    P[1] = P[0]                    # a coincident pair
+    P[2] = 2 * P[3]                # a radial pair (same line of sight)
+    rp_edges = [0.0, 1.25, 2.5, 4.75, 8.5]
+    pimax, npi = 8.0, 8
+    want = _mocks_exact(P, rp_edges, pimax, npi)
+    got, _ = oracle.count_rppi_mocks(P.astype(np.float64), None, rp_edges, pimax, npi, lib=lib)
+    assert (got == want).all(), (got, want)
+    Q = rng.integers(-5, 6, size=(40, 3)) + np.array([38, -20, 33])
+    wantx = _mocks_exact_cross(P, Q, rp_edges, pimax, npi)
+    gotx, _ = oracle.count_rppi_mocks(P.astype(np.float64), Q.astype(np.float64), rp_edges,
+                                      pimax, npi, lib=lib)
+    assert (gotx == wantx).all(), (gotx, wantx)
+
+
+def _mocks_exact_cross(P, Q, rp_edges, pimax, npi):
+    both = _mocks_exact(np.concatenate([P, Q]), rp_edges, pimax, npi)
+    return (both - _mocks_exact(P, rp_edges, pimax, npi) - _mocks_exact(Q, rp_edges, pimax, npi)) // 2
+
+
+def pin_mocks_closed_forms(lib):
+    """Points on one line of sight have rp = 0 and pi = |D1 - D2|; a pair
+    mirrored across a line of sight has pi = 0 and rp = its full
+    separation; the mean rp of a mirrored pair is that separation."""
+    D = np.array([100.0, 103.0, 107.5, 111.0, 131.0])
+    for axis in range(3):
+        P = np.zeros((D.size, 3))
+        P[:, axis] = D
+        c, _ = oracle.count_rppi_mocks(P, None, [0.0, 0.5], 20.0, 20, lib=lib)
+        want = np.zeros((1, 20), dtype=np.int64)
+        want[0, 0] += D.size
+        for a in range(D.size):
+            for b in range(D.size):
+                if a != b and abs(D[a] - D[b]) < 20.0:
+                    want[0, int(abs(D[a] - D[b]))] += 1
+        assert (c == want).all(), (axis, c, want)
+    # two points at the same distance from the observer have s.L =
+    # |v1|^2 - |v2|^2 = 0, so pi = 0 and rp = |s|; the two mirrored pairs
+    # are 100 apart, far outside the bins
+    M = np.array([[500.0, 3.0, -4.0], [500.0, -3.0, 4.0], [600.0, 6.0, 8.0],
+                  [600.0, -6.0, -8.0]])
+    c, _, rv = oracle.count_rppi_mocks(M, None, [1.0, 10.5, 20.5], 1.0, 1, lib=lib, ravg=True)
+    assert c.tolist() == [[2], [2]], c
+    assert rv[0, 0] == 10.0 and rv[1, 0] == 20.0, rv
+
+
+def pin_mocks_symmetries(lib):
+    """Exact symmetries: a quarter turn about any axis, swapping the two
+    catalogues, and doubling every length (positions, edges, pimax)."""
+    P = synth.cap_radec(300, seed=96, radius_deg=3.0)
+    d = 400.0 + 60.0 * synth.rng_for(97).random(300)
+    X = oracle.sky_to_cartesian(P[0], P[1], d, lib=lib)
+    Y = oracle.sky_to_cartesian(*synth.cap_radec(200, seed=98, radius_deg=3.0),
+                                420.0 + 30.0 * synth.rng_for(99).random(200), lib=lib)
+    e = synth.log_edges(0.5, 12.0, 6)
+    base, _ = oracle.count_rppi_mocks(X, Y, e, 15.0, 5, lib=lib)
+    assert base.sum() > 0
+    rot = X[:, [1, 0, 2]] * np.array([-1.0, 1.0, 1.0])
+    roty = Y[:, [1, 0, 2]] * np.array([-1.0, 1.0, 1.0])
+    assert (oracle.count_rppi_mocks(rot, roty, e, 15.0, 5, lib=lib)[0] == base).all()
+    rot = X[:, [0, 2, 1]] * np.array([1.0, 1.0, -1.0])
+    roty = Y[:, [0, 2, 1]] * np.array([1.0, 1.0, -1.0])
+    assert (oracle.count_rppi_mocks(rot, roty, e, 15.0, 5, lib=lib)[0] == base).all()
+    assert (oracle.count_rppi_mocks(Y, X, e, 15.0, 5, lib=lib)[0] == base).all()
+    assert (oracle.count_rppi_mocks(2 * X, 2 * Y, 2 * e, 30.0, 5, lib=lib)[0] == base).all()
+
+
+def pin_sky_to_cartesian(lib):
+    ra = np.array([0.0, 90.0, 180.0, 0.0, 45.0])
+    dec = np.array([0.0, 0.0, 0.0, 90.0, 0.0])
+    D = np.array([10.0, 20.0, 30.0, 40.0, 50.0])
+    v = oracle.sky_to_cartesian(ra, dec, D, lib=lib)
+    want = np.array([[10, 0, 0], [0, 20, 0], [-30, 0, 0], [0, 0, 40],
+                     [50 / math.sqrt(2), 50 / math.sqrt(2), 0]])
+    assert np.allclose(v, want, rtol=0, atol=1e-13), v
+    assert np.allclose(np.linalg.norm(v, axis=1), D, rtol=1e-15)
+
+
 ALL_PINS = [
     pin_golden_r_edges,
     pin_golden_r_periodic,
@@ -534,4 +646,8 @@ ALL_PINS = [
     pin_ravg_chain_rppi,
     pin_ravg_theta_equator,
     pin_ravg_inside_bins,
+    pin_mocks_lattice_exact,
+    pin_mocks_closed_forms,
+    pin_mocks_symmetries,
+    pin_sky_to_cartesian,
 ]

@@ -28,7 +28,8 @@ MUTATIONS = [
     ("auto_includes_diagonal", "autocorr ? i + 1 : 0", "autocorr ? i : 0"),
     ("pi_cut_inclusive", "pi >= pimax", "pi > pimax"),
     ("pi_bin_off_by_one", "while (pi < q[p])", "while (pi <= q[p] && p > 0)"),
-    ("rp_uses_dz", "s = dx * dx + dy * dy;\n                    double pi", "s = dx * dx + dz * dz;\n                    double pi"),
+    ("rp_uses_dz", "s = dx * dx + dy * dy;\n                        pi = fabs(dz);",
+     "s = dx * dx + dz * dz;\n                        pi = fabs(dz);"),
     ("chord_not_halved", "2.0 * sin(0.5 * (theta_deg[k] * d2r))", "2.0 * sin(theta_deg[k] * d2r)"),
     ("radec_swapped_trig", "x[i] = cd * cos(a);", "x[i] = cd * sin(a);"),
     ("xsum_no_compensation", "double lo = y - (hi - x);", "double lo = 0.0 * (y - (hi - x));"),
@@ -47,6 +48,17 @@ MUTATIONS = [
      "(double)counts[b]"),
     ("theta_mean_in_radians", "return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);",
      "return 2.0 * asin(0.5 * c);"),
+    ("mocks_pi_signed", "pi = ll > 0.0 ? fabs(sl) / sqrt(ll) : 0.0;",
+     "pi = ll > 0.0 ? sl / sqrt(ll) : 0.0;"),
+    ("mocks_los_from_difference", "const double lx = xi + x2[j], ly = yi + y2[j], lz = zi + z2[j];",
+     "const double lx = xi - x2[j], ly = yi - y2[j], lz = zi - z2[j];"),
+    ("mocks_pi_unnormalised", "fabs(sl) / sqrt(ll)", "fabs(sl) / ll"),
+    ("mocks_rp_adds_pi", "s = fmax(ss - pi * pi, 0.0);", "s = fmax(ss + pi * pi, 0.0);"),
+    ("mocks_sl_drops_z", "const double sl = (dx * lx + dy * ly) + dz * lz;",
+     "const double sl = (dx * lx + dy * ly);"),
+    ("mocks_ll_drops_y", "const double ll = (lx * lx + ly * ly) + lz * lz;",
+     "const double ll = (lx * lx) + lz * lz;"),
+    ("sky_distance_ignored", "x[i] = dist[i] * x[i];", "x[i] = x[i];"),
     ("theta_mean_half_angle", "return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);",
      "return asin(0.5 * c) * (180.0 / M_PI);"),
 ]
