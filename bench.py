@@ -199,6 +199,104 @@ def batch_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def ref_pairs_box(v: np.ndarray, reach: float) -> int:
+    """Unordered candidate pairs of the paper's default grid for a
+    non-periodic catalogue: cubic cells of side >= reach over the bounding
+    box, each cell against itself and its 13 forward neighbours."""
+    lo, hi = v.min(axis=0), v.max(axis=0)
+    ext = np.maximum(hi - lo, reach)
+    n = np.maximum(np.floor(ext / (reach * (1 + 2 ** -28))).astype(np.int64), 1)
+    idx = [np.minimum(((v[:, a] - lo[a]) * (n[a] / ext[a])).astype(np.int64), n[a] - 1)
+           for a in range(3)]
+    cid = (idx[0] * n[1] + idx[1]) * n[2] + idx[2]
+    C = np.bincount(cid, minlength=int(n.prod())).reshape(n).astype(np.int64)
+    total = int((C * (C - 1) // 2).sum())
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                if (dx, dy, dz) <= (0, 0, 0):
+                    continue
+                a = C[max(0, -dx):n[0] - max(0, dx), max(0, -dy):n[1] - max(0, dy),
+                      max(0, -dz):n[2] - max(0, dz)]
+                b = C[max(0, dx):n[0] - max(0, -dx) if dx < 0 else n[0],
+                      max(0, dy):n[1] - max(0, -dy) if dy < 0 else n[1],
+                      max(0, dz):n[2] - max(0, -dz) if dz < 0 else n[2]]
+                total += int((a * b).sum())
+    return total
+
+
+def mocks_bench(args):
+    """On-sky DD(rp, pi) (line of sight through each pair's midpoint) of a
+    clustered 10^6-point mock: a 10-degree cone between distances 500 and
+    1500, half the points in 3-D Gaussian blobs (100 points, width 2); 20
+    log rp bins [0.1, 25], pimax 40 in 40 bins; RA/DEC/distance converted on
+    the device.  The value is pair evaluations per second (the sweep's
+    candidate pairs per step over the step time), and, for scale, the same
+    for the untuned oracle on a bounded sample."""
+    import torch
+    import paper_1911_03545_amd as pcm
+    t0 = time.perf_counter()
+    m = synth.sky_mock(1_000_000, seed=2024)
+    gen_s = time.perf_counter() - t0
+    e = synth.log_edges(0.1, 25.0, 20)
+    dev = torch.device("cuda:0")
+    cols = tuple(torch.from_numpy(np.ascontiguousarray(m[:, k])).to(dev) for k in range(3))
+    torch.cuda.synchronize()
+    import oracle
+    lib = oracle.load()
+    v = oracle.sky_to_cartesian(m[:, 0], m[:, 1], m[:, 2], lib=lib)
+    w_ref = ref_pairs_box(v, float(np.sqrt(25.0 ** 2 + 40.0 ** 2)))
+    ctx = pcm.PairCounter(0, stream=torch.cuda.current_stream(dev))
+    opts = pcm.default_options(collect_timing=1)
+    for _ in range(args.warmup):
+        counts, _ = ctx.count_rppi_mocks(cols, None, e, 40.0, 40, "fp64", options=opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        counts, _ = ctx.count_rppi_mocks(cols, None, e, 40.0, 40, "fp64", options=opts)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    st = ctx.stats()
+    cand = st["candidate_pairs"]
+    line = {
+        "metric": "Gpair-evals/s for on-sky DD(rp,pi) N=1e6 (binary64; reference pairs of "
+                  "the paper's cells of side sqrt(rpmax^2 + pimax^2))",
+        "value": w_ref / (ms / 1e3) / 1e9,
+        "unit": "Gpair-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "on-sky DD(rp,pi) autocorrelation, 1e6 clustered points in a "
+                               "10-degree cone, distances 500-1500, 20 log rp bins [0.1, 25], "
+                               "pimax 40 / 40 bins, RA/DEC/distance float64 inputs in HBM",
+                   "w_ref_pairs": w_ref, "generation_s": gen_s},
+        "sweep": {"kernel_ms": st["t_sweep_ms"], "candidate_pairs": cand,
+                  "candidate_over_ref": cand / w_ref,
+                  "in_range_pairs": int(counts.sum()), "grid": st["grid"],
+                  "phase_ms": {k: st[k] for k in ("t_prepare_ms", "t_grid_ms",
+                                                  "t_worklist_ms", "t_sweep_ms",
+                                                  "t_finalize_ms", "t_total_ms")}},
+    }
+    if not args.no_cpu_baseline:
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+        rng = synth.rng_for(98)
+        k = 1024
+        sample = v[rng.choice(v.shape[0], k, replace=False)]
+        t = time.perf_counter()
+        oracle.count_rppi_mocks(sample, v, e, 40.0, 40, nthreads=cores, lib=lib)
+        el = time.perf_counter() - t
+        rate = k * v.shape[0] / el
+        t_full = v.shape[0] * (v.shape[0] - 1) / 2 / rate
+        line["cpu_baseline"] = {
+            "value": w_ref / t_full / 1e9, "unit": "Gpair-evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"brute-force cross counts of {k} random points against all "
+                      f"{v.shape[0]} ({k * v.shape[0]:.3g} pair evaluations in {el:.1f} s, "
+                      f"{rate / 1e9:.3f} Gpair/s); full auto workload extrapolated to "
+                      f"{t_full:.0f} s"}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def ref_pairs_rppi(pts: np.ndarray, L: float, rpmax: float, pimax: float) -> int:
     """Unordered candidate pairs of the paper's default grid for rp/pi: cells
     of side >= rpmax in x, y and >= pimax along z, 13 forward neighbours plus
@@ -236,6 +334,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the batched DD(rp,pi) benchmark (256 mock catalogues) instead")
     ap.add_argument("--batch-cats", type=int, default=256)
+    ap.add_argument("--mocks", action="store_true",
+                    help="run the on-sky DD(rp,pi) benchmark (1e6-point mock) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; every box in this "
@@ -244,6 +344,9 @@ def main():
 
     if args.batch:
         batch_bench(args)
+        return
+    if args.mocks:
+        mocks_bench(args)
         return
     import torch
     import paper_1911_03545_amd as pcm
@@ -314,6 +417,23 @@ def main():
     graph = {"ms_per_step": msg, "value": w_ref / (msg / 1e3) / 1e9,
              "replayed": ctx.stats()["replayed"]}
 
+    # the same workload with the mean separation per bin (one square root
+    # and two more LDS sums per pair in range), in both precisions
+    ravg = {}
+    for prec in ("fp32", "fp64"):
+        cr, _, rv = ctx.count_r(cols, None, EDGES, L_BOX, prec, ravg=True)
+        if not np.array_equal(cr, counts):
+            raise SystemExit("counts with the mean separation differ")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        kr = max(5, args.steps // 5)
+        for _ in range(kr):
+            ctx.count_r(cols, None, EDGES, L_BOX, prec, options=opts, ravg=True)
+        torch.cuda.synchronize()
+        msr = (time.perf_counter() - t) * 1e3 / kr
+        ravg[prec] = {"value": w_ref / (msr / 1e3) / 1e9, "ms_per_step": msr,
+                      "sweep_ms": ctx.stats()["t_sweep_ms"]}
+
     t_sweep = float(np.mean(sweep_ms)) / 1e3
     achieved = FLOPS_PER_PAIR * st["candidate_pairs"] / t_sweep / 1e12
     line = {
@@ -361,6 +481,7 @@ def main():
         },
         "fp64_path": fp64,
         "graph_replay": graph,
+        "ravg_path": ravg,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pts, w_ref)

@@ -84,7 +84,10 @@ typedef enum { CF_PREC_FP64 = 0, CF_PREC_FP32_RECHECK = 1 } cf_precision;
 
 /* A borrowed view of one catalogue.  For count_pairs_theta x holds RA and y
    holds DEC in degrees and z is unused, unless cf_options.theta_unit_vectors
-   is set, in which case x, y, z are unit vectors. */
+   is set, in which case x, y, z are unit vectors.  For count_pairs_rppi_mocks
+   x, y are RA, DEC in degrees and z the line-of-sight distance, unless
+   cf_options.theta_unit_vectors is set, in which case x, y, z are Cartesian
+   positions (distance times unit vector). */
 typedef struct cf_catalog {
     int64_t n;          /* number of points, >= 0                          */
     int32_t dtype;      /* cf_dtype of x, y, z                             */
@@ -104,7 +107,9 @@ typedef struct cf_options {
     int32_t slices_per_reach;   /* z slices per line-of-sight reach (default 16) */
     int32_t chunk;              /* max j points per work item (default 2048)   */
     int32_t output_on_device;   /* counts / wsum are device pointers           */
-    int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC     */
+    int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC;
+                                   on-sky (mocks) input is Cartesian positions,
+                                   not RA/DEC/distance                         */
     int32_t collect_timing;     /* time phases with HIP events (cf_stats)      */
     int32_t hist_copies;        /* LDS histogram replicas per wave (0: auto)   */
     int32_t use_graph;          /* replay repeated identical calls from a HIP
@@ -223,6 +228,30 @@ cf_status count_pairs_theta_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catal
                                const double *theta_edges_deg, int32_t nbins,
                                cf_precision prec, uint64_t *counts, double *wsum,
                                const cf_options *opt);
+
+/* DD(rp, pi) of on-sky catalogues ("mocks"), Appendix A (spherical volumes,
+   the convention of Fisher et al. 1994): positions v = D u from RA, DEC
+   (degrees) and the line-of-sight distance D, in the units of the bins (the
+   paper's CZ input becomes a distance only through a cosmology, which the
+   caller applies).  With s = v1 - v2 and L = v1 + v2 (twice the line of
+   sight l, which cancels), evaluated in binary64 in this order:
+       sl = (sx*Lx + sy*Ly) + sz*Lz,  LL = (Lx*Lx + Ly*Ly) + Lz*Lz,
+       ss = (sx*sx + sy*sy) + sz*sz,  pi = |sl| / sqrt(LL) (0 if LL == 0),
+       rp^2 = max(ss - pi*pi, 0);
+   the pair is in bin (k, p) iff fl(rp_k^2) <= rp^2 < fl(rp_{k+1}^2) and
+   q_p <= pi < q_{p+1} (q_p as for count_pairs_rppi).  The cell grid reaches
+   sqrt(rp_max^2 + pimax^2) along every axis (section "Partitioning the
+   particles on a grid").  Never periodic.  Both precision modes evaluate in
+   binary64.  counts[k * npi + p], wsum likewise; cf_options.ravg gives the
+   mean rp per bin. */
+cf_status count_pairs_rppi_mocks(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                                 const double *rp_edges, int32_t nrp, double pimax,
+                                 int32_t npi, cf_precision prec, uint64_t *counts,
+                                 double *wsum);
+cf_status count_pairs_rppi_mocks_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                                    const double *rp_edges, int32_t nrp, double pimax,
+                                    int32_t npi, cf_precision prec, uint64_t *counts,
+                                    double *wsum, const cf_options *opt);
 
 /* Grid plan (host only, no device work) -- the cell grid of section
    "Partitioning the particles on a grid": columns of width >= reach_xy in x

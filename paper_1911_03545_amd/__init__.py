@@ -38,7 +38,8 @@ EXPORTED_SYMBOLS = (
     "cf_create", "cf_destroy", "cf_last_error", "cf_get_stats", "cf_default_options",
     "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
-    "count_pairs_rppi_batch_ex", "cf_plan_grid", "cf_fp32_bands",
+    "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
+    "cf_plan_grid", "cf_fp32_bands",
 )
 
 
@@ -132,6 +133,11 @@ def load_library(path: str = LIB_PATH):
     for name in ("count_pairs_rppi", "count_pairs_rppi_ex"):
         f = getattr(lib, name)
         f.argtypes = [vp, cat, cat, vp, i32, dbl, i32, dbl, ctypes.c_int, vp, vp] + (
+            [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
+        f.restype = ctypes.c_int
+    for name in ("count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, cat, cat, vp, i32, dbl, i32, ctypes.c_int, vp, vp] + (
             [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
         f.restype = ctypes.c_int
     for name in ("count_pairs_theta", "count_pairs_theta_ex"):
@@ -415,6 +421,30 @@ class PairCounter:
             None if wsum is None else wsum.ctypes.data, self._opts(options, weight_type, rv))
         self._check(st)
         return self._result(counts, wsum, rv, (ncat, nb, int(npi)))
+
+    def count_rppi_mocks(self, d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
+                         precision="fp64", w1=None, w2=None, options=None, weight_type=None,
+                         ravg=False, cartesian=False):
+        """On-sky DD(rp, pi) with the line of sight through each pair's
+        midpoint.  d1, d2: columns (RA deg, DEC deg, distance), as an (n, 3)
+        array or three arrays; with ``cartesian`` the columns are positions
+        x, y, z.  Returns (counts uint64[nrp, npi], wsum or None), plus the
+        mean rp per bin when ``ravg``."""
+        e = np.ascontiguousarray(rp_edges, dtype=np.float64)
+        nb = e.size - 1
+        c1 = _Cat(d1, w1)
+        c2 = None if d2 is None else _Cat(d2, w2)
+        counts = np.zeros(nb * int(npi), dtype=np.uint64)
+        wsum = np.zeros(nb * int(npi), dtype=np.float64) if w1 is not None else None
+        rv = np.zeros(nb * int(npi), dtype=np.float64) if ravg else None
+        fixed = {"theta_unit_vectors": 1} if cartesian else {}
+        st = self._lib.count_pairs_rppi_mocks_ex(
+            self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
+            e.ctypes.data, nb, float(pimax), int(npi), self._prec(precision), counts.ctypes.data,
+            None if wsum is None else wsum.ctypes.data,
+            self._opts(options, weight_type, rv, **fixed))
+        self._check(st)
+        return self._result(counts, wsum, rv, (nb, int(npi)))
 
     def count_theta(self, ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
                     precision="fp64", w1=None, w2=None, options=None, unit_vectors=None,

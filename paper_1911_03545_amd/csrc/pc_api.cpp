@@ -246,7 +246,9 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Stage the catalogues of one side on the device: host columns are copied
 // into one concatenated buffer per column, device columns are used in place,
 // RA/DEC become unit vectors.
-cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, int side,
+// radec: x, y are RA, DEC in degrees, converted on the device to unit
+// vectors, or (sky) to positions D u with the distance D in z.
+cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, bool sky, int side,
                      SideData &s, unsigned *flags)
 {
     static const BufId inb[2][4] = {{B_IN1X, B_IN1Y, B_IN1Z, B_IN1W},
@@ -267,7 +269,7 @@ cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, int s
         const size_t b = align256(dsize(d[i].dtype) * (size_t)d[i].n);
         need[0] += b;
         need[1] += b;
-        if (!radec)
+        if (!radec || sky)
             need[2] += b;
         if (d[i].w)
             need[3] += align256(dsize(d[i].wdtype) * (size_t)d[i].n);
@@ -296,16 +298,16 @@ cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, int s
         pc_cat &o = s.cats[i];
         const void *x = place(0, cat.x, cat.dtype, cat);
         const void *y = place(1, cat.y, cat.dtype, cat);
-        const void *z = radec ? nullptr : place(2, cat.z, cat.dtype, cat);
+        const void *z = (radec && !sky) ? nullptr : place(2, cat.z, cat.dtype, cat);
         const void *w = cat.w ? place(3, cat.w, cat.wdtype, cat) : nullptr;
-        if (cat.n > 0 && (!x || !y || (!radec && !z) || (cat.w && !w)))
+        if (cat.n > 0 && (!x || !y || ((!radec || sky) && !z) || (cat.w && !w)))
             return fail(c, CF_EDEVICE, "host-to-device copy of catalogue %d failed", i);
         if (radec) {
             double *v = dptr<double>(c, uvb);
             double *vx = v + o.off, *vy = v + s.ntot + o.off, *vz = v + 2 * s.ntot + o.off;
             if (cat.n > 0)
-                HIPCHK(pc::launch_radec(c->stream, cat.n, x, y, cat.dtype == CF_F32,
-                                        M_PI / 180.0, vx, vy, vz, flags));
+                HIPCHK(pc::launch_radec(c->stream, cat.n, x, y, sky ? z : nullptr,
+                                        cat.dtype == CF_F32, M_PI / 180.0, vx, vy, vz, flags));
             o.x = vx;
             o.y = vy;
             o.z = vz;
@@ -396,7 +398,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
             return fail(c, CF_EINVAL, "cf_options.struct_size mismatch");
         opt = *opt_in;
     }
-    const bool unit_vec = theta && opt.theta_unit_vectors;
+    // on-sky (rp, pi): RA, DEC and distance, or Cartesian positions with
+    // theta_unit_vectors; theta: RA, DEC, or unit vectors
+    const bool sky = metric == PC_METRIC_MOCKS;
+    const bool unit_vec = (theta || sky) && opt.theta_unit_vectors;
     cf_status st;
     if (ncat < 1 || ncat > PC_MAX_CATS)
         return fail(c, CF_EINVAL, "number of catalogues must be in [1, %d]", PC_MAX_CATS);
@@ -423,7 +428,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "unknown precision mode");
     if ((st = check_edges(c, edges, nb, true)))
         return st;
-    if (metric == PC_METRIC_RPPI) {
+    if (metric != PC_METRIC_R) {
         if (npi < 1 || npi > PC_MAX_NPI)
             return fail(c, CF_EINVAL, "npi must be in [1, %d]", PC_MAX_NPI);
         if (!(pimax > 0.0) || !isfinite(pimax))
@@ -447,6 +452,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "boxsize must be finite");
     if (theta && boxsize > 0.0)
         return fail(c, CF_EINVAL, "angular counts are never periodic");
+    if (sky && boxsize > 0.0)
+        return fail(c, CF_EINVAL, "on-sky counts are never periodic");
 
     // theta: chord edges c_k = 2 sin(theta_k / 2) on the host
     std::vector<double> lin(edges, edges + nb + 1);
@@ -461,8 +468,12 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
             if (!(lin[k] < lin[k + 1]))
                 return fail(c, CF_EINVAL, "theta edges give non-increasing chords");
     }
-    const double reach_xy = lin[nb];
-    const double reach_z = (metric == PC_METRIC_RPPI) ? pimax : lin[nb];
+    // on-sky pairs: the line of sight varies, so every axis must reach the
+    // largest 3-D separation sqrt(rp_max^2 + pimax^2) (kept a little wider
+    // than its rounding)
+    const double reach_sky = std::sqrt(lin[nb] * lin[nb] + pimax * pimax) * (1.0 + 0x1p-30);
+    const double reach_xy = sky ? reach_sky : lin[nb];
+    const double reach_z = sky ? reach_sky : (metric == PC_METRIC_RPPI) ? pimax : lin[nb];
     int64_t n1 = 0;
     for (int i = 0; i < ncat; i++)
         n1 += d1[i].n;
@@ -524,11 +535,11 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
 
     // ---- stage inputs ----------------------------------------------------
     unsigned *flags = (unsigned *)(misc(c) + M_FLAGS);
-    const bool radec = theta && !unit_vec;
+    const bool radec = (theta || sky) && !unit_vec;
     SideData s1, s2;
-    if ((st2 = stage_side(c, d1, ncat, radec, 0, s1, flags)))
+    if ((st2 = stage_side(c, d1, ncat, radec, sky, 0, s1, flags)))
         return st2;
-    if (!autocorr && (st2 = stage_side(c, d2, 1, radec, 1, s2, flags)))
+    if (!autocorr && (st2 = stage_side(c, d2, 1, radec, sky, 1, s2, flags)))
         return st2;
     if ((st2 = ensure(c, B_CATS1, sizeof(pc_cat) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CATS2, sizeof(pc_cat))))
@@ -594,7 +605,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     double scale = periodic ? boxsize : 0.0;
     for (int a = 0; a < 3; a++)
         scale = std::max(scale, g.extent[a]);
-    bool fp32 = prec == CF_PREC_FP32_RECHECK;
+    // on-sky pairs are evaluated in binary64 in either mode (same counts):
+    // the definition has a division and a square root per pair, and the
+    // vector binary64 rate equals the non-packed float32 rate here
+    bool fp32 = prec == CF_PREC_FP32_RECHECK && !sky;
     // float32 rp/pi path: z as fixed point with one pi bin = 2^k quanta, k
     // as large as keeps every biased value (and the periodic offset) below
     // 2^31.  When a bin would get fewer than 2^4 quanta the call sweeps in
@@ -630,7 +644,9 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return st2;
     // the bin description is built on the host while the gridding kernels run
     pc::HostBins hb;
-    rc = pc::build_bins(metric, fp32, lin.data(), nb, pimax, npi, scale, fscale_log2, priv, &hb);
+    // on-sky pairs bin (rp, pi) like the Cartesian statistic
+    rc = pc::build_bins(sky ? PC_METRIC_RPPI : metric, fp32, lin.data(), nb, pimax, npi, scale,
+                        fscale_log2, priv, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
     if (g.zq_shift > 0) {
@@ -1072,7 +1088,7 @@ void record_graph(cf_ctx *c, std::vector<char> &&key, const RunCtl &eager, int m
         c->gkey = std::move(key);
         c->g_misc = ctl.p_misc;
         c->g_out = ctl.p_out;
-        c->g_nout = (size_t)ncat * (size_t)nb * (size_t)(metric == PC_METRIC_RPPI ? npi : 1);
+        c->g_nout = (size_t)ncat * (size_t)nb * (size_t)(metric != PC_METRIC_R ? npi : 1);
         c->g_wsum = wsum != nullptr && d1->w != nullptr;
         c->g_ravg = opt && opt->ravg != nullptr;
         c->gstats = keep;
@@ -1323,6 +1339,24 @@ cf_status count_pairs_rppi(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2
 {
     return count_pairs_rppi_ex(c, d1, d2, rp_edges, nrp, pimax, npi, boxsize, prec, counts, wsum,
                                nullptr);
+}
+
+cf_status count_pairs_rppi_mocks_ex(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2,
+                                    const double *rp_edges, int32_t nrp, double pimax,
+                                    int32_t npi, cf_precision prec, uint64_t *counts,
+                                    double *wsum, const cf_options *opt)
+{
+    return count(c, PC_METRIC_MOCKS, false, d1, 1, d2, rp_edges, nrp, pimax, npi, 0.0, prec,
+                 counts, wsum, opt);
+}
+
+cf_status count_pairs_rppi_mocks(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2,
+                                 const double *rp_edges, int32_t nrp, double pimax,
+                                 int32_t npi, cf_precision prec, uint64_t *counts,
+                                 double *wsum)
+{
+    return count_pairs_rppi_mocks_ex(c, d1, d2, rp_edges, nrp, pimax, npi, prec, counts, wsum,
+                                     nullptr);
 }
 
 cf_status count_pairs_rppi_batch_ex(cf_ctx *c, const cf_catalog *cats, int32_t ncat,

@@ -40,7 +40,9 @@
 #define PC_D_PLUS 1u
 #define PC_D_MINUS 2u
 
-enum { PC_METRIC_R = 0, PC_METRIC_RPPI = 1 };
+// R: 3-D r (and theta as chords); RPPI: rp and pi with z as the line of
+// sight; MOCKS: rp and pi with the line of sight through the pair midpoint
+enum { PC_METRIC_R = 0, PC_METRIC_RPPI = 1, PC_METRIC_MOCKS = 2 };
 
 // Cell grid: x/y columns of width >= the transverse reach, z slices.
 // Cell id = (ix * ny + iy) * nz + iz, so columns are contiguous runs of cells

@@ -47,8 +47,10 @@ __global__ void k_zero(uint32_t *p, int64_t n)
 }
 
 // RA/DEC (degrees) -> unit vectors; d2r = fl(pi) / 180 as a binary64 value.
-__global__ void k_radec(int64_t n, const void *ra, const void *dec, int f32, double d2r,
-                        double *x, double *y, double *z, unsigned *flags)
+// Unit vectors of RA/DEC (degrees), or, with a distance column, the
+// positions D u of on-sky catalogues.
+__global__ void k_radec(int64_t n, const void *ra, const void *dec, const void *dist, int f32,
+                        double d2r, double *x, double *y, double *z, unsigned *flags)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -57,9 +59,18 @@ __global__ void k_radec(int64_t n, const void *ra, const void *dec, int f32, dou
             atomicOr(flags, PC_FLAG_RADEC);
         const double ar = a * d2r, dr = d * d2r;
         const double cd = cos(dr);
-        x[i] = cd * cos(ar);
-        y[i] = cd * sin(ar);
-        z[i] = sin(dr);
+        double ux = cd * cos(ar), uy = cd * sin(ar), uz = sin(dr);
+        if (dist) {
+            const double D = ld(dist, f32, i);
+            if (!(D >= 0.0) || !isfinite(D))
+                atomicOr(flags, PC_FLAG_NONFINITE);
+            ux = D * ux;
+            uy = D * uy;
+            uz = D * uz;
+        }
+        x[i] = ux;
+        y[i] = uy;
+        z[i] = uz;
     }
 }
 
@@ -529,11 +540,12 @@ hipError_t launch_zero(hipStream_t s, void *p, size_t bytes)
     return hipGetLastError();
 }
 
-hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
-                        double d2r, double *x, double *y, double *z, unsigned *flags)
+hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec,
+                        const void *dist, int f32, double d2r, double *x, double *y, double *z,
+                        unsigned *flags)
 {
-    hipLaunchKernelGGL(k_radec, dim3(grid_for(n)), dim3(kThreads), 0, s, n, ra, dec, f32, d2r,
-                       x, y, z, flags);
+    hipLaunchKernelGGL(k_radec, dim3(grid_for(n)), dim3(kThreads), 0, s, n, ra, dec, dist, f32,
+                       d2r, x, y, z, flags);
     return hipGetLastError();
 }
 

@@ -54,8 +54,11 @@ hipError_t launch_build_table(hipStream_t s, const pc_bins &B, int nedges, const
                               const float *hi, const float *lo_min, void *tbl);
 // zero `bytes` (a multiple of 4) of device memory with a kernel
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
-hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec, int f32,
-                        double d2r, double *x, double *y, double *z, unsigned *flags);
+// unit vectors of RA/DEC in degrees, times the distance column when `dist`
+// is not NULL (on-sky positions)
+hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec,
+                        const void *dist, int f32, double d2r, double *x, double *y, double *z,
+                        unsigned *flags);
 hipError_t launch_minmax(hipStream_t s, int64_t n, const void *x, const void *y,
                          const void *z, int f32, double *part, int nparts, unsigned *flags);
 hipError_t launch_minmax_final(hipStream_t s, const double *part, int nparts, double *out6);

@@ -446,9 +446,24 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
         if (M == PC_METRIC_R) {
             s[k] = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
             c[k] = s[k] < a.B.E_top;
-        } else {
+        } else if (M == PC_METRIC_RPPI) {
             s[k] = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
             pz[k] = fabs(dz);
+            c[k] = (s[k] < a.B.E_top) && (pz[k] < a.B.pimax);
+        } else {
+            // on-sky: the line of sight L = v1 + v2 through the pair's
+            // midpoint; pi = |s.L| / |L|, rp^2 = s.s - pi^2 (Appendix A),
+            // every operation rounded as written
+            const double lx = __dadd_rn(xi, xs[k]), ly = __dadd_rn(yi, ys[k]),
+                         lz = __dadd_rn(zi, zs[k]);
+            const double sl = __dadd_rn(__dadd_rn(__dmul_rn(dx, lx), __dmul_rn(dy, ly)),
+                                        __dmul_rn(dz, lz));
+            const double ll = __dadd_rn(__dadd_rn(__dmul_rn(lx, lx), __dmul_rn(ly, ly)),
+                                        __dmul_rn(lz, lz));
+            const double ss = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                        __dmul_rn(dz, dz));
+            pz[k] = ll > 0.0 ? __ddiv_rn(fabs(sl), __dsqrt_rn(ll)) : 0.0;
+            s[k] = fmax(__dsub_rn(ss, __dmul_rn(pz[k], pz[k])), 0.0);
             c[k] = (s[k] < a.B.E_top) && (pz[k] < a.B.pimax);
         }
         if (TRI)
@@ -482,7 +497,7 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
         int slot = e[k];
         if (is_slow<T16>(e[k]))
             slot = slow_slot_exact<T16>(s[k], e[k], L.E, a.B.nb + 1);
-        if (M == PC_METRIC_RPPI) {
+        if (M != PC_METRIC_R) {
             const int npi = a.B.npi;
             int kp = pi_fast(__double2float_rn(pz[k]), a.B.inv_dpi, a.B.pi_tau, npi);
             if (kp < 0)
@@ -492,7 +507,7 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
         lds_add(&hb[slot], 1u);
         if (W)
             add_weight_f64<W>(a, whb, slot, wi, ws[k], s[k],
-                              M == PC_METRIC_RPPI ? 1 : a.ravg);
+                              M != PC_METRIC_R ? 1 : a.ravg);
     }
 }
 
@@ -821,7 +836,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                 tbl[k] = src[k];
         }
         // float bands: the r / rp edges, then (rppi) the pi edges
-        const int ne = a.B.nb + 1, nq = (M == PC_METRIC_RPPI) ? a.B.npi + 1 : 0;
+        const int ne = a.B.nb + 1, nq = (M != PC_METRIC_R) ? a.B.npi + 1 : 0;
         LDS float *lo = (LDS float *)(sm + a.o_lo);
         LDS float *hi = (LDS float *)(sm + a.o_hi);
         for (int k = tid; k < ne; k += kSweepThreads) {
@@ -910,7 +925,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         pending += work;
         const bool act = lane < ni;
         const int i = it.i0 + (act ? lane : 0);
-        if (P32) {
+        if constexpr (P32) {
             if (tri)
                 item_f32<M, W, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
                                                rechecks);
@@ -1026,9 +1041,12 @@ const void *sweep_fn_w(int wmode, bool t16, bool unc, bool priv)
     return sweep_fn<M, P32, 0>(t16, unc, priv);
 }
 
-// wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums
+// wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums.
+// On-sky pairs have binary64 kernels only.
 const void *sweep_ptr(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv)
 {
+    if (metric == PC_METRIC_MOCKS)
+        return sweep_fn_w<PC_METRIC_MOCKS, false>(wmode, t16, unc, priv);
     if (metric == PC_METRIC_R)
         return fp32 ? sweep_fn_w<PC_METRIC_R, true>(wmode, t16, unc, priv)
                     : sweep_fn_w<PC_METRIC_R, false>(wmode, t16, unc, priv);

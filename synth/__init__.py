@@ -165,3 +165,46 @@ def batch_sizes(ncat: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """Catalogue sizes drawn uniformly from the integers [lo, hi]."""
     rng = rng_for(seed)
     return rng.integers(int(lo), int(hi) + 1, size=int(ncat))
+
+
+def sky_mock(n: int, seed: int, radius_deg: float = 10.0, dmin: float = 500.0,
+             dmax: float = 1500.0, clustered: bool = True, per_blob: int = 200,
+             sigma: float = 2.0, frac: float = 0.5, ra0_deg: float = 0.0,
+             dec0_deg: float = 30.0):
+    """An on-sky catalogue: (RA deg, DEC deg, distance) columns as an (n, 3)
+    float64 array.  Points fill the cone of angular radius ``radius_deg``
+    around (ra0, dec0) between distances dmin and dmax uniformly in volume;
+    with ``clustered`` a fraction ``frac`` of them sit in 3-D Gaussian blobs
+    of width ``sigma`` (length units of the distances) around uniform
+    centres, ``per_blob`` / 2 points each at the default fraction, redrawn
+    until they fall inside the cone and the distance range."""
+    rng = rng_for(seed)
+    n = int(n)
+    c, east, north = _cap_frame(ra0_deg, dec0_deg)
+    rad = np.deg2rad(radius_deg)
+
+    def uniform(m):
+        u = _uniform_cap_vectors(rng, m, c, east, north, rad)
+        d = np.cbrt(rng.uniform(dmin ** 3, dmax ** 3, size=m))
+        return u * d[:, None]
+
+    if not clustered:
+        p = uniform(n)
+    else:
+        n_cl = int(round(n * frac))
+        nblobs = max(1, (2 * n_cl) // max(per_blob, 1))
+        centres = uniform(nblobs)
+        owner = np.arange(n_cl) % nblobs
+        out = np.empty((n_cl, 3))
+        todo = np.arange(n_cl)
+        cos_rad = np.cos(rad)
+        while todo.size:
+            v = centres[owner[todo]] + rng.normal(0.0, sigma, size=(todo.size, 3))
+            d = np.linalg.norm(v, axis=1)
+            ok = (d >= dmin) & (d <= dmax) & ((v @ c) >= cos_rad * d)
+            out[todo[ok]] = v[ok]
+            todo = todo[~ok]
+        p = np.concatenate([uniform(n - n_cl), out], axis=0)[rng.permutation(n)]
+    d = np.linalg.norm(p, axis=1)
+    ra, dec = _to_radec(p / d[:, None])
+    return np.stack([ra, dec, d], axis=1)
