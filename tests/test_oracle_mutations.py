@@ -1,11 +1,13 @@
 """Each plausible mistake planted into a copy of the oracle must be caught by
 at least one pin.  Mistakes are planted in the oracle source on the CPU only."""
+import json
 import os
+import subprocess
+import sys
 
 import pytest
 
 import oracle
-from oracle_pins import ALL_PINS
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "paircount_oracle.c")
 
@@ -64,6 +66,26 @@ MUTATIONS = [
 ]
 
 
+# Runs every pin against a mutated library in a child process: a planted
+# mistake can make the oracle index outside its arrays, which must not take
+# the test process down.  The child prints the names of the pins that fail.
+_CHILD = """
+import json, sys
+sys.path[:0] = {paths!r}
+import oracle
+lib = oracle.load({so!r}, rebuild_if_missing=False)
+failures = []
+for pin in ALL_PINS:
+    try:
+        pin(lib)
+    except AssertionError:
+        failures.append(pin.__name__)
+    except oracle.OracleError:
+        failures.append(pin.__name__ + "(error)")
+print(json.dumps(failures))
+"""
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_mutation_is_caught(name, old, new, tmp_path):
@@ -74,13 +96,13 @@ def test_mutation_is_caught(name, old, new, tmp_path):
     path.write_text(mutated)
     so = str(tmp_path / "libmut.so")
     oracle.build(src=str(path), out=so)
-    lib = oracle.load(so)
-    failures = []
-    for pin in ALL_PINS:
-        try:
-            pin(lib)
-        except AssertionError:
-            failures.append(pin.__name__)
-        except oracle.OracleError:
-            failures.append(pin.__name__ + "(error)")
+    here = os.path.dirname(os.path.abspath(__file__))
+    paths = [here, os.path.dirname(here)]
+    r = subprocess.run([sys.executable, "-c", _CHILD.format(paths=paths, so=so)],
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        # the mutated oracle crashed on a pin's input: the mistake is caught
+        assert r.returncode < 0 or "Error" in r.stderr, (r.returncode, r.stderr[-2000:])
+        return
+    failures = json.loads(r.stdout.strip().splitlines()[-1])
     assert failures, f"planted mistake {name} was not caught by any pin"
