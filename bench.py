@@ -83,7 +83,7 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(pts: np.ndarray, w_ref: int, target_s: float = 10.0):
+def cpu_baseline(pts: np.ndarray, w_ref: int, target_s: float = 12.0):
     """The CPU oracle, untuned, on a bounded sample of the same workload:
     cross-counts of a random subset S against all N points.  Its brute-force
     pair rate is scaled to the full workload (N(N-1)/2 unique pairs) and
@@ -92,12 +92,18 @@ def cpu_baseline(pts: np.ndarray, w_ref: int, target_s: float = 10.0):
     lib = oracle.load()
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     rng = synth.rng_for(99)
-    # calibrate on a small sample, then size the sample to ~target_s
-    s0 = pts[rng.choice(pts.shape[0], 64, replace=False)]
-    t = time.perf_counter()
-    oracle.count_r(s0, pts, EDGES, L_BOX, nthreads=cores, lib=lib)
-    dt = max(time.perf_counter() - t, 1e-3)
-    m = int(min(pts.shape[0], max(64, 64 * target_s / dt)))
+    # calibrate on growing samples until one takes a measurable time, then
+    # size the sample to ~target_s
+    m0 = 64
+    while True:
+        s0 = pts[rng.choice(pts.shape[0], m0, replace=False)]
+        t = time.perf_counter()
+        oracle.count_r(s0, pts, EDGES, L_BOX, nthreads=cores, lib=lib)
+        dt = time.perf_counter() - t
+        if dt > 0.5 or m0 >= pts.shape[0]:
+            break
+        m0 = min(pts.shape[0], m0 * 4)
+    m = int(min(pts.shape[0], max(64, m0 * target_s / dt)))
     sample = pts[rng.choice(pts.shape[0], m, replace=False)]
     t = time.perf_counter()
     oracle.count_r(sample, pts, EDGES, L_BOX, nthreads=cores, lib=lib)
