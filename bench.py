@@ -334,6 +334,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the graph-replay and mean-separation runs (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer three times (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -408,25 +410,27 @@ def main():
 
     # the same call replayed from a recorded HIP graph (repeated identical
     # calls on the same device buffers; every kernel still runs)
-    gopts = pcm.default_options(use_graph=1)
-    cg, _ = ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
-    for _ in range(3):
-        ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(args.steps):
+    graph = None
+    if not args.no_extras:
+        gopts = pcm.default_options(use_graph=1)
         cg, _ = ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
-    torch.cuda.synchronize()
-    msg = (time.perf_counter() - t) * 1e3 / args.steps
-    if not np.array_equal(cg, counts):
-        raise SystemExit("graph replay and eager counts differ")
-    graph = {"ms_per_step": msg, "value": w_ref / (msg / 1e3) / 1e9,
-             "replayed": ctx.stats()["replayed"]}
+        for _ in range(3):
+            ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            cg, _ = ctx.count_r(cols, None, EDGES, L_BOX, args.precision, options=gopts)
+        torch.cuda.synchronize()
+        msg = (time.perf_counter() - t) * 1e3 / args.steps
+        if not np.array_equal(cg, counts):
+            raise SystemExit("graph replay and eager counts differ")
+        graph = {"ms_per_step": msg, "value": w_ref / (msg / 1e3) / 1e9,
+                 "replayed": ctx.stats()["replayed"]}
 
     # the same workload with the mean separation per bin (one square root
     # and two more LDS sums per pair in range), in both precisions
     ravg = {}
-    for prec in ("fp32", "fp64"):
+    for prec in (() if args.no_extras else ("fp32", "fp64")):
         cr, _, rv = ctx.count_r(cols, None, EDGES, L_BOX, prec, ravg=True)
         if not np.array_equal(cr, counts):
             raise SystemExit("counts with the mean separation differ")
