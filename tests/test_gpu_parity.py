@@ -323,6 +323,48 @@ def test_repeatable(pc):
 
 
 # ---------------------------------------------------------------- errors
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bin_count_limits(pc, olib, prec):
+    """The largest bin counts the library accepts: 1024 r bins (the edge
+    limit), 64 x 64 = 4096 rp/pi bins (the total limit), 4 x 1024 (the pi
+    limit), 2048 weighted bins and 1365 bins with the mean separation; one
+    more bin is an error."""
+    import paper_1911_03545_amd as m
+    say("bin limits", prec)
+    pts = synth.clustered_box(4000, 60.0, seed=61, nblobs=20)
+    w = synth.uniform_weights(4000, seed=62)
+    e = np.r_[0.0, synth.log_edges(0.02, 15.0, 1023)]
+    got, _ = pc.count_r(pts, None, e, 60.0, prec)
+    want, _ = oracle.count_r(pts, None, e, 60.0, lib=olib)
+    assert (got == want).all()
+    e64 = synth.log_edges(0.05, 15.0, 64)
+    got, _ = pc.count_rppi(pts, None, e64, 16.0, 64, 60.0, prec)
+    want, _ = oracle.count_rppi(pts, None, e64, 16.0, 64, 60.0, lib=olib)
+    assert (got == want).all()
+    e4 = synth.log_edges(0.5, 15.0, 4)
+    got, _ = pc.count_rppi(pts, None, e4, 16.0, 1024, 60.0, prec)
+    want, _ = oracle.count_rppi(pts, None, e4, 16.0, 1024, 60.0, lib=olib)
+    assert (got == want).all()
+    e32 = synth.log_edges(0.05, 15.0, 32)
+    got, gw = pc.count_rppi(pts, None, e32, 16.0, 64, 60.0, prec, w1=w)
+    want, ww = oracle.count_rppi(pts, None, e32, 16.0, 64, 60.0, w1=w, lib=olib)
+    assert (got == want).all()
+    check_w(gw, ww)
+    e21 = synth.log_edges(0.05, 15.0, 21)
+    got, _, gr = pc.count_rppi(pts, None, e21, 16.0, 65, 60.0, prec, ravg=True)
+    want, _, wr = oracle.count_rppi(pts, None, e21, 16.0, 65, 60.0, lib=olib, ravg=True)
+    assert (got == want).all()
+    if prec == "fp64":
+        check_w(gr, wr)
+    for args, kw in (((e64, 16.0, 65), {}), ((e32, 16.0, 65), {"w1": w}),
+                     ((e21, 16.0, 66), {"ravg": True})):
+        with pytest.raises(m.PairCountError) as ex:
+            pc.count_rppi(pts, None, *args, 60.0, prec, **kw)
+        assert ex.value.status == m.CF_EINVAL
+    with pytest.raises(m.PairCountError):
+        pc.count_r(pts, None, np.r_[0.0, synth.log_edges(0.02, 15.0, 1024)], 60.0, prec)
+
+
 def test_error_codes(pc):
     import paper_1911_03545_amd as m
     say("errors")
