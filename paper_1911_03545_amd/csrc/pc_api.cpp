@@ -40,6 +40,7 @@ enum {
     M_FLAGS = 0,        // unsigned
     M_RQCOUNT = 16,     // unsigned
     M_CAND = 32,        // u64
+    M_SIZES = 40,       // 2 int32: work items, blocks (copied by the finalize kernel)
     M_OUT6 = 64,        // 6 doubles
     M_SIZE = 256
 };
@@ -61,6 +62,9 @@ struct cf_ctx {
     int num_cu = 256;
     // graph replay of repeated identical calls (cf_options.use_graph)
     int32_t last_items = 0;          // work items of the last eager call
+    std::vector<char> last_shape;    // shape of the last eager call (see run)
+    // sweep workgroups per CU by kernel variant and LDS size
+    std::map<std::vector<int64_t>, int> occupancy;
     std::vector<char> gkey;          // signature of the cached graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -372,8 +376,14 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
 // How run() executes: eagerly (with host synchronisations), or as the
 // synchronisation-free sequence recorded into a graph, with a fixed
 // work-item capacity and its own pinned staging.
+void key_add(std::vector<char> &k, const void *p, size_t n)
+{
+    k.insert(k.end(), static_cast<const char *>(p), static_cast<const char *>(p) + n);
+}
+
 struct RunCtl {
     bool capture = false;
+    bool no_async = false;  // eager call: read the work-item count before the sweep
     int32_t item_cap = 0;
     char *pin = nullptr;
     size_t pin_cap = 0;
@@ -634,6 +644,49 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     g.fscale = std::ldexp(1.0, fscale_log2);
     record(c, timing, 1);
 
+    // ---- work-list and sweep buffers, cleared by one kernel ahead of the
+    // gridding (the host issues it while nothing else waits on it) ----------
+    const int32_t ncol = g.n[0] * g.n[1] * ncat;   // columns of every catalogue
+    const int64_t maxblocks = n1 / PC_BLOCK_I + ncol + 1;
+    const int chunk = opt.chunk > 0 ? std::min(opt.chunk, 1 << 20) : 2048;
+    if ((st2 = ensure(c, B_BCNT, sizeof(int32_t) * (size_t)ncol)) ||
+        (st2 = ensure(c, B_BOFF, sizeof(int32_t) * (size_t)(ncol + 1))) ||
+        (st2 = ensure(c, B_BLOCKS, sizeof(pc_block) * (size_t)maxblocks)) ||
+        (st2 = ensure(c, B_ICNT, sizeof(int32_t) * (size_t)maxblocks)) ||
+        (st2 = ensure(c, B_IOFF, sizeof(int32_t) * (size_t)(maxblocks + 1))) ||
+        (st2 = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(std::max<int64_t>(
+                                        std::max<int64_t>(maxblocks, ncol),
+                                        (int64_t)ncat * g.ncell)))) ||
+        (st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nout)) ||
+        (st2 = ensure(c, B_WHIST, sizeof(double) * nout)) ||
+        (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nout)) ||
+        (st2 = ensure(c, B_OUTW, sizeof(double) * nout)) ||
+        (want_ravg && (st2 = ensure(c, B_RHIST, sizeof(double) * nout))) ||
+        (want_ravg && (st2 = ensure(c, B_OUTR, sizeof(double) * nout))) ||
+        (st2 = ensure(c, B_WSQ, sizeof(double) * (size_t)ncat)) ||
+        (st2 = ensure(c, B_CTRS, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE)))
+        return st2;
+    {
+        void *zp[PC_ZERO_MAX];
+        size_t zb[PC_ZERO_MAX];
+        int nz = 0;
+        zp[nz] = c->buf[B_ICNT].p;
+        zb[nz++] = sizeof(int32_t) * (size_t)maxblocks;
+        zp[nz] = c->buf[B_CTRS].p;
+        zb[nz++] = sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE;
+        zp[nz] = c->buf[B_HIST].p;
+        zb[nz++] = sizeof(unsigned long long) * nout;
+        if (weighted) {
+            zp[nz] = c->buf[B_WHIST].p;
+            zb[nz++] = sizeof(double) * nout;
+        }
+        if (want_ravg) {
+            zp[nz] = c->buf[B_RHIST].p;
+            zb[nz++] = sizeof(double) * nout;
+        }
+        HIPCHK(pc::launch_zero_multi(c->stream, nz, zp, zb));
+    }
+
     // ---- grid ------------------------------------------------------------
     if ((st2 = grid_side(c, s1, cats1_dev, weighted, g, B_START1, B_X1, B_Y1, B_Z1, B_XD1, B_YD1,
                          B_ZD1, B_WD1, B_CS1, flags)))
@@ -671,18 +724,6 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     record(c, timing, 2);
 
     // ---- work list ---------------------------------------------------------
-    const int32_t ncol = g.n[0] * g.n[1] * ncat;   // columns of every catalogue
-    const int64_t maxblocks = n1 / PC_BLOCK_I + ncol + 1;
-    const int chunk = opt.chunk > 0 ? std::min(opt.chunk, 1 << 20) : 2048;
-    if ((st2 = ensure(c, B_BCNT, sizeof(int32_t) * (size_t)ncol)) ||
-        (st2 = ensure(c, B_BOFF, sizeof(int32_t) * (size_t)(ncol + 1))) ||
-        (st2 = ensure(c, B_BLOCKS, sizeof(pc_block) * (size_t)maxblocks)) ||
-        (st2 = ensure(c, B_ICNT, sizeof(int32_t) * (size_t)maxblocks)) ||
-        (st2 = ensure(c, B_IOFF, sizeof(int32_t) * (size_t)(maxblocks + 1))) ||
-        (st2 = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(std::max<int64_t>(
-                                        std::max<int64_t>(maxblocks, ncol),
-                                        (int64_t)ncat * g.ncell)))))
-        return st2;
     const int32_t *start1 = dptr<int32_t>(c, B_START1);
     const int32_t *start2 = autocorr ? start1 : dptr<int32_t>(c, B_START2);
     HIPCHK(pc::launch_block_count(c->stream, ncol, g.n[2], start1, dptr<int32_t>(c, B_BCNT)));
@@ -691,7 +732,6 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     HIPCHK(pc::launch_block_emit(c->stream, ncol, g.n[2], start1, dptr<int32_t>(c, B_BOFF),
                                  dptr<pc_block>(c, B_BLOCKS)));
     const int32_t *nblocks_dev = dptr<int32_t>(c, B_BOFF) + ncol;
-    HIPCHK(pc::launch_zero(c->stream, c->buf[B_ICNT].p, sizeof(int32_t) * (size_t)maxblocks));
     unsigned long long *cand = (unsigned long long *)(misc(c) + M_CAND);
     HIPCHK(pc::launch_item_count(c->stream, (int32_t)maxblocks, nblocks_dev,
                                  dptr<pc_block>(c, B_BLOCKS), g, start2, dptr<int32_t>(c, B_CS1),
@@ -701,10 +741,28 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     // Item count to the host (sizes the item array and the sweep launch);
     // a recorded call instead takes a fixed capacity and leaves the count
     // on the device, where the emit kernel and the sweep read it.
+    // A repeat of the previous eager call's shape (same statistic, sizes,
+    // bins, box, options and grid) also leaves the count on the device:
+    // the items array is sized from the last count with a margin, and a
+    // call whose work list overflows it raises PC_FLAG_ITEMS and is redone
+    // with the count read first.  This saves a host round trip per call.
+    std::vector<char> shape;
+    {
+        const int64_t sh[] = {metric, theta ? 1 : 0, ncat, autocorr ? 1 : 0, n1, n2, nb, npi,
+                              (int64_t)prec, opt.slices_per_reach, chunk, g.n[0], g.n[1],
+                              g.n[2], weighted ? 1 : 0};
+        key_add(shape, sh, sizeof(sh));
+        key_add(shape, &boxsize, sizeof(boxsize));
+        key_add(shape, &pimax, sizeof(pimax));
+    }
+    const bool async_items = !ctl.capture && !ctl.no_async && c->last_items > 0 &&
+                             shape == c->last_shape;
     int32_t hcounts[2] = {0, 0};
     int32_t n_items;
     if (ctl.capture) {
         n_items = ctl.item_cap;
+    } else if (async_items) {
+        n_items = c->last_items + c->last_items / 4 + 1024;
     } else {
         HIPCHK(hipMemcpyAsync(pin + p_misc, dptr<int32_t>(c, B_IOFF) + maxblocks,
                               sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -727,28 +785,12 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     record(c, timing, 3);
 
     // ---- sweep -------------------------------------------------------------
-    if ((st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nout)) ||
-        (st2 = ensure(c, B_WHIST, sizeof(double) * nout)) ||
-        (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nout)) ||
-        (st2 = ensure(c, B_OUTW, sizeof(double) * nout)) ||
-        (want_ravg && (st2 = ensure(c, B_RHIST, sizeof(double) * nout))) ||
-        (want_ravg && (st2 = ensure(c, B_OUTR, sizeof(double) * nout))) ||
-        (st2 = ensure(c, B_WSQ, sizeof(double) * (size_t)ncat)) ||
-        (st2 = ensure(c, B_CTRS, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE)))
-        return st2;
-    HIPCHK(pc::launch_zero(c->stream, c->buf[B_CTRS].p,
-                           sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE));
-    HIPCHK(pc::launch_zero(c->stream, c->buf[B_HIST].p, sizeof(unsigned long long) * nout));
-    if (weighted)
-        HIPCHK(pc::launch_zero(c->stream, c->buf[B_WHIST].p, sizeof(double) * nout));
-    if (want_ravg)
-        HIPCHK(pc::launch_zero(c->stream, c->buf[B_RHIST].p, sizeof(double) * nout));
     const char *bb = (const char *)c->buf[B_BINS].p;
     pc::SweepArgs a;
     memset(&a, 0, sizeof(a));
     a.items = dptr<pc_item>(c, B_ITEMS);
     a.n_items = n_items;
-    a.n_items_dev = ctl.capture ? dptr<int32_t>(c, B_IOFF) + maxblocks : nullptr;
+    a.n_items_dev = (ctl.capture || async_items) ? dptr<int32_t>(c, B_IOFF) + maxblocks : nullptr;
     a.counter = dptr<int32_t>(c, B_CTRS);
     a.X1 = dptr<float>(c, B_X1);
     a.Y1 = dptr<float>(c, B_Y1);
@@ -840,12 +882,23 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
 
     int per_cu = 0;
     const int wmode = weighted ? (want_ravg ? 2 : 1) : 0;
-    HIPCHK(pc::sweep_occupancy(metric, fp32, wmode, hb.hdr.tbl_wide != 0, copies == PC_WAVE,
-                               priv, off, &per_cu));
+    {
+        const std::vector<int64_t> ok = {metric, fp32 ? 1 : 0, wmode, hb.hdr.tbl_wide != 0 ? 1 : 0,
+                                         copies == PC_WAVE ? 1 : 0, priv ? 1 : 0, off};
+        auto it = c->occupancy.find(ok);
+        if (it != c->occupancy.end()) {
+            per_cu = it->second;
+        } else {
+            HIPCHK(pc::sweep_occupancy(metric, fp32, wmode, hb.hdr.tbl_wide != 0,
+                                       copies == PC_WAVE, priv, off, &per_cu));
+            c->occupancy[ok] = per_cu;
+        }
+    }
     per_cu = std::max(per_cu, 1);
-    int nwg = ctl.capture ? c->num_cu * per_cu
-                          : (int)std::min<int64_t>((n_items + waves - 1) / waves,
-                                                   (int64_t)c->num_cu * per_cu);
+    int nwg = (ctl.capture || async_items)
+                  ? c->num_cu * per_cu
+                  : (int)std::min<int64_t>((n_items + waves - 1) / waves,
+                                           (int64_t)c->num_cu * per_cu);
     nwg = std::max(nwg, 1);
     c->stats.sweep_workgroups = nwg;
     c->stats.hist_copies = copies;
@@ -873,7 +926,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         HIPCHK(pc::launch_zero(c->stream, wsum, sizeof(double) * nout));
     HIPCHK(pc::launch_finalize(c->stream, ncat, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero,
                                cats1_dev, a.g_hist, a.g_whist, a.g_rhist, wsq, outc, outw,
-                               outr));
+                               outr, dptr<int32_t>(c, B_IOFF) + maxblocks, nblocks_dev,
+                               (int32_t *)(misc(c) + M_SIZES)));
     char *hp = pin + p_out;
     HIPCHK(hipMemcpyAsync(pin + p_misc, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
     if (!opt.output_on_device) {
@@ -903,6 +957,25 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_ERANGE, "periodic coordinate outside [0, boxsize]");
     if (hflags & PC_FLAG_WEIGHT)
         return fail(c, CF_EINVAL, "non-finite weight");
+    int32_t sizes[2];
+    memcpy(sizes, hm + M_SIZES, sizeof(sizes));
+    if (async_items && (hflags & PC_FLAG_ITEMS)) {
+        // the work list outgrew the capacity taken from the last call: redo
+        // the call with the count read first
+        c->last_items = 0;
+        RunCtl again = ctl;
+        again.no_async = true;
+        const cf_status st3 = run(c, again, metric, theta, d1, ncat, d2, edges, nb, pimax, npi,
+                                  boxsize, prec, counts, wsum, opt_in);
+        ctl.pin_need = again.pin_need;
+        ctl.p_misc = again.p_misc;
+        ctl.p_out = again.p_out;
+        return st3;
+    }
+    c->last_items = sizes[0];
+    c->last_shape = std::move(shape);
+    hcounts[0] = sizes[0];
+    hcounts[1] = sizes[1];
     if (!opt.output_on_device) {
         memcpy(counts, hp, sizeof(uint64_t) * nout);
         if (wsum && user_w)
@@ -924,7 +997,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     S.slices_per_reach = opt.slices_per_reach > 0 ? opt.slices_per_reach : 16;
     S.chunk = chunk;
     S.n_blocks = hcounts[1];
-    S.n_items = n_items;
+    S.n_items = hcounts[0];
     S.candidate_pairs = cnd;
     S.rechecks = (uint64_t)rqn;
     if (timing) {
@@ -940,10 +1013,6 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
 
 // ---- graph replay of repeated identical calls --------------------------
 
-void key_add(std::vector<char> &k, const void *p, size_t n)
-{
-    k.insert(k.end(), static_cast<const char *>(p), static_cast<const char *>(p) + n);
-}
 
 // Everything a recorded call depends on: the catalogue views (pointers and
 // sizes, not the data), bins, box, precision, options and device outputs.

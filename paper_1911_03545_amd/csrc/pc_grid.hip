@@ -46,9 +46,23 @@ __global__ void k_zero(uint32_t *p, int64_t n)
         p[i] = 0u;
 }
 
-// RA/DEC (degrees) -> unit vectors; d2r = fl(pi) / 180 as a binary64 value.
-// Unit vectors of RA/DEC (degrees), or, with a distance column, the
-// positions D u of on-sky catalogues.
+// Several regions cleared by one launch (blockIdx.y selects the region).
+struct ZeroSet {
+    uint32_t *p[PC_ZERO_MAX];
+    int64_t n[PC_ZERO_MAX];
+};
+
+__global__ void k_zero_multi(ZeroSet z)
+{
+    uint32_t *p = z.p[blockIdx.y];
+    const int64_t n = z.n[blockIdx.y];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Unit vectors of RA/DEC (degrees; d2r = fl(pi) / 180), or, with a distance
+// column, the positions D u of on-sky catalogues.
 __global__ void k_radec(int64_t n, const void *ra, const void *dec, const void *dist, int f32,
                         double d2r, double *x, double *y, double *z, unsigned *flags)
 {
@@ -529,6 +543,24 @@ __global__ void k_build_table(pc_bins B, int nedges, const float *lo, const floa
 }
 
 }  // namespace
+
+hipError_t launch_zero_multi(hipStream_t s, int count, void *const *ptrs, const size_t *bytes)
+{
+    if (count < 1 || count > PC_ZERO_MAX)
+        return hipErrorInvalidValue;
+    ZeroSet z;
+    int64_t most = 0;
+    for (int k = 0; k < count; k++) {
+        z.p[k] = static_cast<uint32_t *>(ptrs[k]);
+        z.n[k] = (int64_t)(bytes[k] / 4);
+        most = std::max(most, z.n[k]);
+    }
+    if (most <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_zero_multi, dim3(grid_for(most, kThreads, 512), count), dim3(kThreads),
+                       0, s, z);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes)
 {

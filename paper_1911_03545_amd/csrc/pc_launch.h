@@ -54,6 +54,9 @@ hipError_t launch_build_table(hipStream_t s, const pc_bins &B, int nedges, const
                               const float *hi, const float *lo_min, void *tbl);
 // zero `bytes` (a multiple of 4) of device memory with a kernel
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
+// zero `count` (at most PC_ZERO_MAX) such regions with one launch
+#define PC_ZERO_MAX 6
+hipError_t launch_zero_multi(hipStream_t s, int count, void *const *ptrs, const size_t *bytes);
 // unit vectors of RA/DEC in degrees, times the distance column when `dist`
 // is not NULL (on-sky positions)
 hipError_t launch_radec(hipStream_t s, int64_t n, const void *ra, const void *dec,
@@ -100,11 +103,13 @@ hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t 
 // counts (and weight sums, mean separations) of every catalogue: doubling
 // and self-pairs of autocorrelations; the mean separation is the separation
 // sum over the weight sum
+// (it also copies the device work-item and block counts to `sizes_out`)
 hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
                            const double *g_whist, const double *g_rhist, const double *wsq,
                            unsigned long long *out_counts, double *out_wsum,
-                           double *out_ravg);
+                           double *out_ravg, const int32_t *n_items_dev,
+                           const int32_t *n_blocks_dev, int32_t *sizes_out);
 // resident sweep workgroups per CU for a dynamic LDS size
 // waves per sweep workgroup
 int sweep_waves();

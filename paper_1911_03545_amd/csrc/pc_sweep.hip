@@ -991,8 +991,14 @@ __global__ void k_wsq(int64_t ncell, const int32_t *start, const double *w, int 
 __global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
                            const double *g_whist, const double *g_rhist, const double *wsq,
-                           unsigned long long *out_counts, double *out_wsum, double *out_ravg)
+                           unsigned long long *out_counts, double *out_wsum, double *out_ravg,
+                           const int32_t *n_items_dev, const int32_t *n_blocks_dev,
+                           int32_t *sizes_out)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sizes_out[0] = *n_items_dev;
+        sizes_out[1] = *n_blocks_dev;
+    }
     const int64_t total = (int64_t)ncat * nbt;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -1100,14 +1106,15 @@ hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocor
                            const pc_cat *cats, const unsigned long long *g_hist,
                            const double *g_whist, const double *g_rhist, const double *wsq,
                            unsigned long long *out_counts, double *out_wsum,
-                           double *out_ravg)
+                           double *out_ravg, const int32_t *n_items_dev,
+                           const int32_t *n_blocks_dev, int32_t *sizes_out)
 {
     const int64_t total = (int64_t)ncat * nbt;
     int64_t g = (total + 255) / 256;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(256), 0, s, ncat, nbt, autocorr,
                        e0_zero, cats, g_hist, g_whist, g_rhist, wsq, out_counts, out_wsum,
-                       out_ravg);
+                       out_ravg, n_items_dev, n_blocks_dev, sizes_out);
     return hipGetLastError();
 }
 

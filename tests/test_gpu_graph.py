@@ -10,6 +10,7 @@ holds must fall back to an eager call.
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -17,6 +18,11 @@ pytestmark = pytest.mark.gpu
 
 def say(*a):
     print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def olib():
+    return oracle.load()
 
 
 @pytest.fixture(scope="module")
@@ -135,3 +141,24 @@ def test_autotune_same_counts(pc):
         st = pc.stats()
         assert st["slices_per_reach"] in (2, 4, 8, 16, 32)
         assert st["chunk"] in (512, 1024, 2048, 4096, 8192)
+
+
+def test_repeat_calls_item_overflow(pc, olib):
+    """A repeat of the previous call's shape sizes its work list from the
+    last call and keeps the count on the device; new data needing far more
+    items (uniform -> one dense clump) must be redone and stay exact."""
+    say("repeat overflow")
+    n, L = 20000, 100.0
+    e = synth.log_edges(0.5, 10.0, 8)
+    uni = synth.uniform_box(n, L, seed=71)
+    a, _ = pc.count_r(uni, None, e, L, "fp32")
+    items_uni = pc.stats()["n_items"]
+    b, _ = pc.count_r(uni, None, e, L, "fp32")
+    assert (a == b).all() and pc.stats()["n_items"] == items_uni
+    rng = synth.rng_for(72)
+    clump = np.clip(50.0 + rng.normal(0.0, 3.0, size=(n, 3)), 0.0, L)
+    want, _ = oracle.count_r(clump, None, e, L, lib=olib)
+    for _ in range(2):
+        got, _ = pc.count_r(clump, None, e, L, "fp32")
+        assert (got == want).all()
+        assert pc.stats()["n_items"] > items_uni
