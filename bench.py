@@ -10,8 +10,8 @@ the number of unordered candidate pairs of the paper's default cell grid
 grid-independent measure of the work, so runs with different internal grids
 or precisions are comparable.
 
-Prints one JSON line (see --help).  With --gpus N > 1 it exits: this build
-measures a single GPU.
+Prints one JSON line (see --help).  With --gpus N > 1 it exits: the
+benchmark measures a single GPU.
 """
 from __future__ import annotations
 
@@ -346,8 +346,9 @@ def main():
                     help="run the on-sky DD(rp,pi) benchmark (1e6-point mock) instead")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark measures one GPU; every box in this "
-                                   "setup has a single MI355X, so --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark measures the single-GPU path only; "
+                                   "--gpus must be 1 (how the path would shard over "
+                                   "several GPUs is a design note, not a measured mode)"}))
         sys.exit(2)
 
     if args.batch:
