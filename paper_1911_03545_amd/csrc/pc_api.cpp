@@ -381,6 +381,14 @@ void key_add(std::vector<char> &k, const void *p, size_t n)
     k.insert(k.end(), static_cast<const char *>(p), static_cast<const char *>(p) + n);
 }
 
+// Work-item capacity for a call that does not read the count first: the
+// last count plus a quarter plus 1024, or 0 when that would not fit int32.
+int32_t item_margin(int32_t last)
+{
+    const int64_t cap = (int64_t)last + last / 4 + 1024;
+    return cap <= (int64_t)0x7fffffff ? (int32_t)cap : 0;
+}
+
 struct RunCtl {
     bool capture = false;
     bool no_async = false;  // eager call: read the work-item count before the sweep
@@ -756,13 +764,13 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         key_add(shape, &pimax, sizeof(pimax));
     }
     const bool async_items = !ctl.capture && !ctl.no_async && c->last_items > 0 &&
-                             shape == c->last_shape;
+                             item_margin(c->last_items) > 0 && shape == c->last_shape;
     int32_t hcounts[2] = {0, 0};
     int32_t n_items;
     if (ctl.capture) {
         n_items = ctl.item_cap;
     } else if (async_items) {
-        n_items = c->last_items + c->last_items / 4 + 1024;
+        n_items = item_margin(c->last_items);
     } else {
         HIPCHK(hipMemcpyAsync(pin + p_misc, dptr<int32_t>(c, B_IOFF) + maxblocks,
                               sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -1129,7 +1137,9 @@ void record_graph(cf_ctx *c, std::vector<char> &&key, const RunCtl &eager, int m
     }
     RunCtl ctl;
     ctl.capture = true;
-    ctl.item_cap = c->last_items + c->last_items / 4 + 1024;
+    ctl.item_cap = item_margin(c->last_items);
+    if (ctl.item_cap <= 0)
+        return;
     ctl.pin = static_cast<char *>(c->gpin);
     ctl.pin_cap = c->gpin_cap;
     if (ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)ctl.item_cap) != CF_OK)

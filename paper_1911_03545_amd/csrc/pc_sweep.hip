@@ -237,11 +237,13 @@ __device__ __forceinline__ unsigned tbl_key(float s, unsigned base, int sh, unsi
 }
 
 // Key of the float32 path's linear table: floor(s) for s below the last
-// cell, the last cell for everything above (s >= 0; coordinates are scaled
-// so that the top band lies below the last cell).
+// cell, the last cell for everything above (coordinates are scaled so that
+// the top band lies below the last cell).  s is a sum of squares, or +inf
+// for an inactive lane, never negative or NaN, so its bit pattern orders
+// like its value and an integer min clamps it in one instruction.
 __device__ __forceinline__ unsigned tbl_key_linear(float s, float kmax)
 {
-    return (unsigned)fminf(s, kmax);
+    return (unsigned)__uint_as_float(min(__float_as_uint(s), __float_as_uint(kmax)));
 }
 
 // Number of bands wholly below s (bin + 1), or -1 when s lies inside a band.
