@@ -456,17 +456,28 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
             // on-sky: the line of sight L = v1 + v2 through the pair's
             // midpoint; pi = |s.L| / |L|, rp^2 = s.s - pi^2 (Appendix A),
             // every operation rounded as written
-            const double lx = __dadd_rn(xi, xs[k]), ly = __dadd_rn(yi, ys[k]),
-                         lz = __dadd_rn(zi, zs[k]);
-            const double sl = __dadd_rn(__dadd_rn(__dmul_rn(dx, lx), __dmul_rn(dy, ly)),
-                                        __dmul_rn(dz, lz));
-            const double ll = __dadd_rn(__dadd_rn(__dmul_rn(lx, lx), __dmul_rn(ly, ly)),
-                                        __dmul_rn(lz, lz));
             const double ss = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
                                         __dmul_rn(dz, dz));
-            pz[k] = ll > 0.0 ? __ddiv_rn(fabs(sl), __dsqrt_rn(ll)) : 0.0;
-            s[k] = fmax(__dsub_rn(ss, __dmul_rn(pz[k], pz[k])), 0.0);
-            c[k] = (s[k] < a.B.E_top) && (pz[k] < a.B.pimax);
+            // A pair in range has s.s below rp_max^2 + pimax^2 up to a few
+            // roundings (if pi < pimax then rp^2 >= s.s - pimax^2 - O(u)),
+            // so with the relative margin 2^-30 a slot where no lane is
+            // below the limit skips the division and square root.
+            const double lim = (a.B.E_top + a.B.pimax * a.B.pimax) * (1.0 + 0x1p-30);
+            if (__any(ss < lim)) {
+                const double lx = __dadd_rn(xi, xs[k]), ly = __dadd_rn(yi, ys[k]),
+                             lz = __dadd_rn(zi, zs[k]);
+                const double sl = __dadd_rn(__dadd_rn(__dmul_rn(dx, lx), __dmul_rn(dy, ly)),
+                                            __dmul_rn(dz, lz));
+                const double ll = __dadd_rn(__dadd_rn(__dmul_rn(lx, lx), __dmul_rn(ly, ly)),
+                                            __dmul_rn(lz, lz));
+                pz[k] = ll > 0.0 ? __ddiv_rn(fabs(sl), __dsqrt_rn(ll)) : 0.0;
+                s[k] = fmax(__dsub_rn(ss, __dmul_rn(pz[k], pz[k])), 0.0);
+                c[k] = (s[k] < a.B.E_top) && (pz[k] < a.B.pimax);
+            } else {
+                pz[k] = 1.0e300;
+                s[k] = 1.0e300;
+                c[k] = false;
+            }
         }
         if (TRI)
             c[k] = c[k] && (j + k > i);
