@@ -207,3 +207,32 @@ def test_theta_dr_n2e6_5e6(pc, olib, cap):
                             unit_vectors=(v_d[idx], v_r))
     want, _ = oracle.count_theta(ra_d[idx], dec_d[idx], ra_r, dec_r, e, lib=olib)
     assert (got == want).all()
+
+
+# ------------------------- batched DD(rp, pi) with full-size mock catalogues
+def test_batch_fullsize_catalogues(pc, olib):
+    """Catalogues of the batched workload's sizes (2e5-2e6 clustered points,
+    periodic L = 1000) in one batched, graph-replayed float32 call: every
+    slice equals the single-catalogue binary64 call, and sampled cross counts
+    of the largest catalogue equal the oracle's."""
+    import torch
+    say("batch full-size catalogues")
+    L = 1000.0
+    sizes = [2_000_000, 200_000, 1_100_000]
+    pts = [synth.clustered_box(n, L, seed=5000 + k, nblobs=n // 200, sigma=2.0)
+           for k, n in enumerate(sizes)]
+    cols = [tuple(torch.from_numpy(np.ascontiguousarray(p[:, a])).cuda() for a in range(3))
+            for p in pts]
+    e = synth.log_edges(0.1, 25.0, 20)
+    g = {"use_graph": 1}
+    for _ in range(2):   # record, then replay
+        got, _ = pc.count_rppi_batch(cols, e, 40.0, 40, L, "fp32", options=g)
+    assert pc.stats()["replayed"] == 1
+    for k, c in enumerate(cols):
+        one, _ = pc.count_rppi(c, None, e, 40.0, 40, L, "fp64")
+        assert (got[k] == one).all(), k
+    big = pts[0]
+    s = big[sample(big.shape[0], NSAMPLE // 2, 18)]
+    gx, _ = pc.count_rppi(s, big, e, 40.0, 40, L, "fp32")
+    want, _ = oracle.count_rppi(s, big, e, 40.0, 40, L, lib=olib)
+    assert (gx == want).all()
