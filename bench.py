@@ -285,7 +285,17 @@ def mocks_bench(args):
     if not args.no_cpu_baseline:
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
         rng = synth.rng_for(98)
-        k = 1024
+        # calibrate on growing samples, then size the sample to ~12 s
+        k = 256
+        while True:
+            sample = v[rng.choice(v.shape[0], k, replace=False)]
+            t = time.perf_counter()
+            oracle.count_rppi_mocks(sample, v, e, 40.0, 40, nthreads=cores, lib=lib)
+            el = time.perf_counter() - t
+            if el > 0.5 or k >= v.shape[0]:
+                break
+            k = min(v.shape[0], k * 4)
+        k = int(min(v.shape[0], max(256, k * 12.0 / el)))
         sample = v[rng.choice(v.shape[0], k, replace=False)]
         t = time.perf_counter()
         oracle.count_rppi_mocks(sample, v, e, 40.0, 40, nthreads=cores, lib=lib)
