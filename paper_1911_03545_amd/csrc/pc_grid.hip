@@ -130,16 +130,23 @@ __global__ void k_minmax(int64_t n, const void *x, const void *y, const void *z,
 
 __global__ void k_minmax_final(const double *part, int nparts, double *out6)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
+    // one wavefront: each lane folds a strided share of the partials, then
+    // the lanes are combined with shuffles (fmin / fmax are exact, so the
+    // order does not change the result)
     double r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int p = 0; p < nparts; p++)
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x)
         for (int a = 0; a < 3; a++) {
             r[a] = fmin(r[a], part[p * 6 + a]);
             r[3 + a] = fmax(r[3 + a], part[p * 6 + 3 + a]);
         }
-    for (int a = 0; a < 6; a++)
-        out6[a] = r[a];
+    for (int off = 32; off > 0; off >>= 1)
+        for (int a = 0; a < 3; a++) {
+            r[a] = fmin(r[a], __shfl_xor(r[a], off, 64));
+            r[3 + a] = fmax(r[3 + a], __shfl_xor(r[3 + a], off, 64));
+        }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; a++)
+            out6[a] = r[a];
 }
 
 // Cell coordinate: t = fl(fl(x - lo) * inv_w) is monotone in x; NaN and
