@@ -27,7 +27,7 @@ struct DevBuf {
 
 enum BufId {
     B_IN1X, B_IN1Y, B_IN1Z, B_IN1W, B_IN2X, B_IN2Y, B_IN2Z, B_IN2W,
-    B_CNT, B_START1, B_START2, B_CELLOF, B_RANKOF, B_PERM, B_REC,
+    B_CNT, B_START1, B_START2, B_CELLOF, B_RANKOF, B_PERM, B_REC, B_WOFF, B_LAY, B_COLS,
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
@@ -355,6 +355,39 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
         return st;
     if (weighted && (st = ensure(c, WD, sizeof(double) * (size_t)n)))
         return st;
+    // Two-level counting sort when the columns of a catalogue and the z
+    // slices of a column fit an LDS histogram: chunks of at least 2048
+    // points (and 8 per column, bounding the count matrix by n / 8 + ...)
+    const int32_t ncolc = g.n[0] * g.n[1];
+    const int32_t nz = g.n[2];
+    const int64_t chunk = ((std::max<int64_t>(2048, 8 * (int64_t)ncolc) + 255) / 256) * 256;
+    int64_t nchunks = 0;
+    for (const pc_cat &k : s.cats)
+        nchunks += (k.n + chunk - 1) / chunk;
+    const int64_t m = nchunks * ncolc;
+    if (ncolc <= PC_SORT2_MAX_BINS && nz <= PC_SORT2_MAX_BINS && m < 0x7ffffff0 &&
+        nchunks < 0x7fffffff && (int64_t)s.ncat * ncolc < 0x7fffffff && chunk < 0x7fffffff) {
+        if ((st = ensure(c, B_CNT, sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1))) ||
+            (st = ensure(c, B_WOFF, sizeof(int32_t) * (size_t)(m + 1))) ||
+            (st = ensure(c, B_LAY, sizeof(int32_t) * 3 * (size_t)(s.ncat + 1))) ||
+            (st = ensure(c, B_COLS, 2 * sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1))) ||
+            (st = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(m))))
+            return st;
+        HIPCHK(pc::launch_sort2(c->stream, s.ncat, cats_dev, n, g, (int32_t)chunk, ncolc,
+                                (int32_t)nchunks, m, dptr<int32_t>(c, B_LAY),
+                                dptr<int32_t>(c, B_CNT), dptr<int32_t>(c, B_WOFF),
+                                dptr<int32_t>(c, B_SCANTMP), dptr<int32_t>(c, B_CELLOF),
+                                dptr<int32_t>(c, B_RANKOF), c->buf[B_REC].p,
+                                c->buf[B_COLS].p, dptr<int32_t>(c, B_PERM),
+                                dptr<int32_t>(c, start), dptr<int32_t>(c, CS), flags));
+        HIPCHK(pc::launch_gather(c->stream, n, g, dptr<int32_t>(c, B_PERM), nullptr,
+                                 c->buf[B_REC].p, dptr<float>(c, X),
+                                 dptr<float>(c, Y), dptr<float>(c, Z), dptr<double>(c, XD),
+                                 dptr<double>(c, YD), dptr<double>(c, ZD),
+                                 weighted ? dptr<double>(c, WD) : nullptr,
+                                 dptr<int32_t>(c, CS)));
+        return CF_OK;
+    }
     HIPCHK(pc::launch_zero(c->stream, c->buf[B_CNT].p, sizeof(int32_t) * (size_t)ncells));
     HIPCHK(pc::launch_cell_index(c->stream, s.ncat, cats_dev, n, g, dptr<unsigned>(c, B_CNT),
                                  dptr<int32_t>(c, B_CELLOF), dptr<int32_t>(c, B_RANKOF),

@@ -270,6 +270,144 @@ __global__ void k_scan_apply(const int32_t *in, int64_t n, const int32_t *offs, 
         out[n] = run;
 }
 
+// ---- two-level counting sort (no global atomics) --------------------------
+// Level 1 groups the points by column: a workgroup takes a chunk of one
+// catalogue's points, counts them per column in LDS (the LDS atomic gives a
+// point its rank among the chunk's points of that column) and writes the
+// chunk's column counts into a [catalogue][column][chunk] matrix, whose
+// exclusive scan is every (chunk, column) run's place in column order.
+// Level 2 sorts each column's points by z slice in LDS and writes the final
+// cell order (`perm`) and the cell starts.  Layout per catalogue k (computed
+// on the device): lay[3k] = first chunk index, lay[3k+1] = chunks, lay[3k+2]
+// = first matrix entry.
+__global__ void k_grid_layout(int ncat, const pc_cat *cats, int32_t chunk, int32_t ncolc,
+                              int32_t *lay)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    int64_t wg = 0, mb = 0;
+    for (int k = 0; k < ncat; k++) {
+        const int64_t nw = (cats[k].n + chunk - 1) / chunk;
+        lay[3 * k] = (int32_t)wg;
+        lay[3 * k + 1] = (int32_t)nw;
+        lay[3 * k + 2] = (int32_t)mb;
+        wg += nw;
+        mb += nw * ncolc;
+    }
+    lay[3 * ncat] = (int32_t)wg;
+    lay[3 * ncat + 1] = 0;
+    lay[3 * ncat + 2] = (int32_t)mb;
+}
+
+// Level 1, counting: one workgroup per chunk, LDS histogram of ncolc columns.
+__global__ void k_cell_hist(int ncat, const pc_cat *cats, const int32_t *lay, pc_grid g,
+                            int32_t chunk, int32_t ncolc, int32_t *cell_of, int32_t *rank_of,
+                            double4 *rec, int32_t *wcnt, unsigned *flags)
+{
+    extern __shared__ unsigned hist[];
+    const int w = blockIdx.x;
+    int k = 0, hi = ncat - 1;   // the last catalogue whose first chunk is <= w
+    while (k < hi) {
+        const int mid = (k + hi + 1) >> 1;
+        if (lay[3 * mid] <= w)
+            k = mid;
+        else
+            hi = mid - 1;
+    }
+    const pc_cat &ct = cats[k];
+    const int wl = w - lay[3 * k], nw = lay[3 * k + 1], mb = lay[3 * k + 2];
+    const int64_t i0 = ct.off + (int64_t)wl * chunk;
+    const int64_t i1 = min(ct.off + ct.n, i0 + chunk);
+    for (int c = threadIdx.x; c < ncolc; c += blockDim.x)
+        hist[c] = 0u;
+    __syncthreads();
+    unsigned fl = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const int64_t j = i - ct.off;
+        const double c[3] = {ld(ct.x, ct.f32, j), ld(ct.y, ct.f32, j), ld(ct.z, ct.f32, j)};
+        int ia[3];
+        for (int a = 0; a < 3; a++) {
+            if (!isfinite(c[a]))
+                fl |= PC_FLAG_NONFINITE;
+            else if (g.periodic && (c[a] < 0.0 || c[a] > g.boxsize))
+                fl |= PC_FLAG_RANGE;
+            ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
+        }
+        // unit weights without weights (the mean-separation sums use them)
+        const double wt = ct.w ? ld(ct.w, ct.wf32, j) : 1.0;
+        if (!isfinite(wt))
+            fl |= PC_FLAG_WEIGHT;
+        const int col = ia[0] * g.n[1] + ia[1];
+        cell_of[i] = (int)((int64_t)k * g.ncell) + col * g.n[2] + ia[2];
+        rec[i] = make_double4(c[0], c[1], c[2], wt);
+        rank_of[i] = (int32_t)atomicAdd(&hist[col], 1u);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncolc; c += blockDim.x)
+        wcnt[mb + (int64_t)c * nw + wl] = (int32_t)hist[c];
+    if (fl)
+        atomicOr(flags, fl);
+}
+
+// Level 1, placement: every point, with its z slice, to its column-ordered
+// place (so that level 2 streams through its column without gathers).
+__global__ void k_col_scatter(int64_t ntot, int ncat, const pc_cat *cats, const int32_t *lay,
+                              int32_t nz, int32_t chunk, int32_t ncolc, const int32_t *cell_of,
+                              const int32_t *rank_of, const int32_t *woff, int2 *colsorted)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntot;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = ncat == 1 ? 0 : find_cat(cats, ncat, i);
+        const int wl = (int)((i - cats[k].off) / chunk);
+        const int cell = cell_of[i];
+        const int cz = cell / nz;
+        const int64_t m = lay[3 * k + 2] + (int64_t)(cz - k * ncolc) * lay[3 * k + 1] + wl;
+        colsorted[woff[m] + rank_of[i]] = make_int2((int32_t)i, cell - cz * nz);
+    }
+}
+
+// Level 2: one workgroup per column sorts the column's points by z slice
+// (LDS counts and prefix) and writes perm and the column's cell starts.
+__global__ void k_slice_sort(int ncat, const int32_t *lay, int32_t ncolc, int32_t nz,
+                             const int32_t *woff, const int2 *colsorted, int32_t *rank2,
+                             int32_t *perm, int32_t *start, int32_t *cell_sorted)
+{
+    extern __shared__ unsigned sh[];
+    const int64_t colall = blockIdx.x;
+    const int k = (int)(colall / ncolc), col = (int)(colall % ncolc);
+    const int nw = lay[3 * k + 1], mb = lay[3 * k + 2];
+    const int cs = woff[mb + (int64_t)col * nw];
+    const int ce = woff[mb + (int64_t)(col + 1) * nw];
+    const int64_t cell0 = colall * nz;
+    for (int z = threadIdx.x; z < nz; z += blockDim.x)
+        sh[z] = 0u;
+    __syncthreads();
+    for (int p = cs + threadIdx.x; p < ce; p += blockDim.x)
+        rank2[p] = (int32_t)atomicAdd(&sh[colsorted[p].y], 1u);
+    __syncthreads();
+    int carry = 0;
+    for (int base = 0; base < nz; base += blockDim.x) {
+        const int z = base + (int)threadIdx.x;
+        const int v = z < nz ? (int)sh[z] : 0;
+        int total;
+        const int ex = block_exclusive(v, &total);
+        if (z < nz)
+            sh[z] = (unsigned)(carry + ex);
+        carry += total;
+        __syncthreads();
+    }
+    for (int z = threadIdx.x; z < nz; z += blockDim.x)
+        start[cell0 + z] = cs + (int)sh[z];
+    if (colall == (int64_t)ncat * ncolc - 1 && threadIdx.x == 0)
+        start[cell0 + nz] = ce;
+    for (int p = cs + threadIdx.x; p < ce; p += blockDim.x) {
+        const int2 iz = colsorted[p];
+        const int q = cs + (int)sh[iz.y] + rank2[p];
+        perm[q] = iz.x;
+        cell_sorted[q] = (int32_t)(cell0 + iz.y);
+    }
+}
+
 // ---- scatter into per-cell contiguous structure-of-arrays ----------------
 // Counting-sort placement in two steps.  Writing every column of a point to
 // its sorted place would scatter eight small writes per point over the whole
@@ -304,7 +442,8 @@ __global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int
         zd[d] = r.z;
         if (wd)
             wd[d] = r.w;
-        cell_sorted[d] = cell_of[i];
+        if (cell_of)
+            cell_sorted[d] = cell_of[i];
     }
 }
 
@@ -652,9 +791,46 @@ hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const i
 {
     hipLaunchKernelGGL(k_perm, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, cell_of, rank_of,
                        start, perm);
+    return launch_gather(s, ntot, g, perm, cell_of, rec, X, Y, Z, xd, yd, zd, wd, cell_sorted);
+}
+
+hipError_t launch_gather(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *perm,
+                         const int32_t *cell_of, const void *rec, float *X, float *Y, float *Z,
+                         double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
+{
     hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, g, perm,
                        cell_of, static_cast<const double4 *>(rec), X, Y, Z, xd, yd, zd, wd,
                        cell_sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
+                        const pc_grid &g, int32_t chunk, int32_t ncolc, int32_t n_chunks,
+                        int64_t m, int32_t *lay, int32_t *wcnt, int32_t *woff, int32_t *tmp,
+                        int32_t *cell_of, int32_t *rank_of, void *rec, void *colsorted,
+                        int32_t *perm, int32_t *start, int32_t *cell_sorted, unsigned *flags)
+{
+    int2 *cols = static_cast<int2 *>(colsorted);
+    hipLaunchKernelGGL(k_grid_layout, dim3(1), dim3(64), 0, s, ncat, cats, chunk, ncolc, lay);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (n_chunks > 0)
+        hipLaunchKernelGGL(k_cell_hist, dim3((unsigned)n_chunks), dim3(kThreads),
+                           sizeof(unsigned) * (size_t)ncolc, s, ncat, cats, lay, g, chunk, ncolc,
+                           cell_of, rank_of, static_cast<double4 *>(rec), wcnt, flags);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if ((e = scan_exclusive(s, wcnt, m, woff, tmp)) != hipSuccess)
+        return e;
+    if (ntot > 0)
+        hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, ncat,
+                           cats, lay, g.n[2], chunk, ncolc, cell_of, rank_of, woff, cols);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_slice_sort, dim3((unsigned)((int64_t)ncat * ncolc)), dim3(kThreads),
+                       sizeof(unsigned) * (size_t)g.n[2], s, ncat, lay, ncolc, g.n[2], woff, cols,
+                       rank_of, perm, start, cell_sorted);
     return hipGetLastError();
 }
 
