@@ -324,6 +324,26 @@ def test_repeatable(pc):
 
 # ---------------------------------------------------------------- errors
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fine_grid_gridding_paths(pc, olib, prec):
+    """A grid of more columns (142 x 142 > 16384) than the two-level sort's
+    LDS histogram holds is gridded by the one-atomic-per-point path; both
+    paths must give the same exact counts (the coarse call uses the
+    two-level sort)."""
+    say("fine grid", prec)
+    pts = synth.clustered_box(20000, 1000.0, seed=63, nblobs=100, sigma=2.0)
+    e = synth.log_edges(0.5, 7.0, 8)
+    got, _ = pc.count_r(pts, None, e, 1000.0, prec, options={"slices_per_reach": 1})
+    assert pc.stats()["grid"][0] * pc.stats()["grid"][1] > 16384
+    want, _ = oracle.count_r(pts, None, e, 1000.0, lib=olib)
+    assert (got == want).all()
+    e2 = synth.log_edges(0.5, 20.0, 8)
+    got, _ = pc.count_r(pts, None, e2, 1000.0, prec)
+    assert pc.stats()["grid"][0] * pc.stats()["grid"][1] <= 16384
+    want, _ = oracle.count_r(pts, None, e2, 1000.0, lib=olib)
+    assert (got == want).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_bin_count_limits(pc, olib, prec):
     """The largest bin counts the library accepts: 1024 r bins (the edge
     limit), 64 x 64 = 4096 rp/pi bins (the total limit), 4 x 1024 (the pi
