@@ -120,7 +120,20 @@ typedef struct cf_options {
     int32_t weight_type;        /* cf_weight: weight of a pair from the weights
                                    of its two points (needs weights unless
                                    CF_WEIGHT_PRODUCT)                          */
-    int32_t reserved[6];
+    int32_t angular_grid;       /* angular counts only.  0: cells of the 3-D grid
+                                   on the unit vectors (chord reach).  n > 0:
+                                   the paper's angular grid (section
+                                   "Partitioning the particles on a grid:
+                                   angular correlation functions"):
+                                   declination bands one angular reach high,
+                                   cut into right-ascension cells 1/n of the
+                                   band's right-ascension reach wide, with
+                                   slices_per_reach declination slices per
+                                   band.  Counts are identical either way;
+                                   inputs must be unit vectors (squared norm
+                                   within 2^-20 of 1, else CF_EINVAL), which
+                                   RA/DEC input always gives.  At most 64.     */
+    int32_t reserved[5];
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
                                    in each bin (r, rp, or theta in degrees),
@@ -137,7 +150,9 @@ typedef enum { CF_WEIGHT_PRODUCT = 0, CF_WEIGHT_SUM = 1 } cf_weight;
 
 /* Statistics of the last counting call on a context. */
 typedef struct cf_stats {
-    int32_t grid[3];            /* x columns, y columns, z slices              */
+    int32_t grid[3];            /* x columns, y columns, z slices (angular
+                                   grid: declination bands, right-ascension
+                                   cells of all bands, slices per band)        */
     int32_t zreach;             /* z slices searched on each side              */
     double cell_width[3];       /* x, y column widths and z slice width        */
     int64_t n_blocks;           /* i-blocks of up to 64 points                 */
@@ -275,6 +290,35 @@ typedef struct cf_grid_plan {
 cf_status cf_plan_grid(const double lo[3], const double hi[3], double boxsize,
                        double reach_xy, double reach_z, int32_t slices_per_reach,
                        cf_grid_plan *out);
+
+/* Angular grid plan (host only, no device work) -- see
+   cf_options.angular_grid.  chord_reach: the largest chord 2 sin(theta_max/2)
+   of the bins; zlo, zhi: range of the unit vectors' z components (the
+   declination range).  Band b covers declinations from dec_lo + b *
+   band_height; its RA cells are columns col0 .. col0 + nra - 1, cell a
+   starting at RA 2 pi a / nra.  dra[d] bounds the right-ascension difference
+   (radians, round the circle) of two vectors within the reach, one in band b
+   and one in band b - 1 + d; a value >= pi means any.  bands receives nband
+   entries (at most max_bands, else CF_EINVAL). */
+typedef struct cf_sky_band {
+    int32_t col0;
+    int32_t nra;
+    double ra_scale;       /* nra / (2 pi)                                    */
+    double dra[3];
+} cf_sky_band;
+typedef struct cf_sky_plan {
+    int32_t nband;
+    int32_t ncol;          /* RA cells of all bands                           */
+    int32_t slices;        /* declination slices per band                     */
+    int32_t zreach;        /* slices searched on each side                    */
+    double dec_lo;         /* radians                                         */
+    double band_height;    /* radians, >= the angular reach                   */
+    double inv_slice;      /* slices per radian of declination                */
+    double theta_reach;    /* angular reach with its margins (radians)        */
+} cf_sky_plan;
+cf_status cf_plan_sky_grid(double chord_reach, double zlo, double zhi, int32_t slices,
+                           int32_t ra_refine, cf_sky_plan *out, cf_sky_band *bands,
+                           int32_t max_bands);
 
 /* Float32 decision bands (host only) -- for each squared edge E_k the float32
    interval [lo_k, hi_k] outside which a float32-evaluated separation decides

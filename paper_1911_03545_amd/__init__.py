@@ -39,7 +39,7 @@ EXPORTED_SYMBOLS = (
     "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
-    "cf_plan_grid", "cf_fp32_bands",
+    "cf_plan_grid", "cf_plan_sky_grid", "cf_fp32_bands",
 )
 
 
@@ -60,7 +60,8 @@ class cf_options(ctypes.Structure):
                 ("output_on_device", ctypes.c_int32), ("theta_unit_vectors", ctypes.c_int32),
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("weight_type", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+                ("weight_type", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5),
                 ("ravg", ctypes.c_void_p)]
 
 
@@ -84,6 +85,18 @@ class cf_grid_plan(ctypes.Structure):
                 ("n", ctypes.c_int32 * 3), ("zreach", ctypes.c_int32),
                 ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("boxsize", ctypes.c_double), ("ncell", ctypes.c_int64)]
+
+
+class cf_sky_band(ctypes.Structure):
+    _fields_ = [("col0", ctypes.c_int32), ("nra", ctypes.c_int32),
+                ("ra_scale", ctypes.c_double), ("dra", ctypes.c_double * 3)]
+
+
+class cf_sky_plan(ctypes.Structure):
+    _fields_ = [("nband", ctypes.c_int32), ("ncol", ctypes.c_int32),
+                ("slices", ctypes.c_int32), ("zreach", ctypes.c_int32),
+                ("dec_lo", ctypes.c_double), ("band_height", ctypes.c_double),
+                ("inv_slice", ctypes.c_double), ("theta_reach", ctypes.c_double)]
 
 
 class PairCountError(RuntimeError):
@@ -152,6 +165,9 @@ def load_library(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.cf_plan_grid.argtypes = [vp, vp, dbl, dbl, dbl, i32, ctypes.POINTER(cf_grid_plan)]
     lib.cf_plan_grid.restype = ctypes.c_int
+    lib.cf_plan_sky_grid.argtypes = [dbl, dbl, dbl, i32, i32, ctypes.POINTER(cf_sky_plan),
+                                     vp, i32]
+    lib.cf_plan_sky_grid.restype = ctypes.c_int
     lib.cf_fp32_bands.argtypes = [vp, i32, i32, dbl, vp, vp]
     lib.cf_fp32_bands.restype = ctypes.c_int
     _lib = lib
@@ -183,6 +199,24 @@ def plan_grid(lo, hi, boxsize: float, reach_xy: float, reach_z: float,
     return {"n": list(p.n), "width": list(p.width), "extent": list(p.extent),
             "inv_width": list(p.inv_width), "lo": list(p.lo), "zreach": p.zreach,
             "periodic": p.periodic, "ncell": p.ncell}
+
+
+def plan_sky_grid(chord_reach: float, zlo: float, zhi: float, slices: int = 16,
+                  ra_refine: int = 1) -> dict:
+    """Host-only angular grid plan (declination bands, right-ascension cells)."""
+    lib = load_library()
+    p = cf_sky_plan()
+    bands = (cf_sky_band * 1024)()
+    st = lib.cf_plan_sky_grid(float(chord_reach), float(zlo), float(zhi), int(slices),
+                              int(ra_refine), ctypes.byref(p), ctypes.addressof(bands), 1024)
+    if st != CF_OK:
+        raise PairCountError(st, "cf_plan_sky_grid failed")
+    out = {k: getattr(p, k) for k, _ in cf_sky_plan._fields_}
+    out["col0"] = np.array([bands[k].col0 for k in range(p.nband)], dtype=np.int64)
+    out["nra"] = np.array([bands[k].nra for k in range(p.nband)], dtype=np.int64)
+    out["ra_scale"] = np.array([bands[k].ra_scale for k in range(p.nband)])
+    out["dra"] = np.array([list(bands[k].dra) for k in range(p.nband)])
+    return out
 
 
 def fp32_bands(edges_sq, ndim: int, coord_scale: float):
@@ -448,10 +482,13 @@ class PairCounter:
 
     def count_theta(self, ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None,
                     precision="fp64", w1=None, w2=None, options=None, unit_vectors=None,
-                    weight_type=None, ravg=False):
+                    weight_type=None, ravg=False, angular_grid=None):
         """DD(theta)/DR(theta) from RA/DEC in degrees (or unit vectors when
         ``unit_vectors=(v1, v2)`` is given), plus the mean angle per bin in
-        degrees when ``ravg``."""
+        degrees when ``ravg``.  ``angular_grid=n`` (n > 0) uses declination
+        bands and right-ascension cells (1/n of the reach) instead of 3-D
+        cells on the unit vectors."""
+        grid = {} if angular_grid is None else {"angular_grid": angular_grid}
         e = np.ascontiguousarray(theta_edges_deg, dtype=np.float64)
         nb = e.size - 1
         rv = np.zeros(nb, dtype=np.float64) if ravg else None
@@ -459,11 +496,11 @@ class PairCounter:
             v1, v2 = unit_vectors
             c1 = _Cat(v1, w1)
             c2 = None if v2 is None else _Cat(v2, w2)
-            optp = self._opts(options, weight_type, rv, theta_unit_vectors=1)
+            optp = self._opts(options, weight_type, rv, theta_unit_vectors=1, **grid)
         else:
             c1 = _Cat((ra1, dec1), w1, two_columns=True)
             c2 = None if ra2 is None else _Cat((ra2, dec2), w2, two_columns=True)
-            optp = self._opts(options, weight_type, rv)
+            optp = self._opts(options, weight_type, rv, **grid)
         counts = np.zeros(nb, dtype=np.uint64)
         wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
         st = self._lib.count_pairs_theta_ex(

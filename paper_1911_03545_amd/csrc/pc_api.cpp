@@ -31,7 +31,7 @@ enum BufId {
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
-    B_BINS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_RHIST, B_OUTR, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
+    B_BINS, B_BANDS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_RHIST, B_OUTR, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
     B_COUNT
 };
 
@@ -505,6 +505,11 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "angular counts are never periodic");
     if (sky && boxsize > 0.0)
         return fail(c, CF_EINVAL, "on-sky counts are never periodic");
+    if (opt.angular_grid < 0 || opt.angular_grid > 64)
+        return fail(c, CF_EINVAL, "angular_grid must be in [0, 64]");
+    if (opt.angular_grid > 0 && !theta)
+        return fail(c, CF_EINVAL, "angular_grid applies to angular counts only");
+    const bool sky_grid = theta && opt.angular_grid > 0;
 
     // theta: chord edges c_k = 2 sin(theta_k / 2) on the host
     std::vector<double> lin(edges, edges + nb + 1);
@@ -569,7 +574,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     const size_t p_cats2 = p_cats1 + align256(sizeof(pc_cat) * (size_t)ncat);
     const size_t p_bins = p_cats2 + align256(sizeof(pc_cat));
     const size_t bins_cap = 256 * 1024 + 64 * (size_t)(nb + npi + 2);
-    const size_t p_out = p_bins + bins_cap;
+    const size_t p_sky = p_bins + bins_cap;
+    const size_t p_out = p_sky + (sky_grid ? align256(sizeof(pc_band) * PC_MAX_BANDS) : 0);
     ctl.pin_need = p_out + (sizeof(uint64_t) + 2 * sizeof(double)) * nout;
     ctl.p_misc = p_misc;
     ctl.p_out = p_out;
@@ -651,6 +657,21 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
                     "periodic box needs every reach (r, rp, pi) at most boxsize/3");
     if (rc)
         return fail(c, (cf_status)rc, "grid planning failed");
+    if (sky_grid) {
+        // declination bands and right-ascension cells on the unit vectors
+        std::vector<pc_band> bands;
+        rc = pc::plan_sky_grid(lin[nb], lo[2], hi[2], opt.slices_per_reach, opt.angular_grid,
+                               &g, &bands);
+        if (rc)
+            return fail(c, (cf_status)rc, "angular grid planning failed");
+        const size_t bytes = sizeof(pc_band) * bands.size();
+        if ((st2 = ensure(c, B_BANDS, bytes)))
+            return st2;
+        memcpy(pin + p_sky, bands.data(), bytes);
+        HIPCHK(hipMemcpyAsync(c->buf[B_BANDS].p, pin + p_sky, bytes, hipMemcpyHostToDevice,
+                              c->stream));
+        g.bands = dptr<pc_band>(c, B_BANDS);
+    }
     if ((int64_t)ncat * g.ncell + 1 > (int64_t)0x7fffffff)
         return fail(c, CF_EINVAL, "too many cells for this batch; use fewer z slices");
     double scale = periodic ? boxsize : 0.0;
@@ -791,7 +812,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     {
         const int64_t sh[] = {metric, theta ? 1 : 0, ncat, autocorr ? 1 : 0, n1, n2, nb, npi,
                               (int64_t)prec, opt.slices_per_reach, chunk, g.n[0], g.n[1],
-                              g.n[2], weighted ? 1 : 0};
+                              g.n[2], weighted ? 1 : 0, opt.angular_grid};
         key_add(shape, sh, sizeof(sh));
         key_add(shape, &boxsize, sizeof(boxsize));
         key_add(shape, &pimax, sizeof(pimax));
@@ -998,6 +1019,9 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_ERANGE, "periodic coordinate outside [0, boxsize]");
     if (hflags & PC_FLAG_WEIGHT)
         return fail(c, CF_EINVAL, "non-finite weight");
+    if (hflags & PC_FLAG_UNIT)
+        return fail(c, CF_EINVAL,
+                    "the angular grid needs unit vectors (squared norm within 2^-20 of 1)");
     int32_t sizes[2];
     memcpy(sizes, hm + M_SIZES, sizeof(sizes));
     if (async_items && (hflags & PC_FLAG_ITEMS)) {
@@ -1034,6 +1058,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         S.grid[k] = g.n[k];
         S.cell_width[k] = g.width[k];
     }
+    if (sky_grid)
+        S.grid[0] = g.nband;
     S.zreach = g.zreach;
     S.slices_per_reach = opt.slices_per_reach > 0 ? opt.slices_per_reach : 16;
     S.chunk = chunk;
@@ -1248,8 +1274,9 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
         tuned_opt = *opt_in;
         tuned_opt.autotune = 0;
         tuned_opt.collect_timing = 0;
-        const std::vector<int64_t> tk =
+        std::vector<int64_t> tk =
             tune_key(metric, theta, d1, ncat, d2, edges, nb, pimax, npi, boxsize, prec);
+        tk.push_back(opt_in->angular_grid);
         auto it = c->tuned.find(tk);
         if (it == c->tuned.end()) {
             RunCtl probe;

@@ -44,9 +44,29 @@
 // sight; MOCKS: rp and pi with the line of sight through the pair midpoint
 enum { PC_METRIC_R = 0, PC_METRIC_RPPI = 1, PC_METRIC_MOCKS = 2 };
 
+// A declination band of the angular grid: its right-ascension cells are the
+// columns col0 .. col0 + nra - 1, each 2 pi / nra wide.  dra[d] bounds the
+// right-ascension difference (radians, taken round the circle) of two unit
+// vectors within the angular reach when one lies in this band and the other
+// in band b - 1 + d; a value >= pi means any difference.
+struct pc_band {
+    int32_t col0;
+    int32_t nra;
+    double ra_scale;   // nra / (2 pi)
+    double dra[3];
+};
+
+#define PC_MAX_BANDS 1024
+#define PC_MAX_RA 4096
+#define PC_MAX_SKY_COLS (1 << 20)
+
 // Cell grid: x/y columns of width >= the transverse reach, z slices.
 // Cell id = (ix * ny + iy) * nz + iz, so columns are contiguous runs of cells
 // ordered by z.
+//
+// The angular grid (nband > 0, unit vectors only) keeps this layout with
+// n = {1, columns, slices per band}: a column is one right-ascension cell of
+// one declination band, and a slice a declination interval inside the band.
 struct pc_grid {
     double lo[3];
     double extent[3];
@@ -62,6 +82,13 @@ struct pc_grid {
     // fixed-point z of the float32 rp/pi path: Zq = round((z - lo_z) * zq_inv)
     // + 2^30 as uint32 bits, one pi bin = 2^zq_shift quanta
     double zq_inv;
+    // angular grid: declination bands of nband * n[2] slices, slice index
+    // floor((dec - dec_lo) * inv_hs); bands is a device table of nband entries
+    int32_t nband;
+    int32_t ra_refine;
+    double dec_lo;
+    double inv_hs;
+    const pc_band *bands;
 };
 
 // A block: up to 64 consecutive sorted points of one column (one per lane).

@@ -161,6 +161,42 @@ __device__ __forceinline__ int cell_coord(double d, double inv, int n)
     return (int)t;
 }
 
+// Column and slice of a point; non-finite coordinates and coordinates outside
+// a periodic box raise flags.  Angular grid: the declination slice and the
+// right-ascension cell of the vector's direction (atan2 of its components,
+// so the vector need not be exactly unit; its squared norm is checked to lie
+// within 2^-20 of 1, the bound the grid's reach was planned for).
+template <bool SKY>
+__device__ __forceinline__ int2 point_cell(const pc_grid &g, const double c[3], unsigned &fl)
+{
+    for (int a = 0; a < 3; a++) {
+        if (!isfinite(c[a]))
+            fl |= PC_FLAG_NONFINITE;
+        else if (g.periodic && (c[a] < 0.0 || c[a] > g.boxsize))
+            fl |= PC_FLAG_RANGE;
+    }
+    if constexpr (SKY) {
+        const double rho2 = c[0] * c[0] + c[1] * c[1];
+        const double r2 = rho2 + c[2] * c[2];
+        if (!(fabs(r2 - 1.0) <= 0x1p-20))
+            fl |= PC_FLAG_UNIT;
+        const double dec = atan2(c[2], sqrt(rho2));
+        double ra = atan2(c[1], c[0]);
+        if (ra < 0.0)
+            ra += 2.0 * M_PI;
+        const int S = g.n[2];
+        const int gs = cell_coord(dec - g.dec_lo, g.inv_hs, g.nband * S);
+        const int b = gs / S;
+        const pc_band &B = g.bands[b];
+        return make_int2(B.col0 + cell_coord(ra, B.ra_scale, B.nra), gs - b * S);
+    } else {
+    const int ix = cell_coord(c[0] - g.lo[0], g.inv_w[0], g.n[0]);
+    const int iy = cell_coord(c[1] - g.lo[1], g.inv_w[1], g.n[1]);
+    const int iz = cell_coord(c[2] - g.lo[2], g.inv_w[2], g.n[2]);
+    return make_int2(ix * g.n[1] + iy, iz);
+    }
+}
+
 // Catalogue of flattened index i: the last catalogue starting at or before
 // i (empty catalogues share their start with the next one, which wins).
 __device__ __forceinline__ int find_cat(const pc_cat *cats, int ncat, int64_t i)
@@ -181,6 +217,7 @@ __device__ __forceinline__ int find_cat(const pc_cat *cats, int ncat, int64_t i)
 // checks (finite, inside the periodic box, finite weights) raise flags.
 // It also writes each point as one 32-byte record (x, y, z, w) in input
 // order, so that the gather after the sort reads one line per point.
+template <bool SKY>
 __global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid g,
                              unsigned *cnt, int32_t *cell_of, int32_t *rank_of, double4 *rec,
                              unsigned *flags)
@@ -192,19 +229,12 @@ __global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid
         const pc_cat &k = cats[ci];
         const int64_t j = i - k.off;
         const double c[3] = {ld(k.x, k.f32, j), ld(k.y, k.f32, j), ld(k.z, k.f32, j)};
-        int ia[3];
-        for (int a = 0; a < 3; a++) {
-            if (!isfinite(c[a]))
-                fl |= PC_FLAG_NONFINITE;
-            else if (g.periodic && (c[a] < 0.0 || c[a] > g.boxsize))
-                fl |= PC_FLAG_RANGE;
-            ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
-        }
+        const int2 cs = point_cell<SKY>(g, c, fl);
         // unit weights without weights (the mean-separation sums use them)
         const double w = k.w ? ld(k.w, k.wf32, j) : 1.0;
         if (!isfinite(w))
             fl |= PC_FLAG_WEIGHT;
-        const int cell = (int)(ci * g.ncell) + (ia[0] * g.n[1] + ia[1]) * g.n[2] + ia[2];
+        const int cell = (int)(ci * g.ncell) + cs.x * g.n[2] + cs.y;
         cell_of[i] = cell;
         rec[i] = make_double4(c[0], c[1], c[2], w);
         rank_of[i] = (int32_t)atomicAdd(&cnt[cell], 1u);
@@ -300,6 +330,7 @@ __global__ void k_grid_layout(int ncat, const pc_cat *cats, int32_t chunk, int32
 }
 
 // Level 1, counting: one workgroup per chunk, LDS histogram of ncolc columns.
+template <bool SKY>
 __global__ void k_cell_hist(int ncat, const pc_cat *cats, const int32_t *lay, pc_grid g,
                             int32_t chunk, int32_t ncolc, int32_t *cell_of, int32_t *rank_of,
                             double4 *rec, int32_t *wcnt, unsigned *flags)
@@ -325,20 +356,13 @@ __global__ void k_cell_hist(int ncat, const pc_cat *cats, const int32_t *lay, pc
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const int64_t j = i - ct.off;
         const double c[3] = {ld(ct.x, ct.f32, j), ld(ct.y, ct.f32, j), ld(ct.z, ct.f32, j)};
-        int ia[3];
-        for (int a = 0; a < 3; a++) {
-            if (!isfinite(c[a]))
-                fl |= PC_FLAG_NONFINITE;
-            else if (g.periodic && (c[a] < 0.0 || c[a] > g.boxsize))
-                fl |= PC_FLAG_RANGE;
-            ia[a] = cell_coord(c[a] - g.lo[a], g.inv_w[a], g.n[a]);
-        }
+        const int2 cs = point_cell<SKY>(g, c, fl);
         // unit weights without weights (the mean-separation sums use them)
         const double wt = ct.w ? ld(ct.w, ct.wf32, j) : 1.0;
         if (!isfinite(wt))
             fl |= PC_FLAG_WEIGHT;
-        const int col = ia[0] * g.n[1] + ia[1];
-        cell_of[i] = (int)((int64_t)k * g.ncell) + col * g.n[2] + ia[2];
+        const int col = cs.x;
+        cell_of[i] = (int)((int64_t)k * g.ncell) + col * g.n[2] + cs.y;
         rec[i] = make_double4(c[0], c[1], c[2], wt);
         rank_of[i] = (int32_t)atomicAdd(&hist[col], 1u);
     }
@@ -491,9 +515,79 @@ struct SegCtx {
 // periodic wrap past the top face), and the four columns (0,+1), (+1,-1),
 // (+1,0), (+1,+1) over the full z window.  Cross-correlation visits all nine
 // columns over the full window.
+// Angular grid: the block's own cell and the right-ascension cells of its
+// own and the two neighbouring declination bands that come within the
+// right-ascension reach of the block's cell (its east and west edges
+// projected onto the target band, widened by the reach, then every target
+// cell met, each once even where the range wraps round).  Declination slices
+// outside zreach of the block's slices are skipped.  Autocorrelation visits
+// only cells after the block's own (a cell pair from its lower-numbered
+// cell), and the own cell forward along the sorted order.
 template <class F>
+__device__ void sky_segments(const SegCtx &c, const pc_block &b, F &&f)
+{
+    const int S = c.g.n[2], zr = c.g.zreach, nband = c.g.nband;
+    const int ncolc = c.g.n[1];
+    const int lcol = b.col % ncolc;
+    const int cbase = b.col - lcol;
+    int band = 0, hi = nband - 1;   // the last band whose first column is <= lcol
+    while (band < hi) {
+        const int mid = (band + hi + 1) >> 1;
+        if (c.g.bands[mid].col0 <= lcol)
+            band = mid;
+        else
+            hi = mid - 1;
+    }
+    const pc_band &B = c.g.bands[band];
+    const int a = lcol - B.col0;
+    const int sa = c.cell1_sorted[b.i0] % S;
+    const int sb = c.cell1_sorted[b.i0 + b.ni - 1] % S;
+    if (c.autocorr) {
+        if (b.ni > 1)
+            f(b.i0 + 1, b.i0 + b.ni, 0u, 1);
+        const int jend = c.start2[(int64_t)b.col * S + min(sb + zr, S - 1) + 1];
+        if (jend > b.i0 + b.ni)
+            f(b.i0 + b.ni, jend, 0u, 0);
+    }
+    for (int d = c.autocorr ? 0 : -1; d <= 1; d++) {
+        const int b2 = band + d;
+        if (b2 < 0 || b2 >= nband)
+            continue;
+        const int a0 = max(sa - zr - d * S, 0), a1 = min(sb + zr - d * S, S - 1);
+        if (a0 > a1)
+            continue;
+        const pc_band &C = c.g.bands[b2];
+        const double D = d < 0 ? B.dra[0] : (d == 0 ? B.dra[1] : B.dra[2]);
+        int k0 = 0, k1 = C.nra - 1;
+        if (D < M_PI) {
+            const double x0 = ((double)a / B.ra_scale - D) * C.ra_scale;
+            const double x1 = ((double)(a + 1) / B.ra_scale + D) * C.ra_scale;
+            const int f0 = (int)floor(x0), f1 = (int)floor(x1);
+            if (f1 - f0 + 1 < C.nra) {
+                k0 = f0;
+                k1 = f1;
+            }
+        }
+        for (int k = k0; k <= k1; k++) {
+            int a2 = k % C.nra;
+            if (a2 < 0)
+                a2 += C.nra;
+            const int col2 = cbase + C.col0 + a2;
+            if (c.autocorr && col2 <= b.col)
+                continue;
+            const int64_t base = (int64_t)col2 * S;
+            f(c.start2[base + a0], c.start2[base + a1 + 1], 0u, 0);
+        }
+    }
+}
+
+template <bool SKY, class F>
 __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
 {
+    if constexpr (SKY) {
+        sky_segments(c, b, f);
+        return;
+    }
     const int nx = c.g.n[0], ny = c.g.n[1], nz = c.g.n[2];
     // columns are numbered across catalogues: catalogue k owns columns
     // k * nx * ny ..; neighbours stay inside the block's own catalogue
@@ -563,6 +657,7 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
     }
 }
 
+template <bool SKY>
 __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
                              const pc_block *blocks, SegCtx c, int chunk, int32_t *icnt,
                              unsigned long long *cand)
@@ -573,7 +668,7 @@ __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
          bi += gridDim.x * blockDim.x) {
         const pc_block b = blocks[bi];
         int total = 0;
-        for_each_segment(c, b, [&](int j0, int j1, unsigned, int tri) {
+        for_each_segment<SKY>(c, b, [&](int j0, int j1, unsigned, int tri) {
             if (j1 <= j0)
                 return;
             total += (j1 - j0 + chunk - 1) / chunk;
@@ -588,6 +683,7 @@ __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
 
 // Items beyond `cap` are not written; the flag PC_FLAG_ITEMS reports them
 // (a replayed call whose inputs now need more items than it was built for).
+template <bool SKY>
 __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const pc_block *blocks,
                             SegCtx c, int chunk, const int32_t *ioff, pc_item *items, int32_t cap,
                             unsigned *flags)
@@ -598,7 +694,7 @@ __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const p
         const pc_block b = blocks[bi];
         const int cat = b.col / (c.g.n[0] * c.g.n[1]);
         int o = ioff[bi];
-        for_each_segment(c, b, [&](int j0, int j1, unsigned dcode, int tri) {
+        for_each_segment<SKY>(c, b, [&](int j0, int j1, unsigned dcode, int tri) {
             for (int j = j0; j < j1; j += chunk) {
                 pc_item it;
                 it.i0 = b.i0;
@@ -745,8 +841,8 @@ hipError_t launch_cell_index(hipStream_t s, int ncat, const pc_cat *cats, int64_
                              const pc_grid &g, unsigned *cnt, int32_t *cell_of, int32_t *rank_of,
                              void *rec, unsigned *flags)
 {
-    hipLaunchKernelGGL(k_cell_index, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot,
-                       g, cnt, cell_of, rank_of, static_cast<double4 *>(rec), flags);
+    hipLaunchKernelGGL(g.nband > 0 ? k_cell_index<true> : k_cell_index<false>,
+                       dim3(grid_for(ntot)), dim3(kThreads), 0, s, ncat, cats, ntot, g, cnt, cell_of, rank_of, static_cast<double4 *>(rec), flags);
     return hipGetLastError();
 }
 
@@ -816,7 +912,8 @@ hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t nto
     if (e != hipSuccess)
         return e;
     if (n_chunks > 0)
-        hipLaunchKernelGGL(k_cell_hist, dim3((unsigned)n_chunks), dim3(kThreads),
+        hipLaunchKernelGGL(g.nband > 0 ? k_cell_hist<true> : k_cell_hist<false>,
+                           dim3((unsigned)n_chunks), dim3(kThreads),
                            sizeof(unsigned) * (size_t)ncolc, s, ncat, cats, lay, g, chunk, ncolc,
                            cell_of, rank_of, static_cast<double4 *>(rec), wcnt, flags);
     if ((e = hipGetLastError()) != hipSuccess)
@@ -856,7 +953,8 @@ hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblo
                              int32_t *icnt, unsigned long long *cand)
 {
     SegCtx c{g, start2, cell1_sorted, autocorr};
-    hipLaunchKernelGGL(k_item_count, dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
+    hipLaunchKernelGGL(g.nband > 0 ? k_item_count<true> : k_item_count<false>,
+                       dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
                        nblocks_dev, blocks, c, chunk, icnt, cand);
     return hipGetLastError();
 }
@@ -867,7 +965,8 @@ hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nbloc
                             const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags)
 {
     SegCtx c{g, start2, cell1_sorted, autocorr};
-    hipLaunchKernelGGL(k_item_emit, dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
+    hipLaunchKernelGGL(g.nband > 0 ? k_item_emit<true> : k_item_emit<false>,
+                       dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
                        nblocks_dev, blocks, c, chunk, ioff, items, cap, flags);
     return hipGetLastError();
 }

@@ -13,6 +13,7 @@ namespace pc {
 #define PC_FLAG_WEIGHT 4u
 #define PC_FLAG_RADEC 8u
 #define PC_FLAG_ITEMS 16u
+#define PC_FLAG_UNIT 32u      // angular grid: a vector whose squared norm is not within 2^-20 of 1
 
 struct SweepArgs {
     const pc_item *items;

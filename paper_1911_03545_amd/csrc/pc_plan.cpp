@@ -131,6 +131,118 @@ int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
     return CF_OK;
 }
 
+// Angular grid of section "Partitioning the particles on a grid: angular
+// correlation functions": declination bands at least one angular reach high
+// (two points further apart in declination are further apart on the sky), each
+// split into right-ascension cells whose reach follows from the haversine
+// relation (the section's angular-distance equation): for two points in
+// bands b, b' whose cos(dec) is at least c_b, c_b', sin(dRA / 2) <=
+// sin(theta / 2) / sqrt(c_b c_b').  With c_b = c_b' this is the paper's
+// right-ascension binning equation; the product form is tighter across bands.
+// Cells are 1 / ra_refine of the band's own reach wide ("Sub-dividing the
+// cells").  Inside a band, `slices` declination slices give the window search.
+//
+// Inputs are unit vectors whose squared norm is within 2^-20 of 1 (the
+// gridding kernel checks it), so their directions are within 2^-20 of the
+// vectors and a chord below `chord_reach` between vectors means an angle
+// below 2 asin((chord_reach + 2^-19) / 2) between directions.  Every derived
+// reach carries a relative margin of 2^-20 and an absolute one of 2^-40
+// radians, far above the rounding of the device's atan2 and of the cell
+// arithmetic.  zlo, zhi bound the z components (declination range).
+int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra_refine,
+                  pc_grid *g, std::vector<pc_band> *bands)
+{
+    if (!(chord_reach > 0.0) || !isfinite(chord_reach) || !isfinite(zlo) || !isfinite(zhi) ||
+        zhi < zlo)
+        return CF_EINVAL;
+    if (slices <= 0)
+        slices = 16;
+    slices = std::min(slices, 4096);
+    if (ra_refine <= 0)
+        ra_refine = 1;
+    const double cc = chord_reach * (1.0 + 0x1p-40) + 0x1p-19;
+    const double theta = (cc >= 2.0 ? M_PI : 2.0 * asin(0.5 * cc)) * (1.0 + 0x1p-20) + 0x1p-40;
+    // bands are a little higher than the reach, so that a declination window
+    // of the reach never spans more than the neighbouring band
+    const double hmin = theta * (1.0 + 0x1p-20);
+    const double za = std::max(-1.0, zlo - 0x1p-18), zb = std::min(1.0, zhi + 0x1p-18);
+    const double dlo = std::max(-M_PI_2, asin(za) - 0x1p-30);
+    const double dhi = std::min(M_PI_2, asin(zb) + 0x1p-30);
+    const double span = dhi - dlo;
+    int nb = (int)std::min(std::max(floor(span / hmin), 1.0), (double)PC_MAX_BANDS);
+    while (nb > 1 && span / nb < hmin)
+        nb--;
+    const double h = std::max(span / nb, hmin);
+
+    // lower bound of cos(dec) over each band (its edge furthest from the
+    // equator, widened by the margin)
+    std::vector<double> cmin(nb);
+    for (int b = 0; b < nb; b++) {
+        const double d0 = dlo + b * h, d1 = dlo + (b + 1) * h;
+        const double m = std::min(M_PI_2, std::max(fabs(d0), fabs(d1)) + 0x1p-30);
+        cmin[b] = std::max(0.0, cos(m));
+    }
+    const double s2 = sin(0.5 * std::min(theta, M_PI));
+    auto reach_ra = [&](int b, int b2) {
+        if (b2 < 0 || b2 >= nb)
+            return 8.0;
+        const double den = sqrt(cmin[b] * cmin[b2]);
+        if (!(den > 0.0) || s2 >= den)
+            return 8.0;
+        const double d = 2.0 * asin(s2 / den) * (1.0 + 0x1p-20) + 0x1p-40;
+        return d >= M_PI ? 8.0 : d;
+    };
+    bands->assign(nb, pc_band{});
+    std::vector<int> nra(nb);
+    for (int b = 0; b < nb; b++) {
+        const double d = reach_ra(b, b);
+        const double want = d >= M_PI ? 1.0 : floor(2.0 * M_PI * ra_refine / d);
+        nra[b] = (int)std::min(std::max(want, 1.0), (double)PC_MAX_RA);
+    }
+    // keep the column count bounded (coarser cells stay correct)
+    auto total = [&]() {
+        int64_t t = 0;
+        for (int b = 0; b < nb; b++)
+            t += nra[b];
+        return t;
+    };
+    while (total() > PC_MAX_SKY_COLS)
+        for (int b = 0; b < nb; b++)
+            nra[b] = std::max(1, nra[b] / 2);
+    const int64_t ncol = total();
+    while (slices > 1 && ncol * slices > (int64_t(1) << 26))
+        slices = (slices + 1) / 2;
+    int32_t col0 = 0;
+    for (int b = 0; b < nb; b++) {
+        pc_band &B = (*bands)[b];
+        B.col0 = col0;
+        B.nra = nra[b];
+        B.ra_scale = nra[b] / (2.0 * M_PI);
+        for (int d = 0; d < 3; d++)
+            B.dra[d] = reach_ra(b, b - 1 + d);
+        col0 += nra[b];
+    }
+    g->n[0] = 1;
+    g->n[1] = (int32_t)ncol;
+    g->n[2] = slices;
+    g->ncell = ncol * slices;
+    g->nband = nb;
+    g->ra_refine = ra_refine;
+    g->dec_lo = dlo;
+    g->inv_hs = slices / h;
+    g->inv_w[0] = 0.0;
+    g->inv_w[1] = 0.0;
+    g->inv_w[2] = g->inv_hs;
+    g->width[0] = h;
+    g->width[1] = theta;
+    g->width[2] = h / slices;
+    const double r = theta * g->inv_hs;
+    const int zr = (int)floor(r * (1.0 + 0x1p-28) + 0x1p-28) + 1;
+    g->zreach = std::min(zr, slices);
+    g->bands = nullptr;
+    return CF_OK;
+}
+
 // Float32 decision bands.  The float32 sweep evaluates, per axis,
 //   X = fl32(fl64(x - lo)),  A_i = fl32(X_i + fl32(D)),  d32 = fl32(A_i - X_j)
 // and then s32 with one multiply and fused multiply-adds.  With S bounding
@@ -450,6 +562,41 @@ extern "C" cf_status cf_plan_grid(const double lo[3], const double hi[3],
     out->periodic = g.periodic;
     out->boxsize = g.boxsize;
     out->ncell = g.ncell;
+    return CF_OK;
+}
+
+static_assert(sizeof(cf_sky_band) == sizeof(pc_band), "cf_sky_band mirrors pc_band");
+
+extern "C" cf_status cf_plan_sky_grid(double chord_reach, double zlo, double zhi,
+                                      int32_t slices, int32_t ra_refine, cf_sky_plan *out,
+                                      cf_sky_band *bands, int32_t max_bands)
+{
+    if (!out || !bands)
+        return CF_EINVAL;
+    pc_grid g;
+    memset(&g, 0, sizeof(g));
+    std::vector<pc_band> b;
+    int rc = pc::plan_sky_grid(chord_reach, zlo, zhi, slices, ra_refine, &g, &b);
+    if (rc)
+        return (cf_status)rc;
+    if ((int64_t)b.size() > max_bands)
+        return CF_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->nband = g.nband;
+    out->ncol = g.n[1];
+    out->slices = g.n[2];
+    out->zreach = g.zreach;
+    out->dec_lo = g.dec_lo;
+    out->band_height = g.width[0];
+    out->inv_slice = g.inv_hs;
+    out->theta_reach = g.width[1];
+    for (size_t k = 0; k < b.size(); k++) {
+        bands[k].col0 = b[k].col0;
+        bands[k].nra = b[k].nra;
+        bands[k].ra_scale = b[k].ra_scale;
+        for (int d = 0; d < 3; d++)
+            bands[k].dra[d] = b[k].dra[d];
+    }
     return CF_OK;
 }
 

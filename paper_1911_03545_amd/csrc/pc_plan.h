@@ -19,6 +19,10 @@ struct HostBins {
 
 int plan_grid(const double lo[3], const double hi[3], double boxsize, double reach_xy,
               double reach_z, int slices_per_reach, pc_grid *g);
+// angular grid of unit vectors (overrides n, ncell, zreach and the slice
+// fields of a grid planned on the vectors' bounding box)
+int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra_refine,
+                  pc_grid *g, std::vector<pc_band> *bands);
 int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
                float *hi);
 // `priv`: size the lookup table for the private-histogram (batched) sweep
