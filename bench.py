@@ -313,6 +313,110 @@ def mocks_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def ref_pairs_box_cross(v1: np.ndarray, v2: np.ndarray, reach: float) -> int:
+    """Cross-correlation candidate pairs of the paper's default grid: cubic
+    cells of side >= reach over the joint bounding box, each cell of the
+    first catalogue against the 27 cells around it in the second."""
+    lo = np.minimum(v1.min(axis=0), v2.min(axis=0))
+    hi = np.maximum(v1.max(axis=0), v2.max(axis=0))
+    ext = np.maximum(hi - lo, reach)
+    n = np.maximum(np.floor(ext / (reach * (1 + 2 ** -28))).astype(np.int64), 1)
+
+    def hist(v):
+        idx = [np.minimum(((v[:, a] - lo[a]) * (n[a] / ext[a])).astype(np.int64), n[a] - 1)
+               for a in range(3)]
+        cid = (idx[0] * n[1] + idx[1]) * n[2] + idx[2]
+        return np.bincount(cid, minlength=int(n.prod())).reshape(n).astype(np.int64)
+
+    A, B = hist(v1), hist(v2)
+    Bp = np.pad(B, 1)
+    total = 0
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                total += int((A * Bp[1 + dx:1 + dx + n[0], 1 + dy:1 + dy + n[1],
+                                     1 + dz:1 + dz + n[2]]).sum())
+    return total
+
+
+def theta_bench(args):
+    """DD(theta) and DR(theta) on a 30-degree cap centred at (RA, DEC) =
+    (0, 30) (across the RA seam): D = 2e6 points, half uniform, half in
+    10 000 Gaussian blobs of width 0.1 degree; R = 5e6 uniform; 20 log bins in
+    [0.01, 10] degrees; RA/DEC float64 in HBM.  Each statistic runs on the 3-D
+    chord grid and on the angular grid (declination bands, right-ascension
+    cells 1/n of the reach, n = 4, 8 (the default), 16; 32 declination slices
+    per band), in float32 + recheck and binary64.
+    Values are reference pairs (the paper's cubic cells of side
+    2 sin(5 degrees) on the unit vectors) per second."""
+    import torch
+    import paper_1911_03545_amd as pcm
+    import oracle
+    t0 = time.perf_counter()
+    ra, dec = synth.cap_radec(2_000_000, seed=4, radius_deg=30.0, clustered=True)
+    rr, rd = synth.cap_radec(5_000_000, seed=40, radius_deg=30.0)
+    gen_s = time.perf_counter() - t0
+    te = synth.log_edges(0.01, 10.0, 20)
+    lib = oracle.load()
+    vd = oracle.radec_to_unit(ra, dec, lib=lib)
+    vr = oracle.radec_to_unit(rr, rd, lib=lib)
+    reach = 2.0 * np.sin(0.5 * np.deg2rad(10.0))
+    wref = {"DD": ref_pairs_box(vd, reach), "DR": ref_pairs_box_cross(vd, vr, reach)}
+    dev = torch.device("cuda:0")
+    D = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ra, dec))
+    R = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (rr, rd))
+    torch.cuda.synchronize()
+    ctx = pcm.PairCounter(0, stream=torch.cuda.current_stream(dev))
+    runs = {}
+    ref_counts = {}
+    for stat in ("DD", "DR"):
+        other = (None, None) if stat == "DD" else R
+        for prec in ("fp32", "fp64"):
+            for grid in (-1, 4, 8, 16):
+                opts = pcm.default_options(collect_timing=1, angular_grid=grid)
+
+                def call():
+                    return ctx.count_theta(D[0], D[1], other[0], other[1], te, prec,
+                                           options=opts)
+                for _ in range(args.warmup):
+                    counts, _ = call()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(args.steps):
+                    counts, _ = call()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t) * 1e3 / args.steps
+                st = ctx.stats()
+                if stat not in ref_counts:
+                    ref_counts[stat] = counts.copy()
+                elif not np.array_equal(ref_counts[stat], counts):
+                    raise SystemExit(f"{stat} counts differ between grids / precisions")
+                key = f"{stat}_{prec}_" + ("chord" if grid < 0 else f"angular{grid}")
+                runs[key] = {"ms_per_step": ms,
+                             "value": wref[stat] / (ms / 1e3) / 1e9,
+                             "sweep_ms": st["t_sweep_ms"],
+                             "candidate_pairs": st["candidate_pairs"],
+                             "candidate_over_ref": st["candidate_pairs"] / wref[stat],
+                             "grid": st["grid"]}
+                print(key, json.dumps(runs[key]), flush=True)
+    best = min((k for k in runs if k.startswith("DD_fp32")), key=lambda k: runs[k]["ms_per_step"])
+    line = {
+        "metric": "Gpair-evals/s for DD(theta) N=2e6 on a 30-degree cap (reference pairs of "
+                  "the paper's cubic cells on the unit vectors)",
+        "value": runs[best]["value"], "unit": "Gpair-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": runs[best]["ms_per_step"], "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "DD(theta) / DR(theta): D 2e6 (half in 10000 blobs of 0.1 deg), "
+                               "R 5e6 uniform, 30-degree cap at (0, 30) across the RA seam, "
+                               "20 log bins [0.01, 10] deg, RA/DEC float64 in HBM",
+                   "best": best, "w_ref_pairs": wref, "generation_s": gen_s},
+        "runs": runs,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def ref_pairs_rppi(pts: np.ndarray, L: float, rpmax: float, pimax: float) -> int:
     """Unordered candidate pairs of the paper's default grid for rp/pi: cells
     of side >= rpmax in x, y and >= pimax along z, 13 forward neighbours plus
@@ -354,6 +458,9 @@ def main():
     ap.add_argument("--batch-cats", type=int, default=256)
     ap.add_argument("--mocks", action="store_true",
                     help="run the on-sky DD(rp,pi) benchmark (1e6-point mock) instead")
+    ap.add_argument("--theta", action="store_true",
+                    help="run the DD(theta)/DR(theta) benchmark (2e6 + 5e6 points on a cap, "
+                         "chord and angular grids) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures the single-GPU path only; "
@@ -366,6 +473,9 @@ def main():
         return
     if args.mocks:
         mocks_bench(args)
+        return
+    if args.theta:
+        theta_bench(args)
         return
     import torch
     import paper_1911_03545_amd as pcm

@@ -104,7 +104,8 @@ typedef struct cf_catalog {
    cf_default_options.  Zero fields take the defaults. */
 typedef struct cf_options {
     int32_t struct_size;        /* sizeof(cf_options)                          */
-    int32_t slices_per_reach;   /* z slices per line-of-sight reach (default 16) */
+    int32_t slices_per_reach;   /* z slices per line-of-sight reach (0: 16, or
+                                   32 per band on the angular grid)            */
     int32_t chunk;              /* max j points per work item (default 2048)   */
     int32_t output_on_device;   /* counts / wsum are device pointers           */
     int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC;
@@ -120,19 +121,21 @@ typedef struct cf_options {
     int32_t weight_type;        /* cf_weight: weight of a pair from the weights
                                    of its two points (needs weights unless
                                    CF_WEIGHT_PRODUCT)                          */
-    int32_t angular_grid;       /* angular counts only.  0: cells of the 3-D grid
-                                   on the unit vectors (chord reach).  n > 0:
-                                   the paper's angular grid (section
-                                   "Partitioning the particles on a grid:
-                                   angular correlation functions"):
-                                   declination bands one angular reach high,
-                                   cut into right-ascension cells 1/n of the
-                                   band's right-ascension reach wide, with
+    int32_t angular_grid;       /* angular counts only: the cell layout.  0
+                                   (default): the paper's angular grid
+                                   (section "Partitioning the particles on a
+                                   grid: angular correlation functions") with
+                                   8 right-ascension cells per reach.  n in
+                                   1..64: declination bands one angular reach
+                                   high, cut into right-ascension cells 1/n of
+                                   the band's right-ascension reach wide, with
                                    slices_per_reach declination slices per
-                                   band.  Counts are identical either way;
-                                   inputs must be unit vectors (squared norm
-                                   within 2^-20 of 1, else CF_EINVAL), which
-                                   RA/DEC input always gives.  At most 64.     */
+                                   band.  -1: 3-D cells on the unit vectors
+                                   (chord reach).  Counts are identical either
+                                   way.  The angular grid needs unit vectors
+                                   (squared norm within 2^-20 of 1, else
+                                   CF_EINVAL), which RA/DEC input always
+                                   gives.  Other statistics need 0.            */
     int32_t reserved[5];
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
@@ -170,7 +173,7 @@ typedef struct cf_stats {
     int32_t slices_per_reach;   /* z slices per reach used (after autotuning)  */
     int32_t chunk;              /* max j points per work item used             */
     int32_t replayed;           /* 1 when the call replayed a recorded graph   */
-    float reserved_f[1];
+    int32_t angular_grid;       /* angular grid refinement used (0: 3-D cells) */
 } cf_stats;
 
 typedef struct cf_ctx cf_ctx;

@@ -76,7 +76,7 @@ class cf_stats(ctypes.Structure):
                 ("t_finalize_ms", ctypes.c_float),
                 ("t_total_ms", ctypes.c_float),
                 ("slices_per_reach", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("replayed", ctypes.c_int32), ("reserved_f", ctypes.c_float * 1)]
+                ("replayed", ctypes.c_int32), ("angular_grid", ctypes.c_int32)]
 
 
 class cf_grid_plan(ctypes.Structure):
@@ -485,9 +485,9 @@ class PairCounter:
                     weight_type=None, ravg=False, angular_grid=None):
         """DD(theta)/DR(theta) from RA/DEC in degrees (or unit vectors when
         ``unit_vectors=(v1, v2)`` is given), plus the mean angle per bin in
-        degrees when ``ravg``.  ``angular_grid=n`` (n > 0) uses declination
-        bands and right-ascension cells (1/n of the reach) instead of 3-D
-        cells on the unit vectors."""
+        degrees when ``ravg``.  ``angular_grid``: None / 0 the default angular
+        grid, n > 0 declination bands and right-ascension cells 1/n of the
+        reach, -1 3-D cells on the unit vectors."""
         grid = {} if angular_grid is None else {"angular_grid": angular_grid}
         e = np.ascontiguousarray(theta_edges_deg, dtype=np.float64)
         nb = e.size - 1

@@ -75,8 +75,11 @@ struct cf_ctx {
     bool g_wsum = false;
     bool g_ravg = false;
     cf_stats gstats;
-    // autotuned (slices_per_reach, chunk) per workload class
-    std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned;
+    // autotuned choices per workload class
+    struct Tuned {
+        int32_t slices_per_reach, chunk, angular_grid;
+    };
+    std::map<std::vector<int64_t>, Tuned> tuned;
 };
 
 namespace {
@@ -505,11 +508,19 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "angular counts are never periodic");
     if (sky && boxsize > 0.0)
         return fail(c, CF_EINVAL, "on-sky counts are never periodic");
-    if (opt.angular_grid < 0 || opt.angular_grid > 64)
-        return fail(c, CF_EINVAL, "angular_grid must be in [0, 64]");
-    if (opt.angular_grid > 0 && !theta)
+    if (opt.angular_grid < -1 || opt.angular_grid > 64)
+        return fail(c, CF_EINVAL, "angular_grid must be in [-1, 64]");
+    if (opt.angular_grid != 0 && !theta)
         return fail(c, CF_EINVAL, "angular_grid applies to angular counts only");
+    // angular counts default to the angular grid with 8 right-ascension
+    // cells per reach; -1 selects 3-D cells on the unit vectors
+    if (theta && opt.angular_grid == 0)
+        opt.angular_grid = 8;
+    if (opt.angular_grid < 0)
+        opt.angular_grid = 0;
     const bool sky_grid = theta && opt.angular_grid > 0;
+    if (opt.slices_per_reach <= 0)
+        opt.slices_per_reach = sky_grid ? 32 : 16;
 
     // theta: chord edges c_k = 2 sin(theta_k / 2) on the host
     std::vector<double> lin(edges, edges + nb + 1);
@@ -1061,7 +1072,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (sky_grid)
         S.grid[0] = g.nband;
     S.zreach = g.zreach;
-    S.slices_per_reach = opt.slices_per_reach > 0 ? opt.slices_per_reach : 16;
+    S.slices_per_reach = opt.slices_per_reach;
+    S.angular_grid = opt.angular_grid;
     S.chunk = chunk;
     S.n_blocks = hcounts[1];
     S.n_items = hcounts[0];
@@ -1265,8 +1277,9 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
                 double boxsize, cf_precision prec, uint64_t *counts, double *wsum,
                 const cf_options *opt_in)
 {
-    // autotuning: pick slices_per_reach and chunk by timing whole calls on
-    // the live input (coordinate descent over both), once per workload class
+    // autotuning: pick slices_per_reach and chunk (and, for angular counts,
+    // the right-ascension refinement of the angular grid) by timing whole
+    // calls on the live input (coordinate descent), once per workload class
     cf_options tuned_opt;
     const cf_options *opt = opt_in;
     if (c && opt_in && opt_in->struct_size == (int32_t)sizeof(cf_options) && opt_in->autotune &&
@@ -1280,11 +1293,18 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
         auto it = c->tuned.find(tk);
         if (it == c->tuned.end()) {
             RunCtl probe;
-            auto time_call = [&](int32_t spr, int32_t chunk, double *ms) -> cf_status {
+            // the angular grid of angular counts is tuned too when left at
+            // its default
+            const bool tune_ang = theta && opt_in->angular_grid == 0;
+            int32_t best_ang = tune_ang ? 8 : opt_in->angular_grid;
+            int32_t best_spr = theta && best_ang >= 0 ? 32 : 16, best_chunk = 2048;
+            auto time_call = [&](int32_t spr, int32_t chunk, int32_t ang,
+                                 double *ms) -> cf_status {
                 cf_options o = tuned_opt;
                 o.use_graph = 0;
                 o.slices_per_reach = spr;
                 o.chunk = chunk;
+                o.angular_grid = ang;
                 const auto t0 = std::chrono::steady_clock::now();
                 cf_status st = run(c, probe, metric, theta, d1, ncat, d2, edges, nb, pimax, npi,
                                    boxsize, prec, counts, wsum, &o);
@@ -1292,16 +1312,17 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
                           std::chrono::steady_clock::now() - t0).count();
                 return st;
             };
-            int32_t best_spr = 16, best_chunk = 2048;
             double best = 0.0;
-            cf_status st = time_call(best_spr, best_chunk, &best);   // also warms buffers
+            cf_status st = time_call(best_spr, best_chunk, best_ang, &best);   // warms buffers
             if (st != CF_OK)
                 return st;
-            if ((st = time_call(best_spr, best_chunk, &best)))
+            if ((st = time_call(best_spr, best_chunk, best_ang, &best)))
                 return st;
-            for (int32_t spr : {2, 4, 8, 32}) {
+            for (int32_t spr : {2, 4, 8, 16, 32}) {
+                if (spr == best_spr)
+                    continue;
                 double ms;
-                if ((st = time_call(spr, best_chunk, &ms)))
+                if ((st = time_call(spr, best_chunk, best_ang, &ms)))
                     return st;
                 if (ms < best) {
                     best = ms;
@@ -1310,17 +1331,28 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
             }
             for (int32_t chunk : {512, 1024, 4096, 8192}) {
                 double ms;
-                if ((st = time_call(best_spr, chunk, &ms)))
+                if ((st = time_call(best_spr, chunk, best_ang, &ms)))
                     return st;
                 if (ms < best) {
                     best = ms;
                     best_chunk = chunk;
                 }
             }
-            it = c->tuned.emplace(tk, std::make_pair(best_spr, best_chunk)).first;
+            if (tune_ang)
+                for (int32_t ang : {4, 16}) {
+                    double ms;
+                    if ((st = time_call(best_spr, best_chunk, ang, &ms)))
+                        return st;
+                    if (ms < best) {
+                        best = ms;
+                        best_ang = ang;
+                    }
+                }
+            it = c->tuned.emplace(tk, cf_ctx::Tuned{best_spr, best_chunk, best_ang}).first;
         }
-        tuned_opt.slices_per_reach = it->second.first;
-        tuned_opt.chunk = it->second.second;
+        tuned_opt.slices_per_reach = it->second.slices_per_reach;
+        tuned_opt.chunk = it->second.chunk;
+        tuned_opt.angular_grid = it->second.angular_grid;
         tuned_opt.collect_timing = opt_in->collect_timing;
         opt = &tuned_opt;
     }
@@ -1364,7 +1396,6 @@ void cf_default_options(cf_options *opt)
         return;
     memset(opt, 0, sizeof(*opt));
     opt->struct_size = (int32_t)sizeof(cf_options);
-    opt->slices_per_reach = 16;
     opt->chunk = 2048;
 }
 

@@ -6,7 +6,8 @@ binned by the same chord^2 definition, so counts must equal the oracle's
 bit for bit for any band / cell layout: full sky with both poles, a cap on
 the RA = 0 / 360 seam, very large and very small angular reaches, points
 exactly at the poles and on the seam, several right-ascension refinements and
-slice counts, both precisions, weights and mean angles.
+slice counts, both precisions, weights and mean angles.  The 3-D chord grid
+(angular_grid=-1) is checked alongside.
 """
 import numpy as np
 import pytest
@@ -84,8 +85,10 @@ def test_seam_cap_matches_chord_grid(pc, olib, prec):
     for refine in (1, 2, 4):
         got, _ = pc.count_theta(ra, dec, None, None, te, prec, angular_grid=refine)
         assert (got == want).all(), (refine, got, want)
-    chord, _ = pc.count_theta(ra, dec, None, None, te, prec)
+    chord, _ = pc.count_theta(ra, dec, None, None, te, prec, angular_grid=-1)
     assert (chord == want).all()
+    default, _ = pc.count_theta(ra, dec, None, None, te, prec)
+    assert (default == want).all() and pc.stats()["angular_grid"] == 8
     want, _ = oracle.count_theta(ra, dec, rr, rd, te, lib=olib)
     got, _ = pc.count_theta(ra, dec, rr, rd, te, prec, angular_grid=2)
     assert (got == want).all()
@@ -154,7 +157,7 @@ def test_float32_unit_vectors(pc):
         got, _ = pc.count_theta(None, None, theta_edges_deg=te, precision=prec,
                                 unit_vectors=(v, None), angular_grid=1)
         chord, _ = pc.count_theta(None, None, theta_edges_deg=te, precision=prec,
-                                  unit_vectors=(v, None))
+                                  unit_vectors=(v, None), angular_grid=-1)
         assert chord.sum() > 0 and (got == chord).all(), prec
 
 
@@ -163,10 +166,12 @@ def test_errors(pc):
     say("angular grid errors")
     v = np.array([[1.0, 0.0, 0.0], [0.0, 2.0, 0.0], [0.0, 0.0, 1.0]])
     te = synth.log_edges(0.5, 15.0, 4)
-    with pytest.raises(m.PairCountError):
-        pc.count_theta(None, None, theta_edges_deg=te, unit_vectors=(v, None), angular_grid=1)
+    for grid in (None, 1):
+        with pytest.raises(m.PairCountError):
+            pc.count_theta(None, None, theta_edges_deg=te, unit_vectors=(v, None),
+                           angular_grid=grid)
     # the chord grid takes any vectors
-    pc.count_theta(None, None, theta_edges_deg=te, unit_vectors=(v, None))
+    pc.count_theta(None, None, theta_edges_deg=te, unit_vectors=(v, None), angular_grid=-1)
     with pytest.raises(m.PairCountError):
         pc.count_r(synth.uniform_box(100, 10.0, seed=1), None, synth.log_edges(0.1, 1.0, 3),
                    10.0, options={"angular_grid": 1})
@@ -174,22 +179,24 @@ def test_errors(pc):
     with pytest.raises(m.PairCountError):
         pc.count_theta(ra, dec, None, None, te, angular_grid=65)
     with pytest.raises(m.PairCountError):
-        pc.count_theta(ra, dec, None, None, te, angular_grid=-1)
+        pc.count_theta(ra, dec, None, None, te, angular_grid=-2)
 
 
 def test_cap_fullsize_equals_chord_grid(pc, olib):
     """2*10^6 clustered points on the 30-degree seam cap, 20 bins in
-    [0.01, 10] degrees: the angular grid's counts equal the 3-D chord grid's,
-    and sampled cross counts of 256 points equal the oracle's."""
+    [0.01, 10] degrees: the angular grid's counts equal the 3-D chord grid's
+    (which evaluates more candidate pairs), and sampled cross counts of 256
+    points equal the oracle's."""
     say("angular grid N=2e6")
     ra, dec = synth.cap_radec(2_000_000, seed=4, radius_deg=30.0, clustered=True)
     te = synth.log_edges(0.01, 10.0, 20)
     a, _ = pc.count_theta(ra, dec, None, None, te, "fp32", angular_grid=2)
     sa = pc.stats()
-    c, _ = pc.count_theta(ra, dec, None, None, te, "fp32")
+    c, _ = pc.count_theta(ra, dec, None, None, te, "fp32", angular_grid=-1)
     sc = pc.stats()
     say("candidates angular", sa["candidate_pairs"], "chord", sc["candidate_pairs"])
     assert (a == c).all()
+    assert sa["candidate_pairs"] < sc["candidate_pairs"]
     idx = np.sort(synth.rng_for(512).choice(ra.size, size=256, replace=False))
     got, _ = pc.count_theta(ra[idx], dec[idx], ra, dec, te, "fp32", angular_grid=2)
     want, _ = oracle.count_theta(ra[idx], dec[idx], ra, dec, te, lib=olib)
