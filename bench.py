@@ -182,6 +182,7 @@ def batch_bench(args):
                      "batched_value": w_ref / tb / 1e9, "sequential_value": w_ref / ts / 1e9,
                      "candidate_pairs": st["candidate_pairs"], "rechecks": st["rechecks"],
                      "slices_per_reach": st["slices_per_reach"], "chunk": st["chunk"],
+                     "xy_refine": st["xy_refine"],
                      "replayed": st["replayed"]}
     line = {
         "metric": "Gpair-evals/s for batched DD(rp,pi), 256 mocks, FP32+recheck batched vs "

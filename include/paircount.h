@@ -136,7 +136,15 @@ typedef struct cf_options {
                                    (squared norm within 2^-20 of 1, else
                                    CF_EINVAL), which RA/DEC input always
                                    gives.  Other statistics need 0.            */
-    int32_t reserved[5];
+    int32_t xy_refine;          /* 3-D grids: columns at least reach/k wide in
+                                   x and y (section "Sub-dividing the cells"),
+                                   k in 1..4 (0: 1); a block then pairs with
+                                   the (2k+1)^2 columns around its own, each
+                                   over a z window narrowed by the columns'
+                                   transverse distance when the reach is a
+                                   ball.  Lowered when a periodic box has fewer
+                                   than 2k+1 columns.                           */
+    int32_t reserved[4];
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
                                    in each bin (r, rp, or theta in degrees),
@@ -174,6 +182,8 @@ typedef struct cf_stats {
     int32_t chunk;              /* max j points per work item used             */
     int32_t replayed;           /* 1 when the call replayed a recorded graph   */
     int32_t angular_grid;       /* angular grid refinement used (0: 3-D cells) */
+    int32_t xy_refine;          /* x/y refinement of a 3-D grid (0: angular)   */
+    int32_t reserved_s;
 } cf_stats;
 
 typedef struct cf_ctx cf_ctx;

@@ -61,7 +61,7 @@ class cf_options(ctypes.Structure):
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("weight_type", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5),
+                ("xy_refine", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
                 ("ravg", ctypes.c_void_p)]
 
 
@@ -76,7 +76,8 @@ class cf_stats(ctypes.Structure):
                 ("t_finalize_ms", ctypes.c_float),
                 ("t_total_ms", ctypes.c_float),
                 ("slices_per_reach", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("replayed", ctypes.c_int32), ("angular_grid", ctypes.c_int32)]
+                ("replayed", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
+                ("xy_refine", ctypes.c_int32), ("reserved_s", ctypes.c_int32)]
 
 
 class cf_grid_plan(ctypes.Structure):

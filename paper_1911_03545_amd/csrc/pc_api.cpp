@@ -77,7 +77,7 @@ struct cf_ctx {
     cf_stats gstats;
     // autotuned choices per workload class
     struct Tuned {
-        int32_t slices_per_reach, chunk, angular_grid;
+        int32_t slices_per_reach, chunk, angular_grid, xy_refine;
     };
     std::map<std::vector<int64_t>, Tuned> tuned;
 };
@@ -519,6 +519,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (opt.angular_grid < 0)
         opt.angular_grid = 0;
     const bool sky_grid = theta && opt.angular_grid > 0;
+    if (opt.xy_refine < 0 || opt.xy_refine > PC_MAX_XYK)
+        return fail(c, CF_EINVAL, "xy_refine must be in [0, %d]", PC_MAX_XYK);
+    if (opt.xy_refine == 0)
+        opt.xy_refine = 1;
     if (opt.slices_per_reach <= 0)
         opt.slices_per_reach = sky_grid ? 32 : 16;
 
@@ -662,7 +666,9 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
 
     // ---- plan ------------------------------------------------------------
     pc_grid g;
-    int rc = pc::plan_grid(lo, hi, boxsize, reach_xy, reach_z, opt.slices_per_reach, &g);
+    // r, angular chords and on-sky pairs are bounded by a 3-D ball
+    int rc = pc::plan_grid(lo, hi, boxsize, reach_xy, reach_z, opt.slices_per_reach, &g,
+                           opt.xy_refine, metric != PC_METRIC_RPPI);
     if (rc == CF_EUNSUPPORTED)
         return fail(c, CF_EUNSUPPORTED,
                     "periodic box needs every reach (r, rp, pi) at most boxsize/3");
@@ -823,7 +829,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     {
         const int64_t sh[] = {metric, theta ? 1 : 0, ncat, autocorr ? 1 : 0, n1, n2, nb, npi,
                               (int64_t)prec, opt.slices_per_reach, chunk, g.n[0], g.n[1],
-                              g.n[2], weighted ? 1 : 0, opt.angular_grid};
+                              g.n[2], weighted ? 1 : 0, opt.angular_grid, g.xyk};
         key_add(shape, sh, sizeof(sh));
         key_add(shape, &boxsize, sizeof(boxsize));
         key_add(shape, &pimax, sizeof(pimax));
@@ -1074,6 +1080,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     S.zreach = g.zreach;
     S.slices_per_reach = opt.slices_per_reach;
     S.angular_grid = opt.angular_grid;
+    S.xy_refine = sky_grid ? 0 : g.xyk;
     S.chunk = chunk;
     S.n_blocks = hcounts[1];
     S.n_items = hcounts[0];
@@ -1278,8 +1285,9 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
                 const cf_options *opt_in)
 {
     // autotuning: pick slices_per_reach and chunk (and, for angular counts,
-    // the right-ascension refinement of the angular grid) by timing whole
-    // calls on the live input (coordinate descent), once per workload class
+    // the right-ascension refinement of the angular grid, else the x/y
+    // refinement of the 3-D grid) by timing whole calls on the live input
+    // (coordinate descent), once per workload class
     cf_options tuned_opt;
     const cf_options *opt = opt_in;
     if (c && opt_in && opt_in->struct_size == (int32_t)sizeof(cf_options) && opt_in->autotune &&
@@ -1290,6 +1298,7 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
         std::vector<int64_t> tk =
             tune_key(metric, theta, d1, ncat, d2, edges, nb, pimax, npi, boxsize, prec);
         tk.push_back(opt_in->angular_grid);
+        tk.push_back(opt_in->xy_refine);
         auto it = c->tuned.find(tk);
         if (it == c->tuned.end()) {
             RunCtl probe;
@@ -1298,6 +1307,9 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
             const bool tune_ang = theta && opt_in->angular_grid == 0;
             int32_t best_ang = tune_ang ? 8 : opt_in->angular_grid;
             int32_t best_spr = theta && best_ang >= 0 ? 32 : 16, best_chunk = 2048;
+            // x/y refinement of a 3-D grid, when left at its default
+            const bool tune_xy = opt_in->xy_refine == 0 && !(theta && best_ang >= 0);
+            int32_t best_xy = tune_xy ? 1 : opt_in->xy_refine;
             auto time_call = [&](int32_t spr, int32_t chunk, int32_t ang,
                                  double *ms) -> cf_status {
                 cf_options o = tuned_opt;
@@ -1305,6 +1317,7 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
                 o.slices_per_reach = spr;
                 o.chunk = chunk;
                 o.angular_grid = ang;
+                o.xy_refine = best_xy;
                 const auto t0 = std::chrono::steady_clock::now();
                 cf_status st = run(c, probe, metric, theta, d1, ncat, d2, edges, nb, pimax, npi,
                                    boxsize, prec, counts, wsum, &o);
@@ -1348,11 +1361,23 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
                         best_ang = ang;
                     }
                 }
-            it = c->tuned.emplace(tk, cf_ctx::Tuned{best_spr, best_chunk, best_ang}).first;
+            if (tune_xy) {
+                best_xy = 2;
+                double ms;
+                if ((st = time_call(best_spr, best_chunk, best_ang, &ms)))
+                    return st;
+                if (ms < best)
+                    best = ms;
+                else
+                    best_xy = 1;
+            }
+            it = c->tuned.emplace(tk, cf_ctx::Tuned{best_spr, best_chunk, best_ang, best_xy})
+                     .first;
         }
         tuned_opt.slices_per_reach = it->second.slices_per_reach;
         tuned_opt.chunk = it->second.chunk;
         tuned_opt.angular_grid = it->second.angular_grid;
+        tuned_opt.xy_refine = it->second.xy_refine;
         tuned_opt.collect_timing = opt_in->collect_timing;
         opt = &tuned_opt;
     }

@@ -56,6 +56,7 @@ struct pc_band {
     double dra[3];
 };
 
+#define PC_MAX_XYK 4
 #define PC_MAX_BANDS 1024
 #define PC_MAX_RA 4096
 #define PC_MAX_SKY_COLS (1 << 20)
@@ -82,6 +83,13 @@ struct pc_grid {
     // fixed-point z of the float32 rp/pi path: Zq = round((z - lo_z) * zq_inv)
     // + 2^30 as uint32 bits, one pi bin = 2^zq_shift quanta
     double zq_inv;
+    // x/y refinement: columns at least reach / xyk wide, so a pair within
+    // the reach is at most xyk columns apart per axis; zro[|ox|][|oy|] is the
+    // z window (slices each side) of the column at that offset, narrowed by
+    // the offset's smallest transverse distance when the reach is a 3-D
+    // ball, -1 where no pair of the two columns can be within reach
+    int32_t xyk;
+    int16_t zro[PC_MAX_XYK + 1][PC_MAX_XYK + 1];
     // angular grid: declination bands of nband * n[2] slices, slice index
     // floor((dec - dec_lo) * inv_hs); bands is a device table of nband entries
     int32_t nband;

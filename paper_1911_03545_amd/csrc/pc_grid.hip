@@ -512,9 +512,11 @@ struct SegCtx {
 // Autocorrelation visits each unordered pair once: the block's own column
 // forward along the sorted order (the triangle j > i inside the block, then
 // later points up to zreach slices beyond the block's last slice, then the
-// periodic wrap past the top face), and the four columns (0,+1), (+1,-1),
-// (+1,0), (+1,+1) over the full z window.  Cross-correlation visits all nine
-// columns over the full window.
+// periodic wrap past the top face), and the forward half of the column
+// offsets within xyk ((0, +1..), then (+1.., any)), each over its z window.
+// Cross-correlation visits all (2 xyk + 1)^2 columns.  With 2 xyk + 1 columns
+// or more on a periodic axis every offset names a distinct column, so the
+// forward half meets each pair of columns once.
 // Angular grid: the block's own cell and the right-ascension cells of its
 // own and the two neighbouring declination bands that come within the
 // right-ascension reach of the block's cell (its east and west edges
@@ -599,9 +601,9 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
     const int zr = c.g.zreach;
     const bool per = c.g.periodic != 0;
 
-    auto zwin = [&](int ccol, unsigned dxy) {
+    auto zwin = [&](int ccol, unsigned dxy, int zw) {
         const int64_t base = (int64_t)ccol * nz;
-        const int lo_s = sa - zr, hi_s = sb + zr;
+        const int lo_s = sa - zw, hi_s = sb + zw;
         const int a0 = max(lo_s, 0), a1 = min(hi_s, nz - 1);
         if (a0 <= a1)
             f(c.start2[base + a0], c.start2[base + a1 + 1], dxy, 0);
@@ -617,6 +619,9 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
         }
     };
     auto column = [&](int ox, int oy) {
+        const int zw = c.g.zro[ox < 0 ? -ox : ox][oy < 0 ? -oy : oy];
+        if (zw < 0)
+            return;
         int jx = ix + ox, jy = iy + oy;
         unsigned code = 0;
         if (jx < 0 || jx >= nx) {
@@ -631,9 +636,10 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
             code |= ((jy < 0) ? PC_D_PLUS : PC_D_MINUS) << 2;
             jy = (jy < 0) ? jy + ny : jy - ny;
         }
-        zwin(cbase + jx * ny + jy, code);
+        zwin(cbase + jx * ny + jy, code, zw);
     };
 
+    const int k = c.g.xyk;
     if (c.autocorr) {
         if (b.ni > 1)
             f(b.i0 + 1, b.i0 + b.ni, 0u, 1);
@@ -646,13 +652,15 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
             const int w1 = min(hi_s - nz, nz - 1);
             f(c.start2[base], c.start2[base + w1 + 1], PC_D_MINUS << 4, 0);
         }
-        column(0, 1);
-        column(1, -1);
-        column(1, 0);
-        column(1, 1);
+        // the forward half of the offsets: (0, 1..k), then (1..k, -k..k)
+        for (int oy = 1; oy <= k; oy++)
+            column(0, oy);
+        for (int ox = 1; ox <= k; ox++)
+            for (int oy = -k; oy <= k; oy++)
+                column(ox, oy);
     } else {
-        for (int ox = -1; ox <= 1; ox++)
-            for (int oy = -1; oy <= 1; oy++)
+        for (int ox = -k; ox <= k; ox++)
+            for (int oy = -k; oy <= k; oy++)
                 column(ox, oy);
     }
 }

@@ -51,6 +51,10 @@ float bits_f(uint32_t u)
 
 }  // namespace
 
+int plan_grid_k(const double lo_in[3], const double hi_in[3], double boxsize,
+                double reach_xy, double reach_z, int slices_per_reach,
+                pc_grid *g, int k, bool zball);
+
 // Cell grid of section "Partitioning the particles on a grid".
 //
 // Transverse columns (x, y) are at least `reach_xy` wide, so two points within
@@ -66,9 +70,31 @@ float bits_f(uint32_t u)
 // reach_z / slices_per_reach, of which `zreach` are searched on each side of a
 // block.  zreach = floor(reach_z / width_z (1 + 2^-28) + 2^-28) + 1 covers
 // every point within reach_z of any point of the block.
+//
+// With xy_refine = k > 1 ("Sub-dividing the cells") the columns are at least
+// reach_xy / k wide and a block pairs with the (2k + 1)^2 columns around its
+// own; a periodic axis needs 2k + 1 columns, else k is lowered.  When the
+// reach is a 3-D ball (`zball`: r, angular chords, on-sky pairs) the z window
+// of a column at offset (ox, oy) shrinks to sqrt(reach^2 - d^2), d the
+// smallest transverse distance between the two columns ((|o| - 1) column
+// widths per axis, less a margin of 2^-30 of the extent); columns no pair can
+// reach are skipped.
 int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
               double reach_xy, double reach_z, int slices_per_reach,
-              pc_grid *g)
+              pc_grid *g, int xy_refine, bool zball)
+{
+    int k = std::min(std::max(xy_refine, 1), PC_MAX_XYK);
+    for (;; k--) {
+        const int rc = plan_grid_k(lo_in, hi_in, boxsize, reach_xy, reach_z, slices_per_reach,
+                                   g, k, zball);
+        if (rc != CF_EUNSUPPORTED || k == 1)
+            return rc;
+    }
+}
+
+int plan_grid_k(const double lo_in[3], const double hi_in[3], double boxsize,
+                double reach_xy, double reach_z, int slices_per_reach,
+                pc_grid *g, int k, bool zball)
 {
     memset(g, 0, sizeof(*g));
     g->fscale = 1.0;
@@ -97,12 +123,12 @@ int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
     const int max_cols = 1024;
     for (int a = 0; a < 2; a++) {
         const double ext = g->extent[a];
-        const double need = reach_xy * (1.0 + 0x1p-28) + ext * 0x1p-40;
+        const double need = reach_xy / k * (1.0 + 0x1p-28) + ext * 0x1p-40;
         double nd = ext > 0.0 ? floor(ext / need) : 1.0;
         int n = (int)std::min(std::max(nd, 1.0), (double)max_cols);
         while (n > 1 && ext / n < need)
             n--;
-        if (periodic && n < 3)
+        if (periodic && n < 2 * k + 1)
             return CF_EUNSUPPORTED;
         g->n[a] = n;
         g->inv_w[a] = ext > 0.0 ? (double)n / ext : 0.0;
@@ -128,6 +154,22 @@ int plan_grid(const double lo_in[3], const double hi_in[3], double boxsize,
         g->zreach = std::min(zr, n);
     }
     g->ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    g->xyk = k;
+    for (int a = 0; a <= PC_MAX_XYK; a++)
+        for (int b = 0; b <= PC_MAX_XYK; b++) {
+            const double dx = std::max(0.0, (a - 1) * g->width[0] - g->extent[0] * 0x1p-30);
+            const double dy = std::max(0.0, (b - 1) * g->width[1] - g->extent[1] * 0x1p-30);
+            const double d2 = dx * dx + dy * dy;
+            int zr = g->zreach;
+            if (a > k || b > k || d2 >= reach_xy * reach_xy * (1.0 + 0x1p-30)) {
+                zr = -1;
+            } else if (zball && d2 > 0.0) {
+                const double rz = sqrt(std::max(0.0, reach_z * reach_z * (1.0 + 0x1p-30) - d2));
+                const double r = rz * g->inv_w[2];
+                zr = std::min((int)floor(r * (1.0 + 0x1p-28) + 0x1p-28) + 1, g->zreach);
+            }
+            g->zro[a][b] = (int16_t)zr;
+        }
     return CF_OK;
 }
 
@@ -240,6 +282,10 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
     const int zr = (int)floor(r * (1.0 + 0x1p-28) + 0x1p-28) + 1;
     g->zreach = std::min(zr, slices);
     g->bands = nullptr;
+    g->xyk = 1;
+    for (int a = 0; a <= PC_MAX_XYK; a++)
+        for (int b = 0; b <= PC_MAX_XYK; b++)
+            g->zro[a][b] = (int16_t)g->zreach;
     return CF_OK;
 }
 
@@ -547,7 +593,7 @@ extern "C" cf_status cf_plan_grid(const double lo[3], const double hi[3],
         return CF_EINVAL;
     pc_grid g;
     int rc = pc::plan_grid(lo ? lo : zl, hi ? hi : zh, boxsize, reach_xy, reach_z,
-                           slices_per_reach, &g);
+                           slices_per_reach, &g, 1, false);
     if (rc)
         return (cf_status)rc;
     memset(out, 0, sizeof(*out));

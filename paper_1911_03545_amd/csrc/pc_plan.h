@@ -18,7 +18,8 @@ struct HostBins {
 };
 
 int plan_grid(const double lo[3], const double hi[3], double boxsize, double reach_xy,
-              double reach_z, int slices_per_reach, pc_grid *g);
+              double reach_z, int slices_per_reach, pc_grid *g, int xy_refine = 1,
+              bool zball = false);
 // angular grid of unit vectors (overrides n, ncell, zreach and the slice
 // fields of a grid planned on the vectors' bounding box)
 int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra_refine,
