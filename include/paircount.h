@@ -104,8 +104,9 @@ typedef struct cf_catalog {
    cf_default_options.  Zero fields take the defaults. */
 typedef struct cf_options {
     int32_t struct_size;        /* sizeof(cf_options)                          */
-    int32_t slices_per_reach;   /* z slices per line-of-sight reach (0: 16, or
-                                   32 per band on the angular grid)            */
+    int32_t slices_per_reach;   /* z slices per line-of-sight reach (0: 32;
+                                   declination slices per band on the angular
+                                   grid)                                       */
     int32_t chunk;              /* max j points per work item (default 2048)   */
     int32_t output_on_device;   /* counts / wsum are device pointers           */
     int32_t theta_unit_vectors; /* theta input is unit vectors, not RA/DEC;

@@ -524,7 +524,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (opt.xy_refine == 0)
         opt.xy_refine = 1;
     if (opt.slices_per_reach <= 0)
-        opt.slices_per_reach = sky_grid ? 32 : 16;
+        opt.slices_per_reach = 32;
 
     // theta: chord edges c_k = 2 sin(theta_k / 2) on the host
     std::vector<double> lin(edges, edges + nb + 1);
@@ -1306,7 +1306,7 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
             // its default
             const bool tune_ang = theta && opt_in->angular_grid == 0;
             int32_t best_ang = tune_ang ? 8 : opt_in->angular_grid;
-            int32_t best_spr = theta && best_ang >= 0 ? 32 : 16, best_chunk = 2048;
+            int32_t best_spr = 32, best_chunk = 2048;
             // x/y refinement of a 3-D grid, when left at its default
             const bool tune_xy = opt_in->xy_refine == 0 && !(theta && best_ang >= 0);
             int32_t best_xy = tune_xy ? 1 : opt_in->xy_refine;
