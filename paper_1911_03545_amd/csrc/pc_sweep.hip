@@ -623,12 +623,9 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
 }
 
 // ---- item loops ----------------------------------------------------------
-// The block's own point (xi, yi, zi, wv: lane i's coordinates and weight)
-// is loaded by the caller, ahead of the next item's fetch.
 template <int M, int W, bool TRI, bool T16, bool UNC>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                         lds_f64wp whb, int i, bool act, float xi, float yi,
-                                         float zi, double wv, int j0, int j1,
+                                         lds_f64wp whb, int i, bool act, int j0, int j1,
                                          unsigned dcode, unsigned &rechecks)
 {
     const float Lf = a.Lf32;
@@ -637,9 +634,9 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     const float Dy = cy == PC_D_PLUS ? Lf : (cy == PC_D_MINUS ? -Lf : 0.0f);
     const float Dz = cz == PC_D_PLUS ? Lf : (cz == PC_D_MINUS ? -Lf : 0.0f);
     // inactive lanes sit far away: their separations overflow to +inf
-    const float ax = act ? xi + Dx : 3.0e30f;
-    const float ay = act ? yi + Dy : 3.0e30f;
-    const LaneW wi = lane_weight(a.wtype, (W && act) ? wv : 0.0);
+    const float ax = act ? a.X1[i] + Dx : 3.0e30f;
+    const float ay = act ? a.Y1[i] + Dy : 3.0e30f;
+    const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
     // second-catalogue points are wave-uniform: read them through the scalar
     // cache (the arrays are not written during the sweep)
     const kf32p X2 = (kf32p)a.X2, Y2 = (kf32p)a.Y2, Z2 = (kf32p)a.Z2;
@@ -649,7 +646,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     if constexpr (M == PC_METRIC_RPPI) {
         // z in fixed point: the periodic z offset is a whole number of quanta
         const unsigned Dq = cz == PC_D_PLUS ? a.B.zq_L : (cz == PC_D_MINUS ? 0u - a.B.zq_L : 0u);
-        const unsigned azq = __float_as_uint(zi) + Dq;
+        const unsigned azq = __float_as_uint(a.Z1[i]) + Dq;
         for (; j + CH <= j1; j += CH) {
             float xs[CH], ys[CH], zs[CH];
             double ws[CH];
@@ -680,7 +677,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
         }
         return;
     } else {
-        const float az = act ? zi + Dz : 3.0e30f;
+        const float az = act ? a.Z1[i] + Dz : 3.0e30f;
         for (; j + CH <= j1; j += CH) {
             float xs[CH], ys[CH], zs[CH];
             double ws[CH];
@@ -715,15 +712,15 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
 
 template <int M, int W, bool TRI, bool OFS, bool T16, bool UNC>
 __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                         lds_f64wp whb, int i, bool act, double xl, double yl,
-                                         double zl, double wv, int j0, int j1, unsigned dcode)
+                                         lds_f64wp whb, int i, bool act, int j0, int j1,
+                                         unsigned dcode)
 {
     const double Dx = dval(dcode & 3u, a.L), Dy = dval((dcode >> 2) & 3u, a.L),
                  Dz = dval((dcode >> 4) & 3u, a.L);
-    const double xi = act ? xl : 1.0e300;
-    const double yi = act ? yl : 1.0e300;
-    const double zi = act ? zl : 1.0e300;
-    const LaneW wi = lane_weight(a.wtype, (W && act) ? wv : 0.0);
+    const double xi = act ? a.x1[i] : 1.0e300;
+    const double yi = act ? a.y1[i] : 1.0e300;
+    const double zi = act ? a.z1[i] : 1.0e300;
+    const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
     const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2, w2 = (kf64p)a.w2;
     constexpr int CH = W ? 4 : 8;
     int j = j0;
@@ -925,31 +922,18 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     bool probe = false;
     int next = wave_fetch(a.counter, n_items, lane, stream, probe);
     pc_item nit = {};
-    if (next < n_items)
+    if (P32 && next < n_items)
         nit = a.items[next];
     while (next < n_items) {
-        const pc_item it = nit;
-        const int ni0 = (int)PC_META_NI(it.meta);
-        const int i = it.i0 + (lane < ni0 ? lane : 0);
-        // this item's own points load while the next item is taken, and the
-        // next item's descriptor while this one runs
-        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-        double dx = 0.0, dy = 0.0, dz = 0.0, wv = 0.0;
-        if constexpr (P32) {
-            fx = a.X1[i];
-            fy = a.Y1[i];
-            fz = a.Z1[i];
-        } else {
-            dx = a.x1[i];
-            dy = a.y1[i];
-            dz = a.z1[i];
-        }
-        if (W)
-            wv = a.w1[i];
+        // float32 sweeps load the following item's descriptor while this
+        // item runs (measured slower for the binary64 sweep, which keeps the
+        // load after the take)
+        const int cur = next;
+        const pc_item it = P32 ? nit : a.items[cur];
         next = wave_fetch(a.counter, n_items, lane, stream, probe);
-        if (next < n_items)
+        if (P32 && next < n_items)
             nit = a.items[next];
-        const int ni = ni0;
+        const int ni = (int)PC_META_NI(it.meta);
         const unsigned dcode = PC_META_DCODE(it.meta);
         const bool tri = PC_META_TRI(it.meta) != 0;
         const unsigned long long work = (unsigned long long)ni * (unsigned)(it.j1 - it.j0);
@@ -968,23 +952,23 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         }
         pending += work;
         const bool act = lane < ni;
+        const int i = it.i0 + (act ? lane : 0);
         if constexpr (P32) {
             if (tri)
-                item_f32<M, W, true, T16, UNC>(a, L, hb, whb, i, act, fx, fy, fz, wv, it.j0,
-                                               it.j1, dcode, rechecks);
+                item_f32<M, W, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                                               rechecks);
             else
-                item_f32<M, W, false, T16, UNC>(a, L, hb, whb, i, act, fx, fy, fz, wv, it.j0,
-                                                it.j1, dcode, rechecks);
+                item_f32<M, W, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                                                rechecks);
         } else {
             if (tri)
-                item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, dx, dy, dz, wv,
-                                                      it.j0, it.j1, dcode);
+                item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
             else if (dcode == 0u)
-                item_f64<M, W, false, false, T16, UNC>(a, L, hb, whb, i, act, dx, dy, dz, wv,
-                                                       it.j0, it.j1, dcode);
+                item_f64<M, W, false, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1,
+                                                       dcode);
             else
-                item_f64<M, W, false, true, T16, UNC>(a, L, hb, whb, i, act, dx, dy, dz, wv,
-                                                      it.j0, it.j1, dcode);
+                item_f64<M, W, false, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1,
+                                                      dcode);
         }
     }
     if (PRIV) {
