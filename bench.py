@@ -111,11 +111,29 @@ def cpu_baseline(pts: np.ndarray, w_ref: int, target_s: float = 12.0):
     rate = m * pts.shape[0] / el                 # brute-force pair evaluations / s
     full_pairs = pts.shape[0] * (pts.shape[0] - 1) / 2
     t_full = full_pairs / rate
+    # one thread on a sample of about 3 s, for the per-core rate
+    m1 = max(16, int(m * 3.0 / max(el, 1e-9) / cores))
+    s1 = pts[rng.choice(pts.shape[0], min(m1, pts.shape[0]), replace=False)]
+    t = time.perf_counter()
+    oracle.count_r(s1, pts, EDGES, L_BOX, nthreads=1, lib=lib)
+    el1 = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": w_ref / t_full / 1e9,
         "unit": "Gpair-evals/s",
         "cores": cores,
         "kind": "oracle",
+        "nproc": os.cpu_count(),
+        "cpu_model": model,
+        "single_thread_gpair_per_s": s1.shape[0] * pts.shape[0] / el1 / 1e9,
         "sample": (f"brute-force cross counts of {m} random points against all "
                    f"{pts.shape[0]} ({m * pts.shape[0]:.3g} pair evaluations in {el:.1f} s, "
                    f"{rate / 1e9:.3f} Gpair/s); full auto workload of {full_pairs:.3g} unique "
