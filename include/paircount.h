@@ -194,6 +194,19 @@ typedef struct cf_ctx cf_ctx;
    owned by the caller and must outlive the context. */
 cf_status cf_create(int device, void *hip_stream, cf_ctx **out);
 cf_status cf_destroy(cf_ctx *ctx);
+/* Device scratch allocator of a context (the gridded arrays, work lists,
+   histograms: everything the library keeps on the device between calls).
+   alloc(bytes, user) must return `bytes` of device memory on the context's
+   device, 256-byte aligned, usable on the context's stream (NULL on failure,
+   which the call reports as CF_ENOMEM); free_(ptr, user) takes it back.  The
+   library frees a buffer only after synchronising its stream.  Passing NULL
+   for both restores hipMalloc / hipFree.  Buffers held when the allocator
+   changes go back to the allocator that made them first; cf_destroy returns
+   the rest.  Errors: CF_EINVAL when ctx is NULL or exactly one function is
+   NULL. */
+typedef void *(*cf_alloc_fn)(size_t bytes, void *user);
+typedef void (*cf_free_fn)(void *ptr, void *user);
+cf_status cf_set_allocator(cf_ctx *ctx, cf_alloc_fn alloc, cf_free_fn free_, void *user);
 /* Message of the last failing call on ctx, or with ctx == NULL of the last
    failing cf_create on this thread (never NULL). */
 const char *cf_last_error(const cf_ctx *ctx);

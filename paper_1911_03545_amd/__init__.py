@@ -35,7 +35,8 @@ STATUS_NAMES = {
 }
 
 EXPORTED_SYMBOLS = (
-    "cf_create", "cf_destroy", "cf_last_error", "cf_get_stats", "cf_default_options",
+    "cf_create", "cf_destroy", "cf_set_allocator", "cf_last_error", "cf_get_stats",
+    "cf_default_options",
     "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
@@ -98,6 +99,10 @@ class cf_sky_plan(ctypes.Structure):
                 ("slices", ctypes.c_int32), ("zreach", ctypes.c_int32),
                 ("dec_lo", ctypes.c_double), ("band_height", ctypes.c_double),
                 ("inv_slice", ctypes.c_double), ("theta_reach", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class PairCountError(RuntimeError):
@@ -166,6 +171,8 @@ def load_library(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.cf_plan_grid.argtypes = [vp, vp, dbl, dbl, dbl, i32, ctypes.POINTER(cf_grid_plan)]
     lib.cf_plan_grid.restype = ctypes.c_int
+    lib.cf_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
+    lib.cf_set_allocator.restype = ctypes.c_int
     lib.cf_plan_sky_grid.argtypes = [dbl, dbl, dbl, i32, i32, ctypes.POINTER(cf_sky_plan),
                                      vp, i32]
     lib.cf_plan_sky_grid.restype = ctypes.c_int
@@ -335,11 +342,41 @@ class PairCounter:
             raise PairCountError(st, f"cf_create(device={device}): "
                                      f"{msg.decode() if msg else ''}")
         self._ctx = ctx
+        self._device = int(device)
+        self._stream_handle = handle
+        self._alloc_cbs = None
+
+    def set_allocator(self, alloc=None, free=None):
+        """Route the context's device scratch through ``alloc(nbytes) -> int``
+        (a device pointer, 256-byte aligned) and ``free(ptr)``; both None
+        restores hipMalloc / hipFree."""
+        if (alloc is None) != (free is None):
+            raise ValueError("give both alloc and free, or neither")
+        if alloc is None:
+            st = self._lib.cf_set_allocator(self._ctx, ALLOC_FN(), FREE_FN(), None)
+            self._check(st)
+            self._alloc_cbs = None
+            return
+        a = ALLOC_FN(lambda n, user: int(alloc(int(n))) or None)
+        f = FREE_FN(lambda p, user: free(int(p)))
+        st = self._lib.cf_set_allocator(self._ctx, a, f, None)
+        self._check(st)
+        self._alloc_cbs = (a, f)   # kept alive while the library may call them
+
+    def use_torch_allocator(self):
+        """Take device scratch from torch's caching allocator on this
+        context's device and stream (it then shows in
+        torch.cuda.memory_allocated and is reused across contexts)."""
+        import torch
+        dev, stream = self._device, self._stream_handle or 0
+        self.set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev, stream),
+                           torch.cuda.caching_allocator_delete)
 
     def close(self):
         if getattr(self, "_ctx", None):
             self._lib.cf_destroy(self._ctx)
             self._ctx = None
+        self._alloc_cbs = None
 
     def __del__(self):
         try:

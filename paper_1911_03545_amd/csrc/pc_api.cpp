@@ -23,6 +23,7 @@ namespace {
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    bool user = false;   // came from the registered allocator
 };
 
 enum BufId {
@@ -80,6 +81,10 @@ struct cf_ctx {
         int32_t slices_per_reach, chunk, angular_grid, xy_refine;
     };
     std::map<std::vector<int64_t>, Tuned> tuned;
+    // registered scratch allocator (cf_set_allocator); NULL: hipMalloc
+    cf_alloc_fn alloc = nullptr;
+    cf_free_fn free_ = nullptr;
+    void *alloc_user = nullptr;
 };
 
 namespace {
@@ -106,6 +111,22 @@ cf_status fail(cf_ctx *c, cf_status st, const char *fmt, ...)
 
 void drop_graph(cf_ctx *c);
 
+// Give a scratch buffer back to whichever allocator made it.
+hipError_t release(cf_ctx *c, DevBuf &b)
+{
+    hipError_t e = hipSuccess;
+    if (b.p) {
+        if (b.user)
+            c->free_(b.p, c->alloc_user);
+        else
+            e = hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    b.user = false;
+    return e;
+}
+
 cf_status ensure(cf_ctx *c, BufId id, size_t bytes)
 {
     bytes = std::max<size_t>(bytes, 256);
@@ -116,15 +137,26 @@ cf_status ensure(cf_ctx *c, BufId id, size_t bytes)
     drop_graph(c);
     if (b.p) {
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(b.p));
-        b.p = nullptr;
-        b.cap = 0;
+        HIPCHK(release(c, b));
     }
     size_t want = bytes + bytes / 4;
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, CF_ENOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    if (c->alloc) {
+        b.p = c->alloc(want, c->alloc_user);
+        if (!b.p)
+            return fail(c, CF_ENOMEM, "registered allocator returned NULL for %zu bytes", want);
+        if (reinterpret_cast<uintptr_t>(b.p) % 256 != 0) {
+            c->free_(b.p, c->alloc_user);
+            b.p = nullptr;
+            return fail(c, CF_EINVAL, "registered allocator returned memory not 256-byte aligned");
+        }
+        b.user = true;
+    } else {
+        hipError_t e = hipMalloc(&b.p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(c, CF_ENOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+        }
     }
     b.cap = want;
     return CF_OK;
@@ -1473,8 +1505,7 @@ cf_status cf_destroy(cf_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->buf)
-        if (b.p)
-            (void)hipFree(b.p);
+        (void)release(c, b);
     if (c->pinned)
         (void)hipHostFree(c->pinned);
     drop_graph(c);
@@ -1486,6 +1517,28 @@ cf_status cf_destroy(cf_ctx *c)
         if (ev)
             (void)hipEventDestroy(ev);
     delete c;
+    return CF_OK;
+}
+
+cf_status cf_set_allocator(cf_ctx *c, cf_alloc_fn alloc, cf_free_fn free_, void *user)
+{
+    if (!c)
+        return CF_EINVAL;
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return fail(c, CF_EINVAL, "give both an allocation and a release function, or neither");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    // buffers from the previous allocator go back to it; a recorded graph
+    // held their addresses
+    drop_graph(c);
+    for (auto &b : c->buf)
+        HIPCHK(release(c, b));
+    c->last_items = 0;
+    c->last_shape.clear();
+    c->alloc = alloc;
+    c->free_ = free_;
+    c->alloc_user = user;
+    c->err.clear();
     return CF_OK;
 }
 

@@ -143,3 +143,9 @@ def test_options_layout_matches_library(lib):
     assert o.struct_size == ctypes.sizeof(pc.cf_options)
     assert pc.cf_options.ravg.offset == 64 and ctypes.sizeof(pc.cf_options) == 72
     assert o.weight_type == pc.CF_WEIGHT_PRODUCT and not o.ravg
+
+
+def test_set_allocator_rejects_null_context(lib):
+    """The allocator hook checks its context before touching any device."""
+    st = lib.cf_set_allocator(None, pc.ALLOC_FN(), pc.FREE_FN(), None)
+    assert st == pc.CF_EINVAL
