@@ -36,6 +36,7 @@ SEED = 2
 FLOPS_PER_PAIR = 8          # 3 subtractions, 1 multiply, 2 fused multiply-adds
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_r_fp32_n1e6_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_r_fp32_n1e6_counters.txt")
 SWEEP_SRC = os.path.join(ROOT, "paper_1911_03545_amd", "csrc", "pc_sweep.hip")
 
 
@@ -62,6 +63,46 @@ def ref_pairs(pts: np.ndarray, L: float, rmax: float) -> int:
     for o in offs:
         total += int((C * np.roll(C, shift=(-o[0], -o[1], -o[2]), axis=(0, 1, 2))).sum())
     return total
+
+
+def profile_value(path, key):
+    """A `key: value` line of a committed rocprofv3 summary, if the summary
+    was taken on the current sweep source (else None)."""
+    if not os.path.exists(path):
+        return None
+    src_hash = hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("sweep_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(vals[key])
+    except (KeyError, ValueError):
+        return None
+
+
+def valu_fractions(t_sweep_s: float, candidates: int):
+    """The sweep's VALU use three ways, from the committed SQ_INSTS_VALU count
+    of the same launch (per dispatch) and the live sweep time: (1) VALU
+    lane-operations over the packed float32 lane-operation peak (256 CU x 64
+    lanes x 2 x 2.4 GHz = 78.6e12/s), and over the non-packed issue limit
+    this build runs at (half that); (2) useful-op efficiency, 6 lane-operations
+    per candidate pair (3 subtractions, a multiply, 2 fused multiply-adds) over
+    the lane-operations executed; (3) their product."""
+    insts = profile_value(COUNTERS_FILE, "valu_insts_per_dispatch")
+    if insts is None or t_sweep_s <= 0:
+        return None
+    lane_ops = insts * 64.0
+    util = lane_ops / (t_sweep_s * 78.6e12)
+    useful = 6.0 * candidates / lane_ops
+    return {"valu_lane_ops_per_launch": lane_ops,
+            "utilisation_vs_packed_peak": util,
+            "utilisation_vs_issue_limit": 2.0 * util,
+            "useful_op_efficiency": useful,
+            "algorithmic_fraction": util * useful}
 
 
 def read_traffic():
@@ -623,6 +664,8 @@ def main():
             "frac": achieved / PEAK_FP32_NONPACKED,
             "traffic": read_traffic(),
         },
+        "valu": valu_fractions(t_sweep, st["candidate_pairs"]) if args.precision == "fp32"
+        else None,
         "sweep": {
             "kernel_ms": t_sweep * 1e3,
             "candidate_pairs": st["candidate_pairs"],
