@@ -183,7 +183,7 @@ def cpu_baseline(pts: np.ndarray, w_ref: int, target_s: float = 12.0):
 
 
 def batch_bench(args):
-    """Batched DD(rp, pi): 256 clustered mock catalogues of 2e5-2e6 points in
+    """Batched DD(rp, pi): 256 (--batch-cats) clustered mock catalogues of 2e5-2e6 points in
     periodic L = 1000 boxes, 20 log rp bins in [0.1, 25], pimax = 40 in 40
     bins.  Reports the 2x2 ablation {binary64, float32 + recheck} x {256
     sequential calls, one batched call replayed from a graph}, as Gpair-evals/s
@@ -244,8 +244,8 @@ def batch_bench(args):
                      "xy_refine": st["xy_refine"],
                      "replayed": st["replayed"]}
     line = {
-        "metric": "Gpair-evals/s for batched DD(rp,pi), 256 mocks, FP32+recheck batched vs "
-                  "plain FP64 sequential",
+        "metric": f"Gpair-evals/s for batched DD(rp,pi), {len(sizes)} mocks, FP32+recheck "
+                  "batched vs plain FP64 sequential",
         "value": res["fp32"]["batched_value"],
         "unit": "Gpair-evals/s",
         "n_gpus": 1,
