@@ -89,7 +89,7 @@ def valu_fractions(t_sweep_s: float, candidates: int):
     of the same launch (per dispatch) and the live sweep time: (1) VALU
     lane-operations over the packed float32 lane-operation peak (256 CU x 64
     lanes x 2 x 2.4 GHz = 78.6e12/s), and over the non-packed issue limit
-    this build runs at (half that); (2) useful-op efficiency, 6 lane-operations
+    the kernels are compiled for (half that: packed float32 is disabled); (2) useful-op efficiency, 6 lane-operations
     per candidate pair (3 subtractions, a multiply, 2 fused multiply-adds) over
     the lane-operations executed; (3) their product."""
     insts = profile_value(COUNTERS_FILE, "valu_insts_per_dispatch")
