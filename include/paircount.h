@@ -145,7 +145,16 @@ typedef struct cf_options {
                                    transverse distance when the reach is a
                                    ball.  Lowered when a periodic box has fewer
                                    than 2k+1 columns.                           */
-    int32_t reserved[4];
+    int32_t radec_on_host;      /* RA/DEC (and distance) input: 1 converts to
+                                   unit vectors (positions) on the host with
+                                   the C library's sin and cos, the same
+                                   formula and library as a host reference, so
+                                   counts are reproducible against it bit for
+                                   bit; 0 (default) converts on the device,
+                                   whose math library may differ in the last
+                                   bit.  Device-resident input is copied to the
+                                   host first.                                 */
+    int32_t reserved[3];
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
                                    in each bin (r, rp, or theta in degrees),

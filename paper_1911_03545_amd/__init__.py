@@ -62,7 +62,8 @@ class cf_options(ctypes.Structure):
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("weight_type", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
-                ("xy_refine", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
+                ("xy_refine", ctypes.c_int32), ("radec_on_host", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3),
                 ("ravg", ctypes.c_void_p)]
 
 

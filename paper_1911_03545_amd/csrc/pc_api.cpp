@@ -287,8 +287,69 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // RA/DEC become unit vectors.
 // radec: x, y are RA, DEC in degrees, converted on the device to unit
 // vectors, or (sky) to positions D u with the distance D in z.
+// RA/DEC (and distance) of one catalogue to unit vectors (positions) on the
+// host with the C library's sin and cos: v = (cos d cos a, cos d sin a, sin d)
+// with a, d in radians (degrees times pi/180), times the distance for on-sky
+// pairs.  The vectors go to vx, vy, vz on the device.
+cf_status radec_on_host(cf_ctx *c, const cf_catalog &cat, bool sky, double *vx, double *vy,
+                        double *vz)
+{
+    const size_t n = (size_t)cat.n;
+    std::vector<double> in((sky ? 3 : 2) * n), out(3 * n);
+    auto fetch = [&](const void *src, int dtype, double *dst) -> cf_status {
+        const size_t bytes = dsize(dtype) * n;
+        std::vector<char> tmp;
+        const void *h = src;
+        if (cat.mem == CF_MEM_DEVICE) {
+            tmp.resize(bytes);
+            HIPCHK(hipMemcpyAsync(tmp.data(), src, bytes, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            h = tmp.data();
+        }
+        if (dtype == CF_F32)
+            for (size_t i = 0; i < n; i++)
+                dst[i] = static_cast<const float *>(h)[i];
+        else
+            memcpy(dst, h, bytes);
+        return CF_OK;
+    };
+    cf_status st;
+    if ((st = fetch(cat.x, cat.dtype, in.data())) ||
+        (st = fetch(cat.y, cat.dtype, in.data() + n)) ||
+        (sky && (st = fetch(cat.z, cat.dtype, in.data() + 2 * n))))
+        return st;
+    const double d2r = M_PI / 180.0;
+    for (size_t i = 0; i < n; i++) {
+        const double a = in[i], d = in[n + i];
+        if (!(a >= 0.0 && a <= 360.0 && d >= -90.0 && d <= 90.0))
+            return fail(c, CF_ERANGE, "RA must lie in [0, 360] and DEC in [-90, 90]");
+        const double ar = a * d2r, dr = d * d2r;
+        const double cd = cos(dr);
+        double ux = cd * cos(ar), uy = cd * sin(ar), uz = sin(dr);
+        if (sky) {
+            const double D = in[2 * n + i];
+            if (!(D >= 0.0) || !std::isfinite(D))
+                return fail(c, CF_EINVAL, "distances must be finite and non-negative");
+            ux = D * ux;
+            uy = D * uy;
+            uz = D * uz;
+        }
+        out[i] = ux;
+        out[n + i] = uy;
+        out[2 * n + i] = uz;
+    }
+    HIPCHK(hipMemcpyAsync(vx, out.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(vy, out.data() + n, sizeof(double) * n, hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(vz, out.data() + 2 * n, sizeof(double) * n, hipMemcpyHostToDevice,
+                          c->stream));
+    // `out` is released on return
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CF_OK;
+}
+
 cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, bool sky, int side,
-                     SideData &s, unsigned *flags)
+                     SideData &s, unsigned *flags, bool host_radec)
 {
     static const BufId inb[2][4] = {{B_IN1X, B_IN1Y, B_IN1Z, B_IN1W},
                                     {B_IN2X, B_IN2Y, B_IN2Z, B_IN2W}};
@@ -335,18 +396,25 @@ cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, bool 
     for (int i = 0; i < ncat; i++) {
         const cf_catalog &cat = d[i];
         pc_cat &o = s.cats[i];
-        const void *x = place(0, cat.x, cat.dtype, cat);
-        const void *y = place(1, cat.y, cat.dtype, cat);
-        const void *z = (radec && !sky) ? nullptr : place(2, cat.z, cat.dtype, cat);
+        // RA/DEC converted on the host are read where they are
+        const bool hconv = radec && host_radec;
+        const void *x = hconv ? cat.x : place(0, cat.x, cat.dtype, cat);
+        const void *y = hconv ? cat.y : place(1, cat.y, cat.dtype, cat);
+        const void *z = ((radec && !sky) || hconv) ? nullptr : place(2, cat.z, cat.dtype, cat);
         const void *w = cat.w ? place(3, cat.w, cat.wdtype, cat) : nullptr;
-        if (cat.n > 0 && (!x || !y || ((!radec || sky) && !z) || (cat.w && !w)))
+        if (cat.n > 0 &&
+            (!x || !y || ((!radec || sky) && !hconv && !z) || (cat.w && !w)))
             return fail(c, CF_EDEVICE, "host-to-device copy of catalogue %d failed", i);
         if (radec) {
             double *v = dptr<double>(c, uvb);
             double *vx = v + o.off, *vy = v + s.ntot + o.off, *vz = v + 2 * s.ntot + o.off;
-            if (cat.n > 0)
+            if (cat.n > 0 && hconv) {
+                if ((st = radec_on_host(c, cat, sky, vx, vy, vz)))
+                    return st;
+            } else if (cat.n > 0) {
                 HIPCHK(pc::launch_radec(c->stream, cat.n, x, y, sky ? z : nullptr,
                                         cat.dtype == CF_F32, M_PI / 180.0, vx, vy, vz, flags));
+            }
             o.x = vx;
             o.y = vy;
             o.z = vz;
@@ -641,9 +709,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     unsigned *flags = (unsigned *)(misc(c) + M_FLAGS);
     const bool radec = (theta || sky) && !unit_vec;
     SideData s1, s2;
-    if ((st2 = stage_side(c, d1, ncat, radec, sky, 0, s1, flags)))
+    if ((st2 = stage_side(c, d1, ncat, radec, sky, 0, s1, flags, opt.radec_on_host != 0)))
         return st2;
-    if (!autocorr && (st2 = stage_side(c, d2, 1, radec, sky, 1, s2, flags)))
+    if (!autocorr &&
+        (st2 = stage_side(c, d2, 1, radec, sky, 1, s2, flags, opt.radec_on_host != 0)))
         return st2;
     if ((st2 = ensure(c, B_CATS1, sizeof(pc_cat) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CATS2, sizeof(pc_cat))))

@@ -93,9 +93,9 @@ struct pc_grid {
     // angular grid: declination bands of nband * n[2] slices, slice index
     // floor((dec - dec_lo) * inv_hs); bands is a device table of nband entries
     int32_t nband;
-    int32_t ra_refine;
     double dec_lo;
     double inv_hs;
+    double sky_reach;   // angular reach with its margins (radians)
     const pc_band *bands;
 };
 

@@ -269,14 +269,14 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
     g->n[2] = slices;
     g->ncell = ncol * slices;
     g->nband = nb;
-    g->ra_refine = ra_refine;
     g->dec_lo = dlo;
     g->inv_hs = slices / h;
     g->inv_w[0] = 0.0;
     g->inv_w[1] = 0.0;
     g->inv_w[2] = g->inv_hs;
     g->width[0] = h;
-    g->width[1] = theta;
+    g->width[1] = 0.0;
+    g->sky_reach = theta;
     g->width[2] = h / slices;
     const double r = theta * g->inv_hs;
     const int zr = (int)floor(r * (1.0 + 0x1p-28) + 0x1p-28) + 1;
@@ -635,7 +635,7 @@ extern "C" cf_status cf_plan_sky_grid(double chord_reach, double zlo, double zhi
     out->dec_lo = g.dec_lo;
     out->band_height = g.width[0];
     out->inv_slice = g.inv_hs;
-    out->theta_reach = g.width[1];
+    out->theta_reach = g.sky_reach;
     for (size_t k = 0; k < b.size(); k++) {
         bands[k].col0 = b[k].col0;
         bands[k].nra = b[k].nra;

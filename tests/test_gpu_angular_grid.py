@@ -201,3 +201,35 @@ def test_cap_fullsize_equals_chord_grid(pc, olib):
     got, _ = pc.count_theta(ra[idx], dec[idx], ra, dec, te, "fp32", angular_grid=2)
     want, _ = oracle.count_theta(ra[idx], dec[idx], ra, dec, te, lib=olib)
     assert (got == want).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_radec_converted_on_host(pc, olib, prec):
+    """RA/DEC converted on the host (cf_options.radec_on_host) with the same
+    C library as the oracle: counts equal the oracle's bit for bit, for host
+    and device-resident float64 and float32 input."""
+    import torch
+    say("radec on host", prec)
+    ra, dec = full_sky(60000, 513)
+    rr, rd = synth.cap_radec(50000, seed=514, radius_deg=40.0, dec0_deg=60.0)
+    te = synth.log_edges(0.02, 6.0, 12)
+    opts = {"radec_on_host": 1}
+    want, _ = oracle.count_theta(ra, dec, None, None, te, lib=olib)
+    got, _ = pc.count_theta(ra, dec, None, None, te, prec, options=opts)
+    assert (got == want).all()
+    dra, ddec = (torch.from_numpy(a).to("cuda:0") for a in (ra, dec))
+    got, _ = pc.count_theta(dra, ddec, None, None, te, prec, options=opts)
+    assert (got == want).all()
+    want, _ = oracle.count_theta(ra, dec, rr, rd, te, lib=olib)
+    got, _ = pc.count_theta(ra, dec, rr, rd, te, prec, options=opts)
+    assert (got == want).all()
+    r32, d32 = ra.astype(np.float32), dec.astype(np.float32)
+    want, _ = oracle.count_theta(r32.astype(np.float64), d32.astype(np.float64), None, None, te,
+                                 lib=olib)
+    got, _ = pc.count_theta(r32, d32, None, None, te, prec, options=opts)
+    assert (got == want).all()
+    bad = dec.copy()
+    bad[7] = 91.0
+    import paper_1911_03545_amd as m
+    with pytest.raises(m.PairCountError):
+        pc.count_theta(ra, bad, None, None, te, prec, options=opts)

@@ -154,3 +154,20 @@ def test_mocks_fullsize_sampled(pc, olib):
     got, _ = pc.count_rppi_mocks(v[idx], v, e, 40.0, 40, "fp64", cartesian=True)
     want, _ = oracle.count_rppi_mocks(v[idx], v, e, 40.0, 40, lib=olib)
     assert (got == want).all()
+
+
+def test_mocks_radec_converted_on_host(pc, olib):
+    """RA/DEC/distance converted on the host (cf_options.radec_on_host) with
+    the oracle's C library: counts equal the oracle's on its own conversion
+    bit for bit."""
+    say("mocks radec on host")
+    m = synth.sky_mock(40000, seed=409, radius_deg=6.0, dmin=500.0, dmax=900.0)
+    e = synth.log_edges(0.3, 25.0, 12)
+    want, _ = oracle.count_rppi_mocks(cart(m, olib), None, e, 30.0, 15, lib=olib)
+    got, _ = pc.count_rppi_mocks(m, None, e, 30.0, 15, "fp64", options={"radec_on_host": 1})
+    assert (got == want).all()
+    bad = m.copy()
+    bad[3, 2] = -5.0
+    import paper_1911_03545_amd as mm
+    with pytest.raises(mm.PairCountError):
+        pc.count_rppi_mocks(bad, None, e, 30.0, 15, "fp64", options={"radec_on_host": 1})
