@@ -779,6 +779,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pts, w_ref)
+        # time ratio of the full workload: the oracle's extrapolated time over a GPU call
+        line["cpu_baseline"]["gpu_speedup"] = value / line["cpu_baseline"]["value"]
     ctx.close()
     print(json.dumps(line), flush=True)
 
