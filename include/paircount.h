@@ -326,6 +326,18 @@ typedef struct cf_grid_plan {
 cf_status cf_plan_grid(const double lo[3], const double hi[3], double boxsize,
                        double reach_xy, double reach_z, int32_t slices_per_reach,
                        cf_grid_plan *out);
+/* The same with x/y refinement (cf_options.xy_refine; columns at least
+   reach_xy / k wide, k lowered while a periodic axis has fewer than 2k + 1
+   columns) and, with `ball` nonzero (the reach is a 3-D ball: r, angular
+   chords, on-sky pairs), the z window of each column offset narrowed by the
+   offsets' smallest transverse distance.  zro receives 25 values, zro[5 a +
+   b] for offsets |ox| = a, |oy| = b (0..4): the z slices searched on each
+   side, -1 where no pair of the two columns can be within reach.  *k_used
+   receives k. */
+cf_status cf_plan_grid_ex(const double lo[3], const double hi[3], double boxsize,
+                          double reach_xy, double reach_z, int32_t slices_per_reach,
+                          int32_t xy_refine, int32_t ball, cf_grid_plan *out, int16_t *zro,
+                          int32_t *k_used);
 
 /* Angular grid plan (host only, no device work) -- see
    cf_options.angular_grid.  chord_reach: the largest chord 2 sin(theta_max/2)

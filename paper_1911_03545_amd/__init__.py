@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
-    "cf_plan_grid", "cf_plan_sky_grid", "cf_fp32_bands",
+    "cf_plan_grid", "cf_plan_grid_ex", "cf_plan_sky_grid", "cf_fp32_bands",
 )
 
 
@@ -172,6 +172,9 @@ def load_library(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.cf_plan_grid.argtypes = [vp, vp, dbl, dbl, dbl, i32, ctypes.POINTER(cf_grid_plan)]
     lib.cf_plan_grid.restype = ctypes.c_int
+    lib.cf_plan_grid_ex.argtypes = [vp, vp, dbl, dbl, dbl, i32, i32, i32,
+                                    ctypes.POINTER(cf_grid_plan), vp, vp]
+    lib.cf_plan_grid_ex.restype = ctypes.c_int
     lib.cf_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
     lib.cf_set_allocator.restype = ctypes.c_int
     lib.cf_plan_sky_grid.argtypes = [dbl, dbl, dbl, i32, i32, ctypes.POINTER(cf_sky_plan),
@@ -208,6 +211,28 @@ def plan_grid(lo, hi, boxsize: float, reach_xy: float, reach_z: float,
     return {"n": list(p.n), "width": list(p.width), "extent": list(p.extent),
             "inv_width": list(p.inv_width), "lo": list(p.lo), "zreach": p.zreach,
             "periodic": p.periodic, "ncell": p.ncell}
+
+
+def plan_grid_refined(lo, hi, boxsize: float, reach_xy: float, reach_z: float,
+                      slices_per_reach: int = 32, xy_refine: int = 1, ball: bool = True) -> dict:
+    """Host-only grid plan with x/y refinement; adds the per-offset z windows
+    ``zro`` (5 x 5, -1: offset skipped) and the refinement used ``k``."""
+    lib = load_library()
+    lo_a = np.ascontiguousarray(lo if lo is not None else [0, 0, 0], dtype=np.float64)
+    hi_a = np.ascontiguousarray(hi if hi is not None else [0, 0, 0], dtype=np.float64)
+    p = cf_grid_plan()
+    zro = np.zeros(25, dtype=np.int16)
+    k = ctypes.c_int32(0)
+    st = lib.cf_plan_grid_ex(lo_a.ctypes.data, hi_a.ctypes.data, float(boxsize),
+                             float(reach_xy), float(reach_z), int(slices_per_reach),
+                             int(xy_refine), int(bool(ball)), ctypes.byref(p), zro.ctypes.data,
+                             ctypes.byref(k))
+    if st != CF_OK:
+        raise PairCountError(st, "cf_plan_grid_ex failed")
+    return {"n": list(p.n), "width": list(p.width), "extent": list(p.extent),
+            "inv_width": list(p.inv_width), "lo": list(p.lo), "zreach": p.zreach,
+            "periodic": p.periodic, "ncell": p.ncell, "zro": zro.reshape(5, 5).copy(),
+            "k": k.value}
 
 
 def plan_sky_grid(chord_reach: float, zlo: float, zhi: float, slices: int = 16,

@@ -586,14 +586,25 @@ extern "C" cf_status cf_plan_grid(const double lo[3], const double hi[3],
                                   double boxsize, double reach_xy, double reach_z,
                                   int32_t slices_per_reach, cf_grid_plan *out)
 {
+    return cf_plan_grid_ex(lo, hi, boxsize, reach_xy, reach_z, slices_per_reach, 1, 0, out,
+                           nullptr, nullptr);
+}
+
+extern "C" cf_status cf_plan_grid_ex(const double lo[3], const double hi[3], double boxsize,
+                                     double reach_xy, double reach_z, int32_t slices_per_reach,
+                                     int32_t xy_refine, int32_t ball, cf_grid_plan *out,
+                                     int16_t *zro, int32_t *k_used)
+{
     if (!out)
         return CF_EINVAL;
     double zl[3] = {0, 0, 0}, zh[3] = {0, 0, 0};
     if (boxsize <= 0.0 && (!lo || !hi))
         return CF_EINVAL;
+    if (xy_refine < 1 || xy_refine > PC_MAX_XYK)
+        return CF_EINVAL;
     pc_grid g;
     int rc = pc::plan_grid(lo ? lo : zl, hi ? hi : zh, boxsize, reach_xy, reach_z,
-                           slices_per_reach, &g, 1, false);
+                           slices_per_reach, &g, xy_refine, ball != 0);
     if (rc)
         return (cf_status)rc;
     memset(out, 0, sizeof(*out));
@@ -608,6 +619,12 @@ extern "C" cf_status cf_plan_grid(const double lo[3], const double hi[3],
     out->periodic = g.periodic;
     out->boxsize = g.boxsize;
     out->ncell = g.ncell;
+    if (zro)
+        for (int a = 0; a <= PC_MAX_XYK; a++)
+            for (int b = 0; b <= PC_MAX_XYK; b++)
+                zro[a * (PC_MAX_XYK + 1) + b] = g.zro[a][b];
+    if (k_used)
+        *k_used = g.xyk;
     return CF_OK;
 }
 
