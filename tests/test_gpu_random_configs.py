@@ -5,7 +5,7 @@ Each case draws a statistic (DD(r), DD(rp, pi), DD(theta), on-sky DD(rp,
 pi), batched DD(rp, pi)), auto or cross, periodic or not, float32 or
 float64 inputs on the host or the device, weights (product or sum), the mean
 separation, precision, slices per reach, work-item chunk, x/y or angular
-refinement, and bin edges (log, linear, with e0 = 0 or not), with sizes the
+refinement, RA/DEC input converted on the host or unit vectors, and bin edges (log, linear, with e0 = 0 or not), with sizes the
 oracle counts in well under a second.  Counts must equal the oracle's bit for
 bit; weighted sums within 1e-12 relative; mean separations within 1e-9
 relative in binary64, and in float32 within the bound 10u C + 8u r of the
@@ -173,9 +173,15 @@ def test_random_config(pc, olib, case):
         v1 = oracle.radec_to_unit(ra, dec, lib=olib)
         v2 = None if auto else oracle.radec_to_unit(r2, d2, lib=olib)
         grid = opts.pop("angular_grid")
-        got = pc.count_theta(None, None, theta_edges_deg=te, precision=prec, w1=w1, w2=w2,
-                             unit_vectors=(v1, v2), options=opts, ravg=ravg,
-                             angular_grid=grid, **kw)
+        if rng.random() < 0.5:
+            # RA/DEC converted on the host with the oracle's library
+            opts["radec_on_host"] = 1
+            got = pc.count_theta(ra, dec, r2, d2, te, prec, w1=w1, w2=w2, options=opts,
+                                 ravg=ravg, angular_grid=grid, **kw)
+        else:
+            got = pc.count_theta(None, None, theta_edges_deg=te, precision=prec, w1=w1, w2=w2,
+                                 unit_vectors=(v1, v2), options=opts, ravg=ravg,
+                                 angular_grid=grid, **kw)
         want = oracle.count_theta(ra, dec, r2, d2, te, w1=w1, w2=w2, lib=olib, ravg=ravg,
                                   weight_type=wtype or "product")
     elif stat == "mocks":
@@ -194,8 +200,13 @@ def test_random_config(pc, olib, case):
         e = edges_for(rng, 0.1, float(rng.uniform(5.0, 25.0)), int(rng.integers(1, 20)))
         pimax = float(rng.uniform(5.0, 40.0))
         npi = int(rng.integers(1, 40))
-        got = pc.count_rppi_mocks(v1, v2, e, pimax, npi, prec, w1=w1, w2=w2, options=opts,
-                                  ravg=ravg, cartesian=True, **kw)
+        if rng.random() < 0.5:
+            opts["radec_on_host"] = 1
+            got = pc.count_rppi_mocks(m1, None if auto else m2, e, pimax, npi, prec, w1=w1,
+                                      w2=w2, options=opts, ravg=ravg, **kw)
+        else:
+            got = pc.count_rppi_mocks(v1, v2, e, pimax, npi, prec, w1=w1, w2=w2, options=opts,
+                                      ravg=ravg, cartesian=True, **kw)
         want = oracle.count_rppi_mocks(v1, v2, e, pimax, npi, w1=w1, w2=w2, lib=olib,
                                        ravg=ravg, weight_type=wtype or "product")
     else:
