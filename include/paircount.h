@@ -116,9 +116,11 @@ typedef struct cf_options {
     int32_t hist_copies;        /* LDS histogram replicas per wave (0: auto)   */
     int32_t use_graph;          /* replay repeated identical calls from a HIP
                                    graph (periodic, device-resident inputs)    */
-    int32_t autotune;           /* time slices_per_reach and chunk candidates on
-                                   the first call of a workload class and reuse
-                                   the fastest (cached per context)            */
+    int32_t autotune;           /* time slices_per_reach and chunk candidates
+                                   (and, when left at 0, angular_grid 4 / 16
+                                   for angular counts or xy_refine 2 for 3-D
+                                   grids) on the first call of a workload class
+                                   and reuse the fastest (cached per context)  */
     int32_t weight_type;        /* cf_weight: weight of a pair from the weights
                                    of its two points (needs weights unless
                                    CF_WEIGHT_PRODUCT)                          */
