@@ -709,6 +709,24 @@ def main():
         graph = {"ms_per_step": msg, "value": w_ref / (msg / 1e3) / 1e9,
                  "replayed": ctx.stats()["replayed"]}
 
+    # the same call on host-resident columns: each call copies the 24 MB of
+    # float64 coordinates over PCIe first (reported, never the headline)
+    host = None
+    if not args.no_extras:
+        hcols = tuple(np.ascontiguousarray(pts[:, k]) for k in range(3))
+        ch, _ = ctx.count_r(hcols, None, EDGES, L_BOX, args.precision)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        k_host = max(5, args.steps // 5)
+        for _ in range(k_host):
+            ch, _ = ctx.count_r(hcols, None, EDGES, L_BOX, args.precision)
+        torch.cuda.synchronize()
+        msh = (time.perf_counter() - t) * 1e3 / k_host
+        if not np.array_equal(ch, counts):
+            raise SystemExit("host-input and device-input counts differ")
+        host = {"ms_per_step": msh, "value": w_ref / (msh / 1e3) / 1e9,
+                "input_bytes": int(sum(c.nbytes for c in hcols))}
+
     # the same workload with the mean separation per bin (one square root
     # and two more LDS sums per pair in range), in both precisions
     ravg = {}
@@ -775,6 +793,7 @@ def main():
         },
         "fp64_path": fp64,
         "graph_replay": graph,
+        "host_input_path": host,
         "ravg_path": ravg,
     }
     if not args.no_cpu_baseline:
