@@ -20,7 +20,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-NCASES = 100
+NCASES = 400
 U32 = 2.0 ** -24
 R2D = 180.0 / np.pi
 
