@@ -33,7 +33,8 @@
  *    of the coordinates (relative to the domain origin) and of the result.
  *  * boxsize > 0 selects a periodic cube [0, boxsize]^3 (every coordinate
  *    must lie in the closed interval); boxsize <= 0 selects a non-periodic
- *    domain bounded by the bounding box of both catalogues.
+ *    domain bounded by the bounding box of both catalogues; NaN or +inf is
+ *    CF_EINVAL.
  *  * Precision: CF_PREC_FP64 evaluates every pair in binary64 exactly as
  *    above.  CF_PREC_FP32_RECHECK evaluates pairs in float32 and decides only
  *    the pairs that a proven error bound places away from every squared edge;

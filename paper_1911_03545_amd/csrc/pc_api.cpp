@@ -602,8 +602,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     const int64_t nbt = (int64_t)nb * npi;
     if (nbt > PC_MAX_BINS_TOTAL / (want_ravg ? 3 : (weighted ? 2 : 1)))
         return fail(c, CF_EINVAL, "too many output bins (%lld)", (long long)nbt);
-    if (!isfinite(boxsize) && boxsize > 0.0)
-        return fail(c, CF_EINVAL, "boxsize must be finite");
+    if (isnan(boxsize) || (!isfinite(boxsize) && boxsize > 0.0))
+        return fail(c, CF_EINVAL, "boxsize must be finite (or <= 0 for no wrap)");
     if (theta && boxsize > 0.0)
         return fail(c, CF_EINVAL, "angular counts are never periodic");
     if (sky && boxsize > 0.0)

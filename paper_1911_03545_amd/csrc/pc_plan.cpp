@@ -105,7 +105,7 @@ int plan_grid_k(const double lo_in[3], const double hi_in[3], double boxsize,
     if (slices_per_reach <= 0)
         slices_per_reach = 16;
     const bool periodic = boxsize > 0.0;
-    if (periodic && !isfinite(boxsize))
+    if (std::isnan(boxsize) || (periodic && !isfinite(boxsize)))
         return CF_EINVAL;
     g->periodic = periodic ? 1 : 0;
     g->boxsize = periodic ? boxsize : 0.0;
@@ -598,7 +598,7 @@ extern "C" cf_status cf_plan_grid_ex(const double lo[3], const double hi[3], dou
     if (!out)
         return CF_EINVAL;
     double zl[3] = {0, 0, 0}, zh[3] = {0, 0, 0};
-    if (boxsize <= 0.0 && (!lo || !hi))
+    if (std::isnan(boxsize) || (boxsize <= 0.0 && (!lo || !hi)))
         return CF_EINVAL;
     if (xy_refine < 1 || xy_refine > PC_MAX_XYK)
         return CF_EINVAL;

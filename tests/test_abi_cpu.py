@@ -79,6 +79,18 @@ def test_plan_grid_unsupported_periodic(lib):
         pc.plan_grid(None, None, 100.0, 10.0, 34.0)   # pi reach above L/3
 
 
+def test_plan_grid_rejects_nan_and_inf_box(lib):
+    for box in (float("nan"), float("inf")):
+        with pytest.raises(pc.PairCountError) as e:
+            pc.plan_grid(None, None, box, 10.0, 10.0)
+        assert e.value.status == pc.CF_EINVAL
+        with pytest.raises(pc.PairCountError) as e:
+            pc.plan_grid([0, 0, 0], [50, 50, 50], box, 10.0, 10.0)
+        assert e.value.status == pc.CF_EINVAL
+    # -inf is a non-positive box: no wrap, bounded by lo/hi
+    assert pc.plan_grid([0, 0, 0], [50, 50, 50], float("-inf"), 10.0, 10.0)["periodic"] == 0
+
+
 def test_plan_grid_nonperiodic(lib):
     p = pc.plan_grid([0, 0, 0], [5, 50, 500], 0.0, 10.0, 10.0)
     assert p["n"][0] == 1 and p["n"][1] == 4

@@ -417,6 +417,10 @@ def test_error_codes(pc):
     with pytest.raises(m.PairCountError) as ex:
         pc.count_r(pts, pts, e, 10.0, w1=np.ones(100))
     assert ex.value.status == m.CF_EINVAL
+    for box in (float("nan"), float("inf")):
+        with pytest.raises(m.PairCountError) as ex:
+            pc.count_r(pts, None, e, box)
+        assert ex.value.status == m.CF_EINVAL
     # the context stays usable after errors
     got, _ = pc.count_r(pts, None, e, 10.0)
     assert got.sum() > 0
