@@ -105,6 +105,36 @@ def test_batch_many_small(pc, olib):
         assert (g32[k] == want).all(), k
 
 
+def test_batch_thousands_of_tiny_catalogues(pc, olib):
+    """5000 catalogues of 0-60 points (a quarter of them empty, a few with
+    one point) in one call, both precisions and as a recorded graph: every
+    slice equals the binary64 slice, every tenth the oracle's, and empty or
+    single-point catalogues count nothing."""
+    import torch
+    say("batch 5000 tiny")
+    rng = synth.rng_for(811)
+    sizes = rng.integers(0, 61, 5000)
+    sizes[rng.random(5000) < 0.25] = 0
+    sizes[:3] = [1, 0, 1]
+    cats = catalogues(list(sizes), 100.0, seed=20000)
+    e = synth.log_edges(0.1, 12.0, 6)
+    g64, _ = pc.count_rppi_batch(cats, e, 12.0, 6, 100.0, "fp64")
+    g32, _ = pc.count_rppi_batch(cats, e, 12.0, 6, 100.0, "fp32")
+    assert (g32 == g64).all()
+    # device-resident columns, recorded and then replayed
+    cols = [tuple(torch.from_numpy(np.ascontiguousarray(c[:, a])).cuda() for a in range(3))
+            for c in cats]
+    for rep in range(2):
+        g32, _ = pc.count_rppi_batch(cols, e, 12.0, 6, 100.0, "fp32", options={"use_graph": 1})
+        assert (g32 == g64).all()
+    assert pc.stats()["replayed"] == 1
+    assert g64.shape == (5000, 6, 6)
+    assert not g64[sizes <= 1].any()
+    for k in range(0, len(cats), 10):
+        want, _ = oracle.count_rppi(cats[k], None, e, 12.0, 6, 100.0, lib=olib)
+        assert (g64[k] == want).all(), (k, sizes[k])
+
+
 def test_batch_errors(pc):
     import paper_1911_03545_amd as m
     say("batch errors")
