@@ -112,6 +112,38 @@ def test_r_lattice_edge_ties(pc, olib, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_r_edges_one_ulp_apart(pc, olib, prec):
+    """Edges packed within a few ulps of sqrt(1), sqrt(2), sqrt(3), 2 and
+    sqrt(5) (each edge, its neighbours one ulp either side and one 1e-9
+    above), on integer lattice points whose squared separations are exact
+    integers, plus jittered points: float32 error bands of neighbouring edges
+    overlap, so the table's multi-edge cells and the binary64 recheck decide
+    every pair near them, and the counts between the packed edges come from
+    the binary64 rounding of the squared edges alone.  DD(rp, pi) on the
+    same rp edges with integer pi edges adds ties along the line of sight."""
+    say("r edges one ulp apart", prec)
+    rng = synth.rng_for(13)
+    lat = rng.integers(0, 24, size=(5000, 3)).astype(np.float64)
+    jit = lat[:2000] + rng.uniform(-1e-6, 1e-6, size=(2000, 3))
+    pts = np.clip(np.r_[lat, jit], 0.0, 24.0)
+    base = np.sqrt(np.array([1.0, 2.0, 3.0, 4.0, 5.0]))
+    e = np.unique(np.concatenate([base, np.nextafter(base, 0.0), np.nextafter(base, 9.0),
+                                  base * (1 + 1e-9)]))
+    assert e.size == 20 and np.all(np.diff(e) > 0)
+    for box in (24.0, 0.0):
+        got, _ = pc.count_r(pts, None, e, box, prec)
+        want, _ = oracle.count_r(pts, None, e, box, lib=olib)
+        assert (got == want).all(), (box, got, want)
+        assert want.sum() > 0
+        if prec == "fp32":
+            assert pc.stats()["rechecks"] > 0
+        # the same rp edges with integer pi edges: ties in both dimensions
+        got, _ = pc.count_rppi(pts, None, e, 5.0, 5, box, prec)
+        want, _ = oracle.count_rppi(pts, None, e, 5.0, 5, box, lib=olib)
+        assert (got == want).all(), (box, got, want)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_r_points_on_faces_and_coincident(pc, olib, prec):
     say("r faces", prec)
     pts = synth.uniform_box(4000, 30.0, seed=12)
