@@ -318,6 +318,29 @@ def test_theta_auto_cross(pc, olib, prec):
     assert (got == want).all(), (got, want)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_theta_edges_one_ulp_apart(pc, olib, prec):
+    """theta edges packed within an ulp of 0.5, 1, 1.5 and 2 degrees (each
+    edge and its neighbours one ulp either side) on a half-degree RA/DEC grid
+    (many separations of exactly those angles up to rounding) plus random cap
+    points, converted on the host: counts equal the oracle's on the angular
+    and the 3-D chord grid."""
+    say("theta edges one ulp apart", prec)
+    g = np.arange(0.0, 10.01, 0.5)
+    gra, gdec = (a.ravel() for a in np.meshgrid(g, g - 5.0))
+    ra, dec = synth.cap_radec(8000, seed=35, radius_deg=7.0, ra0_deg=5.0, dec0_deg=0.0)
+    ra, dec = np.r_[gra, ra], np.r_[gdec, dec]
+    base = np.array([0.5, 1.0, 1.5, 2.0])
+    te = np.unique(np.concatenate([base, np.nextafter(base, 0.0), np.nextafter(base, 9.0)]))
+    assert te.size == 12
+    want, _ = oracle.count_theta(ra, dec, None, None, te, lib=olib)
+    assert want.sum() > 0
+    for grid in (None, -1):
+        got, _ = pc.count_theta(ra, dec, None, None, te, prec, angular_grid=grid,
+                                options={"radec_on_host": 1})
+        assert (got == want).all(), (grid, got, want)
+
+
 def test_theta_unit_vectors_and_weights(pc, olib):
     say("theta unit vectors")
     ra, dec = synth.cap_radec(9000, seed=33, radius_deg=20.0, clustered=True,
