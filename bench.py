@@ -616,7 +616,7 @@ def main():
                          "chord and angular grids) instead")
     ap.add_argument("--weighted", action="store_true",
                     help="run the weighted xi(r) / wp(rp) benchmark (4e6 points, L=1100) instead")
-    ap.add_argument("--theta-grids", default="-1,4,8,16",
+    ap.add_argument("--theta-grids", default="-1,8,16,32",
                     help="angular_grid values for --theta (-1: 3-D chord grid)")
     ap.add_argument("--theta-precisions", default="fp32,fp64")
     args = ap.parse_args()

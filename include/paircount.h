@@ -118,7 +118,7 @@ typedef struct cf_options {
     int32_t use_graph;          /* replay repeated identical calls from a HIP
                                    graph (periodic, device-resident inputs)    */
     int32_t autotune;           /* time slices_per_reach and chunk candidates
-                                   (and, when left at 0, angular_grid 4 / 16
+                                   (and, when left at 0, angular_grid 8 / 32
                                    for angular counts or xy_refine 2 for 3-D
                                    grids) on the first call of a workload class
                                    and reuse the fastest (cached per context)  */
@@ -129,7 +129,7 @@ typedef struct cf_options {
                                    (default): the paper's angular grid
                                    (section "Partitioning the particles on a
                                    grid: angular correlation functions") with
-                                   8 right-ascension cells per reach.  n in
+                                   16 right-ascension cells per reach.  n in
                                    1..64: declination bands one angular reach
                                    high, cut into right-ascension cells 1/n of
                                    the band's right-ascension reach wide, with

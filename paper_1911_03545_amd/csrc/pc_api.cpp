@@ -612,10 +612,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "angular_grid must be in [-1, 64]");
     if (opt.angular_grid != 0 && !theta)
         return fail(c, CF_EINVAL, "angular_grid applies to angular counts only");
-    // angular counts default to the angular grid with 8 right-ascension
+    // angular counts default to the angular grid with 16 right-ascension
     // cells per reach; -1 selects 3-D cells on the unit vectors
     if (theta && opt.angular_grid == 0)
-        opt.angular_grid = 8;
+        opt.angular_grid = 16;
     if (opt.angular_grid < 0)
         opt.angular_grid = 0;
     const bool sky_grid = theta && opt.angular_grid > 0;
@@ -1408,7 +1408,7 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
             // the angular grid of angular counts is tuned too when left at
             // its default
             const bool tune_ang = theta && opt_in->angular_grid == 0;
-            int32_t best_ang = tune_ang ? 8 : opt_in->angular_grid;
+            int32_t best_ang = tune_ang ? 16 : opt_in->angular_grid;
             int32_t best_spr = 32, best_chunk = 2048;
             // x/y refinement of a 3-D grid, when left at its default
             const bool tune_xy = opt_in->xy_refine == 0 && !(theta && best_ang >= 0);
@@ -1455,7 +1455,7 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
                 }
             }
             if (tune_ang)
-                for (int32_t ang : {4, 16}) {
+                for (int32_t ang : {8, 32}) {
                     double ms;
                     if ((st = time_call(best_spr, best_chunk, ang, &ms)))
                         return st;

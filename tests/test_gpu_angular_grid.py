@@ -88,7 +88,7 @@ def test_seam_cap_matches_chord_grid(pc, olib, prec):
     chord, _ = pc.count_theta(ra, dec, None, None, te, prec, angular_grid=-1)
     assert (chord == want).all()
     default, _ = pc.count_theta(ra, dec, None, None, te, prec)
-    assert (default == want).all() and pc.stats()["angular_grid"] == 8
+    assert (default == want).all() and pc.stats()["angular_grid"] == 16
     want, _ = oracle.count_theta(ra, dec, rr, rd, te, lib=olib)
     got, _ = pc.count_theta(ra, dec, rr, rd, te, prec, angular_grid=2)
     assert (got == want).all()
