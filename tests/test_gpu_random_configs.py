@@ -105,7 +105,7 @@ def options_for(rng, stat):
     if stat in ("r", "rppi", "mocks") and rng.random() < 0.5:
         o["xy_refine"] = int(rng.integers(1, 5))
     if stat == "theta":
-        o["angular_grid"] = int(rng.choice([-1, 1, 2, 8, 16]))
+        o["angular_grid"] = int(rng.choice([-1, 0, 1, 2, 8, 16, 32]))
     return o
 
 
@@ -151,6 +151,8 @@ def test_random_config(pc, olib, case):
         else:
             pimax = float(rng.uniform(1.0, L / 3.2))
             npi = int(rng.integers(1, 60))
+            if ravg:   # the library's limit on bins with the mean separation
+                npi = min(npi, 1365 // (e.size - 1))
             got = pc.count_rppi(da, db, e, pimax, npi, box, prec, w1=dw1, w2=dw2,
                                 options=opts, ravg=ravg, **kw)
             want = oracle.count_rppi(ha, hb, e, pimax, npi, box, w1=w1, w2=w2, lib=olib,
