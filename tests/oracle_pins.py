@@ -624,6 +624,40 @@ def pin_sky_to_cartesian(lib):
     assert np.allclose(np.linalg.norm(v, axis=1), D, rtol=1e-15)
 
 
+def pin_pi_edges_inexact_width(lib):
+    """pi edges for a width pimax/npi that binary64 cannot hold (reading of
+    Appendix A's linear pi bins): q_p is p times the rounded width, rounded
+    once more, q_npi = pimax, and a bin is half-open.  The expected edges come
+    from exact rational arithmetic (Fraction) rounded by Python's
+    correctly-rounded conversion; pairs placed exactly on each edge and one
+    ulp below it must land in the upper and lower bin respectively.  With
+    pimax = 10 and npi = 9 the edge q_7 differs from the once-rounded 70/9,
+    so the rounding order is visible; with pimax = 13 and npi = 23 the width
+    times npi falls one ulp short of pimax, so the top edge must be pimax
+    itself."""
+    for pimax, npi in ((10.0, 9), (13.0, 23)):
+        width = float(Fraction(pimax) / npi)
+        want = [float(Fraction(p) * Fraction(width)) for p in range(npi)] + [pimax]
+        if npi == 9:
+            assert want[7] != float(Fraction(7) * Fraction(pimax) / npi)
+        else:
+            assert float(Fraction(npi) * Fraction(width)) != pimax
+        q = oracle.pi_edges(pimax, npi, lib=lib)
+        assert q.tolist() == want, (q, want)
+        zs, expect = [], np.zeros(npi, dtype=np.int64)
+        for p in range(1, npi + 1):
+            on, below = want[p], math.nextafter(want[p], 0.0)
+            zs += [on, below]
+            if p < npi:
+                expect[p] += 1
+            expect[p - 1] += 1
+        d1 = np.array([[1.0, 2.0, 0.0]])
+        d2 = np.array([[1.0, 2.0, z] for z in zs])
+        c, _ = oracle.count_rppi(d1, d2, [0.0, 1.0], pimax, npi, 0.0, lib=lib)
+        assert c[0].tolist() == expect.tolist(), (pimax, npi, c, expect)
+        c, _ = oracle.count_rppi(d2, d1, [0.0, 1.0], pimax, npi, 0.0, lib=lib)
+        assert c[0].tolist() == expect.tolist(), (pimax, npi, c, expect)
+
 ALL_PINS = [
     pin_golden_r_edges,
     pin_golden_r_periodic,
@@ -650,4 +684,5 @@ ALL_PINS = [
     pin_mocks_closed_forms,
     pin_mocks_symmetries,
     pin_sky_to_cartesian,
+    pin_pi_edges_inexact_width,
 ]

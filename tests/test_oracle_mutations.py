@@ -61,6 +61,8 @@ MUTATIONS = [
     ("mocks_ll_drops_y", "const double ll = (lx * lx + ly * ly) + lz * lz;",
      "const double ll = (lx * lx) + lz * lz;"),
     ("sky_distance_ignored", "x[i] = dist[i] * x[i];", "x[i] = x[i];"),
+    ("pi_edges_rounded_once", "q[p] = (double)p * dpi;", "q[p] = (double)p * pimax / (double)npi;"),
+    ("pi_top_edge_from_width", "q[npi] = pimax;", "q[npi] = (double)npi * dpi;"),
     ("theta_mean_half_angle", "return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);",
      "return asin(0.5 * c) * (180.0 / M_PI);"),
 ]
@@ -73,7 +75,9 @@ _CHILD = """
 import json, sys
 sys.path[:0] = {paths!r}
 import oracle
+from oracle_pins import ALL_PINS
 lib = oracle.load({so!r}, rebuild_if_missing=False)
+print("PINS-START", len(ALL_PINS), flush=True)
 failures = []
 for pin in ALL_PINS:
     try:
@@ -86,23 +90,44 @@ print(json.dumps(failures))
 """
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_mutation_is_caught(name, old, new, tmp_path):
-    src = open(SRC).read()
-    assert src.count(old) >= 1, f"mutation {name}: pattern not found"
-    mutated = src.replace(old, new, 1)
+def _run_pins(src_text, tmp_path):
+    """Build `src_text` as an oracle library and run every pin against it in
+    a child process.  Returns the list of failing pins, or ["<signal N>"] when
+    the child died from a signal after the pins started (a planted mistake
+    that makes the oracle index outside its arrays).  Any other abnormal exit
+    (an import error, a pin that raises something unexpected, a child that
+    never reached the pins) fails the test: it would prove nothing."""
     path = tmp_path / "mut.c"
-    path.write_text(mutated)
+    path.write_text(src_text)
     so = str(tmp_path / "libmut.so")
     oracle.build(src=str(path), out=so)
     here = os.path.dirname(os.path.abspath(__file__))
     paths = [here, os.path.dirname(here)]
     r = subprocess.run([sys.executable, "-c", _CHILD.format(paths=paths, so=so)],
                        capture_output=True, text=True, timeout=600)
-    if r.returncode != 0:
-        # the mutated oracle crashed on a pin's input: the mistake is caught
-        assert r.returncode < 0 or "Error" in r.stderr, (r.returncode, r.stderr[-2000:])
-        return
-    failures = json.loads(r.stdout.strip().splitlines()[-1])
+    lines = r.stdout.strip().splitlines()
+    started = any(line.startswith("PINS-START") for line in lines)
+    assert started, ("child never started the pins", r.returncode, r.stderr[-2000:])
+    if r.returncode < 0:
+        return [f"<signal {-r.returncode}>"]
+    assert r.returncode == 0, ("child failed outside the pins", r.returncode,
+                               r.stderr[-2000:])
+    return json.loads(lines[-1])
+
+
+@pytest.mark.slow
+def test_unmutated_oracle_passes_every_pin(tmp_path):
+    """Control: the harness run on the oracle as committed reports no failing
+    pin, so a failure reported for a mutant comes from its planted mistake."""
+    src = open(SRC).read()
+    assert _run_pins(src, tmp_path) == []
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_mutation_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation {name}: pattern not found"
+    failures = _run_pins(src.replace(old, new, 1), tmp_path)
+    print(name, "caught by", failures)
     assert failures, f"planted mistake {name} was not caught by any pin"
