@@ -83,6 +83,18 @@ def _bind(lib):
     lib.oracle_pi_edges.restype = ctypes.c_int
     lib.oracle_xsum.argtypes = [i64, dp]
     lib.oracle_xsum.restype = dbl
+    lib.oracle_count_r_pruned.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, i64, dp, dp,
+                                          dp, dp, ctypes.c_int, dp, i32, dbl, up, dp,
+                                          ctypes.c_int, ctypes.c_int]
+    lib.oracle_count_r_pruned.restype = ctypes.c_int
+    lib.oracle_count_rppi_pruned.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, i64, dp,
+                                             dp, dp, dp, ctypes.c_int, dp, i32, dbl, i32,
+                                             dbl, up, dp, ctypes.c_int, ctypes.c_int]
+    lib.oracle_count_rppi_pruned.restype = ctypes.c_int
+    lib.oracle_count_theta_uv_pruned.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, i64,
+                                                 dp, dp, dp, dp, ctypes.c_int, dp, i32,
+                                                 up, dp, ctypes.c_int, ctypes.c_int]
+    lib.oracle_count_theta_uv_pruned.restype = ctypes.c_int
     return lib
 
 
@@ -292,3 +304,86 @@ def xsum(v, lib=None) -> float:
     lib = lib or load()
     v = _f64(v)
     return float(lib.oracle_xsum(v.size, _ptr(v)))
+
+
+# --------------------------------------------------------------------------
+# Exactly pruned variants: identical results to count_r / count_rppi /
+# count_theta, visiting only pairs whose difference along one axis (with its
+# periodic images) is within the reach plus a margin.  For reference counts
+# of catalogues too large to enumerate.
+# --------------------------------------------------------------------------
+def count_r_pruned(d1, d2=None, edges=None, boxsize: float = 0.0, w1=None, w2=None,
+                   axis: int = 2, nthreads: int = 0, lib=None,
+                   weight_type: str = "product"):
+    """DD(r) counts and weighted sums, pruned along ``axis``."""
+    lib = lib or load()
+    edges = _f64(edges)
+    nb = edges.size - 1
+    x1, y1, z1 = _xyz(d1)
+    auto = d2 is None
+    x2, y2, z2 = (x1, y1, z1) if auto else _xyz(d2)
+    ww1 = None if w1 is None else _f64(w1)
+    ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
+    counts = np.zeros(nb, dtype=np.uint64)
+    wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
+    rc = lib.oracle_count_r_pruned(int(axis), x1.size, _ptr(x1), _ptr(y1), _ptr(z1),
+                                   _ptr(ww1), x2.size, _ptr(x2), _ptr(y2), _ptr(z2),
+                                   _ptr(ww2), int(auto), _ptr(edges), nb, float(boxsize),
+                                   counts.ctypes.data, _ptr(wsum), _wtype(weight_type),
+                                   int(nthreads))
+    _check(rc, "oracle_count_r_pruned")
+    return counts, wsum
+
+
+def count_rppi_pruned(d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
+                      boxsize: float = 0.0, w1=None, w2=None, axis: int = 2,
+                      nthreads: int = 0, lib=None, weight_type: str = "product"):
+    """DD(rp, pi) counts uint64[nrp, npi] (and weighted sums), pruned along
+    ``axis`` (the reach is pimax along z, the largest rp edge along x or y)."""
+    lib = lib or load()
+    rp_edges = _f64(rp_edges)
+    nb = rp_edges.size - 1
+    x1, y1, z1 = _xyz(d1)
+    auto = d2 is None
+    x2, y2, z2 = (x1, y1, z1) if auto else _xyz(d2)
+    ww1 = None if w1 is None else _f64(w1)
+    ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
+    counts = np.zeros(nb * npi, dtype=np.uint64)
+    wsum = np.zeros(nb * npi, dtype=np.float64) if w1 is not None else None
+    rc = lib.oracle_count_rppi_pruned(int(axis), x1.size, _ptr(x1), _ptr(y1), _ptr(z1),
+                                      _ptr(ww1), x2.size, _ptr(x2), _ptr(y2), _ptr(z2),
+                                      _ptr(ww2), int(auto), _ptr(rp_edges), nb,
+                                      float(pimax), int(npi), float(boxsize),
+                                      counts.ctypes.data, _ptr(wsum), _wtype(weight_type),
+                                      int(nthreads))
+    _check(rc, "oracle_count_rppi_pruned")
+    counts = counts.reshape(nb, npi)
+    if wsum is not None:
+        wsum = wsum.reshape(nb, npi)
+    return counts, wsum
+
+
+def count_theta_pruned(ra1, dec1, ra2=None, dec2=None, theta_edges_deg=None, w1=None,
+                       w2=None, axis: int = 1, nthreads: int = 0, lib=None,
+                       weight_type: str = "product"):
+    """DD(theta) / DR(theta) from RA/DEC in degrees (converted like
+    count_theta), pruned along one axis of the unit vectors."""
+    lib = lib or load()
+    te = _f64(theta_edges_deg)
+    nb = te.size - 1
+    v1 = radec_to_unit(ra1, dec1, lib=lib)
+    auto = ra2 is None
+    v2 = v1 if auto else radec_to_unit(ra2, dec2, lib=lib)
+    x1, y1, z1 = _xyz(v1)
+    x2, y2, z2 = (x1, y1, z1) if auto else _xyz(v2)
+    ww1 = None if w1 is None else _f64(w1)
+    ww2 = None if (w1 is None) else (ww1 if auto else _f64(w2))
+    counts = np.zeros(nb, dtype=np.uint64)
+    wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
+    rc = lib.oracle_count_theta_uv_pruned(int(axis), x1.size, _ptr(x1), _ptr(y1),
+                                          _ptr(z1), _ptr(ww1), x2.size, _ptr(x2),
+                                          _ptr(y2), _ptr(z2), _ptr(ww2), int(auto),
+                                          _ptr(te), nb, counts.ctypes.data, _ptr(wsum),
+                                          _wtype(weight_type), int(nthreads))
+    _check(rc, "oracle_count_theta_uv_pruned")
+    return counts, wsum

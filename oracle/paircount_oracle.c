@@ -231,12 +231,92 @@ static double pair_weight(int wtype, double a, double b)
     return wtype == 1 ? a + b : a * b;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Exactly pruned pair sets (for the full-size reference counts)             */
+/* ------------------------------------------------------------------------ */
+/* Every summand of a separation is non-negative and rounding is monotone,
+   so s = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)) >= fl(d*d) for each axis
+   difference d (likewise rp^2 >= fl(dx*dx), fl(dy*dy); and pi = |dz|).  If
+   the wrapped, rounded difference along one axis has |d| >= R, where R is
+   the largest edge (pimax for pi), then fl(d*d) >= fl(R*R) and the pair lies
+   outside every bin.  The rounded difference is within a few ulps of the
+   exact one, so a pair whose exact difference along the axis (and, in a
+   periodic box, along its images at +-L) exceeds R + margin, with the margin
+   far above those ulps, can be skipped without changing any count.  The
+   pruned variant sorts the second catalogue by that axis and visits, for
+   each i, only the j whose key lies within R + margin of the key of i or of
+   its periodic images; every visited pair goes through the unchanged
+   definition below.                                                         */
+
+/* First index of the ascending array k[0..n-1] whose value is >= v.      */
+static int64_t first_at_least(const double *k, int64_t n, double v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (k[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+/* First index whose value is > v.                                         */
+static int64_t first_above(const double *k, int64_t n, double v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (k[mid] <= v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+/* The ranges of j visited for row i.  key2 == NULL: every j (j > i for an
+   autocorrelation), the plain definition.  Otherwise key2 (ascending) holds
+   the pruning axis of the second catalogue and ki that of point i; the
+   ranges cover every j with |key2[j] - ki| <= reach and, in a periodic box
+   of side L > 2 reach (so the three ranges are disjoint), with
+   |key2[j] - ki -+ L| <= reach.  Returns the number of ranges (<= 3).      */
+static int j_ranges(int64_t i, int autocorr, int64_t n2, const double *key2,
+                    double ki, double reach, double L, int64_t *lo,
+                    int64_t *hi)
+{
+    const int64_t jmin = autocorr ? i + 1 : 0;
+    if (key2 == NULL) {
+        lo[0] = jmin;
+        hi[0] = n2;
+        return 1;
+    }
+    int nr = 0;
+    const double shift[3] = {0.0, L, -L};
+    const int nimg = L > 0.0 ? 3 : 1;
+    for (int m = 0; m < nimg; m++) {
+        int64_t a = first_at_least(key2, n2, (ki + shift[m]) - reach);
+        const int64_t b = first_above(key2, n2, (ki + shift[m]) + reach);
+        if (a < jmin)
+            a = jmin;
+        if (a < b) {
+            lo[nr] = a;
+            hi[nr] = b;
+            nr++;
+        }
+    }
+    return nr;
+}
+
 /* One engine for the 1-D (r or chord) and the 2-D (rp, pi) statistics.
    mode 0: s = (dx*dx + dy*dy) + dz*dz, bins k over E
    mode 1: s = dx*dx + dy*dy, pi = |dz|, bins k*npi + p over E x q
    mode 2: s = rp^2 and pi of the on-sky convention, bins as mode 1
    wtype: pair weight (0 product, 1 sum); ravg (optional): mean separation
-   per bin, angle != 0 reporting angles from squared chords.                */
+   per bin, angle != 0 reporting angles from squared chords.
+   key2 (optional): the exactly pruned pair set of j_ranges, with key1 and
+   key2 the pruning axis of the first and (ascending) second catalogue.      */
 static int count_engine(int mode,
                         int64_t n1, const double *x1, const double *y1,
                         const double *z1, const double *w1,
@@ -245,7 +325,8 @@ static int count_engine(int mode,
                         int autocorr, const double *edges, int32_t nbins,
                         const double *q, int32_t npi, double boxsize,
                         uint64_t *counts, double *wsum, int wtype, int angle,
-                        double *ravg, int nthreads)
+                        double *ravg, int nthreads, const double *key1,
+                        const double *key2, double reach)
 {
     int rc = check_edges(edges, nbins);
     if (rc)
@@ -258,6 +339,7 @@ static int count_engine(int mode,
         y2 = y1;
         z2 = z1;
         w2 = w1;
+        key2 = key1;
     } else if (n2 < 0) {
         return ORACLE_EINVAL;
     }
@@ -312,60 +394,64 @@ static int count_engine(int mode,
             if (!ok)
                 continue;
             const double xi = x1[i], yi = y1[i], zi = z1[i];
-            const int64_t j0 = autocorr ? i + 1 : 0;
-            for (int64_t j = j0; j < n2; j++) {
-                double dx = xi - x2[j];
-                double dy = yi - y2[j];
-                double dz = zi - z2[j];
-                if (periodic) {
-                    dx = wrap_axis(dx, L, half);
-                    dy = wrap_axis(dy, L, half);
-                    dz = wrap_axis(dz, L, half);
-                }
-                int bin;
-                double s;
-                if (mode == 0) {
-                    s = (dx * dx + dy * dy) + dz * dz;
-                    if (s < E[0] || s >= E[nbins])
-                        continue;
-                    int k = nbins - 1; /* reverse scan over the bins */
-                    while (s < E[k])
-                        k--;
-                    bin = k;
-                } else {
-                    double pi;
-                    if (mode == 1) {
-                        s = dx * dx + dy * dy;
-                        pi = fabs(dz);
-                    } else {
-                        const double lx = xi + x2[j], ly = yi + y2[j], lz = zi + z2[j];
-                        const double sl = (dx * lx + dy * ly) + dz * lz;
-                        const double ll = (lx * lx + ly * ly) + lz * lz;
-                        const double ss = (dx * dx + dy * dy) + dz * dz;
-                        pi = ll > 0.0 ? fabs(sl) / sqrt(ll) : 0.0;
-                        s = fmax(ss - pi * pi, 0.0);
+            int64_t rlo[3], rhi[3];
+            const int nr = j_ranges(i, autocorr, n2, key2, key2 ? key1[i] : 0.0,
+                                    reach, L, rlo, rhi);
+            for (int r = 0; r < nr; r++) {
+                for (int64_t j = rlo[r]; j < rhi[r]; j++) {
+                    double dx = xi - x2[j];
+                    double dy = yi - y2[j];
+                    double dz = zi - z2[j];
+                    if (periodic) {
+                        dx = wrap_axis(dx, L, half);
+                        dy = wrap_axis(dy, L, half);
+                        dz = wrap_axis(dz, L, half);
                     }
-                    if (s < E[0] || s >= E[nbins] || pi >= pimax)
-                        continue;
-                    int k = nbins - 1;
-                    while (s < E[k])
-                        k--;
-                    int p = npi - 1;
-                    while (pi < q[p])
-                        p--;
-                    bin = k * npi + p;
-                }
-                c[bin]++;
-                double prod = 1.0;
-                if (weighted) {
-                    prod = pair_weight(wtype, w1[i], w2[j]);
-                    /* autocorrelation: the unique pair stands for (i,j) and
-                       (j,i); doubling is exact in binary64 */
-                    xacc_add(&acc[bin], autocorr ? 2.0 * prod : prod);
-                }
-                if (want_r) {
-                    const double rw = separation_value(angle, s) * prod;
-                    xacc_add(&racc[bin], autocorr ? 2.0 * rw : rw);
+                    int bin;
+                    double s;
+                    if (mode == 0) {
+                        s = (dx * dx + dy * dy) + dz * dz;
+                        if (s < E[0] || s >= E[nbins])
+                            continue;
+                        int k = nbins - 1; /* reverse scan over the bins */
+                        while (s < E[k])
+                            k--;
+                        bin = k;
+                    } else {
+                        double pi;
+                        if (mode == 1) {
+                            s = dx * dx + dy * dy;
+                            pi = fabs(dz);
+                        } else {
+                            const double lx = xi + x2[j], ly = yi + y2[j], lz = zi + z2[j];
+                            const double sl = (dx * lx + dy * ly) + dz * lz;
+                            const double ll = (lx * lx + ly * ly) + lz * lz;
+                            const double ss = (dx * dx + dy * dy) + dz * dz;
+                            pi = ll > 0.0 ? fabs(sl) / sqrt(ll) : 0.0;
+                            s = fmax(ss - pi * pi, 0.0);
+                        }
+                        if (s < E[0] || s >= E[nbins] || pi >= pimax)
+                            continue;
+                        int k = nbins - 1;
+                        while (s < E[k])
+                            k--;
+                        int p = npi - 1;
+                        while (pi < q[p])
+                            p--;
+                        bin = k * npi + p;
+                    }
+                    c[bin]++;
+                    double prod = 1.0;
+                    if (weighted) {
+                        prod = pair_weight(wtype, w1[i], w2[j]);
+                        /* autocorrelation: the unique pair stands for (i,j) and
+                           (j,i); doubling is exact in binary64 */
+                        xacc_add(&acc[bin], autocorr ? 2.0 * prod : prod);
+                    }
+                    if (want_r) {
+                        const double rw = separation_value(angle, s) * prod;
+                        xacc_add(&racc[bin], autocorr ? 2.0 * rw : rw);
+                    }
                 }
             }
         }
@@ -444,7 +530,7 @@ int oracle_count_r_ex(int64_t n1, const double *x1, const double *y1,
 {
     return count_engine(0, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
                         edges, nbins, NULL, 0, boxsize, counts, wsum, wtype,
-                        0, ravg, nthreads);
+                        0, ravg, nthreads, NULL, NULL, 0.0);
 }
 
 int oracle_count_r(int64_t n1, const double *x1, const double *y1,
@@ -480,7 +566,7 @@ int oracle_count_rppi_ex(int64_t n1, const double *x1, const double *y1,
     if (rc == ORACLE_OK)
         rc = count_engine(1, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2,
                           autocorr, rp_edges, nrp, q, npi, boxsize, counts,
-                          wsum, wtype, 0, ravg, nthreads);
+                          wsum, wtype, 0, ravg, nthreads, NULL, NULL, 0.0);
     free(q);
     return rc;
 }
@@ -519,7 +605,7 @@ int oracle_count_rppi_mocks(int64_t n1, const double *x1, const double *y1,
     if (rc == ORACLE_OK)
         rc = count_engine(2, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2,
                           autocorr, rp_edges, nrp, q, npi, 0.0, counts,
-                          wsum, wtype, 0, ravg, nthreads);
+                          wsum, wtype, 0, ravg, nthreads, NULL, NULL, 0.0);
     free(q);
     return rc;
 }
@@ -601,7 +687,7 @@ int oracle_count_theta_ex(int64_t n1, const double *ra1, const double *dec1,
             rc = count_engine(0, n1, v1, v1 + n1, v1 + 2 * n1, w1, n2, v2,
                               v2 + n2, v2 + 2 * n2, w2, autocorr, c, nbins,
                               NULL, 0, 0.0, counts, wsum, wtype, 1, ravg,
-                              nthreads);
+                              nthreads, NULL, NULL, 0.0);
     }
     free(v1);
     free(v2);
@@ -618,4 +704,175 @@ int oracle_count_theta(int64_t n1, const double *ra1, const double *dec1,
     return oracle_count_theta_ex(n1, ra1, dec1, w1, n2, ra2, dec2, w2,
                                  autocorr, theta_edges_deg, nbins, counts,
                                  wsum, 0, NULL, nthreads);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exactly pruned variants (see j_ranges): the same counts and exactly      */
+/* rounded sums as the plain functions, for inputs too large to enumerate.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double key;
+    int64_t idx;
+} keyed;
+
+static int keyed_cmp(const void *a, const void *b)
+{
+    const keyed *p = (const keyed *)a, *q = (const keyed *)b;
+    if (p->key < q->key)
+        return -1;
+    if (p->key > q->key)
+        return 1;
+    return (p->idx > q->idx) - (p->idx < q->idx);
+}
+
+/* A copy of a catalogue sorted by coordinate `axis`: columns x, y, z, w
+   (w may be NULL) and the key column.  Returns NULL on allocation failure;
+   the single block is released with free().                               */
+static double *sorted_copy(int64_t n, const double *x, const double *y,
+                           const double *z, const double *w, int axis,
+                           double **sx, double **sy, double **sz, double **sw,
+                           double **sk)
+{
+    const double *cols[3] = {x, y, z};
+    keyed *order = (keyed *)malloc(sizeof(keyed) * (size_t)(n + 1));
+    double *blk = (double *)malloc(sizeof(double) * 5 * (size_t)(n + 1));
+    if (!order || !blk) {
+        free(order);
+        free(blk);
+        return NULL;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        order[i].key = cols[axis][i];
+        order[i].idx = i;
+    }
+    qsort(order, (size_t)n, sizeof(keyed), keyed_cmp);
+    *sx = blk;
+    *sy = blk + n;
+    *sz = blk + 2 * n;
+    *sw = w ? blk + 3 * n : NULL;
+    *sk = blk + 4 * n;
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t o = order[i].idx;
+        (*sx)[i] = x[o];
+        (*sy)[i] = y[o];
+        (*sz)[i] = z[o];
+        if (w)
+            (*sw)[i] = w[o];
+        (*sk)[i] = order[i].key;
+    }
+    free(order);
+    return blk;
+}
+
+/* Largest magnitude of a column (the scale of its rounding errors).       */
+static double max_abs(int64_t n, const double *v)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; i++)
+        if (fabs(v[i]) > m)
+            m = fabs(v[i]);
+    return m;
+}
+
+/* Pruned DD(r) (mode 0) or DD(rp, pi) (mode 1) along axis 0, 1 or 2: the
+   reach is the largest edge, or pimax for the line of sight of mode 1.  The
+   margin 1e-9 (L, or the coordinate scale without a box) exceeds the error
+   of a rounded axis difference by orders of magnitude.  A periodic box must
+   exceed 2.5 times the reach with its margin, so that the three key ranges
+   of j_ranges are disjoint with room to spare.                             */
+static int count_pruned(int mode, int axis, int64_t n1, const double *x1,
+                        const double *y1, const double *z1, const double *w1,
+                        int64_t n2, const double *x2, const double *y2,
+                        const double *z2, const double *w2, int autocorr,
+                        const double *edges, int32_t nbins, const double *q,
+                        int32_t npi, double boxsize, uint64_t *counts,
+                        double *wsum, int wtype, int angle, int nthreads)
+{
+    if (axis < 0 || axis > 2 || n1 < 0 || (!autocorr && n2 < 0))
+        return ORACLE_EINVAL;
+    int rc = check_edges(edges, nbins);
+    if (rc)
+        return rc;
+    const double *c1[3] = {x1, y1, z1}, *c2[3] = {x2, y2, z2};
+    const double R = (mode == 1 && axis == 2) ? q[npi] : edges[nbins];
+    double scale = boxsize > 0.0 ? boxsize : max_abs(n1, c1[axis]);
+    if (!autocorr && boxsize <= 0.0 && max_abs(n2, c2[axis]) > scale)
+        scale = max_abs(n2, c2[axis]);
+    const double reach = R + 1e-9 * (scale + R);
+    if (boxsize > 0.0 && !(boxsize > 2.5 * reach))
+        return ORACLE_EINVAL;
+    double *bx, *by, *bz, *bw, *bk;
+    double *blk = sorted_copy(autocorr ? n1 : n2, autocorr ? x1 : x2, autocorr ? y1 : y2,
+                              autocorr ? z1 : z2, autocorr ? w1 : w2, axis, &bx, &by,
+                              &bz, &bw, &bk);
+    if (!blk)
+        return ORACLE_ENOMEM;
+    if (autocorr)
+        rc = count_engine(mode, n1, bx, by, bz, bw, n1, bx, by, bz, bw, 1, edges,
+                          nbins, q, npi, boxsize, counts, wsum, wtype, angle, NULL,
+                          nthreads, bk, bk, reach);
+    else /* the first catalogue keeps its order; its keys are its own column */
+        rc = count_engine(mode, n1, x1, y1, z1, w1, n2, bx, by, bz, bw, 0, edges,
+                          nbins, q, npi, boxsize, counts, wsum, wtype, angle, NULL,
+                          nthreads, c1[axis], bk, reach);
+    free(blk);
+    return rc;
+}
+
+int oracle_count_r_pruned(int axis, int64_t n1, const double *x1, const double *y1,
+                          const double *z1, const double *w1, int64_t n2,
+                          const double *x2, const double *y2, const double *z2,
+                          const double *w2, int autocorr, const double *edges,
+                          int32_t nbins, double boxsize, uint64_t *counts,
+                          double *wsum, int wtype, int nthreads)
+{
+    return count_pruned(0, axis, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
+                        edges, nbins, NULL, 0, boxsize, counts, wsum, wtype, 0,
+                        nthreads);
+}
+
+int oracle_count_rppi_pruned(int axis, int64_t n1, const double *x1,
+                             const double *y1, const double *z1, const double *w1,
+                             int64_t n2, const double *x2, const double *y2,
+                             const double *z2, const double *w2, int autocorr,
+                             const double *rp_edges, int32_t nrp, double pimax,
+                             int32_t npi, double boxsize, uint64_t *counts,
+                             double *wsum, int wtype, int nthreads)
+{
+    if (npi < 1)
+        return ORACLE_EINVAL;
+    double *q = (double *)malloc(sizeof(double) * (size_t)(npi + 1));
+    if (!q)
+        return ORACLE_ENOMEM;
+    int rc = oracle_pi_edges(pimax, npi, q);
+    if (rc == ORACLE_OK)
+        rc = count_pruned(1, axis, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
+                          rp_edges, nrp, q, npi, boxsize, counts, wsum, wtype, 0,
+                          nthreads);
+    free(q);
+    return rc;
+}
+
+/* Pruned DD(theta) / DR(theta) of unit vectors (from oracle_radec_to_unit)
+   and theta edges in degrees, along one axis of the unit vectors.         */
+int oracle_count_theta_uv_pruned(int axis, int64_t n1, const double *x1,
+                                 const double *y1, const double *z1,
+                                 const double *w1, int64_t n2, const double *x2,
+                                 const double *y2, const double *z2,
+                                 const double *w2, int autocorr,
+                                 const double *theta_edges_deg, int32_t nbins,
+                                 uint64_t *counts, double *wsum, int wtype,
+                                 int nthreads)
+{
+    if (nbins < 1)
+        return ORACLE_EINVAL;
+    double *c = (double *)malloc(sizeof(double) * (size_t)(nbins + 1));
+    if (!c)
+        return ORACLE_ENOMEM;
+    int rc = oracle_theta_chord_edges(nbins + 1, theta_edges_deg, c);
+    if (rc == ORACLE_OK)
+        rc = count_pruned(0, axis, n1, x1, y1, z1, w1, n2, x2, y2, z2, w2, autocorr,
+                          c, nbins, NULL, 0, 0.0, counts, wsum, wtype, 1, nthreads);
+    free(c);
+    return rc;
 }

@@ -658,6 +658,51 @@ def pin_pi_edges_inexact_width(lib):
         c, _ = oracle.count_rppi(d2, d1, [0.0, 1.0], pimax, npi, 0.0, lib=lib)
         assert c[0].tolist() == expect.tolist(), (pimax, npi, c, expect)
 
+def pin_pruned_equals_plain(lib):
+    """The exactly pruned variants (one axis sorted, pairs beyond the reach
+    along it skipped) give the plain oracle's counts and exactly rounded
+    weighted sums bit for bit: periodic and open boxes, auto and cross,
+    float32-valued inputs, lattice inputs with exact edge ties, every
+    pruning axis, DD(rp, pi) with its pi reach along z, and DD(theta)."""
+    pts = synth.clustered_box(2500, 60.0, seed=121, nblobs=40, sigma=1.5)
+    w = synth.uniform_weights(2500, seed=122)
+    e = synth.log_edges(0.2, 20.0, 9)
+    for box in (60.0, 0.0):
+        want = oracle.count_r(pts, None, e, box, w1=w, lib=lib)
+        for ax in range(3):
+            got = oracle.count_r_pruned(pts, None, e, box, w1=w, axis=ax, lib=lib)
+            assert (got[0] == want[0]).all(), (box, ax, got[0], want[0])
+            assert got[1].tolist() == want[1].tolist(), (box, ax)
+        a, b = pts[:900], pts[900:]
+        want = oracle.count_rppi(a, b, e, 14.0, 7, box, w1=w[:900], w2=w[900:], lib=lib)
+        for ax in range(3):
+            got = oracle.count_rppi_pruned(a, b, e, 14.0, 7, box, w1=w[:900], w2=w[900:],
+                                           axis=ax, lib=lib)
+            assert (got[0] == want[0]).all(), (box, ax)
+            assert got[1].tolist() == want[1].tolist(), (box, ax)
+    f32 = pts.astype(np.float32)
+    assert (oracle.count_r_pruned(f32, None, e, 60.0, lib=lib)[0]
+            == oracle.count_r(f32, None, e, 60.0, lib=lib)[0]).all()
+    lat = synth.lattice_box(1500, 32, seed=123)
+    el = [0.0, 1.0, 2.0, 3.0, 5.0, 8.0]
+    for ax in range(3):
+        assert (oracle.count_r_pruned(lat, None, el, 32.0, axis=ax, lib=lib)[0]
+                == oracle.count_r(lat, None, el, 32.0, lib=lib)[0]).all()
+        assert (oracle.count_rppi_pruned(lat, None, el, 4.0, 4, 32.0, axis=ax, lib=lib)[0]
+                == oracle.count_rppi(lat, None, el, 4.0, 4, 32.0, lib=lib)[0]).all()
+    ra, dec = synth.cap_radec(1500, seed=124, radius_deg=20.0, clustered=True,
+                              nblobs=30, sigma_deg=0.5)
+    ra2, dec2 = synth.cap_radec(700, seed=125, radius_deg=20.0)
+    te = synth.log_edges(0.05, 8.0, 8)
+    want = oracle.count_theta(ra, dec, None, None, te, lib=lib)[0]
+    wantx = oracle.count_theta(ra, dec, ra2, dec2, te, lib=lib)[0]
+    for ax in range(3):
+        assert (oracle.count_theta_pruned(ra, dec, None, None, te, axis=ax, lib=lib)[0]
+                == want).all(), ax
+        assert (oracle.count_theta_pruned(ra, dec, ra2, dec2, te, axis=ax, lib=lib)[0]
+                == wantx).all(), ax
+
+
 ALL_PINS = [
     pin_golden_r_edges,
     pin_golden_r_periodic,
@@ -685,4 +730,5 @@ ALL_PINS = [
     pin_mocks_symmetries,
     pin_sky_to_cartesian,
     pin_pi_edges_inexact_width,
+    pin_pruned_equals_plain,
 ]

@@ -16,22 +16,22 @@ MUTATIONS = [
     ("dropped_z_term", "s = (dx * dx + dy * dy) + dz * dz;", "s = (dx * dx + dy * dy);"),
     ("wrong_sign_dy", "double dy = yi - y2[j];", "double dy = yi + y2[j];"),
     ("wrong_array_z", "double dz = zi - z2[j];", "double dz = zi - y2[j];"),
-    ("bottom_edge_exclusive", "if (s < E[0] || s >= E[nbins])\n                        continue;\n                    int k",
-     "if (s <= E[0] || s >= E[nbins])\n                        continue;\n                    int k"),
+    ("bottom_edge_exclusive", "if (s < E[0] || s >= E[nbins])\n                            continue;\n                        int k",
+     "if (s <= E[0] || s >= E[nbins])\n                            continue;\n                        int k"),
     ("wrap_positive_side_missing", "if (d > half)", "if (d > L)"),
     ("wrap_wrong_direction", "d -= L;", "d += L;"),
-    ("edge_inclusive_upper", "while (s < E[k])\n                        k--;\n                    bin = k;",
-     "while (s <= E[k] && k > 0)\n                        k--;\n                    bin = k;"),
-    ("top_edge_inclusive", "if (s < E[0] || s >= E[nbins])\n                        continue;\n                    int k",
-     "if (s < E[0] || s > E[nbins])\n                        continue;\n                    int k"),
+    ("edge_inclusive_upper", "while (s < E[k])\n                            k--;\n                        bin = k;",
+     "while (s <= E[k] && k > 0)\n                            k--;\n                        bin = k;"),
+    ("top_edge_inclusive", "if (s < E[0] || s >= E[nbins])\n                            continue;\n                        int k",
+     "if (s < E[0] || s > E[nbins])\n                            continue;\n                        int k"),
     ("unsquared_edges", "E[k] = edges[k] * edges[k];", "E[k] = edges[k];"),
     ("no_self_pairs", "counts[0] += (uint64_t)n1;", ""),
     ("no_doubling", "counts[b] *= 2u;", ""),
     ("auto_includes_diagonal", "autocorr ? i + 1 : 0", "autocorr ? i : 0"),
     ("pi_cut_inclusive", "pi >= pimax", "pi > pimax"),
     ("pi_bin_off_by_one", "while (pi < q[p])", "while (pi <= q[p] && p > 0)"),
-    ("rp_uses_dz", "s = dx * dx + dy * dy;\n                        pi = fabs(dz);",
-     "s = dx * dx + dz * dz;\n                        pi = fabs(dz);"),
+    ("rp_uses_dz", "s = dx * dx + dy * dy;\n                            pi = fabs(dz);",
+     "s = dx * dx + dz * dz;\n                            pi = fabs(dz);"),
     ("chord_not_halved", "2.0 * sin(0.5 * (theta_deg[k] * d2r))", "2.0 * sin(theta_deg[k] * d2r)"),
     ("radec_swapped_trig", "x[i] = cd * cos(a);", "x[i] = cd * sin(a);"),
     ("xsum_no_compensation", "double lo = y - (hi - x);", "double lo = 0.0 * (y - (hi - x));"),
@@ -63,6 +63,11 @@ MUTATIONS = [
     ("sky_distance_ignored", "x[i] = dist[i] * x[i];", "x[i] = x[i];"),
     ("pi_edges_rounded_once", "q[p] = (double)p * dpi;", "q[p] = (double)p * pimax / (double)npi;"),
     ("pi_top_edge_from_width", "q[npi] = pimax;", "q[npi] = (double)npi * dpi;"),
+    ("prune_no_periodic_images", "const int nimg = L > 0.0 ? 3 : 1;", "const int nimg = 1;"),
+    ("prune_half_reach", "(ki + shift[m]) + reach)", "(ki + shift[m]) + 0.5 * reach)"),
+    ("prune_pi_reach_on_every_axis", "(mode == 1 && axis == 2) ? q[npi]", "(mode == 1) ? q[npi]"),
+    ("prune_key_of_wrong_axis", "order[i].key = cols[axis][i];",
+     "order[i].key = cols[(axis + 1) % 3][i];"),
     ("theta_mean_half_angle", "return (2.0 * asin(0.5 * c)) * (180.0 / M_PI);",
      "return asin(0.5 * c) * (180.0 / M_PI);"),
 ]
