@@ -148,16 +148,27 @@ typedef struct cf_options {
                                    transverse distance when the reach is a
                                    ball.  Lowered when a periodic box has fewer
                                    than 2k+1 columns.                           */
-    int32_t radec_on_host;      /* RA/DEC (and distance) input: 1 converts to
-                                   unit vectors (positions) on the host with
-                                   the C library's sin and cos, the same
-                                   formula and library as a host reference, so
-                                   counts are reproducible against it bit for
-                                   bit; 0 (default) converts on the device,
-                                   whose math library may differ in the last
-                                   bit.  Device-resident input is copied to the
-                                   host first.                                 */
-    int32_t reserved[3];
+    int32_t radec_on_device;    /* RA/DEC (and distance) input: 0 (default)
+                                   converts to unit vectors (positions) on the
+                                   host with the C library's sin and cos, in
+                                   parallel threads, the formula and library
+                                   of a host reference, so counts are
+                                   reproducible against it bit for bit
+                                   (device-resident input is copied to the
+                                   host and back); 1 converts on the device, a
+                                   faster mode whose math library may differ
+                                   from the host's in the last bit of a
+                                   vector, which can move a pair lying within
+                                   an ulp of an edge into the next bin.       */
+    int32_t flush_pairs;        /* > 0: merge a wave's LDS histogram replicas
+                                   into the global bins whenever its pending
+                                   pair evaluations would exceed this many (at
+                                   most the default, which keeps the uint32
+                                   LDS counters from wrapping); a test hook
+                                   for the overflow guard of section "Finding
+                                   and updating the histogram bins".  0: the
+                                   default bound.                              */
+    int32_t reserved[2];
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
                                    in each bin (r, rp, or theta in degrees),
@@ -197,6 +208,8 @@ typedef struct cf_stats {
     int32_t angular_grid;       /* angular grid refinement used (0: 3-D cells) */
     int32_t xy_refine;          /* x/y refinement of a 3-D grid (0: angular)   */
     int32_t reserved_s;
+    uint64_t flushes;           /* mid-sweep merges of LDS histogram replicas
+                                   forced by the overflow bound (flush_pairs)  */
 } cf_stats;
 
 typedef struct cf_ctx cf_ctx;
@@ -272,8 +285,9 @@ cf_status count_pairs_rppi_batch_ex(cf_ctx *ctx, const cf_catalog *cats, int32_t
    (Appendix A, spherical volumes) binned through the squared chord of unit
    vectors, |v1 - v2|^2 = 2 - 2 cos(theta), a monotone function of theta.
    Unit vectors v = (cos d cos a, cos d sin a, sin d) with a, d = RA, DEC in
-   radians (degrees * fl(pi/180)) are formed on the device; chord edges
-   c_k = 2 sin(theta_k / 2) on the host.  theta edges in degrees, at most 180.
+   radians (degrees * fl(pi/180)) are formed on the host (on the device with
+   cf_options.radec_on_device); chord edges c_k = 2 sin(theta_k / 2) on the
+   host.  theta edges in degrees, at most 180.
    Never periodic.  counts[nbins], wsum[nbins]. */
 cf_status count_pairs_theta(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
                             const double *theta_edges_deg, int32_t nbins,

@@ -62,8 +62,8 @@ class cf_options(ctypes.Structure):
                 ("collect_timing", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("weight_type", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
-                ("xy_refine", ctypes.c_int32), ("radec_on_host", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3),
+                ("xy_refine", ctypes.c_int32), ("radec_on_device", ctypes.c_int32),
+                ("flush_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
                 ("ravg", ctypes.c_void_p)]
 
 
@@ -79,7 +79,8 @@ class cf_stats(ctypes.Structure):
                 ("t_total_ms", ctypes.c_float),
                 ("slices_per_reach", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("replayed", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
-                ("xy_refine", ctypes.c_int32), ("reserved_s", ctypes.c_int32)]
+                ("xy_refine", ctypes.c_int32), ("reserved_s", ctypes.c_int32),
+                ("flushes", ctypes.c_uint64)]
 
 
 class cf_grid_plan(ctypes.Structure):
@@ -148,7 +149,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("count_pairs_r", "count_pairs_r_ex"):
         f = getattr(lib, name)
         f.argtypes = [vp, cat, cat, vp, i32, dbl, ctypes.c_int, vp, vp] + (
-            [ctypes.POINTER(cf_options)] if name.endswith("_ex") else [])
+            [] if name == "count_pairs_r" else [ctypes.POINTER(cf_options)])
         f.restype = ctypes.c_int
     for name in ("count_pairs_rppi", "count_pairs_rppi_ex"):
         f = getattr(lib, name)

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/paircount.h"
@@ -42,6 +43,7 @@ enum {
     M_RQCOUNT = 16,     // unsigned
     M_CAND = 32,        // u64
     M_SIZES = 40,       // 2 int32: work items, blocks (copied by the finalize kernel)
+    M_FLUSH = 48,       // unsigned: mid-sweep histogram flushes
     M_OUT6 = 64,        // 6 doubles
     M_SIZE = 256
 };
@@ -290,7 +292,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // RA/DEC (and distance) of one catalogue to unit vectors (positions) on the
 // host with the C library's sin and cos: v = (cos d cos a, cos d sin a, sin d)
 // with a, d in radians (degrees times pi/180), times the distance for on-sky
-// pairs.  The vectors go to vx, vy, vz on the device.
+// pairs, split over host threads.  The vectors go to vx, vy, vz on the
+// device.
 cf_status radec_on_host(cf_ctx *c, const cf_catalog &cat, bool sky, double *vx, double *vy,
                         double *vz)
 {
@@ -319,24 +322,48 @@ cf_status radec_on_host(cf_ctx *c, const cf_catalog &cat, bool sky, double *vx, 
         (sky && (st = fetch(cat.z, cat.dtype, in.data() + 2 * n))))
         return st;
     const double d2r = M_PI / 180.0;
-    for (size_t i = 0; i < n; i++) {
-        const double a = in[i], d = in[n + i];
-        if (!(a >= 0.0 && a <= 360.0 && d >= -90.0 && d <= 90.0))
-            return fail(c, CF_ERANGE, "RA must lie in [0, 360] and DEC in [-90, 90]");
-        const double ar = a * d2r, dr = d * d2r;
-        const double cd = cos(dr);
-        double ux = cd * cos(ar), uy = cd * sin(ar), uz = sin(dr);
-        if (sky) {
-            const double D = in[2 * n + i];
-            if (!(D >= 0.0) || !std::isfinite(D))
-                return fail(c, CF_EINVAL, "distances must be finite and non-negative");
-            ux = D * ux;
-            uy = D * uy;
-            uz = D * uz;
+    // bad[0]: RA/DEC out of range, bad[1]: bad distance (per thread slice)
+    auto convert = [&](size_t i0, size_t i1, int *bad) {
+        for (size_t i = i0; i < i1; i++) {
+            const double a = in[i], d = in[n + i];
+            if (!(a >= 0.0 && a <= 360.0 && d >= -90.0 && d <= 90.0)) {
+                bad[0] = 1;
+                return;
+            }
+            const double ar = a * d2r, dr = d * d2r;
+            const double cd = cos(dr);
+            double ux = cd * cos(ar), uy = cd * sin(ar), uz = sin(dr);
+            if (sky) {
+                const double D = in[2 * n + i];
+                if (!(D >= 0.0) || !std::isfinite(D)) {
+                    bad[1] = 1;
+                    return;
+                }
+                ux = D * ux;
+                uy = D * uy;
+                uz = D * uz;
+            }
+            out[i] = ux;
+            out[n + i] = uy;
+            out[2 * n + i] = uz;
         }
-        out[i] = ux;
-        out[n + i] = uy;
-        out[2 * n + i] = uz;
+    };
+    // the conversion is independent per point: split it over host threads
+    // (at most 16, at least 64 Ki points each)
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nthr = std::max<size_t>(1, std::min<size_t>({(size_t)hw, 16, n / 65536}));
+    std::vector<int> bad(2 * nthr, 0);
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nthr; t++)
+        pool.emplace_back(convert, n * t / nthr, n * (t + 1) / nthr, &bad[2 * t]);
+    convert(0, n / nthr, &bad[0]);
+    for (auto &th : pool)
+        th.join();
+    for (size_t t = 0; t < nthr; t++) {
+        if (bad[2 * t])
+            return fail(c, CF_ERANGE, "RA must lie in [0, 360] and DEC in [-90, 90]");
+        if (bad[2 * t + 1])
+            return fail(c, CF_EINVAL, "distances must be finite and non-negative");
     }
     HIPCHK(hipMemcpyAsync(vx, out.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(vy, out.data() + n, sizeof(double) * n, hipMemcpyHostToDevice,
@@ -619,6 +646,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (opt.angular_grid < 0)
         opt.angular_grid = 0;
     const bool sky_grid = theta && opt.angular_grid > 0;
+    if (opt.flush_pairs < 0)
+        return fail(c, CF_EINVAL, "flush_pairs must be >= 0");
     if (opt.xy_refine < 0 || opt.xy_refine > PC_MAX_XYK)
         return fail(c, CF_EINVAL, "xy_refine must be in [0, %d]", PC_MAX_XYK);
     if (opt.xy_refine == 0)
@@ -709,10 +738,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     unsigned *flags = (unsigned *)(misc(c) + M_FLAGS);
     const bool radec = (theta || sky) && !unit_vec;
     SideData s1, s2;
-    if ((st2 = stage_side(c, d1, ncat, radec, sky, 0, s1, flags, opt.radec_on_host != 0)))
+    if ((st2 = stage_side(c, d1, ncat, radec, sky, 0, s1, flags, opt.radec_on_device == 0)))
         return st2;
     if (!autocorr &&
-        (st2 = stage_side(c, d2, 1, radec, sky, 1, s2, flags, opt.radec_on_host != 0)))
+        (st2 = stage_side(c, d2, 1, radec, sky, 1, s2, flags, opt.radec_on_device == 0)))
         return st2;
     if ((st2 = ensure(c, B_CATS1, sizeof(pc_cat) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CATS2, sizeof(pc_cat))))
@@ -1009,6 +1038,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.wtype = opt.weight_type;
     a.sep_scale = 1.0 / g.fscale;
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
+    a.flush_count = (unsigned *)(misc(c) + M_FLUSH);
     a.nbt = (int32_t)nbt;
     a.slots = (int32_t)((nb + 2) * hb.hdr.row_w);
     a.priv = priv ? 1 : 0;
@@ -1032,6 +1062,11 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     while (copies > 1 && copies * a.rep_stride > PC_MAX_HIST_WAVE)
         copies /= 2;
     const int waves = pc::sweep_waves();
+    // private replicas take up to 2^31 adds per slot; shared ones are bounded
+    // by the sum of the waves' pending counts
+    a.flush_at = priv ? 0x7fffffffull : 0x7fffffffull / (unsigned)waves;
+    if (opt.flush_pairs > 0)
+        a.flush_at = std::min<unsigned long long>(a.flush_at, (unsigned long long)opt.flush_pairs);
     const int slot_bytes = 4 + (weighted ? 8 : 0) + (want_ravg ? 8 : 0);
     while (priv && copies > 1 && waves * copies * a.rep_stride * slot_bytes > 28 * 1024)
         copies /= 2;
@@ -1173,7 +1208,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     }
     unsigned long long cnd;
     memcpy(&cnd, hm + M_CAND, 8);
+    unsigned nflush = 0;
+    memcpy(&nflush, hm + M_FLUSH, 4);
     cf_stats &S = c->stats;
+    S.flushes = nflush;
     for (int k = 0; k < 3; k++) {
         S.grid[k] = g.n[k];
         S.cell_width[k] = g.width[k];
@@ -1287,6 +1325,9 @@ cf_status replay(cf_ctx *c, uint64_t *counts, double *wsum, const cf_options &op
     memcpy(&cnd, hm + M_CAND, 8);
     c->stats.rechecks = rqn;
     c->stats.candidate_pairs = cnd;
+    unsigned nflush = 0;
+    memcpy(&nflush, hm + M_FLUSH, 4);
+    c->stats.flushes = nflush;
     return CF_OK;
 }
 

@@ -37,6 +37,11 @@ struct SweepArgs {
     int32_t wtype;         // pair weight: 0 product, 1 sum
     double sep_scale;      // float32 pass: length per float32 coordinate unit (2^-m)
     unsigned *rq_count;   // float32 pass: pairs re-evaluated in binary64
+    // a wave merges its LDS replicas into the global bins before its pending
+    // pair evaluations since the last merge would exceed flush_at (so no
+    // uint32 LDS counter can wrap); flush_count counts those merges
+    unsigned long long flush_at;
+    unsigned *flush_count;
     int32_t priv;       // per-wave private replicas, flushed per catalogue (batches)
     int32_t copies;     // LDS histogram replicas per wave (power of two; 64 = one per
                         // lane with unconditional updates, 1-D unweighted only)

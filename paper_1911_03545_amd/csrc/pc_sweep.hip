@@ -906,9 +906,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     // Pairs this wave added since its last flush.  A shared slot holds at
     // most the adds since the most recent flush by any wave, i.e. at most the
     // sum of every wave's pending count, so a per-wave bound of 2^31 / waves
-    // keeps the uint32 slots from wrapping; private slots take 2^31.
+    // keeps the uint32 slots from wrapping; private slots take 2^31.  The
+    // host passes that bound, or a smaller one (a test hook).
     unsigned long long pending = 0;
-    const unsigned long long flush_at = PRIV ? 0x7fffffffull : 0x7fffffffull / kWaves;
+    const unsigned long long flush_at = a.flush_at;
     unsigned cur_cat = 0;
 
     unsigned rechecks = 0;   // pairs this lane settled in binary64
@@ -949,6 +950,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         if (pending + work > flush_at) {
             flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
             pending = 0;
+            if (lane == 0)
+                atomicAdd(a.flush_count, 1u);
         }
         pending += work;
         const bool act = lane < ni;

@@ -205,15 +205,15 @@ def test_cap_fullsize_equals_chord_grid(pc, olib):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_radec_converted_on_host(pc, olib, prec):
-    """RA/DEC converted on the host (cf_options.radec_on_host) with the same
-    C library as the oracle: counts equal the oracle's bit for bit, for host
-    and device-resident float64 and float32 input."""
+    """RA/DEC converted on the host (the default) with the same C library as
+    the oracle: counts equal the oracle's bit for bit, for host and
+    device-resident float64 and float32 input."""
     import torch
     say("radec on host", prec)
     ra, dec = full_sky(60000, 513)
     rr, rd = synth.cap_radec(50000, seed=514, radius_deg=40.0, dec0_deg=60.0)
     te = synth.log_edges(0.02, 6.0, 12)
-    opts = {"radec_on_host": 1}
+    opts = None
     want, _ = oracle.count_theta(ra, dec, None, None, te, lib=olib)
     got, _ = pc.count_theta(ra, dec, None, None, te, prec, options=opts)
     assert (got == want).all()

@@ -185,9 +185,13 @@ def test_theta_dd_n2e6(pc, olib, cap):
                             unit_vectors=(v[idx], v))
     want, _ = oracle.count_theta(ra[idx], dec[idx], ra, dec, e, lib=olib)
     assert (got == want).all()
-    # RA/DEC input converted on the device: parity across math libraries is
-    # not pinned, so only the size of any difference is bounded and reported
+    # RA/DEC input, converted on the host by default: identical counts
     r32, _ = pc.count_theta(ra, dec, theta_edges_deg=e, precision="fp32")
+    assert (r32 == a32).all()
+    # converted on the device (opt-in): parity across math libraries is not
+    # pinned, so only the size of any difference is bounded and reported
+    r32, _ = pc.count_theta(ra, dec, theta_edges_deg=e, precision="fp32",
+                            options={"radec_on_device": 1})
     diff = np.abs(r32.astype(np.int64) - a32.astype(np.int64))
     say("theta DD device-conversion differences:", int(diff.sum()), "of", int(a32.sum()))
     assert diff.sum() <= 1e-9 * a32.sum() + 64

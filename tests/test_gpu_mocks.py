@@ -2,9 +2,11 @@
 (needs an MI355X).
 
 Exact parity uses Cartesian positions from the oracle's own sky conversion
-(host libm), so both sides start from identical binary64 positions; counts
-must then be identical and weighted sums / mean rp within 1e-12 relative.
-RA/DEC/distance input converted on the device goes through the device's
+(host libm), or RA/DEC/distance input, which the library converts on the host
+with the same formula and library by default, so both sides start from
+identical binary64 positions; counts must then be identical and weighted sums
+/ mean rp within 1e-12 relative.  RA/DEC/distance converted on the device
+(the opt-in cf_options.radec_on_device) goes through the device's
 trigonometric functions, whose last-bit agreement with the host libm is not
 pinned: there only the size of any count difference is bounded.
 """
@@ -99,24 +101,29 @@ def test_mocks_edge_cases(pc, olib):
         rel_ok(gr, wr)
 
 
-def test_mocks_device_conversion(pc, olib):
-    """RA, DEC, distance converted on the device: counts may differ from the
-    host conversion only through last-bit trigonometric differences."""
-    say("mocks device conversion")
+def test_mocks_default_and_device_conversion(pc, olib):
+    """RA, DEC, distance input: the default host conversion gives the
+    counts of the oracle's own conversion bit for bit (float64 and float32
+    columns); the opt-in device conversion may differ only through last-bit
+    trigonometric differences, whose count is reported and bounded."""
+    say("mocks default and device conversion")
     m = synth.sky_mock(20000, seed=405, radius_deg=5.0, dmin=600.0, dmax=900.0)
     e = synth.log_edges(0.5, 25.0, 10)
-    dev, _ = pc.count_rppi_mocks(m, None, e, 30.0, 15, "fp64")
     host, _ = pc.count_rppi_mocks(cart(m, olib), None, e, 30.0, 15, "fp64", cartesian=True)
+    got, _ = pc.count_rppi_mocks(m, None, e, 30.0, 15, "fp64")
+    assert (got == host).all()
+    dev, _ = pc.count_rppi_mocks(m, None, e, 30.0, 15, "fp64", options={"radec_on_device": 1})
     diff = np.abs(dev.astype(np.int64) - host.astype(np.int64))
     say("mocks device-conversion differences:", int(diff.sum()), "of", int(host.sum()))
     assert diff.sum() <= 1e-6 * host.sum() + 16
     # three separate columns, float32 input
     cols = tuple(np.ascontiguousarray(m[:, k]).astype(np.float32) for k in range(3))
-    c32, _ = pc.count_rppi_mocks(cols, None, e, 30.0, 15, "fp64")
     h32 = oracle.sky_to_cartesian(*[c.astype(np.float64) for c in cols], lib=olib)
     w32, _ = pc.count_rppi_mocks(h32, None, e, 30.0, 15, "fp64", cartesian=True)
-    d32 = np.abs(c32.astype(np.int64) - w32.astype(np.int64))
-    assert d32.sum() <= 1e-6 * w32.sum() + 16
+    c32, _ = pc.count_rppi_mocks(cols, None, e, 30.0, 15, "fp64")
+    assert (c32 == w32).all()
+    d32, _ = pc.count_rppi_mocks(cols, None, e, 30.0, 15, "fp64", options={"radec_on_device": 1})
+    assert np.abs(d32.astype(np.int64) - w32.astype(np.int64)).sum() <= 1e-6 * w32.sum() + 16
 
 
 def test_mocks_errors(pc):
@@ -157,17 +164,16 @@ def test_mocks_fullsize_sampled(pc, olib):
 
 
 def test_mocks_radec_converted_on_host(pc, olib):
-    """RA/DEC/distance converted on the host (cf_options.radec_on_host) with
-    the oracle's C library: counts equal the oracle's on its own conversion
-    bit for bit."""
+    """RA/DEC/distance converted on the host (the default) with the oracle's
+    C library: counts equal the oracle's on its own conversion bit for bit."""
     say("mocks radec on host")
     m = synth.sky_mock(40000, seed=409, radius_deg=6.0, dmin=500.0, dmax=900.0)
     e = synth.log_edges(0.3, 25.0, 12)
     want, _ = oracle.count_rppi_mocks(cart(m, olib), None, e, 30.0, 15, lib=olib)
-    got, _ = pc.count_rppi_mocks(m, None, e, 30.0, 15, "fp64", options={"radec_on_host": 1})
+    got, _ = pc.count_rppi_mocks(m, None, e, 30.0, 15, "fp64")
     assert (got == want).all()
     bad = m.copy()
     bad[3, 2] = -5.0
     import paper_1911_03545_amd as mm
     with pytest.raises(mm.PairCountError):
-        pc.count_rppi_mocks(bad, None, e, 30.0, 15, "fp64", options={"radec_on_host": 1})
+        pc.count_rppi_mocks(bad, None, e, 30.0, 15, "fp64")

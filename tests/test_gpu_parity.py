@@ -336,8 +336,7 @@ def test_theta_edges_one_ulp_apart(pc, olib, prec):
     want, _ = oracle.count_theta(ra, dec, None, None, te, lib=olib)
     assert want.sum() > 0
     for grid in (None, -1):
-        got, _ = pc.count_theta(ra, dec, None, None, te, prec, angular_grid=grid,
-                                options={"radec_on_host": 1})
+        got, _ = pc.count_theta(ra, dec, None, None, te, prec, angular_grid=grid)
         assert (got == want).all(), (grid, got, want)
 
 

@@ -176,8 +176,8 @@ def test_random_config(pc, olib, case):
         v2 = None if auto else oracle.radec_to_unit(r2, d2, lib=olib)
         grid = opts.pop("angular_grid")
         if rng.random() < 0.5:
-            # RA/DEC converted on the host with the oracle's library
-            opts["radec_on_host"] = 1
+            # RA/DEC converted on the host (the default) with the oracle's
+            # library
             got = pc.count_theta(ra, dec, r2, d2, te, prec, w1=w1, w2=w2, options=opts,
                                  ravg=ravg, angular_grid=grid, **kw)
         else:
@@ -203,7 +203,6 @@ def test_random_config(pc, olib, case):
         pimax = float(rng.uniform(5.0, 40.0))
         npi = int(rng.integers(1, 40))
         if rng.random() < 0.5:
-            opts["radec_on_host"] = 1
             got = pc.count_rppi_mocks(m1, None if auto else m2, e, pimax, npi, prec, w1=w1,
                                       w2=w2, options=opts, ravg=ravg, **kw)
         else:
