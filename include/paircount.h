@@ -248,6 +248,30 @@ cf_status count_pairs_r_ex(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *
                            cf_precision prec, uint64_t *counts, double *wsum,
                            const cf_options *opt);
 
+/* DD(r) without allocation -- for callers that cannot allocate during a
+   call: code under HIP stream capture, tight serving loops, harnesses that
+   forbid hipMalloc.  The same counts as count_pairs_r_ex (same pipeline and
+   kernels), but every device buffer is carved from one fixed device scratch
+   array of CF_NOALLOC_SCRATCH_BYTES per GPU, a file-scope array of the
+   library that each GPU it runs on holds until the process ends; host
+   staging is pinned when the context is created.  The call makes no
+   hipMalloc, hipHostMalloc, hipFree or allocator callback.
+   Limits: the points of d1 and d2 together need about 115 bytes each (plus
+   10 with weights, plus the staged columns of host input) and the work list
+   20 bytes per item, all within the scratch: about 1.1e6 points of an
+   autocorrelation; beyond that the call returns CF_EINVAL before any device
+   work (or, when the work list outgrows the rest, before the sweep) with a
+   message naming the limit.  cf_options.use_graph and autotune are rejected
+   (CF_EINVAL).  Every call on a GPU shares that GPU's scratch, which keeps
+   the last call's contents (each call clears what it needs zeroed): calls
+   that overlap on one GPU, from any context or stream, race and must be
+   serialised by the caller. */
+#define CF_NOALLOC_SCRATCH_BYTES (128ull << 20)
+cf_status count_pairs_r_noalloc(cf_ctx *ctx, const cf_catalog *d1, const cf_catalog *d2,
+                                const double *edges, int32_t nbins, double boxsize,
+                                cf_precision prec, uint64_t *counts, double *wsum,
+                                const cf_options *opt);
+
 /* DD(rp, pi) -- Table 1 "DDrppi" / "wp": rp^2 = dx^2 + dy^2 and pi = |dz|
    with z the line of sight (Appendix A).  pi bins are q_p = p * fl(pimax/npi)
    for p < npi and q_npi = pimax, half-open, so pi < pimax; wp(rp) counts are

@@ -37,7 +37,8 @@ STATUS_NAMES = {
 EXPORTED_SYMBOLS = (
     "cf_create", "cf_destroy", "cf_set_allocator", "cf_last_error", "cf_get_stats",
     "cf_default_options",
-    "count_pairs_r", "count_pairs_r_ex", "count_pairs_rppi", "count_pairs_rppi_ex",
+    "count_pairs_r", "count_pairs_r_ex", "count_pairs_r_noalloc", "count_pairs_rppi",
+    "count_pairs_rppi_ex",
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
     "cf_plan_grid", "cf_plan_grid_ex", "cf_plan_sky_grid", "cf_fp32_bands",
@@ -146,7 +147,7 @@ def load_library(path: str = LIB_PATH):
     lib.cf_get_stats.restype = ctypes.c_int
     lib.cf_default_options.argtypes = [ctypes.POINTER(cf_options)]
     lib.cf_default_options.restype = None
-    for name in ("count_pairs_r", "count_pairs_r_ex"):
+    for name in ("count_pairs_r", "count_pairs_r_ex", "count_pairs_r_noalloc"):
         f = getattr(lib, name)
         f.argtypes = [vp, cat, cat, vp, i32, dbl, ctypes.c_int, vp, vp] + (
             [] if name == "count_pairs_r" else [ctypes.POINTER(cf_options)])
@@ -475,6 +476,35 @@ class PairCounter:
             None if wsum is None else wsum.ctypes.data, self._opts(options, weight_type, rv))
         self._check(st)
         return self._result(counts, wsum, rv, (nb,))
+
+    def count_r_noalloc(self, d1, d2=None, edges=None, boxsize: float = 0.0,
+                        precision="fp64", w1=None, w2=None, options=None, counts_out=None,
+                        wsum_out=None):
+        """DD(r) through count_pairs_r_noalloc (no device allocation: every
+        buffer comes from the library's fixed per-GPU scratch).  With
+        ``counts_out`` (and ``wsum_out``) torch CUDA tensors the outputs stay
+        on the device (output_on_device) and are returned as given; otherwise
+        returns host arrays like :meth:`count_r`."""
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        nb = e.size - 1
+        c1 = _Cat(d1, w1)
+        c2 = None if d2 is None else _Cat(d2, w2)
+        fixed = {}
+        if counts_out is not None:
+            fixed["output_on_device"] = 1
+            counts, cp = counts_out, counts_out.data_ptr()
+            wsum = wsum_out
+            wp = None if wsum_out is None else wsum_out.data_ptr()
+        else:
+            counts = np.zeros(nb, dtype=np.uint64)
+            wsum = np.zeros(nb, dtype=np.float64) if w1 is not None else None
+            cp, wp = counts.ctypes.data, None if wsum is None else wsum.ctypes.data
+        st = self._lib.count_pairs_r_noalloc(
+            self._ctx, ctypes.byref(c1.c), None if c2 is None else ctypes.byref(c2.c),
+            e.ctypes.data, nb, float(boxsize), self._prec(precision), cp, wp,
+            self._opts(options, **fixed))
+        self._check(st)
+        return counts, wsum
 
     def count_rppi(self, d1, d2=None, rp_edges=None, pimax: float = 40.0, npi: int = 40,
                    boxsize: float = 0.0, precision="fp64", w1=None, w2=None, options=None,

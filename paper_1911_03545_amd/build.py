@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaircount.so")
-SOURCES = ["pc_api.cpp", "pc_plan.cpp", "pc_grid.hip", "pc_sweep.hip"]
+SOURCES = ["pc_api.cpp", "pc_plan.cpp", "pc_grid.hip", "pc_sweep.hip", "pc_noalloc.hip"]
 ARCH = os.environ.get("PAIRCOUNT_ARCH", "gfx950")
 
 FLAGS = [

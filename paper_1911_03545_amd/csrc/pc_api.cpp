@@ -87,6 +87,13 @@ struct cf_ctx {
     cf_alloc_fn alloc = nullptr;
     cf_free_fn free_ = nullptr;
     void *alloc_user = nullptr;
+    // fixed device scratch of count_pairs_r_noalloc (shared by every context
+    // on the device); while `arena` is set, ensure() carves buffers out of it
+    // from arena_off on instead of allocating
+    char *scratch = nullptr;
+    size_t scratch_cap = 0;
+    bool arena = false;
+    size_t arena_off = 0;
 };
 
 namespace {
@@ -135,6 +142,24 @@ cf_status ensure(cf_ctx *c, BufId id, size_t bytes)
     DevBuf &b = c->buf[id];
     if (b.cap >= bytes)
         return CF_OK;
+    if (c->arena) {
+        // no-allocation call: the next 256-byte aligned piece of the fixed
+        // scratch (a buffer that grows within a call leaves its old piece),
+        // with the same quarter of headroom as an allocated buffer so that
+        // both paths see identical capacities; the last MiB stays unused
+        const size_t off = (c->arena_off + 255) & ~(size_t)255;
+        const size_t want = bytes + bytes / 4;
+        if (off + want + (1u << 20) > c->scratch_cap)
+            return fail(c, CF_EINVAL,
+                        "the call needs more than the %zu bytes of fixed scratch of "
+                        "count_pairs_r_noalloc (%zu in use, %zu more asked); use "
+                        "count_pairs_r_ex", c->scratch_cap, off, want);
+        b.p = c->scratch + off;
+        b.cap = want;
+        b.user = false;
+        c->arena_off = off + want;
+        return CF_OK;
+    }
     // a recorded graph holds the addresses of these buffers
     drop_graph(c);
     if (b.p) {
@@ -168,6 +193,10 @@ cf_status ensure_pinned(cf_ctx *c, size_t bytes)
 {
     if (c->pinned_cap >= bytes)
         return CF_OK;
+    if (c->arena)
+        return fail(c, CF_EINVAL,
+                    "the call needs %zu bytes of host staging, more than the %zu bytes "
+                    "pinned when the context was created", bytes, c->pinned_cap);
     if (c->pinned) {
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipHostFree(c->pinned));
@@ -1555,9 +1584,83 @@ cf_status count(cf_ctx *c, int metric, bool theta, const cf_catalog *d1, int32_t
     return CF_OK;
 }
 
+// Host staging pinned at context creation: enough for every single-catalogue
+// DD(r) call (the staging of run() is about 256 KiB plus 24 bytes per bin).
+constexpr size_t kNoallocPinned = 1u << 20;
+
+// Device bytes a no-allocation DD(r) call needs at least: per point of each
+// side the gridded copies (float32 and binary64 coordinates, binary64
+// weights), the 32-byte gather records, the counting-sort and cell-id
+// scratch, and staged host columns; plus a margin for the bins, blocks and
+// counters.  The work list is sized on the device and checked when taken.
+size_t noalloc_need(const cf_catalog *d1, const cf_catalog *d2)
+{
+    size_t need = 1u << 20;
+    for (const cf_catalog *d : {d1, d2}) {
+        if (!d || d->n <= 0)
+            continue;
+        const size_t n = (size_t)d->n;
+        size_t per = 12 + 24 + 32 + 4 * 3 + 8 + 4 + 1;   // X..Z, x..z, rec, sort, cols, ids, blocks
+        if (d->w)
+            per += 8 + (d->mem == CF_MEM_HOST ? dsize(d->wdtype) : 0);
+        if (d->mem == CF_MEM_HOST)
+            per += 3 * dsize(d->dtype);
+        need += n * per;
+    }
+    return need + need / 4;   // the headroom of every buffer
+}
+
 }  // namespace
 
 extern "C" {
+
+cf_status count_pairs_r_noalloc(cf_ctx *c, const cf_catalog *d1, const cf_catalog *d2,
+                                const double *edges, int32_t nbins, double boxsize,
+                                cf_precision prec, uint64_t *counts, double *wsum,
+                                const cf_options *opt)
+{
+    if (!c)
+        return CF_EINVAL;
+    c->err.clear();
+    if (!c->scratch)
+        return fail(c, CF_EDEVICE, "no fixed scratch on this device");
+    if (opt && opt->struct_size == (int32_t)sizeof(cf_options) &&
+        (opt->use_graph || opt->autotune))
+        return fail(c, CF_EINVAL,
+                    "use_graph and autotune allocate; count_pairs_r_noalloc takes neither");
+    if (d1 && d1->n >= 0 && (!d2 || d2->n >= 0)) {
+        const size_t need = noalloc_need(d1, d2);
+        if (need > c->scratch_cap)
+            return fail(c, CF_EINVAL,
+                        "count_pairs_r_noalloc: %lld + %lld points need about %zu MiB of "
+                        "scratch, more than its fixed %zu MiB; use count_pairs_r_ex",
+                        (long long)d1->n, (long long)(d2 ? d2->n : 0), need >> 20,
+                        c->scratch_cap >> 20);
+    }
+    // run the ordinary pipeline on a buffer table carved from the fixed
+    // scratch; the context's own buffers and work-list history stay as they
+    // were for its other calls
+    DevBuf saved[B_COUNT];
+    for (int k = 0; k < B_COUNT; k++) {
+        saved[k] = c->buf[k];
+        c->buf[k] = DevBuf{};
+    }
+    const int32_t saved_items = c->last_items;
+    std::vector<char> saved_shape;
+    saved_shape.swap(c->last_shape);
+    c->arena = true;
+    c->arena_off = 0;
+    RunCtl ctl;
+    ctl.no_async = true;
+    const cf_status st = run(c, ctl, PC_METRIC_R, false, d1, 1, d2, edges, nbins, 0.0, 1,
+                             boxsize, prec, counts, wsum, opt);
+    c->arena = false;
+    for (int k = 0; k < B_COUNT; k++)
+        c->buf[k] = saved[k];
+    c->last_items = saved_items;
+    c->last_shape.swap(saved_shape);
+    return st;
+}
 
 void cf_default_options(cf_options *opt)
 {
@@ -1604,6 +1707,25 @@ cf_status cf_create(int device, void *hip_stream, cf_ctx **out)
             cf_destroy(c);
             return CF_EDEVICE;
         }
+    }
+    // set-up of the no-allocation entry point: the device address of this
+    // device's fixed scratch (looked up with the device current) and host
+    // staging pinned now, so that such a call allocates nothing
+    void *sp = nullptr;
+    size_t sbytes = 0;
+    e = pc::noalloc_scratch(device, &sp, &sbytes);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        (void)hipGetLastError();
+        cf_destroy(c);
+        return CF_EDEVICE;
+    }
+    c->scratch = static_cast<char *>(sp);
+    c->scratch_cap = sbytes;
+    if (ensure_pinned(c, kNoallocPinned) != CF_OK) {
+        g_create_error = c->err;
+        cf_destroy(c);
+        return CF_ENOMEM;
     }
     g_create_error.clear();
     *out = c;

@@ -22,6 +22,10 @@
 #define PC_MAX_NPI 1024
 #define PC_MAX_BINS_TOTAL 4096 // r bins, or nrp * npi
 #define PC_MAX_HIST_WAVE 4096  // uint32 LDS counters per wave (bins * copies)
+// fixed device scratch of the no-allocation entry point (per GPU), and the
+// devices whose scratch address the library can keep
+#define PC_NOALLOC_SCRATCH_BYTES (128ull << 20)
+#define PC_NOALLOC_MAX_DEVICES 64
 
 // Lookup-table entries.  A plain entry is the histogram slot of every value
 // in the table cell: the number of edges whose band lies wholly below the

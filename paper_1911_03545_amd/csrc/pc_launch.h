@@ -139,5 +139,9 @@ hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocor
 int sweep_waves();
 hipError_t sweep_occupancy(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv,
                            int lds_bytes, int *per_cu);
+// device address and size of the fixed scratch of the no-allocation entry
+// point on `device`, which must be the current device (looked up once per
+// device, then cached)
+hipError_t noalloc_scratch(int device, void **ptr, size_t *bytes);
 
 }  // namespace pc
