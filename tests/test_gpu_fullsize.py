@@ -1,28 +1,49 @@
 """Parity at the full workload sizes (needs an MI355X).
 
-The oracle cannot count 10^6-10^7 points in full within a test, so at these
-sizes the GPU result is checked three ways:
+At these sizes the GPU result is checked against:
 
-* sampled outputs the oracle computes exactly: cross counts of a random
-  subset S of the first catalogue against the whole second catalogue, which
-  runs the full-size grid, work list and sweep on the GPU;
+* the oracle's full histograms, computed ahead of the tests by
+  ``tests/golden/make_fullsize.py`` (the exactly pruned oracle, equal to the
+  brute-force definition bit for bit) and stored in
+  ``tests/golden/fullsize_*.json`` with the SHA-256 of their inputs, which the
+  tests draw again and check; every auto (and cross) histogram of both
+  precisions must equal them bit for bit, and weighted sums must lie within
+  1e-12 of the exactly rounded sums;
+* sampled outputs the oracle computes on the spot: cross counts of a random
+  subset S of the first catalogue against the whole second catalogue;
 * properties that hold at any size: the float32+recheck path equals the
   binary64 path bit for bit, and the autocorrelation launch equals the
-  cross-correlation of the catalogue with itself;
-* for weights, both GPU paths against each other and the sampled cross sums
-  against the oracle's exactly rounded sums.
+  cross-correlation of the catalogue with itself.
 
 Workloads: clustered periodic boxes of 10^6 points (L = 420) and 4 x 10^6
 weighted points (L = 1100), and a 30-degree cap with 2 x 10^6 clustered and
 5 x 10^6 uniform RA/DEC points.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from golden import make_fullsize as recipes
 
 pytestmark = pytest.mark.gpu
+
+
+def golden(name, *inputs):
+    """The stored oracle histograms of a workload, after checking that the
+    inputs drawn here are the ones they were computed on."""
+    path = recipes.path_of(name)
+    assert os.path.exists(path), f"missing {path}: run tests/golden/make_fullsize.py"
+    with open(path) as fh:
+        g = json.load(fh)
+    assert g["input_sha256"] == recipes.sha(*inputs), f"{name}: inputs differ from the golden's"
+    g["counts"] = np.array(g["counts"], dtype=np.uint64)
+    if "wsum_hex" in g:
+        g["wsum"] = np.array([float.fromhex(v) for v in g["wsum_hex"]])
+    return g
 
 WSUM_RTOL = 1e-12
 NSAMPLE = 384
@@ -59,7 +80,7 @@ def check_w(got, want, rtol=WSUM_RTOL):
 # ---------------------------------------------------- 10^6 points, L = 420
 @pytest.fixture(scope="module")
 def box420():
-    return synth.clustered_box(1_000_000, 420.0, seed=2, nblobs=5000, sigma=2.0)
+    return recipes.box420(np.float64)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -67,9 +88,12 @@ def test_r_n1e6(pc, olib, box420, dtype):
     say("r N=1e6 L=420", dtype.__name__)
     pts = box420.astype(dtype)
     e = synth.log_edges(0.1, 25.0, 20)
+    g = golden("r_n1e6_L420_" + ("f64" if dtype == np.float64 else "f32"), pts)
+    assert (np.array(g["recipe"]["edges"]) == e).all()
     a32, _ = pc.count_r(pts, None, e, 420.0, "fp32")
     a64, _ = pc.count_r(pts, None, e, 420.0, "fp64")
-    assert (a32 == a64).all()
+    assert (a32 == g["counts"]).all(), (a32, g["counts"])
+    assert (a64 == g["counts"]).all()
     x32, _ = pc.count_r(pts, pts.copy(), e, 420.0, "fp32")
     assert (a32 == x32).all()
     assert int(a32.sum()) % 2 == 0
@@ -84,9 +108,11 @@ def test_rppi_n1e6(pc, olib, box420, dtype):
     say("rppi N=1e6 L=420", dtype.__name__)
     pts = box420.astype(dtype)
     e = synth.log_edges(0.1, 25.0, 20)
+    g = golden("rppi_n1e6_L420_" + ("f64" if dtype == np.float64 else "f32"), pts)
     a32, _ = pc.count_rppi(pts, None, e, 40.0, 40, 420.0, "fp32")
     a64, _ = pc.count_rppi(pts, None, e, 40.0, 40, 420.0, "fp64")
-    assert (a32 == a64).all()
+    assert (a32.ravel() == g["counts"]).all()
+    assert (a64.ravel() == g["counts"]).all()
     x32, _ = pc.count_rppi(pts, pts.copy(), e, 40.0, 40, 420.0, "fp32")
     assert (a32 == x32).all()
     s = pts[sample(pts.shape[0], NSAMPLE, 12)]
@@ -121,19 +147,19 @@ def test_r_ravg_n1e6(pc, olib, box420):
 # ------------------------------------------- 4 x 10^6 weighted, L = 1100
 @pytest.fixture(scope="module")
 def box1100():
-    pts = synth.clustered_box(4_000_000, 1100.0, seed=3, nblobs=20000, sigma=2.0)
-    w = synth.uniform_weights(4_000_000, seed=33)
-    return pts, w
+    return recipes.box1100()
 
 
 def test_r_weighted_n4e6(pc, olib, box1100):
     say("weighted r N=4e6 L=1100")
     pts, w = box1100
     e = synth.log_edges(0.1, 50.0, 25)
+    g = golden("r_w_n4e6_L1100", pts, w)
     c32, w32 = pc.count_r(pts, None, e, 1100.0, "fp32", w1=w)
     c64, w64 = pc.count_r(pts, None, e, 1100.0, "fp64", w1=w)
-    assert (c32 == c64).all()
-    check_w(w32, w64, 2 * WSUM_RTOL)
+    assert (c32 == g["counts"]).all() and (c64 == g["counts"]).all()
+    check_w(w32, g["wsum"])
+    check_w(w64, g["wsum"])
     idx = sample(pts.shape[0], NSAMPLE, 13)
     got, gw = pc.count_r(pts[idx], pts, e, 1100.0, "fp32", w1=w[idx], w2=w)
     want, ww = oracle.count_r(pts[idx], pts, e, 1100.0, w1=w[idx], w2=w, lib=olib)
@@ -145,10 +171,12 @@ def test_rppi_weighted_n4e6(pc, olib, box1100):
     say("weighted rppi N=4e6 L=1100")
     pts, w = box1100
     e = synth.log_edges(0.1, 50.0, 25)
+    g = golden("rppi_w_n4e6_L1100", pts, w)
     c32, w32 = pc.count_rppi(pts, None, e, 40.0, 40, 1100.0, "fp32", w1=w)
     c64, w64 = pc.count_rppi(pts, None, e, 40.0, 40, 1100.0, "fp64", w1=w)
-    assert (c32 == c64).all()
-    check_w(w32, w64, 2 * WSUM_RTOL)
+    assert (c32.ravel() == g["counts"]).all() and (c64.ravel() == g["counts"]).all()
+    check_w(w32.ravel(), g["wsum"])
+    check_w(w64.ravel(), g["wsum"])
     idx = sample(pts.shape[0], NSAMPLE, 14)
     got, gw = pc.count_rppi(pts[idx], pts, e, 40.0, 40, 1100.0, "fp32", w1=w[idx], w2=w)
     want, ww = oracle.count_rppi(pts[idx], pts, e, 40.0, 40, 1100.0, w1=w[idx], w2=w,
@@ -160,8 +188,8 @@ def test_rppi_weighted_n4e6(pc, olib, box1100):
 # ------------------------------------- theta on a 30-degree cap, 2e6 / 5e6
 @pytest.fixture(scope="module")
 def cap(olib):
-    ra_d, dec_d = synth.cap_radec(2_000_000, seed=4, clustered=True)
-    ra_r, dec_r = synth.cap_radec(5_000_000, seed=40)
+    ra_d, dec_d = recipes.cap_d()
+    ra_r, dec_r = recipes.cap_r(5_000_000)
     # unit vectors from the host conversion the oracle itself uses
     v_d = oracle.radec_to_unit(ra_d, dec_d, lib=olib)
     v_r = oracle.radec_to_unit(ra_r, dec_r, lib=olib)
@@ -172,11 +200,12 @@ def test_theta_dd_n2e6(pc, olib, cap):
     say("theta DD N=2e6")
     (ra, dec, v), _ = cap
     e = synth.log_edges(0.01, 10.0, 20)
+    g = golden("theta_dd_cap_n2e6", ra, dec)
     a32, _ = pc.count_theta(None, None, theta_edges_deg=e, precision="fp32",
                             unit_vectors=(v, None))
     a64, _ = pc.count_theta(None, None, theta_edges_deg=e, precision="fp64",
                             unit_vectors=(v, None))
-    assert (a32 == a64).all()
+    assert (a32 == g["counts"]).all() and (a64 == g["counts"]).all()
     x32, _ = pc.count_theta(None, None, theta_edges_deg=e, precision="fp32",
                             unit_vectors=(v, v.copy()))
     assert (a32 == x32).all()
@@ -206,6 +235,14 @@ def test_theta_dr_n2e6_5e6(pc, olib, cap):
     c64, _ = pc.count_theta(None, None, theta_edges_deg=e, precision="fp64",
                             unit_vectors=(v_d, v_r))
     assert (c32 == c64).all()
+    # the whole D against the first 5e5 randoms, against the stored oracle
+    # histogram, from RA/DEC converted on the host (the default)
+    k = 500_000
+    g = golden("theta_dr_cap_n2e6_r5e5", ra_d, dec_d, ra_r[:k], dec_r[:k])
+    for prec in ("fp32", "fp64"):
+        got, _ = pc.count_theta(ra_d, dec_d, ra_r[:k], dec_r[:k], theta_edges_deg=e,
+                                precision=prec)
+        assert (got == g["counts"]).all(), prec
     idx = sample(ra_d.size, NSAMPLE // 2, 16)
     got, _ = pc.count_theta(None, None, theta_edges_deg=e, precision="fp32",
                             unit_vectors=(v_d[idx], v_r))
@@ -217,14 +254,14 @@ def test_theta_dr_n2e6_5e6(pc, olib, cap):
 def test_batch_fullsize_catalogues(pc, olib):
     """Catalogues of the batched workload's sizes (2e5-2e6 clustered points,
     periodic L = 1000) in one batched, graph-replayed float32 call: every
-    slice equals the single-catalogue binary64 call, and sampled cross counts
-    of the largest catalogue equal the oracle's."""
+    slice, and every single-catalogue binary64 call, equals the oracle's
+    stored histogram, and sampled cross counts of the largest catalogue equal
+    the oracle's."""
     import torch
     say("batch full-size catalogues")
     L = 1000.0
-    sizes = [2_000_000, 200_000, 1_100_000]
-    pts = [synth.clustered_box(n, L, seed=5000 + k, nblobs=n // 200, sigma=2.0)
-           for k, n in enumerate(sizes)]
+    pts = [recipes.batch_cat(k) for k in range(len(recipes.BATCH_SIZES))]
+    gold = [golden(f"batch_L1000_c{k}", p) for k, p in enumerate(pts)]
     cols = [tuple(torch.from_numpy(np.ascontiguousarray(p[:, a])).cuda() for a in range(3))
             for p in pts]
     e = synth.log_edges(0.1, 25.0, 20)
@@ -233,8 +270,9 @@ def test_batch_fullsize_catalogues(pc, olib):
         got, _ = pc.count_rppi_batch(cols, e, 40.0, 40, L, "fp32", options=g)
     assert pc.stats()["replayed"] == 1
     for k, c in enumerate(cols):
+        assert (got[k].ravel() == gold[k]["counts"]).all(), k
         one, _ = pc.count_rppi(c, None, e, 40.0, 40, L, "fp64")
-        assert (got[k] == one).all(), k
+        assert (one.ravel() == gold[k]["counts"]).all(), k
     big = pts[0]
     s = big[sample(big.shape[0], NSAMPLE // 2, 18)]
     gx, _ = pc.count_rppi(s, big, e, 40.0, 40, L, "fp32")
