@@ -207,14 +207,17 @@ def cpu_baseline(pts: np.ndarray, w_ref: int, target_s: float = 12.0):
     }
 
 
-def batch_bench(args):
+def batch_bench(args, steps=None, emit=True):
     """Batched DD(rp, pi): 256 (--batch-cats) clustered mock catalogues of 2e5-2e6 points in
     periodic L = 1000 boxes, 20 log rp bins in [0.1, 25], pimax = 40 in 40
     bins.  Reports the 2x2 ablation {binary64, float32 + recheck} x {256
     sequential calls, one batched call replayed from a graph}, as Gpair-evals/s
-    over the sum of the catalogues' reference candidate pairs."""
+    over the sum of the catalogues' reference candidate pairs.  Returns the
+    result line (printed when `emit`)."""
     import torch
     import paper_1911_03545_amd as pcm
+
+    steps = args.steps if steps is None else steps
 
     dev = torch.device("cuda:0")
     L = 1000.0
@@ -248,7 +251,7 @@ def batch_bench(args):
     for prec in ("fp32", "fp64"):
         opts = pcm.default_options(use_graph=1, autotune=1)
         tb, (cb, _) = timed(lambda: ctx.count_rppi_batch(cats, edges, 40.0, 40, L, prec,
-                                                         options=opts), args.steps)
+                                                         options=opts), steps)
         st = ctx.stats()
         print(f"{prec}: batched {tb * 1e3:.2f} ms", file=sys.stderr, flush=True)
         sopts = pcm.default_options(autotune=1)
@@ -256,7 +259,10 @@ def batch_bench(args):
         def seq():
             return np.stack([ctx.count_rppi(cc, None, edges, 40.0, 40, L, prec,
                                             options=sopts)[0] for cc in cats])
-        ts, cs = timed(seq, max(1, args.steps // 5))
+        if args.batch_only:
+            ts, cs = float("nan"), cb
+        else:
+            ts, cs = timed(seq, max(1, steps // 5))
         print(f"{prec}: sequential {ts * 1e3:.2f} ms", file=sys.stderr, flush=True)
         if ref is None:
             ref = cb
@@ -274,7 +280,7 @@ def batch_bench(args):
         "value": res["fp32"]["batched_value"],
         "unit": "Gpair-evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "higher_is_better": True,
         "vs_plain_fp64_sequential": res["fp32"]["batched_value"] / res["fp64"]["sequential_value"],
         "dtype": "f32",
@@ -287,7 +293,11 @@ def batch_bench(args):
         "ablation": res,
     }
     ctx.close()
-    print(json.dumps(line), flush=True)
+    del cats
+    torch.cuda.empty_cache()
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def ref_pairs_box(v: np.ndarray, reach: float) -> int:
@@ -629,6 +639,13 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the batched DD(rp,pi) benchmark (256 mock catalogues) instead")
     ap.add_argument("--batch-cats", type=int, default=256)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave the batched 256-catalogue ablation out of the default line")
+    ap.add_argument("--batch-steps", type=int, default=3,
+                    help="timed batched calls per precision in the default line's ablation")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="with --batch: time only the batched calls (no sequential cells; "
+                         "for profiling)")
     ap.add_argument("--mocks", action="store_true",
                     help="run the on-sky DD(rp,pi) benchmark (1e6-point mock) instead")
     ap.add_argument("--theta", action="store_true",
@@ -825,6 +842,16 @@ def main():
         # time ratio of the full workload: the oracle's extrapolated time over a GPU call
         line["cpu_baseline"]["gpu_speedup"] = value / line["cpu_baseline"]["value"]
     ctx.close()
+    # the metric's second half: the batched workload's 2x2 ablation
+    # {binary64, float32 + recheck} x {256 sequential calls, one batched
+    # graph-replayed call}, after the timed DD(r) steps
+    if not args.no_batch:
+        b = batch_bench(args, steps=args.batch_steps, emit=False)
+        line["batch_ablation"] = {
+            "metric": b["metric"], "unit": b["unit"], "config": b["config"],
+            "value_fp32_batched": b["value"],
+            "fp32_batched_vs_fp64_sequential": b["vs_plain_fp64_sequential"],
+            "cells": b["ablation"], "steps": b["steps"]}
     print(json.dumps(line), flush=True)
 
 

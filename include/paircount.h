@@ -418,6 +418,18 @@ cf_status cf_plan_sky_grid(double chord_reach, double zlo, double zhi, int32_t s
    gets the empty band [-1, -1].  Returns CF_EINVAL on bad input. */
 cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32_t ndim,
                         double coord_scale, float *lo, float *hi);
+/* The same with a rounding bound per axis (axis_eps[ndim]): the largest
+   total error of the two float32 coordinates whose difference is taken on
+   that axis.  cf_fp32_bands uses 6 u S on every axis (box-frame
+   coordinates, u = 2^-24, S = coord_scale); the float32 sweeps of 3-D grids
+   hold x and y relative to column centres, so their bound scales with the
+   column width.  Per axis dl = eps (1 + u) + u (r + eps) + 2 U S with
+   U = 2^-53, r = sqrt(E); then B = (2 r sqrt(sum dl^2) + sum dl^2 +
+   (ndim + 1)(u + U) s') * 1.25 with s' = E + 2 r sqrt(sum dl^2) + sum dl^2,
+   and the band is [E - B, E + B] rounded outward to float32. */
+cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, int32_t ndim,
+                             const double *axis_eps, double coord_scale, float *lo,
+                             float *hi);
 
 #ifdef __cplusplus
 }

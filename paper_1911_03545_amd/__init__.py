@@ -42,6 +42,7 @@ EXPORTED_SYMBOLS = (
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
     "cf_plan_grid", "cf_plan_grid_ex", "cf_plan_sky_grid", "cf_fp32_bands",
+    "cf_fp32_bands_axes",
 )
 
 
@@ -184,6 +185,8 @@ def load_library(path: str = LIB_PATH):
     lib.cf_plan_sky_grid.restype = ctypes.c_int
     lib.cf_fp32_bands.argtypes = [vp, i32, i32, dbl, vp, vp]
     lib.cf_fp32_bands.restype = ctypes.c_int
+    lib.cf_fp32_bands_axes.argtypes = [vp, i32, i32, vp, dbl, vp, vp]
+    lib.cf_fp32_bands_axes.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -265,6 +268,23 @@ def fp32_bands(edges_sq, ndim: int, coord_scale: float):
                            lo.ctypes.data, hi.ctypes.data)
     if st != CF_OK:
         raise PairCountError(st, "cf_fp32_bands failed")
+    return lo, hi
+
+
+def fp32_bands_axes(edges_sq, ndim: int, axis_eps, coord_scale: float):
+    """Host-only float32 decision bands with a rounding bound per axis (the
+    total error of the two float32 coordinates of that axis)."""
+    lib = load_library()
+    e = np.ascontiguousarray(edges_sq, dtype=np.float64)
+    sc = np.ascontiguousarray(axis_eps, dtype=np.float64)
+    if sc.size < ndim:
+        raise ValueError("one bound per axis")
+    lo = np.zeros(e.size, dtype=np.float32)
+    hi = np.zeros(e.size, dtype=np.float32)
+    st = lib.cf_fp32_bands_axes(e.ctypes.data, e.size, int(ndim), sc.ctypes.data,
+                                float(coord_scale), lo.ctypes.data, hi.ctypes.data)
+    if st != CF_OK:
+        raise PairCountError(st, "cf_fp32_bands_axes failed")
     return lo, hi
 
 

@@ -874,6 +874,16 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
             fp32 = false;
         }
     }
+    // float32 sweeps of 3-D grids keep x and y in column-local frames, so
+    // their rounding scales with the column width instead of the box
+    g.xy_local = (fp32 && !sky_grid) ? 1 : 0;
+    // their rounding bounds: the lane's x (y) lies within k + 1/2 column
+    // widths of the j column's centre, the j point within half a width; z
+    // (box frame) within scale + reach_z and scale
+    const double axis_eps[3] = {
+        pc::frame_eps((g.xyk + 0.5) * g.width[0], 0.5 * g.width[0], scale),
+        pc::frame_eps((g.xyk + 0.5) * g.width[1], 0.5 * g.width[1], scale),
+        pc::frame_eps(scale + reach_z, scale, scale)};
     // batches: private per-wave histograms, flushed per catalogue
     const bool priv = ncat > 1;
     int fscale_log2 = 0;
@@ -937,7 +947,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     pc::HostBins hb;
     // on-sky pairs bin (rp, pi) like the Cartesian statistic
     rc = pc::build_bins(sky ? PC_METRIC_RPPI : metric, fp32, lin.data(), nb, pimax, npi, scale,
-                        fscale_log2, priv, &hb);
+                        g.xy_local ? axis_eps : nullptr, fscale_log2, priv, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
     if (g.zq_shift > 0) {
@@ -1068,6 +1078,16 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.sep_scale = 1.0 / g.fscale;
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
     a.flush_count = (unsigned *)(misc(c) + M_FLUSH);
+    a.xy_local = g.xy_local;
+    a.gnx = g.n[0];
+    a.gny = g.n[1];
+    a.gnz = g.n[2];
+    for (int k = 0; k < 3; k++)
+        a.glo[k] = g.lo[k];
+    a.gw[0] = g.width[0];
+    a.gw[1] = g.width[1];
+    a.fscale = g.fscale;
+    a.cs2 = autocorr ? dptr<int32_t>(c, B_CS1) : dptr<int32_t>(c, B_CS2);
     a.nbt = (int32_t)nbt;
     a.slots = (int32_t)((nb + 2) * hb.hdr.row_w);
     a.priv = priv ? 1 : 0;

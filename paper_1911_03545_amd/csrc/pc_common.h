@@ -94,6 +94,9 @@ struct pc_grid {
     // ball, -1 where no pair of the two columns can be within reach
     int32_t xyk;
     int16_t zro[PC_MAX_XYK + 1][PC_MAX_XYK + 1];
+    // float32 path on a 3-D grid: x and y stored relative to the centre of
+    // each point's column (column-local frames), else relative to lo
+    int32_t xy_local;
     // angular grid: declination bands of nband * n[2] slices, slice index
     // floor((dec - dec_lo) * inv_hs); bands is a device table of nband entries
     int32_t nband;

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pc_common.h"
+#include "pc_frame.h"
 #include "pc_launch.h"
 
 namespace pc {
@@ -455,8 +456,17 @@ __global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int
          d += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = perm[d];
         const double4 r = rec[i];
-        X[d] = (float)((r.x - g.lo[0]) * g.fscale);
-        Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
+        if (g.xy_local) {
+            // x and y relative to the centre of the point's own column
+            const int cell = cell_of ? cell_of[i] : cell_sorted[d];
+            int ix, iy;
+            cell_column(cell, g.n[0], g.n[1], g.n[2], &ix, &iy);
+            X[d] = (float)((r.x - col_centre(g.lo[0], g.width[0], ix)) * g.fscale);
+            Y[d] = (float)((r.y - col_centre(g.lo[1], g.width[1], iy)) * g.fscale);
+        } else {
+            X[d] = (float)((r.x - g.lo[0]) * g.fscale);
+            Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
+        }
         if (g.zq_shift > 0)
             Z[d] = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
         else

@@ -20,7 +20,7 @@ struct SweepArgs {
     int32_t n_items;              // items, or the item capacity when n_items_dev is set
     const int32_t *n_items_dev;   // device item count (replayed calls), or NULL
     int32_t *counter;      // PC_STREAMS item counters, PC_STREAM_STRIDE apart, zeroed
-    const float *X1, *Y1, *Z1, *X2, *Y2, *Z2;    // float32, box frame
+    const float *X1, *Y1, *Z1, *X2, *Y2, *Z2;    // float32 (x, y column-local when xy_local)
     const double *x1, *y1, *z1, *x2, *y2, *z2;   // binary64, input values
     const double *w1, *w2;
     double L;
@@ -42,6 +42,15 @@ struct SweepArgs {
     // uint32 LDS counter can wrap); flush_count counts those merges
     unsigned long long flush_at;
     unsigned *flush_count;
+    // float32 sweeps of 3-D grids: x and y of side 2 are column-local
+    // (pc_frame.h); each lane's point is placed in the frame of the item's j
+    // column, found from the cell id of the item's first j point
+    int32_t xy_local;
+    int32_t gnx, gny, gnz;
+    double glo[3];
+    double gw[2];
+    double fscale;
+    const int32_t *cs2;   // cell id of every sorted point of side 2
     int32_t priv;       // per-wave private replicas, flushed per catalogue (batches)
     int32_t copies;     // LDS histogram replicas per wave (power of two; 64 = one per
                         // lane with unconditional updates, 1-D unweighted only)

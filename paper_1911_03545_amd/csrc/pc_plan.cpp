@@ -289,26 +289,33 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
     return CF_OK;
 }
 
-// Float32 decision bands.  The float32 sweep evaluates, per axis,
-//   X = fl32(fl64(x - lo)),  A_i = fl32(X_i + fl32(D)),  d32 = fl32(A_i - X_j)
-// and then s32 with one multiply and fused multiply-adds.  With S bounding
-// every coordinate and periodic offset, u = 2^-24 and U = 2^-53:
-//   |d32 - d| <= eps_a + u (|d| + eps_a),   eps_a = 6 u S
-// for the exact wrapped difference d.  Summing ndim squares,
-//   |s32 - s| <= 2 sqrt(ndim) sqrt(s) dl + ndim dl^2 + (ndim + 1) u s'
-// with dl the per-axis bound; the binary64 definition itself differs from the
-// exact s by at most 2 sqrt(ndim) sqrt(s) (2 U S) + ... + (ndim + 1) U s.  The
-// band of edge E is [E - B(E), E + B(E)] rounded outward to float32, with B
-// the sum of both bounds times kSafety.  Because B grows slower than s, a
-// float32 value below the band proves s64 < E and one above proves s64 > E.
-int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale,
-               float *lo, float *hi)
+// Float32 decision bands.  The float32 sweep evaluates, per axis, the float32
+// difference d32 = fl32(A - X_j) of two float32 coordinates whose rounding
+// errors (from the binary64 values, and any offset added on the way) sum to
+// at most eps_a, and then s32 with one multiply and fused multiply-adds.
+// With u = 2^-24 and U = 2^-53:
+//   |d32 - d| <= dl_a = eps_a (1 + u) + u (|d| + eps_a) + 2 U S
+// for the exact wrapped difference d (S bounds every coordinate and periodic
+// offset; the 2 U S term covers the binary64 differences).  Summing ndim
+// squares (Cauchy-Schwarz on the cross terms),
+//   |s32 - s| <= 2 sqrt(s) sqrt(sum dl_a^2) + sum dl_a^2 + (ndim + 1) u s'
+// and the binary64 definition differs from the exact s by at most
+// (ndim + 1) U s'.  The band of edge E is [E - B(E), E + B(E)] rounded
+// outward to float32, with B the sum of both bounds times kSafety.  Because
+// B grows slower than s, a float32 value below the band proves s64 < E and
+// one above proves s64 > E.
+int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
+                    double scale, float *lo, float *hi)
 {
     if (nedges < 1 || ndim < 1 || ndim > 3 || !(scale >= 0.0) || !isfinite(scale))
         return CF_EINVAL;
-    const double eps_a = 6.0 * kU32 * scale;
+    double eps[3];
+    for (int a = 0; a < ndim; a++) {
+        if (!(axis_eps[a] >= 0.0) || !isfinite(axis_eps[a]))
+            return CF_EINVAL;
+        eps[a] = axis_eps[a];
+    }
     const double d64 = 2.0 * kU64 * scale;
-    const double sq = sqrt((double)ndim);
     for (int k = 0; k < nedges; k++) {
         const double E = edges_sq[k];
         if (!isfinite(E) || E < 0.0 || E > 1e30)
@@ -321,12 +328,16 @@ int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale,
         double B;
         if (ndim == 1) {
             // an unsquared line-of-sight edge compared with |dz|
-            B = eps_a * (1.0 + kU32) + kU32 * (E + eps_a) + d64;
+            B = eps[0] * (1.0 + kU32) + kU32 * (E + eps[0]) + d64;
         } else {
             const double r = sqrt(E);
-            const double dl = eps_a * (1.0 + kU32) + kU32 * (r + eps_a) + d64;
-            const double s_hi = E + 2.0 * sq * r * dl + ndim * dl * dl;
-            B = 2.0 * sq * r * dl + ndim * dl * dl + (ndim + 1) * kU32 * s_hi +
+            double sum2 = 0.0;
+            for (int a = 0; a < ndim; a++) {
+                const double dl = eps[a] * (1.0 + kU32) + kU32 * (r + eps[a]) + d64;
+                sum2 += dl * dl;
+            }
+            const double s_hi = E + 2.0 * r * sqrt(sum2) + sum2;
+            B = 2.0 * r * sqrt(sum2) + sum2 + (ndim + 1) * kU32 * s_hi +
                 (ndim + 1) * kU64 * s_hi;
         }
         B = B * kSafety + 1e-300;
@@ -334,6 +345,29 @@ int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale,
         hi[k] = float_up(E + B);
     }
     return CF_OK;
+}
+
+// Box-frame coordinates (every axis): X = fl32(x - lo), the lane's A =
+// fl32(X_i + fl32(D)) and the difference: eps = 6 u S covers the roundings
+// of X_i, X_j, D and A.
+int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
+               float *hi)
+{
+    const double e = 6.0 * kU32 * scale;
+    const double e3[3] = {e, e, e};
+    return fp32_bands_axes(edges_sq, nedges, ndim, e3, scale, lo, hi);
+}
+
+// Rounding bound of one axis of the column-local frames (pc_frame.h): the
+// lane's coordinate (i point plus offset, in the frame of the j column, at
+// most `a_max` from its origin) and the j coordinate (at most `b_max`) are
+// each rounded once from binary64 values, so their errors sum to at most
+// u (a_max + b_max), plus the binary64 roundings of forming them (a few U
+// times the box scale); a relative 2^-20 covers points a rounding outside
+// their column.
+double frame_eps(double a_max, double b_max, double scale)
+{
+    return kU32 * (a_max + b_max) * (1.0 + 0x1p-20) + 8.0 * kU64 * scale;
 }
 
 // Binary64 path: the float32 value fl32(s64) is compared against the edge
@@ -428,7 +462,8 @@ int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale,
 }
 
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
-               int npi, double coord_scale, int fscale_log2, bool priv, HostBins *out)
+               int npi, double coord_scale, const double *axis_eps, int fscale_log2,
+               bool priv, HostBins *out)
 {
     if (!fp32)
         fscale_log2 = 0;
@@ -450,7 +485,10 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     int rc;
     const int ndim = (metric == PC_METRIC_RPPI) ? 2 : 3;
     if (fp32) {
-        rc = fp32_bands(E.data(), ne, ndim, coord_scale, lo.data(), hi.data());
+        const double e = 6.0 * kU32 * coord_scale;
+        const double e3[3] = {e, e, e};
+        rc = fp32_bands_axes(E.data(), ne, ndim, axis_eps ? axis_eps : e3, coord_scale,
+                             lo.data(), hi.data());
         if (rc)
             return rc;
     } else {
@@ -669,4 +707,14 @@ extern "C" cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32
     if (!edges_sq || !lo || !hi)
         return CF_EINVAL;
     return (cf_status)pc::fp32_bands(edges_sq, nedges, ndim, coord_scale, lo, hi);
+}
+
+extern "C" cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, int32_t ndim,
+                                        const double *axis_eps, double coord_scale,
+                                        float *lo, float *hi)
+{
+    if (!edges_sq || !axis_eps || !lo || !hi)
+        return CF_EINVAL;
+    return (cf_status)pc::fp32_bands_axes(edges_sq, nedges, ndim, axis_eps, coord_scale, lo,
+                                          hi);
 }

@@ -26,10 +26,18 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
                   pc_grid *g, std::vector<pc_band> *bands);
 int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
                float *hi);
+// per-axis rounding bounds of the two float32 coordinates (ndim values)
+int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
+                    double scale, float *lo, float *hi);
+// rounding bound of one column-local axis: coordinates at most a_max and
+// b_max from the frame origin, each rounded once from binary64
+double frame_eps(double a_max, double b_max, double scale);
 // `priv`: size the lookup table for the private-histogram (batched) sweep
 int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, bool priv,
                     int *m);
+// axis_eps (optional, x y z): per-axis rounding bounds (else box-frame 6 u S)
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax, int npi,
-               double coord_scale, int fscale_log2, bool priv, HostBins *out);
+               double coord_scale, const double *axis_eps, int fscale_log2, bool priv,
+               HostBins *out);
 
 }  // namespace pc

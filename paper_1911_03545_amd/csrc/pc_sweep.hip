@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pc_common.h"
+#include "pc_frame.h"
 #include "pc_launch.h"
 
 namespace pc {
@@ -626,7 +627,7 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
 template <int M, int W, bool TRI, bool T16, bool UNC>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
-                                         unsigned dcode, unsigned &rechecks)
+                                         unsigned dcode, unsigned &rechecks, int jx, int jy)
 {
     const float Lf = a.Lf32;
     const unsigned cx = dcode & 3u, cy = (dcode >> 2) & 3u, cz = (dcode >> 4) & 3u;
@@ -634,8 +635,20 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     const float Dy = cy == PC_D_PLUS ? Lf : (cy == PC_D_MINUS ? -Lf : 0.0f);
     const float Dz = cz == PC_D_PLUS ? Lf : (cz == PC_D_MINUS ? -Lf : 0.0f);
     // inactive lanes sit far away: their separations overflow to +inf
-    const float ax = act ? a.X1[i] + Dx : 3.0e30f;
-    const float ay = act ? a.Y1[i] + Dy : 3.0e30f;
+    float ax, ay;
+    if (a.xy_local) {
+        // the lane's point (shifted by the item's periodic offset) in the
+        // frame of the j column, from its binary64 coordinates, rounded once
+        ax = act ? (float)((a.x1[i] + dval(cx, a.L) - col_centre(a.glo[0], a.gw[0], jx)) *
+                           a.fscale)
+                 : 3.0e30f;
+        ay = act ? (float)((a.y1[i] + dval(cy, a.L) - col_centre(a.glo[1], a.gw[1], jy)) *
+                           a.fscale)
+                 : 3.0e30f;
+    } else {
+        ax = act ? a.X1[i] + Dx : 3.0e30f;
+        ay = act ? a.Y1[i] + Dy : 3.0e30f;
+    }
     const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
     // second-catalogue points are wave-uniform: read them through the scalar
     // cache (the arrays are not written during the sweep)
@@ -677,7 +690,11 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
         }
         return;
     } else {
-        const float az = act ? a.Z1[i] + Dz : 3.0e30f;
+        float az;
+        if (a.xy_local)
+            az = act ? (float)((a.z1[i] + dval(cz, a.L) - a.glo[2]) * a.fscale) : 3.0e30f;
+        else
+            az = act ? a.Z1[i] + Dz : 3.0e30f;
         for (; j + CH <= j1; j += CH) {
             float xs[CH], ys[CH], zs[CH];
             double ws[CH];
@@ -957,12 +974,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         const bool act = lane < ni;
         const int i = it.i0 + (act ? lane : 0);
         if constexpr (P32) {
+            // the item's j column (every j point of an item lies in one column)
+            int jx = 0, jy = 0;
+            if (a.xy_local)
+                cell_column(__builtin_amdgcn_readfirstlane(((const KCONST int32_t *)a.cs2)[it.j0]),
+                            a.gnx, a.gny, a.gnz, &jx, &jy);
             if (tri)
                 item_f32<M, W, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
-                                               rechecks);
+                                               rechecks, jx, jy);
             else
                 item_f32<M, W, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
-                                                rechecks);
+                                                rechecks, jx, jy);
         } else {
             if (tri)
                 item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);

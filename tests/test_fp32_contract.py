@@ -1,0 +1,288 @@
+"""The float32 + binary64-recheck contract, validated on the CPU.
+
+The float32 sweep may decide a pair only when its float32 separation lies
+outside the decision band [lo_k, hi_k] of every squared edge E_k; inside a
+band the pair is re-evaluated in binary64.  The bands come from a proven
+bound B(s) on |s32 - s64| (cf_fp32_bands_axes).  These tests emulate the
+sweep's float32 arithmetic exactly -- the column-local x and y frames of 3-D
+grids, z in the domain frame, the periodic offset of the work item, the
+power-of-two coordinate scale, one float32 multiply and two fused
+multiply-adds with a single rounding each -- on more than 10^8 pairs (random
+pairs over the whole reach, periodic wraps, and adversarial pairs within a
+few ulps of every edge), and check that
+
+* the largest ratio |s32 - s64| / B(s64) is below 1 for the raw bound (the
+  library adds a 1.25 safety factor on top), and is reported;
+* no pair is decided the wrong way against any edge: s32 < lo_k implies
+  s64 < E_k and s32 > hi_k implies s64 > E_k;
+
+for DD(r) (3 axes), rp^2 (2 axes) and squared chords of unit vectors
+(3 axes, no box), and that the fixed-point line-of-sight coordinate of the
+float32 DD(rp, pi) path stays within 1.5 quanta of the exact |dz|, below the
+2-quanta margin inside which pi bins are re-decided in binary64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_1911_03545_amd as pc
+import synth
+
+U32 = 2.0 ** -24
+SAFETY = 1.25
+
+
+def fma32(a, b, c):
+    """Fused multiply-add of float32 arrays with one rounding to float32.
+
+    a * b is exact in binary64 (24 + 24 bits); p + c is computed in binary64
+    with its exact residual (two-sum).  Rounding the binary64 sum to float32
+    can only differ from rounding the exact sum when the binary64 sum sits
+    exactly half-way between two float32 values while the residual is not
+    zero; the result is then the float32 neighbour on the residual's side."""
+    p = a.astype(np.float64) * b.astype(np.float64)
+    c64 = c.astype(np.float64)
+    r = p + c64
+    bb = r - p
+    err = (p - (r - bb)) + (c64 - bb)
+    f = r.astype(np.float32)
+    f64 = f.astype(np.float64)
+    up = np.nextafter(f, np.float32(np.inf))
+    dn = np.nextafter(f, np.float32(-np.inf))
+    # r exactly half-way between f and its neighbour on r's side
+    tie_hi = (r > f64) & (r - f64 == (up.astype(np.float64) - f64) / 2)
+    tie_lo = (r < f64) & (f64 - r == (f64 - dn.astype(np.float64)) / 2)
+    # the exact value is beyond the midpoint, away from f, on err's side
+    f = np.where(tie_hi & (err > 0), up, f)
+    f = np.where(tie_lo & (err < 0), dn, f)
+    return f.astype(np.float32)
+
+
+def test_fma32_emulation_exact():
+    """The emulated fused multiply-add equals exact rational arithmetic
+    rounded once (checked with Fraction on random and tie-prone inputs)."""
+    from fractions import Fraction
+    rng = synth.rng_for(900)
+    a = rng.normal(size=4000).astype(np.float32)
+    b = rng.normal(size=4000).astype(np.float32)
+    c = (rng.normal(size=4000) * 10.0 ** rng.integers(-8, 8, 4000)).astype(np.float32)
+    # products exactly half-way between two float32 values, plus addends that
+    # are zero (a true tie), representable next to it, or far below binary64's
+    # resolution there (the binary64 sum is the midpoint, the exact one not)
+    a[:2000] = np.float32(1.0) + np.float32(2.0 ** -12)
+    b[:2000] = np.float32(1.0) + np.float32(2.0 ** -12)
+    c[:1000] = (np.float32(2.0 ** -30) * rng.integers(-4, 4, 1000)).astype(np.float32)
+    c[1000:2000] = (np.float32(2.0 ** -62) * rng.integers(-4, 4, 1000)).astype(np.float32)
+    got = fma32(a, b, c)
+    for k in range(a.size):
+        exact = Fraction(float(a[k])) * Fraction(float(b[k])) + Fraction(float(c[k]))
+        want = np.float32(float(exact))     # float() rounds the rational once to binary64
+        # binary64 rounding of the exact value cannot create a float32 tie
+        # here except at the constructed midpoints: settle those exactly
+        lo = np.float32(want)
+        cands = [np.nextafter(lo, np.float32(-np.inf)), lo, np.nextafter(lo, np.float32(np.inf))]
+        best = min(cands, key=lambda v: (abs(Fraction(float(v)) - exact),
+                                         int(np.float32(v).view(np.int32)) & 1))
+        assert got[k] == best, (k, a[k], b[k], c[k], got[k], best)
+
+
+def plan(L, reach, k=1):
+    return pc.plan_grid_refined(None, None, L, reach, reach, 32, k, True)
+
+
+def frames(p, g, L):
+    """Column centres of every point (as the gridding assigns columns)."""
+    idx = []
+    for a in range(2):
+        i = np.floor((p[:, a] - g["lo"][a]) * g["inv_width"][a]).astype(np.int64)
+        idx.append(np.clip(i, 0, g["n"][a] - 1))
+    cx = g["lo"][0] + (idx[0] + 0.5) * g["width"][0]
+    cy = g["lo"][1] + (idx[1] + 0.5) * g["width"][1]
+    return cx, cy
+
+
+def emulate_r(pi, pj, g, L, c, ndim):
+    """float32 s of the sweep for pairs (pi, pj): x, y in the j column's
+    frame with the periodic offset on the i point, z in the domain frame."""
+    cx, cy = frames(pj, g, L)
+    d = pi - pj
+    D = np.where(d > L / 2, -L, np.where(d <= -L / 2, L, 0.0)) if L > 0 else np.zeros_like(d)
+    ax = (((pi[:, 0] + D[:, 0]) - cx) * c).astype(np.float32)
+    ay = (((pi[:, 1] + D[:, 1]) - cy) * c).astype(np.float32)
+    bx = ((pj[:, 0] - cx) * c).astype(np.float32)
+    by = ((pj[:, 1] - cy) * c).astype(np.float32)
+    dx = ax - bx
+    dy = ay - by
+    t = dx * dx
+    t = fma32(dy, dy, t)
+    if ndim == 2:
+        return t
+    az = (((pi[:, 2] + D[:, 2]) - g["lo"][2]) * c).astype(np.float32)
+    bz = ((pj[:, 2] - g["lo"][2]) * c).astype(np.float32)
+    dz = az - bz
+    return fma32(dz, dz, t)
+
+
+def exact_s(pi, pj, L, ndim):
+    """The binary64 definition: Code 3's wrap, ((dx^2 + dy^2) + dz^2)."""
+    d = pi - pj
+    if L > 0:
+        d = np.where(d > 0.5 * L, d - L, d)
+        d = np.where(d <= -0.5 * L, d + L, d)
+    s = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+    if ndim == 3:
+        s = s + d[:, 2] * d[:, 2]
+    return s
+
+
+def draw_pairs(rng, n, L, reach, lo=0.0, hi=None, radial=None):
+    """n pairs: i uniform in the box, j at a separation up to 1.05 reach in
+    a random direction (or at the given radial distances), wrapped."""
+    hi = L if hi is None else hi
+    pi = rng.uniform(lo, hi, size=(n, 3))
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    r = rng.uniform(0.0, 1.05 * reach, n) if radial is None else radial
+    pj = pi + u * r[:, None]
+    if L > 0:
+        pj = np.mod(pj, L)
+    else:
+        pj = np.clip(pj, lo, hi)
+    return pi, pj
+
+
+def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats):
+    s64 = exact_s(pi, pj, L, ndim)
+    s32 = emulate_r(pi, pj, g, L, c, ndim).astype(np.float64) / (c * c)
+    E = edges * edges
+    lo, hi = pc.fp32_bands_axes(E, ndim, axis_eps, coord_scale)
+    for k in range(E.size):
+        if E[k] == 0.0:
+            continue
+        below = s32 < lo[k]
+        above = s32 > hi[k]
+        assert np.all(s64[below] < E[k]), ("decided below but not", k)
+        assert np.all(s64[above] > E[k]), ("decided above but not", k)
+    # the bound at each pair's own separation
+    ok = s64 > 0
+    blo, bhi = pc.fp32_bands_axes(s64[ok], ndim, axis_eps, coord_scale)
+    half = np.minimum(s64[ok] - blo.astype(np.float64), bhi.astype(np.float64) - s64[ok])
+    err = np.abs(s32[ok] - s64[ok])
+    ratio_band = err / half
+    stats["pairs"] += int(s64.size)
+    stats["max_ratio_band"] = max(stats["max_ratio_band"], float(ratio_band.max()))
+    stats["max_ratio_raw"] = max(stats["max_ratio_raw"], float((ratio_band * SAFETY).max()))
+
+
+def scale_for(edges, S, cells=40960):
+    """The power of two the library applies to float32 coordinates: the top
+    band just below the last linear table cell."""
+    E = edges[-1] ** 2
+    lo, hi = pc.fp32_bands(np.array([E]), 3, S)
+    m = 0
+    while math.ldexp(float(hi[0]), 2 * m) >= cells - 1:
+        m -= 1
+    while math.ldexp(float(hi[0]), 2 * (m + 1)) < cells - 1:
+        m += 1
+    return 2.0 ** m
+
+
+@pytest.mark.parametrize("case", ["r_box420", "r_box1100_k2", "rp_box1000", "chord_open"])
+def test_fp32_bound_holds_on_1e8_pairs(case):
+    rng = synth.rng_for(hash(case) % (1 << 31))
+    stats = {"pairs": 0, "max_ratio_band": 0.0, "max_ratio_raw": 0.0}
+    if case == "r_box420":
+        L, reach, k, ndim = 420.0, 25.0, 1, 3
+        edges = synth.log_edges(0.1, 25.0, 20)
+        npairs = 40_000_000
+    elif case == "r_box1100_k2":
+        L, reach, k, ndim = 1100.0, 50.0, 2, 3
+        edges = synth.log_edges(0.1, 50.0, 25)
+        npairs = 20_000_000
+    elif case == "rp_box1000":
+        L, reach, k, ndim = 1000.0, 25.0, 1, 2
+        edges = synth.log_edges(0.1, 25.0, 20)
+        npairs = 20_000_000
+    else:   # unit vectors, 3-D chord grid, no box
+        L, reach, k, ndim = 0.0, 2 * math.sin(math.radians(5.0)), 1, 3
+        edges = 2 * np.sin(np.radians(synth.log_edges(0.01, 10.0, 20)) / 2)
+        npairs = 20_000_000
+    if L > 0:
+        g = plan(L, reach, k)
+        S = L
+    else:
+        g = pc.plan_grid_refined([-1.0, -1.0, -1.0], [1.0, 1.0, 1.0], 0.0, reach, reach, 32,
+                                 k, True)
+        S = 2.0
+    # the library's per-axis rounding bounds for column-local x and y (the
+    # lane within k + 1/2 widths of the j column's centre, the j point within
+    # half a width, each rounded once) and box-frame z
+    def frame_eps(a_max, b_max):
+        return U32 * (a_max + b_max) * (1 + 2.0 ** -20) + 8 * 2.0 ** -53 * S
+    kk = g["k"]
+    axis_eps = [frame_eps((kk + 0.5) * g["width"][0], 0.5 * g["width"][0]),
+                frame_eps((kk + 0.5) * g["width"][1], 0.5 * g["width"][1]),
+                frame_eps(S + reach, S)]
+    for c in (1.0, scale_for(edges, S)):
+        done = 0
+        while done < npairs // 2:
+            n = 2_000_000
+            if L > 0:
+                pi, pj = draw_pairs(rng, n, L, reach)
+            else:
+                pi = rng.normal(size=(n, 3))
+                pi /= np.linalg.norm(pi, axis=1)[:, None]
+                pj = pi + rng.normal(size=(n, 3)) * (reach / 2)
+                pj /= np.linalg.norm(pj, axis=1)[:, None]
+            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats)
+            done += n
+        # adversarial: separations within a few ulps of every edge
+        e_rep = np.repeat(edges[edges > 0], 20000)
+        jitter = e_rep * (1.0 + rng.integers(-8, 9, e_rep.size) * 2.0 ** -52)
+        if L > 0:
+            pi, pj = draw_pairs(rng, e_rep.size, L, reach, radial=jitter)
+            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats)
+    print(case, stats)
+    assert stats["pairs"] >= npairs
+    assert stats["max_ratio_raw"] < 1.0, stats
+    assert stats["max_ratio_band"] < 1.0 / SAFETY, stats
+
+
+def test_fixed_point_pi_within_margin():
+    """Fixed-point z of the float32 DD(rp, pi) path: Zq = round((z - lo)
+    2^k / dpi) as an integer and the periodic offset round(L 2^k / dpi); the
+    integer |Zq_i + D - Zq_j| differs from the exact |dz| 2^k / dpi by at most
+    1.5 quanta (three roundings to an integer), inside the 2-quanta margin,
+    at the benchmark's boxes and on pairs placed on the pi edges."""
+    rng = synth.rng_for(901)
+    worst = 0.0
+    for L, pimax, npi in ((420.0, 40.0, 40), (1000.0, 40.0, 40), (1100.0, 40.0, 13)):
+        dpi = pimax / npi
+        # the library's choice: as many quanta per pi bin as keep every value
+        # below 2^29
+        k = 24
+        while k >= 4 and math.ldexp(L / dpi, k) > 2.0 ** 29:
+            k -= 1
+        inv = math.ldexp(1.0, k) / dpi
+        zq_L = round(L * inv)
+        n = 4_000_000
+        zi = rng.uniform(0.0, L, n)
+        dz = rng.uniform(-pimax * 1.1, pimax * 1.1, n)
+        # and differences exactly on the pi edges and one ulp beside them
+        q = np.arange(npi + 1) * dpi
+        on = np.repeat(q, 2000)
+        on = on * (1.0 + rng.integers(-1, 2, on.size) * 2.0 ** -52)
+        dz[: on.size] = on * np.where(rng.random(on.size) < 0.5, -1.0, 1.0)
+        zj = np.mod(zi - dz, L)
+        d = zi - zj
+        D = np.where(d > L / 2, -L, np.where(d <= -L / 2, L, 0.0))
+        Zi = np.rint(zi * inv).astype(np.int64)
+        Zj = np.rint(zj * inv).astype(np.int64)
+        Dq = np.where(D > 0, zq_L, np.where(D < 0, -zq_L, 0))
+        got = np.abs(Zi + Dq - Zj).astype(np.float64)
+        exact = np.abs(d + D) * inv
+        err = np.abs(got - exact)
+        worst = max(worst, float(err.max()))
+    print("fixed-point pi: worst error", worst, "quanta")
+    assert worst <= 1.5 + 1e-6
