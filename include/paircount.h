@@ -168,7 +168,27 @@ typedef struct cf_options {
                                    for the overflow guard of section "Finding
                                    and updating the histogram bins".  0: the
                                    default bound.                              */
-    int32_t reserved[2];
+    int32_t deterministic_weights; /* 1: sum the pair weights (section 2.1,
+                                   weight_func) in exact fixed point instead of
+                                   binary64 atomics: wsum is then the exact sum
+                                   of the binary64 pair weights, rounded once
+                                   (ties to even), identical in every run and
+                                   on every device.  Every pair weight must be
+                                   a multiple of one power of two 2^Q (found
+                                   from the weights: the lowest set bits of
+                                   their significands, and for products the
+                                   ulp of the smallest product) with |w_ij| <
+                                   2^(Q + 94) and Q >= -1022, else CF_EINVAL:
+                                   products of weights that span less than
+                                   2^23 in magnitude (float32 values) or 2^20
+                                   (any binary64 values) fit; sums span far
+                                   wider ranges.
+                                   The self-pair weights (first edge zero) are
+                                   summed the same way; the mean separation's
+                                   numerator stays a binary64 sum.  0: binary64
+                                   atomics (the default; sums then agree with
+                                   the exact sum to about 1e-12 relative).     */
+    int32_t reserved;
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
                                    in each bin (r, rp, or theta in degrees),
@@ -430,6 +450,14 @@ cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32_t ndim,
 cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, int32_t ndim,
                              const double *axis_eps, double coord_scale, float *lo,
                              float *hi);
+
+/* Host-only: the exact sum of n values p[k], each an integer multiple of 2^q
+   with |p[k]| < 2^(q + 94), rounded once to binary64 (ties to even), through
+   the same fixed-point arithmetic as cf_options.deterministic_weights (three
+   signed 32-bit limbs per value, int64 limb sums, a 192-bit total).
+   CF_EINVAL for a value off the grid or too large, or q outside
+   [-1022, 900].  out: one double. */
+cf_status cf_fixed_sum(const double *p, int64_t n, int32_t q, double *out);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,7 @@ EXPORTED_SYMBOLS = (
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
     "cf_plan_grid", "cf_plan_grid_ex", "cf_plan_sky_grid", "cf_fp32_bands",
     "cf_fp32_bands_axes",
+    "cf_fixed_sum",
 )
 
 
@@ -65,7 +66,8 @@ class cf_options(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("weight_type", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
                 ("xy_refine", ctypes.c_int32), ("radec_on_device", ctypes.c_int32),
-                ("flush_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("flush_pairs", ctypes.c_int32), ("deterministic_weights", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
                 ("ravg", ctypes.c_void_p)]
 
 
@@ -187,6 +189,8 @@ def load_library(path: str = LIB_PATH):
     lib.cf_fp32_bands.restype = ctypes.c_int
     lib.cf_fp32_bands_axes.argtypes = [vp, i32, i32, vp, dbl, vp, vp]
     lib.cf_fp32_bands_axes.restype = ctypes.c_int
+    lib.cf_fixed_sum.argtypes = [vp, ctypes.c_int64, i32, vp]
+    lib.cf_fixed_sum.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -286,6 +290,18 @@ def fp32_bands_axes(edges_sq, ndim: int, axis_eps, coord_scale: float):
     if st != CF_OK:
         raise PairCountError(st, "cf_fp32_bands_axes failed")
     return lo, hi
+
+
+def fixed_sum(values, q: int) -> float:
+    """Host-only exact sum of multiples of 2^q through the fixed-point
+    arithmetic of the deterministic weight sums, rounded once."""
+    lib = load_library()
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    out = ctypes.c_double(0.0)
+    st = lib.cf_fixed_sum(v.ctypes.data if v.size else None, v.size, int(q), ctypes.byref(out))
+    if st != CF_OK:
+        raise PairCountError(st, "cf_fixed_sum failed")
+    return out.value
 
 
 def _is_torch(a) -> bool:

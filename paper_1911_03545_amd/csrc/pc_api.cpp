@@ -45,8 +45,10 @@ enum {
     M_SIZES = 40,       // 2 int32: work items, blocks (copied by the finalize kernel)
     M_FLUSH = 48,       // unsigned: mid-sweep histogram flushes
     M_OUT6 = 64,        // 6 doubles
+    M_WFIX = 128,       // pc_wfixed: grid of the fixed-point weight sums
     M_SIZE = 256
 };
+static_assert(M_WFIX + sizeof(pc::pc_wfixed) <= M_SIZE, "misc layout");
 
 }  // namespace
 
@@ -655,6 +657,9 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     // the sweep carries weights when the caller gives them or asks for the
     // mean separation (unit weights then, whose sums are the counts)
     const bool weighted = user_w || want_ravg;
+    // exact fixed-point weight sums (unit weights, for the mean separation
+    // alone, sum exactly in binary64 anyway)
+    const bool wfixed = user_w && opt.deterministic_weights != 0;
     const int64_t nbt = (int64_t)nb * npi;
     if (nbt > PC_MAX_BINS_TOTAL / (want_ravg ? 3 : (weighted ? 2 : 1)))
         return fail(c, CF_EINVAL, "too many output bins (%lld)", (long long)nbt);
@@ -886,10 +891,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         pc::frame_eps(scale + reach_z, scale, scale)};
     // batches: private per-wave histograms, flushed per catalogue
     const bool priv = ncat > 1;
-    int fscale_log2 = 0;
-    if (fp32 && (rc = pc::fp32_scale_log2(metric, lin.data(), nb, scale, priv, &fscale_log2)))
+    double fscale = 1.0;
+    if (fp32 && (rc = pc::fp32_scale(metric, lin.data(), nb, scale, priv, &fscale)))
         return fail(c, (cf_status)rc, "float32 scaling failed");
-    g.fscale = std::ldexp(1.0, fscale_log2);
+    g.fscale = fscale;
     record(c, timing, 1);
 
     // ---- work-list and sweep buffers, cleared by one kernel ahead of the
@@ -906,12 +911,12 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
                                         std::max<int64_t>(maxblocks, ncol),
                                         (int64_t)ncat * g.ncell)))) ||
         (st2 = ensure(c, B_HIST, sizeof(unsigned long long) * nout)) ||
-        (st2 = ensure(c, B_WHIST, sizeof(double) * nout)) ||
+        (st2 = ensure(c, B_WHIST, (wfixed ? 24 : 8) * nout)) ||
         (st2 = ensure(c, B_OUTC, sizeof(unsigned long long) * nout)) ||
         (st2 = ensure(c, B_OUTW, sizeof(double) * nout)) ||
         (want_ravg && (st2 = ensure(c, B_RHIST, sizeof(double) * nout))) ||
         (want_ravg && (st2 = ensure(c, B_OUTR, sizeof(double) * nout))) ||
-        (st2 = ensure(c, B_WSQ, sizeof(double) * (size_t)ncat)) ||
+        (st2 = ensure(c, B_WSQ, (wfixed ? 24 : 8) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CTRS, sizeof(int32_t) * PC_STREAMS * PC_STREAM_STRIDE)))
         return st2;
     {
@@ -926,7 +931,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         zb[nz++] = sizeof(unsigned long long) * nout;
         if (weighted) {
             zp[nz] = c->buf[B_WHIST].p;
-            zb[nz++] = sizeof(double) * nout;
+            zb[nz++] = (wfixed ? 24 : 8) * nout;
         }
         if (want_ravg) {
             zp[nz] = c->buf[B_RHIST].p;
@@ -943,11 +948,19 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         (st2 = grid_side(c, s2, cats2_dev, weighted, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2,
                          B_YD2, B_ZD2, B_WD2, B_CS2, flags)))
         return st2;
+    // fixed-point weight sums: the grid 2^Q of this call's pair weights
+    pc::pc_wfixed *wfx = wfixed ? (pc::pc_wfixed *)(misc(c) + M_WFIX) : nullptr;
+    if (wfixed) {
+        HIPCHK(pc::launch_wfixed_scan(c->stream, s1.ntot, dptr<double>(c, B_WD1), 0, wfx));
+        if (!autocorr)
+            HIPCHK(pc::launch_wfixed_scan(c->stream, s2.ntot, dptr<double>(c, B_WD2), 1, wfx));
+        HIPCHK(pc::launch_wfixed_plan(c->stream, opt.weight_type, autocorr ? 0 : 1, wfx, flags));
+    }
     // the bin description is built on the host while the gridding kernels run
     pc::HostBins hb;
     // on-sky pairs bin (rp, pi) like the Cartesian statistic
     rc = pc::build_bins(sky ? PC_METRIC_RPPI : metric, fp32, lin.data(), nb, pimax, npi, scale,
-                        g.xy_local ? axis_eps : nullptr, fscale_log2, priv, &hb);
+                        g.xy_local ? axis_eps : nullptr, fscale, priv, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
     if (g.zq_shift > 0) {
@@ -1071,7 +1084,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.q = (const double *)(bb + hb.lay.q);
     a.tbl = (const uint16_t *)(bb + hb.lay.tbl);
     a.g_hist = dptr<unsigned long long>(c, B_HIST);
-    a.g_whist = weighted ? dptr<double>(c, B_WHIST) : nullptr;
+    a.g_whist = (weighted && !wfixed) ? dptr<double>(c, B_WHIST) : nullptr;
+    a.wfixed = wfixed ? 1 : 0;
+    a.wfx = wfx;
+    a.g_wfix = wfixed ? dptr<unsigned long long>(c, B_WHIST) : nullptr;
     a.g_rhist = want_ravg ? dptr<double>(c, B_RHIST) : nullptr;
     a.ravg = want_ravg ? (theta ? 2 : 1) : 0;
     a.wtype = opt.weight_type;
@@ -1116,8 +1132,12 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.flush_at = priv ? 0x7fffffffull : 0x7fffffffull / (unsigned)waves;
     if (opt.flush_pairs > 0)
         a.flush_at = std::min<unsigned long long>(a.flush_at, (unsigned long long)opt.flush_pairs);
-    const int slot_bytes = 4 + (weighted ? 8 : 0) + (want_ravg ? 8 : 0);
+    const int slot_bytes = 4 + (weighted ? (wfixed ? 24 : 8) : 0) + (want_ravg ? 8 : 0);
     while (priv && copies > 1 && waves * copies * a.rep_stride * slot_bytes > 28 * 1024)
+        copies /= 2;
+    // fixed-point sums take three times the weight area: fewer shared copies
+    // where they would crowd the LDS
+    while (wfixed && !priv && copies > 1 && copies * a.rep_stride * slot_bytes > 64 * 1024)
         copies /= 2;
     a.copies = copies;
     // dynamic LDS layout
@@ -1137,12 +1157,16 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.hist_stride = (int32_t)(copies * a.rep_stride);
     a.o_hist = take(4 * sets * a.hist_stride);
     a.whist_stride = weighted ? (int32_t)(copies * a.rep_stride) : 0;
-    a.o_whist = take(weighted ? 8 * sets * a.whist_stride : 0);
+    a.wlimb = wfixed ? sets * a.whist_stride : 0;
+    a.o_whist = take(weighted ? 8 * (wfixed ? 3 : 1) * sets * a.whist_stride : 0);
     a.o_rhist = take(want_ravg ? 8 * sets * a.whist_stride : 0);
     a.lds_bytes = off;
     // static LDS of the sweep: the lookup table
     const int tbl_bytes = priv ? PC_TBL_PRIV_BYTES
-                               : (PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX : 2 * PC_TBL16_MAX);
+                               : (fp32 && !hb.hdr.tbl_wide)
+                                     ? PC_TBL_PK_CELLS
+                                     : (PC_TBL8_MAX > 2 * PC_TBL16_MAX ? PC_TBL8_MAX
+                                                                       : 2 * PC_TBL16_MAX);
     if (off + tbl_bytes > 160 * 1024)
         return fail(c, CF_EINVAL, "bin configuration needs too much LDS (%d bytes)", off);
 
@@ -1169,8 +1193,13 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     c->stats.sweep_workgroups = nwg;
     c->stats.hist_copies = copies;
     double *wsq = nullptr;
-    if (weighted && autocorr && hb.hdr.e0_zero)
-        wsq = dptr<double>(c, B_WSQ);
+    unsigned long long *wsq_fix = nullptr;
+    if (weighted && autocorr && hb.hdr.e0_zero) {
+        if (wfixed)
+            wsq_fix = dptr<unsigned long long>(c, B_WSQ);
+        else
+            wsq = dptr<double>(c, B_WSQ);
+    }
     unsigned long long *outc = opt.output_on_device ? (unsigned long long *)counts
                                                     : dptr<unsigned long long>(c, B_OUTC);
     double *outw = (wsum && user_w) ? (opt.output_on_device ? wsum : dptr<double>(c, B_OUTW))
@@ -1185,14 +1214,20 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         HIPCHK(pc::launch_wsq(c->stream, ncat, g.ncell, start1, dptr<double>(c, B_WD1),
                               opt.weight_type, wsq));
     }
+    if (wsq_fix) {
+        HIPCHK(pc::launch_zero(c->stream, wsq_fix, 24 * (size_t)ncat));
+        HIPCHK(pc::launch_wsq_fixed(c->stream, ncat, g.ncell, start1, dptr<double>(c, B_WD1),
+                                    opt.weight_type, wfx, wsq_fix));
+    }
     double *outr = want_ravg ? (opt.output_on_device ? opt.ravg : dptr<double>(c, B_OUTR))
                              : nullptr;
     // without weights the weight sums are zero
     if (wsum && !user_w && opt.output_on_device)
         HIPCHK(pc::launch_zero(c->stream, wsum, sizeof(double) * nout));
     HIPCHK(pc::launch_finalize(c->stream, ncat, (int32_t)nbt, autocorr ? 1 : 0, hb.hdr.e0_zero,
-                               cats1_dev, a.g_hist, a.g_whist, a.g_rhist, wsq, outc, outw,
-                               outr, dptr<int32_t>(c, B_IOFF) + maxblocks, nblocks_dev,
+                               cats1_dev, a.g_hist, a.g_whist, a.g_rhist, wsq, a.g_wfix,
+                               wsq_fix, wfx, outc, outw, outr,
+                               dptr<int32_t>(c, B_IOFF) + maxblocks, nblocks_dev,
                                (int32_t *)(misc(c) + M_SIZES)));
     char *hp = pin + p_out;
     HIPCHK(hipMemcpyAsync(pin + p_misc, misc(c), M_SIZE, hipMemcpyDeviceToHost, c->stream));
@@ -1226,6 +1261,11 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (hflags & PC_FLAG_UNIT)
         return fail(c, CF_EINVAL,
                     "the angular grid needs unit vectors (squared norm within 2^-20 of 1)");
+    if (hflags & PC_FLAG_WFIXED)
+        return fail(c, CF_EINVAL,
+                    "deterministic_weights: the weights span too wide a range for exact "
+                    "fixed-point sums (every pair weight must be a multiple of one power of "
+                    "two 2^Q, Q >= -1022, and below 2^(Q + 94))");
     int32_t sizes[2];
     memcpy(sizes, hm + M_SIZES, sizeof(sizes));
     if (async_items && (hflags & PC_FLAG_ITEMS)) {
@@ -1355,6 +1395,8 @@ cf_status replay(cf_ctx *c, uint64_t *counts, double *wsum, const cf_options &op
         return fail(c, CF_ERANGE, "periodic coordinate outside [0, boxsize]");
     if (hflags & PC_FLAG_WEIGHT)
         return fail(c, CF_EINVAL, "non-finite weight");
+    if (hflags & PC_FLAG_WFIXED)
+        return fail(c, CF_EINVAL, "deterministic_weights: the weights span too wide a range");
     if (!opt.output_on_device) {
         memcpy(counts, pin + c->g_out, sizeof(uint64_t) * c->g_nout);
         if (wsum && c->g_wsum)

@@ -11,6 +11,10 @@
 #define PC_TBL16_MAX 20480     // 16-bit lookup-table entries (more bins)
 #endif
 #define PC_TBL8_MAX_BINS 125
+// cells of the float32 path's rounding-key table: key = round(s * 32767) for
+// a scaled s in [0, 1] (one v_cvt_pknorm_i16_f32: clamp, scale, round to
+// nearest); used with byte entries by the shared-histogram sweeps
+#define PC_TBL_PK_CELLS 32768
 // lookup-table bytes of the private-histogram (batched) sweep
 #define PC_TBL_PRIV_BYTES 16384
 // The sweep's work items are dealt to PC_STREAMS streams (contiguous item
@@ -83,7 +87,7 @@ struct pc_grid {
     int32_t zq_shift;    // > 0: float32 rp/pi path stores z as fixed point (below)
     double boxsize;
     int64_t ncell;
-    double fscale;       // power of two applied to the float32 coordinates
+    double fscale;       // scale applied to the float32 coordinates
     // fixed-point z of the float32 rp/pi path: Zq = round((z - lo_z) * zq_inv)
     // + 2^30 as uint32 bits, one pi bin = 2^zq_shift quanta
     double zq_inv;
@@ -147,7 +151,7 @@ struct pc_bins {
     int32_t e0_zero;     // first r / rp edge is exactly zero
     int32_t tbl_wide;    // 0: byte entries, 1: 16-bit entries
     uint32_t tbl_base;   // float bit pattern subtracted before the shift
-    int32_t fscale_log2; // float32 path: coordinates scaled by 2^fscale_log2
+    int32_t fscale_log2; // unused (0)
     float s_top;         // float32 prefilter: candidate only if s32 <= s_top
     float pi_top;        // rppi: candidate only if pi32 <= pi_top
     float inv_dpi;       // rppi: npi / pimax in float32
@@ -159,9 +163,12 @@ struct pc_bins {
     // rppi: row_w npi + 2, col0 1 (columns 0 and npi + 1 out of range)
     int32_t row_w;
     int32_t col0;
-    // lookup-table construction (done on the device): linear cells [k, k+1)
-    // (float32 path) or float-bit cells (binary64 path); out_zero: cells
-    // wholly out of range hold 0; ordered: band tops never decrease
+    // lookup-table construction (done on the device): 1: linear cells
+    // [k, k+1) (float32 path, key = floor(min(s, cells - 1))); 2: rounding
+    // cells [(k - 1/2) / 32767, (k + 1/2) / 32767) (float32 path, key =
+    // round(min(s, 1) * 32767)); 0: float-bit cells (binary64 path);
+    // out_zero: cells wholly out of range hold 0; ordered: band tops never
+    // decrease
     int32_t tbl_linear;
     int32_t tbl_out_zero;
     int32_t tbl_ordered;

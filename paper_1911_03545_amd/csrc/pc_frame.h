@@ -3,7 +3,7 @@
 //
 // On 3-D grids the float32 x and y coordinates of a point are stored relative
 // to the centre of its own column, z relative to the domain origin, all
-// scaled by the power of two g.fscale:
+// scaled by g.fscale:
 //     X = fl32((x - cx) * s),  Y = fl32((y - cy) * s),  Z = fl32((z - lo_z) * s).
 // The sweep places the i point of a work item in the frame of the item's j
 // column (plus the item's periodic offset), so a float32 difference carries

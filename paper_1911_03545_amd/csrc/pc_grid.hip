@@ -750,7 +750,17 @@ __global__ void k_build_table(pc_bins B, int nedges, const float *lo, const floa
             e = B.tbl_out_zero ? 0u : (unsigned)nedges;
         } else {
             float c_lo, c_hi;
-            if (B.tbl_linear) {
+            if (B.tbl_linear == 2) {
+                // values whose rounded key is `key`: (key -+ 1/2) / 32767, the
+                // bounds widened outward by a float32 ulp (the conversion
+                // rounds the exact product, and no float32 value gives an
+                // exact tie); the last cell takes everything above
+                const double q = 1.0 / 32767.0;
+                c_lo = key == 0 ? 0.0f : nextafterf((float)(((double)key - 0.5) * q), 0.0f);
+                c_hi = key + 1 < B.tbl_n
+                           ? nextafterf((float)(((double)key + 0.5) * q), INFINITY)
+                           : INFINITY;
+            } else if (B.tbl_linear) {
                 c_lo = (float)key;
                 c_hi = key + 1 < B.tbl_n ? nextafterf((float)(key + 1), 0.0f) : INFINITY;
             } else {

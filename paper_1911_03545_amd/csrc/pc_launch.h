@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "pc_common.h"
+#include "pc_fixed.h"
 
 namespace pc {
 
@@ -14,6 +15,7 @@ namespace pc {
 #define PC_FLAG_RADEC 8u
 #define PC_FLAG_ITEMS 16u
 #define PC_FLAG_UNIT 32u      // angular grid: a vector whose squared norm is not within 2^-20 of 1
+#define PC_FLAG_WFIXED 64u    // fixed-point weight sums: no grid holds every pair weight
 
 struct SweepArgs {
     const pc_item *items;
@@ -31,11 +33,17 @@ struct SweepArgs {
     const uint16_t *tbl;
     unsigned long long *g_hist;
     double *g_whist;
+    // fixed-point weight sums (pc_fixed.h): the LDS weight area holds three
+    // uint64 limb sums per slot, wlimb slots apart; g_wfix three words per bin
+    int32_t wfixed;
+    int32_t wlimb;
+    const pc_wfixed *wfx;
+    unsigned long long *g_wfix;
     double *g_rhist;       // sums of separation x pair weight (mean separation), or NULL
     int32_t ravg;          // 0: no mean separation; 1: distance sqrt(s);
                            // 2: angle in degrees of a squared chord s
     int32_t wtype;         // pair weight: 0 product, 1 sum
-    double sep_scale;      // float32 pass: length per float32 coordinate unit (2^-m)
+    double sep_scale;      // float32 pass: length per float32 coordinate unit (1 / fscale)
     unsigned *rq_count;   // float32 pass: pairs re-evaluated in binary64
     // a wave merges its LDS replicas into the global bins before its pending
     // pair evaluations since the last merge would exceed flush_at (so no
@@ -133,6 +141,17 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, int wmode, const S
 // weights) over the cell-ordered weights of a side
 hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
                       const double *w, int wtype, double *out);
+// Fixed-point weight sums: atomic maxima over the nonzero weights of one
+// side (side 0 or 1) into fx (zeroed first), then the grid and its checks
+// (PC_FLAG_WFIXED when the weights do not fit), then the self-pair sums
+// (three words per catalogue, zeroed first).
+hipError_t launch_wfixed_scan(hipStream_t s, int64_t n, const double *w, int side,
+                              pc_wfixed *fx);
+hipError_t launch_wfixed_plan(hipStream_t s, int wtype, int two_sided, pc_wfixed *fx,
+                              unsigned *flags);
+hipError_t launch_wsq_fixed(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
+                            const double *w, int wtype, const pc_wfixed *fx,
+                            unsigned long long *out);
 // counts (and weight sums, mean separations) of every catalogue: doubling
 // and self-pairs of autocorrelations; the mean separation is the separation
 // sum over the weight sum
@@ -140,6 +159,8 @@ hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t 
 hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
                            const double *g_whist, const double *g_rhist, const double *wsq,
+                           const unsigned long long *g_wfix,
+                           const unsigned long long *wsq_fix, const pc_wfixed *wfx,
                            unsigned long long *out_counts, double *out_wsum,
                            double *out_ravg, const int32_t *n_items_dev,
                            const int32_t *n_blocks_dev, int32_t *sizes_out);

@@ -9,6 +9,7 @@
 
 #include "../../include/paircount.h"
 #include "pc_common.h"
+#include "pc_fixed.h"
 #include "pc_plan.h"
 
 namespace pc {
@@ -396,6 +397,19 @@ static int table_cells(int nb, bool priv)
     return nb > PC_TBL8_MAX_BINS ? PC_TBL16_MAX : PC_TBL8_MAX;
 }
 
+// The float32 path of the shared-histogram sweeps with byte entries keys its
+// table by rounding: key = round(min(s, 1) * 32767) (one instruction), over
+// PC_TBL_PK_CELLS cells; the private-histogram and 16-bit tables keep the
+// linear key floor(min(s, cells - 1)).
+static bool rounding_key(int nb, bool priv) { return !priv && nb <= PC_TBL8_MAX_BINS; }
+
+// The largest scaled value the float32 key keeps apart from "above every
+// edge": below the last cell of either key.
+static double key_top(int nb, bool priv)
+{
+    return rounding_key(nb, priv) ? 32766.0 / 32767.0 : (double)(table_cells(nb, priv) - 1);
+}
+
 // Table geometry of the binary64 path: key = sat(bits(s) - base) >> sh over
 // float bit patterns (monotone for s >= 0).  The table starts one cell below
 // the first band that matters, so every value below it shares cell 0; `sh`
@@ -430,15 +444,16 @@ static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 // Pack pc_bins and its arrays for one call.  `edges` are linear (r, rp or
 // chord) edges, squared here as fl(e * e).  For rppi the pi edges are
 // q_p = p * fl(pimax / npi) (p < npi) and q_npi = pimax.
-// Power of two m for the float32 path.  The sweep works on coordinates
-// scaled by 2^m, which scales every float32 difference, square and sum by an
-// exact power of two and so changes no rounding.  m is the largest power
-// that keeps the top band below cells - 1, where cells is the length of the
-// linear lookup table: the table cell of a value s is floor(min(s, cells -
-// 1)), so every value above the top band lands in the last cell, and the top
-// band lies in [(cells - 1) / 4, cells - 1).
-int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, bool priv,
-                    int *m_out)
+// Scale c of the float32 path's coordinates (every float32 coordinate is
+// fl32(c (x - origin))).  c puts the top band just below the key's top
+// (key_top: cells - 1 for the linear key, just below 1 for the rounding
+// key), so that nearly every value above the top band -- most candidate
+// pairs -- lands in the one last cell: its table reads are then a broadcast
+// of a single LDS address.  c need not be a power of two: every float32
+// coordinate is rounded once from its binary64 scaled value either way, and
+// the decision bands are scaled by c^2 and rounded outward.
+int fp32_scale(int metric, const double *edges, int nb, double coord_scale, bool priv,
+               double *c_out)
 {
     const double E = edges[nb] * edges[nb];
     float lo, hi;
@@ -448,25 +463,22 @@ int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale,
         return rc;
     if (!(hi > 0.0f) || !std::isfinite(hi))
         return CF_EINVAL;
-    const double top = (double)(table_cells(nb, priv) - 1);
-    int m = 0;
-    while (m > -60 && std::ldexp((double)hi, 2 * m) >= top)
-        m--;
-    while (m < 60 && std::ldexp((double)hi, 2 * (m + 1)) < top)
-        m++;
+    double c = std::sqrt(key_top(nb, priv) * (1.0 - 0x1p-16) / (double)hi);
     // keep every scaled coordinate and offset a normal float32 of moderate size
-    while (m > -60 && std::ldexp(2.0 * coord_scale + 1.0, m) > 0x1p100)
-        m--;
-    *m_out = m;
+    while (c > 0x1p-60 && (2.0 * coord_scale + 1.0) * c > 0x1p100)
+        c *= 0.5;
+    if (!(c > 0.0) || !std::isfinite(c))
+        return CF_EINVAL;
+    *c_out = c;
     return CF_OK;
 }
 
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
-               int npi, double coord_scale, const double *axis_eps, int fscale_log2,
-               bool priv, HostBins *out)
+               int npi, double coord_scale, const double *axis_eps, double fscale, bool priv,
+               HostBins *out)
 {
     if (!fp32)
-        fscale_log2 = 0;
+        fscale = 1.0;
     if (nb < 1 || nb + 1 > PC_MAX_EDGES)
         return CF_EINVAL;
     if (metric == PC_METRIC_RPPI) {
@@ -513,29 +525,34 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
             fp64_bands(q.data(), nq, plo.data(), phi.data());
         }
     }
-    // float32 path: move the float bands into the scaled coordinates (exact
-    // power-of-two scaling)
-    const int m = fscale_log2;
+    // float32 path: move the float bands into the scaled coordinates (c^2
+    // for squared separations, c for the line of sight), rounded outward
     if (fp32) {
+        const double c2 = fscale * fscale;
         for (int k = 0; k < ne; k++) {
-            lo[k] = std::ldexp(lo[k], 2 * m);
-            hi[k] = std::ldexp(hi[k], 2 * m);
+            if (hi[k] < 0.0f)   // the empty band of a zero edge
+                continue;
+            lo[k] = float_down((double)lo[k] * c2);
+            hi[k] = float_up((double)hi[k] * c2);
             if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) ||
                 std::fpclassify(lo[k]) == FP_SUBNORMAL || std::fpclassify(hi[k]) == FP_SUBNORMAL)
                 return CF_EINVAL;
         }
         for (int p = 0; p < nq; p++) {
-            plo[p] = std::ldexp(plo[p], m);
-            phi[p] = std::ldexp(phi[p], m);
+            if (phi[p] < 0.0f)
+                continue;
+            plo[p] = float_down((double)plo[p] * fscale);
+            phi[p] = float_up((double)phi[p] * fscale);
         }
     }
     int shift = 0;
     uint32_t base = 0, tbl_n = 0;
     const bool wide = nb > PC_TBL8_MAX_BINS;
     const bool rppi = metric == PC_METRIC_RPPI;
+    const bool pk = fp32 && rounding_key(nb, priv);
     if (fp32) {
-        tbl_n = (uint32_t)table_cells(nb, priv);
-        if (!(hi[nb] < (float)(tbl_n - 1)))
+        tbl_n = pk ? (uint32_t)PC_TBL_PK_CELLS : (uint32_t)table_cells(nb, priv);
+        if (!((double)hi[nb] < key_top(nb, priv)))
             return CF_EINVAL;
     } else {
         log_table_geometry(lo.data(), hi.data(), ne, hi[nb], (uint32_t)table_cells(nb, priv),
@@ -563,8 +580,8 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     h.e0_zero = (E[0] == 0.0) ? 1 : 0;
     h.s_top = hi[nb];
     h.pi_top = (metric == PC_METRIC_RPPI) ? phi[npi] : 0.0f;
-    h.inv_dpi = (metric == PC_METRIC_RPPI) ? std::ldexp((float)((double)npi / pimax), -m) : 0.0f;
-    h.fscale_log2 = m;
+    h.inv_dpi = (metric == PC_METRIC_RPPI) ? (float)((double)npi / pimax) : 0.0f;
+    h.fscale_log2 = 0;
     if (metric == PC_METRIC_RPPI && !fp32) {
         // (the float32 pass bins pi in fixed point and needs no margin)
         // error of rounding the binary64 |dz| to float32, in units of the pi
@@ -581,7 +598,7 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
     h.pimax = (metric == PC_METRIC_RPPI) ? pimax : 0.0;
     h.row_w = rppi ? npi + 2 : 1;
     h.col0 = rppi ? 1 : 0;
-    h.tbl_linear = fp32 ? 1 : 0;
+    h.tbl_linear = fp32 ? (pk ? 2 : 1) : 0;
     h.tbl_out_zero = rppi ? 1 : 0;
     h.tbl_ordered = ordered ? 1 : 0;
 
@@ -717,4 +734,36 @@ extern "C" cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, 
         return CF_EINVAL;
     return (cf_status)pc::fp32_bands_axes(edges_sq, nedges, ndim, axis_eps, coord_scale, lo,
                                           hi);
+}
+
+// Host twin of the fixed-point weight sums (pc_fixed.h): the same limb split,
+// limb sums and 192-bit assembly as the sweep and its merges, in one thread.
+extern "C" cf_status cf_fixed_sum(const double *p, int64_t n, int32_t q, double *out)
+{
+    if (!out || n < 0 || (n > 0 && !p) || q < -1022 || q > 900)
+        return CF_EINVAL;
+    unsigned long long acc[3] = {0ull, 0ull, 0ull};
+    unsigned long long s0 = 0, s1 = 0, s2 = 0;
+    int64_t pending = 0;
+    for (int64_t k = 0; k < n; k++) {
+        const double P = ldexp(p[k], -q);
+        if (!(fabs(P) < 0x1p94) || P != floor(P))
+            return CF_EINVAL;
+        unsigned long long l0, l1, l2;
+        pc::fixed_limbs(P, l0, l1, l2);
+        s0 += l0;
+        s1 += l1;
+        s2 += l2;
+        // merge before 2^31 limbs could overflow the int64 sums, as the
+        // sweep's flush bound does
+        if (++pending == 0x7fffffff || k + 1 == n) {
+            unsigned long long v[3];
+            pc::fixed_words((long long)s0, (long long)s1, (long long)s2, v);
+            pc::fixed_add(acc, v);
+            s0 = s1 = s2 = 0;
+            pending = 0;
+        }
+    }
+    *out = pc::fixed_to_double(acc, q);
+    return CF_OK;
 }

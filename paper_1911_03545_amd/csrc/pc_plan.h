@@ -33,11 +33,12 @@ int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *
 // b_max from the frame origin, each rounded once from binary64
 double frame_eps(double a_max, double b_max, double scale);
 // `priv`: size the lookup table for the private-histogram (batched) sweep
-int fp32_scale_log2(int metric, const double *edges, int nb, double coord_scale, bool priv,
-                    int *m);
-// axis_eps (optional, x y z): per-axis rounding bounds (else box-frame 6 u S)
+int fp32_scale(int metric, const double *edges, int nb, double coord_scale, bool priv,
+               double *c);
+// axis_eps (optional, x y z): per-axis rounding bounds (else box-frame 6 u S);
+// fscale: the float32 coordinate scale (bands are moved into it)
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax, int npi,
-               double coord_scale, const double *axis_eps, int fscale_log2, bool priv,
+               double coord_scale, const double *axis_eps, double fscale, bool priv,
                HostBins *out);
 
 }  // namespace pc

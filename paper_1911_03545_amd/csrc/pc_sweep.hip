@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "pc_common.h"
+#include "pc_fixed.h"
 #include "pc_frame.h"
 #include "pc_launch.h"
 
@@ -44,6 +45,7 @@ typedef const LDS float *lds_f32p;
 typedef const LDS double *lds_f64p;
 typedef LDS unsigned *lds_u32p;
 typedef LDS double *lds_f64wp;
+typedef LDS unsigned long long *lds_u64p;
 typedef const KCONST float *kf32p;
 typedef const KCONST double *kf64p;
 
@@ -63,6 +65,14 @@ __device__ __forceinline__ unsigned lds_take(LDS unsigned *p)
 __device__ __forceinline__ double lds_take(LDS double *p)
 {
     return __hip_atomic_exchange(p, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(LDS unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned long long lds_take(LDS unsigned long long *p)
+{
+    return __hip_atomic_exchange(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 #ifndef PC_SWEEP_THREADS
@@ -147,14 +157,36 @@ __device__ __forceinline__ double pair_weight(int wtype, double a, double b)
 
 // A lane's side of the pair weight as one fused multiply-add,
 // w_ij = fma(a, w_j, b): (w_i, 0) for products, (1, w_i) for sums.  Either
-// form rounds once, so it equals w_i * w_j or w_i + w_j.
+// form rounds once, so it equals w_i * w_j or w_i + w_j.  With fixed-point
+// weight sums (pc_fixed.h) both parts carry the grid's scale 2^-Q, which
+// commutes with the rounding, so fma gives the integer P = w_ij 2^-Q; `u`
+// (2^Q, else 1) scales it back for the mean-separation sums.
 struct LaneW {
-    double a, b;
+    double a, b, u;
 };
 
-__device__ __forceinline__ LaneW lane_weight(int wtype, double wi)
+__device__ __forceinline__ LaneW lane_weight(const SweepArgs &a, double wi)
 {
-    return wtype == 1 ? LaneW{1.0, wi} : LaneW{wi, 0.0};
+    double sc = 1.0, u = 1.0;
+    if (a.wfixed) {
+        sc = a.wfx->scale;
+        u = a.wfx->unscale;
+    }
+    return a.wtype == 1 ? LaneW{sc, wi * sc, u} : LaneW{wi * sc, 0.0, u};
+}
+
+// Exact fixed-point add of a scaled pair weight P (an integer, |P| < 2^94):
+// its three signed limbs (magnitudes below 2^32) go to three int64 LDS sums,
+// wlimb slots apart.  A slot receives at most 2^31 adds between merges (the
+// flush bound), so every limb sum stays below 2^63 in magnitude.
+__device__ __forceinline__ void add_fixed(const SweepArgs &a, lds_f64wp whb, int slot, double P)
+{
+    unsigned long long l0, l1, l2;
+    fixed_limbs(P, l0, l1, l2);
+    lds_u64p u = (lds_u64p)whb + slot;
+    lds_add(u, l0);
+    lds_add(u + a.wlimb, l1);
+    lds_add(u + 2 * a.wlimb, l2);
 }
 
 // Separation reported by the mean-separation output, from the squared
@@ -170,10 +202,11 @@ __device__ __forceinline__ double sep_value(int kind, double s)
 // unit is `scale` in length).
 __device__ __forceinline__ double sep_value_f32(int kind, float s, double scale)
 {
-    const float c = sqrtf(s) * (float)scale;   // scale is a power of two
+    // (scale need not be a power of two: the product is taken in binary64)
+    const double c = (double)sqrtf(s) * scale;
     if (kind == 1)
-        return (double)c;
-    return (double)(2.0f * asinf(0.5f * c)) * (180.0 / M_PI);
+        return c;
+    return (double)(2.0f * asinf(0.5f * (float)c)) * (180.0 / M_PI);
 }
 
 // Pair weight and (W == 2) mean-separation sums of one pair in range.  The
@@ -184,10 +217,13 @@ __device__ __forceinline__ void add_weight_f32(const SweepArgs &a, lds_f64wp whb
                                                LaneW wi, double wj, float s, int kind)
 {
     const double wp = fma(wi.a, wj, wi.b);
-    lds_add(&whb[slot], wp);
+    if (a.wfixed)
+        add_fixed(a, whb, slot, wp);
+    else
+        lds_add(&whb[slot], wp);
     if (W == 2)
         lds_add(&whb[slot + ((a.o_rhist - a.o_whist) >> 3)],
-                wp * sep_value_f32(kind, s, a.sep_scale));
+                (wp * wi.u) * sep_value_f32(kind, s, a.sep_scale));
 }
 
 template <int W>
@@ -195,9 +231,12 @@ __device__ __forceinline__ void add_weight_f64(const SweepArgs &a, lds_f64wp whb
                                                LaneW wi, double wj, double s, int kind)
 {
     const double wp = fma(wi.a, wj, wi.b);
-    lds_add(&whb[slot], wp);
+    if (a.wfixed)
+        add_fixed(a, whb, slot, wp);
+    else
+        lds_add(&whb[slot], wp);
     if (W == 2)
-        lds_add(&whb[slot + ((a.o_rhist - a.o_whist) >> 3)], wp * sep_value(kind, s));
+        lds_add(&whb[slot + ((a.o_rhist - a.o_whist) >> 3)], (wp * wi.u) * sep_value(kind, s));
 }
 
 // Table entry of a value (float bits already reduced to the key).
@@ -245,6 +284,26 @@ __device__ __forceinline__ unsigned tbl_key(float s, unsigned base, int sh, unsi
 __device__ __forceinline__ unsigned tbl_key_linear(float s, float kmax)
 {
     return (unsigned)__uint_as_float(min(__float_as_uint(s), __float_as_uint(kmax)));
+}
+
+// Key of the float32 path: the rounding key round(min(s, 1) * 32767) of the
+// shared-histogram sweeps' byte tables in one v_cvt_pknorm_i16_f32 (s >= 0
+// here, and the high half, the conversion of 0.0, is zero), else the linear
+// key.
+template <bool PK>
+__device__ __forceinline__ unsigned tbl_key_f32(float s, float kmax)
+{
+    if constexpr (PK)
+        return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pknorm_i16(s, 0.0f));
+    else
+        return tbl_key_linear(s, kmax);
+}
+
+// Value that the key sends to the last cell ("above every edge").
+template <bool PK>
+__device__ __forceinline__ float key_top_value(const SweepArgs &a)
+{
+    return PK ? 1.0f : (float)(a.B.tbl_n - 1);
 }
 
 // Number of bands wholly below s (bin + 1), or -1 when s lies inside a band.
@@ -332,7 +391,7 @@ __device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int 
 // unweighted 1-D statistics.
 // MASK: the item's last, partial chunk; pairs k >= rem are padding (their
 // loads repeat the item's last point) and are sent out of range.
-template <int M, int W, bool TRI, bool T16, bool UNC, int CH, bool MASK = false>
+template <int M, int W, bool TRI, bool T16, bool UNC, bool PK, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                           lds_f64wp whb, float ax, float ay, float az,
                                           LaneW wi, int i, const float *xs, const float *ys,
@@ -344,7 +403,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
     bool c[CH];
     unsigned key[CH];
     int e[CH];
-    const float kmax = (float)(a.B.tbl_n - 1);
+    const float kmax = key_top_value<PK>(a);
 #pragma unroll
     for (int k = 0; k < CH; k++) {
         const float dx = ax - xs[k], dy = ay - ys[k], dz = az - zs[k];
@@ -362,7 +421,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
             c[k] = false;
             s[k] = kmax;
         }
-        key[k] = tbl_key_linear(s[k], kmax);
+        key[k] = tbl_key_f32<PK>(s[k], kmax);
     }
     // every lane reads (no exec-mask changes), so the CH reads stay in flight
 #pragma unroll
@@ -541,7 +600,7 @@ __device__ __forceinline__ unsigned absdiff_plus(unsigned a, unsigned b, unsigne
     return (max(a, b) - min(a, b)) + c;
 }
 
-template <int W, bool TRI, bool T16, int CH, bool MASK = false>
+template <int W, bool TRI, bool T16, bool PK, int CH, bool MASK = false>
 __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                                  lds_f64wp whb, float ax, float ay,
                                                  unsigned azq, LaneW wi, int i,
@@ -550,8 +609,7 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
                                                  unsigned dcode, unsigned &rechecks,
                                                  int rem = CH)
 {
-    const float kmax = (float)(a.B.tbl_n - 1);
-    const unsigned kmaxb = __float_as_uint(kmax);
+    const float kmax = key_top_value<PK>(a);
     const int sh = a.B.zq_shift;
     const unsigned mask = (1u << sh) - 1u;
     const unsigned npi = (unsigned)a.B.npi;
@@ -571,7 +629,7 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
             u[k] = 1u << (sh - 1);
         }
         // s >= 0, so the bit patterns order like the values (no NaN here)
-        key[k] = (unsigned)__uint_as_float(min(__float_as_uint(s[k]), kmaxb));
+        key[k] = tbl_key_f32<PK>(s[k], kmax);
         near[k] = u[k] & mask;
         nmin = min(nmin, near[k]);
     }
@@ -624,7 +682,7 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
 }
 
 // ---- item loops ----------------------------------------------------------
-template <int M, int W, bool TRI, bool T16, bool UNC>
+template <int M, int W, bool TRI, bool T16, bool UNC, bool PK>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, int j0, int j1,
                                          unsigned dcode, unsigned &rechecks, int jx, int jy)
@@ -649,7 +707,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
         ax = act ? a.X1[i] + Dx : 3.0e30f;
         ay = act ? a.Y1[i] + Dy : 3.0e30f;
     }
-    const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
+    const LaneW wi = lane_weight(a, (W && act) ? a.w1[i] : 0.0);
     // second-catalogue points are wave-uniform: read them through the scalar
     // cache (the arrays are not written during the sweep)
     const kf32p X2 = (kf32p)a.X2, Y2 = (kf32p)a.Y2, Z2 = (kf32p)a.Z2;
@@ -670,8 +728,8 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
                 zs[k] = Z2[j + k];
                 ws[k] = W ? w2[j + k] : 0.0;
             }
-            chunk_f32_rppi_q<W, TRI, T16, CH>(a, L, hb, whb, ax, ay, azq, wi, i, xs, ys, zs, ws,
-                                              j, dcode, rechecks);
+            chunk_f32_rppi_q<W, TRI, T16, PK, CH>(a, L, hb, whb, ax, ay, azq, wi, i, xs, ys, zs,
+                                                  ws, j, dcode, rechecks);
         }
         if (j < j1) {
             const int rem = j1 - j;
@@ -685,8 +743,8 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
                 zs[k] = Z2[jk];
                 ws[k] = W ? w2[jk] : 0.0;
             }
-            chunk_f32_rppi_q<W, TRI, T16, CH, true>(a, L, hb, whb, ax, ay, azq, wi, i, xs, ys,
-                                                    zs, ws, j, dcode, rechecks, rem);
+            chunk_f32_rppi_q<W, TRI, T16, PK, CH, true>(a, L, hb, whb, ax, ay, azq, wi, i, xs,
+                                                        ys, zs, ws, j, dcode, rechecks, rem);
         }
         return;
     } else {
@@ -705,8 +763,8 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
                 zs[k] = Z2[j + k];
                 ws[k] = W ? w2[j + k] : 0.0;
             }
-            chunk_f32<M, W, TRI, T16, UNC, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs, ws, j,
-                                               dcode, rechecks);
+            chunk_f32<M, W, TRI, T16, UNC, PK, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs,
+                                                   ws, j, dcode, rechecks);
         }
         if (j < j1) {
             // the partial last chunk, padded with the item's last point
@@ -721,8 +779,8 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
                 zs[k] = Z2[jk];
                 ws[k] = W ? w2[jk] : 0.0;
             }
-            chunk_f32<M, W, TRI, T16, UNC, CH, true>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs,
-                                                     ws, j, dcode, rechecks, rem);
+            chunk_f32<M, W, TRI, T16, UNC, PK, CH, true>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys,
+                                                         zs, ws, j, dcode, rechecks, rem);
         }
     }
 }
@@ -737,7 +795,7 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
     const double xi = act ? a.x1[i] : 1.0e300;
     const double yi = act ? a.y1[i] : 1.0e300;
     const double zi = act ? a.z1[i] : 1.0e300;
-    const LaneW wi = lane_weight(a.wtype, (W && act) ? a.w1[i] : 0.0);
+    const LaneW wi = lane_weight(a, (W && act) ? a.w1[i] : 0.0);
     const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2, w2 = (kf64p)a.w2;
     constexpr int CH = W ? 4 : 8;
     int j = j0;
@@ -816,21 +874,39 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
     const bool R = W && a.ravg;
     const int roff = (a.o_rhist - a.o_whist) >> 3;
     double *gr = R ? a.g_rhist + (size_t)cat * a.nbt : nullptr;
+    // fixed-point weight sums: three uint64 limb sums per slot
+    const bool F = W && a.wfixed;
+    const lds_u64p fx = F ? (lds_u64p)L.whist : (lds_u64p) nullptr;
+    unsigned long long *gf = F ? a.g_wfix + 3 * (size_t)cat * a.nbt : nullptr;
     for (int b = first; b < a.nbt; b += step) {
         const int slot = (b / npi + 1) * rw + b % npi + c0;
         unsigned long long c = 0;
         double w = 0.0, rs = 0.0;
+        unsigned long long f0 = 0, f1 = 0, f2 = 0;
         for (int r = 0; r < a.copies; r++) {
             c += lds_take(&L.hist[r * a.rep_stride + slot]);
-            if (W)
+            if (F) {
+                const int o = r * a.rep_stride + slot;
+                f0 += lds_take(&fx[o]);
+                f1 += lds_take(&fx[o + a.wlimb]);
+                f2 += lds_take(&fx[o + 2 * a.wlimb]);
+            } else if (W) {
                 w += lds_take(&L.whist[r * a.rep_stride + slot]);
+            }
             if (R)
                 rs += lds_take(&L.whist[r * a.rep_stride + slot + roff]);
         }
         if (c)
             atomicAdd(&gh[b], c);
-        if (W && w != 0.0)
+        if (F) {
+            if (f0 | f1 | f2) {
+                unsigned long long v[3];
+                fixed_words((long long)f0, (long long)f1, (long long)f2, v);
+                fixed_atomic_add(gf + 3 * (size_t)b, v);
+            }
+        } else if (W && w != 0.0) {
             atomicAdd(&gw[b], w);
+        }
         if (R && rs != 0.0)
             atomicAdd(&gr[b], rs);
     }
@@ -840,8 +916,14 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         if (row >= 1 && row <= a.B.nb && col >= 0 && col < npi)
             continue;
         lds_take(&L.hist[r * a.rep_stride + sl]);
-        if (W)
+        if (F) {
+            const int o = r * a.rep_stride + sl;
+            lds_take(&fx[o]);
+            lds_take(&fx[o + a.wlimb]);
+            lds_take(&fx[o + 2 * a.wlimb]);
+        } else if (W) {
             lds_take(&L.whist[r * a.rep_stride + sl]);
+        }
         if (R)
             lds_take(&L.whist[r * a.rep_stride + sl + roff]);
     }
@@ -855,7 +937,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
 {
     // the lookup table has a fixed place so its address folds into the
     // LDS instructions; the rest of the layout is dynamic
-    __shared__ __align__(16) unsigned char s_tbl[PRIV ? kTblBytesPriv : kTblBytes];
+    // (the rounding-key byte table of float32 shared-histogram sweeps is
+    // smaller, which leaves room for a fourth workgroup per CU)
+    __shared__ __align__(16) unsigned char
+        s_tbl[PRIV ? kTblBytesPriv : ((P32 && !T16) ? PC_TBL_PK_CELLS : kTblBytes)];
     extern __shared__ __align__(16) unsigned char smem[];
     LDS unsigned char *sm = (LDS unsigned char *)smem;
     {
@@ -894,11 +979,12 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         for (int k = tid; k < sets * a.hist_stride; k += kSweepThreads)
             hist[k] = 0u;
         if (W) {
-            // weight sums, then (mean separation) the separation sums
-            LDS double *wh = (LDS double *)(sm + a.o_whist);
-            const int nw = (a.ravg ? (a.o_rhist - a.o_whist) >> 3 : 0) + sets * a.whist_stride;
+            // weight sums (binary64, or three uint64 limb sums), then (mean
+            // separation) the separation sums: the rest of the layout
+            LDS unsigned long long *wh = (LDS unsigned long long *)(sm + a.o_whist);
+            const int nw = (a.lds_bytes - a.o_whist) >> 3;
             for (int k = tid; k < nw; k += kSweepThreads)
-                wh[k] = 0.0;
+                wh[k] = 0ull;
         }
     }
     __syncthreads();
@@ -979,12 +1065,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
             if (a.xy_local)
                 cell_column(__builtin_amdgcn_readfirstlane(((const KCONST int32_t *)a.cs2)[it.j0]),
                             a.gnx, a.gny, a.gnz, &jx, &jy);
+            constexpr bool PK = !PRIV && !T16;
             if (tri)
-                item_f32<M, W, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
-                                               rechecks, jx, jy);
+                item_f32<M, W, true, T16, UNC, PK>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                                                   rechecks, jx, jy);
             else
-                item_f32<M, W, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
-                                                rechecks, jx, jy);
+                item_f32<M, W, false, T16, UNC, PK>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                                                    rechecks, jx, jy);
         } else {
             if (tri)
                 item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
@@ -1037,13 +1124,146 @@ __global__ void k_wsq(int64_t ncell, const int32_t *start, const double *w, int 
         atomicAdd(&out[c], sm[0]);
 }
 
+// ---- fixed-point weight sums (pc_fixed.h) ---------------------------------
+// Lowest set bit of a nonzero, finite |w| (bits without the sign): w is a
+// multiple of 2^low.
+__device__ __forceinline__ int low_bit_exp(unsigned long long bits)
+{
+    const int e = (int)(bits >> 52);
+    unsigned long long m = bits & ((1ull << 52) - 1ull);
+    if (e)
+        m |= 1ull << 52;
+    const int base = e ? e - 1075 : -1074;
+    return base + __ffsll((long long)m) - 1;
+}
+
+// Atomic maxima over the nonzero weights of one side: 2100 - low(w), |w|,
+// and the complement of |w| (whose maximum gives the minimum).
+__global__ void k_wfixed_scan(int64_t n, const double *w, int side, pc_wfixed *fx)
+{
+    unsigned key = 0;
+    unsigned long long mx = 0, nmn = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long b = __double_as_longlong(w[i]) & ~(1ull << 63);
+        if (b == 0)
+            continue;
+        key = max(key, (unsigned)(2100 - low_bit_exp(b)));
+        mx = max(mx, b);
+        nmn = max(nmn, ~b);
+    }
+    for (int off = PC_WAVE / 2; off > 0; off >>= 1) {
+        key = max(key, (unsigned)__shfl_xor((int)key, off));
+        mx = max(mx, (unsigned long long)__shfl_xor((long long)mx, off));
+        nmn = max(nmn, (unsigned long long)__shfl_xor((long long)nmn, off));
+    }
+    if ((threadIdx.x & (PC_WAVE - 1)) == 0 && key) {
+        atomicMax(&fx->lowkey[side], key);
+        atomicMax(&fx->maxbits[side], mx);
+        atomicMax(&fx->notmin[side], nmn);
+    }
+}
+
+// The grid 2^Q of the call and its checks (one thread).  two_sided: side 1
+// was scanned separately (cross-correlations); otherwise side 2 is side 1.
+__global__ void k_wfixed_plan(int wtype, int two_sided, pc_wfixed *fx, unsigned *flags)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    const int s2 = two_sided ? 1 : 0;
+    const bool any1 = fx->lowkey[0] != 0, any2 = fx->lowkey[s2] != 0;
+    int q = 0;
+    double pmax = 0.0;   // bound on max |pair weight|
+    const double mx1 = any1 ? __longlong_as_double((long long)fx->maxbits[0]) : 0.0;
+    const double mx2 = any2 ? __longlong_as_double((long long)fx->maxbits[s2]) : 0.0;
+    const double mn1 = any1 ? __longlong_as_double((long long)~fx->notmin[0]) : 0.0;
+    const double mn2 = any2 ? __longlong_as_double((long long)~fx->notmin[s2]) : 0.0;
+    const int low1 = 2100 - (int)fx->lowkey[0], low2 = 2100 - (int)fx->lowkey[s2];
+    bool ok = true;
+    if (wtype == 1) {
+        if (any1 || any2) {
+            q = any1 ? (any2 ? min(low1, low2) : low1) : low2;
+            pmax = mx1 + mx2;
+        }
+    } else if (any1 && any2) {
+        q = low1 + low2;
+        // a product is also a multiple of its own ulp, at least that of the
+        // smallest product fl(min1 * min2) when that is normal
+        const double pmin = mn1 * mn2;
+        if (pmin >= 0x1p-1022) {
+            int e;
+            frexp(pmin, &e);   // pmin in [2^(e-1), 2^e)
+            q = max(q, e - 1 - 52);
+        }
+        pmax = mx1 * mx2;
+    }
+    // every scaled pair weight below 2^94 (a margin over the 2^95 of the
+    // limbs for the rounding of pmax), every scaled lane weight a normal
+    // finite number, and every nonzero result normal
+    if (q < -1022 || q > 900)
+        ok = false;
+    if (ok && !(ldexp(pmax, -q) < 0x1p94))
+        ok = false;
+    if (ok && (any1 || any2)) {
+        const double big = fmax(mx1, mx2), small = any1 && any2 ? fmin(mn1, mn2) : (any1 ? mn1 : mn2);
+        if (!(ldexp(big, -q) < 0x1p1000) || !(ldexp(small, -q) >= 0x1p-1000))
+            ok = false;
+    }
+    fx->q = ok ? q : 0;
+    fx->scale = ok ? ldexp(1.0, -q) : 0.0;
+    fx->unscale = ok ? ldexp(1.0, q) : 0.0;
+    fx->ok = ok ? 1 : 0;
+    if (!ok)
+        atomicOr(flags, PC_FLAG_WFIXED);
+}
+
+// Self-pair weights of every catalogue in fixed point (k_wsq's sums, exact):
+// 192-bit totals, three words per catalogue.
+__global__ void k_wsq_fixed(int64_t ncell, const int32_t *start, const double *w, int wtype,
+                            const pc_wfixed *fx, unsigned long long *out)
+{
+    const int c = blockIdx.y;
+    const int64_t a = start[c * ncell], b = start[(c + 1) * ncell];
+    const double sc = fx->scale;
+    unsigned long long s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double P = wtype == 1 ? fma(sc, w[i], w[i] * sc) : fma(w[i] * sc, w[i], 0.0);
+        unsigned long long l0, l1, l2;
+        fixed_limbs(P, l0, l1, l2);
+        s0 += l0;
+        s1 += l1;
+        s2 += l2;
+    }
+    __shared__ unsigned long long sm[3][256];
+    sm[0][threadIdx.x] = s0;
+    sm[1][threadIdx.x] = s1;
+    sm[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 3; k++)
+                sm[k][threadIdx.x] += sm[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long v[3];
+        fixed_words((long long)sm[0][0], (long long)sm[1][0], (long long)sm[2][0], v);
+        fixed_atomic_add(out + 3 * (size_t)c, v);
+    }
+}
+
 // Appendix B: autocorrelation counts are doubled (ordered pairs) and the
 // N self-pairs of each catalogue join its bin 0 when the first edge is zero
 // (with their weights, and separation 0).  The mean separation is the
-// separation sum over the weight sum (doubling cancels).
+// separation sum over the weight sum (doubling cancels).  Fixed-point weight
+// sums (g_wfix, wsq_fix: three words per bin or catalogue) are doubled and
+// completed in 192-bit integers and rounded to binary64 once.
 __global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
                            const double *g_whist, const double *g_rhist, const double *wsq,
+                           const unsigned long long *g_wfix,
+                           const unsigned long long *wsq_fix, const pc_wfixed *wfx,
                            unsigned long long *out_counts, double *out_wsum, double *out_ravg,
                            const int32_t *n_items_dev, const int32_t *n_blocks_dev,
                            int32_t *sizes_out)
@@ -1066,6 +1286,20 @@ __global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                 if (wsq)
                     w += wsq[c];
             }
+        }
+        if (g_wfix) {
+            unsigned long long f[3] = {g_wfix[3 * t], g_wfix[3 * t + 1], g_wfix[3 * t + 2]};
+            if (autocorr) {
+                f[2] = (f[2] << 1) | (f[1] >> 63);
+                f[1] = (f[1] << 1) | (f[0] >> 63);
+                f[0] <<= 1;
+                if (e0_zero && b == 0 && wsq_fix) {
+                    const unsigned long long d[3] = {wsq_fix[3 * c], wsq_fix[3 * c + 1],
+                                                     wsq_fix[3 * c + 2]};
+                    fixed_add(f, d);
+                }
+            }
+            w = fixed_to_double(f, wfx->q);
         }
         out_counts[t] = v;
         if (out_wsum)
@@ -1158,6 +1392,8 @@ hipError_t launch_wsq(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t 
 hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
                            const pc_cat *cats, const unsigned long long *g_hist,
                            const double *g_whist, const double *g_rhist, const double *wsq,
+                           const unsigned long long *g_wfix,
+                           const unsigned long long *wsq_fix, const pc_wfixed *wfx,
                            unsigned long long *out_counts, double *out_wsum,
                            double *out_ravg, const int32_t *n_items_dev,
                            const int32_t *n_blocks_dev, int32_t *sizes_out)
@@ -1166,8 +1402,35 @@ hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocor
     int64_t g = (total + 255) / 256;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(256), 0, s, ncat, nbt, autocorr,
-                       e0_zero, cats, g_hist, g_whist, g_rhist, wsq, out_counts, out_wsum,
-                       out_ravg, n_items_dev, n_blocks_dev, sizes_out);
+                       e0_zero, cats, g_hist, g_whist, g_rhist, wsq, g_wfix, wsq_fix, wfx,
+                       out_counts, out_wsum, out_ravg, n_items_dev, n_blocks_dev, sizes_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wfixed_scan(hipStream_t s, int64_t n, const double *w, int side,
+                              pc_wfixed *fx)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    g = g > 1024 ? 1024 : g;
+    hipLaunchKernelGGL(k_wfixed_scan, dim3((unsigned)g), dim3(256), 0, s, n, w, side, fx);
+    return hipGetLastError();
+}
+
+hipError_t launch_wfixed_plan(hipStream_t s, int wtype, int two_sided, pc_wfixed *fx,
+                              unsigned *flags)
+{
+    hipLaunchKernelGGL(k_wfixed_plan, dim3(1), dim3(64), 0, s, wtype, two_sided, fx, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_wsq_fixed(hipStream_t s, int32_t ncat, int64_t ncell, const int32_t *start,
+                            const double *w, int wtype, const pc_wfixed *fx,
+                            unsigned long long *out)
+{
+    hipLaunchKernelGGL(k_wsq_fixed, dim3(64, (unsigned)ncat), dim3(256), 0, s, ncell, start, w,
+                       wtype, fx, out);
     return hipGetLastError();
 }
 

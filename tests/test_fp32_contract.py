@@ -6,7 +6,7 @@ band the pair is re-evaluated in binary64.  The bands come from a proven
 bound B(s) on |s32 - s64| (cf_fp32_bands_axes).  These tests emulate the
 sweep's float32 arithmetic exactly -- the column-local x and y frames of 3-D
 grids, z in the domain frame, the periodic offset of the work item, the
-power-of-two coordinate scale, one float32 multiply and two fused
+coordinate scale (not a power of two), one float32 multiply and two fused
 multiply-adds with a single rounding each -- on more than 10^8 pairs (random
 pairs over the whole reach, periodic wraps, and adversarial pairs within a
 few ulps of every edge), and check that
@@ -175,22 +175,17 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats):
     stats["max_ratio_raw"] = max(stats["max_ratio_raw"], float((ratio_band * SAFETY).max()))
 
 
-def scale_for(edges, S, cells=40960):
-    """The power of two the library applies to float32 coordinates: the top
-    band just below the last linear table cell."""
+def scale_for(edges, S, top=32766.0 / 32767.0):
+    """A coordinate scale like the library's: the top band just below the
+    top of the rounding key (not a power of two)."""
     E = edges[-1] ** 2
     lo, hi = pc.fp32_bands(np.array([E]), 3, S)
-    m = 0
-    while math.ldexp(float(hi[0]), 2 * m) >= cells - 1:
-        m -= 1
-    while math.ldexp(float(hi[0]), 2 * (m + 1)) < cells - 1:
-        m += 1
-    return 2.0 ** m
+    return math.sqrt(top * (1.0 - 2.0 ** -16) / float(hi[0]))
 
 
 @pytest.mark.parametrize("case", ["r_box420", "r_box1100_k2", "rp_box1000", "chord_open"])
 def test_fp32_bound_holds_on_1e8_pairs(case):
-    rng = synth.rng_for(hash(case) % (1 << 31))
+    rng = synth.rng_for(sum(map(ord, case)))
     stats = {"pairs": 0, "max_ratio_band": 0.0, "max_ratio_raw": 0.0}
     if case == "r_box420":
         L, reach, k, ndim = 420.0, 25.0, 1, 3

@@ -8,7 +8,8 @@ At these sizes the GPU result is checked against:
   ``tests/golden/fullsize_*.json`` with the SHA-256 of their inputs, which the
   tests draw again and check; every auto (and cross) histogram of both
   precisions must equal them bit for bit, and weighted sums must lie within
-  1e-12 of the exactly rounded sums;
+  1e-12 of the exactly rounded sums (equal them bit for bit with
+  deterministic_weights);
 * sampled outputs the oracle computes on the spot: cross counts of a random
   subset S of the first catalogue against the whole second catalogue;
 * properties that hold at any size: the float32+recheck path equals the
@@ -160,6 +161,12 @@ def test_r_weighted_n4e6(pc, olib, box1100):
     assert (c32 == g["counts"]).all() and (c64 == g["counts"]).all()
     check_w(w32, g["wsum"])
     check_w(w64, g["wsum"])
+    # exact fixed-point sums: the oracle's exactly rounded sums, bit for bit
+    for prec in ("fp32", "fp64"):
+        cd, wd = pc.count_r(pts, None, e, 1100.0, prec, w1=w,
+                            options={"deterministic_weights": 1})
+        assert (cd == g["counts"]).all()
+        assert np.array_equal(wd, g["wsum"]), prec
     idx = sample(pts.shape[0], NSAMPLE, 13)
     got, gw = pc.count_r(pts[idx], pts, e, 1100.0, "fp32", w1=w[idx], w2=w)
     want, ww = oracle.count_r(pts[idx], pts, e, 1100.0, w1=w[idx], w2=w, lib=olib)
@@ -177,6 +184,11 @@ def test_rppi_weighted_n4e6(pc, olib, box1100):
     assert (c32.ravel() == g["counts"]).all() and (c64.ravel() == g["counts"]).all()
     check_w(w32.ravel(), g["wsum"])
     check_w(w64.ravel(), g["wsum"])
+    for prec in ("fp32", "fp64"):
+        cd, wd = pc.count_rppi(pts, None, e, 40.0, 40, 1100.0, prec, w1=w,
+                               options={"deterministic_weights": 1})
+        assert (cd.ravel() == g["counts"]).all()
+        assert np.array_equal(wd.ravel(), g["wsum"]), prec
     idx = sample(pts.shape[0], NSAMPLE, 14)
     got, gw = pc.count_rppi(pts[idx], pts, e, 40.0, 40, 1100.0, "fp32", w1=w[idx], w2=w)
     want, ww = oracle.count_rppi(pts[idx], pts, e, 40.0, 40, 1100.0, w1=w[idx], w2=w,
