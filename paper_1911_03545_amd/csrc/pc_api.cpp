@@ -534,19 +534,17 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
             (st = ensure(c, B_COLS, 2 * sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1))) ||
             (st = ensure(c, B_SCANTMP, sizeof(int32_t) * pc::scan_tmp_elems(m))))
             return st;
+        // (the record buffer holds the column-ordered records here)
         HIPCHK(pc::launch_sort2(c->stream, s.ncat, cats_dev, n, g, (int32_t)chunk, ncolc,
                                 (int32_t)nchunks, m, dptr<int32_t>(c, B_LAY),
                                 dptr<int32_t>(c, B_CNT), dptr<int32_t>(c, B_WOFF),
                                 dptr<int32_t>(c, B_SCANTMP), dptr<int32_t>(c, B_CELLOF),
-                                dptr<int32_t>(c, B_RANKOF), c->buf[B_REC].p,
-                                c->buf[B_COLS].p, dptr<int32_t>(c, B_PERM),
-                                dptr<int32_t>(c, start), dptr<int32_t>(c, CS), flags));
-        HIPCHK(pc::launch_gather(c->stream, n, g, dptr<int32_t>(c, B_PERM), nullptr,
-                                 c->buf[B_REC].p, dptr<float>(c, X),
-                                 dptr<float>(c, Y), dptr<float>(c, Z), dptr<double>(c, XD),
-                                 dptr<double>(c, YD), dptr<double>(c, ZD),
-                                 weighted ? dptr<double>(c, WD) : nullptr,
-                                 dptr<int32_t>(c, CS)));
+                                dptr<int32_t>(c, B_RANKOF), c->buf[B_REC].p, c->buf[B_COLS].p,
+                                dptr<int32_t>(c, B_PERM), dptr<int32_t>(c, start),
+                                dptr<int32_t>(c, CS), dptr<float>(c, X), dptr<float>(c, Y),
+                                dptr<float>(c, Z), dptr<double>(c, XD), dptr<double>(c, YD),
+                                dptr<double>(c, ZD), weighted ? dptr<double>(c, WD) : nullptr,
+                                flags));
         return CF_OK;
     }
     HIPCHK(pc::launch_zero(c->stream, c->buf[B_CNT].p, sizeof(int32_t) * (size_t)ncells));

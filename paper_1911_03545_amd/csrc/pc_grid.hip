@@ -331,10 +331,17 @@ __global__ void k_grid_layout(int ncat, const pc_cat *cats, int32_t chunk, int32
 }
 
 // Level 1, counting: one workgroup per chunk, LDS histogram of ncolc columns.
+// Each thread loads kHistPer points before it bins them, so that their loads
+// are in flight together.
+constexpr int kHistPer = 8;
 template <bool SKY>
-__global__ void k_cell_hist(int ncat, const pc_cat *cats, const int32_t *lay, pc_grid g,
-                            int32_t chunk, int32_t ncolc, int32_t *cell_of, int32_t *rank_of,
-                            double4 *rec, int32_t *wcnt, unsigned *flags)
+__global__ __launch_bounds__(kThreads) void k_cell_hist(int ncat, const pc_cat *cats,
+                                                        const int32_t *lay, pc_grid g,
+                                                        int32_t chunk, int32_t ncolc,
+                                                        int32_t *__restrict__ cell_of,
+                                                        int32_t *__restrict__ rank_of,
+                                                        int32_t *__restrict__ wcnt,
+                                                        unsigned *flags)
 {
     extern __shared__ unsigned hist[];
     const int w = blockIdx.x;
@@ -354,18 +361,26 @@ __global__ void k_cell_hist(int ncat, const pc_cat *cats, const int32_t *lay, pc
         hist[c] = 0u;
     __syncthreads();
     unsigned fl = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const int64_t j = i - ct.off;
-        const double c[3] = {ld(ct.x, ct.f32, j), ld(ct.y, ct.f32, j), ld(ct.z, ct.f32, j)};
-        const int2 cs = point_cell<SKY>(g, c, fl);
-        // unit weights without weights (the mean-separation sums use them)
-        const double wt = ct.w ? ld(ct.w, ct.wf32, j) : 1.0;
-        if (!isfinite(wt))
-            fl |= PC_FLAG_WEIGHT;
-        const int col = cs.x;
-        cell_of[i] = (int)((int64_t)k * g.ncell) + col * g.n[2] + cs.y;
-        rec[i] = make_double4(c[0], c[1], c[2], wt);
-        rank_of[i] = (int32_t)atomicAdd(&hist[col], 1u);
+    for (int64_t base = i0 + threadIdx.x; base < i1; base += (int64_t)kHistPer * blockDim.x) {
+        double c[kHistPer][3];
+#pragma unroll
+        for (int p = 0; p < kHistPer; p++) {
+            const int64_t i = base + (int64_t)p * blockDim.x;
+            const int64_t j = (i < i1 ? i : i0) - ct.off;
+            c[p][0] = ld(ct.x, ct.f32, j);
+            c[p][1] = ld(ct.y, ct.f32, j);
+            c[p][2] = ld(ct.z, ct.f32, j);
+        }
+#pragma unroll
+        for (int p = 0; p < kHistPer; p++) {
+            const int64_t i = base + (int64_t)p * blockDim.x;
+            if (i >= i1)
+                break;
+            const int2 cs = point_cell<SKY>(g, c[p], fl);
+            const int col = cs.x;
+            cell_of[i] = (int)((int64_t)k * g.ncell) + col * g.n[2] + cs.y;
+            rank_of[i] = (int32_t)atomicAdd(&hist[col], 1u);
+        }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < ncolc; c += blockDim.x)
@@ -374,30 +389,112 @@ __global__ void k_cell_hist(int ncat, const pc_cat *cats, const int32_t *lay, pc
         atomicOr(flags, fl);
 }
 
-// Level 1, placement: every point, with its z slice, to its column-ordered
-// place (so that level 2 streams through its column without gathers).
-__global__ void k_col_scatter(int64_t ntot, int ncat, const pc_cat *cats, const int32_t *lay,
-                              int32_t nz, int32_t chunk, int32_t ncolc, const int32_t *cell_of,
-                              const int32_t *rank_of, const int32_t *woff, int2 *colsorted)
+// Level 1, placement: every point, as one 32-byte record (x, y, z, w) read
+// from the input columns, to its column-ordered place, so that level 2
+// streams through its column.  Non-finite weights raise a flag here.
+__global__ __launch_bounds__(kThreads) void k_col_scatter(
+    int64_t ntot, int ncat, const pc_cat *cats, const int32_t *lay, int32_t nz, int32_t chunk,
+    int32_t ncolc, const int32_t *__restrict__ cell_of, const int32_t *__restrict__ rank_of,
+    const int32_t *__restrict__ woff, double4 *__restrict__ colrec, unsigned *flags)
 {
+    unsigned fl = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntot;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int k = ncat == 1 ? 0 : find_cat(cats, ncat, i);
-        const int wl = (int)((i - cats[k].off) / chunk);
-        const int cell = cell_of[i];
-        const int cz = cell / nz;
+        const pc_cat &ct = cats[k];
+        const int64_t j = i - ct.off;
+        const double x = ld(ct.x, ct.f32, j), y = ld(ct.y, ct.f32, j), z = ld(ct.z, ct.f32, j);
+        // unit weights without weights (the mean-separation sums use them)
+        const double wt = ct.w ? ld(ct.w, ct.wf32, j) : 1.0;
+        if (!isfinite(wt))
+            fl |= PC_FLAG_WEIGHT;
+        const int wl = (int)((uint32_t)j / (uint32_t)chunk);
+        const int cz = (int)((uint32_t)cell_of[i] / (uint32_t)nz);
         const int64_t m = lay[3 * k + 2] + (int64_t)(cz - k * ncolc) * lay[3 * k + 1] + wl;
-        colsorted[woff[m] + rank_of[i]] = make_int2((int32_t)i, cell - cz * nz);
+        colrec[(int64_t)woff[m] + rank_of[i]] = make_double4(x, y, z, wt);
     }
+    if (fl)
+        atomicOr(flags, fl);
+}
+
+// Exclusive prefix of v over a workgroup of NT threads (NT a multiple of the
+// wave size, at most 64 waves), with the workgroup's total.
+template <int NT>
+__device__ int block_exclusive_waves(int v, int *total)
+{
+    constexpr int NWV = NT / PC_WAVE;
+    __shared__ int wsum[NWV];
+    const int lane = threadIdx.x & (PC_WAVE - 1), wv = threadIdx.x / PC_WAVE;
+    int x = v;
+    for (int off = 1; off < PC_WAVE; off <<= 1) {
+        const int t = __shfl_up(x, off, PC_WAVE);
+        if (lane >= off)
+            x += t;
+    }
+    if (lane == PC_WAVE - 1)
+        wsum[wv] = x;
+    __syncthreads();
+    if (wv == 0) {
+        int y = lane < NWV ? wsum[lane] : 0;
+        for (int off = 1; off < NWV; off <<= 1) {
+            const int t = __shfl_up(y, off, PC_WAVE);
+            if (lane >= off)
+                y += t;
+        }
+        if (lane < NWV)
+            wsum[lane] = y;
+    }
+    __syncthreads();
+    const int before = wv ? wsum[wv - 1] : 0;
+    *total = wsum[NWV - 1];
+    __syncthreads();
+    return before + x - v;
+}
+
+// One point to its sorted place d: the float32 coordinates of the bulk
+// sweep (x and y relative to the centre of the point's own column on 3-D
+// grids, z relative to the domain origin, all scaled by g.fscale; z as fixed
+// point on the float32 rp/pi path) and the binary64 values.
+__device__ __forceinline__ void store_sorted(const pc_grid &g, const double4 &r, int cell,
+                                             int64_t d, float *X, float *Y, float *Z,
+                                             double *xd, double *yd, double *zd, double *wd)
+{
+    if (g.xy_local) {
+        int ix, iy;
+        cell_column(cell, g.n[0], g.n[1], g.n[2], &ix, &iy);
+        X[d] = (float)((r.x - col_centre(g.lo[0], g.width[0], ix)) * g.fscale);
+        Y[d] = (float)((r.y - col_centre(g.lo[1], g.width[1], iy)) * g.fscale);
+    } else {
+        X[d] = (float)((r.x - g.lo[0]) * g.fscale);
+        Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
+    }
+    if (g.zq_shift > 0)
+        Z[d] = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
+    else
+        Z[d] = (float)((r.z - g.lo[2]) * g.fscale);
+    xd[d] = r.x;
+    yd[d] = r.y;
+    zd[d] = r.z;
+    if (wd)
+        wd[d] = r.w;
 }
 
 // Level 2: one workgroup per column sorts the column's points by z slice
-// (LDS counts and prefix) and writes perm and the column's cell starts.
-__global__ void k_slice_sort(int ncat, const int32_t *lay, int32_t ncolc, int32_t nz,
-                             const int32_t *woff, const int2 *colsorted, int32_t *rank2,
-                             int32_t *perm, int32_t *start, int32_t *cell_sorted)
+// (LDS counts and prefix) and writes the column's cell starts, the cell of
+// every sorted place and `perm`, the column-ordered index of the point that
+// goes there (k_gather then reads the records in sorted order).  The slice
+// of a point is recomputed from its record with the same arithmetic as its
+// cell in k_cell_hist (point_cell), so it is the same value.
+constexpr int kSliceThreads = 1024;
+constexpr int kSlicePer = 4;
+template <bool SKY>
+__global__ __launch_bounds__(kSliceThreads) void k_slice_sort(
+    int ncat, const int32_t *lay, int32_t ncolc, pc_grid g, const int32_t *__restrict__ woff,
+    const double4 *__restrict__ colrec, int2 *__restrict__ rank_slice, int32_t *start,
+    int32_t *__restrict__ perm, int32_t *__restrict__ cell_sorted)
 {
     extern __shared__ unsigned sh[];
+    const int nz = g.n[2];
     const int64_t colall = blockIdx.x;
     const int k = (int)(colall / ncolc), col = (int)(colall % ncolc);
     const int nw = lay[3 * k + 1], mb = lay[3 * k + 2];
@@ -407,15 +504,31 @@ __global__ void k_slice_sort(int ncat, const int32_t *lay, int32_t ncolc, int32_
     for (int z = threadIdx.x; z < nz; z += blockDim.x)
         sh[z] = 0u;
     __syncthreads();
-    for (int p = cs + threadIdx.x; p < ce; p += blockDim.x)
-        rank2[p] = (int32_t)atomicAdd(&sh[colsorted[p].y], 1u);
+    unsigned fl = 0;   // (the flags were raised by k_cell_hist already)
+    for (int base = cs + (int)threadIdx.x; base < ce; base += kSlicePer * kSliceThreads) {
+        double4 r[kSlicePer];
+#pragma unroll
+        for (int p = 0; p < kSlicePer; p++) {
+            const int q = base + p * kSliceThreads;
+            r[p] = colrec[q < ce ? q : cs];
+        }
+#pragma unroll
+        for (int p = 0; p < kSlicePer; p++) {
+            const int q = base + p * kSliceThreads;
+            if (q >= ce)
+                break;
+            const double c[3] = {r[p].x, r[p].y, r[p].z};
+            const int sl = point_cell<SKY>(g, c, fl).y;
+            rank_slice[q] = make_int2((int)atomicAdd(&sh[sl], 1u), sl);
+        }
+    }
     __syncthreads();
     int carry = 0;
-    for (int base = 0; base < nz; base += blockDim.x) {
+    for (int base = 0; base < nz; base += kSliceThreads) {
         const int z = base + (int)threadIdx.x;
         const int v = z < nz ? (int)sh[z] : 0;
         int total;
-        const int ex = block_exclusive(v, &total);
+        const int ex = block_exclusive_waves<kSliceThreads>(v, &total);
         if (z < nz)
             sh[z] = (unsigned)(carry + ex);
         carry += total;
@@ -425,11 +538,22 @@ __global__ void k_slice_sort(int ncat, const int32_t *lay, int32_t ncolc, int32_
         start[cell0 + z] = cs + (int)sh[z];
     if (colall == (int64_t)ncat * ncolc - 1 && threadIdx.x == 0)
         start[cell0 + nz] = ce;
-    for (int p = cs + threadIdx.x; p < ce; p += blockDim.x) {
-        const int2 iz = colsorted[p];
-        const int q = cs + (int)sh[iz.y] + rank2[p];
-        perm[q] = iz.x;
-        cell_sorted[q] = (int32_t)(cell0 + iz.y);
+    for (int base = cs + (int)threadIdx.x; base < ce; base += kSlicePer * kSliceThreads) {
+        int2 rs[kSlicePer];
+#pragma unroll
+        for (int p = 0; p < kSlicePer; p++) {
+            const int q = base + p * kSliceThreads;
+            rs[p] = rank_slice[q < ce ? q : cs];
+        }
+#pragma unroll
+        for (int p = 0; p < kSlicePer; p++) {
+            const int q = base + p * kSliceThreads;
+            if (q >= ce)
+                break;
+            const int d = cs + (int)sh[rs[p].y] + rs[p].x;
+            perm[d] = q;
+            cell_sorted[d] = (int)(cell0 + rs[p].y);
+        }
     }
 }
 
@@ -448,36 +572,25 @@ __global__ void k_perm(int64_t ntot, const int32_t *cell_of, const int32_t *rank
         perm[(int64_t)start[cell_of[i]] + rank_of[i]] = (int32_t)i;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b to XCD b % 8);
+// the launch remaps b so that each XCD walks one contiguous eighth of the
+// sorted order, and the records a column's places read (after the two-level
+// sort: one column-ordered range) are fetched into one XCD's L2.
+constexpr int kXcds = 8;
 __global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int32_t *cell_of,
                          const double4 *rec, float *X, float *Y, float *Z, double *xd, double *yd,
                          double *zd, double *wd, int32_t *cell_sorted)
 {
-    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < ntot;
+    const int per = (int)(gridDim.x / kXcds);   // gridDim.x is a multiple of kXcds
+    const int lb = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    for (int64_t d = lb * (int64_t)blockDim.x + threadIdx.x; d < ntot;
          d += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = perm[d];
         const double4 r = rec[i];
-        if (g.xy_local) {
-            // x and y relative to the centre of the point's own column
-            const int cell = cell_of ? cell_of[i] : cell_sorted[d];
-            int ix, iy;
-            cell_column(cell, g.n[0], g.n[1], g.n[2], &ix, &iy);
-            X[d] = (float)((r.x - col_centre(g.lo[0], g.width[0], ix)) * g.fscale);
-            Y[d] = (float)((r.y - col_centre(g.lo[1], g.width[1], iy)) * g.fscale);
-        } else {
-            X[d] = (float)((r.x - g.lo[0]) * g.fscale);
-            Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
-        }
-        if (g.zq_shift > 0)
-            Z[d] = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
-        else
-            Z[d] = (float)((r.z - g.lo[2]) * g.fscale);
-        xd[d] = r.x;
-        yd[d] = r.y;
-        zd[d] = r.z;
-        if (wd)
-            wd[d] = r.w;
+        const int cell = cell_of ? cell_of[i] : cell_sorted[d];
+        store_sorted(g, r, cell, d, X, Y, Z, xd, yd, zd, wd);
         if (cell_of)
-            cell_sorted[d] = cell_of[i];
+            cell_sorted[d] = cell;
     }
 }
 
@@ -922,7 +1035,8 @@ hipError_t launch_gather(hipStream_t s, int64_t ntot, const pc_grid &g, const in
                          const int32_t *cell_of, const void *rec, float *X, float *Y, float *Z,
                          double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
 {
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, g, perm,
+    const int gw = (grid_for(ntot) + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(k_gather, dim3(gw), dim3(kThreads), 0, s, ntot, g, perm,
                        cell_of, static_cast<const double4 *>(rec), X, Y, Z, xd, yd, zd, wd,
                        cell_sorted);
     return hipGetLastError();
@@ -931,10 +1045,12 @@ hipError_t launch_gather(hipStream_t s, int64_t ntot, const pc_grid &g, const in
 hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
                         const pc_grid &g, int32_t chunk, int32_t ncolc, int32_t n_chunks,
                         int64_t m, int32_t *lay, int32_t *wcnt, int32_t *woff, int32_t *tmp,
-                        int32_t *cell_of, int32_t *rank_of, void *rec, void *colsorted,
-                        int32_t *perm, int32_t *start, int32_t *cell_sorted, unsigned *flags)
+                        int32_t *cell_of, int32_t *rank_of, void *colrec, void *rank_slice,
+                        int32_t *perm, int32_t *start, int32_t *cell_sorted, float *X, float *Y,
+                        float *Z, double *xd, double *yd, double *zd, double *wd,
+                        unsigned *flags)
 {
-    int2 *cols = static_cast<int2 *>(colsorted);
+    double4 *cr = static_cast<double4 *>(colrec);
     hipLaunchKernelGGL(k_grid_layout, dim3(1), dim3(64), 0, s, ncat, cats, chunk, ncolc, lay);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -943,20 +1059,24 @@ hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t nto
         hipLaunchKernelGGL(g.nband > 0 ? k_cell_hist<true> : k_cell_hist<false>,
                            dim3((unsigned)n_chunks), dim3(kThreads),
                            sizeof(unsigned) * (size_t)ncolc, s, ncat, cats, lay, g, chunk, ncolc,
-                           cell_of, rank_of, static_cast<double4 *>(rec), wcnt, flags);
+                           cell_of, rank_of, wcnt, flags);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     if ((e = scan_exclusive(s, wcnt, m, woff, tmp)) != hipSuccess)
         return e;
     if (ntot > 0)
         hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, ncat,
-                           cats, lay, g.n[2], chunk, ncolc, cell_of, rank_of, woff, cols);
+                           cats, lay, g.n[2], chunk, ncolc, cell_of, rank_of, woff, cr, flags);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_slice_sort, dim3((unsigned)((int64_t)ncat * ncolc)), dim3(kThreads),
-                       sizeof(unsigned) * (size_t)g.n[2], s, ncat, lay, ncolc, g.n[2], woff, cols,
-                       rank_of, perm, start, cell_sorted);
-    return hipGetLastError();
+    hipLaunchKernelGGL(g.nband > 0 ? k_slice_sort<true> : k_slice_sort<false>,
+                       dim3((unsigned)((int64_t)ncat * ncolc)), dim3(kSliceThreads),
+                       sizeof(unsigned) * (size_t)g.n[2], s, ncat, lay, ncolc, g, woff, cr,
+                       static_cast<int2 *>(rank_slice), start, perm, cell_sorted);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    return launch_gather(s, ntot, g, perm, nullptr, colrec, X, Y, Z, xd, yd, zd, wd,
+                         cell_sorted);
 }
 
 hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,

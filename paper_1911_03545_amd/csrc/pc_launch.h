@@ -110,18 +110,22 @@ hipError_t launch_gather(hipStream_t s, int64_t ntot, const pc_grid &g, const in
                          const int32_t *cell_of, const void *rec, float *X, float *Y, float *Z,
                          double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted);
 // Two-level counting sort without global atomics (columns in LDS per chunk of
-// `chunk` points, then z slices in LDS per column): writes cell_of, rec,
-// perm and start (ncat * ncell + 1) like launch_cell_index + scan +
-// launch_scatter's permutation.  Needs ncolc and g.n[2] at most
-// PC_SORT2_MAX_BINS; `lay` holds 3 (ncat + 1) ints, wcnt m ints, woff m + 1
-// ints (m = sum over catalogues of ncolc * chunks), tmp scan_tmp_elems(m)
-// ints, colsorted ntot int2 (point, slice) pairs; rank_of is reused.
+// `chunk` points, then z slices in LDS per column) followed by the gather
+// into the sorted arrays: start (ncat * ncell + 1), cell_sorted, X, Y, Z, xd,
+// yd, zd and (optional) wd, like launch_cell_index + scan + launch_scatter.
+// Needs ncolc and g.n[2] at most PC_SORT2_MAX_BINS; `lay` holds 3 (ncat + 1)
+// ints, wcnt m ints, woff m + 1 ints (m = sum over catalogues of ncolc *
+// chunks), tmp scan_tmp_elems(m) ints; scratch: colrec ntot 32-byte records
+// (column order), rank_slice ntot int pairs, perm, cell_of and rank_of ntot
+// ints each.
 #define PC_SORT2_MAX_BINS 16384
 hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t ntot,
                         const pc_grid &g, int32_t chunk, int32_t ncolc, int32_t n_chunks,
                         int64_t m, int32_t *lay, int32_t *wcnt, int32_t *woff, int32_t *tmp,
-                        int32_t *cell_of, int32_t *rank_of, void *rec, void *colsorted,
-                        int32_t *perm, int32_t *start, int32_t *cell_sorted, unsigned *flags);
+                        int32_t *cell_of, int32_t *rank_of, void *colrec, void *rank_slice,
+                        int32_t *perm, int32_t *start, int32_t *cell_sorted, float *X, float *Y,
+                        float *Z, double *xd, double *yd, double *zd, double *wd,
+                        unsigned *flags);
 hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
                               int32_t *bcnt);
 hipError_t launch_block_emit(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
