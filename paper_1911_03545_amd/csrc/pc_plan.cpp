@@ -544,6 +544,13 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
             plo[p] = float_down((double)plo[p] * fscale);
             phi[p] = float_up((double)phi[p] * fscale);
         }
+        // bottoms and tops that never decrease (a band only ever widens,
+        // which sends more values to the binary64 recheck): the sweep then
+        // finds the band of a value by a binary search over the tops
+        for (int k = ne - 2; k >= 0; k--)
+            lo[k] = std::min(lo[k], lo[k + 1]);
+        for (int k = 1; k < ne; k++)
+            hi[k] = std::max(hi[k], hi[k - 1]);
     }
     int shift = 0;
     uint32_t base = 0, tbl_n = 0;

@@ -307,16 +307,20 @@ __device__ __forceinline__ float key_top_value(const SweepArgs &a)
 }
 
 // Number of bands wholly below s (bin + 1), or -1 when s lies inside a band.
+// Band bottoms and tops never decrease (the planner widens bands where they
+// would), so the first band whose top reaches s is the only one that can
+// hold it: a binary search over the tops and one test of that band's bottom.
 __device__ __forceinline__ int band_scan(float s, lds_f32p lo, lds_f32p hi, int nedges)
 {
-    int below = 0;
-    for (int k = 0; k < nedges; k++) {
-        if (s > hi[k])
-            below++;
-        else if (s >= lo[k])
-            return -1;
+    int a = 0, b = nedges;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (s > hi[m])
+            a = m + 1;
+        else
+            b = m;
     }
-    return below;
+    return (a < nedges && s >= lo[a]) ? -1 : a;
 }
 
 // Float32 slot of a value in a flagged table cell: the number of bands
