@@ -519,10 +519,13 @@ def weighted_bench(args):
     2 holding half of them) in a periodic L = 1100 box with float32 weights
     uniform in [0.5, 1.5) and product pair weights: xi(r) counts with 25 log
     bins in [0.1, 50], and wp(rp) counts with the same rp bins, pimax 40 in 40
-    bins; each in float32 + recheck and in binary64.  Reports time per call,
-    reference pairs per second, and the weighted sums' agreement: float32 +
-    recheck against binary64 over the whole catalogue, and against the oracle
-    on sampled cross counts (256 points against all)."""
+    bins; each in float32 + recheck and in binary64, with binary64 atomic
+    weight sums and with exact fixed-point sums (deterministic_weights).
+    Reports time per call, reference pairs per second, and the weighted sums'
+    agreement: float32 + recheck against binary64 over the whole catalogue,
+    and against the oracle on sampled cross counts (256 points against all);
+    the fixed-point sums must equal across precisions and equal the oracle's
+    exactly rounded sums bit for bit."""
     import torch
     import paper_1911_03545_amd as pcm
     import oracle
@@ -567,6 +570,30 @@ def weighted_bench(args):
                                       "rechecks": st["rechecks"]}
         if not np.array_equal(sums["fp32"][0], sums["fp64"][0]):
             raise SystemExit(f"{stat}: float32 + recheck and binary64 counts differ")
+        fixed = {}
+        fopts = pcm.default_options(collect_timing=1, deterministic_weights=1)
+        for prec in ("fp32", "fp64"):
+            if stat == "r":
+                def call():
+                    return ctx.count_r(cols, None, e, L, prec, w1=wd, options=fopts)
+            else:
+                def call():
+                    return ctx.count_rppi(cols, None, e, 40.0, 40, L, prec, w1=wd,
+                                          options=fopts)
+            for _ in range(args.warmup):
+                c, ws = call()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                c, ws = call()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / args.steps
+            fixed[prec] = ws
+            runs[f"{stat}_{prec}_fixed_sums"] = {
+                "ms_per_step": ms, "value": wref[stat] / (ms / 1e3) / 1e9,
+                "sweep_ms": ctx.stats()["t_sweep_ms"]}
+        if not np.array_equal(fixed["fp32"], fixed["fp64"]):
+            raise SystemExit(f"{stat}: fixed-point weight sums differ between precisions")
         a, b = sums["fp32"][1], sums["fp64"][1]
         nz = b != 0
         runs[f"{stat}_wsum_rel_fp32_vs_fp64"] = float(np.max(np.abs(a[nz] - b[nz]) / np.abs(b[nz])))
@@ -582,6 +609,15 @@ def weighted_bench(args):
         nz = ow != 0
         runs[f"{stat}_wsum_rel_vs_oracle_sampled"] = float(
             np.max(np.abs(gw[nz] - ow[nz]) / np.abs(ow[nz])))
+        det = {"deterministic_weights": 1}
+        if stat == "r":
+            _, fw = ctx.count_r(pts[idx], pts, e, L, "fp32", w1=w[idx], w2=w, options=det)
+        else:
+            _, fw = ctx.count_rppi(pts[idx], pts, e, 40.0, 40, L, "fp32", w1=w[idx], w2=w,
+                                   options=det)
+        if not np.array_equal(fw, ow):
+            raise SystemExit(f"{stat}: fixed-point sums differ from the oracle's")
+        runs[f"{stat}_fixed_sums_equal_oracle_sampled"] = True
     line = {
         "metric": "Gpair-evals/s for weighted xi(r) / wp(rp) counts, N=4e6 periodic L=1100 "
                   "(reference pairs of the paper's cells)",
