@@ -13,20 +13,23 @@
 // j0 .. j1-1 arrive as wave-uniform scalar loads, so each VALU instruction
 // evaluates 64 pairs that share one j.
 //
-// Bin search: a lookup table indexed by the float32 bit pattern of the
-// squared separation (monotone for non-negative values) gives, for most
-// values, the histogram slot directly: slot = bin + 1, with slot 0 and slot
-// nb + 1 catching separations below the first and above the last edge.  Table
-// cells that meet an edge's decision band are flagged and resolved on a rare
-// slow path.
+// Bin search: an LDS lookup table keyed by the squared separation gives, for
+// most values, the histogram slot directly: slot = bin + 1, with slot 0 and
+// slot nb + 1 catching separations below the first and above the last edge.
+// Keys: the float bit pattern (monotone for non-negative values) on the
+// binary64 path; on the float32 path round(min(s, 1) * 32767) (one
+// v_cvt_pknorm_i16_f32) or the linear floor(min(s, cells - 1)) of the
+// private-histogram and 16-bit tables.  Table cells that meet an edge's
+// decision band are flagged and resolved on a rare slow path.
 //
 // Two precisions:
 //  * binary64: dx = fl(x_i - x_j) (+ offset), s = ((dx*dx + dy*dy) + dz*dz),
 //    one rounding per operation -- the definition itself; flagged cells are
 //    resolved by an exact binary64 comparison with the edge.
-//  * float32: differences of box-frame float32 coordinates and fused
-//    multiply-adds; a value inside an edge's error band is not decided but
-//    queued for the binary64 recheck kernel.
+//  * float32: differences of float32 coordinates (x and y in the frame of
+//    the item's j column on 3-D grids, pc_frame.h) and fused multiply-adds; a
+//    value inside an edge's proven error band is not decided in float32 but
+//    re-evaluated from the binary64 coordinates inline (exact_slot).
 #include <hip/hip_runtime.h>
 
 #include "pc_common.h"
