@@ -247,6 +247,9 @@ __global__ void k_cell_index(int ncat, const pc_cat *cats, int64_t ntot, pc_grid
 // ---- exclusive scan (int32), 1024 values per workgroup -------------------
 constexpr int kScanPer = 4;
 constexpr int kScanBlock = kThreads * kScanPer;
+// block totals a k_scan_apply_parts block sums itself (up to 2048 values of
+// loads per block, instead of one more scan launch)
+constexpr int kScanPartsInline = 2048;
 
 __device__ int block_exclusive(int v, int *total)
 {
@@ -276,6 +279,36 @@ __global__ void k_scan_reduce(const int32_t *in, int64_t n, int32_t *part)
     block_exclusive(s, &total);
     if (threadIdx.x == 0)
         part[blockIdx.x] = total;
+}
+
+// Like k_scan_apply below, with the block's offset summed from the block
+// totals `part` (nparts of them, at most a few thousand) by the block itself,
+// so a scan of up to kScanBlock * nparts values takes two launches.
+__global__ void k_scan_apply_parts(const int32_t *in, int64_t n, const int32_t *part,
+                                   int32_t *out)
+{
+    int pre = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kThreads)
+        pre += part[k];
+    int total;
+    block_exclusive(pre, &total);
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int s = 0;
+    for (int k = 0; k < kScanPer; k++) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot2;
+    int run = block_exclusive(s, &tot2) + total;
+    for (int k = 0; k < kScanPer; k++) {
+        if (base + k < n)
+            out[base + k] = run;
+        run += v[k];
+    }
+    const int64_t end = (int64_t)(blockIdx.x + 1) * kScanBlock;
+    if (threadIdx.x == kThreads - 1 && end >= n)
+        out[n] = run;
 }
 
 // out[i] = exclusive prefix + offset[block]; the workgroup holding the end
@@ -1013,6 +1046,12 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    if (nb <= kScanPartsInline) {
+        // each block sums the totals before it itself: no scan of the totals
+        hipLaunchKernelGGL(k_scan_apply_parts, dim3((unsigned)nb), dim3(kThreads), 0, s, in, n,
+                           (const int32_t *)part, out);
+        return hipGetLastError();
+    }
     e = scan_exclusive(s, part, nb, part_scan, tmp + 2 * nb + 1);
     if (e != hipSuccess)
         return e;
