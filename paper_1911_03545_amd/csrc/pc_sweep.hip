@@ -689,10 +689,44 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
 }
 
 // ---- item loops ----------------------------------------------------------
+// A lane's point as the float32 item loop reads it: binary64 x and y (3-D
+// grids with column-local frames) or float32 X and Y, z as the item needs it,
+// and the weight.  Consecutive items of a wave mostly share their block, so
+// the sweep loads this once per block rather than once per item.
+struct LanePt {
+    double x, y, z, w;
+    float X, Y, Z;
+};
+
+template <int M, int W>
+__device__ __forceinline__ LanePt load_lane(const SweepArgs &a, int i, bool act)
+{
+    LanePt p = {0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f, 0.0f};
+    if (!act)
+        return p;
+    if (a.xy_local) {
+        p.x = a.x1[i];
+        p.y = a.y1[i];
+        if (M == PC_METRIC_R)
+            p.z = a.z1[i];
+    } else {
+        p.X = a.X1[i];
+        p.Y = a.Y1[i];
+        if (M == PC_METRIC_R)
+            p.Z = a.Z1[i];
+    }
+    if (M != PC_METRIC_R)
+        p.Z = a.Z1[i];
+    if (W)
+        p.w = a.w1[i];
+    return p;
+}
+
 template <int M, int W, bool TRI, bool T16, bool UNC, bool PK>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                         lds_f64wp whb, int i, bool act, int j0, int j1,
-                                         unsigned dcode, unsigned &rechecks, int jx, int jy)
+                                         lds_f64wp whb, int i, bool act, const LanePt &lp,
+                                         int j0, int j1, unsigned dcode, unsigned &rechecks,
+                                         int jx, int jy)
 {
     const float Lf = a.Lf32;
     const unsigned cx = dcode & 3u, cy = (dcode >> 2) & 3u, cz = (dcode >> 4) & 3u;
@@ -704,17 +738,17 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     if (a.xy_local) {
         // the lane's point (shifted by the item's periodic offset) in the
         // frame of the j column, from its binary64 coordinates, rounded once
-        ax = act ? (float)((a.x1[i] + dval(cx, a.L) - col_centre(a.glo[0], a.gw[0], jx)) *
+        ax = act ? (float)((lp.x + dval(cx, a.L) - col_centre(a.glo[0], a.gw[0], jx)) *
                            a.fscale)
                  : 3.0e30f;
-        ay = act ? (float)((a.y1[i] + dval(cy, a.L) - col_centre(a.glo[1], a.gw[1], jy)) *
+        ay = act ? (float)((lp.y + dval(cy, a.L) - col_centre(a.glo[1], a.gw[1], jy)) *
                            a.fscale)
                  : 3.0e30f;
     } else {
-        ax = act ? a.X1[i] + Dx : 3.0e30f;
-        ay = act ? a.Y1[i] + Dy : 3.0e30f;
+        ax = act ? lp.X + Dx : 3.0e30f;
+        ay = act ? lp.Y + Dy : 3.0e30f;
     }
-    const LaneW wi = lane_weight(a, (W && act) ? a.w1[i] : 0.0);
+    const LaneW wi = lane_weight(a, (W && act) ? lp.w : 0.0);
     // second-catalogue points are wave-uniform: read them through the scalar
     // cache (the arrays are not written during the sweep)
     const kf32p X2 = (kf32p)a.X2, Y2 = (kf32p)a.Y2, Z2 = (kf32p)a.Z2;
@@ -724,7 +758,7 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     if constexpr (M == PC_METRIC_RPPI) {
         // z in fixed point: the periodic z offset is a whole number of quanta
         const unsigned Dq = cz == PC_D_PLUS ? a.B.zq_L : (cz == PC_D_MINUS ? 0u - a.B.zq_L : 0u);
-        const unsigned azq = __float_as_uint(a.Z1[i]) + Dq;
+        const unsigned azq = __float_as_uint(lp.Z) + Dq;
         for (; j + CH <= j1; j += CH) {
             float xs[CH], ys[CH], zs[CH];
             double ws[CH];
@@ -757,9 +791,9 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
     } else {
         float az;
         if (a.xy_local)
-            az = act ? (float)((a.z1[i] + dval(cz, a.L) - a.glo[2]) * a.fscale) : 3.0e30f;
+            az = act ? (float)((lp.z + dval(cz, a.L) - a.glo[2]) * a.fscale) : 3.0e30f;
         else
-            az = act ? a.Z1[i] + Dz : 3.0e30f;
+            az = act ? lp.Z + Dz : 3.0e30f;
         for (; j + CH <= j1; j += CH) {
             float xs[CH], ys[CH], zs[CH];
             double ws[CH];
@@ -1031,6 +1065,9 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     if (a.n_items_dev)
         n_items = min(n_items, __builtin_amdgcn_readfirstlane(*(const volatile int32_t *)a.n_items_dev));
     bool probe = false;
+    // the float32 loop's lane point, kept while consecutive items share a block
+    int lp_i0 = -1, lp_ni = -1;
+    LanePt lp = {0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f, 0.0f};
     int next = wave_fetch(a.counter, n_items, lane, stream, probe);
     pc_item nit = {};
     if (P32 && next < n_items)
@@ -1073,12 +1110,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                 cell_column(__builtin_amdgcn_readfirstlane(((const KCONST int32_t *)a.cs2)[it.j0]),
                             a.gnx, a.gny, a.gnz, &jx, &jy);
             constexpr bool PK = !PRIV && !T16;
+            if (it.i0 != lp_i0 || ni != lp_ni) {
+                lp = load_lane<M, W>(a, i, act);
+                lp_i0 = it.i0;
+                lp_ni = ni;
+            }
             if (tri)
-                item_f32<M, W, true, T16, UNC, PK>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
+                item_f32<M, W, true, T16, UNC, PK>(a, L, hb, whb, i, act, lp, it.j0, it.j1, dcode,
                                                    rechecks, jx, jy);
             else
-                item_f32<M, W, false, T16, UNC, PK>(a, L, hb, whb, i, act, it.j0, it.j1, dcode,
-                                                    rechecks, jx, jy);
+                item_f32<M, W, false, T16, UNC, PK>(a, L, hb, whb, i, act, lp, it.j0, it.j1,
+                                                    dcode, rechecks, jx, jy);
         } else {
             if (tri)
                 item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
