@@ -1072,15 +1072,40 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     pc_item nit = {};
     if (P32 && next < n_items)
         nit = a.items[next];
+    // float32 sweeps also start the take of the item after the next one
+    // before running an item (one atomic increment on the wave's stream,
+    // `pend`), and read its result only at the next item: the round trip
+    // overlaps the item's work
+    int pv = 0;
+    bool pend = false;
     while (next < n_items) {
         // float32 sweeps load the following item's descriptor while this
         // item runs (measured slower for the binary64 sweep, which keeps the
         // load after the take)
         const int cur = next;
         const pc_item it = P32 ? nit : a.items[cur];
-        next = wave_fetch(a.counter, n_items, lane, stream, probe);
+        if (P32 && pend) {
+            pend = false;
+            const int first = (int)(((long long)n_items * stream) / PC_STREAMS);
+            const int len = (int)(((long long)n_items * (stream + 1)) / PC_STREAMS) - first;
+            const int v = __builtin_amdgcn_readfirstlane(pv);
+            if (v < len) {
+                next = first + v;
+            } else {
+                stream = (stream + 1) & (PC_STREAMS - 1);
+                probe = true;
+                next = wave_fetch(a.counter, n_items, lane, stream, probe);
+            }
+        } else {
+            next = wave_fetch(a.counter, n_items, lane, stream, probe);
+        }
         if (P32 && next < n_items)
             nit = a.items[next];
+        if (P32 && next < n_items && !probe) {
+            if (lane == 0)
+                pv = atomicAdd(a.counter + stream * PC_STREAM_STRIDE, 1);
+            pend = true;
+        }
         const int ni = (int)PC_META_NI(it.meta);
         const unsigned dcode = PC_META_DCODE(it.meta);
         const bool tri = PC_META_TRI(it.meta) != 0;
@@ -1132,6 +1157,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                                                       dcode);
         }
     }
+    // the result of a take still in flight (past the last item) is waited
+    // for, not left outstanding (a counter value is never negative)
+    if (P32 && pend && __builtin_amdgcn_readfirstlane(pv) < 0)
+        rechecks++;
     if (PRIV) {
         flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
     } else {
