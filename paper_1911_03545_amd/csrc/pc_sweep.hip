@@ -722,12 +722,14 @@ __device__ __forceinline__ LanePt load_lane(const SweepArgs &a, int i, bool act)
     return p;
 }
 
-template <int M, int W, bool TRI, bool T16, bool UNC, bool PK>
+// CACHED: the caller holds the lane's point (lpc); otherwise it is loaded here.
+template <int M, int W, bool TRI, bool T16, bool UNC, bool PK, bool CACHED>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                         lds_f64wp whb, int i, bool act, const LanePt &lp,
+                                         lds_f64wp whb, int i, bool act, const LanePt &lpc,
                                          int j0, int j1, unsigned dcode, unsigned &rechecks,
                                          int jx, int jy)
 {
+    const LanePt lp = CACHED ? lpc : load_lane<M, W>(a, i, act);
     const float Lf = a.Lf32;
     const unsigned cx = dcode & 3u, cy = (dcode >> 2) & 3u, cz = (dcode >> 4) & 3u;
     const float Dx = cx == PC_D_PLUS ? Lf : (cx == PC_D_MINUS ? -Lf : 0.0f);
@@ -1072,10 +1074,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     pc_item nit = {};
     if (P32 && next < n_items)
         nit = a.items[next];
-    // float32 sweeps also start the take of the item after the next one
-    // before running an item (one atomic increment on the wave's stream,
-    // `pend`), and read its result only at the next item: the round trip
-    // overlaps the item's work
+    // Unweighted float32 r sweeps of one catalogue also start the take of the
+    // item after the next one before running an item (one atomic increment
+    // on the wave's stream, `pend`), read its result only at the next item
+    // (the round trip overlaps the item's work), and keep the lane's point
+    // while consecutive items share a block.  (The registers these hold
+    // across items cost the weighted, rp/pi and private-histogram sweeps more
+    // occupancy than they save.)
+    constexpr bool PIPE = P32 && W == 0 && !PRIV && M == PC_METRIC_R;
     int pv = 0;
     bool pend = false;
     while (next < n_items) {
@@ -1084,7 +1090,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         // load after the take)
         const int cur = next;
         const pc_item it = P32 ? nit : a.items[cur];
-        if (P32 && pend) {
+        if (PIPE && pend) {
             pend = false;
             const int first = (int)(((long long)n_items * stream) / PC_STREAMS);
             const int len = (int)(((long long)n_items * (stream + 1)) / PC_STREAMS) - first;
@@ -1101,7 +1107,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         }
         if (P32 && next < n_items)
             nit = a.items[next];
-        if (P32 && next < n_items && !probe) {
+        if (PIPE && next < n_items && !probe) {
             if (lane == 0)
                 pv = atomicAdd(a.counter + stream * PC_STREAM_STRIDE, 1);
             pend = true;
@@ -1135,17 +1141,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                 cell_column(__builtin_amdgcn_readfirstlane(((const KCONST int32_t *)a.cs2)[it.j0]),
                             a.gnx, a.gny, a.gnz, &jx, &jy);
             constexpr bool PK = !PRIV && !T16;
-            if (it.i0 != lp_i0 || ni != lp_ni) {
+            if (PIPE && (it.i0 != lp_i0 || ni != lp_ni)) {
                 lp = load_lane<M, W>(a, i, act);
                 lp_i0 = it.i0;
                 lp_ni = ni;
             }
             if (tri)
-                item_f32<M, W, true, T16, UNC, PK>(a, L, hb, whb, i, act, lp, it.j0, it.j1, dcode,
-                                                   rechecks, jx, jy);
+                item_f32<M, W, true, T16, UNC, PK, PIPE>(a, L, hb, whb, i, act, lp, it.j0, it.j1,
+                                                         dcode, rechecks, jx, jy);
             else
-                item_f32<M, W, false, T16, UNC, PK>(a, L, hb, whb, i, act, lp, it.j0, it.j1,
-                                                    dcode, rechecks, jx, jy);
+                item_f32<M, W, false, T16, UNC, PK, PIPE>(a, L, hb, whb, i, act, lp, it.j0,
+                                                          it.j1, dcode, rechecks, jx, jy);
         } else {
             if (tri)
                 item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
@@ -1159,7 +1165,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
     }
     // the result of a take still in flight (past the last item) is waited
     // for, not left outstanding (a counter value is never negative)
-    if (P32 && pend && __builtin_amdgcn_readfirstlane(pv) < 0)
+    if (PIPE && pend && __builtin_amdgcn_readfirstlane(pv) < 0)
         rechecks++;
     if (PRIV) {
         flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
