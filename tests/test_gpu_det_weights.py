@@ -153,12 +153,16 @@ def test_batched_exact(pc, olib, prec):
     cats = [synth.clustered_box(n, L, seed=711 + k, nblobs=max(1, n // 200), sigma=1.5)
             for k, n in enumerate(sizes)]
     ws = [weights("signed", n, 720 + k) for k, n in enumerate(sizes)]
-    e = synth.log_edges(0.2, 14.0, 9)
-    got, gw = pc.count_rppi_batch(cats, e, 25.0, 25, L, prec, weights=ws, options=DET)
-    for k, p in enumerate(cats):
-        want, ww = oracle.count_rppi(p, None, e, 25.0, 25, L, w1=ws[k], lib=olib)
-        assert (got[k] == want).all(), k
-        same_bits(gw[k], ww)
+    # (first rp edge zero: each catalogue's self-pair weights join its bin (0, 0))
+    for e in (synth.log_edges(0.2, 14.0, 9), np.r_[0.0, synth.log_edges(0.2, 14.0, 8)]):
+        for wtype in ("product", "sum"):
+            got, gw = pc.count_rppi_batch(cats, e, 25.0, 25, L, prec, weights=ws, options=DET,
+                                          weight_type=wtype)
+            for k, p in enumerate(cats):
+                want, ww = oracle.count_rppi(p, None, e, 25.0, 25, L, w1=ws[k], lib=olib,
+                                             weight_type=wtype)
+                assert (got[k] == want).all(), (k, wtype)
+                same_bits(gw[k], ww)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
