@@ -422,6 +422,67 @@ __global__ __launch_bounds__(kThreads) void k_cell_hist(int ncat, const pc_cat *
         atomicOr(flags, fl);
 }
 
+// Level 1, placement with a chunk-local sort (chunks of kLocalChunk points,
+// at most kThreads columns): one workgroup per chunk first places its
+// records in LDS in (column, rank) order, then writes each column's run of
+// records contiguously to its column-ordered place; the same result as
+// k_col_scatter with writes in runs instead of one 32-byte record per lane
+// anywhere in the output.
+constexpr int kLocalChunk = 2048;
+__global__ __launch_bounds__(kThreads) void k_col_scatter_local(
+    int ncat, const pc_cat *cats, const int32_t *lay, int32_t nz, int32_t ncolc,
+    const int32_t *__restrict__ cell_of, const int32_t *__restrict__ rank_of,
+    const int32_t *__restrict__ wcnt, const int32_t *__restrict__ woff,
+    double4 *__restrict__ colrec, unsigned *flags)
+{
+    __shared__ double4 s_rec[kLocalChunk];
+    __shared__ int s_pos[kLocalChunk];
+    __shared__ int s_loc[kThreads];
+    __shared__ int s_glob[kThreads];
+    const int w = blockIdx.x;
+    int k = 0, hi = ncat - 1;   // the last catalogue whose first chunk is <= w
+    while (k < hi) {
+        const int mid = (k + hi + 1) >> 1;
+        if (lay[3 * mid] <= w)
+            k = mid;
+        else
+            hi = mid - 1;
+    }
+    const pc_cat &ct = cats[k];
+    const int wl = w - lay[3 * k], nw = lay[3 * k + 1], mb = lay[3 * k + 2];
+    const int64_t i0 = ct.off + (int64_t)wl * kLocalChunk;
+    const int n = (int)min((int64_t)kLocalChunk, ct.off + ct.n - i0);
+    // this chunk's count and output place per column, and the local prefix
+    const int c = threadIdx.x;
+    const int cnt = c < ncolc ? wcnt[mb + (int64_t)c * nw + wl] : 0;
+    if (c < ncolc)
+        s_glob[c] = woff[mb + (int64_t)c * nw + wl];
+    int total;
+    const int ex = block_exclusive(cnt, &total);
+    if (c < ncolc)
+        s_loc[c] = ex;
+    __syncthreads();
+    unsigned fl = 0;
+    for (int p = threadIdx.x; p < n; p += kThreads) {
+        const int64_t i = i0 + p;
+        const int64_t j = i - ct.off;
+        const double wt = ct.w ? ld(ct.w, ct.wf32, j) : 1.0;
+        if (!isfinite(wt))
+            fl |= PC_FLAG_WEIGHT;
+        const int col = (int)((uint32_t)cell_of[i] / (uint32_t)nz) - k * ncolc;
+        const int r = rank_of[i];
+        const int slot = s_loc[col] + r;
+        s_rec[slot] = make_double4(ld(ct.x, ct.f32, j), ld(ct.y, ct.f32, j), ld(ct.z, ct.f32, j),
+                                   wt);
+        s_pos[slot] = s_glob[col] + r;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += kThreads)
+        colrec[s_pos[q]] = s_rec[q];
+    if (fl)
+        atomicOr(flags, fl);
+}
+
 // Level 1, placement: every point, as one 32-byte record (x, y, z, w) read
 // from the input columns, to its column-ordered place, so that level 2
 // streams through its column.  Non-finite weights raise a flag here.
@@ -1103,7 +1164,11 @@ hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t nto
         return e;
     if ((e = scan_exclusive(s, wcnt, m, woff, tmp)) != hipSuccess)
         return e;
-    if (ntot > 0)
+    if (ntot > 0 && chunk == kLocalChunk && ncolc <= kThreads && n_chunks > 0)
+        hipLaunchKernelGGL(k_col_scatter_local, dim3((unsigned)n_chunks), dim3(kThreads), 0, s,
+                           ncat, cats, lay, g.n[2], ncolc, cell_of, rank_of, wcnt, woff, cr,
+                           flags);
+    else if (ntot > 0)
         hipLaunchKernelGGL(k_col_scatter, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, ncat,
                            cats, lay, g.n[2], chunk, ncolc, cell_of, rank_of, woff, cr, flags);
     if ((e = hipGetLastError()) != hipSuccess)
