@@ -188,7 +188,23 @@ typedef struct cf_options {
                                    numerator stays a binary64 sum.  0: binary64
                                    atomics (the default; sums then agree with
                                    the exact sum to about 1e-12 relative).     */
-    int32_t reserved;
+    int32_t separation_form;    /* float32 DD(r) and theta-as-chord sweeps of
+                                   3-D grids (no mean separation): how the
+                                   squared separation is formed.  1: from the
+                                   coordinate differences dx^2 + dy^2 + dz^2;
+                                   2: x and y expanded as |a|^2 + |b|^2 -
+                                   2 a.b (|b|^2 stored per point by the
+                                   gridding, -2 a and |a|^2 per lane), one
+                                   instruction fewer per pair, with a larger
+                                   absolute rounding bound (about u times 17
+                                   squared column widths, folded into the
+                                   decision bands, so results stay exact);
+                                   0 (default): 2 when that bound widens the
+                                   band of the smallest nonzero edge by at
+                                   most an eighth of its value, else 1.  Other
+                                   statistics and the binary64 mode ignore
+                                   it.  cf_stats.separation_form reports the
+                                   form used.                                  */
     double *ravg;               /* optional output, same layout and memory kind
                                    as counts: the mean separation of the pairs
                                    in each bin (r, rp, or theta in degrees),
@@ -227,7 +243,9 @@ typedef struct cf_stats {
     int32_t replayed;           /* 1 when the call replayed a recorded graph   */
     int32_t angular_grid;       /* angular grid refinement used (0: 3-D cells) */
     int32_t xy_refine;          /* x/y refinement of a 3-D grid (0: angular)   */
-    int32_t reserved_s;
+    int32_t separation_form;    /* float32 sweep: 1 differences, 2 expanded x
+                                   and y (cf_options.separation_form); 0 when
+                                   no float32 sweep ran                        */
     uint64_t flushes;           /* mid-sweep merges of LDS histogram replicas
                                    forced by the overflow bound (flush_pairs)  */
 } cf_stats;
@@ -450,6 +468,16 @@ cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32_t ndim,
 cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, int32_t ndim,
                              const double *axis_eps, double coord_scale, float *lo,
                              float *hi);
+/* The bands of the expanded form of a 3-D float32 sweep
+   (cf_options.separation_form 2): x and y as t0 = fl(dz dz + Bj), t1 =
+   fl(-2 a_x b_x + t0), t2 = fl(-2 a_y b_y + t1), s = fl(t2 + A) with Bj =
+   fl(b_y b_y + fl(b_x b_x)) and A = fl(a_y a_y + fl(a_x a_x)).  The
+   arithmetic term (ndim + 1) u s' above becomes u (6 s' + 5 |b|^2 + 2 |a|^2
+   + 4 (|a_x b_x| + |a_y b_y|)) (1 + 2^-20) at the largest magnitudes, given
+   as xy_max = {a_x, a_y, b_x, b_y} (the lane's largest |x|, |y| in the j
+   column's frame, the j point's); the coordinate term is unchanged. */
+cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, const double *axis_eps,
+                           const double *xy_max, double coord_scale, float *lo, float *hi);
 
 /* Host-only: the exact sum of n values p[k], each an integer multiple of 2^q
    with |p[k]| < 2^(q + 94), rounded once to binary64 (ties to even), through

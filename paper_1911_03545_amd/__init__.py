@@ -42,7 +42,7 @@ EXPORTED_SYMBOLS = (
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
     "cf_plan_grid", "cf_plan_grid_ex", "cf_plan_sky_grid", "cf_fp32_bands",
-    "cf_fp32_bands_axes",
+    "cf_fp32_bands_axes", "cf_fp32_bands_xy",
     "cf_fixed_sum",
 )
 
@@ -67,7 +67,7 @@ class cf_options(ctypes.Structure):
                 ("weight_type", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
                 ("xy_refine", ctypes.c_int32), ("radec_on_device", ctypes.c_int32),
                 ("flush_pairs", ctypes.c_int32), ("deterministic_weights", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("separation_form", ctypes.c_int32),
                 ("ravg", ctypes.c_void_p)]
 
 
@@ -83,7 +83,7 @@ class cf_stats(ctypes.Structure):
                 ("t_total_ms", ctypes.c_float),
                 ("slices_per_reach", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("replayed", ctypes.c_int32), ("angular_grid", ctypes.c_int32),
-                ("xy_refine", ctypes.c_int32), ("reserved_s", ctypes.c_int32),
+                ("xy_refine", ctypes.c_int32), ("separation_form", ctypes.c_int32),
                 ("flushes", ctypes.c_uint64)]
 
 
@@ -189,6 +189,8 @@ def load_library(path: str = LIB_PATH):
     lib.cf_fp32_bands.restype = ctypes.c_int
     lib.cf_fp32_bands_axes.argtypes = [vp, i32, i32, vp, dbl, vp, vp]
     lib.cf_fp32_bands_axes.restype = ctypes.c_int
+    lib.cf_fp32_bands_xy.argtypes = [vp, i32, vp, vp, dbl, vp, vp]
+    lib.cf_fp32_bands_xy.restype = ctypes.c_int
     lib.cf_fixed_sum.argtypes = [vp, ctypes.c_int64, i32, vp]
     lib.cf_fixed_sum.restype = ctypes.c_int
     _lib = lib
@@ -289,6 +291,25 @@ def fp32_bands_axes(edges_sq, ndim: int, axis_eps, coord_scale: float):
                                 float(coord_scale), lo.ctypes.data, hi.ctypes.data)
     if st != CF_OK:
         raise PairCountError(st, "cf_fp32_bands_axes failed")
+    return lo, hi
+
+
+def fp32_bands_xy(edges_sq, axis_eps, xy_max, coord_scale: float):
+    """Host-only float32 decision bands of a 3-D sweep whose x and y are
+    expanded (|a|^2 + |b|^2 - 2 a.b); xy_max = (a_x, a_y, b_x, b_y), the
+    largest coordinate magnitudes of the lane and of the j point."""
+    lib = load_library()
+    e = np.ascontiguousarray(edges_sq, dtype=np.float64)
+    sc = np.ascontiguousarray(axis_eps, dtype=np.float64)
+    mx = np.ascontiguousarray(xy_max, dtype=np.float64)
+    if sc.size < 3 or mx.size < 4:
+        raise ValueError("three axis bounds and four magnitudes")
+    lo = np.zeros(e.size, dtype=np.float32)
+    hi = np.zeros(e.size, dtype=np.float32)
+    st = lib.cf_fp32_bands_xy(e.ctypes.data, e.size, sc.ctypes.data, mx.ctypes.data,
+                              float(coord_scale), lo.ctypes.data, hi.ctypes.data)
+    if st != CF_OK:
+        raise PairCountError(st, "cf_fp32_bands_xy failed")
     return lo, hi
 
 

@@ -31,7 +31,7 @@ enum BufId {
     B_IN1X, B_IN1Y, B_IN1Z, B_IN1W, B_IN2X, B_IN2Y, B_IN2Z, B_IN2W,
     B_CNT, B_START1, B_START2, B_CELLOF, B_RANKOF, B_PERM, B_REC, B_WOFF, B_LAY, B_COLS,
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
-    B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2,
+    B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2, B_Q1, B_Q2,
     B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
     B_BINS, B_BANDS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_RHIST, B_OUTR, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
     B_COUNT
@@ -492,9 +492,11 @@ cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, bool 
 // Grid the catalogues of one side: cell index -> scan -> scatter.  Cells of
 // catalogue k are k * ncell .. (k + 1) * ncell - 1, so the sorted arrays hold
 // the catalogues one after the other, each in cell order.
+// Q (or B_COUNT: none): (x, y, z, |b|^2) in float32 of every sorted point,
+// side by side, for sweeps that expand x and y (X, Y, Z are then not written)
 cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool weighted,
                     const pc_grid &g, BufId start, BufId X, BufId Y, BufId Z, BufId XD, BufId YD,
-                    BufId ZD, BufId WD, BufId CS, unsigned *flags)
+                    BufId ZD, BufId WD, BufId CS, BufId Q, unsigned *flags)
 {
     const int64_t n = s.ntot;
     const int64_t ncells = (int64_t)s.ncat * g.ncell;
@@ -516,6 +518,9 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
         return st;
     if (weighted && (st = ensure(c, WD, sizeof(double) * (size_t)n)))
         return st;
+    if (Q != B_COUNT && (st = ensure(c, Q, 4 * sizeof(float) * (size_t)n)))
+        return st;
+    float4 *qd = Q != B_COUNT ? static_cast<float4 *>(c->buf[Q].p) : nullptr;
     // Two-level counting sort when the columns of a catalogue and the z
     // slices of a column fit an LDS histogram: chunks of at least 2048
     // points (and 8 per column, bounding the count matrix by n / 8 + ...)
@@ -544,7 +549,7 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
                                 dptr<int32_t>(c, CS), dptr<float>(c, X), dptr<float>(c, Y),
                                 dptr<float>(c, Z), dptr<double>(c, XD), dptr<double>(c, YD),
                                 dptr<double>(c, ZD), weighted ? dptr<double>(c, WD) : nullptr,
-                                flags));
+                                qd, flags));
         return CF_OK;
     }
     HIPCHK(pc::launch_zero(c->stream, c->buf[B_CNT].p, sizeof(int32_t) * (size_t)ncells));
@@ -558,7 +563,8 @@ cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool w
                               dptr<int32_t>(c, start), dptr<int32_t>(c, B_PERM),
                               dptr<float>(c, X), dptr<float>(c, Y), dptr<float>(c, Z),
                               dptr<double>(c, XD), dptr<double>(c, YD), dptr<double>(c, ZD),
-                              weighted ? dptr<double>(c, WD) : nullptr, dptr<int32_t>(c, CS)));
+                              weighted ? dptr<double>(c, WD) : nullptr, qd,
+                              dptr<int32_t>(c, CS)));
     return CF_OK;
 }
 
@@ -652,6 +658,8 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if (opt.weight_type != CF_WEIGHT_PRODUCT && !user_w)
         return fail(c, CF_EINVAL, "summed pair weights need weights");
     const bool want_ravg = opt.ravg != nullptr;
+    if (opt.separation_form < 0 || opt.separation_form > 2)
+        return fail(c, CF_EINVAL, "separation_form must be 0, 1 or 2");
     // the sweep carries weights when the caller gives them or asks for the
     // mean separation (unit weights then, whose sums are the counts)
     const bool weighted = user_w || want_ravg;
@@ -887,10 +895,28 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         pc::frame_eps((g.xyk + 0.5) * g.width[0], 0.5 * g.width[0], scale),
         pc::frame_eps((g.xyk + 0.5) * g.width[1], 0.5 * g.width[1], scale),
         pc::frame_eps(scale + reach_z, scale, scale)};
+    // Float32 DD(r) (and chords) of 3-D grids without the mean separation:
+    // x and y expanded as |a|^2 + |b|^2 - 2 a.b, one instruction fewer per
+    // pair, unless its absolute rounding term would widen the band of the
+    // smallest nonzero edge by more than an eighth of that edge (the float32
+    // mean separation takes the square root of s and keeps the differences)
+    double xy_mag = 0.0;
+    if (fp32 && g.xy_local && metric == PC_METRIC_R && !want_ravg && opt.separation_form != 1) {
+        const double am[2] = {(g.xyk + 0.5) * g.width[0], (g.xyk + 0.5) * g.width[1]};
+        const double bm[2] = {0.5 * g.width[0], 0.5 * g.width[1]};
+        const double mag = pc::xy_expand_mag(am, bm);
+        double emin = INFINITY;
+        for (int k = 0; k <= nb; k++)
+            if (lin[k] > 0.0)
+                emin = std::min(emin, lin[k] * lin[k]);
+        if (opt.separation_form == 2 || 1.25 * 0x1p-24 * mag <= 0.125 * emin)
+            xy_mag = mag;
+    }
     // batches: private per-wave histograms, flushed per catalogue
     const bool priv = ncat > 1;
     double fscale = 1.0;
-    if (fp32 && (rc = pc::fp32_scale(metric, lin.data(), nb, scale, priv, &fscale)))
+    if (fp32 && (rc = pc::fp32_scale(metric, lin.data(), nb, scale, priv,
+                                     g.xy_local ? axis_eps : nullptr, xy_mag, &fscale)))
         return fail(c, (cf_status)rc, "float32 scaling failed");
     g.fscale = fscale;
     record(c, timing, 1);
@@ -939,12 +965,14 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     }
 
     // ---- grid ------------------------------------------------------------
+    // (|b|^2 for the expanded form: on the j side only)
     if ((st2 = grid_side(c, s1, cats1_dev, weighted, g, B_START1, B_X1, B_Y1, B_Z1, B_XD1, B_YD1,
-                         B_ZD1, B_WD1, B_CS1, flags)))
+                         B_ZD1, B_WD1, B_CS1, (xy_mag > 0.0 && autocorr) ? B_Q1 : B_COUNT,
+                         flags)))
         return st2;
     if (!autocorr &&
         (st2 = grid_side(c, s2, cats2_dev, weighted, g, B_START2, B_X2, B_Y2, B_Z2, B_XD2,
-                         B_YD2, B_ZD2, B_WD2, B_CS2, flags)))
+                         B_YD2, B_ZD2, B_WD2, B_CS2, xy_mag > 0.0 ? B_Q2 : B_COUNT, flags)))
         return st2;
     // fixed-point weight sums: the grid 2^Q of this call's pair weights
     pc::pc_wfixed *wfx = wfixed ? (pc::pc_wfixed *)(misc(c) + M_WFIX) : nullptr;
@@ -958,7 +986,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     pc::HostBins hb;
     // on-sky pairs bin (rp, pi) like the Cartesian statistic
     rc = pc::build_bins(sky ? PC_METRIC_RPPI : metric, fp32, lin.data(), nb, pimax, npi, scale,
-                        g.xy_local ? axis_eps : nullptr, fscale, priv, &hb);
+                        g.xy_local ? axis_eps : nullptr, fscale, priv, xy_mag, &hb);
     if (rc)
         return fail(c, (cf_status)rc, "bin description failed");
     if (g.zq_shift > 0) {
@@ -1093,6 +1121,9 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.rq_count = (unsigned *)(misc(c) + M_RQCOUNT);
     a.flush_count = (unsigned *)(misc(c) + M_FLUSH);
     a.xy_local = g.xy_local;
+    a.xy_exp = xy_mag > 0.0 ? 1 : 0;
+    a.P2 = xy_mag > 0.0 ? static_cast<const float4 *>(c->buf[autocorr ? B_Q1 : B_Q2].p)
+                        : nullptr;
     a.gnx = g.n[0];
     a.gny = g.n[1];
     a.gnz = g.n[2];
@@ -1172,13 +1203,14 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     const int wmode = weighted ? (want_ravg ? 2 : 1) : 0;
     {
         const std::vector<int64_t> ok = {metric, fp32 ? 1 : 0, wmode, hb.hdr.tbl_wide != 0 ? 1 : 0,
-                                         copies == PC_WAVE ? 1 : 0, priv ? 1 : 0, off};
+                                         copies == PC_WAVE ? 1 : 0, priv ? 1 : 0, off,
+                                         xy_mag > 0.0 ? 1 : 0};
         auto it = c->occupancy.find(ok);
         if (it != c->occupancy.end()) {
             per_cu = it->second;
         } else {
             HIPCHK(pc::sweep_occupancy(metric, fp32, wmode, hb.hdr.tbl_wide != 0,
-                                       copies == PC_WAVE, priv, off, &per_cu));
+                                       copies == PC_WAVE, priv, xy_mag > 0.0, off, &per_cu));
             c->occupancy[ok] = per_cu;
         }
     }
@@ -1309,6 +1341,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     S.slices_per_reach = opt.slices_per_reach;
     S.angular_grid = opt.angular_grid;
     S.xy_refine = sky_grid ? 0 : g.xyk;
+    S.separation_form = fp32 ? (xy_mag > 0.0 ? 2 : 1) : 0;
     S.chunk = chunk;
     S.n_blocks = hcounts[1];
     S.n_items = hcounts[0];

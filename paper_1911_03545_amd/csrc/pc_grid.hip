@@ -562,21 +562,32 @@ __device__ int block_exclusive_waves(int v, int *total)
 // point on the float32 rp/pi path) and the binary64 values.
 __device__ __forceinline__ void store_sorted(const pc_grid &g, const double4 &r, int cell,
                                              int64_t d, float *X, float *Y, float *Z,
-                                             double *xd, double *yd, double *zd, double *wd)
+                                             double *xd, double *yd, double *zd, double *wd,
+                                             float4 *P)
 {
+    float fx, fy, fz;
     if (g.xy_local) {
         int ix, iy;
         cell_column(cell, g.n[0], g.n[1], g.n[2], &ix, &iy);
-        X[d] = (float)((r.x - col_centre(g.lo[0], g.width[0], ix)) * g.fscale);
-        Y[d] = (float)((r.y - col_centre(g.lo[1], g.width[1], iy)) * g.fscale);
+        fx = (float)((r.x - col_centre(g.lo[0], g.width[0], ix)) * g.fscale);
+        fy = (float)((r.y - col_centre(g.lo[1], g.width[1], iy)) * g.fscale);
     } else {
-        X[d] = (float)((r.x - g.lo[0]) * g.fscale);
-        Y[d] = (float)((r.y - g.lo[1]) * g.fscale);
+        fx = (float)((r.x - g.lo[0]) * g.fscale);
+        fy = (float)((r.y - g.lo[1]) * g.fscale);
     }
     if (g.zq_shift > 0)
-        Z[d] = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
+        fz = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
     else
-        Z[d] = (float)((r.z - g.lo[2]) * g.fscale);
+        fz = (float)((r.z - g.lo[2]) * g.fscale);
+    if (P) {
+        // the expanded form's j points: x, y, z and |b|^2 = fl(y y + fl(x x)),
+        // rounded as the sweep's bound assumes, side by side
+        P[d] = make_float4(fx, fy, fz, __fmaf_rn(fy, fy, __fmul_rn(fx, fx)));
+    } else {
+        X[d] = fx;
+        Y[d] = fy;
+        Z[d] = fz;
+    }
     xd[d] = r.x;
     yd[d] = r.y;
     zd[d] = r.z;
@@ -697,7 +708,7 @@ __global__ void k_perm(int64_t ntot, const int32_t *cell_of, const int32_t *rank
 constexpr int kXcds = 8;
 __global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int32_t *cell_of,
                          const double4 *rec, float *X, float *Y, float *Z, double *xd, double *yd,
-                         double *zd, double *wd, int32_t *cell_sorted)
+                         double *zd, double *wd, float4 *P, int32_t *cell_sorted)
 {
     const int per = (int)(gridDim.x / kXcds);   // gridDim.x is a multiple of kXcds
     const int lb = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
@@ -706,7 +717,7 @@ __global__ void k_gather(int64_t ntot, pc_grid g, const int32_t *perm, const int
         const int64_t i = perm[d];
         const double4 r = rec[i];
         const int cell = cell_of ? cell_of[i] : cell_sorted[d];
-        store_sorted(g, r, cell, d, X, Y, Z, xd, yd, zd, wd);
+        store_sorted(g, r, cell, d, X, Y, Z, xd, yd, zd, wd, P);
         if (cell_of)
             cell_sorted[d] = cell;
     }
@@ -1148,20 +1159,21 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
 hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *cell_of,
                           const int32_t *rank_of, const void *rec, const int32_t *start,
                           int32_t *perm, float *X, float *Y, float *Z, double *xd, double *yd,
-                          double *zd, double *wd, int32_t *cell_sorted)
+                          double *zd, double *wd, float4 *P, int32_t *cell_sorted)
 {
     hipLaunchKernelGGL(k_perm, dim3(grid_for(ntot)), dim3(kThreads), 0, s, ntot, cell_of, rank_of,
                        start, perm);
-    return launch_gather(s, ntot, g, perm, cell_of, rec, X, Y, Z, xd, yd, zd, wd, cell_sorted);
+    return launch_gather(s, ntot, g, perm, cell_of, rec, X, Y, Z, xd, yd, zd, wd, P, cell_sorted);
 }
 
 hipError_t launch_gather(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *perm,
                          const int32_t *cell_of, const void *rec, float *X, float *Y, float *Z,
-                         double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted)
+                         double *xd, double *yd, double *zd, double *wd, float4 *P,
+                         int32_t *cell_sorted)
 {
     const int gw = (grid_for(ntot) + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL(k_gather, dim3(gw), dim3(kThreads), 0, s, ntot, g, perm,
-                       cell_of, static_cast<const double4 *>(rec), X, Y, Z, xd, yd, zd, wd,
+                       cell_of, static_cast<const double4 *>(rec), X, Y, Z, xd, yd, zd, wd, P,
                        cell_sorted);
     return hipGetLastError();
 }
@@ -1171,7 +1183,7 @@ hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t nto
                         int64_t m, int32_t *lay, int32_t *wcnt, int32_t *woff, int32_t *tmp,
                         int32_t *cell_of, int32_t *rank_of, void *colrec, void *rank_slice,
                         int32_t *perm, int32_t *start, int32_t *cell_sorted, float *X, float *Y,
-                        float *Z, double *xd, double *yd, double *zd, double *wd,
+                        float *Z, double *xd, double *yd, double *zd, double *wd, float4 *P,
                         unsigned *flags)
 {
     double4 *cr = static_cast<double4 *>(colrec);
@@ -1207,7 +1219,7 @@ hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t nto
                        static_cast<int2 *>(rank_slice), start, perm, cell_sorted);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    return launch_gather(s, ntot, g, perm, nullptr, colrec, X, Y, Z, xd, yd, zd, wd,
+    return launch_gather(s, ntot, g, perm, nullptr, colrec, X, Y, Z, xd, yd, zd, wd, P,
                          cell_sorted);
 }
 

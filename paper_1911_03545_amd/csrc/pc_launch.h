@@ -54,6 +54,11 @@ struct SweepArgs {
     // (pc_frame.h); each lane's point is placed in the frame of the item's j
     // column, found from the cell id of the item's first j point
     int32_t xy_local;
+    // float32 DD(r) of 3-D grids: x and y expanded as |a|^2 + |b|^2 - 2 a.b,
+    // with P2 = (x, y, z, |b|^2) of every sorted point of side 2 in float32
+    // (X2, Y2 and Z2 are then not written)
+    int32_t xy_exp;
+    const float4 *P2;
     int32_t gnx, gny, gnz;
     double glo[3];
     double gw[2];
@@ -99,16 +104,20 @@ size_t scan_tmp_elems(int64_t n);
 hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *out,
                           int32_t *tmp);
 // place every point at start[cell] + rank: a permutation scatter of source
-// indices into `perm` (ntot int32), then a gather in sorted order
+// indices into `perm` (ntot int32), then a gather in sorted order.  P
+// (optional; the expanded float32 r sweep): the float32 x, y, z and
+// fl(y y + fl(x x)) of every sorted point side by side, written in place of
+// X, Y and Z.
 hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *cell_of,
                           const int32_t *rank_of, const void *rec, const int32_t *start,
                           int32_t *perm, float *X, float *Y, float *Z, double *xd, double *yd,
-                          double *zd, double *wd, int32_t *cell_sorted);
+                          double *zd, double *wd, float4 *P, int32_t *cell_sorted);
 // the gather half of launch_scatter (perm already known; with cell_of NULL
 // the cell ids of the sorted points are left as they are)
 hipError_t launch_gather(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *perm,
                          const int32_t *cell_of, const void *rec, float *X, float *Y, float *Z,
-                         double *xd, double *yd, double *zd, double *wd, int32_t *cell_sorted);
+                         double *xd, double *yd, double *zd, double *wd, float4 *P,
+                         int32_t *cell_sorted);
 // Two-level counting sort without global atomics (columns in LDS per chunk of
 // `chunk` points, then z slices in LDS per column) followed by the gather
 // into the sorted arrays: start (ncat * ncell + 1), cell_sorted, X, Y, Z, xd,
@@ -124,7 +133,7 @@ hipError_t launch_sort2(hipStream_t s, int ncat, const pc_cat *cats, int64_t nto
                         int64_t m, int32_t *lay, int32_t *wcnt, int32_t *woff, int32_t *tmp,
                         int32_t *cell_of, int32_t *rank_of, void *colrec, void *rank_slice,
                         int32_t *perm, int32_t *start, int32_t *cell_sorted, float *X, float *Y,
-                        float *Z, double *xd, double *yd, double *zd, double *wd,
+                        float *Z, double *xd, double *yd, double *zd, double *wd, float4 *P,
                         unsigned *flags);
 hipError_t launch_block_count(hipStream_t s, int32_t ncol, int32_t nz, const int32_t *start,
                               int32_t *bcnt);
@@ -171,8 +180,9 @@ hipError_t launch_finalize(hipStream_t s, int32_t ncat, int32_t nbt, int autocor
 // resident sweep workgroups per CU for a dynamic LDS size
 // waves per sweep workgroup
 int sweep_waves();
+// (exp: the float32 r sweep with x and y expanded)
 hipError_t sweep_occupancy(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv,
-                           int lds_bytes, int *per_cu);
+                           bool exp, int lds_bytes, int *per_cu);
 // device address and size of the fixed scratch of the no-allocation entry
 // point on `device`, which must be the current device (looked up once per
 // device, then cached)

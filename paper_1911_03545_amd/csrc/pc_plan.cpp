@@ -305,9 +305,32 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
 // outward to float32, with B the sum of both bounds times kSafety.  Because
 // B grows slower than s, a float32 value below the band proves s64 < E and
 // one above proves s64 > E.
-int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
-                    double scale, float *lo, float *hi)
+//
+// Expanded x and y (xy_mag > 0): the sweep forms
+//   t0 = fl(dz dz + Bj), t1 = fl(-2 a_x b_x + t0), t2 = fl(-2 a_y b_y + t1),
+//   s32 = fl(t2 + A)
+// with Bj = fl(b_y b_y + fl(b_x b_x)) stored per point and A = fl(a_y a_y +
+// fl(a_x a_x)) per lane (-2 a is exact), whose exact value at the rounded
+// coordinates is the same sum of squared differences.  With
+// |Bj - |b|^2| <= 2u |b|^2, |A - |a|^2| <= 2u |a|^2, |dz^2 - dz*^2| <= 2u s',
+// |t0| <= s' + |b|^2, |t1| <= |t0| + 2|a_x b_x|, |t2| <= |t1| + 2|a_y b_y|
+// (to first order), the arithmetic part of the bound becomes
+//   u (6 s' + 5 |b|^2 + 2 |a|^2 + 4 (|a_x b_x| + |a_y b_y|)) (1 + 2^-20),
+// the magnitudes taken at their maxima (xy_mag, xy_expand_mag) in place of
+// (ndim + 1) u s'; the coordinate part stays as above (it also covers the
+// rounding of x and y differences, which the expanded form does not make).
+double xy_expand_mag(const double a_max[2], const double b_max[2])
 {
+    const double g = 1.0 + 0x1p-16;   // points a rounding outside their column
+    const double ax = a_max[0] * g, ay = a_max[1] * g, bx = b_max[0] * g, by = b_max[1] * g;
+    return 5.0 * (bx * bx + by * by) + 2.0 * (ax * ax + ay * ay) + 4.0 * (ax * bx + ay * by);
+}
+
+int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
+                    double scale, float *lo, float *hi, double xy_mag)
+{
+    if (!(xy_mag >= 0.0) || !isfinite(xy_mag) || (xy_mag > 0.0 && ndim != 3))
+        return CF_EINVAL;
     if (nedges < 1 || ndim < 1 || ndim > 3 || !(scale >= 0.0) || !isfinite(scale))
         return CF_EINVAL;
     double eps[3];
@@ -338,8 +361,10 @@ int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *
                 sum2 += dl * dl;
             }
             const double s_hi = E + 2.0 * r * sqrt(sum2) + sum2;
-            B = 2.0 * r * sqrt(sum2) + sum2 + (ndim + 1) * kU32 * s_hi +
-                (ndim + 1) * kU64 * s_hi;
+            const double arith = xy_mag > 0.0
+                                     ? kU32 * (6.0 * s_hi + xy_mag) * (1.0 + 0x1p-20)
+                                     : (ndim + 1) * kU32 * s_hi;
+            B = 2.0 * r * sqrt(sum2) + sum2 + arith + (ndim + 1) * kU64 * s_hi;
         }
         B = B * kSafety + 1e-300;
         lo[k] = float_down(E - B);
@@ -453,7 +478,7 @@ static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 // coordinate is rounded once from its binary64 scaled value either way, and
 // the decision bands are scaled by c^2 and rounded outward.
 int fp32_scale(int metric, const double *edges, int nb, double coord_scale, bool priv,
-               double *c_out)
+               const double *axis_eps, double xy_mag, double *c_out)
 {
     const double E = edges[nb] * edges[nb];
     float lo, hi;
@@ -461,6 +486,13 @@ int fp32_scale(int metric, const double *edges, int nb, double coord_scale, bool
     int rc = fp32_bands(&E, 1, ndim, coord_scale, &lo, &hi);
     if (rc)
         return rc;
+    if (axis_eps) {
+        // the top band the sweep will use, when it is the wider one
+        float lo2, hi2;
+        if ((rc = fp32_bands_axes(&E, 1, ndim, axis_eps, coord_scale, &lo2, &hi2, xy_mag)))
+            return rc;
+        hi = std::max(hi, hi2);
+    }
     if (!(hi > 0.0f) || !std::isfinite(hi))
         return CF_EINVAL;
     double c = std::sqrt(key_top(nb, priv) * (1.0 - 0x1p-16) / (double)hi);
@@ -475,7 +507,7 @@ int fp32_scale(int metric, const double *edges, int nb, double coord_scale, bool
 
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
                int npi, double coord_scale, const double *axis_eps, double fscale, bool priv,
-               HostBins *out)
+               double xy_mag, HostBins *out)
 {
     if (!fp32)
         fscale = 1.0;
@@ -500,7 +532,7 @@ int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax,
         const double e = 6.0 * kU32 * coord_scale;
         const double e3[3] = {e, e, e};
         rc = fp32_bands_axes(E.data(), ne, ndim, axis_eps ? axis_eps : e3, coord_scale,
-                             lo.data(), hi.data());
+                             lo.data(), hi.data(), axis_eps ? xy_mag : 0.0);
         if (rc)
             return rc;
     } else {
@@ -741,6 +773,20 @@ extern "C" cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, 
         return CF_EINVAL;
     return (cf_status)pc::fp32_bands_axes(edges_sq, nedges, ndim, axis_eps, coord_scale, lo,
                                           hi);
+}
+
+extern "C" cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges,
+                                      const double *axis_eps, const double *xy_max,
+                                      double coord_scale, float *lo, float *hi)
+{
+    if (!edges_sq || !axis_eps || !xy_max || !lo || !hi)
+        return CF_EINVAL;
+    for (int k = 0; k < 4; k++)
+        if (!(xy_max[k] >= 0.0) || !std::isfinite(xy_max[k]))
+            return CF_EINVAL;
+    const double mag = pc::xy_expand_mag(xy_max, xy_max + 2);
+    return (cf_status)pc::fp32_bands_axes(edges_sq, nedges, 3, axis_eps, coord_scale, lo, hi,
+                                          mag > 0.0 ? mag : 0x1p-1000);
 }
 
 // Host twin of the fixed-point weight sums (pc_fixed.h): the same limb split,

@@ -26,19 +26,25 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
                   pc_grid *g, std::vector<pc_band> *bands);
 int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
                float *hi);
-// per-axis rounding bounds of the two float32 coordinates (ndim values)
+// per-axis rounding bounds of the two float32 coordinates (ndim values);
+// xy_mag > 0 (ndim 3): the float32 sweep expands x and y as |a|^2 + |b|^2 -
+// 2 a.b, with xy_mag = xy_expand_mag of the coordinates' maxima
 int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
-                    double scale, float *lo, float *hi);
+                    double scale, float *lo, float *hi, double xy_mag = 0.0);
+// magnitude term of the expanded x and y: a_max = the lane's largest |x|, |y|
+// in the j column's frame, b_max = the j point's
+double xy_expand_mag(const double a_max[2], const double b_max[2]);
 // rounding bound of one column-local axis: coordinates at most a_max and
 // b_max from the frame origin, each rounded once from binary64
 double frame_eps(double a_max, double b_max, double scale);
 // `priv`: size the lookup table for the private-histogram (batched) sweep
+// (axis_eps and xy_mag, when given: the sweep's own top band also fits)
 int fp32_scale(int metric, const double *edges, int nb, double coord_scale, bool priv,
-               double *c);
+               const double *axis_eps, double xy_mag, double *c);
 // axis_eps (optional, x y z): per-axis rounding bounds (else box-frame 6 u S);
 // fscale: the float32 coordinate scale (bands are moved into it)
 int build_bins(int metric, bool fp32, const double *edges, int nb, double pimax, int npi,
                double coord_scale, const double *axis_eps, double fscale, bool priv,
-               HostBins *out);
+               double xy_mag, HostBins *out);
 
 }  // namespace pc

@@ -389,6 +389,25 @@ __device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int 
     return row * a.B.row_w + col;
 }
 
+// A lane's point as the float32 item loop reads it: binary64 x and y (3-D
+// grids with column-local frames) or float32 X and Y, z as the item needs it,
+// and the weight.  Consecutive items of a wave mostly share their block, so
+// the sweep loads this once per block rather than once per item.
+struct LanePt {
+    double x, y, z, w;
+    float X, Y, Z;
+};
+
+// Binary64 slot of an r pair whose lane point (binary64) is at hand.
+__device__ __forceinline__ int exact_slot_r_at(const SweepArgs &a, const Lds &L, double xi,
+                                               double yi, double zi, int j, unsigned dcode)
+{
+    const kf64p x2 = (kf64p)a.x2, y2 = (kf64p)a.y2, z2 = (kf64p)a.z2;
+    double s, pz;
+    exact_sep<PC_METRIC_R>(xi, yi, zi, x2[j], y2[j], z2[j], dcode, a.L, &s, &pz);
+    return exact_bin<PC_METRIC_R>(s, pz, L.E, a.B.nb, L.q, 1, 0.0) + 1;
+}
+
 // ---- float32 chunk: CH pairs sharing lane i ------------------------------
 // Three phases so that the CH table reads are in flight together: (1)
 // separations, candidate masks and table keys, (2) table reads, (3) slot
@@ -398,12 +417,18 @@ __device__ __forceinline__ int exact_slot(const SweepArgs &a, const Lds &L, int 
 // unweighted 1-D statistics.
 // MASK: the item's last, partial chunk; pairs k >= rem are padding (their
 // loads repeat the item's last point) and are sent out of range.
-template <int M, int W, bool TRI, bool T16, bool UNC, bool PK, int CH, bool MASK = false>
+// EXP: x and y expanded, s = fl(fl(fl(fl(dz dz + |b|^2) - 2 a_x b_x) -
+// 2 a_y b_y) + |a|^2) with qs = |b|^2 of the j points, ax and ay holding
+// -2 a_x and -2 a_y, and A = |a|^2: four instructions instead of six, with
+// the rounding bound the planner's expanded bands assume.
+template <int M, int W, bool TRI, bool T16, bool UNC, bool PK, int CH, bool MASK = false,
+          bool EXP = false>
 __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                          lds_f64wp whb, float ax, float ay, float az,
-                                          LaneW wi, int i, const float *xs, const float *ys,
-                                          const float *zs, const double *ws, int j,
-                                          unsigned dcode, unsigned &rechecks, int rem = CH)
+                                          lds_f64wp whb, float ax, float ay, float az, float A,
+                                          LaneW wi, int i, const LanePt &lp, const float *xs,
+                                          const float *ys, const float *zs, const float *qs,
+                                          const double *ws, int j, unsigned dcode,
+                                          unsigned &rechecks, int rem = CH)
 {
     static_assert(M == PC_METRIC_R, "float32 rp/pi pairs take the fixed-point chunk");
     float s[CH];
@@ -413,8 +438,16 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
     const float kmax = key_top_value<PK>(a);
 #pragma unroll
     for (int k = 0; k < CH; k++) {
-        const float dx = ax - xs[k], dy = ay - ys[k], dz = az - zs[k];
-        s[k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if constexpr (EXP) {
+            const float dz = az - zs[k];
+            float t = fmaf(dz, dz, qs[k]);
+            t = fmaf(ax, xs[k], t);
+            t = fmaf(ay, ys[k], t);
+            s[k] = t + A;
+        } else {
+            const float dx = ax - xs[k], dy = ay - ys[k], dz = az - zs[k];
+            s[k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        }
         c[k] = s[k] <= a.B.s_top;
         if (TRI) {
             c[k] = c[k] && (j + k > i);
@@ -430,10 +463,21 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         }
         key[k] = tbl_key_f32<PK>(s[k], kmax);
     }
-    // every lane reads (no exec-mask changes), so the CH reads stay in flight
+    // every lane reads (no exec-mask changes), so the CH reads stay in flight;
+    // byte entries of the unconditional path are read unsigned (a flagged
+    // cell has bit 7 set)
+    constexpr bool U8 = UNC && !T16;
 #pragma unroll
     for (int k = 0; k < CH; k++)
-        e[k] = tbl_entry<T16>(L, key[k]);
+        e[k] = U8 ? (int)((const LDS unsigned char *)L.tbl)[key[k]] : tbl_entry<T16>(L, key[k]);
+    if constexpr (U8) {
+        // keep the entries as the zero-extended words the or below takes
+        // (otherwise one is read sign-extended for the per-pair tests and
+        // masked back for the or: one instruction more per chunk)
+#pragma unroll
+        for (int k = 0; k < CH; k++)
+            asm volatile("" : "+v"(e[k]));
+    }
     if (UNC) {
         // M == PC_METRIC_R, unweighted.  One test for the whole chunk: the
         // slow flags of all CH entries are or-ed together, so the per-pair
@@ -442,13 +486,16 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
 #pragma unroll
         for (int k = 0; k < CH; k++)
             any |= (unsigned)e[k];
-        if (is_slow<T16>((int)any)) {
+        if (U8 ? any >= PC_TBL8_BAND : is_slow<T16>((int)any)) {
 #pragma unroll
             for (int k = 0; k < CH; k++) {
-                if (is_slow<T16>(e[k])) {
+                if (U8 ? (unsigned)e[k] >= PC_TBL8_BAND : is_slow<T16>(e[k])) {
                     int slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
                     if (slot < 0) {
-                        slot = exact_slot<M>(a, L, i, j + k, dcode);
+                        // (the expanded form runs on 3-D grids, whose lane
+                        // point holds the binary64 coordinates)
+                        slot = EXP ? exact_slot_r_at(a, L, lp.x, lp.y, lp.z, j + k, dcode)
+                                   : exact_slot<M>(a, L, i, j + k, dcode);
                         rechecks++;
                     }
                     e[k] = slot;
@@ -468,7 +515,8 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         if (is_slow<T16>(e[k])) {
             slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
             if (slot < 0) {
-                slot = exact_slot<M>(a, L, i, j + k, dcode);
+                slot = EXP ? exact_slot_r_at(a, L, lp.x, lp.y, lp.z, j + k, dcode)
+                           : exact_slot<M>(a, L, i, j + k, dcode);
                 rechecks++;
             }
         }
@@ -689,14 +737,70 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
 }
 
 // ---- item loops ----------------------------------------------------------
-// A lane's point as the float32 item loop reads it: binary64 x and y (3-D
-// grids with column-local frames) or float32 X and Y, z as the item needs it,
-// and the weight.  Consecutive items of a wave mostly share their block, so
-// the sweep loads this once per block rather than once per item.
-struct LanePt {
-    double x, y, z, w;
-    float X, Y, Z;
-};
+// The float32 r pairs of one item: chunks of CH j points, then the partial
+// last chunk padded with the item's last point.  Second-catalogue points are
+// wave-uniform and read through the scalar cache (the arrays are not written
+// during the sweep); the expanded form reads them as (x, y, z, |b|^2) side
+// by side, two 64-byte scalar loads per chunk from one base address.
+template <int W, bool TRI, bool T16, bool UNC, bool PK, int CH, bool EXP>
+__device__ __forceinline__ void r_loop(const SweepArgs &a, const Lds &L, lds_u32p hb,
+                                       lds_f64wp whb, float ax, float ay, float az, float A,
+                                       LaneW wi, int i, const LanePt &lp, int j0, int j1,
+                                       unsigned dcode, unsigned &rechecks)
+{
+    const kf32p X2 = (kf32p)a.X2, Y2 = (kf32p)a.Y2, Z2 = (kf32p)a.Z2;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const KCONST v4f *P2 = (const KCONST v4f *)a.P2;   // (x, y, z, |b|^2) per point
+    const kf64p w2 = (kf64p)a.w2;
+    int j = j0;
+    for (; j + CH <= j1; j += CH) {
+        float xs[CH], ys[CH], zs[CH], qs[CH];
+        double ws[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if constexpr (EXP) {
+                const v4f p = P2[j + k];
+                xs[k] = p.x;
+                ys[k] = p.y;
+                zs[k] = p.z;
+                qs[k] = p.w;
+            } else {
+                xs[k] = X2[j + k];
+                ys[k] = Y2[j + k];
+                zs[k] = Z2[j + k];
+                qs[k] = 0.0f;
+            }
+            ws[k] = W ? w2[j + k] : 0.0;
+        }
+        chunk_f32<PC_METRIC_R, W, TRI, T16, UNC, PK, CH, false, EXP>(
+            a, L, hb, whb, ax, ay, az, A, wi, i, lp, xs, ys, zs, qs, ws, j, dcode, rechecks);
+    }
+    if (j < j1) {
+        const int rem = j1 - j;
+        float xs[CH], ys[CH], zs[CH], qs[CH];
+        double ws[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const int jk = j + min(k, rem - 1);
+            if constexpr (EXP) {
+                const v4f p = P2[jk];
+                xs[k] = p.x;
+                ys[k] = p.y;
+                zs[k] = p.z;
+                qs[k] = p.w;
+            } else {
+                xs[k] = X2[jk];
+                ys[k] = Y2[jk];
+                zs[k] = Z2[jk];
+                qs[k] = 0.0f;
+            }
+            ws[k] = W ? w2[jk] : 0.0;
+        }
+        chunk_f32<PC_METRIC_R, W, TRI, T16, UNC, PK, CH, true, EXP>(
+            a, L, hb, whb, ax, ay, az, A, wi, i, lp, xs, ys, zs, qs, ws, j, dcode, rechecks,
+            rem);
+    }
+}
 
 template <int M, int W>
 __device__ __forceinline__ LanePt load_lane(const SweepArgs &a, int i, bool act)
@@ -723,7 +827,8 @@ __device__ __forceinline__ LanePt load_lane(const SweepArgs &a, int i, bool act)
 }
 
 // CACHED: the caller holds the lane's point (lpc); otherwise it is loaded here.
-template <int M, int W, bool TRI, bool T16, bool UNC, bool PK, bool CACHED>
+// EXP: r pairs with x and y expanded (float32 DD(r) of 3-D grids).
+template <int M, int W, bool TRI, bool T16, bool UNC, bool PK, bool CACHED, bool EXP>
 __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u32p hb,
                                          lds_f64wp whb, int i, bool act, const LanePt &lpc,
                                          int j0, int j1, unsigned dcode, unsigned &rechecks,
@@ -796,34 +901,16 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
             az = act ? (float)((lp.z + dval(cz, a.L) - a.glo[2]) * a.fscale) : 3.0e30f;
         else
             az = act ? lp.Z + Dz : 3.0e30f;
-        for (; j + CH <= j1; j += CH) {
-            float xs[CH], ys[CH], zs[CH];
-            double ws[CH];
-#pragma unroll
-            for (int k = 0; k < CH; k++) {
-                xs[k] = X2[j + k];
-                ys[k] = Y2[j + k];
-                zs[k] = Z2[j + k];
-                ws[k] = W ? w2[j + k] : 0.0;
-            }
-            chunk_f32<M, W, TRI, T16, UNC, PK, CH>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys, zs,
-                                                   ws, j, dcode, rechecks);
-        }
-        if (j < j1) {
-            // the partial last chunk, padded with the item's last point
-            const int rem = j1 - j;
-            float xs[CH], ys[CH], zs[CH];
-            double ws[CH];
-#pragma unroll
-            for (int k = 0; k < CH; k++) {
-                const int jk = j + min(k, rem - 1);
-                xs[k] = X2[jk];
-                ys[k] = Y2[jk];
-                zs[k] = Z2[jk];
-                ws[k] = W ? w2[jk] : 0.0;
-            }
-            chunk_f32<M, W, TRI, T16, UNC, PK, CH, true>(a, L, hb, whb, ax, ay, az, wi, i, xs, ys,
-                                                         zs, ws, j, dcode, rechecks, rem);
+        if constexpr (EXP) {
+            // -2 a and |a|^2 = fl(a_y a_y + fl(a_x a_x)) of the lane; an
+            // inactive lane keeps its far z, so s overflows to +inf
+            const float A = act ? __fmaf_rn(ay, ay, __fmul_rn(ax, ax)) : 0.0f;
+            const float ex = act ? -2.0f * ax : 0.0f, ey = act ? -2.0f * ay : 0.0f;
+            r_loop<W, TRI, T16, UNC, PK, CH, true>(a, L, hb, whb, ex, ey, az, A, wi, i, lp, j0,
+                                                   j1, dcode, rechecks);
+        } else {
+            r_loop<W, TRI, T16, UNC, PK, CH, false>(a, L, hb, whb, ax, ay, az, 0.0f, wi, i, lp,
+                                                    j0, j1, dcode, rechecks);
         }
     }
 }
@@ -975,8 +1062,10 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
 // PRIV: every wave owns its histogram replicas and flushes them whenever the
 // catalogue of its work items changes (batched calls); otherwise the
 // workgroup's waves share one set of replicas for a single catalogue.
-template <int M, bool P32, int W, bool T16, bool UNC, bool PRIV>
-__global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
+// EXP: the float32 r sweep with x and y expanded (its own kernel, so the
+// differences form's arrays hold no registers in its loop).
+template <int M, bool P32, int W, bool T16, bool UNC, bool PRIV, bool EXP>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     // the lookup table has a fixed place so its address folds into the
     // LDS instructions; the rest of the layout is dynamic
@@ -1147,10 +1236,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
                 lp_ni = ni;
             }
             if (tri)
-                item_f32<M, W, true, T16, UNC, PK, PIPE>(a, L, hb, whb, i, act, lp, it.j0, it.j1,
+                item_f32<M, W, true, T16, UNC, PK, PIPE, EXP>(a, L, hb, whb, i, act, lp, it.j0, it.j1,
                                                          dcode, rechecks, jx, jy);
             else
-                item_f32<M, W, false, T16, UNC, PK, PIPE>(a, L, hb, whb, i, act, lp, it.j0,
+                item_f32<M, W, false, T16, UNC, PK, PIPE, EXP>(a, L, hb, whb, i, act, lp, it.j0,
                                                           it.j1, dcode, rechecks, jx, jy);
         } else {
             if (tri)
@@ -1181,6 +1270,21 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
         if (lane == 0 && tot)
             atomicAdd(a.rq_count, tot);
     }
+}
+
+template <int M, bool P32, int W, bool T16, bool UNC, bool PRIV, bool EXP = false>
+__global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepArgs a)
+{
+    sweep_body<M, P32, W, T16, UNC, PRIV, EXP>(a);
+}
+
+// The unweighted float32 r sweeps with one histogram replica per lane: their
+// LDS (the 32 KiB byte table and 64 small replicas) fits four workgroups per
+// CU, so their registers are held to 64 per lane (eight waves per SIMD).
+template <int M, bool P32, int W, bool T16, bool UNC, bool PRIV, bool EXP = false>
+__global__ __launch_bounds__(kSweepThreads, 8) void k_sweep_o8(SweepArgs a)
+{
+    sweep_body<M, P32, W, T16, UNC, PRIV, EXP>(a);
 }
 
 // Sum of the self-pair weights of every catalogue of a side (w^2 for
@@ -1395,40 +1499,53 @@ __global__ void k_finalize(int32_t ncat, int32_t nbt, int autocorr, int e0_zero,
     }
 }
 
-template <int M, bool P32, int W>
+template <int M, bool P32, int W, bool EXP>
 const void *sweep_fn(bool t16, bool unc, bool priv)
 {
     if (priv)
-        return t16 ? (const void *)&k_sweep<M, P32, W, true, false, true>
-                   : (const void *)&k_sweep<M, P32, W, false, false, true>;
+        return t16 ? (const void *)&k_sweep<M, P32, W, true, false, true, EXP>
+                   : (const void *)&k_sweep<M, P32, W, false, false, true, EXP>;
     if (t16)
-        return (const void *)&k_sweep<M, P32, W, true, false, false>;
-    if (unc && M == PC_METRIC_R && W == 0)
-        return (const void *)&k_sweep<M, P32, W, false, (M == PC_METRIC_R && W == 0), false>;
-    return (const void *)&k_sweep<M, P32, W, false, false, false>;
+        return (const void *)&k_sweep<M, P32, W, true, false, false, EXP>;
+    if constexpr (M == PC_METRIC_R && W == 0) {
+        if (unc) {
+            if constexpr (P32)
+                return (const void *)&k_sweep_o8<M, P32, W, false, true, false, EXP>;
+            else
+                return (const void *)&k_sweep<M, P32, W, false, true, false, EXP>;
+        }
+    }
+    return (const void *)&k_sweep<M, P32, W, false, false, false, EXP>;
 }
 
 template <int M, bool P32>
-const void *sweep_fn_w(int wmode, bool t16, bool unc, bool priv)
+const void *sweep_fn_w(int wmode, bool t16, bool unc, bool priv, bool exp)
 {
     if (wmode == 2)
-        return sweep_fn<M, P32, 2>(t16, unc, priv);
+        return sweep_fn<M, P32, 2, false>(t16, unc, priv);
+    if constexpr (M == PC_METRIC_R && P32) {
+        if (exp)
+            return wmode == 1 ? sweep_fn<M, P32, 1, true>(t16, unc, priv)
+                              : sweep_fn<M, P32, 0, true>(t16, unc, priv);
+    }
     if (wmode == 1)
-        return sweep_fn<M, P32, 1>(t16, unc, priv);
-    return sweep_fn<M, P32, 0>(t16, unc, priv);
+        return sweep_fn<M, P32, 1, false>(t16, unc, priv);
+    return sweep_fn<M, P32, 0, false>(t16, unc, priv);
 }
 
-// wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums.
-// On-sky pairs have binary64 kernels only.
-const void *sweep_ptr(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv)
+// wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums;
+// exp: the float32 r sweep with x and y expanded (wmode 0 or 1).  On-sky
+// pairs have binary64 kernels only.
+const void *sweep_ptr(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv,
+                      bool exp)
 {
     if (metric == PC_METRIC_MOCKS)
-        return sweep_fn_w<PC_METRIC_MOCKS, false>(wmode, t16, unc, priv);
+        return sweep_fn_w<PC_METRIC_MOCKS, false>(wmode, t16, unc, priv, false);
     if (metric == PC_METRIC_R)
-        return fp32 ? sweep_fn_w<PC_METRIC_R, true>(wmode, t16, unc, priv)
-                    : sweep_fn_w<PC_METRIC_R, false>(wmode, t16, unc, priv);
-    return fp32 ? sweep_fn_w<PC_METRIC_RPPI, true>(wmode, t16, unc, priv)
-                : sweep_fn_w<PC_METRIC_RPPI, false>(wmode, t16, unc, priv);
+        return fp32 ? sweep_fn_w<PC_METRIC_R, true>(wmode, t16, unc, priv, exp)
+                    : sweep_fn_w<PC_METRIC_R, false>(wmode, t16, unc, priv, false);
+    return fp32 ? sweep_fn_w<PC_METRIC_RPPI, true>(wmode, t16, unc, priv, false)
+                : sweep_fn_w<PC_METRIC_RPPI, false>(wmode, t16, unc, priv, false);
 }
 
 }  // namespace
@@ -1439,7 +1556,7 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, int wmode, const S
     SweepArgs copy = a;
     void *args[] = {&copy};
     const void *fn = sweep_ptr(metric, fp32, wmode, a.B.tbl_wide != 0, a.copies == PC_WAVE,
-                               a.priv != 0);
+                               a.priv != 0, a.xy_exp != 0);
     if (a.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            a.lds_bytes);
@@ -1452,9 +1569,9 @@ hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, int wmode, const S
 int sweep_waves() { return kWaves; }
 
 hipError_t sweep_occupancy(int metric, bool fp32, int wmode, bool t16, bool unc, bool priv,
-                           int lds_bytes, int *per_cu)
+                           bool exp, int lds_bytes, int *per_cu)
 {
-    const void *fn = sweep_ptr(metric, fp32, wmode, t16, unc, priv);
+    const void *fn = sweep_ptr(metric, fp32, wmode, t16, unc, priv, exp);
     if (lds_bytes > 64 * 1024) {
         hipError_t e =
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);

@@ -124,6 +124,29 @@ def emulate_r(pi, pj, g, L, c, ndim):
     return fma32(dz, dz, t)
 
 
+def emulate_r_xy(pi, pj, g, L, c):
+    """float32 s of the expanded form: |b|^2 = fl(by by + fl(bx bx)) per j
+    point, |a|^2 = fl(ay ay + fl(ax ax)) per lane, then fl(dz dz + |b|^2),
+    fl(-2 ax bx + .), fl(-2 ay by + .) and fl(. + |a|^2) (the same frames as
+    emulate_r)."""
+    cx, cy = frames(pj, g, L)
+    d = pi - pj
+    D = np.where(d > L / 2, -L, np.where(d <= -L / 2, L, 0.0)) if L > 0 else np.zeros_like(d)
+    ax = (((pi[:, 0] + D[:, 0]) - cx) * c).astype(np.float32)
+    ay = (((pi[:, 1] + D[:, 1]) - cy) * c).astype(np.float32)
+    bx = ((pj[:, 0] - cx) * c).astype(np.float32)
+    by = ((pj[:, 1] - cy) * c).astype(np.float32)
+    az = (((pi[:, 2] + D[:, 2]) - g["lo"][2]) * c).astype(np.float32)
+    bz = ((pj[:, 2] - g["lo"][2]) * c).astype(np.float32)
+    q = fma32(by, by, bx * bx)
+    A = fma32(ay, ay, ax * ax)
+    dz = az - bz
+    t = fma32(dz, dz, q)
+    t = fma32(np.float32(-2.0) * ax, bx, t)
+    t = fma32(np.float32(-2.0) * ay, by, t)
+    return t + A
+
+
 def exact_s(pi, pj, L, ndim):
     """The binary64 definition: Code 3's wrap, ((dx^2 + dy^2) + dz^2)."""
     d = pi - pj
@@ -152,11 +175,21 @@ def draw_pairs(rng, n, L, reach, lo=0.0, hi=None, radial=None):
     return pi, pj
 
 
-def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats):
+def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, xy_max=None):
+    """xy_max given: the expanded form and its bands (cf_fp32_bands_xy)."""
     s64 = exact_s(pi, pj, L, ndim)
-    s32 = emulate_r(pi, pj, g, L, c, ndim).astype(np.float64) / (c * c)
+    if xy_max is None:
+        s32 = emulate_r(pi, pj, g, L, c, ndim).astype(np.float64) / (c * c)
+
+        def bands(e2):
+            return pc.fp32_bands_axes(e2, ndim, axis_eps, coord_scale)
+    else:
+        s32 = emulate_r_xy(pi, pj, g, L, c).astype(np.float64) / (c * c)
+
+        def bands(e2):
+            return pc.fp32_bands_xy(e2, axis_eps, xy_max, coord_scale)
     E = edges * edges
-    lo, hi = pc.fp32_bands_axes(E, ndim, axis_eps, coord_scale)
+    lo, hi = bands(E)
     for k in range(E.size):
         if E[k] == 0.0:
             continue
@@ -166,7 +199,7 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats):
         assert np.all(s64[above] > E[k]), ("decided above but not", k)
     # the bound at each pair's own separation
     ok = s64 > 0
-    blo, bhi = pc.fp32_bands_axes(s64[ok], ndim, axis_eps, coord_scale)
+    blo, bhi = bands(s64[ok])
     half = np.minimum(s64[ok] - blo.astype(np.float64), bhi.astype(np.float64) - s64[ok])
     err = np.abs(s32[ok] - s64[ok])
     ratio_band = err / half
@@ -183,9 +216,15 @@ def scale_for(edges, S, top=32766.0 / 32767.0):
     return math.sqrt(top * (1.0 - 2.0 ** -16) / float(hi[0]))
 
 
-@pytest.mark.parametrize("case", ["r_box420", "r_box1100_k2", "rp_box1000", "chord_open"])
+@pytest.mark.parametrize("case", ["r_box420", "r_box1100_k2", "rp_box1000", "chord_open",
+                                  "r_box420_xy", "r_box1100_k2_xy", "chord_open_xy"])
 def test_fp32_bound_holds_on_1e8_pairs(case):
+    """The _xy cases: the expanded form of x and y (cf_options.separation_form
+    2) against its own bands, fewer pairs (the bound's arithmetic is the
+    same emulation checked above, with other magnitudes)."""
     rng = synth.rng_for(sum(map(ord, case)))
+    xy = case.endswith("_xy")
+    case = case[:-3] if xy else case
     stats = {"pairs": 0, "max_ratio_band": 0.0, "max_ratio_raw": 0.0}
     if case == "r_box420":
         L, reach, k, ndim = 420.0, 25.0, 1, 3
@@ -219,6 +258,11 @@ def test_fp32_bound_holds_on_1e8_pairs(case):
     axis_eps = [frame_eps((kk + 0.5) * g["width"][0], 0.5 * g["width"][0]),
                 frame_eps((kk + 0.5) * g["width"][1], 0.5 * g["width"][1]),
                 frame_eps(S + reach, S)]
+    # the lane's largest |x|, |y| in the j column's frame, the j point's
+    xy_max = ([(kk + 0.5) * g["width"][0], (kk + 0.5) * g["width"][1],
+               0.5 * g["width"][0], 0.5 * g["width"][1]] if xy else None)
+    if xy:
+        npairs //= 2
     for c in (1.0, scale_for(edges, S)):
         done = 0
         while done < npairs // 2:
@@ -230,15 +274,15 @@ def test_fp32_bound_holds_on_1e8_pairs(case):
                 pi /= np.linalg.norm(pi, axis=1)[:, None]
                 pj = pi + rng.normal(size=(n, 3)) * (reach / 2)
                 pj /= np.linalg.norm(pj, axis=1)[:, None]
-            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats)
+            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats, xy_max)
             done += n
         # adversarial: separations within a few ulps of every edge
         e_rep = np.repeat(edges[edges > 0], 20000)
         jitter = e_rep * (1.0 + rng.integers(-8, 9, e_rep.size) * 2.0 ** -52)
         if L > 0:
             pi, pj = draw_pairs(rng, e_rep.size, L, reach, radial=jitter)
-            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats)
-    print(case, stats)
+            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats, xy_max)
+    print(case, "expanded" if xy else "differences", stats)
     assert stats["pairs"] >= npairs
     assert stats["max_ratio_raw"] < 1.0, stats
     assert stats["max_ratio_band"] < 1.0 / SAFETY, stats
