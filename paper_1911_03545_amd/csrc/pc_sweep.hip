@@ -504,7 +504,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         }
 #pragma unroll
         for (int k = 0; k < CH; k++)
-            lds_add(&hb[e[k]], 1u);
+            lds_add(&hb[e[k] * PC_WAVE], 1u);
         return;
     }
 #pragma unroll
@@ -614,7 +614,7 @@ __device__ __forceinline__ void chunk_f64(const SweepArgs &a, const Lds &L, lds_
                 slot = slow_slot_exact<T16>(s[k], slot, L.E, a.B.nb + 1);
             if (TRI && !(j + k > i))
                 slot = 0;
-            lds_add(&hb[slot], 1u);
+            lds_add(&hb[slot * PC_WAVE], 1u);
         }
         return;
     }
@@ -994,6 +994,15 @@ __device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int 
 // every other slot is an out-of-range catch-all and is only cleared.  Called
 // by threads t = first, first + step, ...; slots are taken with atomic
 // exchanges, so other waves may keep adding to shared replicas meanwhile.
+// Word of slot `slot` of count replica r.  One replica per lane (the
+// unconditional sweeps) interleaves the replicas, slot * 64 + lane, so the 64
+// lanes of a wave always add to 64 different banks whatever their slots;
+// fewer replicas keep each replica's slots together, rep_stride apart.
+__device__ __forceinline__ int count_index(const SweepArgs &a, int r, int slot)
+{
+    return a.copies == PC_WAVE ? slot * PC_WAVE + r : r * a.rep_stride + slot;
+}
+
 __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int first, int step,
                                            bool W, unsigned cat)
 {
@@ -1014,7 +1023,7 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         double w = 0.0, rs = 0.0;
         unsigned long long f0 = 0, f1 = 0, f2 = 0;
         for (int r = 0; r < a.copies; r++) {
-            c += lds_take(&L.hist[r * a.rep_stride + slot]);
+            c += lds_take(&L.hist[count_index(a, r, slot)]);
             if (F) {
                 const int o = r * a.rep_stride + slot;
                 f0 += lds_take(&fx[o]);
@@ -1045,7 +1054,7 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         const int row = sl / rw, col = sl % rw - c0;
         if (row >= 1 && row <= a.B.nb && col >= 0 && col < npi)
             continue;
-        lds_take(&L.hist[r * a.rep_stride + sl]);
+        lds_take(&L.hist[count_index(a, r, sl)]);
         if (F) {
             const int o = r * a.rep_stride + sl;
             lds_take(&fx[o]);
@@ -1135,7 +1144,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 : (lds_f64wp) nullptr;
     // this lane's replica
     const int rep = lane & (a.copies - 1);
-    lds_u32p hb = L.hist + rep * a.rep_stride;
+    lds_u32p hb = L.hist + (UNC ? rep : rep * a.rep_stride);   // (count_index)
     lds_f64wp whb = W ? L.whist + rep * a.rep_stride : (lds_f64wp) nullptr;
 
     // Pairs this wave added since its last flush.  A shared slot holds at
