@@ -994,15 +994,17 @@ __device__ __forceinline__ int wave_fetch(int *ctrs, int n_items, int lane, int 
 // every other slot is an out-of-range catch-all and is only cleared.  Called
 // by threads t = first, first + step, ...; slots are taken with atomic
 // exchanges, so other waves may keep adding to shared replicas meanwhile.
-// Word of slot `slot` of count replica r.  One replica per lane (the
+// Word of slot `slot` of count replica r.  One replica per lane (UNC: the
 // unconditional sweeps) interleaves the replicas, slot * 64 + lane, so the 64
 // lanes of a wave always add to 64 different banks whatever their slots;
 // fewer replicas keep each replica's slots together, rep_stride apart.
+template <bool UNC>
 __device__ __forceinline__ int count_index(const SweepArgs &a, int r, int slot)
 {
-    return a.copies == PC_WAVE ? slot * PC_WAVE + r : r * a.rep_stride + slot;
+    return UNC ? slot * PC_WAVE + r : r * a.rep_stride + slot;
 }
 
+template <bool UNC>
 __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int first, int step,
                                            bool W, unsigned cat)
 {
@@ -1023,7 +1025,7 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         double w = 0.0, rs = 0.0;
         unsigned long long f0 = 0, f1 = 0, f2 = 0;
         for (int r = 0; r < a.copies; r++) {
-            c += lds_take(&L.hist[count_index(a, r, slot)]);
+            c += lds_take(&L.hist[count_index<UNC>(a, r, slot)]);
             if (F) {
                 const int o = r * a.rep_stride + slot;
                 f0 += lds_take(&fx[o]);
@@ -1054,7 +1056,7 @@ __device__ __forceinline__ void flush_hist(const SweepArgs &a, const Lds &L, int
         const int row = sl / rw, col = sl % rw - c0;
         if (row >= 1 && row <= a.B.nb && col >= 0 && col < npi)
             continue;
-        lds_take(&L.hist[count_index(a, r, sl)]);
+        lds_take(&L.hist[count_index<UNC>(a, r, sl)]);
         if (F) {
             const int o = r * a.rep_stride + sl;
             lds_take(&fx[o]);
@@ -1218,13 +1220,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             const unsigned cat = PC_META_CAT(it.meta);
             if (cat != cur_cat) {
                 if (pending)
-                    flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
+                    flush_hist<UNC>(a, L, lane, PC_WAVE, W, cur_cat);
                 pending = 0;
                 cur_cat = cat;
             }
         }
         if (pending + work > flush_at) {
-            flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
+            flush_hist<UNC>(a, L, lane, PC_WAVE, W, cur_cat);
             pending = 0;
             if (lane == 0)
                 atomicAdd(a.flush_count, 1u);
@@ -1266,10 +1268,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     if (PIPE && pend && __builtin_amdgcn_readfirstlane(pv) < 0)
         rechecks++;
     if (PRIV) {
-        flush_hist(a, L, lane, PC_WAVE, W, cur_cat);
+        flush_hist<UNC>(a, L, lane, PC_WAVE, W, cur_cat);
     } else {
         __syncthreads();
-        flush_hist(a, L, (int)threadIdx.x, kSweepThreads, W, 0u);
+        flush_hist<UNC>(a, L, (int)threadIdx.x, kSweepThreads, W, 0u);
     }
     if (P32) {
         // one atomic per wave for the recheck statistic
