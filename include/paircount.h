@@ -188,9 +188,10 @@ typedef struct cf_options {
                                    numerator stays a binary64 sum.  0: binary64
                                    atomics (the default; sums then agree with
                                    the exact sum to about 1e-12 relative).     */
-    int32_t separation_form;    /* float32 DD(r) and theta-as-chord sweeps of
-                                   3-D grids (no mean separation): how the
-                                   squared separation is formed.  1: from the
+    int32_t separation_form;    /* float32 DD(r), DD(rp, pi) (also batched)
+                                   and theta-as-chord sweeps of 3-D grids (no
+                                   mean separation): how the squared
+                                   separation (rp^2) is formed.  1: from the
                                    coordinate differences dx^2 + dy^2 + dz^2;
                                    2: x and y expanded as |a|^2 + |b|^2 -
                                    2 a.b (|b|^2 stored per point by the
@@ -199,9 +200,13 @@ typedef struct cf_options {
                                    absolute rounding bound (about u times 17
                                    squared column widths, folded into the
                                    decision bands, so results stay exact);
-                                   0 (default): 2 when that bound widens the
-                                   band of the smallest nonzero edge by at
-                                   most an eighth of its value, else 1.  Other
+                                   0 (default): for DD(r) and chords 2 when
+                                   that bound widens the band of the smallest
+                                   nonzero edge by at most an eighth of its
+                                   value, else 1; for DD(rp, pi) 1 (its pairs
+                                   crowd the small rp edges, where the wider
+                                   bands cost more rechecks than the form
+                                   saves).  Other
                                    statistics and the binary64 mode ignore
                                    it.  cf_stats.separation_form reports the
                                    form used.                                  */
@@ -468,16 +473,21 @@ cf_status cf_fp32_bands(const double *edges_sq, int32_t nedges, int32_t ndim,
 cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, int32_t ndim,
                              const double *axis_eps, double coord_scale, float *lo,
                              float *hi);
-/* The bands of the expanded form of a 3-D float32 sweep
-   (cf_options.separation_form 2): x and y as t0 = fl(dz dz + Bj), t1 =
-   fl(-2 a_x b_x + t0), t2 = fl(-2 a_y b_y + t1), s = fl(t2 + A) with Bj =
-   fl(b_y b_y + fl(b_x b_x)) and A = fl(a_y a_y + fl(a_x a_x)).  The
-   arithmetic term (ndim + 1) u s' above becomes u (6 s' + 5 |b|^2 + 2 |a|^2
-   + 4 (|a_x b_x| + |a_y b_y|)) (1 + 2^-20) at the largest magnitudes, given
+/* The bands of the expanded form of a 3-D grid's float32 sweep
+   (cf_options.separation_form 2), ndim 3 (r): x and y as t0 = fl(dz dz +
+   Bj), t1 = fl(-2 a_x b_x + t0), t2 = fl(-2 a_y b_y + t1), s = fl(t2 + A)
+   with Bj = fl(b_y b_y + fl(b_x b_x)) and A = fl(a_y a_y + fl(a_x a_x));
+   ndim 2 (rp^2): t0 = fl(A + Bj), t1 = fl(-2 a_x b_x + t0), s = fl(-2 a_y
+   b_y + t1).  The arithmetic term (ndim + 1) u s' above becomes u (6 s' + M)
+   (1 + 2^-20) with M = 5 |b|^2 + 2 |a|^2 + 4 (|a_x b_x| + |a_y b_y|) (ndim
+   3) or 4 |a|^2 + 4 |b|^2 + 2 (|a_x b_x| + |a_y b_y|) (ndim 2) at the
+   largest magnitudes, given
    as xy_max = {a_x, a_y, b_x, b_y} (the lane's largest |x|, |y| in the j
-   column's frame, the j point's); the coordinate term is unchanged. */
-cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, const double *axis_eps,
-                           const double *xy_max, double coord_scale, float *lo, float *hi);
+   column's frame, the j point's); the coordinate term is unchanged.
+   axis_eps holds ndim values. */
+cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, int32_t ndim,
+                           const double *axis_eps, const double *xy_max, double coord_scale,
+                           float *lo, float *hi);
 
 /* Host-only: the exact sum of n values p[k], each an integer multiple of 2^q
    with |p[k]| < 2^(q + 94), rounded once to binary64 (ties to even), through

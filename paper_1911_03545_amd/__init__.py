@@ -189,7 +189,7 @@ def load_library(path: str = LIB_PATH):
     lib.cf_fp32_bands.restype = ctypes.c_int
     lib.cf_fp32_bands_axes.argtypes = [vp, i32, i32, vp, dbl, vp, vp]
     lib.cf_fp32_bands_axes.restype = ctypes.c_int
-    lib.cf_fp32_bands_xy.argtypes = [vp, i32, vp, vp, dbl, vp, vp]
+    lib.cf_fp32_bands_xy.argtypes = [vp, i32, i32, vp, vp, dbl, vp, vp]
     lib.cf_fp32_bands_xy.restype = ctypes.c_int
     lib.cf_fixed_sum.argtypes = [vp, ctypes.c_int64, i32, vp]
     lib.cf_fixed_sum.restype = ctypes.c_int
@@ -294,19 +294,20 @@ def fp32_bands_axes(edges_sq, ndim: int, axis_eps, coord_scale: float):
     return lo, hi
 
 
-def fp32_bands_xy(edges_sq, axis_eps, xy_max, coord_scale: float):
-    """Host-only float32 decision bands of a 3-D sweep whose x and y are
-    expanded (|a|^2 + |b|^2 - 2 a.b); xy_max = (a_x, a_y, b_x, b_y), the
-    largest coordinate magnitudes of the lane and of the j point."""
+def fp32_bands_xy(edges_sq, axis_eps, xy_max, coord_scale: float, ndim: int = 3):
+    """Host-only float32 decision bands of a 3-D grid's sweep whose x and y
+    are expanded (|a|^2 + |b|^2 - 2 a.b): squared r (ndim 3) or rp (ndim 2);
+    xy_max = (a_x, a_y, b_x, b_y), the largest coordinate magnitudes of the
+    lane and of the j point."""
     lib = load_library()
     e = np.ascontiguousarray(edges_sq, dtype=np.float64)
     sc = np.ascontiguousarray(axis_eps, dtype=np.float64)
     mx = np.ascontiguousarray(xy_max, dtype=np.float64)
-    if sc.size < 3 or mx.size < 4:
-        raise ValueError("three axis bounds and four magnitudes")
+    if sc.size < ndim or mx.size < 4:
+        raise ValueError("one bound per axis and four magnitudes")
     lo = np.zeros(e.size, dtype=np.float32)
     hi = np.zeros(e.size, dtype=np.float32)
-    st = lib.cf_fp32_bands_xy(e.ctypes.data, e.size, sc.ctypes.data, mx.ctypes.data,
+    st = lib.cf_fp32_bands_xy(e.ctypes.data, e.size, int(ndim), sc.ctypes.data, mx.ctypes.data,
                               float(coord_scale), lo.ctypes.data, hi.ctypes.data)
     if st != CF_OK:
         raise PairCountError(st, "cf_fp32_bands_xy failed")

@@ -493,7 +493,7 @@ cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, bool 
 // catalogue k are k * ncell .. (k + 1) * ncell - 1, so the sorted arrays hold
 // the catalogues one after the other, each in cell order.
 // Q (or B_COUNT: none): (x, y, z, |b|^2) in float32 of every sorted point,
-// side by side, for sweeps that expand x and y (X, Y, Z are then not written)
+// side by side, for sweeps that expand x and y (besides X, Y, Z)
 cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool weighted,
                     const pc_grid &g, BufId start, BufId X, BufId Y, BufId Z, BufId XD, BufId YD,
                     BufId ZD, BufId WD, BufId CS, BufId Q, unsigned *flags)
@@ -895,16 +895,21 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         pc::frame_eps((g.xyk + 0.5) * g.width[0], 0.5 * g.width[0], scale),
         pc::frame_eps((g.xyk + 0.5) * g.width[1], 0.5 * g.width[1], scale),
         pc::frame_eps(scale + reach_z, scale, scale)};
-    // Float32 DD(r) (and chords) of 3-D grids without the mean separation:
-    // x and y expanded as |a|^2 + |b|^2 - 2 a.b, one instruction fewer per
-    // pair, unless its absolute rounding term would widen the band of the
-    // smallest nonzero edge by more than an eighth of that edge (the float32
-    // mean separation takes the square root of s and keeps the differences)
+    // Float32 DD(r) (and chords) and DD(rp, pi) of 3-D grids without the
+    // mean separation: x and y expanded as |a|^2 + |b|^2 - 2 a.b, one
+    // instruction fewer per pair.  By default DD(r) only, and only while its
+    // absolute rounding term widens the band of the smallest nonzero edge by
+    // at most an eighth of that edge: rp/pi pairs crowd the small rp edges
+    // (every pi of the window shares them), and there the wider bands cost
+    // more rechecks than the instruction saves.  (The float32 mean
+    // separation takes the square root of s and keeps the differences.)
     double xy_mag = 0.0;
-    if (fp32 && g.xy_local && metric == PC_METRIC_R && !want_ravg && opt.separation_form != 1) {
+    if (fp32 && g.xy_local && (metric == PC_METRIC_R || metric == PC_METRIC_RPPI) && !sky &&
+        !want_ravg && opt.separation_form != 1 &&
+        (metric == PC_METRIC_R || opt.separation_form == 2)) {
         const double am[2] = {(g.xyk + 0.5) * g.width[0], (g.xyk + 0.5) * g.width[1]};
         const double bm[2] = {0.5 * g.width[0], 0.5 * g.width[1]};
-        const double mag = pc::xy_expand_mag(am, bm);
+        const double mag = pc::xy_expand_mag(am, bm, metric == PC_METRIC_RPPI ? 2 : 3);
         double emin = INFINITY;
         for (int k = 0; k <= nb; k++)
             if (lin[k] > 0.0)

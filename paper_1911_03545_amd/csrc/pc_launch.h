@@ -54,9 +54,9 @@ struct SweepArgs {
     // (pc_frame.h); each lane's point is placed in the frame of the item's j
     // column, found from the cell id of the item's first j point
     int32_t xy_local;
-    // float32 DD(r) of 3-D grids: x and y expanded as |a|^2 + |b|^2 - 2 a.b,
-    // with P2 = (x, y, z, |b|^2) of every sorted point of side 2 in float32
-    // (X2, Y2 and Z2 are then not written)
+    // float32 DD(r) and DD(rp, pi) of 3-D grids: x and y expanded as |a|^2 +
+    // |b|^2 - 2 a.b, with P2 = (x, y, z, |b|^2) of every sorted point of side
+    // 2 in float32 (z: the rp/pi path's fixed-point bits)
     int32_t xy_exp;
     const float4 *P2;
     int32_t gnx, gny, gnz;
@@ -105,9 +105,8 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
                           int32_t *tmp);
 // place every point at start[cell] + rank: a permutation scatter of source
 // indices into `perm` (ntot int32), then a gather in sorted order.  P
-// (optional; the expanded float32 r sweep): the float32 x, y, z and
-// fl(y y + fl(x x)) of every sorted point side by side, written in place of
-// X, Y and Z.
+// (optional; the expanded float32 sweeps): the float32 x, y, z and
+// fl(y y + fl(x x)) of every sorted point side by side, besides X, Y, Z.
 hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *cell_of,
                           const int32_t *rank_of, const void *rec, const int32_t *start,
                           int32_t *perm, float *X, float *Y, float *Z, double *xd, double *yd,

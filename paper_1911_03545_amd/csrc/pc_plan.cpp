@@ -319,17 +319,23 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
 // the magnitudes taken at their maxima (xy_mag, xy_expand_mag) in place of
 // (ndim + 1) u s'; the coordinate part stays as above (it also covers the
 // rounding of x and y differences, which the expanded form does not make).
-double xy_expand_mag(const double a_max[2], const double b_max[2])
+// rp^2 (ndim 2) is formed as t0 = fl(A + Bj), t1 = fl(-2 a_x b_x + t0), s32 =
+// fl(-2 a_y b_y + t1) (each instruction then reads one scalar operand), with
+// |t0| <= |a|^2 + |b|^2 and |t1| <= |t0| + 2|a_x b_x|: the arithmetic part is
+// u (s' + 4 |a|^2 + 4 |b|^2 + 2 |a_x b_x|) to first order, within
+// u (6 s' + xy_mag) for xy_mag = 4 |a|^2 + 4 |b|^2 + 2 (|a_x b_x| + |a_y b_y|).
+double xy_expand_mag(const double a_max[2], const double b_max[2], int ndim)
 {
     const double g = 1.0 + 0x1p-16;   // points a rounding outside their column
     const double ax = a_max[0] * g, ay = a_max[1] * g, bx = b_max[0] * g, by = b_max[1] * g;
-    return 5.0 * (bx * bx + by * by) + 2.0 * (ax * ax + ay * ay) + 4.0 * (ax * bx + ay * by);
+    const double A = ax * ax + ay * ay, B = bx * bx + by * by, P = ax * bx + ay * by;
+    return ndim == 2 ? 4.0 * A + 4.0 * B + 2.0 * P : 5.0 * B + 2.0 * A + 4.0 * P;
 }
 
 int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
                     double scale, float *lo, float *hi, double xy_mag)
 {
-    if (!(xy_mag >= 0.0) || !isfinite(xy_mag) || (xy_mag > 0.0 && ndim != 3))
+    if (!(xy_mag >= 0.0) || !isfinite(xy_mag) || (xy_mag > 0.0 && ndim < 2))
         return CF_EINVAL;
     if (nedges < 1 || ndim < 1 || ndim > 3 || !(scale >= 0.0) || !isfinite(scale))
         return CF_EINVAL;
@@ -775,17 +781,17 @@ extern "C" cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, 
                                           hi);
 }
 
-extern "C" cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges,
+extern "C" cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, int32_t ndim,
                                       const double *axis_eps, const double *xy_max,
                                       double coord_scale, float *lo, float *hi)
 {
-    if (!edges_sq || !axis_eps || !xy_max || !lo || !hi)
+    if (!edges_sq || !axis_eps || !xy_max || !lo || !hi || (ndim != 2 && ndim != 3))
         return CF_EINVAL;
     for (int k = 0; k < 4; k++)
         if (!(xy_max[k] >= 0.0) || !std::isfinite(xy_max[k]))
             return CF_EINVAL;
-    const double mag = pc::xy_expand_mag(xy_max, xy_max + 2);
-    return (cf_status)pc::fp32_bands_axes(edges_sq, nedges, 3, axis_eps, coord_scale, lo, hi,
+    const double mag = pc::xy_expand_mag(xy_max, xy_max + 2, ndim);
+    return (cf_status)pc::fp32_bands_axes(edges_sq, nedges, ndim, axis_eps, coord_scale, lo, hi,
                                           mag > 0.0 ? mag : 0x1p-1000);
 }
 

@@ -27,13 +27,14 @@ int plan_sky_grid(double chord_reach, double zlo, double zhi, int slices, int ra
 int fp32_bands(const double *edges_sq, int nedges, int ndim, double scale, float *lo,
                float *hi);
 // per-axis rounding bounds of the two float32 coordinates (ndim values);
-// xy_mag > 0 (ndim 3): the float32 sweep expands x and y as |a|^2 + |b|^2 -
-// 2 a.b, with xy_mag = xy_expand_mag of the coordinates' maxima
+// xy_mag > 0 (ndim 2 or 3): the float32 sweep expands x and y as |a|^2 +
+// |b|^2 - 2 a.b, with xy_mag = xy_expand_mag of the coordinates' maxima
 int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
                     double scale, float *lo, float *hi, double xy_mag = 0.0);
-// magnitude term of the expanded x and y: a_max = the lane's largest |x|, |y|
-// in the j column's frame, b_max = the j point's
-double xy_expand_mag(const double a_max[2], const double b_max[2]);
+// magnitude term of the expanded x and y of squared r (ndim 3) or rp (ndim
+// 2): a_max = the lane's largest |x|, |y| in the j column's frame, b_max = the
+// j point's
+double xy_expand_mag(const double a_max[2], const double b_max[2], int ndim);
 // rounding bound of one column-local axis: coordinates at most a_max and
 // b_max from the frame origin, each rounded once from binary64
 double frame_eps(double a_max, double b_max, double scale);

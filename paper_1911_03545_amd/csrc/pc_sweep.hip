@@ -655,14 +655,17 @@ __device__ __forceinline__ unsigned absdiff_plus(unsigned a, unsigned b, unsigne
     return (max(a, b) - min(a, b)) + c;
 }
 
-template <int W, bool TRI, bool T16, bool PK, int CH, bool MASK = false>
+// EXP: rp^2 expanded, fl(fl(fl(|a|^2 + |b|^2) - 2 a_x b_x) - 2 a_y b_y) with
+// ax, ay holding -2 a_x, -2 a_y and qs = |b|^2 (the order that gives every
+// instruction one scalar operand: three instructions for rp^2).
+template <int W, bool TRI, bool T16, bool PK, int CH, bool MASK = false, bool EXP = false>
 __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &L, lds_u32p hb,
-                                                 lds_f64wp whb, float ax, float ay,
+                                                 lds_f64wp whb, float ax, float ay, float A,
                                                  unsigned azq, LaneW wi, int i,
                                                  const float *xs, const float *ys,
-                                                 const float *zs, const double *ws, int j,
-                                                 unsigned dcode, unsigned &rechecks,
-                                                 int rem = CH)
+                                                 const float *zs, const float *qs,
+                                                 const double *ws, int j, unsigned dcode,
+                                                 unsigned &rechecks, int rem = CH)
 {
     const float kmax = key_top_value<PK>(a);
     const int sh = a.B.zq_shift;
@@ -674,8 +677,13 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
     unsigned nmin = mask;
 #pragma unroll
     for (int k = 0; k < CH; k++) {
-        const float dx = ax - xs[k], dy = ay - ys[k];
-        s[k] = fmaf(dy, dy, dx * dx);
+        if constexpr (EXP) {
+            const float t = fmaf(ax, xs[k], A + qs[k]);
+            s[k] = fmaf(ay, ys[k], t);
+        } else {
+            const float dx = ax - xs[k], dy = ay - ys[k];
+            s[k] = fmaf(dy, dy, dx * dx);
+        }
         u[k] = absdiff_plus(azq, __float_as_uint(zs[k]), PC_ZQ_MARGIN);
         // the block's own triangle (j <= i) and the padding of a partial
         // chunk: out of range in rp, mid-bin in pi (never undecided)
@@ -737,6 +745,68 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
 }
 
 // ---- item loops ----------------------------------------------------------
+// The float32 rp/pi pairs of one item (z in fixed point), as r_loop.
+template <int W, bool TRI, bool T16, bool PK, int CH, bool EXP>
+__device__ __forceinline__ void rppi_loop(const SweepArgs &a, const Lds &L, lds_u32p hb,
+                                          lds_f64wp whb, float ax, float ay, float A,
+                                          unsigned azq, LaneW wi, int i, int j0, int j1,
+                                          unsigned dcode, unsigned &rechecks)
+{
+    const kf32p X2 = (kf32p)a.X2, Y2 = (kf32p)a.Y2, Z2 = (kf32p)a.Z2;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const KCONST v4f *P2 = (const KCONST v4f *)a.P2;   // (x, y, z bits, |b|^2) per point
+    const kf64p w2 = (kf64p)a.w2;
+    int j = j0;
+    for (; j + CH <= j1; j += CH) {
+        float xs[CH], ys[CH], zs[CH], qs[CH];
+        double ws[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if constexpr (EXP) {
+                const v4f p = P2[j + k];
+                xs[k] = p.x;
+                ys[k] = p.y;
+                zs[k] = p.z;
+                qs[k] = p.w;
+            } else {
+                xs[k] = X2[j + k];
+                ys[k] = Y2[j + k];
+                zs[k] = Z2[j + k];
+                qs[k] = 0.0f;
+            }
+            ws[k] = W ? w2[j + k] : 0.0;
+        }
+        chunk_f32_rppi_q<W, TRI, T16, PK, CH, false, EXP>(a, L, hb, whb, ax, ay, A, azq, wi, i,
+                                                          xs, ys, zs, qs, ws, j, dcode,
+                                                          rechecks);
+    }
+    if (j < j1) {
+        const int rem = j1 - j;
+        float xs[CH], ys[CH], zs[CH], qs[CH];
+        double ws[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            const int jk = j + min(k, rem - 1);
+            if constexpr (EXP) {
+                const v4f p = P2[jk];
+                xs[k] = p.x;
+                ys[k] = p.y;
+                zs[k] = p.z;
+                qs[k] = p.w;
+            } else {
+                xs[k] = X2[jk];
+                ys[k] = Y2[jk];
+                zs[k] = Z2[jk];
+                qs[k] = 0.0f;
+            }
+            ws[k] = W ? w2[jk] : 0.0;
+        }
+        chunk_f32_rppi_q<W, TRI, T16, PK, CH, true, EXP>(a, L, hb, whb, ax, ay, A, azq, wi, i,
+                                                         xs, ys, zs, qs, ws, j, dcode, rechecks,
+                                                         rem);
+    }
+}
+
 // The float32 r pairs of one item: chunks of CH j points, then the partial
 // last chunk padded with the item's last point.  Second-catalogue points are
 // wave-uniform and read through the scalar cache (the arrays are not written
@@ -866,33 +936,16 @@ __device__ __forceinline__ void item_f32(const SweepArgs &a, const Lds &L, lds_u
         // z in fixed point: the periodic z offset is a whole number of quanta
         const unsigned Dq = cz == PC_D_PLUS ? a.B.zq_L : (cz == PC_D_MINUS ? 0u - a.B.zq_L : 0u);
         const unsigned azq = __float_as_uint(lp.Z) + Dq;
-        for (; j + CH <= j1; j += CH) {
-            float xs[CH], ys[CH], zs[CH];
-            double ws[CH];
-#pragma unroll
-            for (int k = 0; k < CH; k++) {
-                xs[k] = X2[j + k];
-                ys[k] = Y2[j + k];
-                zs[k] = Z2[j + k];
-                ws[k] = W ? w2[j + k] : 0.0;
-            }
-            chunk_f32_rppi_q<W, TRI, T16, PK, CH>(a, L, hb, whb, ax, ay, azq, wi, i, xs, ys, zs,
-                                                  ws, j, dcode, rechecks);
-        }
-        if (j < j1) {
-            const int rem = j1 - j;
-            float xs[CH], ys[CH], zs[CH];
-            double ws[CH];
-#pragma unroll
-            for (int k = 0; k < CH; k++) {
-                const int jk = j + min(k, rem - 1);
-                xs[k] = X2[jk];
-                ys[k] = Y2[jk];
-                zs[k] = Z2[jk];
-                ws[k] = W ? w2[jk] : 0.0;
-            }
-            chunk_f32_rppi_q<W, TRI, T16, PK, CH, true>(a, L, hb, whb, ax, ay, azq, wi, i, xs,
-                                                        ys, zs, ws, j, dcode, rechecks, rem);
+        if constexpr (EXP) {
+            const float A = act ? __fmaf_rn(ay, ay, __fmul_rn(ax, ax)) : 0.0f;
+            const float ex = act ? -2.0f * ax : 0.0f, ey = act ? -2.0f * ay : 0.0f;
+            // (an inactive lane: s = 0 + 0 + 0 would be in range, so its
+            // weight-free catch-all is forced through A = +inf)
+            rppi_loop<W, TRI, T16, PK, CH, true>(a, L, hb, whb, ex, ey, act ? A : INFINITY, azq,
+                                                 wi, i, j0, j1, dcode, rechecks);
+        } else {
+            rppi_loop<W, TRI, T16, PK, CH, false>(a, L, hb, whb, ax, ay, 0.0f, azq, wi, i, j0,
+                                                  j1, dcode, rechecks);
         }
         return;
     } else {
@@ -1534,7 +1587,7 @@ const void *sweep_fn_w(int wmode, bool t16, bool unc, bool priv, bool exp)
 {
     if (wmode == 2)
         return sweep_fn<M, P32, 2, false>(t16, unc, priv);
-    if constexpr (M == PC_METRIC_R && P32) {
+    if constexpr ((M == PC_METRIC_R || M == PC_METRIC_RPPI) && P32) {
         if (exp)
             return wmode == 1 ? sweep_fn<M, P32, 1, true>(t16, unc, priv)
                               : sweep_fn<M, P32, 0, true>(t16, unc, priv);
@@ -1555,7 +1608,7 @@ const void *sweep_ptr(int metric, bool fp32, int wmode, bool t16, bool unc, bool
     if (metric == PC_METRIC_R)
         return fp32 ? sweep_fn_w<PC_METRIC_R, true>(wmode, t16, unc, priv, exp)
                     : sweep_fn_w<PC_METRIC_R, false>(wmode, t16, unc, priv, false);
-    return fp32 ? sweep_fn_w<PC_METRIC_RPPI, true>(wmode, t16, unc, priv, false)
+    return fp32 ? sweep_fn_w<PC_METRIC_RPPI, true>(wmode, t16, unc, priv, exp)
                 : sweep_fn_w<PC_METRIC_RPPI, false>(wmode, t16, unc, priv, false);
 }
 

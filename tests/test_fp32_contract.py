@@ -124,11 +124,12 @@ def emulate_r(pi, pj, g, L, c, ndim):
     return fma32(dz, dz, t)
 
 
-def emulate_r_xy(pi, pj, g, L, c):
+def emulate_r_xy(pi, pj, g, L, c, ndim=3):
     """float32 s of the expanded form: |b|^2 = fl(by by + fl(bx bx)) per j
     point, |a|^2 = fl(ay ay + fl(ax ax)) per lane, then fl(dz dz + |b|^2),
-    fl(-2 ax bx + .), fl(-2 ay by + .) and fl(. + |a|^2) (the same frames as
-    emulate_r)."""
+    fl(-2 ax bx + .), fl(-2 ay by + .) and fl(. + |a|^2) for r; for rp^2
+    fl(|a|^2 + |b|^2), fl(-2 ax bx + .) and fl(-2 ay by + .) (the same frames
+    as emulate_r)."""
     cx, cy = frames(pj, g, L)
     d = pi - pj
     D = np.where(d > L / 2, -L, np.where(d <= -L / 2, L, 0.0)) if L > 0 else np.zeros_like(d)
@@ -140,6 +141,10 @@ def emulate_r_xy(pi, pj, g, L, c):
     bz = ((pj[:, 2] - g["lo"][2]) * c).astype(np.float32)
     q = fma32(by, by, bx * bx)
     A = fma32(ay, ay, ax * ax)
+    if ndim == 2:
+        # rp^2: fl(A + |b|^2) first, then the two products
+        t = fma32(np.float32(-2.0) * ax, bx, A + q)
+        return fma32(np.float32(-2.0) * ay, by, t)
     dz = az - bz
     t = fma32(dz, dz, q)
     t = fma32(np.float32(-2.0) * ax, bx, t)
@@ -184,10 +189,10 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, x
         def bands(e2):
             return pc.fp32_bands_axes(e2, ndim, axis_eps, coord_scale)
     else:
-        s32 = emulate_r_xy(pi, pj, g, L, c).astype(np.float64) / (c * c)
+        s32 = emulate_r_xy(pi, pj, g, L, c, ndim).astype(np.float64) / (c * c)
 
         def bands(e2):
-            return pc.fp32_bands_xy(e2, axis_eps, xy_max, coord_scale)
+            return pc.fp32_bands_xy(e2, axis_eps, xy_max, coord_scale, ndim)
     E = edges * edges
     lo, hi = bands(E)
     for k in range(E.size):
@@ -217,7 +222,8 @@ def scale_for(edges, S, top=32766.0 / 32767.0):
 
 
 @pytest.mark.parametrize("case", ["r_box420", "r_box1100_k2", "rp_box1000", "chord_open",
-                                  "r_box420_xy", "r_box1100_k2_xy", "chord_open_xy"])
+                                  "r_box420_xy", "r_box1100_k2_xy", "rp_box1000_xy",
+                                  "chord_open_xy"])
 def test_fp32_bound_holds_on_1e8_pairs(case):
     """The _xy cases: the expanded form of x and y (cf_options.separation_form
     2) against its own bands, fewer pairs (the bound's arithmetic is the

@@ -1,10 +1,11 @@
 """The two forms of the float32 squared separation (needs an MI355X).
 
-cf_options.separation_form 1 takes dx^2 + dy^2 + dz^2 from the coordinate
-differences; 2 expands x and y as |a|^2 + |b|^2 - 2 a.b (one instruction
-fewer per pair, a larger absolute rounding bound folded into the decision
-bands); 0 picks 2 for float32 DD(r) and chords of 3-D grids unless the
-bound would widen the smallest edge's band by more than an eighth of it.
+cf_options.separation_form 1 takes dx^2 + dy^2 + dz^2 (rp^2: dx^2 + dy^2)
+from the coordinate differences; 2 expands x and y as |a|^2 + |b|^2 - 2 a.b
+(one instruction fewer per pair, a larger absolute rounding bound folded into
+the decision bands; DD(rp, pi), single and batched, on request only); 0 picks
+2 for float32 DD(r) and chords of 3-D grids unless the bound would widen the
+smallest edge's band by more than an eighth of it.
 Both forms must give the oracle's counts exactly, whatever the workload:
 clustered and uniform points, periodic and open boxes, auto- and
 cross-correlations, weights, a first edge of zero, integer lattices with
@@ -143,16 +144,66 @@ def test_mean_separation_keeps_differences(pc, olib):
     assert pc.stats()["separation_form"] == 1
 
 
-def test_other_statistics_and_fp64_report(pc, olib):
-    say("separation forms reports")
+def test_fp64_reports_no_form(pc):
+    say("separation forms fp64")
     pts = synth.uniform_box(5000, 50.0, seed=1210)
     e = synth.log_edges(0.5, 5.0, 6)
     pc.count_r(pts, None, e, 50.0, "fp64", options=form(2))
     assert pc.stats()["separation_form"] == 0
-    want, _ = oracle.count_rppi(pts, None, e, 10.0, 10, 50.0, lib=olib)
-    got, _ = pc.count_rppi(pts, None, e, 10.0, 10, 50.0, "fp32", options=form(2))
-    assert (got == want).all()
-    assert pc.stats()["separation_form"] == 1
+
+
+@pytest.mark.parametrize("box", [150.0, 0.0])
+def test_rppi_forms(pc, olib, box):
+    """rp^2 expanded as fl(fl(|a|^2 + |b|^2) - 2 a_x b_x) - 2 a_y b_y, with
+    the fixed-point pi test unchanged."""
+    say("separation forms rppi", box)
+    pts = synth.clustered_box(25000, 150.0, seed=1212, nblobs=120, sigma=2.0)
+    e = synth.log_edges(0.2, 15.0, 14)
+    want, _ = oracle.count_rppi(pts, None, e, 20.0, 20, box, lib=olib)
+    for f in (0, 1, 2):
+        got, _ = pc.count_rppi(pts, None, e, 20.0, 20, box, "fp32", options=form(f))
+        assert (got == want).all(), (f, box)
+        # (the default keeps the differences for rp/pi)
+        assert pc.stats()["separation_form"] == (2 if f == 2 else 1)
+    # weighted cross-correlation, both forms
+    y = synth.uniform_box(15000, 150.0, seed=1213)
+    wx = synth.uniform_weights(25000, 1214)
+    wy = synth.uniform_weights(15000, 1215)
+    want, ww = oracle.count_rppi(pts, y, e, 20.0, 20, box, w1=wx, w2=wy, lib=olib)
+    for f in (1, 2):
+        got, gw = pc.count_rppi(pts, y, e, 20.0, 20, box, "fp32", w1=wx, w2=wy,
+                                options=form(f))
+        assert (got == want).all(), (f, box)
+        np.testing.assert_allclose(gw, ww, rtol=WSUM_RTOL, atol=0)
+
+
+def test_rppi_lattice_ties(pc, olib):
+    """Integer lattice, integer rp^2 edges and integer pi edges: ties in
+    both dimensions go to the binary64 recheck in both forms."""
+    say("separation forms rppi lattice")
+    rng = synth.rng_for(1216)
+    pts = rng.integers(0, 30, size=(6000, 3)).astype(np.float64)
+    e = np.sqrt(np.arange(1.0, 12.0))
+    for box in (30.0, 0.0):
+        want, _ = oracle.count_rppi(pts, None, e, 6.0, 6, box, lib=olib)
+        for f in (1, 2):
+            got, _ = pc.count_rppi(pts, None, e, 6.0, 6, box, "fp32", options=form(f))
+            assert (got == want).all(), (box, f)
+
+
+def test_batched_rppi_forms(pc, olib):
+    say("separation forms batched")
+    L = 200.0
+    sizes = [9000, 300, 0, 4000, 1, 2500]
+    cats = [synth.clustered_box(n, L, seed=1220 + k, nblobs=max(1, n // 200), sigma=2.0)
+            for k, n in enumerate(sizes)]
+    e = synth.log_edges(0.2, 18.0, 12)
+    wants = [oracle.count_rppi(p, None, e, 25.0, 25, L, lib=olib)[0] for p in cats]
+    for f in (1, 2):
+        got, _ = pc.count_rppi_batch(cats, e, 25.0, 25, L, "fp32", options=form(f))
+        for k in range(len(cats)):
+            assert (got[k] == wants[k]).all(), (f, k)
+        assert pc.stats()["separation_form"] == f
 
 
 def test_invalid_form_refused(pc):
