@@ -493,7 +493,7 @@ cf_status stage_side(cf_ctx *c, const cf_catalog *d, int ncat, bool radec, bool 
 // catalogue k are k * ncell .. (k + 1) * ncell - 1, so the sorted arrays hold
 // the catalogues one after the other, each in cell order.
 // Q (or B_COUNT: none): (x, y, z, |b|^2) in float32 of every sorted point,
-// side by side, for sweeps that expand x and y (besides X, Y, Z)
+// side by side, for sweeps that expand x and y (with Z; X and Y not written)
 cf_status grid_side(cf_ctx *c, const SideData &s, const pc_cat *cats_dev, bool weighted,
                     const pc_grid &g, BufId start, BufId X, BufId Y, BufId Z, BufId XD, BufId YD,
                     BufId ZD, BufId WD, BufId CS, BufId Q, unsigned *flags)

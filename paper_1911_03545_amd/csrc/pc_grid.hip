@@ -579,14 +579,17 @@ __device__ __forceinline__ void store_sorted(const pc_grid &g, const double4 &r,
         fz = __uint_as_float((uint32_t)llrint((r.z - g.lo[2]) * g.zq_inv) + PC_ZQ_BIAS);
     else
         fz = (float)((r.z - g.lo[2]) * g.fscale);
-    X[d] = fx;
-    Y[d] = fy;
-    Z[d] = fz;
     // the expanded form's j points: x, y, z and |b|^2 = fl(y y + fl(x x)),
-    // rounded as the sweep's bound assumes, side by side (the lane side
-    // still reads the separate arrays: the rp/pi lane its fixed-point z)
-    if (P)
+    // rounded as the sweep's bound assumes, side by side; its lanes read
+    // binary64 x and y, and z from Z (the rp/pi lane its fixed-point z), so
+    // X and Y are then not written
+    if (P) {
         P[d] = make_float4(fx, fy, fz, __fmaf_rn(fy, fy, __fmul_rn(fx, fx)));
+    } else {
+        X[d] = fx;
+        Y[d] = fy;
+    }
+    Z[d] = fz;
     xd[d] = r.x;
     yd[d] = r.y;
     zd[d] = r.z;

@@ -106,7 +106,8 @@ hipError_t scan_exclusive(hipStream_t s, const int32_t *in, int64_t n, int32_t *
 // place every point at start[cell] + rank: a permutation scatter of source
 // indices into `perm` (ntot int32), then a gather in sorted order.  P
 // (optional; the expanded float32 sweeps): the float32 x, y, z and
-// fl(y y + fl(x x)) of every sorted point side by side, besides X, Y, Z.
+// fl(y y + fl(x x)) of every sorted point side by side, written with Z in
+// place of X and Y.
 hipError_t launch_scatter(hipStream_t s, int64_t ntot, const pc_grid &g, const int32_t *cell_of,
                           const int32_t *rank_of, const void *rec, const int32_t *start,
                           int32_t *perm, float *X, float *Y, float *Z, double *xd, double *yd,
