@@ -96,6 +96,15 @@ struct cf_ctx {
     size_t scratch_cap = 0;
     bool arena = false;
     size_t arena_off = 0;
+    // small inputs the last eager call left on the device (the catalogue
+    // descriptors, the bin description with its table): the bytes and the
+    // buffer they went to.  An identical repeat skips its copy (and the table
+    // build); a buffer (re)allocation, a graph capture or replay clears them.
+    struct Upload {
+        std::vector<char> bytes;
+        const void *p = nullptr;
+    };
+    Upload up_cats1, up_bins;
 };
 
 namespace {
@@ -138,6 +147,23 @@ hipError_t release(cf_ctx *c, DevBuf &b)
     return e;
 }
 
+bool upload_fresh(const cf_ctx::Upload &u, const void *dev, const void *src, size_t n)
+{
+    return u.p == dev && u.bytes.size() == n && memcmp(u.bytes.data(), src, n) == 0;
+}
+
+void upload_keep(cf_ctx::Upload &u, const void *dev, const void *src, size_t n)
+{
+    u.p = dev;
+    u.bytes.assign(static_cast<const char *>(src), static_cast<const char *>(src) + n);
+}
+
+void uploads_clear(cf_ctx *c)
+{
+    c->up_cats1 = cf_ctx::Upload{};
+    c->up_bins = cf_ctx::Upload{};
+}
+
 cf_status ensure(cf_ctx *c, BufId id, size_t bytes)
 {
     bytes = std::max<size_t>(bytes, 256);
@@ -164,6 +190,7 @@ cf_status ensure(cf_ctx *c, BufId id, size_t bytes)
     }
     // a recorded graph holds the addresses of these buffers
     drop_graph(c);
+    uploads_clear(c);
     if (b.p) {
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(release(c, b));
@@ -786,9 +813,21 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     if ((st2 = ensure(c, B_CATS1, sizeof(pc_cat) * (size_t)ncat)) ||
         (st2 = ensure(c, B_CATS2, sizeof(pc_cat))))
         return st2;
-    memcpy(pin + p_cats1, s1.cats.data(), sizeof(pc_cat) * (size_t)ncat);
-    HIPCHK(hipMemcpyAsync(c->buf[B_CATS1].p, pin + p_cats1, sizeof(pc_cat) * (size_t)ncat,
-                          hipMemcpyHostToDevice, c->stream));
+    // (eager calls of the context's own buffers keep their uploads; a graph
+    // capture records every copy, and a no-allocation call's buffers are
+    // shared by every context on the device)
+    const bool keep_uploads = !ctl.capture && !c->arena;
+    const size_t cats1_bytes = sizeof(pc_cat) * (size_t)ncat;
+    if (!(keep_uploads &&
+          upload_fresh(c->up_cats1, c->buf[B_CATS1].p, s1.cats.data(), cats1_bytes))) {
+        memcpy(pin + p_cats1, s1.cats.data(), cats1_bytes);
+        HIPCHK(hipMemcpyAsync(c->buf[B_CATS1].p, pin + p_cats1, cats1_bytes,
+                              hipMemcpyHostToDevice, c->stream));
+        if (keep_uploads)
+            upload_keep(c->up_cats1, c->buf[B_CATS1].p, s1.cats.data(), cats1_bytes);
+        else
+            c->up_cats1 = cf_ctx::Upload{};
+    }
     if (!autocorr) {
         memcpy(pin + p_cats2, s2.cats.data(), sizeof(pc_cat));
         HIPCHK(hipMemcpyAsync(c->buf[B_CATS2].p, pin + p_cats2, sizeof(pc_cat),
@@ -1003,15 +1042,20 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         return fail(c, CF_EINVAL, "bin description too large");
     if ((st2 = ensure(c, B_BINS, hb.lay.total)))
         return st2;
-    memcpy(pin + p_bins, hb.buf.data(), hb.buf.size());
-    HIPCHK(hipMemcpyAsync(c->buf[B_BINS].p, pin + p_bins, hb.buf.size(), hipMemcpyHostToDevice,
-                          c->stream));
-    {
+    if (!(keep_uploads &&
+          upload_fresh(c->up_bins, c->buf[B_BINS].p, hb.buf.data(), hb.buf.size()))) {
+        memcpy(pin + p_bins, hb.buf.data(), hb.buf.size());
+        HIPCHK(hipMemcpyAsync(c->buf[B_BINS].p, pin + p_bins, hb.buf.size(),
+                              hipMemcpyHostToDevice, c->stream));
         char *bd = static_cast<char *>(c->buf[B_BINS].p);
         HIPCHK(pc::launch_build_table(c->stream, hb.hdr, nb + 1,
                                       (const float *)(bd + hb.lay.lo),
                                       (const float *)(bd + hb.lay.hi),
                                       (const float *)(bd + hb.lay.lo_min), bd + hb.lay.tbl));
+        if (keep_uploads)
+            upload_keep(c->up_bins, c->buf[B_BINS].p, hb.buf.data(), hb.buf.size());
+        else
+            c->up_bins = cf_ctx::Upload{};
     }
     record(c, timing, 2);
 
@@ -1402,6 +1446,7 @@ std::vector<char> call_key(int metric, bool theta, const cf_catalog *d1, int32_t
 
 void drop_graph(cf_ctx *c)
 {
+    uploads_clear(c);
     if (c->gexec)
         (void)hipGraphExecDestroy(c->gexec);
     if (c->graph)
@@ -1417,6 +1462,8 @@ void drop_graph(cf_ctx *c)
 cf_status replay(cf_ctx *c, uint64_t *counts, double *wsum, const cf_options &opt)
 {
     HIPCHK(hipSetDevice(c->device));
+    // the graph writes its own uploads into the same buffers
+    uploads_clear(c);
     HIPCHK(hipGraphLaunch(c->gexec, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     const char *pin = static_cast<const char *>(c->gpin);

@@ -837,13 +837,12 @@ __device__ void sky_segments(const SegCtx &c, const pc_block &b, F &&f)
     }
 }
 
-template <bool SKY, class F>
-__device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
+// KX > 0: the x/y refinement is KX (a compile-time constant, so the loops
+// over neighbour columns unroll and their cell-start loads are in flight
+// together); 0: read it from the grid.
+template <int KX, class F>
+__device__ __forceinline__ void grid_segments(const SegCtx &c, const pc_block &b, F &&f)
 {
-    if constexpr (SKY) {
-        sky_segments(c, b, f);
-        return;
-    }
     const int nx = c.g.n[0], ny = c.g.n[1], nz = c.g.n[2];
     // columns are numbered across catalogues: catalogue k owns columns
     // k * nx * ny ..; neighbours stay inside the block's own catalogue
@@ -893,7 +892,7 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
         zwin(cbase + jx * ny + jy, code, zw);
     };
 
-    const int k = c.g.xyk;
+    const int k = KX > 0 ? KX : c.g.xyk;
     if (c.autocorr) {
         if (b.ni > 1)
             f(b.i0 + 1, b.i0 + b.ni, 0u, 1);
@@ -916,6 +915,19 @@ __device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
         for (int ox = -k; ox <= k; ox++)
             for (int oy = -k; oy <= k; oy++)
                 column(ox, oy);
+    }
+}
+
+template <bool SKY, class F>
+__device__ void for_each_segment(const SegCtx &c, const pc_block &b, F &&f)
+{
+    if constexpr (SKY) {
+        sky_segments(c, b, f);
+    } else {
+        if (c.g.xyk == 1)
+            grid_segments<1>(c, b, f);
+        else
+            grid_segments<0>(c, b, f);
     }
 }
 
