@@ -32,7 +32,7 @@ enum BufId {
     B_CNT, B_START1, B_START2, B_CELLOF, B_RANKOF, B_PERM, B_REC, B_WOFF, B_LAY, B_COLS,
     B_X1, B_Y1, B_Z1, B_XD1, B_YD1, B_ZD1, B_WD1, B_CS1,
     B_X2, B_Y2, B_Z2, B_XD2, B_YD2, B_ZD2, B_WD2, B_CS2, B_Q1, B_Q2,
-    B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS,
+    B_SCANTMP, B_BCNT, B_BOFF, B_BLOCKS, B_ICNT, B_IOFF, B_ITEMS, B_ICELL,
     B_BINS, B_BANDS, B_MISC, B_HIST, B_WHIST, B_OUTC, B_OUTW, B_RHIST, B_OUTR, B_PART, B_CTRS, B_CATS1, B_CATS2, B_UV1, B_UV2, B_WSQ,
     B_COUNT
 };
@@ -1112,12 +1112,17 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
             return fail(c, CF_EOVERFLOW, "work-item count overflow");
         c->last_items = n_items;
     }
-    if ((st2 = ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)std::max(n_items, 1))))
+    if ((st2 = ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)std::max(n_items, 1))) ||
+        (g.xy_local && (st2 = ensure(c, B_ICELL, sizeof(int32_t) * (size_t)std::max(n_items, 1)))))
         return st2;
+    // (the float32 sweep of 3-D grids takes each item's j column from the
+    // cell of its first j point, written beside the items)
+    const int32_t *cs2_dev = dptr<int32_t>(c, autocorr ? B_CS1 : B_CS2);
     HIPCHK(pc::launch_item_emit(c->stream, (int32_t)maxblocks, nblocks_dev,
                                 dptr<pc_block>(c, B_BLOCKS), g, start2, dptr<int32_t>(c, B_CS1),
                                 autocorr ? 1 : 0, chunk, dptr<int32_t>(c, B_IOFF),
-                                dptr<pc_item>(c, B_ITEMS), n_items, flags));
+                                dptr<pc_item>(c, B_ITEMS), n_items, flags, cs2_dev,
+                                g.xy_local ? dptr<int32_t>(c, B_ICELL) : nullptr));
     record(c, timing, 3);
 
     // ---- sweep -------------------------------------------------------------
@@ -1182,6 +1187,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.gw[1] = g.width[1];
     a.fscale = g.fscale;
     a.cs2 = autocorr ? dptr<int32_t>(c, B_CS1) : dptr<int32_t>(c, B_CS2);
+    a.icell = g.xy_local ? dptr<int32_t>(c, B_ICELL) : nullptr;
     a.nbt = (int32_t)nbt;
     a.slots = (int32_t)((nb + 2) * hb.hdr.row_w);
     a.priv = priv ? 1 : 0;
@@ -1538,7 +1544,8 @@ void record_graph(cf_ctx *c, std::vector<char> &&key, const RunCtl &eager, int m
         return;
     ctl.pin = static_cast<char *>(c->gpin);
     ctl.pin_cap = c->gpin_cap;
-    if (ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)ctl.item_cap) != CF_OK)
+    if (ensure(c, B_ITEMS, sizeof(pc_item) * (size_t)ctl.item_cap) != CF_OK ||
+        ensure(c, B_ICELL, sizeof(int32_t) * (size_t)ctl.item_cap) != CF_OK)
         return;
     const cf_stats keep = c->stats;
     const std::string keep_err = c->err;

@@ -960,7 +960,7 @@ __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
 template <bool SKY>
 __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const pc_block *blocks,
                             SegCtx c, int chunk, const int32_t *ioff, pc_item *items, int32_t cap,
-                            unsigned *flags)
+                            unsigned *flags, const int32_t *cs2, int32_t *icell)
 {
     const int nb = nblocks_dev ? *nblocks_dev : nblocks;
     for (int bi = blockIdx.x * blockDim.x + threadIdx.x; bi < nb;
@@ -976,8 +976,11 @@ __global__ void k_item_emit(int32_t nblocks, const int32_t *nblocks_dev, const p
                 it.j1 = min(j + chunk, j1);
                 it.meta = (unsigned)(b.ni - 1) | (dcode << 6) | ((unsigned)tri << 12) |
                           ((unsigned)cat << 13);
-                if (o < cap)
+                if (o < cap) {
                     items[o] = it;
+                    if (icell)
+                        icell[o] = cs2[j];
+                }
                 o++;
             }
         });
@@ -1268,12 +1271,14 @@ hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblo
 hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
                             const int32_t *cell1_sorted, int autocorr, int chunk,
-                            const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags)
+                            const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags,
+                            const int32_t *cell2_sorted, int32_t *icell)
 {
     SegCtx c{g, start2, cell1_sorted, autocorr};
     hipLaunchKernelGGL(g.nband > 0 ? k_item_emit<true> : k_item_emit<false>,
                        dim3(grid_for(nblocks, 128)), dim3(128), 0, s, nblocks,
-                       nblocks_dev, blocks, c, chunk, ioff, items, cap, flags);
+                       nblocks_dev, blocks, c, chunk, ioff, items, cap, flags, cell2_sorted,
+                       icell);
     return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ struct SweepArgs {
     double gw[2];
     double fscale;
     const int32_t *cs2;   // cell id of every sorted point of side 2
+    const int32_t *icell; // cell id of every item's first j point
     int32_t priv;       // per-wave private replicas, flushed per catalogue (batches)
     int32_t copies;     // LDS histogram replicas per wave (power of two; 64 = one per
                         // lane with unconditional updates, 1-D unweighted only)
@@ -143,10 +144,14 @@ hipError_t launch_item_count(hipStream_t s, int32_t nblocks, const int32_t *nblo
                              const pc_block *blocks, const pc_grid &g, const int32_t *start2,
                              const int32_t *cell1_sorted, int autocorr, int chunk,
                              int32_t *icnt, unsigned long long *cand);
+// icell (optional, with cell2_sorted): the cell id of every item's first j
+// point, beside the items (the float32 sweep of 3-D grids reads it one item
+// ahead, with the item, to place its lanes in the j column's frame)
 hipError_t launch_item_emit(hipStream_t s, int32_t nblocks, const int32_t *nblocks_dev,
                             const pc_block *blocks, const pc_grid &g, const int32_t *start2,
                             const int32_t *cell1_sorted, int autocorr, int chunk,
-                            const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags);
+                            const int32_t *ioff, pc_item *items, int32_t cap, unsigned *flags,
+                            const int32_t *cell2_sorted, int32_t *icell);
 // wmode: 0 unweighted, 1 weight sums, 2 weight and mean-separation sums
 hipError_t launch_sweep(hipStream_t s, int metric, bool fp32, int wmode, const SweepArgs &a,
                         int nwg);

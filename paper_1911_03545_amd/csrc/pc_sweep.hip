@@ -1225,8 +1225,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     LanePt lp = {0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f, 0.0f};
     int next = wave_fetch(a.counter, n_items, lane, stream, probe);
     pc_item nit = {};
-    if (P32 && next < n_items)
+    // (3-D grids: the cell of the next item's first j point, read with the
+    // item so that its column is known when the item starts)
+    const KCONST int32_t *icell = (const KCONST int32_t *)a.icell;
+    int ncell = 0;
+    if (P32 && next < n_items) {
         nit = a.items[next];
+        if (a.xy_local)
+            ncell = icell[next];
+    }
     // Unweighted float32 r sweeps of one catalogue also start the take of the
     // item after the next one before running an item (one atomic increment
     // on the wave's stream, `pend`), read its result only at the next item
@@ -1243,6 +1250,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         // load after the take)
         const int cur = next;
         const pc_item it = P32 ? nit : a.items[cur];
+        const int jcell = ncell;
         if (PIPE && pend) {
             pend = false;
             const int first = (int)(((long long)n_items * stream) / PC_STREAMS);
@@ -1258,8 +1266,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
         } else {
             next = wave_fetch(a.counter, n_items, lane, stream, probe);
         }
-        if (P32 && next < n_items)
+        if (P32 && next < n_items) {
             nit = a.items[next];
+            if (a.xy_local)
+                ncell = icell[next];
+        }
         if (PIPE && next < n_items && !probe) {
             if (lane == 0)
                 pv = atomicAdd(a.counter + stream * PC_STREAM_STRIDE, 1);
@@ -1291,8 +1302,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             // the item's j column (every j point of an item lies in one column)
             int jx = 0, jy = 0;
             if (a.xy_local)
-                cell_column(__builtin_amdgcn_readfirstlane(((const KCONST int32_t *)a.cs2)[it.j0]),
-                            a.gnx, a.gny, a.gnz, &jx, &jy);
+                cell_column(__builtin_amdgcn_readfirstlane(jcell), a.gnx, a.gny, a.gnz, &jx, &jy);
             constexpr bool PK = !PRIV && !T16;
             if (PIPE && (it.i0 != lp_i0 || ni != lp_ni)) {
                 lp = load_lane<M, W>(a, i, act);
