@@ -894,13 +894,14 @@ __device__ __forceinline__ void grid_segments(const SegCtx &c, const pc_block &b
 
     const int k = KX > 0 ? KX : c.g.xyk;
     if (c.autocorr) {
-        if (b.ni > 1)
-            f(b.i0 + 1, b.i0 + b.ni, 0u, 1);
+        // the block against itself (its triangle, j < i0 + ni) and its column
+        // forward up to the reach: one contiguous segment flagged as holding
+        // the triangle (the sweep masks only the chunks that reach into it)
         const int64_t base = (int64_t)b.col * nz;
         const int hi_s = sb + zr;
-        const int jend = c.start2[base + min(hi_s, nz - 1) + 1];
-        if (jend > b.i0 + b.ni)
-            f(b.i0 + b.ni, jend, 0u, 0);
+        const int jend = max(c.start2[base + min(hi_s, nz - 1) + 1], b.i0 + b.ni);
+        if (jend > b.i0 + 1)
+            f(b.i0 + 1, jend, 0u, 1);
         if (per && hi_s >= nz) {
             const int w1 = min(hi_s - nz, nz - 1);
             f(c.start2[base], c.start2[base + w1 + 1], PC_D_MINUS << 4, 0);
@@ -946,7 +947,10 @@ __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
             if (j1 <= j0)
                 return;
             total += (j1 - j0 + chunk - 1) / chunk;
-            my += tri ? (unsigned long long)b.ni * (b.ni - 1) / 2
+            // a triangle segment: the block's unique pairs with itself, then
+            // every j beyond the block (j1 >= i0 + ni)
+            my += tri ? (unsigned long long)b.ni * (b.ni - 1) / 2 +
+                            (unsigned long long)b.ni * (unsigned long long)(j1 - b.i0 - b.ni)
                       : (unsigned long long)b.ni * (unsigned long long)(j1 - j0);
         });
         icnt[bi] = total;

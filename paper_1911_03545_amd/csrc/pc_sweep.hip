@@ -1011,6 +1011,17 @@ __device__ __forceinline__ void item_f64(const SweepArgs &a, const Lds &L, lds_u
     }
 }
 
+// End of the triangle-masked part of an item [j0, j1) whose block ends at
+// iend: the chunks (CH pairs each, as item_f32 and item_f64 take them) up to
+// the first chunk boundary at or past iend.
+template <int W>
+__device__ __forceinline__ int tri_end(int j0, int j1, int iend)
+{
+    constexpr int CH = W ? 4 : 8;
+    const int n = max(iend - j0, 0);
+    return min(j1, j0 + (n + CH - 1) / CH * CH);
+}
+
 // Take the next work item for this wave from stream s, moving on to the
 // following streams once it is exhausted.  Stream s owns the contiguous
 // items [s n / S, (s + 1) n / S), so a wave's consecutive items are
@@ -1309,21 +1320,28 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
                 lp_i0 = it.i0;
                 lp_ni = ni;
             }
-            if (tri)
-                item_f32<M, W, true, T16, UNC, PK, PIPE, EXP>(a, L, hb, whb, i, act, lp, it.j0, it.j1,
+            // an item that holds (part of) the block's triangle masks its
+            // chunks up to the block's end (rounded up to whole chunks: the
+            // mask passes every j >= i0 + ni) and runs the rest unmasked
+            const int tm = tri ? tri_end<W>(it.j0, it.j1, it.i0 + ni) : it.j0;
+            if (tm > it.j0)
+                item_f32<M, W, true, T16, UNC, PK, PIPE, EXP>(a, L, hb, whb, i, act, lp, it.j0, tm,
                                                          dcode, rechecks, jx, jy);
-            else
-                item_f32<M, W, false, T16, UNC, PK, PIPE, EXP>(a, L, hb, whb, i, act, lp, it.j0,
+            if (it.j1 > tm)
+                item_f32<M, W, false, T16, UNC, PK, PIPE, EXP>(a, L, hb, whb, i, act, lp, tm,
                                                           it.j1, dcode, rechecks, jx, jy);
         } else {
-            if (tri)
-                item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1, dcode);
-            else if (dcode == 0u)
-                item_f64<M, W, false, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1,
-                                                       dcode);
-            else
-                item_f64<M, W, false, true, T16, UNC>(a, L, hb, whb, i, act, it.j0, it.j1,
-                                                      dcode);
+            const int tm = tri ? tri_end<W>(it.j0, it.j1, it.i0 + ni) : it.j0;
+            if (tm > it.j0)
+                item_f64<M, W, true, false, T16, UNC>(a, L, hb, whb, i, act, it.j0, tm, dcode);
+            if (it.j1 > tm) {
+                if (dcode == 0u)
+                    item_f64<M, W, false, false, T16, UNC>(a, L, hb, whb, i, act, tm, it.j1,
+                                                           dcode);
+                else
+                    item_f64<M, W, false, true, T16, UNC>(a, L, hb, whb, i, act, tm, it.j1,
+                                                          dcode);
+            }
         }
     }
     // the result of a take still in flight (past the last item) is waited
