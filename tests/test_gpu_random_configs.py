@@ -5,7 +5,8 @@ Each case draws a statistic (DD(r), DD(rp, pi), DD(theta), on-sky DD(rp,
 pi), batched DD(rp, pi)), auto or cross, periodic or not, float32 or
 float64 inputs on the host or the device, weights (product or sum), the mean
 separation, precision, slices per reach, work-item chunk, x/y or angular
-refinement, RA/DEC input converted on the host or unit vectors, and bin edges (log, linear, with e0 = 0 or not), with sizes the
+refinement, the float32 separation form, RA/DEC input converted on the host or
+unit vectors, and bin edges (log, linear, with e0 = 0 or not), with sizes the
 oracle counts in well under a second.  Counts must equal the oracle's bit for
 bit; weighted sums within 1e-12 relative; mean separations within 1e-9
 relative in binary64, and in float32 within the bound 10u C + 8u r of the
@@ -119,6 +120,11 @@ def test_random_config(pc, olib, case):
     ravg = bool(rng.random() < 0.3)
     prec = str(rng.choice(["fp64", "fp32"]))
     opts = options_for(rng, stat)
+    # the float32 separation form (drawn from a stream of its own, so that
+    # every other draw of the case stays as it was)
+    form = int(synth.rng_for(9100 + case).integers(0, 3))
+    if form:
+        opts["separation_form"] = form
     n1 = int(rng.integers(0, 6000)) if rng.random() < 0.1 else int(rng.integers(500, 12000))
     n2 = int(rng.integers(300, 9000))
     say(f"case {case}: {stat} auto={auto} w={wtype} ravg={ravg} {prec} n1={n1} n2={n2} {opts}")
