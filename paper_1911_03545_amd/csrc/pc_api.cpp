@@ -1176,6 +1176,10 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.flush_count = (unsigned *)(misc(c) + M_FLUSH);
     a.xy_local = g.xy_local;
     a.xy_exp = xy_mag > 0.0 ? 1 : 0;
+    a.xy_K = 0.0f;
+    a.xy_M = 0.0f;
+    if (xy_mag > 0.0 && metric == PC_METRIC_R)
+        pc::xy_pair_margin(xy_mag, g.fscale, &a.xy_K, &a.xy_M);
     a.P2 = xy_mag > 0.0 ? static_cast<const float4 *>(c->buf[autocorr ? B_Q1 : B_Q2].p)
                         : nullptr;
     a.gnx = g.n[0];

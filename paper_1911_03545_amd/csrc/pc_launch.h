@@ -59,6 +59,10 @@ struct SweepArgs {
     // 2 in float32 (z: the rp/pi path's fixed-point bits)
     int32_t xy_exp;
     const float4 *P2;
+    // the expanded bands hold the magnitude term xy_M (scaled coordinates)
+    // times xy_K; a pair whose own magnitude term m is smaller may narrow
+    // both sides of its band by xy_K (xy_M - m) (both rounded down)
+    float xy_K, xy_M;
     int32_t gnx, gny, gnz;
     double glo[3];
     double gw[2];

@@ -332,6 +332,19 @@ double xy_expand_mag(const double a_max[2], const double b_max[2], int ndim)
     return ndim == 2 ? 4.0 * A + 4.0 * B + 2.0 * P : 5.0 * B + 2.0 * A + 4.0 * P;
 }
 
+// The bound above holds for each pair with its own magnitudes, m = 5 |b|^2
+// + 2 |a|^2 + 4 (|a_x b_x| + |a_y b_y|), in place of xy_mag; every band
+// holds kSafety u (1 + 2^-20) xy_mag of it, so a pair may narrow both sides
+// of its band by kSafety u (1 + 2^-20) (xy_mag - m).  In the scaled
+// coordinates the band (scaled by c^2 and rounded outward) narrows by K (M -
+// m) with M = c^2 xy_mag, m from the float32 |a|^2 and |b|^2 the sweep holds
+// (each within 2u of the exact value) and |a_x b_x| + |a_y b_y| <= |a| |b|.
+void xy_pair_margin(double xy_mag, double fscale, float *K, float *M)
+{
+    *K = float_down(kSafety * kU32 * (1.0 + 0x1p-20) * (1.0 - 0x1p-40));
+    *M = float_down(xy_mag * fscale * fscale * (1.0 - 0x1p-40));
+}
+
 int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *axis_eps,
                     double scale, float *lo, float *hi, double xy_mag)
 {

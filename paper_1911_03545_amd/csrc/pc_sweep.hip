@@ -408,6 +408,32 @@ __device__ __forceinline__ int exact_slot_r_at(const SweepArgs &a, const Lds &L,
     return exact_bin<PC_METRIC_R>(s, pz, L.E, a.B.nb, L.q, 1, 0.0) + 1;
 }
 
+// An expanded r pair whose float32 value lies inside its edge's band: the
+// band holds the rounding term of the largest magnitudes a lane and a j point
+// can have; narrowed by the pair's own term, from the lane's A = |a|^2 and
+// the j point's |b|^2, it often decides the pair without the binary64
+// recheck.  -1 when the value stays inside the narrowed band, or the cell
+// holds several bands.  Every float32 rounding errs towards a narrower
+// narrowing: m is rounded up, the narrowing and the differences below down.
+template <bool T16>
+__device__ __forceinline__ int tight_slot(const SweepArgs &a, const Lds &L, float s, int e,
+                                          float A, int j)
+{
+    if (is_multi<T16>(e))
+        return -1;
+    const int c = band_edge<T16>(e);
+    const float q = ((kf32p)a.P2)[4 * j + 3];
+    // m >= 5 |b|^2 + 2 |a|^2 + 4 |a| |b|, as 4 |a| |b| <= 6 |b|^2 + (2/3)
+    // |a|^2; (1 + 2^-18) covers the roundings of A, |b|^2 and of m itself
+    const float m = fmaf(11.0f, q, 2.75f * A) * (1.0f + 0x1p-18f);
+    const float D = a.xy_K * (a.xy_M - m) * (1.0f - 0x1p-18f);
+    if (s - L.hi[c] > -D)
+        return c + 1;
+    if (L.lo[c] - s > -D)
+        return c;
+    return -1;
+}
+
 // ---- float32 chunk: CH pairs sharing lane i ------------------------------
 // Three phases so that the CH table reads are in flight together: (1)
 // separations, candidate masks and table keys, (2) table reads, (3) slot
@@ -486,11 +512,15 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
 #pragma unroll
         for (int k = 0; k < CH; k++)
             any |= (unsigned)e[k];
-        if (U8 ? any >= PC_TBL8_BAND : is_slow<T16>((int)any)) {
+        if (__builtin_expect(U8 ? any >= PC_TBL8_BAND : is_slow<T16>((int)any), 0)) {
 #pragma unroll
             for (int k = 0; k < CH; k++) {
                 if (U8 ? (unsigned)e[k] >= PC_TBL8_BAND : is_slow<T16>(e[k])) {
                     int slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
+                    if constexpr (EXP) {
+                        if (slot < 0)
+                            slot = tight_slot<T16>(a, L, s[k], e[k], A, j + k);
+                    }
                     if (slot < 0) {
                         // (the expanded form runs on 3-D grids, whose lane
                         // point holds the binary64 coordinates)
@@ -514,6 +544,10 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         int slot = e[k];
         if (is_slow<T16>(e[k])) {
             slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
+            if constexpr (EXP) {
+                if (slot < 0)
+                    slot = tight_slot<T16>(a, L, s[k], e[k], A, j + k);
+            }
             if (slot < 0) {
                 slot = EXP ? exact_slot_r_at(a, L, lp.x, lp.y, lp.z, j + k, dcode)
                            : exact_slot<M>(a, L, i, j + k, dcode);

@@ -17,7 +17,11 @@ few ulps of every edge), and check that
   s64 < E_k and s32 > hi_k implies s64 > E_k;
 
 for DD(r) (3 axes), rp^2 (2 axes) and squared chords of unit vectors
-(3 axes, no box), and that the fixed-point line-of-sight coordinate of the
+(3 axes, no box).  The expanded form of squared r (x and y as |a|^2 + |b|^2
+- 2 a.b) is also checked with each band narrowed by the pair's own magnitude
+term, computed in float32 as the sweep does before its binary64 recheck: no
+wrong decision, and |s32 - s64| stays within the pair's own raw bound.  And
+that the fixed-point line-of-sight coordinate of the
 float32 DD(rp, pi) path stays within 1.5 quanta of the exact |dz|, below the
 2-quanta margin inside which pi bins are re-decided in binary64.
 """
@@ -124,7 +128,7 @@ def emulate_r(pi, pj, g, L, c, ndim):
     return fma32(dz, dz, t)
 
 
-def emulate_r_xy(pi, pj, g, L, c, ndim=3):
+def emulate_r_xy(pi, pj, g, L, c, ndim=3, parts=False):
     """float32 s of the expanded form: |b|^2 = fl(by by + fl(bx bx)) per j
     point, |a|^2 = fl(ay ay + fl(ax ax)) per lane, then fl(dz dz + |b|^2),
     fl(-2 ax bx + .), fl(-2 ay by + .) and fl(. + |a|^2) for r; for rp^2
@@ -144,12 +148,38 @@ def emulate_r_xy(pi, pj, g, L, c, ndim=3):
     if ndim == 2:
         # rp^2: fl(A + |b|^2) first, then the two products
         t = fma32(np.float32(-2.0) * ax, bx, A + q)
-        return fma32(np.float32(-2.0) * ay, by, t)
+        t = fma32(np.float32(-2.0) * ay, by, t)
+        return (t, A, q) if parts else t
     dz = az - bz
     t = fma32(dz, dz, q)
     t = fma32(np.float32(-2.0) * ax, bx, t)
     t = fma32(np.float32(-2.0) * ay, by, t)
-    return t + A
+    return (t + A, A, q) if parts else t + A
+
+
+def pair_narrowing(A, q, xy_mag, c):
+    """The sweep's float32 per-pair narrowing of an expanded r band (scaled
+    coordinates): m = fl(fl(11 q + fl(2.75 A)) (1 + 2^-18)) bounds 5 |b|^2 +
+    2 |a|^2 + 4 |a| |b| from above, and D = fl(fl(K fl(M - m)) (1 - 2^-18))
+    with K = 1.25 u (1 + 2^-20) and M = c^2 xy_mag, both rounded down."""
+    f = np.float32
+    K = f(SAFETY * U32 * (1 + 2.0 ** -20) * (1 - 2.0 ** -40))
+    if float(K) > SAFETY * U32 * (1 + 2.0 ** -20):
+        K = np.nextafter(K, f(0))
+    M = f(xy_mag * c * c * (1 - 2.0 ** -40))
+    if float(M) > xy_mag * c * c:
+        M = np.nextafter(M, f(0))
+    m = fma32(f(11.0), q, f(2.75) * A) * f(1.0 + 2.0 ** -18)
+    return (K * (M - m)) * f(1.0 - 2.0 ** -18)
+
+
+def expand_mag(xy_max, ndim):
+    """The bands' magnitude term from the coordinates' maxima (a point may
+    round a little outside its column)."""
+    g = 1.0 + 2.0 ** -16
+    ax, ay, bx, by = (v * g for v in xy_max)
+    A, B, P = ax * ax + ay * ay, bx * bx + by * by, ax * bx + ay * by
+    return 4 * A + 4 * B + 2 * P if ndim == 2 else 5 * B + 2 * A + 4 * P
 
 
 def exact_s(pi, pj, L, ndim):
@@ -180,8 +210,10 @@ def draw_pairs(rng, n, L, reach, lo=0.0, hi=None, radial=None):
     return pi, pj
 
 
-def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, xy_max=None):
-    """xy_max given: the expanded form and its bands (cf_fp32_bands_xy)."""
+def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, xy_max=None,
+                   count=True):
+    """xy_max given: the expanded form and its bands (cf_fp32_bands_xy);
+    count: add the pairs to the in-band tallies (random pairs only)."""
     s64 = exact_s(pi, pj, L, ndim)
     if xy_max is None:
         s32 = emulate_r(pi, pj, g, L, c, ndim).astype(np.float64) / (c * c)
@@ -189,7 +221,8 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, x
         def bands(e2):
             return pc.fp32_bands_axes(e2, ndim, axis_eps, coord_scale)
     else:
-        s32 = emulate_r_xy(pi, pj, g, L, c, ndim).astype(np.float64) / (c * c)
+        f32, A, q = emulate_r_xy(pi, pj, g, L, c, ndim, parts=True)
+        s32 = f32.astype(np.float64) / (c * c)
 
         def bands(e2):
             return pc.fp32_bands_xy(e2, axis_eps, xy_max, coord_scale, ndim)
@@ -202,6 +235,29 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, x
         above = s32 > hi[k]
         assert np.all(s64[below] < E[k]), ("decided below but not", k)
         assert np.all(s64[above] > E[k]), ("decided above but not", k)
+    tight = xy_max is not None and ndim == 3
+    if tight:
+        # the narrowed bands, in the scaled coordinates as the sweep takes
+        # them (bands scaled by c^2 and rounded outward, float32 differences)
+        D = pair_narrowing(A, q, expand_mag(xy_max, ndim), c)
+        c2 = c * c
+        for k in range(E.size):
+            if E[k] == 0.0:
+                continue
+            los = np.float32(lo[k] * c2)
+            his = np.float32(hi[k] * c2)
+            if float(los) > float(lo[k]) * c2:
+                los = np.nextafter(los, np.float32(-np.inf))
+            if float(his) < float(hi[k]) * c2:
+                his = np.nextafter(his, np.float32(np.inf))
+            inb = (s32 >= lo[k]) & (s32 <= hi[k])
+            above = inb & ((f32 - his) > -D)
+            below = inb & ((los - f32) > -D)
+            assert np.all(s64[above] > E[k]), ("narrowed: decided above but not", k)
+            assert np.all(s64[below] < E[k]), ("narrowed: decided below but not", k)
+            if count:
+                stats["in_band"] += int(inb.sum())
+                stats["narrowed_decided"] += int((above | below).sum())
     # the bound at each pair's own separation
     ok = s64 > 0
     blo, bhi = bands(s64[ok])
@@ -211,6 +267,13 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, x
     stats["pairs"] += int(s64.size)
     stats["max_ratio_band"] = max(stats["max_ratio_band"], float(ratio_band.max()))
     stats["max_ratio_raw"] = max(stats["max_ratio_raw"], float((ratio_band * SAFETY).max()))
+    if tight:
+        # each pair's own raw bound: its band half width less its narrowing,
+        # divided by the safety factor
+        half_t = half - D[ok].astype(np.float64) / (c * c)
+        assert np.all(half_t > 0)
+        stats["max_ratio_pair_raw"] = max(stats["max_ratio_pair_raw"],
+                                          float((err / half_t * SAFETY).max()))
 
 
 def scale_for(edges, S, top=32766.0 / 32767.0):
@@ -231,7 +294,8 @@ def test_fp32_bound_holds_on_1e8_pairs(case):
     rng = synth.rng_for(sum(map(ord, case)))
     xy = case.endswith("_xy")
     case = case[:-3] if xy else case
-    stats = {"pairs": 0, "max_ratio_band": 0.0, "max_ratio_raw": 0.0}
+    stats = {"pairs": 0, "max_ratio_band": 0.0, "max_ratio_raw": 0.0, "in_band": 0,
+             "narrowed_decided": 0, "max_ratio_pair_raw": 0.0}
     if case == "r_box420":
         L, reach, k, ndim = 420.0, 25.0, 1, 3
         edges = synth.log_edges(0.1, 25.0, 20)
@@ -287,11 +351,17 @@ def test_fp32_bound_holds_on_1e8_pairs(case):
         jitter = e_rep * (1.0 + rng.integers(-8, 9, e_rep.size) * 2.0 ** -52)
         if L > 0:
             pi, pj = draw_pairs(rng, e_rep.size, L, reach, radial=jitter)
-            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats, xy_max)
+            check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, S, stats, xy_max,
+                           count=False)
     print(case, "expanded" if xy else "differences", stats)
     assert stats["pairs"] >= npairs
     assert stats["max_ratio_raw"] < 1.0, stats
     assert stats["max_ratio_band"] < 1.0 / SAFETY, stats
+    if xy and ndim == 3:
+        assert stats["max_ratio_pair_raw"] < 1.0, stats
+        # the narrowing decides most random pairs the expanded bands leave
+        # open
+        assert stats["narrowed_decided"] > 0.5 * stats["in_band"], stats
 
 
 def test_fixed_point_pi_within_margin():
