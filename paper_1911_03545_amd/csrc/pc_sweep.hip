@@ -542,7 +542,7 @@ __device__ __forceinline__ void chunk_f32(const SweepArgs &a, const Lds &L, lds_
         if (!c[k])
             continue;
         int slot = e[k];
-        if (is_slow<T16>(e[k])) {
+        if (__builtin_expect(is_slow<T16>(e[k]), 0)) {
             slot = slow_slot<T16>(s[k], e[k], L.lo, L.hi, a.B.nb + 1);
             if constexpr (EXP) {
                 if (slot < 0)
@@ -738,7 +738,7 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
     for (int k = 0; k < CH; k++)
         flag |= T16 ? ((er[k] << 16) | (er[k] << 17)) : er[k];
     const int nb = a.B.nb;
-    if ((flag < 0) | (nmin < 2u * PC_ZQ_MARGIN)) {
+    if (__builtin_expect((flag < 0) | (nmin < 2u * PC_ZQ_MARGIN), 0)) {
 #pragma unroll
         for (int k = 0; k < CH; k++) {
             const bool sr = is_slow<T16>(er[k]);
