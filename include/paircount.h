@@ -200,13 +200,9 @@ typedef struct cf_options {
                                    absolute rounding bound (about u times 17
                                    squared column widths, folded into the
                                    decision bands, so results stay exact);
-                                   0 (default): for DD(r) and chords 2 when
-                                   that bound widens the band of the smallest
-                                   nonzero edge by at most an eighth of its
-                                   value, else 1; for DD(rp, pi) 1 (its pairs
-                                   crowd the small rp edges, where the wider
-                                   bands cost more rechecks than the form
-                                   saves).  Other
+                                   0 (default): 2 when that bound widens the
+                                   band of the smallest nonzero edge by at
+                                   most an eighth of its value, else 1.  Other
                                    statistics and the binary64 mode ignore
                                    it.  cf_stats.separation_form reports the
                                    form used.                                  */

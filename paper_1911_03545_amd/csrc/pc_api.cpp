@@ -936,16 +936,15 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
         pc::frame_eps(scale + reach_z, scale, scale)};
     // Float32 DD(r) (and chords) and DD(rp, pi) of 3-D grids without the
     // mean separation: x and y expanded as |a|^2 + |b|^2 - 2 a.b, one
-    // instruction fewer per pair.  By default DD(r) only, and only while its
-    // absolute rounding term widens the band of the smallest nonzero edge by
-    // at most an eighth of that edge: rp/pi pairs crowd the small rp edges
-    // (every pi of the window shares them), and there the wider bands cost
-    // more rechecks than the instruction saves.  (The float32 mean
-    // separation takes the square root of s and keeps the differences.)
+    // instruction fewer per pair.  By default only while its absolute
+    // rounding term widens the band of the smallest nonzero edge by at most
+    // an eighth of that edge (the sweep narrows each pair's band by its own
+    // magnitudes before a binary64 recheck, which keeps the rechecks of the
+    // crowded small rp edges in check).  (The float32 mean separation takes
+    // the square root of s and keeps the differences.)
     double xy_mag = 0.0;
     if (fp32 && g.xy_local && (metric == PC_METRIC_R || metric == PC_METRIC_RPPI) && !sky &&
-        !want_ravg && opt.separation_form != 1 &&
-        (metric == PC_METRIC_R || opt.separation_form == 2)) {
+        !want_ravg && opt.separation_form != 1) {
         const double am[2] = {(g.xyk + 0.5) * g.width[0], (g.xyk + 0.5) * g.width[1]};
         const double bm[2] = {0.5 * g.width[0], 0.5 * g.width[1]};
         const double mag = pc::xy_expand_mag(am, bm, metric == PC_METRIC_RPPI ? 2 : 3);
@@ -1178,7 +1177,7 @@ cf_status run(cf_ctx *c, RunCtl &ctl, int metric, bool theta, const cf_catalog *
     a.xy_exp = xy_mag > 0.0 ? 1 : 0;
     a.xy_K = 0.0f;
     a.xy_M = 0.0f;
-    if (xy_mag > 0.0 && metric == PC_METRIC_R)
+    if (xy_mag > 0.0)
         pc::xy_pair_margin(xy_mag, g.fscale, &a.xy_K, &a.xy_M);
     a.P2 = xy_mag > 0.0 ? static_cast<const float4 *>(c->buf[autocorr ? B_Q1 : B_Q2].p)
                         : nullptr;

@@ -333,7 +333,8 @@ double xy_expand_mag(const double a_max[2], const double b_max[2], int ndim)
 }
 
 // The bound above holds for each pair with its own magnitudes, m = 5 |b|^2
-// + 2 |a|^2 + 4 (|a_x b_x| + |a_y b_y|), in place of xy_mag; every band
+// + 2 |a|^2 + 4 (|a_x b_x| + |a_y b_y|) (rp: 4 |a|^2 + 4 |b|^2 + 2 (|a_x b_x|
+// + |a_y b_y|)), in place of xy_mag; every band
 // holds kSafety u (1 + 2^-20) xy_mag of it, so a pair may narrow both sides
 // of its band by kSafety u (1 + 2^-20) (xy_mag - m).  In the scaled
 // coordinates the band (scaled by c^2 and rounded outward) narrows by K (M -

@@ -35,8 +35,8 @@ int fp32_bands_axes(const double *edges_sq, int nedges, int ndim, const double *
 // 2): a_max = the lane's largest |x|, |y| in the j column's frame, b_max = the
 // j point's
 double xy_expand_mag(const double a_max[2], const double b_max[2], int ndim);
-// per-pair narrowing of the expanded r bands (ndim 3) in coordinates scaled
-// by fscale: a pair whose own magnitude term is m (scaled) may take its band
+// per-pair narrowing of the expanded r (ndim 3) and rp (ndim 2) bands in
+// coordinates scaled by fscale: a pair whose own magnitude term is m (scaled) may take its band
 // narrowed by K (M - m) on each side; both constants rounded down
 void xy_pair_margin(double xy_mag, double fscale, float *K, float *M);
 // rounding bound of one column-local axis: coordinates at most a_max and

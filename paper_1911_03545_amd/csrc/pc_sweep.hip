@@ -408,14 +408,15 @@ __device__ __forceinline__ int exact_slot_r_at(const SweepArgs &a, const Lds &L,
     return exact_bin<PC_METRIC_R>(s, pz, L.E, a.B.nb, L.q, 1, 0.0) + 1;
 }
 
-// An expanded r pair whose float32 value lies inside its edge's band: the
-// band holds the rounding term of the largest magnitudes a lane and a j point
-// can have; narrowed by the pair's own term, from the lane's A = |a|^2 and
-// the j point's |b|^2, it often decides the pair without the binary64
-// recheck.  -1 when the value stays inside the narrowed band, or the cell
-// holds several bands.  Every float32 rounding errs towards a narrower
-// narrowing: m is rounded up, the narrowing and the differences below down.
-template <bool T16>
+// An expanded r (NDIM 3) or rp (NDIM 2) pair whose float32 value lies inside
+// its edge's band: the band holds the rounding term of the largest magnitudes
+// a lane and a j point can have; narrowed by the pair's own term, from the
+// lane's A = |a|^2 and the j point's |b|^2, it often decides the pair without
+// the binary64 recheck.  -1 when the value stays inside the narrowed band, or
+// the cell holds several bands.  Every float32 rounding errs towards a
+// narrower narrowing: m is rounded up, the narrowing and the differences
+// below down.
+template <bool T16, int NDIM = 3>
 __device__ __forceinline__ int tight_slot(const SweepArgs &a, const Lds &L, float s, int e,
                                           float A, int j)
 {
@@ -423,9 +424,11 @@ __device__ __forceinline__ int tight_slot(const SweepArgs &a, const Lds &L, floa
         return -1;
     const int c = band_edge<T16>(e);
     const float q = ((kf32p)a.P2)[4 * j + 3];
-    // m >= 5 |b|^2 + 2 |a|^2 + 4 |a| |b|, as 4 |a| |b| <= 6 |b|^2 + (2/3)
-    // |a|^2; (1 + 2^-18) covers the roundings of A, |b|^2 and of m itself
-    const float m = fmaf(11.0f, q, 2.75f * A) * (1.0f + 0x1p-18f);
+    // r: m >= 5 |b|^2 + 2 |a|^2 + 4 |a| |b|, as 4 |a| |b| <= 6 |b|^2 + (2/3)
+    // |a|^2; rp: m >= 4 |b|^2 + 4 |a|^2 + 2 |a| |b|, as 2 |a| |b| <= 3 |b|^2 +
+    // (1/3) |a|^2; (1 + 2^-18) covers the roundings of A, |b|^2 and of m
+    const float m = (NDIM == 3 ? fmaf(11.0f, q, 2.75f * A) : fmaf(7.0f, q, 4.375f * A)) *
+                    (1.0f + 0x1p-18f);
     const float D = a.xy_K * (a.xy_M - m) * (1.0f - 0x1p-18f);
     if (s - L.hi[c] > -D)
         return c + 1;
@@ -747,6 +750,10 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
                 int row = er[k];
                 if (sr) {
                     row = slow_slot<T16>(s[k], er[k], L.lo, L.hi, nb + 1);
+                    if constexpr (EXP) {
+                        if (row < 0)
+                            row = tight_slot<T16, 2>(a, L, s[k], er[k], A, j + k);
+                    }
                     if (row == nb + 1)
                         row = 0;
                 }

@@ -17,9 +17,9 @@ few ulps of every edge), and check that
   s64 < E_k and s32 > hi_k implies s64 > E_k;
 
 for DD(r) (3 axes), rp^2 (2 axes) and squared chords of unit vectors
-(3 axes, no box).  The expanded form of squared r (x and y as |a|^2 + |b|^2
-- 2 a.b) is also checked with each band narrowed by the pair's own magnitude
-term, computed in float32 as the sweep does before its binary64 recheck: no
+(3 axes, no box).  The expanded forms of squared r and rp (x and y as |a|^2 +
+|b|^2 - 2 a.b) are also checked with each band narrowed by the pair's own
+magnitude term, computed in float32 as the sweep does before its binary64 recheck: no
 wrong decision, and |s32 - s64| stays within the pair's own raw bound.  And
 that the fixed-point line-of-sight coordinate of the
 float32 DD(rp, pi) path stays within 1.5 quanta of the exact |dz|, below the
@@ -157,10 +157,11 @@ def emulate_r_xy(pi, pj, g, L, c, ndim=3, parts=False):
     return (t + A, A, q) if parts else t + A
 
 
-def pair_narrowing(A, q, xy_mag, c):
+def pair_narrowing(A, q, xy_mag, c, ndim=3):
     """The sweep's float32 per-pair narrowing of an expanded r band (scaled
     coordinates): m = fl(fl(11 q + fl(2.75 A)) (1 + 2^-18)) bounds 5 |b|^2 +
-    2 |a|^2 + 4 |a| |b| from above, and D = fl(fl(K fl(M - m)) (1 - 2^-18))
+    2 |a|^2 + 4 |a| |b| from above (rp, ndim 2: fl(7 q + fl(4.375 A)) bounds
+    4 |b|^2 + 4 |a|^2 + 2 |a| |b|), and D = fl(fl(K fl(M - m)) (1 - 2^-18))
     with K = 1.25 u (1 + 2^-20) and M = c^2 xy_mag, both rounded down."""
     f = np.float32
     K = f(SAFETY * U32 * (1 + 2.0 ** -20) * (1 - 2.0 ** -40))
@@ -169,7 +170,10 @@ def pair_narrowing(A, q, xy_mag, c):
     M = f(xy_mag * c * c * (1 - 2.0 ** -40))
     if float(M) > xy_mag * c * c:
         M = np.nextafter(M, f(0))
-    m = fma32(f(11.0), q, f(2.75) * A) * f(1.0 + 2.0 ** -18)
+    if ndim == 3:
+        m = fma32(f(11.0), q, f(2.75) * A) * f(1.0 + 2.0 ** -18)
+    else:
+        m = fma32(f(7.0), q, f(4.375) * A) * f(1.0 + 2.0 ** -18)
     return (K * (M - m)) * f(1.0 - 2.0 ** -18)
 
 
@@ -237,11 +241,11 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, x
         above = s32 > hi[k]
         assert np.all(s64[below] < E[k]), ("decided below but not", k)
         assert np.all(s64[above] > E[k]), ("decided above but not", k)
-    tight = xy_max is not None and ndim == 3
+    tight = xy_max is not None
     if tight:
         # the narrowed bands, in the scaled coordinates as the sweep takes
         # them (bands scaled by c^2 and rounded outward, float32 differences)
-        D = pair_narrowing(A, q, expand_mag(xy_max, ndim), c) * np.float32(narrow_scale)
+        D = pair_narrowing(A, q, expand_mag(xy_max, ndim), c, ndim) * np.float32(narrow_scale)
         c2 = c * c
         for k in range(E.size):
             if E[k] == 0.0:
@@ -361,7 +365,7 @@ def test_fp32_bound_holds_on_1e8_pairs(case):
     assert stats["pairs"] >= npairs
     assert stats["max_ratio_raw"] < 1.0, stats
     assert stats["max_ratio_band"] < 1.0 / SAFETY, stats
-    if xy and ndim == 3:
+    if xy:
         assert stats["narrow_wrong"] == 0, stats
         assert stats["max_ratio_pair_raw"] < 1.0, stats
         # the narrowing decides most random pairs the expanded bands leave
