@@ -199,7 +199,10 @@ typedef struct cf_options {
                                    instruction fewer per pair, with a larger
                                    absolute rounding bound (about u times 17
                                    squared column widths, folded into the
-                                   decision bands, so results stay exact);
+                                   decision bands, so results stay exact; a
+                                   pair inside a band is first tested
+                                   against the band narrowed by its own
+                                   magnitudes, then rechecked in binary64);
                                    0 (default): 2 when that bound widens the
                                    band of the smallest nonzero edge by at
                                    most an eighth of its value, else 1.  Other
