@@ -955,7 +955,11 @@ __global__ void k_item_count(int32_t nblocks, const int32_t *nblocks_dev,
         });
         icnt[bi] = total;
     }
-    if (my)
+    // one atomic per wave: a per-thread add to the one counter serialises
+    // every block of the work list at one L2 address
+    for (int off = PC_WAVE / 2; off > 0; off >>= 1)
+        my += __shfl_xor(my, off);
+    if ((threadIdx.x & (PC_WAVE - 1)) == 0 && my)
         atomicAdd(cand, my);
 }
 
