@@ -483,7 +483,10 @@ cf_status cf_fp32_bands_axes(const double *edges_sq, int32_t nedges, int32_t ndi
    largest magnitudes, given
    as xy_max = {a_x, a_y, b_x, b_y} (the lane's largest |x|, |y| in the j
    column's frame, the j point's); the coordinate term is unchanged.
-   axis_eps holds ndim values. */
+   axis_eps holds ndim values.  The sweep narrows the band of a pair inside
+   it by 1.25 u (1 + 2^-20) (M - m), m the same term at the pair's own
+   magnitudes (bounded above from |a|^2 and |b|^2 alone), before it
+   rechecks the pair in binary64. */
 cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, int32_t ndim,
                            const double *axis_eps, const double *xy_max, double coord_scale,
                            float *lo, float *hi);
