@@ -491,6 +491,15 @@ cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, int32_t ndim,
                            const double *axis_eps, const double *xy_max, double coord_scale,
                            float *lo, float *hi);
 
+/* Host-only: the two float32 constants of that narrowing as the sweep
+   receives them, for coordinates scaled by fscale > 0: *K = 1.25 u (1 +
+   2^-20) and *M = fscale^2 times M of the bands above (xy_max and ndim as
+   for cf_fp32_bands_xy), each rounded down; a pair narrows its band by
+   K (M - m) with m in the scaled coordinates.  CF_EINVAL on a null
+   pointer, ndim other than 2 or 3, or a negative or non-finite value. */
+cf_status cf_fp32_pair_margin(const double *xy_max, int32_t ndim, double fscale, float *K,
+                              float *M);
+
 /* Host-only: the exact sum of n values p[k], each an integer multiple of 2^q
    with |p[k]| < 2^(q + 94), rounded once to binary64 (ties to even), through
    the same fixed-point arithmetic as cf_options.deterministic_weights (three

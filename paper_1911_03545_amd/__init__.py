@@ -42,7 +42,7 @@ EXPORTED_SYMBOLS = (
     "count_pairs_theta", "count_pairs_theta_ex", "count_pairs_rppi_batch",
     "count_pairs_rppi_batch_ex", "count_pairs_rppi_mocks", "count_pairs_rppi_mocks_ex",
     "cf_plan_grid", "cf_plan_grid_ex", "cf_plan_sky_grid", "cf_fp32_bands",
-    "cf_fp32_bands_axes", "cf_fp32_bands_xy",
+    "cf_fp32_bands_axes", "cf_fp32_bands_xy", "cf_fp32_pair_margin",
     "cf_fixed_sum",
 )
 
@@ -191,6 +191,8 @@ def load_library(path: str = LIB_PATH):
     lib.cf_fp32_bands_axes.restype = ctypes.c_int
     lib.cf_fp32_bands_xy.argtypes = [vp, i32, i32, vp, vp, dbl, vp, vp]
     lib.cf_fp32_bands_xy.restype = ctypes.c_int
+    lib.cf_fp32_pair_margin.argtypes = [vp, i32, dbl, vp, vp]
+    lib.cf_fp32_pair_margin.restype = ctypes.c_int
     lib.cf_fixed_sum.argtypes = [vp, ctypes.c_int64, i32, vp]
     lib.cf_fixed_sum.restype = ctypes.c_int
     _lib = lib
@@ -312,6 +314,23 @@ def fp32_bands_xy(edges_sq, axis_eps, xy_max, coord_scale: float, ndim: int = 3)
     if st != CF_OK:
         raise PairCountError(st, "cf_fp32_bands_xy failed")
     return lo, hi
+
+
+def fp32_pair_margin(xy_max, fscale: float, ndim: int = 3):
+    """Host-only (K, M) of the sweep's per-pair narrowing of the expanded
+    bands (float32 values): a pair with magnitude term m narrows its band by
+    K (M - m) in the coordinates scaled by fscale."""
+    lib = load_library()
+    mx = np.ascontiguousarray(xy_max, dtype=np.float64)
+    if mx.size < 4:
+        raise ValueError("four magnitudes")
+    K = np.zeros(1, dtype=np.float32)
+    M = np.zeros(1, dtype=np.float32)
+    st = lib.cf_fp32_pair_margin(mx.ctypes.data, int(ndim), float(fscale), K.ctypes.data,
+                                 M.ctypes.data)
+    if st != CF_OK:
+        raise PairCountError(st, "cf_fp32_pair_margin failed")
+    return K[0], M[0]
 
 
 def fixed_sum(values, q: int) -> float:

@@ -809,6 +809,19 @@ extern "C" cf_status cf_fp32_bands_xy(const double *edges_sq, int32_t nedges, in
                                           mag > 0.0 ? mag : 0x1p-1000);
 }
 
+extern "C" cf_status cf_fp32_pair_margin(const double *xy_max, int32_t ndim, double fscale,
+                                         float *K, float *M)
+{
+    if (!xy_max || !K || !M || (ndim != 2 && ndim != 3) || !(fscale > 0.0) ||
+        !std::isfinite(fscale))
+        return CF_EINVAL;
+    for (int k = 0; k < 4; k++)
+        if (!(xy_max[k] >= 0.0) || !std::isfinite(xy_max[k]))
+            return CF_EINVAL;
+    pc::xy_pair_margin(pc::xy_expand_mag(xy_max, xy_max + 2, ndim), fscale, K, M);
+    return CF_OK;
+}
+
 // Host twin of the fixed-point weight sums (pc_fixed.h): the same limb split,
 // limb sums and 192-bit assembly as the sweep and its merges, in one thread.
 extern "C" cf_status cf_fixed_sum(const double *p, int64_t n, int32_t q, double *out)

@@ -157,19 +157,13 @@ def emulate_r_xy(pi, pj, g, L, c, ndim=3, parts=False):
     return (t + A, A, q) if parts else t + A
 
 
-def pair_narrowing(A, q, xy_mag, c, ndim=3):
+def pair_narrowing(A, q, K, M, ndim=3):
     """The sweep's float32 per-pair narrowing of an expanded r band (scaled
     coordinates): m = fl(fl(11 q + fl(2.75 A)) (1 + 2^-18)) bounds 5 |b|^2 +
     2 |a|^2 + 4 |a| |b| from above (rp, ndim 2: fl(7 q + fl(4.375 A)) bounds
     4 |b|^2 + 4 |a|^2 + 2 |a| |b|), and D = fl(fl(K fl(M - m)) (1 - 2^-18))
-    with K = 1.25 u (1 + 2^-20) and M = c^2 xy_mag, both rounded down."""
+    with the library's K and M (cf_fp32_pair_margin)."""
     f = np.float32
-    K = f(SAFETY * U32 * (1 + 2.0 ** -20) * (1 - 2.0 ** -40))
-    if float(K) > SAFETY * U32 * (1 + 2.0 ** -20):
-        K = np.nextafter(K, f(0))
-    M = f(xy_mag * c * c * (1 - 2.0 ** -40))
-    if float(M) > xy_mag * c * c:
-        M = np.nextafter(M, f(0))
     if ndim == 3:
         m = fma32(f(11.0), q, f(2.75) * A) * f(1.0 + 2.0 ** -18)
     else:
@@ -245,7 +239,8 @@ def check_contract(pi, pj, g, L, c, ndim, edges, axis_eps, coord_scale, stats, x
     if tight:
         # the narrowed bands, in the scaled coordinates as the sweep takes
         # them (bands scaled by c^2 and rounded outward, float32 differences)
-        D = pair_narrowing(A, q, expand_mag(xy_max, ndim), c, ndim) * np.float32(narrow_scale)
+        K, M = pc.fp32_pair_margin(xy_max, c, ndim)
+        D = pair_narrowing(A, q, K, M, ndim) * np.float32(narrow_scale)
         c2 = c * c
         for k in range(E.size):
             if E[k] == 0.0:
@@ -443,3 +438,26 @@ def test_wrong_narrowing_is_caught():
     print(got)
     assert got[1.0]["narrow_wrong"] == 0 and got[1.0]["max_ratio_pair_raw"] < 1.0
     assert got[1.25]["narrow_wrong"] > 0
+
+
+def test_pair_margin_constants():
+    """The narrowing constants the library hands the sweep are the bound's,
+    rounded down: K = 1.25 u (1 + 2^-20) and M = c^2 times the magnitude term
+    of the largest coordinates, never above those values and at most a
+    relative 2^-22 below them; bad arguments are refused."""
+    rng = synth.rng_for(4343)
+    for _ in range(200):
+        ndim = int(rng.integers(2, 4))
+        xy_max = rng.uniform(0.0, 50.0, 4)
+        c = float(np.exp(rng.uniform(-6.0, 3.0)))
+        K, M = pc.fp32_pair_margin(xy_max, c, ndim)
+        exact_K = SAFETY * U32 * (1 + 2.0 ** -20)
+        exact_M = expand_mag(xy_max, ndim) * c * c
+        assert exact_K * (1 - 2.0 ** -22) <= float(K) <= exact_K, (K, exact_K)
+        assert exact_M * (1 - 2.0 ** -22) <= float(M) <= exact_M, (ndim, xy_max, c, M, exact_M)
+    with pytest.raises(pc.PairCountError):
+        pc.fp32_pair_margin([1.0, 1.0, 1.0, -1.0], 1.0, 3)
+    with pytest.raises(pc.PairCountError):
+        pc.fp32_pair_margin([1.0, 1.0, 1.0, 1.0], 0.0, 3)
+    with pytest.raises(pc.PairCountError):
+        pc.fp32_pair_margin([1.0, 1.0, 1.0, 1.0], 1.0, 4)
