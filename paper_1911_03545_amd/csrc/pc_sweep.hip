@@ -771,16 +771,20 @@ __device__ __forceinline__ void chunk_f32_rppi_q(const SweepArgs &a, const Lds &
         }
     }
     // kp < npi iff u < npi << sh (every u fits when that shift overflows);
-    // the slot's byte offset is one 24-bit multiply-add
+    // the slot is one 24-bit multiply-add of row and column, and its byte
+    // address one shift-add (the + 1 rides in the LDS instruction's offset)
     const unsigned ulim = npi > (0xFFFFFFFFu >> sh) ? 0xFFFFFFFFu : npi << sh;
-    const unsigned rw4 = 4u * (unsigned)a.B.row_w;
+    const unsigned rw = (unsigned)a.B.row_w;
 #pragma unroll
     for (int k = 0; k < CH; k++) {
         if ((er[k] > 0) & (u[k] < ulim)) {
-            const unsigned off = __umul24((unsigned)er[k], rw4) + ((u[k] >> sh) << 2) + 4u;
-            lds_add((lds_u32p)((LDS char *)hb + off), 1u);
+            unsigned slot = __umul24((unsigned)er[k], rw) + (u[k] >> sh);
+            // (opaque here, or the compiler scales both terms of the sum
+            // separately: two instructions more)
+            asm("" : "+v"(slot));
+            lds_add(&hb[slot + 1u], 1u);
             if (W)
-                add_weight_f32<W>(a, whb, (int)(off >> 2), wi, ws[k], s[k], 1);
+                add_weight_f32<W>(a, whb, (int)(slot + 1u), wi, ws[k], s[k], 1);
         }
     }
 }
